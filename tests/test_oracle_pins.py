@@ -1,0 +1,454 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each ``check_*`` returns an error measure for a given implementation; the
+tests assert it is small for the oracle and large for planted mistakes
+(mutants defined at the bottom), so that a dropped term, a wrong sign, a
+wrong index or a transposed operand in the oracle fails a pin.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import lowrank, metrics, poisson, tucker
+from paper_1306_2150_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ----------------------------------------------------------------- helpers
+def sine_mode(n, p):
+    i = np.arange(1, n + 1, dtype=np.float64)
+    return np.sin(p * math.pi * i / (n + 1))
+
+
+def check_eigs(eig_fn, n):
+    """Relative max error of eig_fn(n) against LAPACK eigvalsh(T)."""
+    ref = np.linalg.eigvalsh(poisson.laplacian_1d(n))
+    got = np.sort(eig_fn(n))
+    return float(np.max(np.abs(got - ref)) / np.max(ref))
+
+
+def check_solve_sylvester(solve_fn, n, seed=0):
+    """Relative error of solve_fn(F) against Bartels-Stewart."""
+    rng = np.random.default_rng(seed)
+    F = rng.standard_normal((n, n))
+    T = poisson.laplacian_1d(n)
+    ref = scipy.linalg.solve_sylvester(T, T, F)
+    got = solve_fn(F)
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def check_single_mode(solve_fn, n, p, q):
+    """F = s_p s_q^T has X = F/(lambda_p + lambda_q) exactly."""
+    lam = poisson.eigenvalues(n)
+    F = np.outer(sine_mode(n, p), sine_mode(n, q))
+    X = F / (lam[p - 1] + lam[q - 1])
+    got = solve_fn(F)
+    return float(np.linalg.norm(got - X) / np.linalg.norm(X))
+
+
+# ------------------------------------------------------------ eigenvalues
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 64, 255])
+def test_eigenvalues_vs_lapack(n):
+    assert check_eigs(poisson.eigenvalues, n) < 1e-13
+
+
+def test_eigenvalues_golden():
+    for line in open(os.path.join(GOLDEN, "eigenvalues_small.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        n, k, expr = line.split()
+        want = eval(expr, {"sqrt": math.sqrt})
+        got = poisson.eigenvalues(int(n))[int(k) - 1]
+        assert abs(got - want) <= 1e-13 * abs(want)
+
+
+def test_eigenvalues_small_k_relative_accuracy():
+    # the sin^2 form keeps full relative accuracy at k = 1 for large n;
+    # pin against the series 4/h^2 sin^2(x) = (pi k)^2 (1 - x^2/3 + 2x^4/45 ...)
+    n = 4096
+    h = 1.0 / (n + 1)
+    x = math.pi * h / 2
+    series = (math.pi) ** 2 * (1 - x * x / 3 + 2 * x ** 4 / 45)
+    assert abs(poisson.eigenvalues(n)[0] - series) / series < 1e-15 * 8
+
+
+# ----------------------------------------------------------- sine transform
+@pytest.mark.parametrize("n", [1, 2, 5, 16, 63])
+def test_sine_matrix_orthonormal_and_diagonalises(n):
+    S = poisson.sine_matrix(n)
+    assert np.max(np.abs(S.T @ S - np.eye(n))) < 1e-14 * max(1, n)
+    D = S @ poisson.laplacian_1d(n) @ S
+    lam = poisson.eigenvalues(n)
+    assert np.max(np.abs(D - np.diag(lam))) < 1e-12 * lam.max()
+
+
+@pytest.mark.parametrize("n", [1, 4, 31, 100])
+def test_library_dst_is_sine_matrix(n):
+    rng = np.random.default_rng(n)
+    X = rng.standard_normal((n, 3))
+    assert np.max(np.abs(poisson.dst(X) - poisson.sine_matrix(n) @ X)) < 1e-13
+
+
+# ------------------------------------------------------------ full solvers
+def test_full_solve2d_golden_n2():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "solve_n2.txt"))
+            if l.strip() and not l.startswith("#")]
+    want = np.array([[float(Fraction(v)) for v in r] for r in rows])
+    F = np.zeros((2, 2))
+    F[0, 0] = 1.0
+    assert np.max(np.abs(poisson.full_solve2d(F) - want)) < 1e-16
+
+
+@pytest.mark.parametrize("n", [8, 64, 128])
+def test_full_solve2d_vs_sylvester(n):
+    # Bartels-Stewart error grows with cond(T) ~ (2n/pi)^2
+    assert check_solve_sylvester(poisson.full_solve2d, n) < 1e-15 * (n + 1) ** 2
+
+
+def test_full_solve2d_vs_dense_kron():
+    n = 12
+    rng = np.random.default_rng(3)
+    F = rng.standard_normal((n, n))
+    T = poisson.laplacian_1d(n)
+    L = np.kron(T, np.eye(n)) + np.kron(np.eye(n), T)
+    x = np.linalg.solve(L, F.reshape(-1))          # row-major vec
+    X = poisson.full_solve2d(F)
+    assert np.max(np.abs(X.reshape(-1) - x)) < 1e-13 * np.max(np.abs(x))
+    res = T @ X + X @ T - F
+    assert np.linalg.norm(res) / np.linalg.norm(F) < 1e-13
+
+
+def test_full_solve2d_rectangular_residual():
+    rng = np.random.default_rng(4)
+    F = rng.standard_normal((9, 14))
+    X = poisson.full_solve2d(F)
+    r = poisson.laplacian_1d(9) @ X + X @ poisson.laplacian_1d(14) - F
+    assert np.linalg.norm(r) / np.linalg.norm(F) < 1e-13
+
+
+@pytest.mark.parametrize("n,p,q", [(257, 1, 1), (257, 3, 200), (1000, 17, 5)])
+def test_full_solve2d_single_mode(n, p, q):
+    # rounding noise in the spectrum is amplified by up to
+    # (lambda_p + lambda_q) / (2 lambda_1) relative to the exact mode
+    lam = poisson.eigenvalues(n)
+    amp = (lam[p - 1] + lam[q - 1]) / (2 * lam[0])
+    assert check_single_mode(poisson.full_solve2d, n, p, q) < 1e-14 * amp
+
+
+def test_full_solve2d_semi_analytic():
+    # F = s_p v^T  =>  X = s_p w^T with (T + lambda_p I) w = v (banded solve)
+    n, p = 1000, 7
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(n)
+    lam = poisson.eigenvalues(n)
+    h2 = (n + 1.0) ** 2
+    ab = np.zeros((3, n))
+    ab[0, 1:] = -h2
+    ab[1, :] = 2 * h2 + lam[p - 1]
+    ab[2, :-1] = -h2
+    w = scipy.linalg.solve_banded((1, 1), ab, v)
+    X = poisson.full_solve2d(np.outer(sine_mode(n, p), v))
+    ref = np.outer(sine_mode(n, p), w)
+    assert np.linalg.norm(X - ref) / np.linalg.norm(ref) < 1e-12
+
+
+def test_full_solve3d_vs_dense_kron():
+    n = 6
+    rng = np.random.default_rng(6)
+    F = rng.standard_normal((n, n, n))
+    T = poisson.laplacian_1d(n)
+    I = np.eye(n)
+    L = (np.kron(np.kron(T, I), I) + np.kron(np.kron(I, T), I)
+         + np.kron(np.kron(I, I), T))
+    x = np.linalg.solve(L, F.reshape(-1))
+    X = poisson.full_solve3d(F)
+    assert np.max(np.abs(X.reshape(-1) - x)) < 1e-13 * np.max(np.abs(x))
+
+
+def test_full_solve3d_single_mode():
+    n = 48
+    lam = poisson.eigenvalues(n)
+    a, b, c = sine_mode(n, 2), sine_mode(n, 9), sine_mode(n, 40)
+    F = np.einsum("i,j,k->ijk", a, b, c)
+    X = poisson.full_solve3d(F)
+    ref = F / (lam[1] + lam[8] + lam[39])
+    assert np.linalg.norm(X - ref) / np.linalg.norm(ref) < 1e-12
+
+
+def test_tucker_full_matches_kron():
+    rng = np.random.default_rng(7)
+    G = rng.standard_normal((2, 3, 4))
+    U1, U2, U3 = (rng.standard_normal((5, q)) for q in (2, 3, 4))
+    A = poisson.tucker_full(G, U1, U2, U3)
+    # brute force over every index
+    ref = np.zeros((5, 5, 5))
+    for i in range(5):
+        for j in range(5):
+            for l in range(5):
+                ref[i, j, l] = sum(G[a, b, c] * U1[i, a] * U2[j, b] * U3[l, c]
+                                   for a in range(2) for b in range(3)
+                                   for c in range(4))
+    assert np.max(np.abs(A - ref)) < 1e-12
+
+
+# --------------------------------------------------------------- metrics
+def test_rel_err_factored_direct():
+    rng = np.random.default_rng(8)
+    Ux, Vx = rng.standard_normal((70, 3)), rng.standard_normal((70, 3))
+    X = rng.standard_normal((70, 70))
+    want = np.linalg.norm(Ux @ Vx.T - X) / np.linalg.norm(X)
+    assert abs(metrics.rel_err_factored(Ux, Vx, X, block=16) - want) < 1e-14
+
+
+def test_rel_err_small_difference_no_cancellation():
+    rng = np.random.default_rng(9)
+    Ux, Vx = rng.standard_normal((300, 4)), rng.standard_normal((300, 4))
+    X = Ux @ Vx.T
+    d = 1e-11 * rng.standard_normal((300, 300))
+    e = metrics.rel_err_factored(Ux, Vx, X + d)
+    want = np.linalg.norm(d) / np.linalg.norm(X + d)
+    assert abs(e - want) / want < 1e-3
+
+
+# ---------------------------------------------------------------- maxvol
+def _lapack_pivot_rows(A):
+    lu, piv = scipy.linalg.lu_factor(A)
+    perm = np.arange(A.shape[0])
+    for j, p in enumerate(piv):
+        perm[[j, p]] = perm[[p, j]]
+    return perm[:A.shape[1]]
+
+
+@pytest.mark.parametrize("n,k", [(10, 1), (50, 7), (300, 20)])
+def test_gepp_rows_match_lapack(n, k):
+    A = np.random.default_rng(n + k).standard_normal((n, k))
+    assert np.array_equal(lowrank.gepp_rows(A), _lapack_pivot_rows(A))
+
+
+def check_maxvol(maxvol_fn, n, k, seed, tau=1.05):
+    """Returns (max|B[I]-Id|, max|B| - tau, brute-force volume ratio)."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, k))
+    I, B, _ = maxvol_fn(A, tau)
+    Bref = A @ np.linalg.inv(A[I, :])
+    e_id = float(np.max(np.abs(Bref[I, :] - np.eye(k))))
+    over = float(np.max(np.abs(Bref)) - tau)
+    ratio = 0.0
+    if n <= 10:
+        import itertools
+        vol = abs(np.linalg.det(A[I, :]))
+        best = max(abs(np.linalg.det(A[list(c), :]))
+                   for c in itertools.combinations(range(n), k))
+        ratio = best / vol / (tau * math.sqrt(k)) ** k
+    return e_id, over, ratio
+
+
+@pytest.mark.parametrize("n,k,seed", [(10, 1, 0), (10, 2, 1), (10, 3, 2),
+                                      (9, 3, 3), (200, 16, 4), (1000, 40, 5)])
+def test_maxvol_invariants(n, k, seed):
+    e_id, over, ratio = check_maxvol(lowrank.maxvol, n, k, seed)
+    assert e_id < 1e-10
+    assert over <= 1e-12
+    assert ratio <= 1.0 + 1e-12
+
+
+def test_maxvol_k1_is_argmax():
+    A = np.random.default_rng(11).standard_normal((100, 1))
+    I, _, _ = lowrank.maxvol(A)
+    assert I[0] == int(np.argmax(np.abs(A[:, 0])))
+
+
+def test_maxvol_swaps_increase_volume():
+    rng = np.random.default_rng(12)
+    A = rng.standard_normal((400, 12))
+    I0 = lowrank.gepp_rows(A)
+    I, _, swaps = lowrank.maxvol(A, 1.0001)
+    v0 = abs(np.linalg.det(A[I0, :]))
+    v1 = abs(np.linalg.det(A[I, :]))
+    assert v1 >= v0 * (1.0001 ** swaps) * (1 - 1e-9)
+
+
+# ------------------------------------------------------------ truncation
+@pytest.mark.parametrize("eps", [1e-2, 1e-5, 1e-9])
+def test_truncation_rank_vs_svd(eps):
+    rng = np.random.default_rng(13)
+    Q1, _ = np.linalg.qr(rng.standard_normal((80, 30)))
+    Q2, _ = np.linalg.qr(rng.standard_normal((60, 30)))
+    s = np.logspace(0, -12, 30)
+    M = (Q1 * s) @ Q2.T
+    sv = np.linalg.svd(M, compute_uv=False)
+    R = lowrank.truncation_rank(sv, eps)
+    # brute force: tail norm after R is <= eps, after R-1 it is not
+    tot = np.linalg.norm(sv)
+    assert np.linalg.norm(sv[R:]) <= eps * tot
+    assert R == 0 or np.linalg.norm(sv[R - 1:]) > eps * tot
+    # and the best rank-R approximation error equals that tail
+    U, S, Vt = np.linalg.svd(M)
+    err = np.linalg.norm(M - (U[:, :R] * S[:R]) @ Vt[:R])
+    assert err <= eps * tot * (1 + 1e-6)
+
+
+def test_truncation_rank_cases():
+    assert lowrank.truncation_rank(np.array([1.0, 1e-3, 1e-6]), 1e-5) == 2
+    assert lowrank.truncation_rank(np.array([1.0, 1e-3, 1e-6]), 2e-3) == 1
+    assert lowrank.truncation_rank(np.zeros(4), 1e-8) == 0
+    assert lowrank.truncation_rank(np.array([]), 1e-8) == 0
+
+
+# ------------------------------------------------------- low-rank 2D solve
+@pytest.mark.parametrize("w,n,inst", [(1, None, 1), (1, None, 2), (1, None, 3),
+                                      (2, 512, 1), (2, 1024, 2), (4, 1024, 1)])
+def test_lr_solve2d_vs_full(w, n, inst):
+    U, V = inputs.workload_rhs(w, inst, n=n)
+    eps = inputs.WORKLOADS[w]["eps"]
+    X = poisson.full_solve2d_factors(U, V)
+    Ux, Vx, info = lowrank.lr_solve2d(U, V, eps)
+    assert info["status"] == "ok"
+    assert metrics.rel_err_factored(Ux, Vx, X) <= 10 * eps
+    # Vx has orthonormal columns (S is orthogonal)
+    assert np.max(np.abs(Vx.T @ Vx - np.eye(Vx.shape[1]))) < 1e-12
+
+
+@pytest.mark.slow
+def test_lr_solve2d_full_size_4096():
+    U, V = inputs.workload_rhs(2, 1)
+    X = poisson.full_solve2d_factors(U, V)
+    Ux, Vx, info = lowrank.lr_solve2d(U, V, 1e-8)
+    assert metrics.rel_err_factored(Ux, Vx, X) <= 1e-7
+    assert 15 <= info["rank"] <= 40
+
+
+def test_lr_solve2d_exact_rank_q():
+    # F = sum_m s_{p_m} v_m^T: the spectrum has exactly q nonzero rows, so
+    # the solution has rank q and a cross with k >= q reproduces it.
+    n, ps = 300, [2, 11, 40, 151]
+    rng = np.random.default_rng(14)
+    U = np.stack([sine_mode(n, p) for p in ps], axis=1)
+    V = rng.standard_normal((n, len(ps)))
+    X = poisson.full_solve2d_factors(U, V)
+    Ux, Vx, info = lowrank.lr_solve2d(U, V, 1e-13)
+    assert info["rank"] == len(ps)
+    assert metrics.rel_err_factored(Ux, Vx, X) < 1e-11
+
+
+def test_lr_solve2d_single_mode_large_n():
+    n = 4096
+    u, v = sine_mode(n, 3), sine_mode(n, 77)
+    lam = poisson.eigenvalues(n)
+    Ux, Vx, info = lowrank.lr_solve2d(u[:, None], v[:, None], 1e-10)
+    assert info["rank"] == 1
+    X1 = Ux[:, 0] * np.linalg.norm(Vx[:, 0])
+    want = u * np.linalg.norm(v) / (lam[2] + lam[76])
+    assert np.linalg.norm(np.abs(X1) - np.abs(want)) / np.linalg.norm(want) < 1e-12
+
+
+def test_lr_solve2d_zero_rhs():
+    U = np.zeros((64, 3))
+    V = np.ones((64, 3))
+    Ux, Vx, info = lowrank.lr_solve2d(U, V, 1e-8)
+    assert Ux.shape == (64, 0) and info["rank"] == 0
+
+
+def test_lr_solve2d_tiny_n_is_exact():
+    rng = np.random.default_rng(15)
+    U, V = rng.standard_normal((5, 2)), rng.standard_normal((5, 2))
+    X = poisson.full_solve2d_factors(U, V)
+    Ux, Vx, info = lowrank.lr_solve2d(U, V, 1e-12)
+    assert metrics.rel_err_factored(Ux, Vx, X) < 1e-12
+
+
+# ------------------------------------------------------- low-rank 3D solve
+@pytest.mark.parametrize("n,eps", [(32, 1e-6), (64, 1e-6), (48, 1e-8)])
+def test_lr_solve3d_vs_full(n, eps):
+    U1, U2, U3, G = inputs.rhs3d_tucker(n, (16, 16, 16), 3001)
+    X = poisson.full_solve3d_tucker(U1, U2, U3, G)
+    f, c, info = tucker.lr_solve3d(U1, U2, U3, G, eps)
+    assert metrics.rel_err_tucker(f[0], f[1], f[2], c, X) <= 10 * eps
+    for q in f:
+        assert np.max(np.abs(q.T @ q - np.eye(q.shape[1]))) < 1e-12
+
+
+def test_lr_solve3d_single_mode():
+    n = 40
+    lam = poisson.eigenvalues(n)
+    U1 = sine_mode(n, 3)[:, None]
+    U2 = sine_mode(n, 5)[:, None]
+    U3 = sine_mode(n, 30)[:, None]
+    G = np.ones((1, 1, 1)) * 2.5
+    f, c, info = tucker.lr_solve3d(U1, U2, U3, G, 1e-10)
+    X = poisson.full_solve3d_tucker(U1, U2, U3, G)
+    assert info["rank"] == (1, 1, 1)
+    assert metrics.rel_err_tucker(f[0], f[1], f[2], c, X) < 1e-12
+    ref = 2.5 / (lam[2] + lam[4] + lam[29])
+    assert abs(abs(c[0, 0, 0]) - ref * np.prod(
+        [np.linalg.norm(u) for u in (U1, U2, U3)])) < 1e-10 * ref * 1e3
+
+
+# --------------------------------------------- planted mistakes are caught
+def _eigs_wrong_h(n):           # uses h = 1/n instead of 1/(n+1)
+    h = 1.0 / n
+    k = np.arange(1, n + 1)
+    return 4.0 / h ** 2 * np.sin(np.pi * k * h / 2) ** 2
+
+
+def _eigs_missing_square(n):    # drops the square on the sine
+    h = 1.0 / (n + 1)
+    k = np.arange(1, n + 1)
+    return 4.0 / h ** 2 * np.sin(np.pi * k * h / 2)
+
+
+def _solve_product_denominator(F):   # divides by lambda_i * lambda_j
+    n = F.shape[0]
+    lam = poisson.eigenvalues(n)
+    Fh = poisson.dst(poisson.dst(F, 0), 1)
+    return poisson.dst(poisson.dst(Fh / np.outer(lam, lam), 0), 1)
+
+
+def _solve_transposed(F):            # transposes the spectrum
+    n = F.shape[0]
+    lam = poisson.eigenvalues(n)
+    Fh = poisson.dst(poisson.dst(F, 0), 1).T
+    return poisson.dst(poisson.dst(Fh / (lam[:, None] + lam[None, :]), 0), 1)
+
+
+def _solve_index_shift(F):           # lambda off by one index
+    n = F.shape[0]
+    lam = np.roll(poisson.eigenvalues(n), 1)
+    Fh = poisson.dst(poisson.dst(F, 0), 1)
+    return poisson.dst(poisson.dst(Fh / (lam[:, None] + lam[None, :]), 0), 1)
+
+
+def _maxvol_no_pivot_scale(A, tau=1.05):
+    A = np.asarray(A)
+    n, k = A.shape
+    I = lowrank.gepp_rows(A)
+    B = np.linalg.solve(A[I, :].T, A.T).T
+    for _ in range(100 * k):
+        i, j = divmod(int(np.argmax(np.abs(B))), k)
+        if abs(B[i, j]) <= tau:
+            break
+        I[j] = i
+        row = B[i, :].copy()
+        row[j] -= 1.0
+        B -= np.outer(B[:, j], row)        # planted: drops the 1/B[i,j]
+    return I, B, 0
+
+
+def test_mutants_are_caught():
+    assert check_eigs(_eigs_wrong_h, 16) > 1e-3
+    assert check_eigs(_eigs_missing_square, 16) > 1e-3
+    assert check_solve_sylvester(_solve_product_denominator, 16) > 1e-3
+    assert check_solve_sylvester(_solve_transposed, 16) > 1e-3
+    assert check_solve_sylvester(_solve_index_shift, 16) > 1e-3
+    assert check_single_mode(_solve_index_shift, 64, 3, 9) > 1e-3
+    caught = False
+    for seed in range(6):
+        e_id, over, _ = check_maxvol(_maxvol_no_pivot_scale, 300, 12, seed,
+                                     tau=1.0001)
+        caught |= (e_id > 1e-6) or (over > 1e-6)
+    assert caught
