@@ -1,0 +1,226 @@
+/*
+ * lrpoisson.h -- C interface of the MI355X low-rank Poisson solver.
+ *
+ * Problem (Muravleva & Oseledets, "Fast low-rank solution of the Poisson
+ * equation with application to the Stokes problem", Section 4.1, eq. "pois"):
+ * solve the Dirichlet Poisson problem on the uniform tensor grid of
+ * [0,1]^d, d = 2 or 3, with n interior unknowns per axis, h = 1/(n+1),
+ *     2D:  T X + X T = F,                 T = h^-2 tridiag(-1, 2, -1),
+ *     3D:  (T(x)I(x)I + I(x)T(x)I + I(x)I(x)T) vec X = vec F,
+ * where the right-hand side arrives in low-rank form -- F = U V^T
+ * (Section 3, eq. "lr") or a Tucker tensor F = G x1 U1 x2 U2 x3 U3
+ * (Section 3, eq. "tucker") -- and the solution is returned in the same
+ * form, accurate to a relative Frobenius tolerance eps (Section 3: the
+ * accuracy is chosen consistent with the discretisation error).
+ *
+ * Method (Sections 4.1-4.2): sine transform of the factors (eq. "diag"),
+ * cross approximation with maxvol pivots of the divided spectrum
+ * Xh_ij = Fh_ij / (lambda_i + lambda_j) (eq. "div"; 3D: + lambda_l),
+ * rounding by QR/SVD to eps (Section 3), inverse transform of the factors.
+ *
+ * Conventions shared by every entry point
+ *  - All matrices are float64, column-major, in DEVICE memory of the
+ *    context's GPU (hipMalloc / torch CUDA tensors).  Leading dimensions are
+ *    in elements.  Input buffers are read-only; output buffers are owned and
+ *    allocated by the caller with capacity for ``rmax`` columns (the output
+ *    rank is not known in advance).
+ *  - ``stream`` is a hipStream_t (NULL = the default stream).  The
+ *    synchronous calls enqueue their work on ``stream`` and return after it
+ *    completed; inputs must stay valid until then.
+ *  - 2D output: Vx has orthonormal columns, Ux carries the scale, so
+ *    X ~= Ux Vx^T.  3D output: U1x, U2x, U3x have orthonormal columns and
+ *    the core Gx (r1 x r2 x r3, i1 fastest) carries the scale.
+ *  - Errors: LRP_EINVAL is returned before any device work for invalid
+ *    arguments (n < 1 or n > LRP_MAX_N, rank < 0 or > LRP_MAX_RANK,
+ *    eps outside (0, 1), a NULL pointer where one is needed, ld < n).
+ *    A rank-0 or all-zero right-hand side returns LRP_OK with rank 0.
+ *    LRP_ENONFINITE: the factors hold Inf/NaN (detected on the device).
+ *    LRP_ERANKCAP: the result needs more than ``rmax`` columns (rank_out is
+ *    set to the rank needed, outputs unspecified) or the cross reached the
+ *    rank cap without slack (best approximation written).
+ *    LRP_ENOCONV: the sweep cap was reached; the last approximation is
+ *    written and info->change holds its last relative change.
+ *    LRP_EDEVICE wraps a HIP runtime error; LRP_ENOMEM a failed allocation.
+ */
+#ifndef LRPOISSON_H
+#define LRPOISSON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LRP_MAX_N 32767   /* grid points per axis (sine table lives in LDS) */
+#define LRP_MAX_RANK 64   /* input rank and cross-rank cap                  */
+
+typedef enum {
+  LRP_OK = 0,
+  LRP_EINVAL = -1,
+  LRP_ENONFINITE = -2,
+  LRP_ERANKCAP = -3,
+  LRP_ENOCONV = -4,
+  LRP_ENOMEM = -5,
+  LRP_EDEVICE = -6,
+  LRP_EBUSY = -7,
+  LRP_ENOTREADY = -8
+} lrp_status;
+
+/* Arithmetic of the two sine-transform contractions (forward on the input
+ * factors, inverse on the output factors).  Everything else -- eigenvalue
+ * denominators, maxvol, QR, SVD, truncation -- is float64 in every mode.
+ *  FP64    float64 MFMA both ways.
+ *  FP32    float32 MFMA (float32 accumulation inside 64-deep K blocks,
+ *          float64 sum across blocks) both ways.
+ *  BF16X3  bfloat16 MFMA on a two-piece split of both operands, three
+ *          products (hi*hi + hi*lo + lo*hi), float32 accumulation inside
+ *          K blocks, float64 across blocks, both ways.
+ *  AUTO    per-request plan from eps: forward transform BF16X3 when
+ *          eps >= 1e-6, FP32 when eps >= 1e-8, else FP64; inverse transform
+ *          FP32 when eps >= 1e-7, else FP64.  The inverse transform passes its
+ *          relative rounding error straight to the result (measured floors:
+ *          FP32 ~2e-7, BF16X3 ~5e-6 on the 4096- and 8192-point bump
+ *          workloads); the forward one is damped by the division by the
+ *          eigenvalue sums. */
+typedef enum {
+  LRP_PREC_FP64 = 0,
+  LRP_PREC_AUTO = 1,
+  LRP_PREC_FP32 = 2,
+  LRP_PREC_BF16X3 = 3
+} lrp_precision;
+
+/* Optional knobs; pass NULL for defaults.  Zero fields take defaults. */
+typedef struct {
+  int32_t prec;         /* lrp_precision, default LRP_PREC_FP64             */
+  int32_t max_sweeps;   /* cross sweeps cap, default 10                     */
+  int32_t rank_cap;     /* cross rank cap k_max, default and max 64         */
+  int32_t kick;         /* cross rank growth step, default 8                */
+  double maxvol_tau;    /* maxvol dominance bound, default 1.05             */
+} lrp_opts;
+
+/* Per-solve report (may be NULL). */
+typedef struct {
+  int32_t status;       /* lrp_status of this solve                          */
+  int32_t sweeps;       /* cross sweeps run                                  */
+  int32_t k;            /* final cross rank                                  */
+  int32_t rank;         /* output rank (2D); 3D: first mode                  */
+  int32_t fwd_prec;     /* lrp_precision used by the forward transform       */
+  int32_t inv_prec;     /* lrp_precision used by the inverse transform       */
+  double change;        /* last relative change between sweeps (-1: none)   */
+} lrp_info;
+
+typedef struct lrp_ctx lrp_ctx;
+
+/* Create a solver context on HIP device ``device``.  ``workspace_bytes`` is
+ * the device-memory budget of the context (0 = 2 GiB); it bounds the
+ * workspace of concurrent solves and the served requests admitted at once.
+ * Device memory is allocated lazily inside that budget. */
+lrp_status lrp_create(lrp_ctx **ctx, int device, size_t workspace_bytes);
+
+/* Free every device allocation of the context.  Not thread-safe with
+ * concurrent calls on the same context. */
+lrp_status lrp_destroy(lrp_ctx *ctx);
+
+/* Text for a status code (static storage). */
+const char *lrp_strerror(int32_t status);
+
+/* One 2D solve (Section 4.2).  U, V: n x rank (ld >= n).  Ux, Vx: n x rmax
+ * (ldx >= n).  On return *rank_out holds the output rank R <= rmax and the
+ * first R columns of Ux, Vx are written. */
+lrp_status lrpoisson_solve2d(lrp_ctx *ctx, int64_t n, int32_t rank,
+                             const double *U, const double *V, int64_t ld,
+                             double eps, const lrp_opts *opts,
+                             double *Ux, double *Vx, int64_t ldx, int32_t rmax,
+                             int32_t *rank_out, lrp_info *info, void *stream);
+
+/* One 2D problem of a batch: the same fields as lrpoisson_solve2d. */
+typedef struct {
+  const double *U;
+  const double *V;
+  int64_t ld;
+  int32_t rank;
+  int32_t rmax;
+  double eps;
+  double *Ux;
+  double *Vx;
+  int64_t ldx;
+  int32_t rank_out;     /* output */
+  lrp_info info;        /* output */
+} lrp_problem2d;
+
+/* ``count`` independent 2D solves on the same grid size n, run together:
+ * every kernel launch covers all of them (one transform GEMM over all their
+ * columns, one launch per cross step).  Each problem's own result is the
+ * same as when it is solved alone.  Returns LRP_OK when every problem
+ * succeeded, otherwise the first failing problem's status; per-problem
+ * status is in probs[i].info.status. */
+lrp_status lrpoisson_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t count,
+                                   lrp_problem2d *probs, const lrp_opts *opts,
+                                   void *stream);
+
+/* One 3D solve in Tucker format.  U1, U2, U3: n x rank[d] (ld >= n);
+ * G: rank[0] x rank[1] x rank[2], i1 fastest.  Outputs U1x, U2x, U3x:
+ * n x rmax[d] (ldx >= n); Gx: capacity rmax[0]*rmax[1]*rmax[2], written as
+ * rank_out[0] x rank_out[1] x rank_out[2], i1 fastest. */
+lrp_status lrpoisson_solve3d(lrp_ctx *ctx, int64_t n, const int32_t rank[3],
+                             const double *U1, const double *U2,
+                             const double *U3, int64_t ld, const double *G,
+                             double eps, const lrp_opts *opts,
+                             double *U1x, double *U2x, double *U3x,
+                             int64_t ldx, double *Gx, const int32_t rmax[3],
+                             int32_t rank_out[3], lrp_info *info, void *stream);
+
+/* The orthonormal sine transform on its own (paper Section 4.1, eq. "diag":
+ * S[j,k] = sqrt(2/(n+1)) sin(pi j k/(n+1)), the DST-I that diagonalises the
+ * 1D operator; S = S^T = S^-1, so the same call transforms forward and
+ * back): dst[:, c] = S src[:, c] for c < ncols.  src: n x ncols (lds >= n),
+ * dst: n x ncols (ldd >= n), both float64 device memory, not overlapping.
+ * ``prec`` is an lrp_precision other than AUTO.  Non-finite input is not
+ * checked here. */
+lrp_status lrp_sine_transform(lrp_ctx *ctx, int64_t n, int32_t ncols,
+                              const double *src, int64_t lds, double *dst,
+                              int64_t ldd, int32_t prec, void *stream);
+
+/* ---- Continuous-batching serving (same solver, asynchronous) ----------
+ * A request is admitted when the context's device-memory budget has room
+ * for its workspace; its factors stay resident on the device.  Each call of
+ * lrp_serve_step() runs one scheduling tick on the context's own stream:
+ * newly admitted requests get their forward transform, every running 2D
+ * request advances one cross sweep, finished requests get their inverse
+ * transform -- all grouped by grid size into shared launches -- so work of
+ * requests that arrived at different times overlaps on the device. */
+typedef struct {
+  int32_t dim;          /* 2 or 3                                            */
+  int32_t prec;         /* lrp_precision                                     */
+  int64_t n;
+  int32_t rank[3];      /* 2D uses rank[0]                                   */
+  int32_t rmax[3];      /* output capacity; 2D uses rmax[0]                  */
+  const double *U[3];   /* 2D: U[0] = U, U[1] = V                            */
+  const double *G;      /* 3D core, else NULL                                */
+  int64_t ld;
+  double *X[3];         /* outputs; 2D: X[0] = Ux, X[1] = Vx                 */
+  double *Gx;           /* 3D output core                                    */
+  int64_t ldx;
+  double eps;
+} lrp_request;
+
+/* Queue a request; never blocks.  *ticket identifies it. */
+lrp_status lrp_submit(lrp_ctx *ctx, const lrp_request *req, uint64_t *ticket);
+
+/* Run one scheduling tick (admission, one step of every running request,
+ * retirement).  Returns the number of requests still queued or running in
+ * *pending. */
+lrp_status lrp_serve_step(lrp_ctx *ctx, int32_t *pending);
+
+/* Non-blocking completion check.  LRP_ENOTREADY while the request is queued
+ * or running; otherwise *result holds its status, rank_out[] its ranks and
+ * *info its report, and the ticket is released. */
+lrp_status lrp_poll(lrp_ctx *ctx, uint64_t ticket, int32_t *result,
+                    int32_t rank_out[3], lrp_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LRPOISSON_H */

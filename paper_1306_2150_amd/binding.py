@@ -1,0 +1,262 @@
+"""ctypes binding of ``liblrpoisson.so`` (declared in ``include/lrpoisson.h``).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  Device buffers are torch CUDA (HIP) float64 tensors in column-major
+layout (a tensor ``t`` of shape (n, r) with ``t.stride() == (1, ld)``, e.g.
+``torch.empty(r, n).T`` or ``x.T.contiguous().T``); the stream is torch's
+current stream unless one is given.  There is no CPU fallback: a missing
+library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                        "liblrpoisson.so")
+
+LRP_OK = 0
+LRP_EINVAL = -1
+LRP_ENONFINITE = -2
+LRP_ERANKCAP = -3
+LRP_ENOCONV = -4
+LRP_ENOMEM = -5
+LRP_EDEVICE = -6
+LRP_EBUSY = -7
+LRP_ENOTREADY = -8
+
+PREC = {"fp64": 0, "auto": 1, "fp32": 2, "bf16x3": 3}
+PREC_NAME = {v: k for k, v in PREC.items()}
+
+MAX_RANK = 64
+MAX_N = 32767
+
+# every symbol the header declares
+EXPORTS = ["lrp_create", "lrp_destroy", "lrp_strerror", "lrpoisson_solve2d",
+           "lrpoisson_solve2d_batch", "lrpoisson_solve3d", "lrp_submit",
+           "lrp_serve_step", "lrp_poll", "lrp_sine_transform"]
+
+
+class LrpOpts(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("rank_cap", ctypes.c_int32), ("kick", ctypes.c_int32),
+                ("maxvol_tau", ctypes.c_double)]
+
+
+class LrpInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("rank", ctypes.c_int32),
+                ("fwd_prec", ctypes.c_int32), ("inv_prec", ctypes.c_int32),
+                ("change", ctypes.c_double)]
+
+    def as_dict(self):
+        return dict(status=self.status, sweeps=self.sweeps, k=self.k,
+                    rank=self.rank, fwd_prec=PREC_NAME.get(self.fwd_prec),
+                    inv_prec=PREC_NAME.get(self.inv_prec), change=self.change)
+
+
+class LrpProblem2D(ctypes.Structure):
+    _fields_ = [("U", ctypes.c_void_p), ("V", ctypes.c_void_p),
+                ("ld", ctypes.c_int64), ("rank", ctypes.c_int32),
+                ("rmax", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("Ux", ctypes.c_void_p), ("Vx", ctypes.c_void_p),
+                ("ldx", ctypes.c_int64), ("rank_out", ctypes.c_int32),
+                ("info", LrpInfo)]
+
+
+class LrpRequest(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("n", ctypes.c_int64), ("rank", ctypes.c_int32 * 3),
+                ("rmax", ctypes.c_int32 * 3), ("U", ctypes.c_void_p * 3),
+                ("G", ctypes.c_void_p), ("ld", ctypes.c_int64),
+                ("X", ctypes.c_void_p * 3), ("Gx", ctypes.c_void_p),
+                ("ldx", ctypes.c_int64), ("eps", ctypes.c_double)]
+
+
+class LrpError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with `python -m paper_1306_2150_amd.build` "
+            "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    I32, I64, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.lrp_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, ctypes.c_size_t]
+    lib.lrp_destroy.argtypes = [P]
+    lib.lrp_strerror.argtypes = [I32]
+    lib.lrp_strerror.restype = ctypes.c_char_p
+    lib.lrpoisson_solve2d.argtypes = [P, I64, I32, P, P, I64, F64,
+                                      ctypes.POINTER(LrpOpts), P, P, I64, I32,
+                                      ctypes.POINTER(I32), ctypes.POINTER(LrpInfo), P]
+    lib.lrpoisson_solve2d_batch.argtypes = [P, I64, I32, ctypes.POINTER(LrpProblem2D),
+                                            ctypes.POINTER(LrpOpts), P]
+    lib.lrpoisson_solve3d.argtypes = [P, I64, ctypes.POINTER(I32), P, P, P, I64, P,
+                                      F64, ctypes.POINTER(LrpOpts), P, P, P, I64, P,
+                                      ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                      ctypes.POINTER(LrpInfo), P]
+    lib.lrp_sine_transform.argtypes = [P, I64, I32, P, I64, P, I64, I32, P]
+    lib.lrp_submit.argtypes = [P, ctypes.POINTER(LrpRequest), ctypes.POINTER(ctypes.c_uint64)]
+    lib.lrp_serve_step.argtypes = [P, ctypes.POINTER(I32)]
+    lib.lrp_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(I32),
+                             ctypes.POINTER(I32), ctypes.POINTER(LrpInfo)]
+    for name in EXPORTS:
+        f = getattr(lib, name)
+        if name != "lrp_strerror":
+            f.restype = ctypes.c_int32
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    if _lib is None:
+        return f"status {status}"
+    return _lib.lrp_strerror(status).decode()
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _ld(t) -> int:
+    """Leading dimension of a column-major (n, r) float64 CUDA tensor."""
+    import torch
+    if t.dtype != torch.float64 or not t.is_cuda:
+        raise ValueError("factors must be float64 tensors on the GPU")
+    if t.dim() != 2 or t.stride(0) != 1:
+        raise ValueError("factors must be column-major (stride(0) == 1)")
+    return max(t.stride(1), t.shape[0])
+
+
+def colmajor(a, device="cuda"):
+    """Copy an (n, r) array / tensor to a column-major float64 GPU tensor."""
+    import numpy as np
+    import torch
+    x = torch.as_tensor(np.asarray(a, dtype=np.float64))
+    n, r = x.shape
+    out = torch.empty((r, n), dtype=torch.float64, device=device).T
+    out.copy_(x.to(device))
+    return out
+
+
+def empty_colmajor(n, r, device="cuda"):
+    import torch
+    return torch.empty((max(r, 1), n), dtype=torch.float64, device=device).T[:, :r]
+
+
+def _opts(prec="fp64", max_sweeps=0, rank_cap=0, kick=0, tau=0.0):
+    return LrpOpts(PREC[prec] if isinstance(prec, str) else int(prec),
+                   max_sweeps, rank_cap, kick, tau)
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(int(s.cuda_stream))
+
+
+class Context:
+    """Solver context on one GPU (owns tables and workspace)."""
+
+    def __init__(self, device: int = 0, workspace_bytes: int = 0):
+        self.lib = load()
+        self.h = ctypes.c_void_p()
+        st = self.lib.lrp_create(ctypes.byref(self.h), device, workspace_bytes)
+        if st != LRP_OK:
+            raise LrpError(st, "lrp_create")
+        self.device = device
+
+    def close(self):
+        if self.h:
+            self.lib.lrp_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- 2D
+    def solve2d(self, U, V, eps, rmax=None, prec="fp64", stream=None, check=True,
+                **kw):
+        """Solve T X + X T = U V^T; returns (Ux, Vx, info) with X ~= Ux Vx^T."""
+        n, r = U.shape
+        rmax = MAX_RANK if rmax is None else rmax
+        Ux = empty_colmajor(n, rmax, U.device)
+        Vx = empty_colmajor(n, rmax, U.device)
+        rank = ctypes.c_int32(0)
+        info = LrpInfo()
+        opts = _opts(prec, **kw)
+        st = self.lib.lrpoisson_solve2d(
+            self.h, n, r, _ptr(U), _ptr(V), _ld(U) if r else n, eps,
+            ctypes.byref(opts), _ptr(Ux), _ptr(Vx), n, rmax, ctypes.byref(rank),
+            ctypes.byref(info), _stream(stream))
+        if check and st not in (LRP_OK,):
+            raise LrpError(st, "lrpoisson_solve2d")
+        R = rank.value
+        d = info.as_dict()
+        d["status_code"] = st
+        return Ux[:, :R], Vx[:, :R], d
+
+    def solve2d_batch(self, problems, prec="fp64", stream=None, rmax=None, **kw):
+        """problems: list of (U, V, eps) on one grid size.  Returns a list of
+        (Ux, Vx, info)."""
+        if not problems:
+            return []
+        n = problems[0][0].shape[0]
+        rmax = MAX_RANK if rmax is None else rmax
+        arr = (LrpProblem2D * len(problems))()
+        outs = []
+        for i, (U, V, eps) in enumerate(problems):
+            Ux = empty_colmajor(n, rmax, U.device)
+            Vx = empty_colmajor(n, rmax, U.device)
+            outs.append((Ux, Vx))
+            r = U.shape[1]
+            arr[i] = LrpProblem2D(_ptr(U), _ptr(V), _ld(U) if r else n, r, rmax,
+                                  eps, _ptr(Ux), _ptr(Vx), n, 0, LrpInfo())
+        opts = _opts(prec, **kw)
+        st = self.lib.lrpoisson_solve2d_batch(self.h, n, len(problems), arr,
+                                              ctypes.byref(opts), _stream(stream))
+        if st in (LRP_EINVAL, LRP_EDEVICE, LRP_ENOMEM):
+            raise LrpError(st, "lrpoisson_solve2d_batch")
+        res = []
+        for i, (Ux, Vx) in enumerate(outs):
+            R = arr[i].rank_out
+            d = arr[i].info.as_dict()
+            res.append((Ux[:, :R], Vx[:, :R], d))
+        return res
+
+    # ---- sine transform
+    def sine_transform(self, X, prec="fp64", out=None, stream=None):
+        """S X for a column-major (n, c) float64 GPU tensor."""
+        n, c = X.shape
+        Y = empty_colmajor(n, c, X.device) if out is None else out
+        st = self.lib.lrp_sine_transform(self.h, n, c, _ptr(X), _ld(X), _ptr(Y),
+                                         _ld(Y) if c else n, PREC[prec],
+                                         _stream(stream))
+        if st != LRP_OK:
+            raise LrpError(st, "lrp_sine_transform")
+        return Y
+
+    # ---- raw call for argument-validation tests
+    def raw_solve2d(self, n, r, U, V, ld, eps, Ux, Vx, ldx, rmax, prec=0):
+        rank = ctypes.c_int32(-1)
+        info = LrpInfo()
+        opts = _opts(prec)
+        return self.lib.lrpoisson_solve2d(self.h, n, r, U, V, ld, eps,
+                                          ctypes.byref(opts), Ux, Vx, ldx, rmax,
+                                          ctypes.byref(rank), ctypes.byref(info),
+                                          None), rank.value

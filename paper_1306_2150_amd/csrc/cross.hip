@@ -1,0 +1,422 @@
+// Cross approximation of the divided spectrum (paper Section 4.2).
+//
+// Entries: Xh_ij = (Uh_i . Vh_j) / (lambda_i + lambda_j)   (eq. "div") -- a
+// rank-r numerator over a rank-2 denominator, O(r) per entry.  A sweep with
+// column set J evaluates the columns Xh[:, J] (k_eval, EV_COLS), orthonormalises
+// them, picks rows I by maxvol, evaluates the rows Xh[I, :] (EV_ROWS),
+// orthonormalises those, picks the next columns Jn by maxvol, and rounds the
+// skeleton through the k x k core (svd.hip).  This file also holds the
+// per-sweep bookkeeping: the skeleton factors A = Q0 W S, B = Q1 Z, the change
+// ||A B^T - Ap Bp^T||_F against the previous sweep, the truncation rank, the
+// rank-growth columns and the stop decision.
+//
+// Change between sweeps without cancellation: with B, Bp orthonormal and
+// M = Bp^T B,   ||A B^T - Ap Bp^T||^2 = ||A - Ap M||^2 + sum_a sp_a^2 ||E_a||^2,
+// E = Bp - B M^T, because Ap^T Ap = diag(sp^2).  Every term is a direct
+// difference of n-row panels, so the result keeps full relative accuracy
+// down to changes of 1e-14 ||X||.
+#include "lrp_internal.h"
+
+namespace lrp {
+namespace {
+
+template <int KM>
+__global__ __launch_bounds__(NTHR) void k_eval(int which, int n,
+                                              const double *__restrict__ lam,
+                                              Solve2D *S) {
+  Solve2D &s = S[blockIdx.y];
+  if (s.active != ACT_SWEEP) return;
+  __shared__ double qs[KMAX * KMAX];   // [alpha][l]
+  __shared__ double ls[KMAX];
+  const double *P, *Qm;
+  const int *sel;
+  if (which == EV_COLS) {
+    P = s.Uh, Qm = s.Vh, sel = s.J;
+  } else {
+    P = s.Vh, Qm = s.Uh, sel = s.I;
+  }
+  const int kk = s.k, r = s.r;
+  for (int e = threadIdx.x; e < r * kk; e += NTHR) {
+    const int a = e / kk, l = e - a * kk;
+    qs[a * KMAX + l] = Qm[clamp_row(sel[l], n) + (long)a * n];
+  }
+  for (int l = threadIdx.x; l < kk; l += NTHR) ls[l] = lam[clamp_row(sel[l], n)];
+  __syncthreads();
+  const int i = blockIdx.x * NTHR + threadIdx.x;
+  if (i >= n) return;
+  double acc[KM];
+#pragma unroll
+  for (int l = 0; l < KM; ++l) acc[l] = 0.0;
+  for (int a = 0; a < r; ++a) {
+    const double p = P[i + (long)a * n];
+#pragma unroll
+    for (int l = 0; l < KM; ++l) acc[l] += p * qs[a * KMAX + l];
+  }
+  const double li = lam[i];
+#pragma unroll
+  for (int l = 0; l < KM; ++l)
+    if (l < kk) s.C[i + (long)l * n] = acc[l] / (li + ls[l]);
+}
+
+// A = Q0 (W diag(sig))  (z = 0),  B = Q1 Z  (z = 1), all k columns.
+template <int KM>
+__global__ __launch_bounds__(NTHR) void k_factors(int n, Solve2D *S) {
+  Solve2D &s = S[blockIdx.y];
+  if (s.active != ACT_SWEEP) return;
+  __shared__ double M[KMAX * KMAX];   // [j][c]
+  const int kk = s.k, z = blockIdx.z;
+  const double *Qz = z ? s.Q1 : s.Q0;
+  double *out = z ? s.B : s.A;
+  for (int e = threadIdx.x; e < kk * kk; e += NTHR) {
+    const int j = e / kk, c = e - j * kk;
+    M[j * KMAX + c] = z ? s.Z[j + c * KMAX] : s.W[j + c * KMAX] * s.sig[c];
+  }
+  __syncthreads();
+  const int i = blockIdx.x * NTHR + threadIdx.x;
+  if (i >= n) return;
+  double acc[KM];
+#pragma unroll
+  for (int c = 0; c < KM; ++c) acc[c] = 0.0;
+  for (int j = 0; j < kk; ++j) {
+    const double q = Qz[i + (long)j * n];
+#pragma unroll
+    for (int c = 0; c < KM; ++c) acc[c] += q * M[j * KMAX + c];
+  }
+#pragma unroll
+  for (int c = 0; c < KM; ++c)
+    if (c < kk) out[i + (long)c * n] = acc[c];
+}
+
+// Partial M = Bp^T B over one 256-row block.
+__global__ __launch_bounds__(NTHR) void k_change_M(int n, Solve2D *S) {
+  Solve2D &s = S[blockIdx.y];
+  if (s.active != ACT_SWEEP || s.kp == 0) return;
+  __shared__ double bp[64 * (KMAX + 1)];
+  __shared__ double bb[64 * (KMAX + 1)];
+  const int kk = s.k, kq = s.kp;
+  const int r0 = blockIdx.x * PANEL_M;
+  const int nout = kq * kk;
+  double acc[16];
+#pragma unroll
+  for (int t = 0; t < 16; ++t) acc[t] = 0.0;
+  for (int ch = 0; ch < PANEL_M / 64; ++ch) {
+    const int rb = r0 + ch * 64;
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * KMAX; e += NTHR) {
+      const int c = e / 64, rr = e - c * 64;
+      const int row = rb + rr;
+      const bool ok = row < n;
+      bp[rr * (KMAX + 1) + c] = (ok && c < kq) ? s.Bp[row + (long)c * n] : 0.0;
+      bb[rr * (KMAX + 1) + c] = (ok && c < kk) ? s.B[row + (long)c * n] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+      const int o = threadIdx.x + NTHR * t;
+      if (o < nout) {
+        const int a = o / kk, c = o - a * kk;
+        double v = 0.0;
+        for (int rr = 0; rr < 64; ++rr) v += bp[rr * (KMAX + 1) + a] * bb[rr * (KMAX + 1) + c];
+        acc[t] += v;
+      }
+    }
+  }
+  double *P = s.part + (size_t)blockIdx.x * KMAX * KMAX;
+#pragma unroll
+  for (int t = 0; t < 16; ++t) {
+    const int o = threadIdx.x + NTHR * t;
+    if (o < nout) P[o] = acc[t];
+  }
+}
+
+__global__ __launch_bounds__(NTHR) void k_change_reduce(int nb0, Solve2D *S) {
+  Solve2D &s = S[blockIdx.x];
+  if (s.active != ACT_SWEEP || s.kp == 0) return;
+  const int kk = s.k, kq = s.kp;
+  for (int o = threadIdx.x; o < kq * kk; o += NTHR) {
+    double v = 0.0;
+    for (int b = 0; b < nb0; ++b) v += s.part[(size_t)b * KMAX * KMAX + o];
+    const int a = o / kk, c = o - a * kk;
+    s.Mc[a * KMAX + c] = v;
+  }
+}
+
+template <int KM>
+__global__ __launch_bounds__(NTHR) void k_change_norms(int n, Solve2D *S) {
+  Solve2D &s = S[blockIdx.y];
+  if (s.active != ACT_SWEEP || s.kp == 0) return;
+  __shared__ double M[KMAX * KMAX];
+  __shared__ double sp2[KMAX];
+  __shared__ double red[2][4];
+  const int kk = s.k, kq = s.kp;
+  for (int e = threadIdx.x; e < KMAX * KMAX; e += NTHR) M[e] = s.Mc[e];
+  for (int a = threadIdx.x; a < kq; a += NTHR) sp2[a] = s.sigp[a] * s.sigp[a];
+  __syncthreads();
+  const int i = blockIdx.x * NTHR + threadIdx.x;
+  double n1 = 0.0, n2 = 0.0;
+  if (i < n) {
+    double v[KM];
+#pragma unroll
+    for (int a = 0; a < KM; ++a) v[a] = (a < kq) ? s.Ap[i + (long)a * n] : 0.0;
+    for (int c = 0; c < kk; ++c) {
+      double x = s.A[i + (long)c * n];
+#pragma unroll
+      for (int a = 0; a < KM; ++a) x -= v[a] * M[a * KMAX + c];
+      n1 += x * x;
+    }
+#pragma unroll
+    for (int c = 0; c < KM; ++c) v[c] = (c < kk) ? s.B[i + (long)c * n] : 0.0;
+    for (int a = 0; a < kq; ++a) {
+      double x = s.Bp[i + (long)a * n];
+#pragma unroll
+      for (int c = 0; c < KM; ++c) x -= v[c] * M[a * KMAX + c];
+      n2 += sp2[a] * x * x;
+    }
+  }
+  n1 = wave_sum(n1);
+  n2 = wave_sum(n2);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[0][wave] = n1, red[1][wave] = n2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s.part[(size_t)blockIdx.x * 2 + 0] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    s.part[(size_t)blockIdx.x * 2 + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+  }
+}
+
+// count evenly spaced indices in [0, n) avoiding used[0:nu); floor((2i+1)n/(2count))
+// moved to the next free index (cyclically).  Single thread.
+__device__ void spread_indices(int n, int count, int *used, int nu, int *out) {
+  int have = nu;
+  for (int i = 0; i < count; ++i) {
+    if (have >= n) break;
+    int j = (int)(((long long)(2 * i + 1) * n) / (2LL * count));
+    for (;;) {
+      bool taken = false;
+      for (int t = 0; t < have; ++t)
+        if (used[t] == j) {
+          taken = true;
+          break;
+        }
+      if (!taken) break;
+      j = (j + 1) % n;
+    }
+    used[have++] = j;
+    out[i] = j;
+  }
+}
+
+// Truncation rank, convergence and growth decision (one workgroup / solve).
+__global__ __launch_bounds__(NTHR) void k_decide(int n, int nb0, Solve2D *S) {
+  Solve2D &s = S[blockIdx.x];
+  if (s.active != ACT_SWEEP) return;
+  __shared__ int used[2 * KMAX];
+  if (threadIdx.x != 0) return;
+  const int kk = s.k;
+  double change = -1.0;
+  if (s.kp > 0) {
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < nb0; ++i) a += s.part[2 * i], b += s.part[2 * i + 1];
+    change = sqrt(a + b);
+  }
+  double tot = 0.0;
+  for (int i = 0; i < kk; ++i) tot += s.sig[i] * s.sig[i];
+  const double nrm = sqrt(tot);
+  // smallest R with ||sig[R:]|| <= eps ||sig||
+  int R = kk;
+  double tail = 0.0;
+  for (int t = kk; t >= 0; --t) {
+    if (t < kk) tail += s.sig[t] * s.sig[t];
+    if (sqrt(tail) <= s.eps * nrm) R = t;
+    else break;
+  }
+  if (nrm == 0.0) R = 0;
+  const bool no_slack = (R > kk - s.min_slack) && (kk < n);
+  int next = NEXT_CONTINUE;
+  if (s.nonfinite) {
+    next = NEXT_STOP;
+    s.status = LRP_ENONFINITE;
+  } else if (nrm == 0.0) {
+    next = NEXT_STOP;
+    s.status = LRP_OK;
+  } else if (no_slack && kk < s.kcap) {
+    next = NEXT_GROW;
+    s.kgrow = min(s.kick, s.kcap - kk);
+  } else if (change >= 0.0 && change <= s.eps * nrm) {
+    next = NEXT_STOP;
+    s.status = no_slack ? LRP_ERANKCAP : LRP_OK;
+  }
+  s.sweep += 1;
+  if (next != NEXT_STOP && s.sweep >= s.max_sweeps) {
+    next = NEXT_STOP;
+    s.status = LRP_ENOCONV;
+  }
+  s.R = R;
+  s.nrm = nrm;
+  s.change = (change >= 0.0 && nrm > 0.0) ? change / nrm : -1.0;
+  s.next = next;
+  if (next == NEXT_GROW) {
+    for (int t = 0; t < kk; ++t) used[t] = s.I[t];
+    spread_indices(n, s.kick, used, kk, s.probe);
+  }
+}
+
+// Residual score of every column on the probe rows (rank growth).
+template <int KM>
+__global__ __launch_bounds__(NTHR) void k_growth_score(int n,
+                                                      const double *__restrict__ lam,
+                                                      Solve2D *S) {
+  Solve2D &s = S[blockIdx.y];
+  if (s.active != ACT_SWEEP || s.next != NEXT_GROW) return;
+  constexpr int PQ = 16;
+  __shared__ double uP[PQ * KMAX];
+  __shared__ double aP[PQ * KMAX];
+  __shared__ double lP[PQ];
+  const int kk = s.k, r = s.r, nq = min(s.kick, PQ);
+  for (int e = threadIdx.x; e < nq * KMAX; e += NTHR) {
+    const int q = e / KMAX, c = e - q * KMAX;
+    const int p = clamp_row(s.probe[q], n);
+    uP[e] = (c < r) ? s.Uh[p + (long)c * n] : 0.0;
+    aP[e] = (c < kk) ? s.A[p + (long)c * n] : 0.0;
+  }
+  for (int q = threadIdx.x; q < nq; q += NTHR) lP[q] = lam[clamp_row(s.probe[q], n)];
+  __syncthreads();
+  const int j = blockIdx.x * NTHR + threadIdx.x;
+  if (j >= n) return;
+  double num[PQ], skel[PQ];
+#pragma unroll
+  for (int q = 0; q < PQ; ++q) num[q] = skel[q] = 0.0;
+  for (int c = 0; c < r; ++c) {
+    const double vc = s.Vh[j + (long)c * n];
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) num[q] += uP[q * KMAX + c] * vc;
+  }
+  for (int c = 0; c < kk; ++c) {
+    const double bc = s.B[j + (long)c * n];
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) skel[q] += aP[q * KMAX + c] * bc;
+  }
+  const double lj = lam[j];
+  double best = 0.0;
+#pragma unroll
+  for (int q = 0; q < PQ; ++q)
+    if (q < nq) best = fmax(best, fabs(num[q] / (lP[q] + lj) - skel[q]));
+  s.score[j] = best;
+}
+
+// Next column set and state swap (one workgroup / solve).
+__global__ __launch_bounds__(NTHR) void k_finalize(int n, Solve2D *S) {
+  Solve2D &s = S[blockIdx.x];
+  if (s.active != ACT_SWEEP) return;
+  __shared__ double rv[4];
+  __shared__ int rk[4];
+  const int kk = s.k;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (s.next == NEXT_GROW) {
+    for (int t = threadIdx.x; t < kk; t += NTHR) s.score[clamp_row(s.Jn[t], n)] = -1.0;
+    __syncthreads();
+    for (int g = 0; g < s.kgrow; ++g) {
+      double best = -2.0;
+      int key = 0x7fffffff;
+      for (int j = threadIdx.x; j < n; j += NTHR) {
+        const double v = s.score[j];
+        if (v > best || (v == best && j < key)) best = v, key = j;
+      }
+      wave_argmax(best, key);
+      if (lane == 0) rv[wave] = best, rk[wave] = key;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double bv = rv[0];
+        int bk = rk[0];
+        for (int w = 1; w < 4; ++w)
+          if (rv[w] > bv || (rv[w] == bv && rk[w] < bk)) bv = rv[w], bk = rk[w];
+        s.J[kk + g] = bk;
+        s.score[bk] = -1.0;
+      }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  if (s.next == NEXT_STOP) {
+    s.active = ACT_DONE;
+    return;
+  }
+  for (int t = 0; t < kk; ++t) s.J[t] = s.Jn[t];
+  double *t;
+  t = s.A, s.A = s.Ap, s.Ap = t;
+  t = s.B, s.B = s.Bp, s.Bp = t;
+  t = s.sig, s.sig = s.sigp, s.sigp = t;
+  s.kp = kk;
+  s.k = kk + (s.next == NEXT_GROW ? s.kgrow : 0);
+}
+
+// After the initial maxvol on the transformed V: pad J to k0 columns.
+__global__ void k_init_J(int n, Solve2D *S) {
+  Solve2D &s = S[blockIdx.x];
+  if (s.active != ACT_INIT || threadIdx.x != 0) return;
+  if (s.nonfinite) {
+    s.active = ACT_DONE;
+    s.status = LRP_ENONFINITE;
+    return;
+  }
+  __shared__ int used[2 * KMAX];
+  const int kin = s.k, k0 = s.k0;
+  for (int t = 0; t < kin; ++t) used[t] = s.J[t];
+  if (k0 > kin) spread_indices(n, k0 - kin, used, kin, s.J + kin);
+  s.k = k0;
+  s.kp = 0;
+  s.sweep = 0;
+  s.active = ACT_SWEEP;
+}
+
+}  // namespace
+
+hipError_t launch_eval(int which, int n, const double *lam, Solve2D *s,
+                       int nsolves, int kmax, hipStream_t st) {
+  dim3 g(ceil_div(n, NTHR), nsolves);
+  if (kmax <= 16) hipLaunchKernelGGL((k_eval<16>), g, dim3(NTHR), 0, st, which, n, lam, s);
+  else if (kmax <= 32) hipLaunchKernelGGL((k_eval<32>), g, dim3(NTHR), 0, st, which, n, lam, s);
+  else hipLaunchKernelGGL((k_eval<64>), g, dim3(NTHR), 0, st, which, n, lam, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_factors(int n, Solve2D *s, int nsolves, int kmax,
+                          hipStream_t st) {
+  dim3 g(ceil_div(n, NTHR), nsolves, 2);
+  if (kmax <= 16) hipLaunchKernelGGL((k_factors<16>), g, dim3(NTHR), 0, st, n, s);
+  else if (kmax <= 32) hipLaunchKernelGGL((k_factors<32>), g, dim3(NTHR), 0, st, n, s);
+  else hipLaunchKernelGGL((k_factors<64>), g, dim3(NTHR), 0, st, n, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_change(int n, int nb0, Solve2D *s, int nsolves, int kmax,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_change_M, dim3(nb0, nsolves), dim3(NTHR), 0, st, n, s);
+  hipLaunchKernelGGL(k_change_reduce, dim3(nsolves), dim3(NTHR), 0, st, nb0, s);
+  dim3 g(ceil_div(n, NTHR), nsolves);
+  if (kmax <= 16) hipLaunchKernelGGL((k_change_norms<16>), g, dim3(NTHR), 0, st, n, s);
+  else if (kmax <= 32) hipLaunchKernelGGL((k_change_norms<32>), g, dim3(NTHR), 0, st, n, s);
+  else hipLaunchKernelGGL((k_change_norms<64>), g, dim3(NTHR), 0, st, n, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_decide(int n, const double *lam, Solve2D *s, int nsolves,
+                         int kmax, int nb0, hipStream_t st) {
+  hipLaunchKernelGGL(k_decide, dim3(nsolves), dim3(NTHR), 0, st, n,
+                     ceil_div(n, NTHR), s);
+  dim3 g(ceil_div(n, NTHR), nsolves);
+  if (kmax <= 16) hipLaunchKernelGGL((k_growth_score<16>), g, dim3(NTHR), 0, st, n, lam, s);
+  else if (kmax <= 32) hipLaunchKernelGGL((k_growth_score<32>), g, dim3(NTHR), 0, st, n, lam, s);
+  else hipLaunchKernelGGL((k_growth_score<64>), g, dim3(NTHR), 0, st, n, lam, s);
+  hipLaunchKernelGGL(k_finalize, dim3(nsolves), dim3(NTHR), 0, st, n, s);
+  (void)nb0;
+  return hipGetLastError();
+}
+
+hipError_t launch_init_J(int n, Solve2D *s, int nsolves, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_J, dim3(nsolves), dim3(64), 0, st, n, s);
+  return hipGetLastError();
+}
+
+}  // namespace lrp

@@ -1,0 +1,610 @@
+// Host runtime: context, per-grid tables, 2D slot groups, synchronous C API.
+#include "host.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+namespace lrp {
+
+#define HIPCHK(x)                         \
+  do {                                    \
+    hipError_t e_ = (x);                  \
+    if (e_ != hipSuccess) return LRP_EDEVICE; \
+  } while (0)
+
+lrp_status dev_alloc(lrp_ctx *ctx, void **p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return LRP_OK;
+  if (ctx->used + bytes > ctx->budget) return LRP_ENOMEM;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    return LRP_ENOMEM;
+  }
+  ctx->used += bytes;
+  return LRP_OK;
+}
+
+void dev_free(lrp_ctx *ctx, void *p, size_t bytes) {
+  if (!p) return;
+  (void)hipFree(p);
+  ctx->used -= std::min(ctx->used, bytes);
+}
+
+static uint32_t bf16_rne_host(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+static float bf16_float_host(uint32_t b) {
+  uint32_t u = b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// Quarter-wave tables of sqrt(2/N) sin(pi q/N), q = 0..floor(N/2), and the
+// eigenvalues lambda_k = 4/h^2 sin^2(pi k/(2N)), h = 1/N, N = n+1, evaluated
+// in long double and rounded once.
+const GridTables *get_tables(lrp_ctx *ctx, int n, lrp_status *err) {
+  *err = LRP_OK;
+  auto it = ctx->tables.find(n);
+  if (it != ctx->tables.end()) return &it->second;
+  const int N = n + 1;
+  const int Q = N / 2 + 1;
+  const int Qp8 = (Q + 1) & ~1, Qp4 = (Q + 3) & ~3;
+  const size_t tab_bytes = (size_t)Qp8 * 8 + (size_t)Qp4 * 4 + (size_t)Qp4 * 4;
+  std::vector<char> host(tab_bytes, 0);
+  double *t64 = (double *)host.data();
+  float *t32 = (float *)(host.data() + (size_t)Qp8 * 8);
+  uint32_t *tbf = (uint32_t *)(host.data() + (size_t)Qp8 * 8 + (size_t)Qp4 * 4);
+  const long double pi = 3.14159265358979323846264338327950288L;
+  const long double scale = sqrtl(2.0L / (long double)N);
+  for (int q = 0; q < Q; ++q) {
+    const long double v = scale * sinl(pi * (long double)q / (long double)N);
+    t64[q] = (double)v;
+    t32[q] = (float)v;
+    const uint32_t hi = bf16_rne_host((float)v);
+    const uint32_t lo = bf16_rne_host((float)(v - (long double)bf16_float_host(hi)));
+    tbf[q] = hi | (lo << 16);
+  }
+  std::vector<double> lam(n);
+  const long double N2 = (long double)N * (long double)N;
+  for (int k = 1; k <= n; ++k) {
+    const long double s = sinl(pi * (long double)k / (2.0L * (long double)N));
+    lam[k - 1] = (double)(4.0L * N2 * s * s);
+  }
+  GridTables g;
+  g.n = n;
+  g.bytes = tab_bytes + (size_t)n * 8;
+  void *p = nullptr;
+  *err = dev_alloc(ctx, &p, g.bytes);
+  if (*err != LRP_OK) return nullptr;
+  g.tab = p;
+  g.lam = (double *)((char *)p + tab_bytes);
+  if (hipMemcpy(g.tab, host.data(), tab_bytes, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(g.lam, lam.data(), (size_t)n * 8, hipMemcpyHostToDevice) != hipSuccess) {
+    dev_free(ctx, p, g.bytes);
+    *err = LRP_EDEVICE;
+    return nullptr;
+  }
+  auto res = ctx->tables.emplace(n, g);
+  return &res.first->second;
+}
+
+Plan make_plan(const lrp_opts *o, double eps, int n) {
+  Plan p;
+  int prec = o ? o->prec : LRP_PREC_FP64;
+  p.max_sweeps = (o && o->max_sweeps > 0) ? o->max_sweeps : 10;
+  p.kcap = (o && o->rank_cap > 0) ? std::min(o->rank_cap, KMAX) : KMAX;
+  p.kcap = std::min(p.kcap, n);
+  p.kick = (o && o->kick > 0) ? std::min(o->kick, 16) : 8;
+  p.min_slack = std::max(1, p.kick / 2);
+  p.tau = (o && o->maxvol_tau > 1.0) ? o->maxvol_tau : 1.05;
+  if (prec == LRP_PREC_AUTO) {
+    // the inverse transform's relative error reaches the result undamped;
+    // the forward one is damped by the eigenvalue division
+    p.fwd_prec = eps >= 1e-6 ? LRP_PREC_BF16X3 : (eps >= 1e-8 ? LRP_PREC_FP32 : LRP_PREC_FP64);
+    p.inv_prec = eps >= 1e-7 ? LRP_PREC_FP32 : LRP_PREC_FP64;
+  } else if (prec == LRP_PREC_FP32 || prec == LRP_PREC_BF16X3) {
+    p.fwd_prec = p.inv_prec = prec;
+  } else {
+    p.fwd_prec = p.inv_prec = LRP_PREC_FP64;
+  }
+  return p;
+}
+
+// ------------------------------------------------------------- Group2D
+struct Layout {
+  size_t off_Uh, off_Vh, off_panels, off_treeR, off_treeH, off_treeTau,
+      off_treeY, off_small, off_part, off_mvval, off_score, off_ints, total;
+};
+
+static size_t tree_nodes(const Tree &t, int from) {
+  size_t s = 0;
+  for (int l = from; l < t.nlev; ++l) s += t.nb[l];
+  return s;
+}
+
+static Layout slot_layout(int n, const Tree &t) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = o;
+    o += (bytes + 255) & ~(size_t)255;
+    return r;
+  };
+  const size_t nb0 = t.nb[0];
+  L.off_Uh = take((size_t)n * KMAX * 8);
+  L.off_Vh = take((size_t)n * KMAX * 8);
+  L.off_panels = take((size_t)8 * n * KMAX * 8);
+  L.off_treeR = take(tree_nodes(t, 0) * KMAX * KMAX * 8);
+  L.off_treeH = take(std::max<size_t>(1, tree_nodes(t, 1)) * PANEL_M * KMAX * 8);
+  L.off_treeTau = take(tree_nodes(t, 0) * KMAX * 8);
+  L.off_treeY = take(tree_nodes(t, 0) * KMAX * KMAX * 8);
+  L.off_small = take((size_t)(7 * KMAX * KMAX + 2 * KMAX) * 8);
+  L.off_part = take(std::max<size_t>(nb0, 1) * KMAX * KMAX * 8);
+  L.off_mvval = take(nb0 * MV_TOP * 8);
+  L.off_score = take((size_t)n * 8);
+  L.off_ints = take((tree_nodes(t, 0) * KMAX + nb0 * MV_TOP + 4 * KMAX) * 4);
+  L.total = o;
+  return L;
+}
+
+Group2D::Group2D(lrp_ctx *ctx, int n, int cap) : ctx_(ctx), n_(n), cap_(cap) {}
+
+Group2D::~Group2D() {
+  dev_free(ctx_, ws_, bytes_);
+  if (h_s_) (void)hipHostFree(h_s_);
+  if (h_cols_) (void)hipHostFree(h_cols_);
+}
+
+lrp_status Group2D::init() {
+  lrp_status err;
+  tabs_ = get_tables(ctx_, n_, &err);
+  if (!tabs_) return err;
+  talloc_ = make_tree(n_, KMAX);
+  const Layout L = slot_layout(n_, talloc_);
+  per_slot_ = L.total;
+  cols_cap_ = cap_ * 2 * KMAX;
+  partial_elems_ = dst_partial_elems(n_, std::min(cols_cap_, 4 * KMAX));
+  const size_t solves_b = ((size_t)cap_ * sizeof(Solve2D) + 255) & ~(size_t)255;
+  const size_t cols_b = ((size_t)cols_cap_ * sizeof(DstCol) + 255) & ~(size_t)255;
+  const size_t part_b = partial_elems_ * 8;
+  bytes_ = per_slot_ * cap_ + solves_b + cols_b + part_b;
+  void *p = nullptr;
+  err = dev_alloc(ctx_, &p, bytes_);
+  if (err != LRP_OK) return err;
+  ws_ = (char *)p;
+  d_s_ = (Solve2D *)(ws_ + per_slot_ * cap_);
+  d_cols_ = (DstCol *)((char *)d_s_ + solves_b);
+  d_partial_ = (double *)((char *)d_cols_ + cols_b);
+  if (hipHostMalloc((void **)&h_s_, sizeof(Solve2D) * cap_, 0) != hipSuccess) return LRP_ENOMEM;
+  if (hipHostMalloc((void **)&h_cols_, sizeof(DstCol) * cols_cap_, 0) != hipSuccess) return LRP_ENOMEM;
+  std::memset(h_s_, 0, sizeof(Solve2D) * cap_);
+  plans_.resize(cap_);
+  kin_.assign(cap_, 0);
+  for (int i = cap_ - 1; i >= 0; --i) free_slots.push_back(i);
+  // carve fixed pointers of every slot once
+  for (int i = 0; i < cap_; ++i) {
+    Solve2D &s = h_s_[i];
+    char *b = ws_ + per_slot_ * i;
+    const size_t nk = (size_t)n_ * KMAX;
+    s.Uh = (double *)(b + L.off_Uh);
+    s.Vh = (double *)(b + L.off_Vh);
+    double *pan = (double *)(b + L.off_panels);
+    s.C = pan;
+    s.Hv = pan + nk;
+    s.Q0 = pan + 2 * nk;
+    s.Q1 = pan + 3 * nk;
+    s.A = pan + 4 * nk;
+    s.B = pan + 5 * nk;
+    s.Ap = pan + 6 * nk;
+    s.Bp = pan + 7 * nk;
+    s.tree_R = (double *)(b + L.off_treeR);
+    s.tree_H = (double *)(b + L.off_treeH);
+    s.tree_tau = (double *)(b + L.off_treeTau);
+    s.tree_Y = (double *)(b + L.off_treeY);
+    double *sm = (double *)(b + L.off_small);
+    const size_t k2 = (size_t)KMAX * KMAX;
+    s.Rfin = sm;
+    s.Inv = sm + k2;
+    s.InvC = sm + 2 * k2;
+    s.W = sm + 3 * k2;
+    s.Z = sm + 4 * k2;
+    s.Mc = sm + 5 * k2;
+    s.sig = sm + 7 * k2;
+    s.sigp = sm + 7 * k2 + KMAX;
+    s.part = (double *)(b + L.off_part);
+    s.mv_val = (double *)(b + L.off_mvval);
+    s.score = (double *)(b + L.off_score);
+    int *ip = (int *)(b + L.off_ints);
+    s.tree_piv = ip;
+    ip += tree_nodes(talloc_, 0) * KMAX;
+    s.mv_row = ip;
+    ip += (size_t)talloc_.nb[0] * MV_TOP;
+    s.I = ip;
+    s.J = ip + KMAX;
+    s.Jn = ip + 2 * KMAX;
+    s.probe = ip + 3 * KMAX;
+    s.active = ACT_DONE;
+  }
+  HIPCHK(hipMemcpy(d_s_, h_s_, sizeof(Solve2D) * cap_, hipMemcpyHostToDevice));
+  return LRP_OK;
+}
+
+void Group2D::setup_slot(int i, const double *U, const double *V, long ld, int r,
+                         double eps, double *Ux, double *Vx, long ldx, int rmax,
+                         const Plan &plan) {
+  Solve2D &s = h_s_[i];
+  plans_[i] = plan;
+  s.n = n_;
+  s.r = r;
+  s.kcap = plan.kcap;
+  s.kick = plan.kick;
+  s.max_sweeps = plan.max_sweeps;
+  s.min_slack = plan.min_slack;
+  s.rmax = rmax;
+  s.eps = eps;
+  s.tau = plan.tau;
+  s.U = U;
+  s.V = V;
+  s.ld = ld;
+  s.Ux = Ux;
+  s.Vx = Vx;
+  s.ldx = ldx;
+  // reset pointer roles that a previous occupant may have swapped
+  double *lo = std::min(s.A, s.Ap), *hi = std::max(s.A, s.Ap);
+  s.A = lo;
+  s.Ap = hi;
+  lo = std::min(s.B, s.Bp);
+  hi = std::max(s.B, s.Bp);
+  s.B = lo;
+  s.Bp = hi;
+  lo = std::min(s.sig, s.sigp);
+  hi = std::max(s.sig, s.sigp);
+  s.sig = lo;
+  s.sigp = hi;
+  const int k0 = std::min(std::min(n_, r + plan.kick), plan.kcap);
+  s.k0 = k0;
+  s.k = std::min(r, k0);   // columns of the initial maxvol on Vh
+  kin_[i] = s.k;
+  s.kp = 0;
+  s.R = 0;
+  s.sweep = 0;
+  s.next = NEXT_CONTINUE;
+  s.status = LRP_OK;
+  s.nonfinite = 0;
+  s.mv_done = 0;
+  s.mv_swaps = 0;
+  s.kgrow = 0;
+  s.nrm = 0.0;
+  s.change = -1.0;
+  s.active = (r > 0) ? ACT_INIT : ACT_DONE;
+}
+
+lrp_status Group2D::upload_slot(int i, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(d_s_ + i, h_s_ + i, sizeof(Solve2D), hipMemcpyHostToDevice, st));
+  return LRP_OK;
+}
+
+lrp_status Group2D::upload_all(int count, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(d_s_, h_s_, sizeof(Solve2D) * count, hipMemcpyHostToDevice, st));
+  return LRP_OK;
+}
+
+lrp_status Group2D::dst_cols(std::vector<DstCol> &cols, int prec, hipStream_t st) {
+  size_t done = 0;
+  while (done < cols.size()) {
+    const int cnt = (int)std::min(cols.size() - done, (size_t)cols_cap_);
+    // the staging buffer is reused: wait for the previous launch's copy
+    HIPCHK(hipStreamSynchronize(st));
+    std::memcpy(h_cols_, cols.data() + done, sizeof(DstCol) * cnt);
+    HIPCHK(hipMemcpyAsync(d_cols_, h_cols_, sizeof(DstCol) * cnt, hipMemcpyHostToDevice, st));
+    HIPCHK(launch_dst(prec, n_, tabs_->tab, d_cols_, cnt, d_s_, d_partial_,
+                      partial_elems_, st));
+    done += cnt;
+  }
+  return LRP_OK;
+}
+
+lrp_status Group2D::forward(const std::vector<int> &slots, hipStream_t st) {
+  for (int prec : {LRP_PREC_FP64, LRP_PREC_FP32, LRP_PREC_BF16X3}) {
+    std::vector<DstCol> cols;
+    for (int i : slots) {
+      const Solve2D &s = h_s_[i];
+      if (plans_[i].fwd_prec != prec || s.r == 0) continue;
+      for (int c = 0; c < s.r; ++c) cols.push_back({s.U + (long)c * s.ld, s.Uh + (long)c * n_, i, 0});
+      for (int c = 0; c < s.r; ++c) cols.push_back({s.V + (long)c * s.ld, s.Vh + (long)c * n_, i, 0});
+    }
+    if (!cols.empty()) {
+      lrp_status e = dst_cols(cols, prec, st);
+      if (e != LRP_OK) return e;
+    }
+  }
+  return LRP_OK;
+}
+
+lrp_status Group2D::step(hipStream_t st) {
+  int kin = 0, kmax = 0, rmax = 0;
+  bool any_init = false, any_sweep = false;
+  for (int i = 0; i < cap_; ++i) {
+    const Solve2D &s = h_s_[i];
+    if (s.active == ACT_INIT) {
+      any_init = true;
+      kin = std::max(kin, s.k);
+      kmax = std::max(kmax, s.k0);
+      rmax = std::max(rmax, s.r);
+    } else if (s.active == ACT_SWEEP) {
+      any_sweep = true;
+      kmax = std::max(kmax, s.k);
+      rmax = std::max(rmax, s.r);
+    }
+  }
+  if (any_init) {
+    // the tree depends on n only, so a slot's arithmetic does not depend on
+    // which other slots share the launch
+    const Tree t = make_tree(n_, KMAX);
+    HIPCHK(launch_tsqr(TS_VH_TO_Q0, n_, t, d_s_, cap_, kin, st));
+    HIPCHK(launch_maxvol(MV_Q0_TO_J, n_, t, d_s_, cap_, kin, st));
+    HIPCHK(launch_init_J(n_, d_s_, cap_, st));
+  }
+  if (!any_init && !any_sweep) return LRP_OK;
+  // k of a slot only grows at the end of a sweep, so kmax bounds this sweep
+  const int km = std::max(kmax, 1);
+  const int kev = std::max(km, rmax);
+  const Tree t = make_tree(n_, KMAX);
+  const int nb0 = ceil_div(n_, NTHR);
+  HIPCHK(launch_eval(EV_COLS, n_, tabs_->lam, d_s_, cap_, kev, st));
+  HIPCHK(launch_tsqr(TS_C_TO_Q0, n_, t, d_s_, cap_, km, st));
+  HIPCHK(launch_maxvol(MV_Q0_TO_I, n_, t, d_s_, cap_, km, st));
+  HIPCHK(launch_eval(EV_ROWS, n_, tabs_->lam, d_s_, cap_, kev, st));
+  HIPCHK(launch_tsqr(TS_C_TO_Q1, n_, t, d_s_, cap_, km, st));
+  HIPCHK(launch_maxvol(MV_Q1_TO_JN, n_, t, d_s_, cap_, km, st));
+  HIPCHK(launch_core(n_, d_s_, cap_, st));
+  HIPCHK(launch_factors(n_, d_s_, cap_, km, st));
+  HIPCHK(launch_change(n_, nb0, d_s_, cap_, km, st));
+  HIPCHK(launch_decide(n_, tabs_->lam, d_s_, cap_, kev, nb0, st));
+  return LRP_OK;
+}
+
+lrp_status Group2D::fetch(hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(h_s_, d_s_, sizeof(Solve2D) * cap_, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return LRP_OK;
+}
+
+lrp_status Group2D::inverse(const std::vector<int> &slots, hipStream_t st) {
+  for (int prec : {LRP_PREC_FP64, LRP_PREC_FP32, LRP_PREC_BF16X3}) {
+    std::vector<DstCol> cols;
+    for (int i : slots) {
+      const Solve2D &s = h_s_[i];
+      if (plans_[i].inv_prec != prec) continue;
+      for (int c = 0; c < s.R; ++c) cols.push_back({s.A + (long)c * n_, s.Ux + (long)c * s.ldx, -1, 0});
+      for (int c = 0; c < s.R; ++c) cols.push_back({s.B + (long)c * n_, s.Vx + (long)c * s.ldx, -1, 0});
+    }
+    if (!cols.empty()) {
+      lrp_status e = dst_cols(cols, prec, st);
+      if (e != LRP_OK) return e;
+    }
+  }
+  return LRP_OK;
+}
+
+}  // namespace lrp
+
+using namespace lrp;
+
+// ---------------------------------------------------------------- C API
+extern "C" {
+
+const char *lrp_strerror(int32_t s) {
+  switch (s) {
+    case LRP_OK: return "ok";
+    case LRP_EINVAL: return "invalid argument";
+    case LRP_ENONFINITE: return "right-hand side holds Inf or NaN";
+    case LRP_ERANKCAP: return "rank cap reached";
+    case LRP_ENOCONV: return "cross sweeps did not converge";
+    case LRP_ENOMEM: return "out of device memory budget";
+    case LRP_EDEVICE: return "HIP runtime error";
+    case LRP_EBUSY: return "busy";
+    case LRP_ENOTREADY: return "not ready";
+    default: return "unknown status";
+  }
+}
+
+lrp_status lrp_create(lrp_ctx **ctx, int device, size_t workspace_bytes) {
+  if (!ctx) return LRP_EINVAL;
+  *ctx = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return LRP_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return LRP_EDEVICE;
+  lrp_ctx *c = new lrp_ctx();
+  c->device = device;
+  c->budget = workspace_bytes ? workspace_bytes : ((size_t)2 << 30);
+  *ctx = c;
+  return LRP_OK;
+}
+
+lrp_status lrp_sine_transform(lrp_ctx *ctx, int64_t n, int32_t ncols,
+                              const double *src, int64_t lds, double *dst,
+                              int64_t ldd, int32_t prec, void *stream) {
+  if (!ctx || n < 1 || n > LRP_MAX_N || ncols < 0) return LRP_EINVAL;
+  if (prec != LRP_PREC_FP64 && prec != LRP_PREC_FP32 && prec != LRP_PREC_BF16X3)
+    return LRP_EINVAL;
+  if (ncols == 0) return LRP_OK;
+  if (!src || !dst || lds < n || ldd < n) return LRP_EINVAL;
+  if (hipSetDevice(ctx->device) != hipSuccess) return LRP_EDEVICE;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  lrp_status err;
+  const GridTables *t = get_tables(ctx, (int)n, &err);
+  if (!t) return err;
+  hipStream_t st = (hipStream_t)stream;
+  const int chunk = 1024;
+  const size_t pe = dst_partial_elems((int)n, 64);
+  if (ctx->tx_cap < chunk || ctx->tx_partial_elems < pe) {
+    if (ctx->tx_dcols) dev_free(ctx, ctx->tx_dcols, ctx->tx_bytes);
+    if (ctx->tx_hcols) (void)hipHostFree(ctx->tx_hcols);
+    ctx->tx_dcols = nullptr;
+    ctx->tx_hcols = nullptr;
+    ctx->tx_cap = 0;
+    const size_t cb = ((size_t)chunk * sizeof(DstCol) + 255) & ~(size_t)255;
+    void *p = nullptr;
+    if ((err = dev_alloc(ctx, &p, cb + pe * 8)) != LRP_OK) return err;
+    ctx->tx_bytes = cb + pe * 8;
+    ctx->tx_dcols = (DstCol *)p;
+    ctx->tx_partial = (double *)((char *)p + cb);
+    ctx->tx_partial_elems = pe;
+    if (hipHostMalloc((void **)&ctx->tx_hcols, sizeof(DstCol) * chunk, 0) != hipSuccess)
+      return LRP_ENOMEM;
+    ctx->tx_cap = chunk;
+  }
+  for (int c0 = 0; c0 < ncols; c0 += chunk) {
+    const int cnt = std::min(chunk, ncols - c0);
+    if (hipStreamSynchronize(st) != hipSuccess) return LRP_EDEVICE;
+    for (int c = 0; c < cnt; ++c)
+      ctx->tx_hcols[c] = {src + (long)(c0 + c) * lds, dst + (long)(c0 + c) * ldd, -1, 0};
+    if (hipMemcpyAsync(ctx->tx_dcols, ctx->tx_hcols, sizeof(DstCol) * cnt,
+                       hipMemcpyHostToDevice, st) != hipSuccess)
+      return LRP_EDEVICE;
+    if (launch_dst(prec, (int)n, t->tab, ctx->tx_dcols, cnt, nullptr,
+                   ctx->tx_partial, ctx->tx_partial_elems, st) != hipSuccess)
+      return LRP_EDEVICE;
+  }
+  return LRP_OK;
+}
+
+lrp_status lrp_destroy(lrp_ctx *ctx) {
+  if (!ctx) return LRP_EINVAL;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (ctx->tx_dcols) dev_free(ctx, ctx->tx_dcols, ctx->tx_bytes);
+  if (ctx->tx_hcols) (void)hipHostFree(ctx->tx_hcols);
+  ctx->batch_groups.clear();
+  ctx->serve_groups.clear();
+  for (auto &kv : ctx->tables) dev_free(ctx, kv.second.tab, kv.second.bytes);
+  if (ctx->serve_stream) (void)hipStreamDestroy(ctx->serve_stream);
+  delete ctx;
+  return LRP_OK;
+}
+
+static lrp_status check_problem(int64_t n, const lrp_problem2d &p) {
+  if (p.rank < 0 || p.rank > LRP_MAX_RANK) return LRP_EINVAL;
+  if (!(p.eps > 0.0 && p.eps < 1.0)) return LRP_EINVAL;
+  if (p.rmax < 0) return LRP_EINVAL;
+  if (p.rank > 0 && (!p.U || !p.V || p.ld < n)) return LRP_EINVAL;
+  if (p.rmax > 0 && (!p.Ux || !p.Vx || p.ldx < n)) return LRP_EINVAL;
+  return LRP_OK;
+}
+
+lrp_status lrpoisson_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t count,
+                                   lrp_problem2d *probs, const lrp_opts *opts,
+                                   void *stream) {
+  if (!ctx || !probs || count < 0) return LRP_EINVAL;
+  if (n < 1 || n > LRP_MAX_N) return LRP_EINVAL;
+  if (opts && (opts->prec < 0 || opts->prec > LRP_PREC_BF16X3)) return LRP_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    lrp_status e = check_problem(n, probs[i]);
+    if (e != LRP_OK) return e;
+  }
+  if (count == 0) return LRP_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) return LRP_EDEVICE;
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  auto &slot = ctx->batch_groups[(int)n];
+  if (!slot || slot->cap() < count) {
+    slot.reset();
+    std::unique_ptr<Group2D> g(new Group2D(ctx, (int)n, count));
+    lrp_status e = g->init();
+    if (e != LRP_OK) return e;
+    slot = std::move(g);
+  }
+  Group2D &g = *slot;
+  std::vector<int> all;
+  for (int i = 0; i < g.cap(); ++i) {
+    if (i < count) {
+      const lrp_problem2d &p = probs[i];
+      const Plan plan = make_plan(opts, p.eps, (int)n);
+      g.setup_slot(i, p.U, p.V, p.ld, p.rank, p.eps, p.Ux, p.Vx, p.ldx, p.rmax, plan);
+      all.push_back(i);
+    } else {
+      g.host(i).active = ACT_DONE;
+    }
+  }
+  lrp_status e = g.upload_all(g.cap(), st);
+  if (e != LRP_OK) return e;
+  if ((e = g.forward(all, st)) != LRP_OK) return e;
+  for (int sweep = 0; sweep <= 64; ++sweep) {
+    if ((e = g.step(st)) != LRP_OK) return e;
+    if ((e = g.fetch(st)) != LRP_OK) return e;
+    bool any = false;
+    for (int i = 0; i < count; ++i) any |= g.host(i).active != ACT_DONE;
+    if (!any) break;
+  }
+  std::vector<int> out;
+  for (int i = 0; i < count; ++i) {
+    Solve2D &s = g.host(i);
+    if (s.status == LRP_ENONFINITE || s.r == 0) {
+      s.R = 0;
+      continue;
+    }
+    if (s.R > s.rmax) {
+      s.status = LRP_ERANKCAP;
+      continue;
+    }
+    out.push_back(i);
+  }
+  if ((e = g.inverse(out, st)) != LRP_OK) return e;
+  if (hipStreamSynchronize(st) != hipSuccess) return LRP_EDEVICE;
+  lrp_status first = LRP_OK;
+  for (int i = 0; i < count; ++i) {
+    const Solve2D &s = g.host(i);
+    lrp_problem2d &p = probs[i];
+    p.rank_out = s.R;
+    p.info.status = s.status;
+    p.info.sweeps = s.sweep;
+    p.info.k = s.k;
+    p.info.rank = s.R;
+    p.info.fwd_prec = g.plan(i).fwd_prec;
+    p.info.inv_prec = g.plan(i).inv_prec;
+    p.info.change = s.change;
+    if (first == LRP_OK && s.status != LRP_OK) first = (lrp_status)s.status;
+  }
+  return first;
+}
+
+lrp_status lrpoisson_solve2d(lrp_ctx *ctx, int64_t n, int32_t rank,
+                             const double *U, const double *V, int64_t ld,
+                             double eps, const lrp_opts *opts, double *Ux,
+                             double *Vx, int64_t ldx, int32_t rmax,
+                             int32_t *rank_out, lrp_info *info, void *stream) {
+  if (!rank_out) return LRP_EINVAL;
+  lrp_problem2d p;
+  std::memset(&p, 0, sizeof(p));
+  p.U = U;
+  p.V = V;
+  p.ld = ld;
+  p.rank = rank;
+  p.rmax = rmax;
+  p.eps = eps;
+  p.Ux = Ux;
+  p.Vx = Vx;
+  p.ldx = ldx;
+  lrp_status e = lrpoisson_solve2d_batch(ctx, n, 1, &p, opts, stream);
+  *rank_out = p.rank_out;
+  if (info) *info = p.info;
+  return e;
+}
+
+lrp_status lrpoisson_solve3d(lrp_ctx *ctx, int64_t n, const int32_t rank[3],
+                             const double *U1, const double *U2,
+                             const double *U3, int64_t ld, const double *G,
+                             double eps, const lrp_opts *opts,
+                             double *U1x, double *U2x, double *U3x,
+                             int64_t ldx, double *Gx, const int32_t rmax[3],
+                             int32_t rank_out[3], lrp_info *info, void *stream);
+
+}  // extern "C"

@@ -1,0 +1,378 @@
+// maxvol: k rows I of an n x k orthonormal basis Q whose k x k submatrix has
+// (locally) maximal volume -- the pivot choice of the cross approximation
+// (paper Section 4.2, "maximal-volume submatrix ... maxvol-algorithm",
+// refs. gt-maxvol-2001, gostz-maxvol-2010).  The exit contract is the one of
+// the algorithm: B = Q Q[I,:]^-1 has B[I,:] = identity and max|B| <= tau.
+//
+// GPU formulation (same contract, parallel steps):
+//  1. starting rows: Gaussian elimination with partial pivoting run as a
+//     tournament -- every 256-row block selects its pivot rows, internal
+//     nodes run the elimination again on the union of their children's
+//     candidates;
+//  2. rounds of: Inv = Q[I,:]^-1 (Gauss-Jordan, partial pivoting); every
+//     block forms its rows of B = Q Inv and reports its largest entries above
+//     tau; one workgroup then runs the classical swap loop (swap the argmax
+//     row in, rank-1 update of B) on I plus the reported rows.  A round that
+//     finds no entry above tau ends the iteration.  Each swap multiplies
+//     |det Q[I,:]| by more than tau, so the rounds terminate.
+#include "panel.h"
+
+namespace lrp {
+namespace {
+
+struct MvIO {
+  const double *Q;
+  int *out;
+  double *inv;
+};
+__device__ inline MvIO mv_io(int which, Solve2D &s) {
+  if (which == MV_Q0_TO_I) return {s.Q0, s.I, s.InvC};
+  if (which == MV_Q1_TO_JN) return {s.Q1, s.Jn, s.Inv};
+  return {s.Q0, s.J, s.Inv};
+}
+
+__device__ inline int mv_phase(int which) {
+  return which == MV_Q0_TO_J ? ACT_INIT : ACT_SWEEP;
+}
+
+__device__ inline size_t piv_off(const Tree &t, int l) {
+  size_t o = 0;
+  for (int i = 0; i < l; ++i) o += (size_t)t.nb[i] * KMAX;
+  return o;
+}
+
+// ---- tournament elimination
+template <int NS>
+__global__ __launch_bounds__(NTHR) void k_mv_leaf(int which, int n, Tree tr,
+                                                 Solve2D *S) {
+  Solve2D &s = S[blockIdx.y];
+  if (s.active != mv_phase(which)) return;
+  __shared__ double lbuf[2 * PANEL_M];
+  __shared__ int shp[2];
+  __shared__ int piv[KMAX];
+  const int kk = s.k;
+  if (threadIdx.x == 0) s.mv_done = 0, s.mv_swaps = 0;
+  const MvIO io = mv_io(which, s);
+  const int b = blockIdx.x, r0 = b * PANEL_M;
+  const int m = min(PANEL_M, n - r0);
+  double y[NS][4];
+  panel_load(y, io.Q + r0, n, m, kk);
+  gepp_select_regs(y, m, kk, lbuf, shp, piv);
+  __syncthreads();
+  const int np = min(m, kk);
+  int *dst = (tr.nlev == 1) ? io.out : (s.tree_piv + piv_off(tr, 0) + (size_t)b * KMAX);
+  for (int j = threadIdx.x; j < kk; j += NTHR) dst[j] = (j < np) ? r0 + piv[j] : -1;
+}
+
+template <int NS>
+__global__ __launch_bounds__(NTHR) void k_mv_node(int which, int n, int lev,
+                                                 Tree tr, Solve2D *S) {
+  Solve2D &s = S[blockIdx.y];
+  if (s.active != mv_phase(which)) return;
+  __shared__ double lbuf[2 * PANEL_M];
+  __shared__ int shp[2];
+  __shared__ int piv[KMAX];
+  __shared__ int rows[PANEL_M];
+  __shared__ int nrows;
+  const int kk = s.k;
+  const MvIO io = mv_io(which, s);
+  const int t = blockIdx.x, c0 = t * tr.fan;
+  const int nch = min(tr.fan, tr.nb[lev - 1] - c0);
+  const int *cp = s.tree_piv + piv_off(tr, lev - 1) + (size_t)c0 * KMAX;
+  if (threadIdx.x == 0) {
+    int cnt = 0;
+    for (int i = 0; i < nch * kk; ++i) {
+      const int ch = i / kk, ii = i - ch * kk;
+      const int rr = cp[(size_t)ch * KMAX + ii];
+      if (rr >= 0) rows[cnt++] = rr;
+    }
+    nrows = cnt;
+  }
+  __syncthreads();
+  const int mp = nrows;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double y[NS][4];
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int c = wave + 4 * sl;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = lane + 64 * q;
+      y[sl][q] = (c < kk && i < mp) ? io.Q[clamp_row(rows[i], n) + (long)c * n] : 0.0;
+    }
+  }
+  gepp_select_regs(y, mp, kk, lbuf, shp, piv);
+  __syncthreads();
+  const int np = min(mp, kk);
+  int *dst = (lev == tr.nlev - 1) ? io.out
+                                  : (s.tree_piv + piv_off(tr, lev) + (size_t)t * KMAX);
+  for (int j = threadIdx.x; j < kk; j += NTHR) dst[j] = (j < np) ? rows[piv[j]] : -1;
+}
+
+// ---- Inv = Q[I,:]^-1 by Gauss-Jordan with partial pivoting (one workgroup)
+__global__ __launch_bounds__(NTHR) void k_mv_inv(int which, int n, int force,
+                                                Solve2D *S) {
+  Solve2D &s = S[blockIdx.x];
+  if (s.active != mv_phase(which)) return;
+  if (!force && s.mv_done) return;
+  __shared__ double a[KMAX][2 * KMAX + 1];
+  __shared__ double f[KMAX];
+  __shared__ int shp;
+  const int kk = s.k, w2 = 2 * kk;
+  const MvIO io = mv_io(which, s);
+  for (int e = threadIdx.x; e < kk * w2; e += NTHR) {
+    const int i = e / w2, c = e - i * w2;
+    a[i][c] = (c < kk) ? io.Q[clamp_row(io.out[i], n) + (long)c * n] : ((c - kk == i) ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int j = 0; j < kk; ++j) {
+    if (threadIdx.x < 64) {
+      double best = -1.0;
+      int key = 0x7fffffff;
+      const int i = threadIdx.x;
+      if (i >= j && i < kk) {
+        best = fabs(a[i][j]);
+        key = i;
+      }
+      wave_argmax(best, key);
+      if (threadIdx.x == 0) shp = key;
+    }
+    __syncthreads();
+    const int p = shp;
+    if (p != j)
+      for (int c = threadIdx.x; c < w2; c += NTHR) {
+        const double t = a[j][c];
+        a[j][c] = a[p][c];
+        a[p][c] = t;
+      }
+    __syncthreads();
+    const double pv = a[j][j];
+    const double ip = (pv != 0.0) ? 1.0 / pv : 0.0;
+    if (threadIdx.x < kk) f[threadIdx.x] = a[threadIdx.x][j];
+    __syncthreads();
+    for (int c = threadIdx.x; c < w2; c += NTHR) a[j][c] *= ip;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kk * w2; e += NTHR) {
+      const int i = e / w2, c = e - i * w2;
+      if (i != j) a[i][c] -= f[i] * a[j][c];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < kk * kk; e += NTHR) {
+    const int i = e / kk, c = e - i * kk;
+    io.inv[i + c * KMAX] = a[i][kk + c];
+  }
+}
+
+// ---- per block: rows of B = Q Inv, report the MV_TOP largest rows > tau
+template <int KM>
+__global__ __launch_bounds__(NTHR) void k_mv_check(int which, int n, Solve2D *S) {
+  Solve2D &s = S[blockIdx.y];
+  if (s.active != mv_phase(which) || s.mv_done) return;
+  __shared__ double inv[KMAX * KMAX];
+  __shared__ double rv[4];
+  __shared__ int rk[4];
+  const int kk = s.k;
+  const MvIO io = mv_io(which, s);
+  for (int e = threadIdx.x; e < kk * kk; e += NTHR) {
+    const int i = e / kk, c = e - i * kk;
+    inv[i * KMAX + c] = io.inv[i + c * KMAX];
+  }
+  __syncthreads();
+  const int row = blockIdx.x * NTHR + threadIdx.x;
+  double mx = -1.0;
+  if (row < n) {
+    double acc[KM];
+#pragma unroll
+    for (int c = 0; c < KM; ++c) acc[c] = 0.0;
+    for (int j = 0; j < kk; ++j) {
+      const double q = io.Q[row + (long)j * n];
+#pragma unroll
+      for (int c = 0; c < KM; ++c) acc[c] += q * inv[j * KMAX + c];
+    }
+#pragma unroll
+    for (int c = 0; c < KM; ++c)
+      if (c < kk) mx = fmax(mx, fabs(acc[c]));
+    if (!(mx > s.tau)) mx = -1.0;   // only violators compete
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int t = 0; t < MV_TOP; ++t) {
+    double v = mx;
+    int key = (row < n) ? row : 0x7fffffff;
+    wave_argmax(v, key);
+    if (lane == 0) {
+      rv[wave] = v;
+      rk[wave] = key;
+    }
+    __syncthreads();
+    double bv = rv[0];
+    int bk = rk[0];
+    for (int w = 1; w < 4; ++w)
+      if (rv[w] > bv || (rv[w] == bv && rk[w] < bk)) bv = rv[w], bk = rk[w];
+    if (threadIdx.x == 0) {
+      s.mv_val[(size_t)blockIdx.x * MV_TOP + t] = bv;
+      s.mv_row[(size_t)blockIdx.x * MV_TOP + t] = (bv > 0.0) ? bk : -1;
+    }
+    if (row == bk) mx = -1.0;
+    __syncthreads();
+  }
+}
+
+// ---- one workgroup: swap loop on I plus the reported rows
+__global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
+                                                 Solve2D *S) {
+  Solve2D &s = S[blockIdx.x];
+  if (s.active != mv_phase(which) || s.mv_done) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int kk = s.k;
+  const MvIO io = mv_io(which, s);
+  double *Bm = (double *)smem;                      // (KMAX+MV_CAND) x KMAX
+  double *inv = Bm + (KMAX + MV_CAND) * KMAX;       // KMAX x KMAX
+  double *prow = inv + KMAX * KMAX;                 // KMAX
+  double *pcol = prow + KMAX;                       // KMAX + MV_CAND
+  int *rows = (int *)(pcol + KMAX + MV_CAND);       // KMAX + MV_CAND
+  int *cnt = rows + KMAX + MV_CAND;                 // [0] count, [1] argmax, [2] swaps
+  __shared__ double rv[4];
+  __shared__ int rk[4];
+  const int ntot = nb0 * MV_TOP;
+  if (threadIdx.x == 0) cnt[0] = 0;
+  __syncthreads();
+  // rank-select the largest reported violators (ties: lower row first)
+  for (int e = threadIdx.x; e < ntot; e += NTHR) {
+    const double v = s.mv_val[e];
+    const int rr = s.mv_row[e];
+    if (rr < 0 || !(v > s.tau)) continue;
+    int rank = 0;
+    for (int f = 0; f < ntot; ++f) {
+      const double w = s.mv_val[f];
+      const int r2 = s.mv_row[f];
+      if (r2 < 0 || !(w > s.tau)) continue;
+      if (w > v || (w == v && r2 < rr)) ++rank;
+    }
+    if (rank < MV_CAND) {
+      rows[kk + rank] = rr;
+      atomicAdd(&cnt[0], 1);
+    }
+  }
+  __syncthreads();
+  const int nc = min(cnt[0], MV_CAND);
+  if (nc == 0) {
+    if (threadIdx.x == 0) s.mv_done = 1;
+    return;
+  }
+  const int nr = kk + nc;
+  for (int j = threadIdx.x; j < kk; j += NTHR) rows[j] = clamp_row(io.out[j], n);
+  for (int e = threadIdx.x; e < kk * kk; e += NTHR) {
+    const int i = e / kk, c = e - i * kk;
+    inv[i * KMAX + c] = io.inv[i + c * KMAX];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nr * kk; e += NTHR) {
+    const int t = e / kk, c = e - t * kk;
+    double v;
+    if (t < kk) {
+      v = (t == c) ? 1.0 : 0.0;
+    } else {
+      v = 0.0;
+      const int rr = clamp_row(rows[t], n);
+      for (int j = 0; j < kk; ++j) v += io.Q[rr + (long)j * n] * inv[j * KMAX + c];
+    }
+    Bm[t * KMAX + c] = v;
+  }
+  if (threadIdx.x == 0) cnt[2] = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int it = 0; it < 4 * kk; ++it) {
+    double best = -1.0;
+    int key = 0x7fffffff;
+    for (int e = threadIdx.x; e < nr * kk; e += NTHR) {
+      const int t = e / kk, c = e - t * kk;
+      const double a = fabs(Bm[t * KMAX + c]);
+      const int kv = rows[t] * KMAX + c;
+      if (a > best || (a == best && kv < key)) best = a, key = kv;
+    }
+    wave_argmax(best, key);
+    if (lane == 0) rv[wave] = best, rk[wave] = key;
+    __syncthreads();
+    double bv = rv[0];
+    int bk = rk[0];
+    for (int w = 1; w < 4; ++w)
+      if (rv[w] > bv || (rv[w] == bv && rk[w] < bk)) bv = rv[w], bk = rk[w];
+    if (!(bv > s.tau)) break;            // uniform: every thread sees bv
+    const int gr = bk / KMAX, cs = bk - gr * KMAX;
+    int ts = 0;
+    for (int t = 0; t < nr; ++t)
+      if (rows[t] == gr) ts = t;          // rows are distinct
+    const double piv = Bm[ts * KMAX + cs];
+    __syncthreads();
+    for (int c = threadIdx.x; c < kk; c += NTHR)
+      prow[c] = (Bm[ts * KMAX + c] - (c == cs ? 1.0 : 0.0)) / piv;
+    for (int t = threadIdx.x; t < nr; t += NTHR) pcol[t] = Bm[t * KMAX + cs];
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * kk; e += NTHR) {
+      const int t = e / kk, c = e - t * kk;
+      Bm[t * KMAX + c] -= pcol[t] * prow[c];
+    }
+    if (threadIdx.x == 0) {
+      io.out[cs] = gr;
+      cnt[2] += 1;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    s.mv_swaps += cnt[2];
+    if (cnt[2] == 0) s.mv_done = 1;
+  }
+}
+
+template <int NS>
+hipError_t run_tournament(int which, int n, const Tree &tr, Solve2D *s, int ns,
+                          hipStream_t st) {
+  hipLaunchKernelGGL((k_mv_leaf<NS>), dim3(tr.nb[0], ns), dim3(NTHR), 0, st,
+                     which, n, tr, s);
+  for (int l = 1; l < tr.nlev; ++l)
+    hipLaunchKernelGGL((k_mv_node<NS>), dim3(tr.nb[l], ns), dim3(NTHR), 0, st,
+                       which, n, l, tr, s);
+  return hipGetLastError();
+}
+
+template <int KM>
+void run_check(int which, int n, const Tree &tr, Solve2D *s, int ns,
+               hipStream_t st) {
+  hipLaunchKernelGGL((k_mv_check<KM>), dim3(tr.nb[0], ns), dim3(NTHR), 0, st,
+                     which, n, s);
+}
+
+}  // namespace
+
+hipError_t launch_maxvol(int which, int n, const Tree &tr, Solve2D *s,
+                         int nsolves, int kmax, hipStream_t st) {
+  hipError_t e;
+  if (kmax <= 16) e = run_tournament<4>(which, n, tr, s, nsolves, st);
+  else if (kmax <= 32) e = run_tournament<8>(which, n, tr, s, nsolves, st);
+  else e = run_tournament<16>(which, n, tr, s, nsolves, st);
+  if (e != hipSuccess) return e;
+  const size_t swap_lds = (size_t)(KMAX + MV_CAND) * KMAX * 8 + (size_t)KMAX * KMAX * 8 +
+                          (size_t)KMAX * 8 + (size_t)(KMAX + MV_CAND) * 8 +
+                          (size_t)(KMAX + MV_CAND) * 4 + 16;
+  static bool attr = false;
+  if (!attr) {
+    e = hipFuncSetAttribute((const void *)k_mv_swap,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)swap_lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  for (int round = 0; round < MV_ROUNDS; ++round) {
+    hipLaunchKernelGGL(k_mv_inv, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
+    if (kmax <= 16) run_check<16>(which, n, tr, s, nsolves, st);
+    else if (kmax <= 32) run_check<32>(which, n, tr, s, nsolves, st);
+    else run_check<64>(which, n, tr, s, nsolves, st);
+    hipLaunchKernelGGL(k_mv_swap, dim3(nsolves), dim3(NTHR), swap_lds, st, which,
+                       n, tr.nb[0], s);
+  }
+  // the last round may have swapped: refresh the inverse for the final rows
+  hipLaunchKernelGGL(k_mv_inv, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
+  return hipGetLastError();
+}
+
+}  // namespace lrp

@@ -1,0 +1,119 @@
+// Rounding of the skeleton (paper Section 3, "rounding": QR of the factors
+// plus SVD of the small core, O((n+m) r^2 + r^3)).
+//
+// After the column basis Q0 (n x k, orthonormal), the rows I picked by
+// maxvol, and the rows' QR  Xh[I,:]^T = Q1 R1, the skeleton of the cross is
+//     X~ = Q0 (Q0[I,:])^-1 Xh[I,:] = Q0 K Q1^T,   K = (Q0[I,:])^-1 R1^T,
+// so its SVD only needs the k x k core K = W S Z^T:  X~ = (Q0 W) S (Q1 Z)^T.
+// The core SVD is one-sided (Hestenes) Jacobi, which keeps small singular
+// values to high relative accuracy (needed for tail truncation at 1e-10);
+// one 256-thread workgroup per solve, K and the accumulated right rotations
+// in LDS, rotations applied to disjoint column pairs in parallel
+// (round-robin ordering).
+#include "lrp_internal.h"
+
+namespace lrp {
+namespace {
+
+constexpr int LD = KMAX + 1;
+
+__global__ __launch_bounds__(NTHR) void k_core(Solve2D *S) {
+  Solve2D &s = S[blockIdx.x];
+  if (s.active != ACT_SWEEP) return;
+  __shared__ double K[KMAX * LD];   // column c at K[c*LD + i]
+  __shared__ double V[KMAX * LD];
+  __shared__ double sg[KMAX];
+  __shared__ int perm[KMAX];
+  __shared__ int rot;
+  const int kk = s.k;
+  const int kp = (kk + 1) & ~1;   // even number of players
+  // K[i][c] = sum_j InvC[i][j] * Rfin[c][j]   (Rfin upper triangular)
+  for (int e = threadIdx.x; e < kp * kp; e += NTHR) {
+    const int c = e / kp, i = e - c * kp;
+    double v = 0.0;
+    if (i < kk && c < kk)
+      for (int j = c; j < kk; ++j) v += s.InvC[i + j * KMAX] * s.Rfin[c + j * KMAX];
+    K[c * LD + i] = v;
+    V[c * LD + i] = (i == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const int npairs = kp / 2;
+  int G = 64;
+  while (G * npairs > NTHR) G >>= 1;          // threads per pair, power of 2
+  const int pr = threadIdx.x / G, gl = threadIdx.x - pr * G;
+  const double tol = 1e-15;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    if (threadIdx.x == 0) rot = 0;
+    __syncthreads();
+    for (int st = 0; st < kp - 1; ++st) {
+      if (pr < npairs) {
+        const int pa = pr, pb = kp - 1 - pr;
+        const int a = (pa == 0) ? 0 : 1 + (pa - 1 + st) % (kp - 1);
+        const int b = 1 + (pb - 1 + st) % (kp - 1);
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int i = gl; i < kp; i += G) {
+          const double x = K[a * LD + i], y = K[b * LD + i];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+        for (int o = G / 2; o > 0; o >>= 1) {
+          al += __shfl_xor(al, o, 64);
+          be += __shfl_xor(be, o, 64);
+          ga += __shfl_xor(ga, o, 64);
+        }
+        if (al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) /
+                           (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
+          for (int i = gl; i < kp; i += G) {
+            const double x = K[a * LD + i], y = K[b * LD + i];
+            K[a * LD + i] = cs * x - sn * y;
+            K[b * LD + i] = sn * x + cs * y;
+            const double u = V[a * LD + i], w = V[b * LD + i];
+            V[a * LD + i] = cs * u - sn * w;
+            V[b * LD + i] = sn * u + cs * w;
+          }
+          if (gl == 0) rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    if (rot == 0) break;
+    __syncthreads();
+  }
+  // singular values and descending order (ties: lower index first)
+  if (threadIdx.x < kk) {
+    double v = 0.0;
+    for (int i = 0; i < kk; ++i) v += K[threadIdx.x * LD + i] * K[threadIdx.x * LD + i];
+    sg[threadIdx.x] = sqrt(v);
+  }
+  __syncthreads();
+  if (threadIdx.x < kk) {
+    const int c = threadIdx.x;
+    int rank = 0;
+    for (int d = 0; d < kk; ++d)
+      if (sg[d] > sg[c] || (sg[d] == sg[c] && d < c)) ++rank;
+    perm[rank] = c;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kk * kk; e += NTHR) {
+    const int t = e / kk, i = e - t * kk;
+    const int c = perm[t];
+    const double sv = sg[c];
+    s.W[i + t * KMAX] = (sv > 0.0) ? K[c * LD + i] / sv : 0.0;
+    s.Z[i + t * KMAX] = V[c * LD + i];
+  }
+  if (threadIdx.x < kk) s.sig[threadIdx.x] = sg[perm[threadIdx.x]];
+}
+
+}  // namespace
+
+hipError_t launch_core(int n, Solve2D *s, int nsolves, hipStream_t st) {
+  (void)n;
+  hipLaunchKernelGGL(k_core, dim3(nsolves), dim3(NTHR), 0, st, s);
+  return hipGetLastError();
+}
+
+}  // namespace lrp

@@ -1,0 +1,247 @@
+// Tall-skinny Householder QR (TSQR) of an n x k panel, k <= 64, with the
+// explicit orthonormal factor Q (n x k).  Used for the orthonormal bases of
+// the cross columns and rows before maxvol and for the rounding of the
+// skeleton (paper Section 3, "rounding": QR of the factors, then SVD of the
+// small core; Section 4.2: maxvol on the cross).
+//
+// Tree: leaves are 256-row blocks; each internal node stacks the R factors of
+// `fan` children (fan * kmax <= 256 rows) and factors them again.  Q is
+// formed top-down: every node applies its reflectors to [Y; 0] and hands the
+// k x k row blocks to its children; the leaves write rows of Q.
+// All kernels run one 256-thread workgroup per (node, solve) with the panel
+// in registers (see panel.h).
+#include "panel.h"
+
+namespace lrp {
+namespace {
+
+__device__ inline size_t lev_off(const Tree &t, int l, size_t per_node) {
+  size_t o = 0;
+  for (int i = 0; i < l; ++i) o += (size_t)t.nb[i] * per_node;
+  return o;
+}
+__device__ inline size_t hlev_off(const Tree &t, int l) {   // levels >= 1
+  size_t o = 0;
+  for (int i = 1; i < l; ++i) o += (size_t)t.nb[i] * PANEL_M * KMAX;
+  return o;
+}
+
+struct TsIO {
+  const double *in;
+  double *out;
+};
+__device__ inline TsIO ts_io(int which, const Solve2D &s) {
+  if (which == TS_C_TO_Q0) return {s.C, s.Q0};
+  if (which == TS_C_TO_Q1) return {s.C, s.Q1};
+  return {s.Vh, s.Q0};
+}
+
+__device__ inline int ts_phase(int which) {
+  return which == TS_VH_TO_Q0 ? ACT_INIT : ACT_SWEEP;
+}
+
+template <int NS>
+__global__ __launch_bounds__(NTHR) void k_tsqr_leaf(int which, int n, Tree tr,
+                                                   Solve2D *S) {
+  Solve2D &s = S[blockIdx.y];
+  if (s.active != ts_phase(which)) return;
+  __shared__ double vbuf[2 * PANEL_M];
+  __shared__ double taus[KMAX];
+  const int kk = s.k;
+  const int b = blockIdx.x;
+  const int r0 = b * PANEL_M;
+  const int m = min(PANEL_M, n - r0);
+  const int mp = max(m, kk);
+  const TsIO io = ts_io(which, s);
+  double y[NS][4];
+  panel_load(y, io.in + r0, n, m, kk);
+  hh_qr_regs(y, mp, kk, vbuf, taus);
+  panel_store(y, s.Hv + r0, n, m, kk);
+  double *R = s.tree_R + lev_off(tr, 0, (size_t)KMAX * KMAX) + (size_t)b * KMAX * KMAX;
+  double *Rf = (tr.nlev == 1) ? s.Rfin : nullptr;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int c = wave + 4 * sl;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = lane + 64 * q;
+      if (c < kk && i < kk) {
+        const double v = (i <= c && i < mp) ? y[sl][q] : 0.0;
+        R[i + c * KMAX] = v;
+        if (Rf) Rf[i + c * KMAX] = v;
+      }
+    }
+  }
+  double *T = s.tree_tau + lev_off(tr, 0, KMAX) + (size_t)b * KMAX;
+  for (int j = threadIdx.x; j < kk; j += NTHR) T[j] = (j < mp) ? taus[j] : 0.0;
+}
+
+template <int NS>
+__global__ __launch_bounds__(NTHR) void k_tsqr_node(int which, int lev, Tree tr,
+                                                   Solve2D *S) {
+  Solve2D &s = S[blockIdx.y];
+  if (s.active != ts_phase(which)) return;
+  __shared__ double vbuf[2 * PANEL_M];
+  __shared__ double taus[KMAX];
+  const int kk = s.k;
+  const int t = blockIdx.x;
+  const int c0 = t * tr.fan;
+  const int nch = min(tr.fan, tr.nb[lev - 1] - c0);
+  const int mp = nch * kk;
+  const double *Rc = s.tree_R + lev_off(tr, lev - 1, (size_t)KMAX * KMAX);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double y[NS][4];
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int c = wave + 4 * sl;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = lane + 64 * q;
+      double v = 0.0;
+      if (c < kk && i < mp) {
+        const int ch = i / kk, ii = i - ch * kk;
+        v = Rc[(size_t)(c0 + ch) * KMAX * KMAX + ii + c * KMAX];
+      }
+      y[sl][q] = v;
+    }
+  }
+  hh_qr_regs(y, mp, kk, vbuf, taus);
+  double *H = s.tree_H + hlev_off(tr, lev) + (size_t)t * PANEL_M * KMAX;
+  panel_store(y, H, PANEL_M, mp, kk);
+  double *R = s.tree_R + lev_off(tr, lev, (size_t)KMAX * KMAX) + (size_t)t * KMAX * KMAX;
+  double *Rf = (lev == tr.nlev - 1) ? s.Rfin : nullptr;
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int c = wave + 4 * sl;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = lane + 64 * q;
+      if (c < kk && i < kk) {
+        const double v = (i <= c && i < mp) ? y[sl][q] : 0.0;
+        R[i + c * KMAX] = v;
+        if (Rf) Rf[i + c * KMAX] = v;
+      }
+    }
+  }
+  double *T = s.tree_tau + lev_off(tr, lev, KMAX) + (size_t)t * KMAX;
+  for (int j = threadIdx.x; j < kk; j += NTHR) T[j] = (j < mp) ? taus[j] : 0.0;
+}
+
+// Top-down Q formation at an internal node: [Y; 0] -> child blocks.
+template <int NS>
+__global__ __launch_bounds__(NTHR) void k_tsqr_node_apply(int which, int lev,
+                                                         Tree tr, Solve2D *S) {
+  Solve2D &s = S[blockIdx.y];
+  if (s.active != ts_phase(which)) return;
+  const int kk = s.k;
+  const int t = blockIdx.x;
+  const int c0 = t * tr.fan;
+  const int nch = min(tr.fan, tr.nb[lev - 1] - c0);
+  const int mp = nch * kk;
+  const bool top = (lev == tr.nlev - 1);
+  const double *Yin = s.tree_Y + lev_off(tr, lev, (size_t)KMAX * KMAX) + (size_t)t * KMAX * KMAX;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double y[NS][4];
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int c = wave + 4 * sl;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = lane + 64 * q;
+      double v = 0.0;
+      if (c < kk && i < kk) v = top ? (i == c ? 1.0 : 0.0) : Yin[i + c * KMAX];
+      y[sl][q] = v;
+    }
+  }
+  const double *H = s.tree_H + hlev_off(tr, lev) + (size_t)t * PANEL_M * KMAX;
+  const double *T = s.tree_tau + lev_off(tr, lev, KMAX) + (size_t)t * KMAX;
+  hh_apply_regs(y, mp, min(mp, kk), kk, H, PANEL_M, T);
+  double *Yc = s.tree_Y + lev_off(tr, lev - 1, (size_t)KMAX * KMAX);
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int c = wave + 4 * sl;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = lane + 64 * q;
+      if (c < kk && i < mp) {
+        const int ch = i / kk, ii = i - ch * kk;
+        Yc[(size_t)(c0 + ch) * KMAX * KMAX + ii + c * KMAX] = y[sl][q];
+      }
+    }
+  }
+}
+
+template <int NS>
+__global__ __launch_bounds__(NTHR) void k_tsqr_leaf_apply(int which, int n,
+                                                         Tree tr, Solve2D *S) {
+  Solve2D &s = S[blockIdx.y];
+  if (s.active != ts_phase(which)) return;
+  const int kk = s.k;
+  const int b = blockIdx.x;
+  const int r0 = b * PANEL_M;
+  const int m = min(PANEL_M, n - r0);
+  const int mp = max(m, kk);
+  const bool top = (tr.nlev == 1);
+  const double *Yin = s.tree_Y + (size_t)b * KMAX * KMAX;   // level 0
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double y[NS][4];
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int c = wave + 4 * sl;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = lane + 64 * q;
+      double v = 0.0;
+      if (c < kk && i < kk) v = top ? (i == c ? 1.0 : 0.0) : Yin[i + c * KMAX];
+      y[sl][q] = v;
+    }
+  }
+  const double *T = s.tree_tau + (size_t)b * KMAX;
+  hh_apply_regs(y, m, min(mp, kk), kk, s.Hv + r0, n, T);
+  const TsIO io = ts_io(which, s);
+  panel_store(y, io.out + r0, n, m, kk);
+}
+
+template <int NS>
+hipError_t run_tsqr(int which, int n, const Tree &tr, Solve2D *s, int ns,
+                    hipStream_t st) {
+  dim3 blk(NTHR);
+  hipLaunchKernelGGL((k_tsqr_leaf<NS>), dim3(tr.nb[0], ns), blk, 0, st, which,
+                     n, tr, s);
+  for (int l = 1; l < tr.nlev; ++l)
+    hipLaunchKernelGGL((k_tsqr_node<NS>), dim3(tr.nb[l], ns), blk, 0, st, which, l,
+                       tr, s);
+  for (int l = tr.nlev - 1; l >= 1; --l)
+    hipLaunchKernelGGL((k_tsqr_node_apply<NS>), dim3(tr.nb[l], ns), blk, 0, st,
+                       which, l, tr, s);
+  hipLaunchKernelGGL((k_tsqr_leaf_apply<NS>), dim3(tr.nb[0], ns), blk, 0, st,
+                     which, n, tr, s);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+Tree make_tree(int n, int kmax) {
+  Tree t{};
+  int kp = 16;
+  while (kp < kmax) kp *= 2;
+  t.fan = PANEL_M / kp;
+  if (t.fan < 2) t.fan = 2;
+  t.nb[0] = ceil_div(n, PANEL_M);
+  t.nlev = 1;
+  while (t.nb[t.nlev - 1] > 1 && t.nlev < 8) {
+    t.nb[t.nlev] = ceil_div(t.nb[t.nlev - 1], t.fan);
+    ++t.nlev;
+  }
+  return t;
+}
+
+hipError_t launch_tsqr(int which, int n, const Tree &tr, Solve2D *s,
+                       int nsolves, int kmax, hipStream_t st) {
+  if (kmax <= 16) return run_tsqr<4>(which, n, tr, s, nsolves, st);
+  if (kmax <= 32) return run_tsqr<8>(which, n, tr, s, nsolves, st);
+  return run_tsqr<16>(which, n, tr, s, nsolves, st);
+}
+
+}  // namespace lrp

@@ -1,0 +1,90 @@
+"""The C-ABI library loads and exports every entry point the header declares,
+and argument validation rejects bad calls before touching a device.  No GPU
+work is done here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1306_2150_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lrpoisson.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.fail("liblrpoisson.so is not built (run __graft_entry__.build())")
+    return binding.load()
+
+
+def test_header_declares_expected_api():
+    names = declared_functions()
+    assert set(names) == set(binding.EXPORTS), names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror_is_host_only(lib):
+    assert binding.strerror(binding.LRP_OK) == "ok"
+    assert "invalid" in binding.strerror(binding.LRP_EINVAL)
+    assert binding.strerror(12345) == "unknown status"
+
+
+def test_null_context_rejected(lib):
+    P = ctypes.c_void_p
+    rank = ctypes.c_int32(0)
+    st = lib.lrpoisson_solve2d(None, 16, 2, P(1), P(1), 16, 1e-8, None, P(1),
+                               P(1), 16, 8, ctypes.byref(rank), None, None)
+    assert st == binding.LRP_EINVAL
+    assert lib.lrp_create(None, 0, 0) == binding.LRP_EINVAL
+    assert lib.lrp_destroy(None) == binding.LRP_EINVAL
+    assert lib.lrp_serve_step(None, None) == binding.LRP_EINVAL
+    assert lib.lrp_sine_transform(None, 16, 1, P(1), 16, P(1), 16, 0, None) == binding.LRP_EINVAL
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes mirrors of the public structs have the C compiler's layout."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "lrpoisson.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\\n", sizeof(lrp_opts), sizeof(lrp_info),
+         sizeof(lrp_problem2d), sizeof(lrp_request));
+  printf("%zu %zu %zu %zu\\n", offsetof(lrp_problem2d, eps),
+         offsetof(lrp_problem2d, info), offsetof(lrp_request, eps),
+         offsetof(lrp_request, Gx));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True,
+                         text=True).stdout.split()
+    got = [int(v) for v in out]
+    want = [ctypes.sizeof(binding.LrpOpts), ctypes.sizeof(binding.LrpInfo),
+            ctypes.sizeof(binding.LrpProblem2D), ctypes.sizeof(binding.LrpRequest),
+            binding.LrpProblem2D.eps.offset, binding.LrpProblem2D.info.offset,
+            binding.LrpRequest.eps.offset, binding.LrpRequest.Gx.offset]
+    assert got == want

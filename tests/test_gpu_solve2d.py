@@ -1,0 +1,202 @@
+"""GPU parity of the 2D path against the CPU oracle (through the C-ABI).
+
+Tolerances: the float64 sine transform must match the oracle's library DST to
+1e-13 (relative Frobenius; both are O(u log n)-accurate); a solve at
+tolerance eps must match the oracle's full-grid solution to 10 eps (relative
+Frobenius), the acceptance bar of the method.  Pivots, ranks and factors are
+not unique, so only the assembled solution and the orthonormality of Vx are
+compared.
+"""
+import numpy as np
+import pytest
+
+from oracle import metrics, poisson
+from paper_1306_2150_amd import binding, inputs
+
+from gpu_util import ctx, dev, host, log, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def sine_mode(n, p):
+    i = np.arange(1, n + 1, dtype=np.float64)
+    return np.sin(p * np.pi * i / (n + 1))
+
+
+# ---------------------------------------------------------- sine transform
+@pytest.mark.parametrize("n,c", [(1, 1), (2, 3), (3, 1), (63, 5), (64, 32),
+                                 (65, 33), (257, 17), (1000, 40), (4096, 32),
+                                 (4096, 100), (16384, 8)])
+def test_dst_fp64_matches_oracle(n, c):
+    log("dst fp64", n, c)
+    rng = np.random.default_rng(n * 7 + c)
+    X = rng.standard_normal((n, c))
+    Y = host(ctx().sine_transform(dev(X), "fp64"))
+    assert rel(Y, poisson.dst(X)) <= 1e-13
+
+
+def test_dst_leading_dimension_and_involution():
+    log("dst ld")
+    import torch
+    n, c = 300, 7
+    rng = np.random.default_rng(1)
+    X = rng.standard_normal((n, c))
+    big = torch.zeros((c, n + 13), dtype=torch.float64, device="cuda").T
+    big[:n].copy_(torch.from_numpy(X).cuda())
+    Xd = big[:n]
+    Y = ctx().sine_transform(Xd, "fp64")
+    Z = ctx().sine_transform(Y, "fp64")           # S S = I
+    assert rel(host(Z), X) <= 1e-13
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("bf16x3", 5e-5)])
+def test_dst_reduced_precision_error_bound(prec, tol):
+    log("dst", prec)
+    n, c = 4096, 32
+    U, V = inputs.rhs2d_bumps(n, 16, 2001)
+    X = np.hstack([U, V])
+    Y = host(ctx().sine_transform(dev(X), prec))
+    e = rel(Y, poisson.dst(X))
+    assert e <= tol, e
+
+
+# ------------------------------------------------------------- 2D solves
+def solve_and_check(U, V, eps, prec="fp64", bar=None, **kw):
+    Ux, Vx, info = ctx().solve2d(dev(U), dev(V), eps, prec=prec, **kw)
+    Ux, Vx = host(Ux), host(Vx)
+    X = poisson.full_solve2d_factors(U, V)
+    e = metrics.rel_err_factored(Ux, Vx, X)
+    bar = 10 * eps if bar is None else bar
+    assert info["status"] == binding.LRP_OK, info
+    assert e <= bar, (e, info)
+    if Vx.shape[1]:
+        # orthonormal to the precision of the inverse transform
+        otol = {"fp64": 1e-10, "fp32": 1e-6, "bf16x3": 1e-4}[info["inv_prec"]]
+        assert np.max(np.abs(Vx.T @ Vx - np.eye(Vx.shape[1]))) < otol
+    return e, info
+
+
+@pytest.mark.parametrize("inst", [1, 2, 3, 4])
+def test_solve2d_n256_eps1e10(inst):
+    log("solve2d n256 inst", inst)
+    U, V = inputs.workload_rhs(1, inst)
+    solve_and_check(U, V, 1e-10)
+
+
+@pytest.mark.parametrize("n,inst", [(1024, 1), (1024, 2), (1000, 3), (2049, 4)])
+def test_solve2d_bumps_eps1e8(n, inst):
+    log("solve2d bumps", n, inst)
+    U, V = inputs.workload_rhs(2, inst, n=n)
+    solve_and_check(U, V, 1e-8)
+
+
+def test_solve2d_n4096_r16_eps1e8():
+    log("solve2d n4096 r16")
+    U, V = inputs.workload_rhs(2, 1)
+    e, info = solve_and_check(U, V, 1e-8, bar=1e-7)
+    assert 15 <= info["rank"] <= 40
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 20])
+def test_solve2d_tiny_grids(n):
+    log("solve2d tiny", n)
+    rng = np.random.default_rng(n)
+    U, V = rng.standard_normal((n, 3)), rng.standard_normal((n, 3))
+    solve_and_check(U, V, 1e-12)
+
+
+def test_solve2d_single_mode_closed_form():
+    log("solve2d single mode")
+    n = 4096
+    u, v = sine_mode(n, 3), sine_mode(n, 77)
+    lam = poisson.eigenvalues(n)
+    Ux, Vx, info = ctx().solve2d(dev(u[:, None]), dev(v[:, None]), 1e-10)
+    Ux, Vx = host(Ux), host(Vx)
+    assert info["rank"] == 1
+    X = np.outer(u, v) / (lam[2] + lam[76])
+    assert metrics.rel_err_factored(Ux, Vx, X) < 1e-11
+
+
+def test_solve2d_exact_rank_q():
+    log("solve2d exact rank")
+    n, ps = 3000, [2, 11, 40, 151, 999]
+    rng = np.random.default_rng(14)
+    U = np.stack([sine_mode(n, p) for p in ps], axis=1)
+    V = rng.standard_normal((n, len(ps)))
+    Ux, Vx, info = ctx().solve2d(dev(U), dev(V), 1e-13)
+    assert info["rank"] == len(ps)
+    X = poisson.full_solve2d_factors(U, V)
+    assert metrics.rel_err_factored(host(Ux), host(Vx), X) < 1e-11
+
+
+def test_solve2d_zero_rhs():
+    log("solve2d zero")
+    U = np.zeros((500, 4))
+    V = np.ones((500, 4))
+    Ux, Vx, info = ctx().solve2d(dev(U), dev(V), 1e-8)
+    assert info["rank"] == 0 and info["status"] == binding.LRP_OK
+
+
+def test_solve2d_nonfinite_rejected():
+    log("solve2d nonfinite")
+    U, V = inputs.workload_rhs(2, 1, n=512)
+    U = U.copy()
+    U[100, 3] = np.nan
+    Ux, Vx, info = ctx().solve2d(dev(U), dev(V), 1e-8, check=False)
+    assert info["status_code"] == binding.LRP_ENONFINITE
+
+
+def test_solve2d_rank_cap_and_rmax():
+    log("solve2d caps")
+    U, V = inputs.workload_rhs(2, 2, n=1024)
+    # a cross capped at 8 columns cannot reach 1e-8 (the solution has rank ~25)
+    Ux, Vx, info = ctx().solve2d(dev(U), dev(V), 1e-8, check=False, rank_cap=8)
+    assert info["status_code"] in (binding.LRP_ERANKCAP, binding.LRP_ENOCONV)
+    # output capacity smaller than the rank: ERANKCAP with the needed rank
+    Ux, Vx, info = ctx().solve2d(dev(U), dev(V), 1e-8, rmax=4, check=False)
+    assert info["status_code"] == binding.LRP_ERANKCAP
+    assert info["rank"] > 4
+    # one sweep cannot show convergence
+    Ux, Vx, info = ctx().solve2d(dev(U), dev(V), 1e-8, check=False, max_sweeps=1)
+    assert info["status_code"] == binding.LRP_ENOCONV
+
+
+def test_solve2d_invalid_arguments():
+    log("solve2d einval")
+    c = ctx()
+    import torch
+    buf = torch.zeros((64, 8), dtype=torch.float64, device="cuda")
+    p = buf.data_ptr()
+    assert c.raw_solve2d(0, 2, p, p, 64, 1e-8, p, p, 64, 8)[0] == binding.LRP_EINVAL
+    assert c.raw_solve2d(64, 65, p, p, 64, 1e-8, p, p, 64, 8)[0] == binding.LRP_EINVAL
+    assert c.raw_solve2d(64, 2, p, p, 63, 1e-8, p, p, 64, 8)[0] == binding.LRP_EINVAL
+    assert c.raw_solve2d(64, 2, p, p, 64, 0.0, p, p, 64, 8)[0] == binding.LRP_EINVAL
+    assert c.raw_solve2d(64, 2, p, p, 64, 1.5, p, p, 64, 8)[0] == binding.LRP_EINVAL
+    assert c.raw_solve2d(64, 2, 0, p, 64, 1e-8, p, p, 64, 8)[0] == binding.LRP_EINVAL
+    assert c.raw_solve2d(64, 2, p, p, 64, 1e-8, p, p, 32, 8)[0] == binding.LRP_EINVAL
+
+
+def test_solve2d_batch_same_as_alone():
+    log("solve2d batch")
+    n = 2048
+    probs = []
+    for inst, eps in [(1, 1e-8), (2, 1e-6), (3, 1e-8), (4, 1e-10)]:
+        U, V = inputs.workload_rhs(2, inst, n=n)
+        probs.append((U, V, eps))
+    res_b = ctx().solve2d_batch([(dev(U), dev(V), eps) for U, V, eps in probs])
+    for (U, V, eps), (Uxb, Vxb, ib) in zip(probs, res_b):
+        Uxa, Vxa, ia = ctx().solve2d(dev(U), dev(V), eps)
+        A = host(Uxa) @ host(Vxa).T
+        B = host(Uxb) @ host(Vxb).T
+        assert ia["rank"] == ib["rank"]
+        assert rel(B, A) <= 1e-12
+        X = poisson.full_solve2d_factors(U, V)
+        assert metrics.rel_err_factored(host(Uxb), host(Vxb), X) <= 10 * eps
+
+
+@pytest.mark.parametrize("prec,eps,bar", [("fp32", 1e-7, 1e-6), ("auto", 1e-8, 1e-7),
+                                          ("auto", 1e-6, 1e-5), ("bf16x3", 1e-5, 1e-4)])
+def test_solve2d_mixed_precision(prec, eps, bar):
+    log("solve2d mixed", prec, eps)
+    U, V = inputs.workload_rhs(2, 1, n=4096)
+    solve_and_check(U, V, eps, prec=prec, bar=bar)
