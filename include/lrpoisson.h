@@ -182,6 +182,24 @@ lrp_status lrp_sine_transform(lrp_ctx *ctx, int64_t n, int32_t ncols,
                               const double *src, int64_t lds, double *dst,
                               int64_t ldd, int32_t prec, void *stream);
 
+/* Kernel timing of the sine-transform launches, for measurement.  While
+ * enabled, every transform launch is bracketed by two HIP events recorded on
+ * the stream it runs on; lrp_kernel_stats() waits for them and returns, per
+ * precision (index = lrp_precision: 0 FP64, 2 FP32, 3 BF16X3), the number of
+ * launches, their summed duration in ms and the summed algorithmic work of
+ * the dense formulation (2 n^2 flops per column).  reset != 0 clears the
+ * counters after reading.  Timing adds two event records per launch. */
+typedef struct {
+  int64_t launches;
+  int64_t columns;
+  double ms;
+  double flops;
+} lrp_kernel_stat;
+
+lrp_status lrp_set_kernel_timing(lrp_ctx *ctx, int32_t enable);
+lrp_status lrp_kernel_stats(lrp_ctx *ctx, int32_t prec, lrp_kernel_stat *out,
+                            int32_t reset);
+
 /* ---- Continuous-batching serving (same solver, asynchronous) ----------
  * A request is admitted when the context's device-memory budget has room
  * for its workspace; its factors stay resident on the device.  Each call of

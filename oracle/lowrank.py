@@ -145,7 +145,7 @@ def _stacked_change(A, B, Ap, Bp) -> float:
 
 def lr_solve2d(U: np.ndarray, V: np.ndarray, eps: float, kick: int = 8,
                k_max: int = 64, tau: float = 1.05, max_sweeps: int = 10,
-               min_slack: int = 4):
+               min_slack: int = 4, k0_extra: int = 0):
     """Low-rank solution of T X + X T = U V^T (returns Ux, Vx, info).
 
     See the module docstring for the steps and the reading of the paper.
@@ -170,7 +170,7 @@ def lr_solve2d(U: np.ndarray, V: np.ndarray, eps: float, kick: int = 8,
         return (Uh[I] @ Vh.T) / (lam[I][:, None] + lam[None, :])
 
     k_cap = min(n, k_max)
-    k = min(n, r + kick, k_max)
+    k = min(n, r + kick + k0_extra, k_max)
     Qv, _ = np.linalg.qr(Vh)
     J, _, _ = maxvol(Qv, tau)
     J = J[:k]

@@ -34,7 +34,8 @@ MAX_N = 32767
 # every symbol the header declares
 EXPORTS = ["lrp_create", "lrp_destroy", "lrp_strerror", "lrpoisson_solve2d",
            "lrpoisson_solve2d_batch", "lrpoisson_solve3d", "lrp_submit",
-           "lrp_serve_step", "lrp_poll", "lrp_sine_transform"]
+           "lrp_serve_step", "lrp_poll", "lrp_sine_transform",
+           "lrp_set_kernel_timing", "lrp_kernel_stats"]
 
 
 class LrpOpts(ctypes.Structure):
@@ -53,6 +54,11 @@ class LrpInfo(ctypes.Structure):
         return dict(status=self.status, sweeps=self.sweeps, k=self.k,
                     rank=self.rank, fwd_prec=PREC_NAME.get(self.fwd_prec),
                     inv_prec=PREC_NAME.get(self.inv_prec), change=self.change)
+
+
+class LrpKernelStat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("columns", ctypes.c_int64),
+                ("ms", ctypes.c_double), ("flops", ctypes.c_double)]
 
 
 class LrpProblem2D(ctypes.Structure):
@@ -108,6 +114,8 @@ def load(path: str = LIB_PATH):
                                       ctypes.POINTER(I32), ctypes.POINTER(I32),
                                       ctypes.POINTER(LrpInfo), P]
     lib.lrp_sine_transform.argtypes = [P, I64, I32, P, I64, P, I64, I32, P]
+    lib.lrp_set_kernel_timing.argtypes = [P, I32]
+    lib.lrp_kernel_stats.argtypes = [P, I32, ctypes.POINTER(LrpKernelStat), I32]
     lib.lrp_submit.argtypes = [P, ctypes.POINTER(LrpRequest), ctypes.POINTER(ctypes.c_uint64)]
     lib.lrp_serve_step.argtypes = [P, ctypes.POINTER(I32)]
     lib.lrp_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(I32),
@@ -250,6 +258,67 @@ class Context:
         if st != LRP_OK:
             raise LrpError(st, "lrp_sine_transform")
         return Y
+
+    # ---- kernel timing
+    def set_kernel_timing(self, on: bool):
+        st = self.lib.lrp_set_kernel_timing(self.h, 1 if on else 0)
+        if st != LRP_OK:
+            raise LrpError(st, "lrp_set_kernel_timing")
+
+    def kernel_stats(self, prec="fp64", reset=False):
+        k = LrpKernelStat()
+        st = self.lib.lrp_kernel_stats(self.h, PREC[prec], ctypes.byref(k),
+                                       1 if reset else 0)
+        if st != LRP_OK:
+            raise LrpError(st, "lrp_kernel_stats")
+        return dict(launches=k.launches, columns=k.columns, ms=k.ms, flops=k.flops)
+
+    # ---- serving
+    def submit(self, U, V, eps, prec="auto", rmax=None, out=None):
+        """Queue a 2D request; returns (ticket, (Ux, Vx))."""
+        n, r = U.shape
+        rmax = MAX_RANK if rmax is None else rmax
+        if out is None:
+            out = (empty_colmajor(n, rmax, U.device), empty_colmajor(n, rmax, U.device))
+        Ux, Vx = out
+        q = LrpRequest()
+        q.dim = 2
+        q.prec = PREC[prec]
+        q.n = n
+        q.rank[0] = r
+        q.rmax[0] = rmax
+        q.U[0] = _ptr(U)
+        q.U[1] = _ptr(V)
+        q.ld = _ld(U) if r else n
+        q.X[0] = _ptr(Ux)
+        q.X[1] = _ptr(Vx)
+        q.ldx = n
+        q.eps = eps
+        t = ctypes.c_uint64(0)
+        st = self.lib.lrp_submit(self.h, ctypes.byref(q), ctypes.byref(t))
+        if st != LRP_OK:
+            raise LrpError(st, "lrp_submit")
+        return t.value, (Ux, Vx)
+
+    def serve_step(self):
+        pend = ctypes.c_int32(0)
+        st = self.lib.lrp_serve_step(self.h, ctypes.byref(pend))
+        if st != LRP_OK:
+            raise LrpError(st, "lrp_serve_step")
+        return pend.value
+
+    def poll(self, ticket):
+        """None while pending, else (status, ranks, info)."""
+        res = ctypes.c_int32(0)
+        ranks = (ctypes.c_int32 * 3)()
+        info = LrpInfo()
+        st = self.lib.lrp_poll(self.h, ticket, ctypes.byref(res), ranks,
+                               ctypes.byref(info))
+        if st == LRP_ENOTREADY:
+            return None
+        if st != LRP_OK:
+            raise LrpError(st, "lrp_poll")
+        return res.value, list(ranks), info.as_dict()
 
     # ---- raw call for argument-validation tests
     def raw_solve2d(self, n, r, U, V, ld, eps, Ux, Vx, ldx, rmax, prec=0):

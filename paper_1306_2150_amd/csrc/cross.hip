@@ -36,10 +36,9 @@ __global__ __launch_bounds__(NTHR) void k_eval(int which, int n,
     P = s.Vh, Qm = s.Uh, sel = s.I;
   }
   const int kk = s.k, r = s.r;
-  for (int e = threadIdx.x; e < r * kk; e += NTHR) {
-    const int a = e / kk, l = e - a * kk;
-    qs[a * KMAX + l] = Qm[clamp_row(sel[l], n) + (long)a * n];
-  }
+  for (int a = threadIdx.x >> 6; a < r; a += 4)
+    for (int l = threadIdx.x & 63; l < kk; l += 64)
+      qs[a * KMAX + l] = Qm[clamp_row(sel[l], n) + (long)a * n];
   for (int l = threadIdx.x; l < kk; l += NTHR) ls[l] = lam[clamp_row(sel[l], n)];
   __syncthreads();
   const int i = blockIdx.x * NTHR + threadIdx.x;
@@ -47,10 +46,16 @@ __global__ __launch_bounds__(NTHR) void k_eval(int which, int n,
   double acc[KM];
 #pragma unroll
   for (int l = 0; l < KM; ++l) acc[l] = 0.0;
-  for (int a = 0; a < r; ++a) {
-    const double p = P[i + (long)a * n];
+  for (int a0 = 0; a0 < r; a0 += 8) {
+    double p[8];
 #pragma unroll
-    for (int l = 0; l < KM; ++l) acc[l] += p * qs[a * KMAX + l];
+    for (int t = 0; t < 8; ++t) p[t] = (a0 + t < r) ? P[i + (long)(a0 + t) * n] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      if (a0 + t >= r) break;
+#pragma unroll
+      for (int l = 0; l < KM; ++l) acc[l] += p[t] * qs[(a0 + t) * KMAX + l];
+    }
   }
   const double li = lam[i];
 #pragma unroll
@@ -67,66 +72,76 @@ __global__ __launch_bounds__(NTHR) void k_factors(int n, Solve2D *S) {
   const int kk = s.k, z = blockIdx.z;
   const double *Qz = z ? s.Q1 : s.Q0;
   double *out = z ? s.B : s.A;
-  for (int e = threadIdx.x; e < kk * kk; e += NTHR) {
-    const int j = e / kk, c = e - j * kk;
-    M[j * KMAX + c] = z ? s.Z[j + c * KMAX] : s.W[j + c * KMAX] * s.sig[c];
-  }
+  for (int j = threadIdx.x >> 6; j < kk; j += 4)
+    for (int c = threadIdx.x & 63; c < kk; c += 64)
+      M[j * KMAX + c] = z ? s.Z[j + c * KMAX] : s.W[j + c * KMAX] * s.sig[c];
   __syncthreads();
   const int i = blockIdx.x * NTHR + threadIdx.x;
   if (i >= n) return;
   double acc[KM];
 #pragma unroll
   for (int c = 0; c < KM; ++c) acc[c] = 0.0;
-  for (int j = 0; j < kk; ++j) {
-    const double q = Qz[i + (long)j * n];
+  for (int j0 = 0; j0 < kk; j0 += 8) {
+    double q[8];
 #pragma unroll
-    for (int c = 0; c < KM; ++c) acc[c] += q * M[j * KMAX + c];
+    for (int t = 0; t < 8; ++t) q[t] = (j0 + t < kk) ? Qz[i + (long)(j0 + t) * n] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      if (j0 + t >= kk) break;
+#pragma unroll
+      for (int c = 0; c < KM; ++c) acc[c] += q[t] * M[(j0 + t) * KMAX + c];
+    }
   }
 #pragma unroll
   for (int c = 0; c < KM; ++c)
     if (c < kk) out[i + (long)c * n] = acc[c];
 }
 
-// Partial M = Bp^T B over one 256-row block.
+// Partial M = Bp^T B over one 256-row block; each thread owns a 4 x 4 tile
+// of the (<= 64 x 64) result.
 __global__ __launch_bounds__(NTHR) void k_change_M(int n, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (s.active != ACT_SWEEP || s.kp == 0) return;
-  __shared__ double bp[64 * (KMAX + 1)];
-  __shared__ double bb[64 * (KMAX + 1)];
+  __shared__ double bp[64 * KMAX];   // [row][col]
+  __shared__ double bb[64 * KMAX];
   const int kk = s.k, kq = s.kp;
   const int r0 = blockIdx.x * PANEL_M;
-  const int nout = kq * kk;
-  double acc[16];
+  const int ta = (threadIdx.x >> 4) * 4, tc = (threadIdx.x & 15) * 4;
+  double acc[4][4];
 #pragma unroll
-  for (int t = 0; t < 16; ++t) acc[t] = 0.0;
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
   for (int ch = 0; ch < PANEL_M / 64; ++ch) {
     const int rb = r0 + ch * 64;
     __syncthreads();
     for (int e = threadIdx.x; e < 64 * KMAX; e += NTHR) {
-      const int c = e / 64, rr = e - c * 64;
+      const int c = e >> 6, rr = e & 63;
       const int row = rb + rr;
       const bool ok = row < n;
-      bp[rr * (KMAX + 1) + c] = (ok && c < kq) ? s.Bp[row + (long)c * n] : 0.0;
-      bb[rr * (KMAX + 1) + c] = (ok && c < kk) ? s.B[row + (long)c * n] : 0.0;
+      bp[rr * KMAX + c] = (ok && c < kq) ? s.Bp[row + (long)c * n] : 0.0;
+      bb[rr * KMAX + c] = (ok && c < kk) ? s.B[row + (long)c * n] : 0.0;
     }
     __syncthreads();
+    for (int rr = 0; rr < 64; ++rr) {
+      double x[4], y[4];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-      const int o = threadIdx.x + NTHR * t;
-      if (o < nout) {
-        const int a = o / kk, c = o - a * kk;
-        double v = 0.0;
-        for (int rr = 0; rr < 64; ++rr) v += bp[rr * (KMAX + 1) + a] * bb[rr * (KMAX + 1) + c];
-        acc[t] += v;
+      for (int t = 0; t < 4; ++t) {
+        x[t] = bp[rr * KMAX + ta + t];
+        y[t] = bb[rr * KMAX + tc + t];
       }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] += x[a] * y[c];
     }
   }
   double *P = s.part + (size_t)blockIdx.x * KMAX * KMAX;
 #pragma unroll
-  for (int t = 0; t < 16; ++t) {
-    const int o = threadIdx.x + NTHR * t;
-    if (o < nout) P[o] = acc[t];
-  }
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      if (ta + a < kq && tc + c < kk) P[(ta + a) * kk + tc + c] = acc[a][c];
 }
 
 __global__ __launch_bounds__(NTHR) void k_change_reduce(int nb0, Solve2D *S) {
@@ -155,22 +170,34 @@ __global__ __launch_bounds__(NTHR) void k_change_norms(int n, Solve2D *S) {
   const int i = blockIdx.x * NTHR + threadIdx.x;
   double n1 = 0.0, n2 = 0.0;
   if (i < n) {
-    double v[KM];
+    double v[KM], w[KM];
 #pragma unroll
-    for (int a = 0; a < KM; ++a) v[a] = (a < kq) ? s.Ap[i + (long)a * n] : 0.0;
-    for (int c = 0; c < kk; ++c) {
-      double x = s.A[i + (long)c * n];
-#pragma unroll
-      for (int a = 0; a < KM; ++a) x -= v[a] * M[a * KMAX + c];
-      n1 += x * x;
+    for (int a = 0; a < KM; ++a) {
+      v[a] = (a < kq) ? s.Ap[i + (long)a * n] : 0.0;
+      w[a] = (a < kk) ? s.A[i + (long)a * n] : 0.0;
     }
 #pragma unroll
-    for (int c = 0; c < KM; ++c) v[c] = (c < kk) ? s.B[i + (long)c * n] : 0.0;
-    for (int a = 0; a < kq; ++a) {
-      double x = s.Bp[i + (long)a * n];
+    for (int c = 0; c < KM; ++c) {
+      if (c < kk) {
+        double x = w[c];
 #pragma unroll
-      for (int c = 0; c < KM; ++c) x -= v[c] * M[a * KMAX + c];
-      n2 += sp2[a] * x * x;
+        for (int a = 0; a < KM; ++a) x -= v[a] * M[a * KMAX + c];
+        n1 += x * x;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < KM; ++c) {
+      v[c] = (c < kk) ? s.B[i + (long)c * n] : 0.0;
+      w[c] = (c < kq) ? s.Bp[i + (long)c * n] : 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < KM; ++a) {
+      if (a < kq) {
+        double x = w[a];
+#pragma unroll
+        for (int c = 0; c < KM; ++c) x -= v[c] * M[a * KMAX + c];
+        n2 += sp2[a] * x * x;
+      }
     }
   }
   n1 = wave_sum(n1);

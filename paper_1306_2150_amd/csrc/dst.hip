@@ -100,140 +100,278 @@ __device__ __forceinline__ void store_out(double v, int row, int col, int n,
 }
 
 // ------------------------------------------------------------------ FP64
+// 128 rows (4 waves x 32) x TN columns per workgroup.  The source tile is
+// staged in LDS as [column][k] with one double of padding per column (the
+// 16 lanes that read one k for 16 columns then hit distinct banks), double
+// buffered: the next K stage is fetched into registers while the MFMAs run on
+// the current one.
+constexpr int TM64 = 128;
+constexpr int KC64 = 32;
+constexpr int LDT = KC64 + 1;
+
+template <int TN_>
 __global__ __launch_bounds__(NTHR) void k_dst_f64(
     int n, int Q, const double *__restrict__ qtab,
     const DstCol *__restrict__ cols, int ncols, int kchunk,
     double *__restrict__ partial, Solve2D *solves) {
+  constexpr int NB = TN_ / 16;                    // column blocks per wave
+  constexpr int PER = KC64 * TN_ / NTHR;          // tile values per thread
   extern __shared__ __align__(16) unsigned char smem[];
   const int Qp = (Q + 1) & ~1;
   double *tab = (double *)smem;
-  double *xs = tab + Qp;                         // [KC][TN]
+  double *xs0 = tab + Qp;                         // [TN][LDT] x 2 buffers
   const int N = n + 1, twoN = 2 * N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int row0 = blockIdx.x * TM, c0 = blockIdx.y * TN;
+  const int row0 = blockIdx.x * TM64, c0 = blockIdx.y * TN_;
   int cb, ce;
   chunk_range(n, kchunk, cb, ce);
   for (int i = tid; i < Q; i += NTHR) tab[i] = qtab[i];
 
-  const int j = row0 + wave * 16 + (lane & 15);  // S row j+1
-  const int kk = lane >> 4;
-  const int step = (int)((4LL * (j + 1)) % twoN);
-  d4 acc[TN / 16];
+  // this thread's share of a K stage: k offset tk (32 lanes read 32
+  // consecutive k of one column), columns tc0 + 8 t
+  const int tk = tid & 31, tc0 = tid >> 5;
+  const double *src[PER];
+  int sidx[PER];
 #pragma unroll
-  for (int b = 0; b < TN / 16; ++b) acc[b] = (d4){0, 0, 0, 0};
+  for (int t = 0; t < PER; ++t) {
+    const int c = c0 + tc0 + 8 * t;
+    src[t] = nullptr;
+    sidx[t] = -1;
+    if (c < ncols) {
+      const DstCol dc = cols[c];
+      src[t] = dc.src;
+      sidx[t] = dc.solve;
+    }
+  }
+  const int kbeg = cb * kchunk, kend = min(n, ce * kchunk);
+  const int nst = (kend - kbeg + KC64 - 1) / KC64;
+  double pre[PER];
+  unsigned bad = 0;
+  auto fetch = [&](int st) {
+    const int k = kbeg + st * KC64 + tk;
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      double v = 0.0;
+      if (src[t] && k < kend) {
+        v = src[t][k];
+        if (!isfinite(v)) bad |= 1u << t;
+      }
+      pre[t] = v;
+    }
+  };
+  auto stash = [&](int st) {
+    double *xs = xs0 + (st & 1) * TN_ * LDT;
+#pragma unroll
+    for (int t = 0; t < PER; ++t) xs[(tc0 + 8 * t) * LDT + tk] = pre[t];
+  };
 
-  for (int ch = cb; ch < ce; ++ch) {
-    const int kb = ch * kchunk, ke = min(n, kb + kchunk);
-    int m = (int)(((long long)(j + 1) * (kb + kk + 1)) % twoN);
-    d4 part[TN / 16];
+  const int jA = row0 + wave * 32 + (lane & 15);  // S rows jA+1, jA+17
+  const int jB = jA + 16;
+  const int kk = lane >> 4;
+  const int stepA = (int)((4LL * (jA + 1)) % twoN);
+  const int stepB = (int)((4LL * (jB + 1)) % twoN);
+  int mA = (int)(((long long)(jA + 1) * (kbeg + kk + 1)) % twoN);
+  int mB = (int)(((long long)(jB + 1) * (kbeg + kk + 1)) % twoN);
+  d4 acc[2][NB], part[2][NB];
 #pragma unroll
-    for (int b = 0; b < TN / 16; ++b) part[b] = (d4){0, 0, 0, 0};
-    for (int k0 = kb; k0 < ke; k0 += KC) {
-      __syncthreads();
-      load_tile(cols, ncols, c0, k0, ke, solves,
-                [&](int kc, int c, double v) { xs[kc * TN + c] = v; });
-      __syncthreads();
-      const int kcn = min(KC, ke - k0);
-      for (int kc = 0; kc < kcn; kc += 4) {
-        const double a = sine_lookup(tab, m, N);
-        m += step;
-        if (m >= twoN) m -= twoN;
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int b = 0; b < TN / 16; ++b) {
-          const double bv = xs[(kc + kk) * TN + b * 16 + (lane & 15)];
-          part[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, part[b], 0, 0, 0);
+    for (int b = 0; b < NB; ++b) acc[h][b] = part[h][b] = (d4){0, 0, 0, 0};
+
+  fetch(0);
+  __syncthreads();                                // table in LDS
+  stash(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int k0 = kbeg + st * KC64;
+    if (st > 0 && (k0 % kchunk) == 0) {           // a new K chunk starts
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          acc[h][b] += part[h][b];
+          part[h][b] = (d4){0, 0, 0, 0};
         }
+    }
+    if (st + 1 < nst) fetch(st + 1);
+    const double *xs = xs0 + (st & 1) * TN_ * LDT;
+    const int kcn = min(KC64, kend - k0);
+    for (int kc = 0; kc < kcn; kc += 4) {
+      const double aA = sine_lookup(tab, mA, N);
+      const double aB = sine_lookup(tab, mB, N);
+      mA += stepA;
+      if (mA >= twoN) mA -= twoN;
+      mB += stepB;
+      if (mB >= twoN) mB -= twoN;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const double bv = xs[(b * 16 + (lane & 15)) * LDT + kc + kk];
+        part[0][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aA, bv, part[0][b], 0, 0, 0);
+        part[1][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aB, bv, part[1][b], 0, 0, 0);
       }
     }
-#pragma unroll
-    for (int b = 0; b < TN / 16; ++b) acc[b] += part[b];
+    if (st + 1 < nst) stash(st + 1);
+    __syncthreads();
   }
+#pragma unroll
+  for (int t = 0; t < PER; ++t)
+    if (((bad >> t) & 1u) && sidx[t] >= 0) solves[sidx[t]].nonfinite = 1;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[h][b] += part[h][b];
   // f64 layout: D[i][jj] at lane jj + 16 (i % 4), register i / 4
 #pragma unroll
-  for (int b = 0; b < TN / 16; ++b)
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = row0 + wave * 16 + (lane >> 4) + 4 * r;
-      const int col = c0 + b * 16 + (lane & 15);
-      store_out(acc[b][r], row, col, n, ncols, cols, partial, blockIdx.z);
-    }
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wave * 32 + h * 16 + (lane >> 4) + 4 * r;
+        const int col = c0 + b * 16 + (lane & 15);
+        store_out(acc[h][b][r], row, col, n, ncols, cols, partial, blockIdx.z);
+      }
 }
 
 // ------------------------------------------------------------------ FP32
+// Same tiling as the float64 kernel with float32 operands; the MFMA sums run
+// in float32 over 32-deep K runs that are flushed into float64 chunk sums.
 constexpr int F32_RUN = 32;   // K depth accumulated in float32
+constexpr int LDT32 = KC64 + 1;
 
+template <int TN_>
 __global__ __launch_bounds__(NTHR) void k_dst_f32(
     int n, int Q, const float *__restrict__ qtab,
     const DstCol *__restrict__ cols, int ncols, int kchunk,
     double *__restrict__ partial, Solve2D *solves) {
+  constexpr int NB = TN_ / 16;
+  constexpr int PER = KC64 * TN_ / NTHR;
   extern __shared__ __align__(16) unsigned char smem[];
   const int Qp = (Q + 3) & ~3;
   float *tab = (float *)smem;
-  float *xs = tab + Qp;                          // [KC][TN]
+  float *xs0 = tab + Qp;                          // [TN][LDT32] x 2 buffers
   const int N = n + 1, twoN = 2 * N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int row0 = blockIdx.x * TM, c0 = blockIdx.y * TN;
+  const int row0 = blockIdx.x * TM64, c0 = blockIdx.y * TN_;
   int cb, ce;
   chunk_range(n, kchunk, cb, ce);
   for (int i = tid; i < Q; i += NTHR) tab[i] = qtab[i];
 
-  const int j = row0 + wave * 16 + (lane & 15);
-  const int kk = lane >> 4;
-  const int step = (int)((4LL * (j + 1)) % twoN);
-  double acc[TN / 16][4], part[TN / 16][4];
-  f4 run[TN / 16];
+  const int tk = tid & 31, tc0 = tid >> 5;
+  const double *src[PER];
+  int sidx[PER];
 #pragma unroll
-  for (int b = 0; b < TN / 16; ++b) {
-    run[b] = (f4){0, 0, 0, 0};
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc[b][r] = 0.0;
-  }
-  for (int ch = cb; ch < ce; ++ch) {
-  const int kb = ch * kchunk, ke = min(n, kb + kchunk);
-  int m = (int)(((long long)(j + 1) * (kb + kk + 1)) % twoN);
-#pragma unroll
-  for (int b = 0; b < TN / 16; ++b)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) part[b][r] = 0.0;
-  for (int k0 = kb; k0 < ke; k0 += KC) {
-    __syncthreads();
-    load_tile(cols, ncols, c0, k0, ke, solves,
-              [&](int kc, int c, double v) { xs[kc * TN + c] = (float)v; });
-    __syncthreads();
-    const int kcn = min(KC, ke - k0);
-    for (int kc = 0; kc < kcn; kc += 4) {
-      const float a = sine_lookup(tab, m, N);
-      m += step;
-      if (m >= twoN) m -= twoN;
-#pragma unroll
-      for (int b = 0; b < TN / 16; ++b) {
-        const float bv = xs[(kc + kk) * TN + b * 16 + (lane & 15)];
-        run[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, run[b], 0, 0, 0);
-      }
-      if (((kc + 4) % F32_RUN) == 0 || kc + 4 >= kcn) {
-#pragma unroll
-        for (int b = 0; b < TN / 16; ++b) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) part[b][r] += (double)run[b][r];
-          run[b] = (f4){0, 0, 0, 0};
-        }
-      }
+  for (int t = 0; t < PER; ++t) {
+    const int c = c0 + tc0 + 8 * t;
+    src[t] = nullptr;
+    sidx[t] = -1;
+    if (c < ncols) {
+      const DstCol dc = cols[c];
+      src[t] = dc.src;
+      sidx[t] = dc.solve;
     }
   }
+  const int kbeg = cb * kchunk, kend = min(n, ce * kchunk);
+  const int nst = (kend - kbeg + KC64 - 1) / KC64;
+  float pre[PER];
+  unsigned bad = 0;
+  auto fetch = [&](int st) {
+    const int k = kbeg + st * KC64 + tk;
 #pragma unroll
-  for (int b = 0; b < TN / 16; ++b)
+    for (int t = 0; t < PER; ++t) {
+      double v = 0.0;
+      if (src[t] && k < kend) {
+        v = src[t][k];
+        if (!isfinite(v)) bad |= 1u << t;
+      }
+      pre[t] = (float)v;
+    }
+  };
+  auto stash = [&](int st) {
+    float *xs = xs0 + (st & 1) * TN_ * LDT32;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[b][r] += part[b][r];
+    for (int t = 0; t < PER; ++t) xs[(tc0 + 8 * t) * LDT32 + tk] = pre[t];
+  };
+
+  const int jA = row0 + wave * 32 + (lane & 15);
+  const int jB = jA + 16;
+  const int kk = lane >> 4;
+  const int stepA = (int)((4LL * (jA + 1)) % twoN);
+  const int stepB = (int)((4LL * (jB + 1)) % twoN);
+  int mA = (int)(((long long)(jA + 1) * (kbeg + kk + 1)) % twoN);
+  int mB = (int)(((long long)(jB + 1) * (kbeg + kk + 1)) % twoN);
+  f4 run[2][NB];
+  double acc[2][NB][4], part[2][NB][4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      run[h][b] = (f4){0, 0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[h][b][r] = part[h][b][r] = 0.0;
+    }
+
+  fetch(0);
+  __syncthreads();
+  stash(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int k0 = kbeg + st * KC64;
+    if (st > 0 && (k0 % kchunk) == 0) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            acc[h][b][r] += part[h][b][r];
+            part[h][b][r] = 0.0;
+          }
+    }
+    if (st + 1 < nst) fetch(st + 1);
+    const float *xs = xs0 + (st & 1) * TN_ * LDT32;
+    const int kcn = min(KC64, kend - k0);
+    for (int kc = 0; kc < kcn; kc += 4) {
+      const float aA = sine_lookup(tab, mA, N);
+      const float aB = sine_lookup(tab, mB, N);
+      mA += stepA;
+      if (mA >= twoN) mA -= twoN;
+      mB += stepB;
+      if (mB >= twoN) mB -= twoN;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const float bv = xs[(b * 16 + (lane & 15)) * LDT32 + kc + kk];
+        run[0][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aA, bv, run[0][b], 0, 0, 0);
+        run[1][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aB, bv, run[1][b], 0, 0, 0);
+      }
+    }
+    // a stage is one 32-deep float32 run
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) part[h][b][r] += (double)run[h][b][r];
+        run[h][b] = (f4){0, 0, 0, 0};
+      }
+    if (st + 1 < nst) stash(st + 1);
+    __syncthreads();
   }
+#pragma unroll
+  for (int t = 0; t < PER; ++t)
+    if (((bad >> t) & 1u) && sidx[t] >= 0) solves[sidx[t]].nonfinite = 1;
   // f32 layout: D[i][jj] at lane jj + 16 (i / 4), register i % 4
 #pragma unroll
-  for (int b = 0; b < TN / 16; ++b)
+  for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = row0 + wave * 16 + 4 * (lane >> 4) + r;
-      const int col = c0 + b * 16 + (lane & 15);
-      store_out(acc[b][r], row, col, n, ncols, cols, partial, blockIdx.z);
-    }
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wave * 32 + h * 16 + 4 * (lane >> 4) + r;
+        const int col = c0 + b * 16 + (lane & 15);
+        store_out(acc[h][b][r] + part[h][b][r], row, col, n, ncols, cols, partial,
+                  blockIdx.z);
+      }
 }
 
 // ---------------------------------------------------------------- BF16x3
@@ -383,19 +521,39 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
   const float *t32 = (const float *)(base + (size_t)Qp8 * 8);
   const uint32_t *tbf = (const uint32_t *)(base + (size_t)Qp8 * 8 + (size_t)Qp4 * 4);
   if (prec == LRP_PREC_FP64) {
-    lds = (size_t)Qp8 * 8 + (size_t)KC * TN * 8;
-    e = hipFuncSetAttribute((const void *)k_dst_f64,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const bool wide = ncols > 32;
+    const int tn = wide ? 64 : 32;
+    dim3 g64(ceil_div(n, TM64), ceil_div(ncols, tn), grid.z);
+    if (g64.x * g64.y >= 512) g64.z = 1;
+    if (g64.z == 1) out_partial = nullptr;
+    lds = (size_t)Qp8 * 8 + (size_t)2 * tn * LDT * 8;
+    const void *fn = wide ? (const void *)k_dst_f64<64> : (const void *)k_dst_f64<32>;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dst_f64, grid, block, lds, st, n, Q, t64, cols, ncols,
-                       kchunk, out_partial, solves);
+    if (wide)
+      hipLaunchKernelGGL(k_dst_f64<64>, g64, block, lds, st, n, Q, t64, cols, ncols,
+                         kchunk, out_partial, solves);
+    else
+      hipLaunchKernelGGL(k_dst_f64<32>, g64, block, lds, st, n, Q, t64, cols, ncols,
+                         kchunk, out_partial, solves);
+    split = g64.z;
   } else if (prec == LRP_PREC_FP32) {
-    lds = (size_t)Qp4 * 4 + (size_t)KC * TN * 4;
-    e = hipFuncSetAttribute((const void *)k_dst_f32,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const bool wide = ncols > 32;
+    const int tn = wide ? 64 : 32;
+    dim3 g32(ceil_div(n, TM64), ceil_div(ncols, tn), grid.z);
+    if (g32.x * g32.y >= 512) g32.z = 1;
+    if (g32.z == 1) out_partial = nullptr;
+    lds = (size_t)Qp4 * 4 + (size_t)2 * tn * LDT32 * 4;
+    const void *fn = wide ? (const void *)k_dst_f32<64> : (const void *)k_dst_f32<32>;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dst_f32, grid, block, lds, st, n, Q, t32, cols, ncols,
-                       kchunk, out_partial, solves);
+    if (wide)
+      hipLaunchKernelGGL(k_dst_f32<64>, g32, block, lds, st, n, Q, t32, cols, ncols,
+                         kchunk, out_partial, solves);
+    else
+      hipLaunchKernelGGL(k_dst_f32<32>, g32, block, lds, st, n, Q, t32, cols, ncols,
+                         kchunk, out_partial, solves);
+    split = g32.z;
   } else {
     lds = (size_t)Qp4 * 4 + (size_t)KC * TN * 2 * 2;
     e = hipFuncSetAttribute((const void *)k_dst_bf16x3,

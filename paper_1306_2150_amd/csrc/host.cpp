@@ -32,6 +32,26 @@ void dev_free(lrp_ctx *ctx, void *p, size_t bytes) {
   ctx->used -= std::min(ctx->used, bytes);
 }
 
+hipError_t timed_dst(lrp_ctx *ctx, int prec, int n, const void *tab,
+                     const DstCol *cols, int ncols, Solve2D *solves,
+                     double *partial, size_t partial_elems, hipStream_t st) {
+  if (!ctx->timing)
+    return launch_dst(prec, n, tab, cols, ncols, solves, partial, partial_elems, st);
+  lrp_ctx::PendingTime pt;
+  hipError_t e = hipEventCreate(&pt.a);
+  if (e != hipSuccess) return e;
+  if ((e = hipEventCreate(&pt.b)) != hipSuccess) return e;
+  if ((e = hipEventRecord(pt.a, st)) != hipSuccess) return e;
+  e = launch_dst(prec, n, tab, cols, ncols, solves, partial, partial_elems, st);
+  if (e != hipSuccess) return e;
+  if ((e = hipEventRecord(pt.b, st)) != hipSuccess) return e;
+  pt.prec = prec;
+  pt.cols = ncols;
+  pt.flops = 2.0 * (double)n * (double)n * (double)ncols;
+  ctx->pending_times.push_back(pt);
+  return hipSuccess;
+}
+
 static uint32_t bf16_rne_host(float f) {
   uint32_t u;
   std::memcpy(&u, &f, 4);
@@ -303,8 +323,8 @@ lrp_status Group2D::dst_cols(std::vector<DstCol> &cols, int prec, hipStream_t st
     HIPCHK(hipStreamSynchronize(st));
     std::memcpy(h_cols_, cols.data() + done, sizeof(DstCol) * cnt);
     HIPCHK(hipMemcpyAsync(d_cols_, h_cols_, sizeof(DstCol) * cnt, hipMemcpyHostToDevice, st));
-    HIPCHK(launch_dst(prec, n_, tabs_->tab, d_cols_, cnt, d_s_, d_partial_,
-                      partial_elems_, st));
+    HIPCHK(timed_dst(ctx_, prec, n_, tabs_->tab, d_cols_, cnt, d_s_, d_partial_,
+                     partial_elems_, st));
     done += cnt;
   }
   return LRP_OK;
@@ -470,10 +490,40 @@ lrp_status lrp_sine_transform(lrp_ctx *ctx, int64_t n, int32_t ncols,
     if (hipMemcpyAsync(ctx->tx_dcols, ctx->tx_hcols, sizeof(DstCol) * cnt,
                        hipMemcpyHostToDevice, st) != hipSuccess)
       return LRP_EDEVICE;
-    if (launch_dst(prec, (int)n, t->tab, ctx->tx_dcols, cnt, nullptr,
-                   ctx->tx_partial, ctx->tx_partial_elems, st) != hipSuccess)
+    if (timed_dst(ctx, prec, (int)n, t->tab, ctx->tx_dcols, cnt, nullptr,
+                  ctx->tx_partial, ctx->tx_partial_elems, st) != hipSuccess)
       return LRP_EDEVICE;
   }
+  return LRP_OK;
+}
+
+lrp_status lrp_set_kernel_timing(lrp_ctx *ctx, int32_t enable) {
+  if (!ctx) return LRP_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  ctx->timing = enable != 0;
+  return LRP_OK;
+}
+
+lrp_status lrp_kernel_stats(lrp_ctx *ctx, int32_t prec, lrp_kernel_stat *out,
+                            int32_t reset) {
+  if (!ctx || prec < 0 || prec > 3 || prec == LRP_PREC_AUTO) return LRP_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  if (hipSetDevice(ctx->device) != hipSuccess) return LRP_EDEVICE;
+  for (auto &pt : ctx->pending_times) {
+    if (hipEventSynchronize(pt.b) != hipSuccess) return LRP_EDEVICE;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pt.a, pt.b) != hipSuccess) return LRP_EDEVICE;
+    lrp_kernel_stat &k = ctx->kstat[pt.prec];
+    k.launches += 1;
+    k.columns += pt.cols;
+    k.ms += ms;
+    k.flops += pt.flops;
+    (void)hipEventDestroy(pt.a);
+    (void)hipEventDestroy(pt.b);
+  }
+  ctx->pending_times.clear();
+  if (out) *out = ctx->kstat[prec];
+  if (reset) ctx->kstat[prec] = lrp_kernel_stat{};
   return LRP_OK;
 }
 

@@ -53,6 +53,7 @@ class Group2D {
   lrp_status inverse(const std::vector<int> &slots, hipStream_t st);
 
   Solve2D &host(int i) { return h_s_[i]; }
+  Solve2D *dev_solves() { return d_s_; }
   const Plan &plan(int i) const { return plans_[i]; }
   std::vector<int> free_slots;
 
@@ -107,6 +108,16 @@ struct lrp_ctx {
   int tx_cap = 0;
   double *tx_partial = nullptr;
   size_t tx_partial_elems = 0, tx_bytes = 0;
+  // transform kernel timing (events recorded around each launch)
+  bool timing = false;
+  struct PendingTime {
+    hipEvent_t a, b;
+    int prec;
+    long cols;
+    double flops;
+  };
+  std::vector<PendingTime> pending_times;
+  lrp_kernel_stat kstat[4] = {};
   std::mutex mu;
 };
 
@@ -114,5 +125,9 @@ namespace lrp {
 const GridTables *get_tables(lrp_ctx *ctx, int n, lrp_status *err);
 Plan make_plan(const lrp_opts *o, double eps, int n);
 lrp_status dev_alloc(lrp_ctx *ctx, void **p, size_t bytes);
+// launch_dst with optional event timing for the context
+hipError_t timed_dst(lrp_ctx *ctx, int prec, int n, const void *tab,
+                     const DstCol *cols, int ncols, Solve2D *solves,
+                     double *partial, size_t partial_elems, hipStream_t st);
 void dev_free(lrp_ctx *ctx, void *p, size_t bytes);
 }  // namespace lrp

@@ -94,25 +94,77 @@ struct DstCol {
 };
 
 // ---------------------------------------------------------------- helpers
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Wave-wide reductions on DPP lane moves (VALU, no LDS round trip): quad
+// permutes and row shifts reduce each 16-lane row into its lane 15, and the
+// four row results are combined from v_readlane values, so every lane gets
+// the same total.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v, int fill) {
+  return __builtin_amdgcn_update_dpp(fill, v, CTRL, 0xf, 0xf, false);
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
 }
 
-// argmax of |v| over a wave with lowest-index tie breaking; index is an
-// arbitrary int key (smaller wins on ties).  Returns value and key in all
-// lanes.
-__device__ __forceinline__ void wave_argmax(double &v, int &key) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    double ov = __shfl_xor(v, o, 64);
-    int ok = __shfl_xor(key, o, 64);
-    if (ov > v || (ov == v && ok < key)) {
-      v = ov;
-      key = ok;
-    }
+constexpr int DPP_QUAD_1032 = 0xb1;   // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_2301 = 0x4e;   // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_SHR4 = 0x114;
+constexpr int DPP_ROW_SHR8 = 0x118;
+
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_f64<DPP_QUAD_1032>(v);
+  v += dpp_f64<DPP_QUAD_2301>(v);
+  v += dpp_f64<DPP_ROW_SHR4>(v);      // out-of-row lanes read 0
+  v += dpp_f64<DPP_ROW_SHR8>(v);
+  return (readlane_f64(v, 15) + readlane_f64(v, 31)) +
+         (readlane_f64(v, 47) + readlane_f64(v, 63));
+}
+
+// Larger value wins; ties go to the smaller key.
+__device__ __forceinline__ void argmax_merge(double &v, int &key, double ov, int ok) {
+  if (ov > v || (ov == v && ok < key)) {
+    v = ov;
+    key = ok;
   }
+}
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(double &v, int &key) {
+  // shifted-in lanes outside the row see (-inf, INT_MAX) and never win
+  const int lo = __builtin_amdgcn_update_dpp((int)0x00000000, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)0xfff00000, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  const int ok = __builtin_amdgcn_update_dpp(0x7fffffff, key, CTRL, 0xf, 0xf, false);
+  argmax_merge(v, key, __hiloint2double(hi, lo), ok);
+}
+
+// argmax of v over the wave with lowest-key tie breaking; result in all
+// lanes.  Lanes that must not compete pass v = -1 (values are |.| >= 0) or
+// -inf.
+__device__ __forceinline__ void wave_argmax(double &v, int &key) {
+  argmax_step<DPP_QUAD_1032>(v, key);
+  argmax_step<DPP_QUAD_2301>(v, key);
+  argmax_step<DPP_ROW_SHR4>(v, key);
+  argmax_step<DPP_ROW_SHR8>(v, key);
+  double bv = readlane_f64(v, 15);
+  int bk = __builtin_amdgcn_readlane(key, 15);
+#pragma unroll
+  for (int r = 1; r < 4; ++r)
+    argmax_merge(bv, bk, readlane_f64(v, 16 * r + 15),
+                 __builtin_amdgcn_readlane(key, 16 * r + 15));
+  v = bv;
+  key = bk;
+}
+
+// Value of lane `src` (wave-uniform) in every lane.
+__device__ __forceinline__ double bcast_f64(double v, int src) {
+  return readlane_f64(v, src);
 }
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }

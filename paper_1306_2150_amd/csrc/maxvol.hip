@@ -109,59 +109,63 @@ __global__ __launch_bounds__(NTHR) void k_mv_node(int which, int n, int lev,
   for (int j = threadIdx.x; j < kk; j += NTHR) dst[j] = (j < np) ? rows[piv[j]] : -1;
 }
 
-// ---- Inv = Q[I,:]^-1 by Gauss-Jordan with partial pivoting (one workgroup)
+// ---- Inv = Q[I,:]^-1 by Gauss-Jordan with partial pivoting (one workgroup).
+// Rows are not exchanged: the pivot row of column j is flagged and scaled,
+// all other rows are eliminated against it; at the end row p_j of the right
+// half is row j of the inverse.  Threads: column cl = tid & 63 (and
+// cl + 64), rows i0 = tid >> 6 stepping by 4.
 __global__ __launch_bounds__(NTHR) void k_mv_inv(int which, int n, int force,
                                                 Solve2D *S) {
   Solve2D &s = S[blockIdx.x];
   if (s.active != mv_phase(which)) return;
   if (!force && s.mv_done) return;
-  __shared__ double a[KMAX][2 * KMAX + 1];
+  constexpr int W2 = 2 * KMAX;                 // augmented row length
+  __shared__ double a[KMAX][W2 + 1];
+  __shared__ double prow[W2];
   __shared__ double f[KMAX];
+  __shared__ int pivrow[KMAX];
+  __shared__ int used[KMAX];
   __shared__ int shp;
+  __shared__ double sip;
   const int kk = s.k, w2 = 2 * kk;
+  const int cl = threadIdx.x & 63, i0 = threadIdx.x >> 6;
   const MvIO io = mv_io(which, s);
-  for (int e = threadIdx.x; e < kk * w2; e += NTHR) {
-    const int i = e / w2, c = e - i * w2;
-    a[i][c] = (c < kk) ? io.Q[clamp_row(io.out[i], n) + (long)c * n] : ((c - kk == i) ? 1.0 : 0.0);
-  }
+  for (int i = i0; i < kk; i += 4)
+    for (int c = cl; c < w2; c += 64)
+      a[i][c] = (c < kk) ? io.Q[clamp_row(io.out[i], n) + (long)c * n]
+                         : ((c - kk == i) ? 1.0 : 0.0);
+  if (threadIdx.x < KMAX) used[threadIdx.x] = 0;
   __syncthreads();
   for (int j = 0; j < kk; ++j) {
     if (threadIdx.x < 64) {
       double best = -1.0;
       int key = 0x7fffffff;
       const int i = threadIdx.x;
-      if (i >= j && i < kk) {
+      if (i < kk && !used[i]) {
         best = fabs(a[i][j]);
         key = i;
       }
       wave_argmax(best, key);
-      if (threadIdx.x == 0) shp = key;
+      if (threadIdx.x == 0) {
+        shp = key;
+        pivrow[j] = key;
+        used[key] = 1;
+        const double pv = a[key][j];
+        sip = (pv != 0.0) ? 1.0 / pv : 0.0;
+      }
     }
     __syncthreads();
     const int p = shp;
-    if (p != j)
-      for (int c = threadIdx.x; c < w2; c += NTHR) {
-        const double t = a[j][c];
-        a[j][c] = a[p][c];
-        a[p][c] = t;
-      }
+    for (int c = threadIdx.x; c < w2; c += NTHR) prow[c] = a[p][c] * sip;
+    if (threadIdx.x < kk) f[threadIdx.x] = (threadIdx.x == p) ? 0.0 : a[threadIdx.x][j];
     __syncthreads();
-    const double pv = a[j][j];
-    const double ip = (pv != 0.0) ? 1.0 / pv : 0.0;
-    if (threadIdx.x < kk) f[threadIdx.x] = a[threadIdx.x][j];
-    __syncthreads();
-    for (int c = threadIdx.x; c < w2; c += NTHR) a[j][c] *= ip;
-    __syncthreads();
-    for (int e = threadIdx.x; e < kk * w2; e += NTHR) {
-      const int i = e / w2, c = e - i * w2;
-      if (i != j) a[i][c] -= f[i] * a[j][c];
-    }
+    for (int i = i0; i < kk; i += 4)
+      for (int c = cl; c < w2; c += 64)
+        a[i][c] = (i == p) ? prow[c] : a[i][c] - f[i] * prow[c];
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < kk * kk; e += NTHR) {
-    const int i = e / kk, c = e - i * kk;
-    io.inv[i + c * KMAX] = a[i][kk + c];
-  }
+  for (int t = i0; t < kk; t += 4)
+    for (int c = cl; c < kk; c += 64) io.inv[t + c * KMAX] = a[pivrow[t]][kk + c];
 }
 
 // ---- per block: rows of B = Q Inv, report the MV_TOP largest rows > tau
@@ -174,10 +178,8 @@ __global__ __launch_bounds__(NTHR) void k_mv_check(int which, int n, Solve2D *S)
   __shared__ int rk[4];
   const int kk = s.k;
   const MvIO io = mv_io(which, s);
-  for (int e = threadIdx.x; e < kk * kk; e += NTHR) {
-    const int i = e / kk, c = e - i * kk;
-    inv[i * KMAX + c] = io.inv[i + c * KMAX];
-  }
+  for (int i = threadIdx.x >> 6; i < kk; i += 4)
+    for (int c = threadIdx.x & 63; c < kk; c += 64) inv[i * KMAX + c] = io.inv[i + c * KMAX];
   __syncthreads();
   const int row = blockIdx.x * NTHR + threadIdx.x;
   double mx = -1.0;
@@ -235,6 +237,7 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
   __shared__ double rv[4];
   __shared__ int rk[4];
   const int ntot = nb0 * MV_TOP;
+  int *cr = rows;
   if (threadIdx.x == 0) cnt[0] = 0;
   __syncthreads();
   // rank-select the largest reported violators (ties: lower row first)
@@ -250,7 +253,7 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
       if (w > v || (w == v && r2 < rr)) ++rank;
     }
     if (rank < MV_CAND) {
-      rows[kk + rank] = rr;
+      cr[kk + rank] = rr;
       atomicAdd(&cnt[0], 1);
     }
   }
@@ -262,13 +265,15 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
   }
   const int nr = kk + nc;
   for (int j = threadIdx.x; j < kk; j += NTHR) rows[j] = clamp_row(io.out[j], n);
-  for (int e = threadIdx.x; e < kk * kk; e += NTHR) {
-    const int i = e / kk, c = e - i * kk;
-    inv[i * KMAX + c] = io.inv[i + c * KMAX];
-  }
+  for (int i = threadIdx.x >> 6; i < kk; i += 4)
+    for (int c = threadIdx.x & 63; c < kk; c += 64) inv[i * KMAX + c] = io.inv[i + c * KMAX];
   __syncthreads();
-  for (int e = threadIdx.x; e < nr * kk; e += NTHR) {
-    const int t = e / kk, c = e - t * kk;
+  // B rows: identity for I, Q[row,:] Inv for the candidates.  Element e ->
+  // (row position e >> 6, column e & 63).
+  const int nrk = nr * KMAX;
+  for (int e = threadIdx.x; e < nrk; e += NTHR) {
+    const int t = e >> 6, c = e & (KMAX - 1);
+    if (c >= kk) continue;
     double v;
     if (t < kk) {
       v = (t == c) ? 1.0 : 0.0;
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
       const int rr = clamp_row(rows[t], n);
       for (int j = 0; j < kk; ++j) v += io.Q[rr + (long)j * n] * inv[j * KMAX + c];
     }
-    Bm[t * KMAX + c] = v;
+    Bm[e] = v;
   }
   if (threadIdx.x == 0) cnt[2] = 0;
   __syncthreads();
@@ -285,11 +290,12 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
   for (int it = 0; it < 4 * kk; ++it) {
     double best = -1.0;
     int key = 0x7fffffff;
-    for (int e = threadIdx.x; e < nr * kk; e += NTHR) {
-      const int t = e / kk, c = e - t * kk;
-      const double a = fabs(Bm[t * KMAX + c]);
+    for (int e = threadIdx.x; e < nrk; e += NTHR) {
+      const int t = e >> 6, c = e & (KMAX - 1);
+      if (c >= kk) continue;
+      const double av = fabs(Bm[e]);
       const int kv = rows[t] * KMAX + c;
-      if (a > best || (a == best && kv < key)) best = a, key = kv;
+      if (av > best || (av == best && kv < key)) best = av, key = kv;
     }
     wave_argmax(best, key);
     if (lane == 0) rv[wave] = best, rk[wave] = key;
@@ -309,9 +315,9 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
       prow[c] = (Bm[ts * KMAX + c] - (c == cs ? 1.0 : 0.0)) / piv;
     for (int t = threadIdx.x; t < nr; t += NTHR) pcol[t] = Bm[t * KMAX + cs];
     __syncthreads();
-    for (int e = threadIdx.x; e < nr * kk; e += NTHR) {
-      const int t = e / kk, c = e - t * kk;
-      Bm[t * KMAX + c] -= pcol[t] * prow[c];
+    for (int e = threadIdx.x; e < nrk; e += NTHR) {
+      const int t = e >> 6, c = e & (KMAX - 1);
+      if (c < kk) Bm[e] -= pcol[t] * prow[c];
     }
     if (threadIdx.x == 0) {
       io.out[cs] = gr;

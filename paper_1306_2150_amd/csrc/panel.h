@@ -84,7 +84,7 @@ __device__ void hh_qr_regs(double (&y)[NS][4], int mp, int kk, double *vbuf,
         if (i > j && i < mp) ss += x[q] * x[q];
       }
       ss = wave_sum(ss);
-      const double alpha = __shfl(x[0], j, 64);   // j < 64: row j in slot 0
+      const double alpha = bcast_f64(x[0], j);   // j < 64: row j in slot 0
       double tj = 0.0, beta = alpha, scale = 0.0;
       if (ss != 0.0) {
         beta = -copysign(sqrt(alpha * alpha + ss), alpha);
@@ -193,8 +193,8 @@ __device__ void gepp_select_regs(double (&y)[NS][4], int mp, int kk,
       }
       wave_argmax(best, key);
       const int p = key;
-      const double pv = pick4(__shfl(x[0], p & 63, 64), __shfl(x[1], p & 63, 64),
-                              __shfl(x[2], p & 63, 64), __shfl(x[3], p & 63, 64),
+      const double pv = pick4(bcast_f64(x[0], p & 63), bcast_f64(x[1], p & 63),
+                              bcast_f64(x[2], p & 63), bcast_f64(x[3], p & 63),
                               p >> 6);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -219,8 +219,8 @@ __device__ void gepp_select_regs(double (&y)[NS][4], int mp, int kk,
       if (c > j && c < kk) {
         // shuffle every row slot first, then choose: a select over the
         // register array itself would be turned into a scratch-memory index
-        const double u = pick4(__shfl(y[s2][0], pl, 64), __shfl(y[s2][1], pl, 64),
-                               __shfl(y[s2][2], pl, 64), __shfl(y[s2][3], pl, 64), pq);
+        const double u = pick4(bcast_f64(y[s2][0], pl), bcast_f64(y[s2][1], pl),
+                               bcast_f64(y[s2][2], pl), bcast_f64(y[s2][3], pl), pq);
 #pragma unroll
         for (int q = 0; q < 4; ++q) y[s2][q] -= ll[q] * u;
       }

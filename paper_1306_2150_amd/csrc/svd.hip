@@ -17,57 +17,75 @@ namespace {
 
 constexpr int LD = KMAX + 1;
 
+// Sum over one 16-lane DPP row; every lane of the row gets the total.
+__device__ __forceinline__ double row_sum16(double v) {
+  v += dpp_f64<0x128>(v);   // row_ror:8
+  v += dpp_f64<0x124>(v);   // row_ror:4
+  v += dpp_f64<0x122>(v);   // row_ror:2
+  v += dpp_f64<0x121>(v);   // row_ror:1
+  return v;
+}
+
 __global__ __launch_bounds__(NTHR) void k_core(Solve2D *S) {
   Solve2D &s = S[blockIdx.x];
   if (s.active != ACT_SWEEP) return;
   __shared__ double K[KMAX * LD];   // column c at K[c*LD + i]
   __shared__ double V[KMAX * LD];
+  __shared__ double Rs[KMAX * LD];  // Rfin, then unused
   __shared__ double sg[KMAX];
   __shared__ int perm[KMAX];
   __shared__ int rot;
   const int kk = s.k;
   const int kp = (kk + 1) & ~1;   // even number of players
-  // K[i][c] = sum_j InvC[i][j] * Rfin[c][j]   (Rfin upper triangular)
-  for (int e = threadIdx.x; e < kp * kp; e += NTHR) {
-    const int c = e / kp, i = e - c * kp;
-    double v = 0.0;
-    if (i < kk && c < kk)
-      for (int j = c; j < kk; ++j) v += s.InvC[i + j * KMAX] * s.Rfin[c + j * KMAX];
-    K[c * LD + i] = v;
-    V[c * LD + i] = (i == c) ? 1.0 : 0.0;
-  }
+  // stage InvC (in V) and Rfin (in Rs); element e -> (e >> 6, e & 63)
+  for (int j = threadIdx.x >> 6; j < kk; j += 4)
+    for (int i = threadIdx.x & 63; i < kk; i += 64) {
+      V[j * LD + i] = s.InvC[i + j * KMAX];
+      Rs[j * LD + i] = s.Rfin[i + j * KMAX];
+    }
+  __syncthreads();
+  // K[i][c] = sum_{j >= c} InvC[i][j] * Rfin[c][j]   (Rfin upper triangular)
+  for (int c = threadIdx.x >> 6; c < kp; c += 4)
+    for (int i = threadIdx.x & 63; i < kp; i += 64) {
+      double v = 0.0;
+      if (i < kk && c < kk)
+        for (int j = c; j < kk; ++j) v += V[j * LD + i] * Rs[j * LD + c];
+      K[c * LD + i] = v;
+    }
+  __syncthreads();
+  for (int c = threadIdx.x >> 6; c < kp; c += 4)
+    for (int i = threadIdx.x & 63; i < kp; i += 64) V[c * LD + i] = (i == c) ? 1.0 : 0.0;
   __syncthreads();
   const int npairs = kp / 2;
-  int G = 64;
-  while (G * npairs > NTHR) G >>= 1;          // threads per pair, power of 2
-  const int pr = threadIdx.x / G, gl = threadIdx.x - pr * G;
+  // 16 threads (one DPP row) per column pair, 16 pairs in flight
+  const int pr0 = threadIdx.x >> 4, gl = threadIdx.x & 15;
   const double tol = 1e-15;
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (threadIdx.x == 0) rot = 0;
     __syncthreads();
     for (int st = 0; st < kp - 1; ++st) {
-      if (pr < npairs) {
+      for (int pr = pr0; pr < ((npairs + 15) & ~15); pr += 16) {
+        const bool live = pr < npairs;
         const int pa = pr, pb = kp - 1 - pr;
-        const int a = (pa == 0) ? 0 : 1 + (pa - 1 + st) % (kp - 1);
-        const int b = 1 + (pb - 1 + st) % (kp - 1);
+        const int a = live ? ((pa == 0) ? 0 : 1 + (pa - 1 + st) % (kp - 1)) : 0;
+        const int b = live ? 1 + (pb - 1 + st) % (kp - 1) : 0;
         double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = gl; i < kp; i += G) {
-          const double x = K[a * LD + i], y = K[b * LD + i];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
-        }
-        for (int o = G / 2; o > 0; o >>= 1) {
-          al += __shfl_xor(al, o, 64);
-          be += __shfl_xor(be, o, 64);
-          ga += __shfl_xor(ga, o, 64);
-        }
-        if (al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+        if (live)
+          for (int i = gl; i < kp; i += 16) {
+            const double x = K[a * LD + i], y = K[b * LD + i];
+            al += x * x;
+            be += y * y;
+            ga += x * y;
+          }
+        al = row_sum16(al);
+        be = row_sum16(be);
+        ga = row_sum16(ga);
+        if (live && al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be)) {
           const double zeta = (be - al) / (2.0 * ga);
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) /
                            (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-          for (int i = gl; i < kp; i += G) {
+          for (int i = gl; i < kp; i += 16) {
             const double x = K[a * LD + i], y = K[b * LD + i];
             K[a * LD + i] = cs * x - sn * y;
             K[b * LD + i] = sn * x + cs * y;
@@ -98,13 +116,13 @@ __global__ __launch_bounds__(NTHR) void k_core(Solve2D *S) {
     perm[rank] = c;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < kk * kk; e += NTHR) {
-    const int t = e / kk, i = e - t * kk;
-    const int c = perm[t];
-    const double sv = sg[c];
-    s.W[i + t * KMAX] = (sv > 0.0) ? K[c * LD + i] / sv : 0.0;
-    s.Z[i + t * KMAX] = V[c * LD + i];
-  }
+  for (int t = threadIdx.x >> 6; t < kk; t += 4)
+    for (int i = threadIdx.x & 63; i < kk; i += 64) {
+      const int c = perm[t];
+      const double sv = sg[c];
+      s.W[i + t * KMAX] = (sv > 0.0) ? K[c * LD + i] / sv : 0.0;
+      s.Z[i + t * KMAX] = V[c * LD + i];
+    }
   if (threadIdx.x < kk) s.sig[threadIdx.x] = sg[perm[threadIdx.x]];
 }
 

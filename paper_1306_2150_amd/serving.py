@@ -1,0 +1,91 @@
+"""Drive the library's continuous-batching request loop with a timed stream.
+
+Requests arrive on a wall clock (Poisson arrivals from
+``inputs.serving_stream``); each tick submits every request whose arrival
+time has passed, runs one scheduling tick of the library
+(``lrp_serve_step``: admit into free slots, one cross sweep of every running
+solve, retire finished ones) and polls the outstanding tickets.  Latency is
+completion time minus arrival time.  The right-hand sides are uploaded to the
+device before the clock starts (factors resident on the device).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import binding, inputs
+
+
+def prepare(requests, device="cuda"):
+    """Upload every request's RHS factors; returns a list of (U, V) tensors."""
+    out = []
+    for q in requests:
+        U, V = q.rhs()
+        out.append((binding.colmajor(U, device), binding.colmajor(V, device)))
+    return out
+
+
+def run_stream(ctx: binding.Context, requests, factors, prec="auto",
+               warmup: int = 0, time_scale: float = 1.0):
+    """Serve ``requests`` (2D) against the wall clock.
+
+    Returns dict with latencies (s) of the measured requests (after
+    ``warmup``), solves/s over the measured window and per-request records.
+    """
+    import torch
+
+    n_req = len(requests)
+    order = sorted(range(n_req), key=lambda i: requests[i].arrival_s)
+    t0 = time.perf_counter()
+    nxt = 0
+    pending = {}
+    done = {}
+    ticks = 0
+    while len(done) < n_req:
+        now = time.perf_counter() - t0
+        while nxt < n_req and requests[order[nxt]].arrival_s * time_scale <= now:
+            i = order[nxt]
+            q = requests[i]
+            U, V = factors[i]
+            ticket, outs = ctx.submit(U, V, q.eps, prec=prec)
+            pending[ticket] = (i, outs)
+            nxt += 1
+        if not pending:
+            # idle until the next arrival
+            wait = requests[order[nxt]].arrival_s * time_scale - now
+            if wait > 0:
+                time.sleep(min(wait, 0.002))
+            continue
+        ctx.serve_step()
+        ticks += 1
+        tdone = time.perf_counter() - t0
+        for ticket in list(pending):
+            r = ctx.poll(ticket)
+            if r is None:
+                continue
+            i, outs = pending.pop(ticket)
+            status, ranks, info = r
+            done[i] = dict(rid=i, arrival=requests[i].arrival_s * time_scale,
+                           finish=tdone, latency=tdone - requests[i].arrival_s * time_scale,
+                           status=status, rank=ranks[0], sweeps=info["sweeps"],
+                           n=requests[i].n, r=requests[i].r, eps=requests[i].eps,
+                           outs=outs)
+    torch.cuda.synchronize()
+    meas = [done[i] for i in range(warmup, n_req)]
+    lat = np.array([d["latency"] for d in meas])
+    t_first = min(d["arrival"] for d in meas)
+    t_last = max(d["finish"] for d in meas)
+    return dict(
+        p50_ms=float(np.percentile(lat, 50) * 1e3),
+        p99_ms=float(np.percentile(lat, 99) * 1e3),
+        mean_ms=float(lat.mean() * 1e3),
+        solves_per_s=len(meas) / (t_last - t_first),
+        measured=len(meas), warmup=warmup, ticks=ticks,
+        statuses=sorted(set(d["status"] for d in meas)),
+        records=[done[i] for i in range(n_req)],
+    )
+
+
+def default_stream(count: int, seed: int = 5000, dims=(2,)):
+    return inputs.serving_stream(count, 200.0, seed, dims=dims)
