@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--distinct", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-warmup", type=int, default=50)

@@ -404,6 +404,7 @@ hipError_t launch_eval(int which, int n, const double *lam, Solve2D *s,
   dim3 g(ceil_div(n, NTHR), nsolves);
   if (kmax <= 16) hipLaunchKernelGGL((k_eval<16>), g, dim3(NTHR), 0, st, which, n, lam, s);
   else if (kmax <= 32) hipLaunchKernelGGL((k_eval<32>), g, dim3(NTHR), 0, st, which, n, lam, s);
+  else if (kmax <= 48) hipLaunchKernelGGL((k_eval<48>), g, dim3(NTHR), 0, st, which, n, lam, s);
   else hipLaunchKernelGGL((k_eval<64>), g, dim3(NTHR), 0, st, which, n, lam, s);
   return hipGetLastError();
 }
@@ -413,6 +414,7 @@ hipError_t launch_factors(int n, Solve2D *s, int nsolves, int kmax,
   dim3 g(ceil_div(n, NTHR), nsolves, 2);
   if (kmax <= 16) hipLaunchKernelGGL((k_factors<16>), g, dim3(NTHR), 0, st, n, s);
   else if (kmax <= 32) hipLaunchKernelGGL((k_factors<32>), g, dim3(NTHR), 0, st, n, s);
+  else if (kmax <= 48) hipLaunchKernelGGL((k_factors<48>), g, dim3(NTHR), 0, st, n, s);
   else hipLaunchKernelGGL((k_factors<64>), g, dim3(NTHR), 0, st, n, s);
   return hipGetLastError();
 }
@@ -424,6 +426,7 @@ hipError_t launch_change(int n, int nb0, Solve2D *s, int nsolves, int kmax,
   dim3 g(ceil_div(n, NTHR), nsolves);
   if (kmax <= 16) hipLaunchKernelGGL((k_change_norms<16>), g, dim3(NTHR), 0, st, n, s);
   else if (kmax <= 32) hipLaunchKernelGGL((k_change_norms<32>), g, dim3(NTHR), 0, st, n, s);
+  else if (kmax <= 48) hipLaunchKernelGGL((k_change_norms<48>), g, dim3(NTHR), 0, st, n, s);
   else hipLaunchKernelGGL((k_change_norms<64>), g, dim3(NTHR), 0, st, n, s);
   return hipGetLastError();
 }
@@ -435,6 +438,7 @@ hipError_t launch_decide(int n, const double *lam, Solve2D *s, int nsolves,
   dim3 g(ceil_div(n, NTHR), nsolves);
   if (kmax <= 16) hipLaunchKernelGGL((k_growth_score<16>), g, dim3(NTHR), 0, st, n, lam, s);
   else if (kmax <= 32) hipLaunchKernelGGL((k_growth_score<32>), g, dim3(NTHR), 0, st, n, lam, s);
+  else if (kmax <= 48) hipLaunchKernelGGL((k_growth_score<48>), g, dim3(NTHR), 0, st, n, lam, s);
   else hipLaunchKernelGGL((k_growth_score<64>), g, dim3(NTHR), 0, st, n, lam, s);
   hipLaunchKernelGGL(k_finalize, dim3(nsolves), dim3(NTHR), 0, st, n, s);
   (void)nb0;

@@ -176,9 +176,19 @@ static Layout slot_layout(int n, const Tree &t) {
 Group2D::Group2D(lrp_ctx *ctx, int n, int cap) : ctx_(ctx), n_(n), cap_(cap) {}
 
 Group2D::~Group2D() {
+  if (stream_) {
+    (void)hipStreamSynchronize(stream_);
+    (void)hipStreamDestroy(stream_);
+  }
   dev_free(ctx_, ws_, bytes_);
   if (h_s_) (void)hipHostFree(h_s_);
   if (h_cols_) (void)hipHostFree(h_cols_);
+}
+
+hipStream_t Group2D::stream() {
+  if (!stream_ && hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking) != hipSuccess)
+    stream_ = nullptr;
+  return stream_;
 }
 
 lrp_status Group2D::init() {
@@ -350,8 +360,10 @@ lrp_status Group2D::forward(const std::vector<int> &slots, hipStream_t st) {
 lrp_status Group2D::step(hipStream_t st) {
   int kin = 0, kmax = 0, rmax = 0;
   bool any_init = false, any_sweep = false;
+  int hi = 0;   // launches cover slots [0, hi): the live ones
   for (int i = 0; i < cap_; ++i) {
     const Solve2D &s = h_s_[i];
+    if (s.active != ACT_DONE) hi = i + 1;
     if (s.active == ACT_INIT) {
       any_init = true;
       kin = std::max(kin, s.k);
@@ -367,9 +379,9 @@ lrp_status Group2D::step(hipStream_t st) {
     // the tree depends on n only, so a slot's arithmetic does not depend on
     // which other slots share the launch
     const Tree t = make_tree(n_, KMAX);
-    HIPCHK(launch_tsqr(TS_VH_TO_Q0, n_, t, d_s_, cap_, kin, st));
-    HIPCHK(launch_maxvol(MV_Q0_TO_J, n_, t, d_s_, cap_, kin, st));
-    HIPCHK(launch_init_J(n_, d_s_, cap_, st));
+    HIPCHK(launch_tsqr(TS_VH_TO_Q0, n_, t, d_s_, hi, kin, st));
+    HIPCHK(launch_maxvol(MV_Q0_TO_J, n_, t, d_s_, hi, kin, st));
+    HIPCHK(launch_init_J(n_, d_s_, hi, st));
   }
   if (!any_init && !any_sweep) return LRP_OK;
   // k of a slot only grows at the end of a sweep, so kmax bounds this sweep
@@ -377,22 +389,22 @@ lrp_status Group2D::step(hipStream_t st) {
   const int kev = std::max(km, rmax);
   const Tree t = make_tree(n_, KMAX);
   const int nb0 = ceil_div(n_, NTHR);
-  HIPCHK(launch_eval(EV_COLS, n_, tabs_->lam, d_s_, cap_, kev, st));
-  HIPCHK(launch_tsqr(TS_C_TO_Q0, n_, t, d_s_, cap_, km, st));
-  HIPCHK(launch_maxvol(MV_Q0_TO_I, n_, t, d_s_, cap_, km, st));
-  HIPCHK(launch_eval(EV_ROWS, n_, tabs_->lam, d_s_, cap_, kev, st));
-  HIPCHK(launch_tsqr(TS_C_TO_Q1, n_, t, d_s_, cap_, km, st));
-  HIPCHK(launch_maxvol(MV_Q1_TO_JN, n_, t, d_s_, cap_, km, st));
-  HIPCHK(launch_core(n_, d_s_, cap_, st));
-  HIPCHK(launch_factors(n_, d_s_, cap_, km, st));
-  HIPCHK(launch_change(n_, nb0, d_s_, cap_, km, st));
-  HIPCHK(launch_decide(n_, tabs_->lam, d_s_, cap_, kev, nb0, st));
+  HIPCHK(launch_eval(EV_COLS, n_, tabs_->lam, d_s_, hi, kev, st));
+  HIPCHK(launch_tsqr(TS_C_TO_Q0, n_, t, d_s_, hi, km, st));
+  HIPCHK(launch_maxvol(MV_Q0_TO_I, n_, t, d_s_, hi, km, st));
+  HIPCHK(launch_eval(EV_ROWS, n_, tabs_->lam, d_s_, hi, kev, st));
+  HIPCHK(launch_tsqr(TS_C_TO_Q1, n_, t, d_s_, hi, km, st));
+  HIPCHK(launch_maxvol(MV_Q1_TO_JN, n_, t, d_s_, hi, km, st));
+  HIPCHK(launch_core(n_, d_s_, hi, st));
+  HIPCHK(launch_factors(n_, d_s_, hi, km, st));
+  HIPCHK(launch_change(n_, nb0, d_s_, hi, km, st));
+  HIPCHK(launch_decide(n_, tabs_->lam, d_s_, hi, kev, nb0, st));
   return LRP_OK;
 }
 
-lrp_status Group2D::fetch(hipStream_t st) {
+lrp_status Group2D::fetch(hipStream_t st, bool sync) {
   HIPCHK(hipMemcpyAsync(h_s_, d_s_, sizeof(Solve2D) * cap_, hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
+  if (sync) HIPCHK(hipStreamSynchronize(st));
   return LRP_OK;
 }
 

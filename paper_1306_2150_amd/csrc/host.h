@@ -47,13 +47,15 @@ class Group2D {
   lrp_status forward(const std::vector<int> &slots, hipStream_t st);
   // Initial maxvol for INIT slots, then one sweep for SWEEP slots.
   lrp_status step(hipStream_t st);
-  // Copy the control state of all slots back (async); then sync the stream.
-  lrp_status fetch(hipStream_t st);
+  // Copy the control state of all slots back; with sync, wait for it.
+  lrp_status fetch(hipStream_t st, bool sync = true);
   // Inverse transform of the listed finished slots.
   lrp_status inverse(const std::vector<int> &slots, hipStream_t st);
 
   Solve2D &host(int i) { return h_s_[i]; }
   Solve2D *dev_solves() { return d_s_; }
+  // own stream (default priority) for the serving loop
+  hipStream_t stream();
   const Plan &plan(int i) const { return plans_[i]; }
   std::vector<int> free_slots;
 
@@ -72,6 +74,7 @@ class Group2D {
   std::vector<Plan> plans_;
   std::vector<int> kin_;
   const GridTables *tabs_ = nullptr;
+  hipStream_t stream_ = nullptr;
 };
 
 }  // namespace lrp

@@ -95,9 +95,9 @@ struct DstCol {
 
 // ---------------------------------------------------------------- helpers
 // Wave-wide reductions on DPP lane moves (VALU, no LDS round trip): quad
-// permutes and row shifts reduce each 16-lane row into its lane 15, and the
-// four row results are combined from v_readlane values, so every lane gets
-// the same total.
+// permutes and row shifts reduce each 16-lane row into its lane 15, row
+// broadcasts fold the four rows into lane 63, and v_readlane hands the total
+// to every lane.
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
   const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, true);
@@ -119,13 +119,24 @@ constexpr int DPP_QUAD_2301 = 0x4e;   // quad_perm [2,3,0,1]
 constexpr int DPP_ROW_SHR4 = 0x114;
 constexpr int DPP_ROW_SHR8 = 0x118;
 
+constexpr int DPP_ROW_BCAST15 = 0x142;   // lane 15 of a row -> next row
+constexpr int DPP_ROW_BCAST31 = 0x143;   // lane 31 -> rows 2 and 3
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_rows_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   v += dpp_f64<DPP_QUAD_1032>(v);
   v += dpp_f64<DPP_QUAD_2301>(v);
   v += dpp_f64<DPP_ROW_SHR4>(v);      // out-of-row lanes read 0
-  v += dpp_f64<DPP_ROW_SHR8>(v);
-  return (readlane_f64(v, 15) + readlane_f64(v, 31)) +
-         (readlane_f64(v, 47) + readlane_f64(v, 63));
+  v += dpp_f64<DPP_ROW_SHR8>(v);      // lane 15 of each row: row sum
+  v += dpp_rows_f64<DPP_ROW_BCAST15, 0xa>(v);   // lanes 31, 63: two rows
+  v += dpp_rows_f64<DPP_ROW_BCAST31, 0xc>(v);   // lane 63: all four rows
+  return readlane_f64(v, 63);
 }
 
 // Larger value wins; ties go to the smaller key.

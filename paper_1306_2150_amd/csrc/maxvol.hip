@@ -356,6 +356,7 @@ hipError_t launch_maxvol(int which, int n, const Tree &tr, Solve2D *s,
   hipError_t e;
   if (kmax <= 16) e = run_tournament<4>(which, n, tr, s, nsolves, st);
   else if (kmax <= 32) e = run_tournament<8>(which, n, tr, s, nsolves, st);
+  else if (kmax <= 48) e = run_tournament<12>(which, n, tr, s, nsolves, st);
   else e = run_tournament<16>(which, n, tr, s, nsolves, st);
   if (e != hipSuccess) return e;
   const size_t swap_lds = (size_t)(KMAX + MV_CAND) * KMAX * 8 + (size_t)KMAX * KMAX * 8 +
@@ -372,6 +373,7 @@ hipError_t launch_maxvol(int which, int n, const Tree &tr, Solve2D *s,
     hipLaunchKernelGGL(k_mv_inv, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
     if (kmax <= 16) run_check<16>(which, n, tr, s, nsolves, st);
     else if (kmax <= 32) run_check<32>(which, n, tr, s, nsolves, st);
+    else if (kmax <= 48) run_check<48>(which, n, tr, s, nsolves, st);
     else run_check<64>(which, n, tr, s, nsolves, st);
     hipLaunchKernelGGL(k_mv_swap, dim3(nsolves), dim3(NTHR), swap_lds, st, which,
                        n, tr.nb[0], s);

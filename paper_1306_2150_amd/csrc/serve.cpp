@@ -73,11 +73,6 @@ lrp_status lrp_serve_step(lrp_ctx *ctx, int32_t *pending) {
   if (!ctx) return LRP_EINVAL;
   if (hipSetDevice(ctx->device) != hipSuccess) return LRP_EDEVICE;
   std::lock_guard<std::mutex> lock(ctx->mu);
-  if (!ctx->serve_stream) {
-    if (hipStreamCreateWithFlags(&ctx->serve_stream, hipStreamNonBlocking) != hipSuccess)
-      return LRP_EDEVICE;
-  }
-  hipStream_t st = ctx->serve_stream;
   lrp_status e;
   // 1. admission (FIFO per grid size: a request waits only for its own group)
   std::map<Group2D *, std::vector<int>> fresh;
@@ -96,7 +91,8 @@ lrp_status lrp_serve_step(lrp_ctx *ctx, int32_t *pending) {
     const Plan plan = make_plan(&o, q.eps, (int)q.n);
     g->setup_slot(slot, q.U[0], q.U[1], q.ld, q.rank[0], q.eps, q.X[0], q.X[1],
                   q.ldx, q.rmax[0], plan);
-    if ((e = g->upload_slot(slot, st)) != LRP_OK) return e;
+    if (!g->stream()) return LRP_EDEVICE;
+    if ((e = g->upload_slot(slot, g->stream())) != LRP_OK) return e;
     fresh[g].push_back(slot);
     ServeReq r = *it;
     r.state = 1;
@@ -105,18 +101,22 @@ lrp_status lrp_serve_step(lrp_ctx *ctx, int32_t *pending) {
     ctx->running[r.ticket] = r;
     it = ctx->queue.erase(it);
   }
-  for (auto &kv : fresh)
-    if ((e = kv.first->forward(kv.second, st)) != LRP_OK) return e;
-  // 2. one step of every group with live slots
+  // 2. every group with live slots: forward transforms of its new slots, the
+  // initial column choice and one sweep, on the group's own stream so that
+  // the groups' latency-bound launches overlap on the device
   std::vector<Group2D *> live;
   for (auto &kv : ctx->serve_groups) {
     Group2D *g = kv.second.get();
     if ((int)g->free_slots.size() < g->cap()) live.push_back(g);
   }
+  for (Group2D *g : live) {
+    auto it = fresh.find(g);
+    if (it != fresh.end() && (e = g->forward(it->second, g->stream())) != LRP_OK) return e;
+    if ((e = g->step(g->stream())) != LRP_OK) return e;
+    if ((e = g->fetch(g->stream(), false)) != LRP_OK) return e;
+  }
   for (Group2D *g : live)
-    if ((e = g->step(st)) != LRP_OK) return e;
-  for (Group2D *g : live)
-    if ((e = g->fetch(st)) != LRP_OK) return e;
+    if (hipStreamSynchronize(g->stream()) != hipSuccess) return LRP_EDEVICE;
   // 3. retirement
   std::map<Group2D *, std::vector<int>> done;
   std::vector<uint64_t> finished;
@@ -134,8 +134,9 @@ lrp_status lrp_serve_step(lrp_ctx *ctx, int32_t *pending) {
     finished.push_back(kv.first);
   }
   for (auto &kv : done)
-    if ((e = kv.first->inverse(kv.second, st)) != LRP_OK) return e;
-  if (!finished.empty() && hipStreamSynchronize(st) != hipSuccess) return LRP_EDEVICE;
+    if ((e = kv.first->inverse(kv.second, kv.first->stream())) != LRP_OK) return e;
+  for (auto &kv : done)
+    if (hipStreamSynchronize(kv.first->stream()) != hipSuccess) return LRP_EDEVICE;
   for (uint64_t t : finished) {
     ServeReq r = ctx->running[t];
     ctx->running.erase(t);

@@ -241,6 +241,7 @@ hipError_t launch_tsqr(int which, int n, const Tree &tr, Solve2D *s,
                        int nsolves, int kmax, hipStream_t st) {
   if (kmax <= 16) return run_tsqr<4>(which, n, tr, s, nsolves, st);
   if (kmax <= 32) return run_tsqr<8>(which, n, tr, s, nsolves, st);
+  if (kmax <= 48) return run_tsqr<12>(which, n, tr, s, nsolves, st);
   return run_tsqr<16>(which, n, tr, s, nsolves, st);
 }
 
