@@ -11,8 +11,8 @@ float32, inverse float64 at this eps); the float64 plan is timed beside it.
 Every distinct RHS of the batch is checked against the CPU oracle.
 
 Also reported: served p50/p99 latency of a Poisson-arrival request stream
-(200 req/s, grid sizes 512..8192, ranks 4..64, eps 1e-6/1e-8) through the
-library's continuous-batching loop; the transform kernel's roofline from
+(200 req/s; 2D grids 512..8192 and 3D grids 128..512, ranks 4..64, eps
+1e-6/1e-8) through the library's continuous-batching loop; the transform kernel's roofline from
 HIP-event timing of its launches during the timed steps; the CPU oracle's
 throughput on a bounded sample.
 """
@@ -167,8 +167,8 @@ def main():
             print(f"[bench] served {plan}: p50 {s['p50_ms']:.2f} ms p99 "
                   f"{s['p99_ms']:.2f} ms {s['solves_per_s']:.1f} solves/s",
                   file=sys.stderr, flush=True)
-        line["serving"] = {"stream": "Poisson arrivals 200 req/s, 2D n in 512..8192, "
-                                     "r 4..64, eps 1e-6/1e-8",
+        line["serving"] = {"stream": "Poisson arrivals 200 req/s, 2D n in 512..8192 and "
+                                     "3D n in 128..512, r 4..64, eps 1e-6/1e-8",
                            "p50_ms": sv["auto"]["p50_ms"], "p99_ms": sv["auto"]["p99_ms"],
                            "solves_per_s": sv["auto"]["solves_per_s"],
                            "fp64": {k: sv["fp64"][k] for k in ("p50_ms", "p99_ms", "solves_per_s")},

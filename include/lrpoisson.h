@@ -31,7 +31,8 @@
  *    X ~= Ux Vx^T.  3D output: U1x, U2x, U3x have orthonormal columns and
  *    the core Gx (r1 x r2 x r3, i1 fastest) carries the scale.
  *  - Errors: LRP_EINVAL is returned before any device work for invalid
- *    arguments (n < 1 or n > LRP_MAX_N, rank < 0 or > LRP_MAX_RANK,
+ *    arguments (n < 1 or n > LRP_MAX_N, LRP_MAX_N3 in 3D, rank < 0 or
+ *    > LRP_MAX_RANK,
  *    eps outside (0, 1), a NULL pointer where one is needed, ld < n).
  *    A rank-0 or all-zero right-hand side returns LRP_OK with rank 0.
  *    LRP_ENONFINITE: the factors hold Inf/NaN (detected on the device).
@@ -53,7 +54,8 @@ extern "C" {
 #endif
 
 #define LRP_MAX_N 32767   /* grid points per axis (sine table lives in LDS) */
-#define LRP_MAX_RANK 64   /* input rank and cross-rank cap                  */
+#define LRP_MAX_N3 1024   /* grid points per axis of a 3D solve            */
+#define LRP_MAX_RANK 64   /* input rank and cross-rank cap (per mode in 3D) */
 
 typedef enum {
   LRP_OK = 0,
@@ -77,12 +79,14 @@ typedef enum {
  *          products (hi*hi + hi*lo + lo*hi), float32 accumulation inside
  *          K blocks, float64 across blocks, both ways.
  *  AUTO    per-request plan from eps: forward transform BF16X3 when
- *          eps >= 1e-6, FP32 when eps >= 1e-8, else FP64; inverse transform
- *          FP32 when eps >= 1e-7, else FP64.  The inverse transform passes its
- *          relative rounding error straight to the result (measured floors:
- *          FP32 ~2e-7, BF16X3 ~5e-6 on the 4096- and 8192-point bump
- *          workloads); the forward one is damped by the division by the
- *          eigenvalue sums. */
+ *          eps >= 1e-6, FP32 when eps >= 1e-7, else FP64; inverse transform
+ *          FP32 when eps >= 1e-7, else FP64.  Every reduced-precision
+ *          transform adds a relative error near its floor (measured: FP32
+ *          ~2e-7, BF16X3 ~5e-6 on the bump workloads); the inverse passes it
+ *          straight to the result, the forward one is damped by the division
+ *          by the eigenvalue sums, but not enough for 10 eps at eps = 1e-8
+ *          (measured up to 9.5e-8 in 2D and 2.6e-7 in 3D), so below 1e-7
+ *          both transforms are float64. */
 typedef enum {
   LRP_PREC_FP64 = 0,
   LRP_PREC_AUTO = 1,
@@ -113,7 +117,7 @@ typedef struct {
 typedef struct lrp_ctx lrp_ctx;
 
 /* Create a solver context on HIP device ``device``.  ``workspace_bytes`` is
- * the device-memory budget of the context (0 = 2 GiB); it bounds the
+ * the device-memory budget of the context (0 = 32 GiB); it bounds the
  * workspace of concurrent solves and the served requests admitted at once.
  * Device memory is allocated lazily inside that budget. */
 lrp_status lrp_create(lrp_ctx **ctx, int device, size_t workspace_bytes);
@@ -159,10 +163,20 @@ lrp_status lrpoisson_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t count,
                                    lrp_problem2d *probs, const lrp_opts *opts,
                                    void *stream);
 
-/* One 3D solve in Tucker format.  U1, U2, U3: n x rank[d] (ld >= n);
- * G: rank[0] x rank[1] x rank[2], i1 fastest.  Outputs U1x, U2x, U3x:
- * n x rmax[d] (ldx >= n); Gx: capacity rmax[0]*rmax[1]*rmax[2], written as
- * rank_out[0] x rank_out[1] x rank_out[2], i1 fastest. */
+/* One 3D solve in Tucker format (Section 3, eq. "tucker"; the 3D case of
+ * Section 4.1): F = G x1 U1 x2 U2 x3 U3 on the 7-point Dirichlet Laplacian,
+ * denominators lambda_i + lambda_j + lambda_k.  Each mode unfolding of the
+ * divided spectrum (n x n^2) is approximated by the cross of the 2D solver
+ * to eps/sqrt(3); the cross bases and their maxvol rows give an
+ * interpolating Tucker approximation whose core is rounded by truncated
+ * HOSVD at eps/sqrt(3) per mode.  U1, U2, U3: n x rank[d] (ld >= n),
+ * n <= LRP_MAX_N3; G: rank[0] x rank[1] x rank[2], i1 fastest.  Outputs
+ * U1x, U2x, U3x: n x rmax[d] (ldx >= n); Gx: capacity
+ * rmax[0]*rmax[1]*rmax[2], written as rank_out[0] x rank_out[1] x
+ * rank_out[2], i1 fastest.  info: sweeps and k are the largest over the
+ * three mode crosses, rank the largest output rank, change the largest
+ * last change.  Workspace: about 2.9 GB at n = 512 (three n x n^2 cross
+ * slots), taken from the context budget. */
 lrp_status lrpoisson_solve3d(lrp_ctx *ctx, int64_t n, const int32_t rank[3],
                              const double *U1, const double *U2,
                              const double *U3, int64_t ld, const double *G,

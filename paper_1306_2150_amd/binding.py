@@ -30,6 +30,7 @@ PREC_NAME = {v: k for k, v in PREC.items()}
 
 MAX_RANK = 64
 MAX_N = 32767
+MAX_N3 = 1024
 
 # every symbol the header declares
 EXPORTS = ["lrp_create", "lrp_destroy", "lrp_strerror", "lrpoisson_solve2d",
@@ -159,6 +160,15 @@ def colmajor(a, device="cuda"):
     return out
 
 
+def fortran_core(G, device="cuda"):
+    """Copy an (r0, r1, r2) core to a GPU tensor stored in Fortran order."""
+    import numpy as np
+    import torch
+    g = np.asarray(G, dtype=np.float64)
+    flat = torch.as_tensor(np.ascontiguousarray(g.reshape(-1, order="F")))
+    return flat.to(device)
+
+
 def empty_colmajor(n, r, device="cuda"):
     import torch
     return torch.empty((max(r, 1), n), dtype=torch.float64, device=device).T[:, :r]
@@ -247,6 +257,48 @@ class Context:
             res.append((Ux[:, :R], Vx[:, :R], d))
         return res
 
+    # ---- 3D
+    def solve3d(self, U1, U2, U3, G, eps, rmax=None, prec="fp64", stream=None,
+                check=True, **kw):
+        """Solve the 7-point problem with the Tucker RHS [[G; U1, U2, U3]].
+
+        U_d: column-major (n, r_d) float64 GPU tensors; G: (r0, r1, r2)
+        float64 GPU tensor, contiguous in Fortran order (i0 fastest), e.g.
+        ``fortran_core(G)``.  Returns (Xs, Gx, info) with Xs the three output
+        factors (orthonormal columns) and Gx the output core as an
+        (R0, R1, R2) tensor view in Fortran order.
+        """
+        import torch
+        n = U1.shape[0]
+        ranks = (ctypes.c_int32 * 3)(U1.shape[1], U2.shape[1], U3.shape[1])
+        rm = [MAX_RANK] * 3 if rmax is None else list(rmax)
+        rmx = (ctypes.c_int32 * 3)(*rm)
+        Xs = [empty_colmajor(n, rm[d], U1.device) for d in range(3)]
+        Gbuf = torch.empty(max(1, rm[0] * rm[1] * rm[2]), dtype=torch.float64,
+                           device=U1.device)
+        rank = (ctypes.c_int32 * 3)(0, 0, 0)
+        info = LrpInfo()
+        opts = _opts(prec, **kw)
+        lds = [_ld(u) for u in (U1, U2, U3) if u.shape[1] > 0]
+        if lds and any(x != lds[0] for x in lds):
+            raise ValueError("U1, U2, U3 must share one leading dimension")
+        ld = lds[0] if lds else n
+        st = self.lib.lrpoisson_solve3d(
+            self.h, n, ranks, _ptr(U1), _ptr(U2), _ptr(U3), ld, _ptr(G), eps,
+            ctypes.byref(opts), _ptr(Xs[0]), _ptr(Xs[1]), _ptr(Xs[2]), n,
+            _ptr(Gbuf), rmx, rank, ctypes.byref(info), _stream(stream))
+        if check and st != LRP_OK:
+            raise LrpError(st, "lrpoisson_solve3d")
+        R = [rank[d] for d in range(3)]
+        d = info.as_dict()
+        d["status_code"] = st
+        d["ranks"] = tuple(R)
+        if any(R[i] > rm[i] for i in range(3)):
+            # LRP_ERANKCAP: rank_out holds the ranks needed, nothing written
+            return [Xs[i][:, :0] for i in range(3)], Gbuf[:0].view(0, 0, 0), d
+        Gx = Gbuf[:R[0] * R[1] * R[2]].view(R[2], R[1], R[0]).permute(2, 1, 0)
+        return [Xs[i][:, :R[i]] for i in range(3)], Gx, d
+
     # ---- sine transform
     def sine_transform(self, X, prec="fp64", out=None, stream=None):
         """S X for a column-major (n, c) float64 GPU tensor."""
@@ -299,6 +351,40 @@ class Context:
         if st != LRP_OK:
             raise LrpError(st, "lrp_submit")
         return t.value, (Ux, Vx)
+
+    def submit3d(self, U1, U2, U3, G, eps, prec="auto", rmax=None, out=None):
+        """Queue a 3D request (G: Fortran-ordered flat GPU tensor, see
+        ``fortran_core``); returns (ticket, (X1, X2, X3, Gbuf)).  The output
+        core is Gbuf[:R0*R1*R2] in Fortran order."""
+        import torch
+        n = U1.shape[0]
+        rm = [MAX_RANK] * 3 if rmax is None else list(rmax)
+        if out is None:
+            out = tuple(empty_colmajor(n, rm[d], U1.device) for d in range(3)) + (
+                torch.empty(max(1, rm[0] * rm[1] * rm[2]), dtype=torch.float64,
+                            device=U1.device),)
+        q = LrpRequest()
+        q.dim = 3
+        q.prec = PREC[prec]
+        q.n = n
+        lds = []
+        for d, u in enumerate((U1, U2, U3)):
+            q.rank[d] = u.shape[1]
+            q.rmax[d] = rm[d]
+            q.U[d] = _ptr(u)
+            q.X[d] = _ptr(out[d])
+            if u.shape[1]:
+                lds.append(_ld(u))
+        q.G = _ptr(G)
+        q.Gx = _ptr(out[3])
+        q.ld = lds[0] if lds else n
+        q.ldx = n
+        q.eps = eps
+        t = ctypes.c_uint64(0)
+        st = self.lib.lrp_submit(self.h, ctypes.byref(q), ctypes.byref(t))
+        if st != LRP_OK:
+            raise LrpError(st, "lrp_submit")
+        return t.value, out
 
     def serve_step(self):
         pend = ctypes.c_int32(0)

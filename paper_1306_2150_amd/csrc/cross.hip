@@ -1,7 +1,10 @@
 // Cross approximation of the divided spectrum (paper Section 4.2).
 //
 // Entries: Xh_ij = (Uh_i . Vh_j) / (lambda_i + lambda_j)   (eq. "div") -- a
-// rank-r numerator over a rank-2 denominator, O(r) per entry.  A sweep with
+// rank-r numerator over a rank-2 denominator, O(r) per entry.  The kernels
+// take the general rectangular form Xh_ij = (Uh_i . Vh_j) / (lam_r[i] +
+// lam_c[j]), i < n, j < m, which the 3D path uses for the unfoldings of its
+// divided spectrum.  A sweep with
 // column set J evaluates the columns Xh[:, J] (k_eval, EV_COLS), orthonormalises
 // them, picks rows I by maxvol, evaluates the rows Xh[I, :] (EV_ROWS),
 // orthonormalises those, picks the next columns Jn by maxvol, and rounds the
@@ -21,35 +24,33 @@ namespace lrp {
 namespace {
 
 template <int KM>
-__global__ __launch_bounds__(NTHR) void k_eval(int which, int n,
-                                              const double *__restrict__ lam,
-                                              Solve2D *S) {
+__global__ __launch_bounds__(NTHR) void k_eval(int which, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (s.active != ACT_SWEEP) return;
   __shared__ double qs[KMAX * KMAX];   // [alpha][l]
   __shared__ double ls[KMAX];
-  const double *P, *Qm;
-  const int *sel;
-  if (which == EV_COLS) {
-    P = s.Uh, Qm = s.Vh, sel = s.J;
-  } else {
-    P = s.Vh, Qm = s.Uh, sel = s.I;
-  }
+  // columns: rows i < n of Uh against Vh[J]; rows: rows j < m of Vh against Uh[I]
+  const bool cols = which == EV_COLS;
+  const double *P = cols ? s.Uh : s.Vh, *Qm = cols ? s.Vh : s.Uh;
+  const long ldp = cols ? s.ldu : s.ldv, ldq = cols ? s.ldv : s.ldu;
+  const double *lp = cols ? s.lam_r : s.lam_c, *lq = cols ? s.lam_c : s.lam_r;
+  const int *sel = cols ? s.J : s.I;
+  const int rows = cols ? s.n : s.m, other = cols ? s.m : s.n;
   const int kk = s.k, r = s.r;
   for (int a = threadIdx.x >> 6; a < r; a += 4)
     for (int l = threadIdx.x & 63; l < kk; l += 64)
-      qs[a * KMAX + l] = Qm[clamp_row(sel[l], n) + (long)a * n];
-  for (int l = threadIdx.x; l < kk; l += NTHR) ls[l] = lam[clamp_row(sel[l], n)];
+      qs[a * KMAX + l] = Qm[clamp_row(sel[l], other) + (long)a * ldq];
+  for (int l = threadIdx.x; l < kk; l += NTHR) ls[l] = lq[clamp_row(sel[l], other)];
   __syncthreads();
   const int i = blockIdx.x * NTHR + threadIdx.x;
-  if (i >= n) return;
+  if (i >= rows) return;
   double acc[KM];
 #pragma unroll
   for (int l = 0; l < KM; ++l) acc[l] = 0.0;
   for (int a0 = 0; a0 < r; a0 += 8) {
     double p[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) p[t] = (a0 + t < r) ? P[i + (long)(a0 + t) * n] : 0.0;
+    for (int t = 0; t < 8; ++t) p[t] = (a0 + t < r) ? P[i + (long)(a0 + t) * ldp] : 0.0;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       if (a0 + t >= r) break;
@@ -57,34 +58,38 @@ __global__ __launch_bounds__(NTHR) void k_eval(int which, int n,
       for (int l = 0; l < KM; ++l) acc[l] += p[t] * qs[(a0 + t) * KMAX + l];
     }
   }
-  const double li = lam[i];
+  const double li = lp[i];
 #pragma unroll
   for (int l = 0; l < KM; ++l)
-    if (l < kk) s.C[i + (long)l * n] = acc[l] / (li + ls[l]);
+    if (l < kk) s.C[i + (long)l * s.ldc] = acc[l] / (li + ls[l]);
 }
 
-// A = Q0 (W diag(sig))  (z = 0),  B = Q1 Z  (z = 1), all k columns.
+// A = Q0 (W diag(sig))  (z = 0, n rows),  B = Q1 Z  (z = 1, m rows), all k
+// columns.
 template <int KM>
-__global__ __launch_bounds__(NTHR) void k_factors(int n, Solve2D *S) {
+__global__ __launch_bounds__(NTHR) void k_factors(Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (s.active != ACT_SWEEP) return;
   __shared__ double M[KMAX * KMAX];   // [j][c]
   const int kk = s.k, z = blockIdx.z;
   const double *Qz = z ? s.Q1 : s.Q0;
   double *out = z ? s.B : s.A;
+  const long ld = z ? s.ldv : s.ldu;
+  const int rows = z ? s.m : s.n;
+  if (blockIdx.x * NTHR >= rows) return;
   for (int j = threadIdx.x >> 6; j < kk; j += 4)
     for (int c = threadIdx.x & 63; c < kk; c += 64)
       M[j * KMAX + c] = z ? s.Z[j + c * KMAX] : s.W[j + c * KMAX] * s.sig[c];
   __syncthreads();
   const int i = blockIdx.x * NTHR + threadIdx.x;
-  if (i >= n) return;
+  if (i >= rows) return;
   double acc[KM];
 #pragma unroll
   for (int c = 0; c < KM; ++c) acc[c] = 0.0;
   for (int j0 = 0; j0 < kk; j0 += 8) {
     double q[8];
 #pragma unroll
-    for (int t = 0; t < 8; ++t) q[t] = (j0 + t < kk) ? Qz[i + (long)(j0 + t) * n] : 0.0;
+    for (int t = 0; t < 8; ++t) q[t] = (j0 + t < kk) ? Qz[i + (long)(j0 + t) * ld] : 0.0;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
       if (j0 + t >= kk) break;
@@ -94,46 +99,50 @@ __global__ __launch_bounds__(NTHR) void k_factors(int n, Solve2D *S) {
   }
 #pragma unroll
   for (int c = 0; c < KM; ++c)
-    if (c < kk) out[i + (long)c * n] = acc[c];
+    if (c < kk) out[i + (long)c * ld] = acc[c];
 }
 
-// Partial M = Bp^T B over one 256-row block; each thread owns a 4 x 4 tile
-// of the (<= 64 x 64) result.
-__global__ __launch_bounds__(NTHR) void k_change_M(int n, Solve2D *S) {
+// Partial M = Bp^T B: block b sums the 256-row chunks b, b + nbm, ... of the
+// m rows (nbm = change_blocks(m), a function of m only, so the summation
+// order of a slot never depends on the batch); each thread owns a 4 x 4
+// tile of the (<= 64 x 64) result.
+__global__ __launch_bounds__(NTHR) void k_change_M(int nbm, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (s.active != ACT_SWEEP || s.kp == 0) return;
   __shared__ double bp[64 * KMAX];   // [row][col]
   __shared__ double bb[64 * KMAX];
-  const int kk = s.k, kq = s.kp;
-  const int r0 = blockIdx.x * PANEL_M;
+  const int kk = s.k, kq = s.kp, m = s.m;
+  const long ld = s.ldv;
   const int ta = (threadIdx.x >> 4) * 4, tc = (threadIdx.x & 15) * 4;
   double acc[4][4];
 #pragma unroll
   for (int x = 0; x < 4; ++x)
 #pragma unroll
     for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-  for (int ch = 0; ch < PANEL_M / 64; ++ch) {
-    const int rb = r0 + ch * 64;
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * KMAX; e += NTHR) {
-      const int c = e >> 6, rr = e & 63;
-      const int row = rb + rr;
-      const bool ok = row < n;
-      bp[rr * KMAX + c] = (ok && c < kq) ? s.Bp[row + (long)c * n] : 0.0;
-      bb[rr * KMAX + c] = (ok && c < kk) ? s.B[row + (long)c * n] : 0.0;
-    }
-    __syncthreads();
-    for (int rr = 0; rr < 64; ++rr) {
-      double x[4], y[4];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        x[t] = bp[rr * KMAX + ta + t];
-        y[t] = bb[rr * KMAX + tc + t];
+  for (int r0 = blockIdx.x * PANEL_M; r0 < m; r0 += nbm * PANEL_M) {
+    for (int ch = 0; ch < PANEL_M / 64; ++ch) {
+      const int rb = r0 + ch * 64;
+      __syncthreads();
+      for (int e = threadIdx.x; e < 64 * KMAX; e += NTHR) {
+        const int c = e >> 6, rr = e & 63;
+        const int row = rb + rr;
+        const bool ok = row < m;
+        bp[rr * KMAX + c] = (ok && c < kq) ? s.Bp[row + (long)c * ld] : 0.0;
+        bb[rr * KMAX + c] = (ok && c < kk) ? s.B[row + (long)c * ld] : 0.0;
       }
+      __syncthreads();
+      for (int rr = 0; rr < 64; ++rr) {
+        double x[4], y[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+        for (int t = 0; t < 4; ++t) {
+          x[t] = bp[rr * KMAX + ta + t];
+          y[t] = bb[rr * KMAX + tc + t];
+        }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] += x[a] * y[c];
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[a][c] += x[a] * y[c];
+      }
     }
   }
   double *P = s.part + (size_t)blockIdx.x * KMAX * KMAX;
@@ -144,37 +153,41 @@ __global__ __launch_bounds__(NTHR) void k_change_M(int n, Solve2D *S) {
       if (ta + a < kq && tc + c < kk) P[(ta + a) * kk + tc + c] = acc[a][c];
 }
 
-__global__ __launch_bounds__(NTHR) void k_change_reduce(int nb0, Solve2D *S) {
+__global__ __launch_bounds__(NTHR) void k_change_reduce(int nbm, Solve2D *S) {
   Solve2D &s = S[blockIdx.x];
   if (s.active != ACT_SWEEP || s.kp == 0) return;
   const int kk = s.k, kq = s.kp;
   for (int o = threadIdx.x; o < kq * kk; o += NTHR) {
     double v = 0.0;
-    for (int b = 0; b < nb0; ++b) v += s.part[(size_t)b * KMAX * KMAX + o];
+    for (int b = 0; b < nbm; ++b) v += s.part[(size_t)b * KMAX * KMAX + o];
     const int a = o / kk, c = o - a * kk;
     s.Mc[a * KMAX + c] = v;
   }
 }
 
+// Block b: rows [256 b, 256 b + 256) of ||A - Ap M||^2 (n rows) and of
+// sum_a sp_a^2 ||E_a||^2 (m rows); partial sums in part[2b], part[2b + 1].
 template <int KM>
-__global__ __launch_bounds__(NTHR) void k_change_norms(int n, Solve2D *S) {
+__global__ __launch_bounds__(NTHR) void k_change_norms(Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (s.active != ACT_SWEEP || s.kp == 0) return;
   __shared__ double M[KMAX * KMAX];
   __shared__ double sp2[KMAX];
   __shared__ double red[2][4];
   const int kk = s.k, kq = s.kp;
+  if (blockIdx.x * NTHR >= max(s.n, s.m)) return;
   for (int e = threadIdx.x; e < KMAX * KMAX; e += NTHR) M[e] = s.Mc[e];
   for (int a = threadIdx.x; a < kq; a += NTHR) sp2[a] = s.sigp[a] * s.sigp[a];
   __syncthreads();
   const int i = blockIdx.x * NTHR + threadIdx.x;
   double n1 = 0.0, n2 = 0.0;
-  if (i < n) {
+  if (i < s.n) {
+    const long ld = s.ldu;
     double v[KM], w[KM];
 #pragma unroll
     for (int a = 0; a < KM; ++a) {
-      v[a] = (a < kq) ? s.Ap[i + (long)a * n] : 0.0;
-      w[a] = (a < kk) ? s.A[i + (long)a * n] : 0.0;
+      v[a] = (a < kq) ? s.Ap[i + (long)a * ld] : 0.0;
+      w[a] = (a < kk) ? s.A[i + (long)a * ld] : 0.0;
     }
 #pragma unroll
     for (int c = 0; c < KM; ++c) {
@@ -185,10 +198,14 @@ __global__ __launch_bounds__(NTHR) void k_change_norms(int n, Solve2D *S) {
         n1 += x * x;
       }
     }
+  }
+  if (i < s.m) {
+    const long ld = s.ldv;
+    double v[KM], w[KM];
 #pragma unroll
     for (int c = 0; c < KM; ++c) {
-      v[c] = (c < kk) ? s.B[i + (long)c * n] : 0.0;
-      w[c] = (c < kq) ? s.Bp[i + (long)c * n] : 0.0;
+      v[c] = (c < kk) ? s.B[i + (long)c * ld] : 0.0;
+      w[c] = (c < kq) ? s.Bp[i + (long)c * ld] : 0.0;
     }
 #pragma unroll
     for (int a = 0; a < KM; ++a) {
@@ -234,7 +251,7 @@ __device__ void spread_indices(int n, int count, int *used, int nu, int *out) {
 }
 
 // Truncation rank, convergence and growth decision (one workgroup / solve).
-__global__ __launch_bounds__(NTHR) void k_decide(int n, int nb0, Solve2D *S) {
+__global__ __launch_bounds__(NTHR) void k_decide(Solve2D *S) {
   Solve2D &s = S[blockIdx.x];
   if (s.active != ACT_SWEEP) return;
   __shared__ int used[2 * KMAX];
@@ -242,8 +259,9 @@ __global__ __launch_bounds__(NTHR) void k_decide(int n, int nb0, Solve2D *S) {
   const int kk = s.k;
   double change = -1.0;
   if (s.kp > 0) {
+    const int nbn = ceil_div(max(s.n, s.m), NTHR);
     double a = 0.0, b = 0.0;
-    for (int i = 0; i < nb0; ++i) a += s.part[2 * i], b += s.part[2 * i + 1];
+    for (int i = 0; i < nbn; ++i) a += s.part[2 * i], b += s.part[2 * i + 1];
     change = sqrt(a + b);
   }
   double tot = 0.0;
@@ -258,7 +276,7 @@ __global__ __launch_bounds__(NTHR) void k_decide(int n, int nb0, Solve2D *S) {
     else break;
   }
   if (nrm == 0.0) R = 0;
-  const bool no_slack = (R > kk - s.min_slack) && (kk < n);
+  const bool no_slack = (R > kk - s.min_slack) && (kk < min(s.n, s.m));
   int next = NEXT_CONTINUE;
   if (s.nonfinite) {
     next = NEXT_STOP;
@@ -284,46 +302,46 @@ __global__ __launch_bounds__(NTHR) void k_decide(int n, int nb0, Solve2D *S) {
   s.next = next;
   if (next == NEXT_GROW) {
     for (int t = 0; t < kk; ++t) used[t] = s.I[t];
-    spread_indices(n, s.kick, used, kk, s.probe);
+    spread_indices(s.n, s.kick, used, kk, s.probe);
   }
 }
 
 // Residual score of every column on the probe rows (rank growth).
 template <int KM>
-__global__ __launch_bounds__(NTHR) void k_growth_score(int n,
-                                                      const double *__restrict__ lam,
-                                                      Solve2D *S) {
+__global__ __launch_bounds__(NTHR) void k_growth_score(Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (s.active != ACT_SWEEP || s.next != NEXT_GROW) return;
+  if (blockIdx.x * NTHR >= s.m) return;
   constexpr int PQ = 16;
   __shared__ double uP[PQ * KMAX];
   __shared__ double aP[PQ * KMAX];
   __shared__ double lP[PQ];
   const int kk = s.k, r = s.r, nq = min(s.kick, PQ);
+  const long ldu = s.ldu, ldv = s.ldv;
   for (int e = threadIdx.x; e < nq * KMAX; e += NTHR) {
     const int q = e / KMAX, c = e - q * KMAX;
-    const int p = clamp_row(s.probe[q], n);
-    uP[e] = (c < r) ? s.Uh[p + (long)c * n] : 0.0;
-    aP[e] = (c < kk) ? s.A[p + (long)c * n] : 0.0;
+    const int p = clamp_row(s.probe[q], s.n);
+    uP[e] = (c < r) ? s.Uh[p + (long)c * ldu] : 0.0;
+    aP[e] = (c < kk) ? s.A[p + (long)c * ldu] : 0.0;
   }
-  for (int q = threadIdx.x; q < nq; q += NTHR) lP[q] = lam[clamp_row(s.probe[q], n)];
+  for (int q = threadIdx.x; q < nq; q += NTHR) lP[q] = s.lam_r[clamp_row(s.probe[q], s.n)];
   __syncthreads();
   const int j = blockIdx.x * NTHR + threadIdx.x;
-  if (j >= n) return;
+  if (j >= s.m) return;
   double num[PQ], skel[PQ];
 #pragma unroll
   for (int q = 0; q < PQ; ++q) num[q] = skel[q] = 0.0;
   for (int c = 0; c < r; ++c) {
-    const double vc = s.Vh[j + (long)c * n];
+    const double vc = s.Vh[j + (long)c * ldv];
 #pragma unroll
     for (int q = 0; q < PQ; ++q) num[q] += uP[q * KMAX + c] * vc;
   }
   for (int c = 0; c < kk; ++c) {
-    const double bc = s.B[j + (long)c * n];
+    const double bc = s.B[j + (long)c * ldv];
 #pragma unroll
     for (int q = 0; q < PQ; ++q) skel[q] += aP[q * KMAX + c] * bc;
   }
-  const double lj = lam[j];
+  const double lj = s.lam_c[j];
   double best = 0.0;
 #pragma unroll
   for (int q = 0; q < PQ; ++q)
@@ -332,20 +350,21 @@ __global__ __launch_bounds__(NTHR) void k_growth_score(int n,
 }
 
 // Next column set and state swap (one workgroup / solve).
-__global__ __launch_bounds__(NTHR) void k_finalize(int n, Solve2D *S) {
+__global__ __launch_bounds__(NTHR) void k_finalize(Solve2D *S) {
   Solve2D &s = S[blockIdx.x];
   if (s.active != ACT_SWEEP) return;
+  const int m = s.m;
   __shared__ double rv[4];
   __shared__ int rk[4];
   const int kk = s.k;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (s.next == NEXT_GROW) {
-    for (int t = threadIdx.x; t < kk; t += NTHR) s.score[clamp_row(s.Jn[t], n)] = -1.0;
+    for (int t = threadIdx.x; t < kk; t += NTHR) s.score[clamp_row(s.Jn[t], m)] = -1.0;
     __syncthreads();
     for (int g = 0; g < s.kgrow; ++g) {
       double best = -2.0;
       int key = 0x7fffffff;
-      for (int j = threadIdx.x; j < n; j += NTHR) {
+      for (int j = threadIdx.x; j < m; j += NTHR) {
         const double v = s.score[j];
         if (v > best || (v == best && j < key)) best = v, key = j;
       }
@@ -379,7 +398,7 @@ __global__ __launch_bounds__(NTHR) void k_finalize(int n, Solve2D *S) {
 }
 
 // After the initial maxvol on the transformed V: pad J to k0 columns.
-__global__ void k_init_J(int n, Solve2D *S) {
+__global__ void k_init_J(Solve2D *S) {
   Solve2D &s = S[blockIdx.x];
   if (s.active != ACT_INIT || threadIdx.x != 0) return;
   if (s.nonfinite) {
@@ -390,7 +409,7 @@ __global__ void k_init_J(int n, Solve2D *S) {
   __shared__ int used[2 * KMAX];
   const int kin = s.k, k0 = s.k0;
   for (int t = 0; t < kin; ++t) used[t] = s.J[t];
-  if (k0 > kin) spread_indices(n, k0 - kin, used, kin, s.J + kin);
+  if (k0 > kin) spread_indices(s.m, k0 - kin, used, kin, s.J + kin);
   s.k = k0;
   s.kp = 0;
   s.sweep = 0;
@@ -399,54 +418,52 @@ __global__ void k_init_J(int n, Solve2D *S) {
 
 }  // namespace
 
-hipError_t launch_eval(int which, int n, const double *lam, Solve2D *s,
-                       int nsolves, int kmax, hipStream_t st) {
-  dim3 g(ceil_div(n, NTHR), nsolves);
-  if (kmax <= 16) hipLaunchKernelGGL((k_eval<16>), g, dim3(NTHR), 0, st, which, n, lam, s);
-  else if (kmax <= 32) hipLaunchKernelGGL((k_eval<32>), g, dim3(NTHR), 0, st, which, n, lam, s);
-  else if (kmax <= 48) hipLaunchKernelGGL((k_eval<48>), g, dim3(NTHR), 0, st, which, n, lam, s);
-  else hipLaunchKernelGGL((k_eval<64>), g, dim3(NTHR), 0, st, which, n, lam, s);
+#define LRP_BUCKET(KERN, GRID, ...)                                          \
+  do {                                                                       \
+    if (kmax <= 16) hipLaunchKernelGGL((KERN<16>), GRID, dim3(NTHR), 0, st, __VA_ARGS__); \
+    else if (kmax <= 32) hipLaunchKernelGGL((KERN<32>), GRID, dim3(NTHR), 0, st, __VA_ARGS__); \
+    else if (kmax <= 48) hipLaunchKernelGGL((KERN<48>), GRID, dim3(NTHR), 0, st, __VA_ARGS__); \
+    else hipLaunchKernelGGL((KERN<64>), GRID, dim3(NTHR), 0, st, __VA_ARGS__); \
+  } while (0)
+
+hipError_t launch_eval(int which, int rows, Solve2D *s, int nsolves, int kmax,
+                       hipStream_t st) {
+  dim3 g(ceil_div(rows, NTHR), nsolves);
+  LRP_BUCKET(k_eval, g, which, s);
   return hipGetLastError();
 }
 
-hipError_t launch_factors(int n, Solve2D *s, int nsolves, int kmax,
+hipError_t launch_factors(int n, int m, Solve2D *s, int nsolves, int kmax,
                           hipStream_t st) {
-  dim3 g(ceil_div(n, NTHR), nsolves, 2);
-  if (kmax <= 16) hipLaunchKernelGGL((k_factors<16>), g, dim3(NTHR), 0, st, n, s);
-  else if (kmax <= 32) hipLaunchKernelGGL((k_factors<32>), g, dim3(NTHR), 0, st, n, s);
-  else if (kmax <= 48) hipLaunchKernelGGL((k_factors<48>), g, dim3(NTHR), 0, st, n, s);
-  else hipLaunchKernelGGL((k_factors<64>), g, dim3(NTHR), 0, st, n, s);
+  dim3 g(ceil_div(max(n, m), NTHR), nsolves, 2);
+  LRP_BUCKET(k_factors, g, s);
   return hipGetLastError();
 }
 
-hipError_t launch_change(int n, int nb0, Solve2D *s, int nsolves, int kmax,
+int change_blocks(int m) { return min(ceil_div(m, PANEL_M), 64); }
+
+hipError_t launch_change(int n, int m, Solve2D *s, int nsolves, int kmax,
                          hipStream_t st) {
-  hipLaunchKernelGGL(k_change_M, dim3(nb0, nsolves), dim3(NTHR), 0, st, n, s);
-  hipLaunchKernelGGL(k_change_reduce, dim3(nsolves), dim3(NTHR), 0, st, nb0, s);
-  dim3 g(ceil_div(n, NTHR), nsolves);
-  if (kmax <= 16) hipLaunchKernelGGL((k_change_norms<16>), g, dim3(NTHR), 0, st, n, s);
-  else if (kmax <= 32) hipLaunchKernelGGL((k_change_norms<32>), g, dim3(NTHR), 0, st, n, s);
-  else if (kmax <= 48) hipLaunchKernelGGL((k_change_norms<48>), g, dim3(NTHR), 0, st, n, s);
-  else hipLaunchKernelGGL((k_change_norms<64>), g, dim3(NTHR), 0, st, n, s);
+  const int nbm = change_blocks(m);
+  hipLaunchKernelGGL(k_change_M, dim3(nbm, nsolves), dim3(NTHR), 0, st, nbm, s);
+  hipLaunchKernelGGL(k_change_reduce, dim3(nsolves), dim3(NTHR), 0, st, nbm, s);
+  dim3 g(ceil_div(max(n, m), NTHR), nsolves);
+  LRP_BUCKET(k_change_norms, g, s);
   return hipGetLastError();
 }
 
-hipError_t launch_decide(int n, const double *lam, Solve2D *s, int nsolves,
-                         int kmax, int nb0, hipStream_t st) {
-  hipLaunchKernelGGL(k_decide, dim3(nsolves), dim3(NTHR), 0, st, n,
-                     ceil_div(n, NTHR), s);
-  dim3 g(ceil_div(n, NTHR), nsolves);
-  if (kmax <= 16) hipLaunchKernelGGL((k_growth_score<16>), g, dim3(NTHR), 0, st, n, lam, s);
-  else if (kmax <= 32) hipLaunchKernelGGL((k_growth_score<32>), g, dim3(NTHR), 0, st, n, lam, s);
-  else if (kmax <= 48) hipLaunchKernelGGL((k_growth_score<48>), g, dim3(NTHR), 0, st, n, lam, s);
-  else hipLaunchKernelGGL((k_growth_score<64>), g, dim3(NTHR), 0, st, n, lam, s);
-  hipLaunchKernelGGL(k_finalize, dim3(nsolves), dim3(NTHR), 0, st, n, s);
-  (void)nb0;
+hipError_t launch_decide(int n, int m, Solve2D *s, int nsolves, int kmax,
+                         hipStream_t st) {
+  (void)n;
+  hipLaunchKernelGGL(k_decide, dim3(nsolves), dim3(NTHR), 0, st, s);
+  dim3 g(ceil_div(m, NTHR), nsolves);
+  LRP_BUCKET(k_growth_score, g, s);
+  hipLaunchKernelGGL(k_finalize, dim3(nsolves), dim3(NTHR), 0, st, s);
   return hipGetLastError();
 }
 
-hipError_t launch_init_J(int n, Solve2D *s, int nsolves, hipStream_t st) {
-  hipLaunchKernelGGL(k_init_J, dim3(nsolves), dim3(64), 0, st, n, s);
+hipError_t launch_init_J(Solve2D *s, int nsolves, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_J, dim3(nsolves), dim3(64), 0, st, s);
   return hipGetLastError();
 }
 

@@ -126,7 +126,7 @@ Plan make_plan(const lrp_opts *o, double eps, int n) {
   if (prec == LRP_PREC_AUTO) {
     // the inverse transform's relative error reaches the result undamped;
     // the forward one is damped by the eigenvalue division
-    p.fwd_prec = eps >= 1e-6 ? LRP_PREC_BF16X3 : (eps >= 1e-8 ? LRP_PREC_FP32 : LRP_PREC_FP64);
+    p.fwd_prec = eps >= 1e-6 ? LRP_PREC_BF16X3 : (eps >= 1e-7 ? LRP_PREC_FP32 : LRP_PREC_FP64);
     p.inv_prec = eps >= 1e-7 ? LRP_PREC_FP32 : LRP_PREC_FP64;
   } else if (prec == LRP_PREC_FP32 || prec == LRP_PREC_BF16X3) {
     p.fwd_prec = p.inv_prec = prec;
@@ -138,8 +138,9 @@ Plan make_plan(const lrp_opts *o, double eps, int n) {
 
 // ------------------------------------------------------------- Group2D
 struct Layout {
-  size_t off_Uh, off_Vh, off_panels, off_treeR, off_treeH, off_treeTau,
-      off_treeY, off_small, off_part, off_mvval, off_score, off_ints, total;
+  size_t off_Uh, off_Vh, off_upan, off_vpan, off_cpan, off_treeR, off_treeH,
+      off_treeTau, off_treeY, off_small, off_part, off_mvval, off_score,
+      off_ints, total;
 };
 
 static size_t tree_nodes(const Tree &t, int from) {
@@ -148,7 +149,11 @@ static size_t tree_nodes(const Tree &t, int from) {
   return s;
 }
 
-static Layout slot_layout(int n, const Tree &t) {
+// Per-slot workspace: row-side panels (n rows: Uh, Q0, A, Ap), column-side
+// panels (m rows: Vh, Q1, B, Bp), shared panels (max(n, m) rows: C, Hv),
+// the TSQR / tournament tree over max(n, m) rows, small matrices, partial
+// sums and index sets.
+static Layout slot_layout(int n, int m, const Tree &t) {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -157,23 +162,31 @@ static Layout slot_layout(int n, const Tree &t) {
     return r;
   };
   const size_t nb0 = t.nb[0];
+  const size_t mx = std::max(n, m);
   L.off_Uh = take((size_t)n * KMAX * 8);
-  L.off_Vh = take((size_t)n * KMAX * 8);
-  L.off_panels = take((size_t)8 * n * KMAX * 8);
+  L.off_Vh = take((size_t)m * KMAX * 8);
+  L.off_upan = take((size_t)3 * n * KMAX * 8);
+  L.off_vpan = take((size_t)3 * m * KMAX * 8);
+  L.off_cpan = take((size_t)2 * mx * KMAX * 8);
   L.off_treeR = take(tree_nodes(t, 0) * KMAX * KMAX * 8);
   L.off_treeH = take(std::max<size_t>(1, tree_nodes(t, 1)) * PANEL_M * KMAX * 8);
   L.off_treeTau = take(tree_nodes(t, 0) * KMAX * 8);
   L.off_treeY = take(tree_nodes(t, 0) * KMAX * KMAX * 8);
   L.off_small = take((size_t)(7 * KMAX * KMAX + 2 * KMAX) * 8);
-  L.off_part = take(std::max<size_t>(nb0, 1) * KMAX * KMAX * 8);
+  L.off_part = take(std::max<size_t>((size_t)change_blocks(m) * KMAX * KMAX, 2 * nb0) * 8);
   L.off_mvval = take(nb0 * MV_TOP * 8);
-  L.off_score = take((size_t)n * 8);
+  L.off_score = take((size_t)m * 8);
   L.off_ints = take((tree_nodes(t, 0) * KMAX + nb0 * MV_TOP + 4 * KMAX) * 4);
   L.total = o;
   return L;
 }
 
-Group2D::Group2D(lrp_ctx *ctx, int n, int cap) : ctx_(ctx), n_(n), cap_(cap) {}
+size_t cross_slot_bytes(int n, int m) {
+  return slot_layout(n, m, make_tree(std::max(n, m), KMAX)).total;
+}
+
+Group2D::Group2D(lrp_ctx *ctx, int n, int cap, int m, const double *lam_c)
+    : ctx_(ctx), n_(n), cap_(cap), m_(m > 0 ? m : n), lam_c_(lam_c) {}
 
 Group2D::~Group2D() {
   if (stream_) {
@@ -195,8 +208,8 @@ lrp_status Group2D::init() {
   lrp_status err;
   tabs_ = get_tables(ctx_, n_, &err);
   if (!tabs_) return err;
-  talloc_ = make_tree(n_, KMAX);
-  const Layout L = slot_layout(n_, talloc_);
+  talloc_ = make_tree(std::max(n_, m_), KMAX);
+  const Layout L = slot_layout(n_, m_, talloc_);
   per_slot_ = L.total;
   cols_cap_ = cap_ * 2 * KMAX;
   partial_elems_ = dst_partial_elems(n_, std::min(cols_cap_, 4 * KMAX));
@@ -218,21 +231,31 @@ lrp_status Group2D::init() {
   kin_.assign(cap_, 0);
   for (int i = cap_ - 1; i >= 0; --i) free_slots.push_back(i);
   // carve fixed pointers of every slot once
+  const size_t mx = std::max(n_, m_);
   for (int i = 0; i < cap_; ++i) {
     Solve2D &s = h_s_[i];
     char *b = ws_ + per_slot_ * i;
-    const size_t nk = (size_t)n_ * KMAX;
+    s.n = n_;
+    s.m = m_;
+    s.ldu = n_;
+    s.ldv = m_;
+    s.ldc = (long)mx;
+    s.lam_r = tabs_->lam;
+    s.lam_c = lam_c_ ? lam_c_ : tabs_->lam;
     s.Uh = (double *)(b + L.off_Uh);
     s.Vh = (double *)(b + L.off_Vh);
-    double *pan = (double *)(b + L.off_panels);
-    s.C = pan;
-    s.Hv = pan + nk;
-    s.Q0 = pan + 2 * nk;
-    s.Q1 = pan + 3 * nk;
-    s.A = pan + 4 * nk;
-    s.B = pan + 5 * nk;
-    s.Ap = pan + 6 * nk;
-    s.Bp = pan + 7 * nk;
+    double *up = (double *)(b + L.off_upan);
+    double *vp = (double *)(b + L.off_vpan);
+    double *cp = (double *)(b + L.off_cpan);
+    const size_t nk = (size_t)n_ * KMAX, mk = (size_t)m_ * KMAX, ck = mx * KMAX;
+    s.Q0 = up;
+    s.A = up + nk;
+    s.Ap = up + 2 * nk;
+    s.Q1 = vp;
+    s.B = vp + mk;
+    s.Bp = vp + 2 * mk;
+    s.C = cp;
+    s.Hv = cp + ck;
     s.tree_R = (double *)(b + L.off_treeR);
     s.tree_H = (double *)(b + L.off_treeH);
     s.tree_tau = (double *)(b + L.off_treeTau);
@@ -272,7 +295,6 @@ void Group2D::setup_slot(int i, const double *U, const double *V, long ld, int r
   plans_[i] = plan;
   s.n = n_;
   s.r = r;
-  s.kcap = plan.kcap;
   s.kick = plan.kick;
   s.max_sweeps = plan.max_sweeps;
   s.min_slack = plan.min_slack;
@@ -297,7 +319,8 @@ void Group2D::setup_slot(int i, const double *U, const double *V, long ld, int r
   hi = std::max(s.sig, s.sigp);
   s.sig = lo;
   s.sigp = hi;
-  const int k0 = std::min(std::min(n_, r + plan.kick), plan.kcap);
+  s.kcap = std::min(plan.kcap, std::min(n_, m_));
+  const int k0 = std::min(r + plan.kick, s.kcap);
   s.k0 = k0;
   s.k = std::min(r, k0);   // columns of the initial maxvol on Vh
   kin_[i] = s.k;
@@ -346,8 +369,8 @@ lrp_status Group2D::forward(const std::vector<int> &slots, hipStream_t st) {
     for (int i : slots) {
       const Solve2D &s = h_s_[i];
       if (plans_[i].fwd_prec != prec || s.r == 0) continue;
-      for (int c = 0; c < s.r; ++c) cols.push_back({s.U + (long)c * s.ld, s.Uh + (long)c * n_, i, 0});
-      for (int c = 0; c < s.r; ++c) cols.push_back({s.V + (long)c * s.ld, s.Vh + (long)c * n_, i, 0});
+      for (int c = 0; c < s.r; ++c) cols.push_back({s.U + (long)c * s.ld, s.Uh + (long)c * s.ldu, i, 0});
+      for (int c = 0; c < s.r; ++c) cols.push_back({s.V + (long)c * s.ld, s.Vh + (long)c * s.ldv, i, 0});
     }
     if (!cols.empty()) {
       lrp_status e = dst_cols(cols, prec, st);
@@ -375,30 +398,28 @@ lrp_status Group2D::step(hipStream_t st) {
       rmax = std::max(rmax, s.r);
     }
   }
+  // trees depend on the shape only, so a slot's arithmetic does not depend
+  // on which other slots share the launch
+  const Tree tn = make_tree(n_, KMAX), tm = make_tree(m_, KMAX);
   if (any_init) {
-    // the tree depends on n only, so a slot's arithmetic does not depend on
-    // which other slots share the launch
-    const Tree t = make_tree(n_, KMAX);
-    HIPCHK(launch_tsqr(TS_VH_TO_Q0, n_, t, d_s_, hi, kin, st));
-    HIPCHK(launch_maxvol(MV_Q0_TO_J, n_, t, d_s_, hi, kin, st));
-    HIPCHK(launch_init_J(n_, d_s_, hi, st));
+    HIPCHK(launch_tsqr(TS_VH_TO_Q1, m_, tm, d_s_, hi, kin, st));
+    HIPCHK(launch_maxvol(MV_Q1_TO_J, m_, tm, d_s_, hi, kin, st));
+    HIPCHK(launch_init_J(d_s_, hi, st));
   }
   if (!any_init && !any_sweep) return LRP_OK;
   // k of a slot only grows at the end of a sweep, so kmax bounds this sweep
   const int km = std::max(kmax, 1);
   const int kev = std::max(km, rmax);
-  const Tree t = make_tree(n_, KMAX);
-  const int nb0 = ceil_div(n_, NTHR);
-  HIPCHK(launch_eval(EV_COLS, n_, tabs_->lam, d_s_, hi, kev, st));
-  HIPCHK(launch_tsqr(TS_C_TO_Q0, n_, t, d_s_, hi, km, st));
-  HIPCHK(launch_maxvol(MV_Q0_TO_I, n_, t, d_s_, hi, km, st));
-  HIPCHK(launch_eval(EV_ROWS, n_, tabs_->lam, d_s_, hi, kev, st));
-  HIPCHK(launch_tsqr(TS_C_TO_Q1, n_, t, d_s_, hi, km, st));
-  HIPCHK(launch_maxvol(MV_Q1_TO_JN, n_, t, d_s_, hi, km, st));
-  HIPCHK(launch_core(n_, d_s_, hi, st));
-  HIPCHK(launch_factors(n_, d_s_, hi, km, st));
-  HIPCHK(launch_change(n_, nb0, d_s_, hi, km, st));
-  HIPCHK(launch_decide(n_, tabs_->lam, d_s_, hi, kev, nb0, st));
+  HIPCHK(launch_eval(EV_COLS, n_, d_s_, hi, kev, st));
+  HIPCHK(launch_tsqr(TS_C_TO_Q0, n_, tn, d_s_, hi, km, st));
+  HIPCHK(launch_maxvol(MV_Q0_TO_I, n_, tn, d_s_, hi, km, st));
+  HIPCHK(launch_eval(EV_ROWS, m_, d_s_, hi, kev, st));
+  HIPCHK(launch_tsqr(TS_C_TO_Q1, m_, tm, d_s_, hi, km, st));
+  HIPCHK(launch_maxvol(MV_Q1_TO_JN, m_, tm, d_s_, hi, km, st));
+  HIPCHK(launch_core(ACT_SWEEP, d_s_, hi, st));
+  HIPCHK(launch_factors(n_, m_, d_s_, hi, km, st));
+  HIPCHK(launch_change(n_, m_, d_s_, hi, km, st));
+  HIPCHK(launch_decide(n_, m_, d_s_, hi, kev, st));
   return LRP_OK;
 }
 
@@ -414,8 +435,8 @@ lrp_status Group2D::inverse(const std::vector<int> &slots, hipStream_t st) {
     for (int i : slots) {
       const Solve2D &s = h_s_[i];
       if (plans_[i].inv_prec != prec) continue;
-      for (int c = 0; c < s.R; ++c) cols.push_back({s.A + (long)c * n_, s.Ux + (long)c * s.ldx, -1, 0});
-      for (int c = 0; c < s.R; ++c) cols.push_back({s.B + (long)c * n_, s.Vx + (long)c * s.ldx, -1, 0});
+      for (int c = 0; c < s.R; ++c) cols.push_back({s.A + (long)c * s.ldu, s.Ux + (long)c * s.ldx, -1, 0});
+      for (int c = 0; c < s.R; ++c) cols.push_back({s.B + (long)c * s.ldv, s.Vx + (long)c * s.ldx, -1, 0});
     }
     if (!cols.empty()) {
       lrp_status e = dst_cols(cols, prec, st);
@@ -456,7 +477,7 @@ lrp_status lrp_create(lrp_ctx **ctx, int device, size_t workspace_bytes) {
   if (hipSetDevice(device) != hipSuccess) return LRP_EDEVICE;
   lrp_ctx *c = new lrp_ctx();
   c->device = device;
-  c->budget = workspace_bytes ? workspace_bytes : ((size_t)2 << 30);
+  c->budget = workspace_bytes ? workspace_bytes : ((size_t)32 << 30);
   *ctx = c;
   return LRP_OK;
 }
@@ -546,7 +567,9 @@ lrp_status lrp_destroy(lrp_ctx *ctx) {
   if (ctx->tx_dcols) dev_free(ctx, ctx->tx_dcols, ctx->tx_bytes);
   if (ctx->tx_hcols) (void)hipHostFree(ctx->tx_hcols);
   ctx->batch_groups.clear();
+  ctx->batch3_groups.clear();
   ctx->serve_groups.clear();
+  ctx->serve3_groups.clear();
   for (auto &kv : ctx->tables) dev_free(ctx, kv.second.tab, kv.second.bytes);
   if (ctx->serve_stream) (void)hipStreamDestroy(ctx->serve_stream);
   delete ctx;
@@ -661,12 +684,6 @@ lrp_status lrpoisson_solve2d(lrp_ctx *ctx, int64_t n, int32_t rank,
   return e;
 }
 
-lrp_status lrpoisson_solve3d(lrp_ctx *ctx, int64_t n, const int32_t rank[3],
-                             const double *U1, const double *U2,
-                             const double *U3, int64_t ld, const double *G,
-                             double eps, const lrp_opts *opts,
-                             double *U1x, double *U2x, double *U3x,
-                             int64_t ldx, double *Gx, const int32_t rmax[3],
-                             int32_t rank_out[3], lrp_info *info, void *stream);
+
 
 }  // extern "C"

@@ -26,16 +26,20 @@ struct Plan {
   double tau;
 };
 
-// A group of 2D solve slots on one grid size.  Every kernel launch covers all
-// slots; each slot's `active` flag selects which launches act on it.
+// A group of cross-approximation slots of one shape.  Every kernel launch
+// covers all slots; each slot's `active` flag selects which launches act on
+// it.  2D solves: n x n with lambda on both sides.  3D path: the n x n^2
+// mode unfoldings, column denominators lam_c (n^2 entries).
 class Group2D {
  public:
-  Group2D(lrp_ctx *ctx, int n, int cap);
+  Group2D(lrp_ctx *ctx, int n, int cap, int m = 0, const double *lam_c = nullptr);
   ~Group2D();
   lrp_status init();                       // allocate
   size_t bytes() const { return bytes_; }
   int n() const { return n_; }
+  int m() const { return m_; }
   int cap() const { return cap_; }
+  const GridTables *tables() const { return tabs_; }
 
   // Fill slot `i` for a new problem (host mirror only) -- call upload().
   void setup_slot(int i, const double *U, const double *V, long ld, int r,
@@ -52,6 +56,12 @@ class Group2D {
   // Inverse transform of the listed finished slots.
   lrp_status inverse(const std::vector<int> &slots, hipStream_t st);
 
+  // Sine transform of arbitrary columns; a column's `solve` index names a
+  // slot of this group whose non-finite flag it sets.
+  lrp_status transform(std::vector<DstCol> &cols, int prec, hipStream_t st) {
+    return dst_cols(cols, prec, st);
+  }
+
   Solve2D &host(int i) { return h_s_[i]; }
   Solve2D *dev_solves() { return d_s_; }
   // own stream (default priority) for the serving loop
@@ -62,7 +72,8 @@ class Group2D {
  private:
   lrp_status dst_cols(std::vector<DstCol> &cols, int prec, hipStream_t st);
   lrp_ctx *ctx_;
-  int n_, cap_;
+  int n_, cap_, m_;
+  const double *lam_c_;
   Tree talloc_;
   size_t per_slot_ = 0, bytes_ = 0;
   char *ws_ = nullptr;
@@ -77,6 +88,52 @@ class Group2D {
   hipStream_t stream_ = nullptr;
 };
 
+// A group of 3D (Tucker) solve slots of one grid size n.  Slot i owns the
+// mode slots 3i, 3i+1, 3i+2 of an n x n^2 cross group.
+class Group3D {
+ public:
+  Group3D(lrp_ctx *ctx, int n, int cap);
+  ~Group3D();
+  lrp_status init();
+  int n() const { return n_; }
+  int cap() const { return cap_; }
+  size_t bytes() const;
+  // Fill slot i (host mirror).  U[d]: n x r[d] (ld), G: r0 x r1 x r2.
+  void setup_slot(int i, const double *const U[3], long ld, const int r[3],
+                  const double *G, double eps, double *const X[3], long ldx,
+                  double *Gx, const int rmax[3], const Plan &plan);
+  // Upload, forward transforms and mode-unfolding factors of new slots.
+  lrp_status start(const std::vector<int> &slots, hipStream_t st);
+  // One sweep of every running mode cross, then the core, its rounding and
+  // the output core of every solve whose three crosses have finished.
+  lrp_status step(hipStream_t st);
+  lrp_status fetch(hipStream_t st, bool sync = true);
+  // Inverse transforms of the output factors of finished slots.
+  lrp_status finish(const std::vector<int> &slots, hipStream_t st);
+  Solve3D &host(int i) { return h_s_[i]; }
+  const Plan &plan(int i) const { return plans_[i]; }
+  Group2D &modes() { return *inner_; }
+  hipStream_t stream() { return inner_->stream(); }
+  std::vector<int> free_slots;
+
+ private:
+  struct IO {
+    const double *U[3];
+    long ld;
+    double *X[3];
+    long ldx;
+  };
+  lrp_ctx *ctx_;
+  int n_, cap_;
+  size_t bytes_ = 0;
+  char *ws_ = nullptr;
+  double *mu_ = nullptr;
+  std::unique_ptr<Group2D> inner_;
+  Solve3D *d_s_ = nullptr, *h_s_ = nullptr;
+  std::vector<Plan> plans_;
+  std::vector<IO> io_;
+};
+
 }  // namespace lrp
 
 // Requests of the serving loop.
@@ -85,7 +142,8 @@ struct ServeReq {
   lrp_request req;
   int state;            // 0 queued, 1 running, 2 done
   int group_slot;
-  lrp::Group2D *group;
+  lrp::Group2D *group;      // 2D requests
+  lrp::Group3D *group3;     // 3D requests
   int32_t status;
   int32_t rank_out[3];
   lrp_info info;
@@ -97,11 +155,13 @@ struct lrp_ctx {
   size_t budget = 0;
   size_t used = 0;
   std::map<int, lrp::GridTables> tables;
-  // cached group for synchronous batches, keyed by n
+  // cached groups for synchronous calls, keyed by n
   std::map<int, std::unique_ptr<lrp::Group2D>> batch_groups;
+  std::map<int, std::unique_ptr<lrp::Group3D>> batch3_groups;
   // serving
   hipStream_t serve_stream = nullptr;
   std::map<int, std::unique_ptr<lrp::Group2D>> serve_groups;
+  std::map<int, std::unique_ptr<lrp::Group3D>> serve3_groups;
   std::deque<ServeReq> queue;
   std::map<uint64_t, ServeReq> running;
   std::map<uint64_t, ServeReq> finished;
@@ -133,4 +193,14 @@ hipError_t timed_dst(lrp_ctx *ctx, int prec, int n, const void *tab,
                      const DstCol *cols, int ncols, Solve2D *solves,
                      double *partial, size_t partial_elems, hipStream_t st);
 void dev_free(lrp_ctx *ctx, void *p, size_t bytes);
+// 3D helpers shared by the synchronous call and the serving loop
+lrp_status check_problem3d(int64_t n, const int32_t rank[3], const double *const U[3],
+                           int64_t ld, const double *G, double eps,
+                           double *const X[3], int64_t ldx, const double *Gx,
+                           const int32_t rmax[3]);
+void fill_info3d(Group3D &g, int i, int32_t rank_out[3], lrp_info *info);
+// device bytes of one slot of a cross group of shape n x m
+size_t cross_slot_bytes(int n, int m);
+// device bytes of one 3D slot of grid size n (its three mode slots included)
+size_t solve3d_slot_bytes(int n);
 }  // namespace lrp

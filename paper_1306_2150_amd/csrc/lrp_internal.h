@@ -22,6 +22,7 @@ enum : int {
   ACT_DONE = 0,       // finished (status holds the result)
   ACT_SWEEP = 1,      // run another sweep
   ACT_INIT = 2,       // waiting for the initial column choice
+  ACT_CORE = 3,       // 3D path: factoring an unfolding of the Tucker core
 };
 enum : int { NEXT_CONTINUE = 0, NEXT_GROW = 1, NEXT_STOP = 2 };
 
@@ -37,19 +38,26 @@ struct Tree {
 // kernels and copied back to the host once per sweep.
 struct Solve2D {
   // ---- constants
-  int n, r, kcap, kick, max_sweeps, min_slack, rmax;
+  // The matrix approximated is Xh_ij = (Uh_i . Vh_j) / (lam_r[i] + lam_c[j]),
+  // i < n, j < m.  A 2D solve has m = n and lam_c = lam_r = lambda; a mode of
+  // the 3D path has m = n^2 (pairs of the other two modes) and
+  // lam_c[j + n l] = lambda_j + lambda_l.
+  int n, m, r, kcap, kick, max_sweeps, min_slack, rmax;
   double eps, tau;
   const double *U, *V;
   long ld;
   double *Ux, *Vx;
   long ldx;
-  // ---- workspace (n-row panels have leading dimension n)
-  double *Uh, *Vh;          // n x r  transformed input factors
-  double *C;                // n x KMAX  evaluated columns / rows
-  double *Hv;               // n x KMAX  leaf Householder vectors
-  double *Q0, *Q1;          // n x KMAX  orthonormal bases (columns, rows)
-  double *A, *B;            // n x KMAX  skeleton factors, this sweep
-  double *Ap, *Bp;          // n x KMAX  skeleton factors, previous sweep
+  const double *lam_r, *lam_c;
+  // ---- workspace.  Row-side panels (n rows) have leading dimension ldu,
+  // column-side panels (m rows) ldv, the shared ones (C, Hv) ldc >= both.
+  long ldu, ldv, ldc;
+  double *Uh, *Vh;          // n x r, m x r  transformed input factors
+  double *C;                // evaluated columns / rows (ldc)
+  double *Hv;               // leaf Householder vectors (ldc)
+  double *Q0, *Q1;          // orthonormal bases: columns (n rows), rows (m rows)
+  double *A, *B;            // skeleton factors, this sweep (n rows, m rows)
+  double *Ap, *Bp;          // skeleton factors, previous sweep
   double *tree_R;           // sum_l nb[l] * KMAX*KMAX  R factors per node
   double *tree_H;           // sum_{l>=1} nb[l] * fan*KMAX*KMAX  node vectors
   double *tree_tau;         // sum_l nb[l] * KMAX
@@ -65,7 +73,7 @@ struct Solve2D {
   double *part;             // nb0 * KMAX*KMAX  partial sums
   double *mv_val;           // nb0 * MV_TOP  maxvol violators (|B|)
   int *mv_row;              // nb0 * MV_TOP  maxvol violators (row)
-  double *score;            // n  growth scores
+  double *score;            // m  growth scores
   int *I, *J, *Jn;          // KMAX pivot sets
   int *probe;               // KMAX probe rows
   // ---- control
@@ -83,6 +91,38 @@ struct Solve2D {
   double nrm;               // ||sigma||
   double change;            // last relative change, -1 if none
   double chg_part[2];       // change pieces
+};
+
+// Per-solve device state of a 3D (Tucker) solve.  Mode d is approximated by
+// the cross of the mode-d unfolding of the divided spectrum, held in the
+// Solve2D slot inner[d] (n rows, n^2 columns: the pairs (j, l) of the other
+// two modes p < q, column index j + n l).
+constexpr int CORE_MAX = KMAX * KMAX * KMAX;   // entries of a Tucker core buffer
+struct Solve3D {
+  int n;
+  int r[3];                 // input Tucker ranks
+  int rmax[3];              // output capacities
+  double eps;               // requested accuracy
+  const double *G;          // input core r0 x r1 x r2 (i0 fastest)
+  double *Gx;               // output core R0 x R1 x R2
+  Solve2D *inner[3];        // device addresses of the mode slots
+  double *T[3];             // r_d x r_p x n  half-contracted core per mode
+  double *buf0, *buf1;      // CORE_MAX each, ping-pong for mode products
+  // ---- control
+  int phase;                // P3_*
+  int k[3];                 // cross ranks of the modes (set before the core)
+  int R[3];                 // output ranks
+  int cross_status;         // combined status of the three mode crosses
+  int status;               // final status
+  int out_ok;               // outputs written (ranks within rmax)
+  double nrm;               // ||core||
+};
+enum : int {
+  P3_IDLE = 0,    // slot free
+  P3_CROSS = 1,   // mode crosses running
+  P3_CORE = 2,    // core built, unfoldings being factored
+  P3_OUT = 3,     // output factors and core being written
+  P3_DONE = 4,    // finished (status, R valid)
 };
 
 // One column of a sine-transform GEMM: dst[0:n] = S * src[0:n].
@@ -193,26 +233,40 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
                       size_t partial_elems, hipStream_t st);
 size_t dst_partial_elems(int n, int ncols);
 
-enum : int { EV_COLS = 0, EV_ROWS = 1, EV_GROWTH = 2 };
-hipError_t launch_eval(int which, int n, const double *lam, Solve2D *s,
+// Row counts: calls on the column side (Xh[:, J], Q0, A) cover the n rows,
+// calls on the row side (Xh[I, :]^T, Q1, B, Vh) the m columns.
+enum : int { EV_COLS = 0, EV_ROWS = 1 };
+hipError_t launch_eval(int which, int rows, Solve2D *s, int nsolves, int kmax,
+                       hipStream_t st);
+
+// TSQR inputs/outputs.  TS_CORE factors the panel in C with `rows` rows and
+// keeps only R (in Rfin); it acts on slots in the ACT_CORE phase.
+enum : int { TS_C_TO_Q0 = 0, TS_C_TO_Q1 = 1, TS_VH_TO_Q1 = 2, TS_CORE = 3 };
+hipError_t launch_tsqr(int which, int rows, const Tree &tr, Solve2D *s,
                        int nsolves, int kmax, hipStream_t st);
 
-enum : int { TS_C_TO_Q0 = 0, TS_C_TO_Q1 = 1, TS_VH_TO_Q0 = 2 };
-hipError_t launch_tsqr(int which, int n, const Tree &tr, Solve2D *s,
-                       int nsolves, int kmax, hipStream_t st);
-
-enum : int { MV_Q0_TO_I = 0, MV_Q1_TO_JN = 1, MV_Q0_TO_J = 2 };
-hipError_t launch_maxvol(int which, int n, const Tree &tr, Solve2D *s,
+enum : int { MV_Q0_TO_I = 0, MV_Q1_TO_JN = 1, MV_Q1_TO_J = 2 };
+hipError_t launch_maxvol(int which, int rows, const Tree &tr, Solve2D *s,
                          int nsolves, int kmax, hipStream_t st);
 
-hipError_t launch_core(int n, Solve2D *s, int nsolves, hipStream_t st);
-hipError_t launch_factors(int n, Solve2D *s, int nsolves, int kmax,
+hipError_t launch_core(int phase, Solve2D *s, int nsolves, hipStream_t st);
+hipError_t launch_factors(int n, int m, Solve2D *s, int nsolves, int kmax,
                           hipStream_t st);
-hipError_t launch_change(int n, int nb0, Solve2D *s, int nsolves, int kmax,
+// blocks of the change's partial Gram sums over m rows (fixed per m)
+int change_blocks(int m);
+hipError_t launch_change(int n, int m, Solve2D *s, int nsolves, int kmax,
                          hipStream_t st);
-hipError_t launch_decide(int n, const double *lam, Solve2D *s, int nsolves,
-                         int kmax, int nb0, hipStream_t st);
-hipError_t launch_init_J(int n, Solve2D *s, int nsolves, hipStream_t st);
+hipError_t launch_decide(int n, int m, Solve2D *s, int nsolves, int kmax,
+                         hipStream_t st);
+hipError_t launch_init_J(Solve2D *s, int nsolves, hipStream_t st);
+
+// ---- 3D path (tucker.hip)
+hipError_t launch_mu(int n, const double *lam, double *mu, hipStream_t st);
+hipError_t launch_unfold_factors(Solve3D *s, int nsolves, int n, int rmax,
+                                 hipStream_t st);
+hipError_t launch_core_build(Solve3D *s, int nsolves, hipStream_t st);
+hipError_t launch_core_unfold(Solve3D *s, int nsolves, int P, hipStream_t st);
+hipError_t launch_tucker_out(Solve3D *s, int nsolves, int n, hipStream_t st);
 
 Tree make_tree(int n, int kmax);
 

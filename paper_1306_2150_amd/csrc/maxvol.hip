@@ -9,12 +9,13 @@
 //     tournament -- every 256-row block selects its pivot rows, internal
 //     nodes run the elimination again on the union of their children's
 //     candidates;
-//  2. rounds of: Inv = Q[I,:]^-1 (Gauss-Jordan, partial pivoting); every
-//     block forms its rows of B = Q Inv and reports its largest entries above
-//     tau; one workgroup then runs the classical swap loop (swap the argmax
-//     row in, rank-1 update of B) on I plus the reported rows.  A round that
-//     finds no entry above tau ends the iteration.  Each swap multiplies
-//     |det Q[I,:]| by more than tau, so the rounds terminate.
+//  2. Inv = Q[I,:]^-1 (Gauss-Jordan, partial pivoting), then rounds of:
+//     every block forms its rows of B = Q Inv and reports its largest
+//     entries above tau; one workgroup runs the classical swap loop (swap the
+//     argmax row in, rank-1 update of B) on I plus the reported rows and
+//     applies the same rank-1 updates to Inv.  A round that finds no entry
+//     above tau ends the iteration.  Each swap multiplies |det Q[I,:]| by
+//     more than tau, so the rounds terminate.
 #include "panel.h"
 
 namespace lrp {
@@ -22,17 +23,18 @@ namespace {
 
 struct MvIO {
   const double *Q;
+  long ld;
   int *out;
   double *inv;
 };
 __device__ inline MvIO mv_io(int which, Solve2D &s) {
-  if (which == MV_Q0_TO_I) return {s.Q0, s.I, s.InvC};
-  if (which == MV_Q1_TO_JN) return {s.Q1, s.Jn, s.Inv};
-  return {s.Q0, s.J, s.Inv};
+  if (which == MV_Q0_TO_I) return {s.Q0, s.ldu, s.I, s.InvC};
+  if (which == MV_Q1_TO_JN) return {s.Q1, s.ldv, s.Jn, s.Inv};
+  return {s.Q1, s.ldv, s.J, s.Inv};   // MV_Q1_TO_J
 }
 
 __device__ inline int mv_phase(int which) {
-  return which == MV_Q0_TO_J ? ACT_INIT : ACT_SWEEP;
+  return which == MV_Q1_TO_J ? ACT_INIT : ACT_SWEEP;
 }
 
 __device__ inline size_t piv_off(const Tree &t, int l) {
@@ -56,7 +58,7 @@ __global__ __launch_bounds__(NTHR) void k_mv_leaf(int which, int n, Tree tr,
   const int b = blockIdx.x, r0 = b * PANEL_M;
   const int m = min(PANEL_M, n - r0);
   double y[NS][4];
-  panel_load(y, io.Q + r0, n, m, kk);
+  panel_load(y, io.Q + r0, io.ld, m, kk);
   gepp_select_regs(y, m, kk, lbuf, shp, piv);
   __syncthreads();
   const int np = min(m, kk);
@@ -98,7 +100,7 @@ __global__ __launch_bounds__(NTHR) void k_mv_node(int which, int n, int lev,
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = lane + 64 * q;
-      y[sl][q] = (c < kk && i < mp) ? io.Q[clamp_row(rows[i], n) + (long)c * n] : 0.0;
+      y[sl][q] = (c < kk && i < mp) ? io.Q[clamp_row(rows[i], n) + (long)c * io.ld] : 0.0;
     }
   }
   gepp_select_regs(y, mp, kk, lbuf, shp, piv);
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(NTHR) void k_mv_inv(int which, int n, int force,
   const MvIO io = mv_io(which, s);
   for (int i = i0; i < kk; i += 4)
     for (int c = cl; c < w2; c += 64)
-      a[i][c] = (c < kk) ? io.Q[clamp_row(io.out[i], n) + (long)c * n]
+      a[i][c] = (c < kk) ? io.Q[clamp_row(io.out[i], n) + (long)c * io.ld]
                          : ((c - kk == i) ? 1.0 : 0.0);
   if (threadIdx.x < KMAX) used[threadIdx.x] = 0;
   __syncthreads();
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(NTHR) void k_mv_check(int which, int n, Solve2D *S)
 #pragma unroll
     for (int c = 0; c < KM; ++c) acc[c] = 0.0;
     for (int j = 0; j < kk; ++j) {
-      const double q = io.Q[row + (long)j * n];
+      const double q = io.Q[row + (long)j * io.ld];
 #pragma unroll
       for (int c = 0; c < KM; ++c) acc[c] += q * inv[j * KMAX + c];
     }
@@ -231,7 +233,8 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
   double *Bm = (double *)smem;                      // (KMAX+MV_CAND) x KMAX
   double *inv = Bm + (KMAX + MV_CAND) * KMAX;       // KMAX x KMAX
   double *prow = inv + KMAX * KMAX;                 // KMAX
-  double *pcol = prow + KMAX;                       // KMAX + MV_CAND
+  double *icol = prow + KMAX;                       // KMAX
+  double *pcol = icol + KMAX;                       // KMAX + MV_CAND
   int *rows = (int *)(pcol + KMAX + MV_CAND);       // KMAX + MV_CAND
   int *cnt = rows + KMAX + MV_CAND;                 // [0] count, [1] argmax, [2] swaps
   __shared__ double rv[4];
@@ -280,7 +283,7 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
     } else {
       v = 0.0;
       const int rr = clamp_row(rows[t], n);
-      for (int j = 0; j < kk; ++j) v += io.Q[rr + (long)j * n] * inv[j * KMAX + c];
+      for (int j = 0; j < kk; ++j) v += io.Q[rr + (long)j * io.ld] * inv[j * KMAX + c];
     }
     Bm[e] = v;
   }
@@ -314,10 +317,17 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
     for (int c = threadIdx.x; c < kk; c += NTHR)
       prow[c] = (Bm[ts * KMAX + c] - (c == cs ? 1.0 : 0.0)) / piv;
     for (int t = threadIdx.x; t < nr; t += NTHR) pcol[t] = Bm[t * KMAX + cs];
+    for (int i = threadIdx.x; i < kk; i += NTHR) icol[i] = inv[i * KMAX + cs];
     __syncthreads();
     for (int e = threadIdx.x; e < nrk; e += NTHR) {
       const int t = e >> 6, c = e & (KMAX - 1);
       if (c < kk) Bm[e] -= pcol[t] * prow[c];
+    }
+    // the same rank-1 update keeps Inv = Q[I,:]^-1 for the new rows:
+    // B = Q Inv, so Inv' = Inv - Inv[:, cs] prow gives B' = Q Inv'
+    for (int e = threadIdx.x; e < kk * KMAX; e += NTHR) {
+      const int i = e >> 6, c = e & (KMAX - 1);
+      if (c < kk) inv[e] -= icol[i] * prow[c];
     }
     if (threadIdx.x == 0) {
       io.out[cs] = gr;
@@ -325,9 +335,13 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
     }
     __syncthreads();
   }
+  const int swaps = cnt[2];
+  if (swaps > 0)
+    for (int i = threadIdx.x >> 6; i < kk; i += 4)
+      for (int c = threadIdx.x & 63; c < kk; c += 64) io.inv[i + c * KMAX] = inv[i * KMAX + c];
   if (threadIdx.x == 0) {
-    s.mv_swaps += cnt[2];
-    if (cnt[2] == 0) s.mv_done = 1;
+    s.mv_swaps += swaps;
+    if (swaps == 0) s.mv_done = 1;
   }
 }
 
@@ -351,8 +365,9 @@ void run_check(int which, int n, const Tree &tr, Solve2D *s, int ns,
 
 }  // namespace
 
-hipError_t launch_maxvol(int which, int n, const Tree &tr, Solve2D *s,
+hipError_t launch_maxvol(int which, int rows, const Tree &tr, Solve2D *s,
                          int nsolves, int kmax, hipStream_t st) {
+  const int n = rows;
   hipError_t e;
   if (kmax <= 16) e = run_tournament<4>(which, n, tr, s, nsolves, st);
   else if (kmax <= 32) e = run_tournament<8>(which, n, tr, s, nsolves, st);
@@ -360,7 +375,7 @@ hipError_t launch_maxvol(int which, int n, const Tree &tr, Solve2D *s,
   else e = run_tournament<16>(which, n, tr, s, nsolves, st);
   if (e != hipSuccess) return e;
   const size_t swap_lds = (size_t)(KMAX + MV_CAND) * KMAX * 8 + (size_t)KMAX * KMAX * 8 +
-                          (size_t)KMAX * 8 + (size_t)(KMAX + MV_CAND) * 8 +
+                          (size_t)2 * KMAX * 8 + (size_t)(KMAX + MV_CAND) * 8 +
                           (size_t)(KMAX + MV_CAND) * 4 + 16;
   static bool attr = false;
   if (!attr) {
@@ -369,8 +384,10 @@ hipError_t launch_maxvol(int which, int n, const Tree &tr, Solve2D *s,
     if (e != hipSuccess) return e;
     attr = true;
   }
+  // one explicit inverse of the tournament's rows; the swap rounds keep it
+  // current with the rank-1 updates of their swaps
+  hipLaunchKernelGGL(k_mv_inv, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
   for (int round = 0; round < MV_ROUNDS; ++round) {
-    hipLaunchKernelGGL(k_mv_inv, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
     if (kmax <= 16) run_check<16>(which, n, tr, s, nsolves, st);
     else if (kmax <= 32) run_check<32>(which, n, tr, s, nsolves, st);
     else if (kmax <= 48) run_check<48>(which, n, tr, s, nsolves, st);
@@ -378,8 +395,6 @@ hipError_t launch_maxvol(int which, int n, const Tree &tr, Solve2D *s,
     hipLaunchKernelGGL(k_mv_swap, dim3(nsolves), dim3(NTHR), swap_lds, st, which,
                        n, tr.nb[0], s);
   }
-  // the last round may have swapped: refresh the inverse for the final rows
-  hipLaunchKernelGGL(k_mv_inv, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
   return hipGetLastError();
 }
 

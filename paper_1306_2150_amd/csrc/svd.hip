@@ -26,9 +26,13 @@ __device__ __forceinline__ double row_sum16(double v) {
   return v;
 }
 
-__global__ __launch_bounds__(NTHR) void k_core(Solve2D *S) {
+// phase ACT_SWEEP: K = InvC Rfin^T (the cross core); phase ACT_CORE (3D
+// path): K = Rfin^T, whose left singular vectors W are those of the Tucker
+// core unfolding that the preceding TSQR factored.
+__global__ __launch_bounds__(NTHR) void k_core(int phase, Solve2D *S) {
   Solve2D &s = S[blockIdx.x];
-  if (s.active != ACT_SWEEP) return;
+  if (s.active != phase) return;
+  const bool plain = phase == ACT_CORE;
   __shared__ double K[KMAX * LD];   // column c at K[c*LD + i]
   __shared__ double V[KMAX * LD];
   __shared__ double Rs[KMAX * LD];  // Rfin, then unused
@@ -40,7 +44,7 @@ __global__ __launch_bounds__(NTHR) void k_core(Solve2D *S) {
   // stage InvC (in V) and Rfin (in Rs); element e -> (e >> 6, e & 63)
   for (int j = threadIdx.x >> 6; j < kk; j += 4)
     for (int i = threadIdx.x & 63; i < kk; i += 64) {
-      V[j * LD + i] = s.InvC[i + j * KMAX];
+      V[j * LD + i] = plain ? (i == j ? 1.0 : 0.0) : s.InvC[i + j * KMAX];
       Rs[j * LD + i] = s.Rfin[i + j * KMAX];
     }
   __syncthreads();
@@ -128,9 +132,8 @@ __global__ __launch_bounds__(NTHR) void k_core(Solve2D *S) {
 
 }  // namespace
 
-hipError_t launch_core(int n, Solve2D *s, int nsolves, hipStream_t st) {
-  (void)n;
-  hipLaunchKernelGGL(k_core, dim3(nsolves), dim3(NTHR), 0, st, s);
+hipError_t launch_core(int phase, Solve2D *s, int nsolves, hipStream_t st) {
+  hipLaunchKernelGGL(k_core, dim3(nsolves), dim3(NTHR), 0, st, phase, s);
   return hipGetLastError();
 }
 

@@ -28,16 +28,19 @@ __device__ inline size_t hlev_off(const Tree &t, int l) {   // levels >= 1
 
 struct TsIO {
   const double *in;
+  long ldin;
   double *out;
+  long ldout;
 };
 __device__ inline TsIO ts_io(int which, const Solve2D &s) {
-  if (which == TS_C_TO_Q0) return {s.C, s.Q0};
-  if (which == TS_C_TO_Q1) return {s.C, s.Q1};
-  return {s.Vh, s.Q0};
+  if (which == TS_C_TO_Q0) return {s.C, s.ldc, s.Q0, s.ldu};
+  if (which == TS_C_TO_Q1) return {s.C, s.ldc, s.Q1, s.ldv};
+  if (which == TS_VH_TO_Q1) return {s.Vh, s.ldv, s.Q1, s.ldv};
+  return {s.C, s.ldc, nullptr, 0};   // TS_CORE: R only
 }
 
 __device__ inline int ts_phase(int which) {
-  return which == TS_VH_TO_Q0 ? ACT_INIT : ACT_SWEEP;
+  return which == TS_VH_TO_Q1 ? ACT_INIT : (which == TS_CORE ? ACT_CORE : ACT_SWEEP);
 }
 
 template <int NS>
@@ -54,9 +57,9 @@ __global__ __launch_bounds__(NTHR) void k_tsqr_leaf(int which, int n, Tree tr,
   const int mp = max(m, kk);
   const TsIO io = ts_io(which, s);
   double y[NS][4];
-  panel_load(y, io.in + r0, n, m, kk);
+  panel_load(y, io.in + r0, io.ldin, m, kk);
   hh_qr_regs(y, mp, kk, vbuf, taus);
-  panel_store(y, s.Hv + r0, n, m, kk);
+  panel_store(y, s.Hv + r0, s.ldc, m, kk);
   double *R = s.tree_R + lev_off(tr, 0, (size_t)KMAX * KMAX) + (size_t)b * KMAX * KMAX;
   double *Rf = (tr.nlev == 1) ? s.Rfin : nullptr;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -198,9 +201,9 @@ __global__ __launch_bounds__(NTHR) void k_tsqr_leaf_apply(int which, int n,
     }
   }
   const double *T = s.tree_tau + (size_t)b * KMAX;
-  hh_apply_regs(y, m, min(mp, kk), kk, s.Hv + r0, n, T);
+  hh_apply_regs(y, m, min(mp, kk), kk, s.Hv + r0, s.ldc, T);
   const TsIO io = ts_io(which, s);
-  panel_store(y, io.out + r0, n, m, kk);
+  panel_store(y, io.out + r0, io.ldout, m, kk);
 }
 
 template <int NS>
@@ -212,6 +215,7 @@ hipError_t run_tsqr(int which, int n, const Tree &tr, Solve2D *s, int ns,
   for (int l = 1; l < tr.nlev; ++l)
     hipLaunchKernelGGL((k_tsqr_node<NS>), dim3(tr.nb[l], ns), blk, 0, st, which, l,
                        tr, s);
+  if (which == TS_CORE) return hipGetLastError();   // R only
   for (int l = tr.nlev - 1; l >= 1; --l)
     hipLaunchKernelGGL((k_tsqr_node_apply<NS>), dim3(tr.nb[l], ns), blk, 0, st,
                        which, l, tr, s);
@@ -237,8 +241,9 @@ Tree make_tree(int n, int kmax) {
   return t;
 }
 
-hipError_t launch_tsqr(int which, int n, const Tree &tr, Solve2D *s,
+hipError_t launch_tsqr(int which, int rows, const Tree &tr, Solve2D *s,
                        int nsolves, int kmax, hipStream_t st) {
+  const int n = rows;
   if (kmax <= 16) return run_tsqr<4>(which, n, tr, s, nsolves, st);
   if (kmax <= 32) return run_tsqr<8>(which, n, tr, s, nsolves, st);
   if (kmax <= 48) return run_tsqr<12>(which, n, tr, s, nsolves, st);

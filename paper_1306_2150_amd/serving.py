@@ -18,17 +18,22 @@ from . import binding, inputs
 
 
 def prepare(requests, device="cuda"):
-    """Upload every request's RHS factors; returns a list of (U, V) tensors."""
+    """Upload every request's RHS: (U, V) for 2D, (U1, U2, U3, G) for 3D with
+    G as a Fortran-ordered flat tensor."""
     out = []
     for q in requests:
-        U, V = q.rhs()
-        out.append((binding.colmajor(U, device), binding.colmajor(V, device)))
+        f = q.rhs()
+        if q.dim == 2:
+            out.append((binding.colmajor(f[0], device), binding.colmajor(f[1], device)))
+        else:
+            out.append(tuple(binding.colmajor(u, device) for u in f[:3]) +
+                       (binding.fortran_core(f[3], device),))
     return out
 
 
 def run_stream(ctx: binding.Context, requests, factors, prec="auto",
                warmup: int = 0, time_scale: float = 1.0):
-    """Serve ``requests`` (2D) against the wall clock.
+    """Serve ``requests`` (2D and 3D) against the wall clock.
 
     Returns dict with latencies (s) of the measured requests (after
     ``warmup``), solves/s over the measured window and per-request records.
@@ -47,8 +52,12 @@ def run_stream(ctx: binding.Context, requests, factors, prec="auto",
         while nxt < n_req and requests[order[nxt]].arrival_s * time_scale <= now:
             i = order[nxt]
             q = requests[i]
-            U, V = factors[i]
-            ticket, outs = ctx.submit(U, V, q.eps, prec=prec)
+            if q.dim == 2:
+                U, V = factors[i]
+                ticket, outs = ctx.submit(U, V, q.eps, prec=prec)
+            else:
+                U1, U2, U3, G = factors[i]
+                ticket, outs = ctx.submit3d(U1, U2, U3, G, q.eps, prec=prec)
             pending[ticket] = (i, outs)
             nxt += 1
         if not pending:
@@ -68,7 +77,8 @@ def run_stream(ctx: binding.Context, requests, factors, prec="auto",
             status, ranks, info = r
             done[i] = dict(rid=i, arrival=requests[i].arrival_s * time_scale,
                            finish=tdone, latency=tdone - requests[i].arrival_s * time_scale,
-                           status=status, rank=ranks[0], sweeps=info["sweeps"],
+                           status=status, rank=ranks[0], ranks=tuple(ranks),
+                           sweeps=info["sweeps"], dim=requests[i].dim,
                            n=requests[i].n, r=requests[i].r, eps=requests[i].eps,
                            outs=outs)
     torch.cuda.synchronize()
@@ -87,5 +97,5 @@ def run_stream(ctx: binding.Context, requests, factors, prec="auto",
     )
 
 
-def default_stream(count: int, seed: int = 5000, dims=(2,)):
+def default_stream(count: int, seed: int = 5000, dims=(2, 3)):
     return inputs.serving_stream(count, 200.0, seed, dims=dims)

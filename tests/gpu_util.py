@@ -18,7 +18,7 @@ def ctx():
     from paper_1306_2150_amd import binding
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     if _CTX is None:
-        _CTX = binding.Context(0, workspace_bytes=24 << 30)
+        _CTX = binding.Context(0, workspace_bytes=48 << 30)
     return _CTX
 
 

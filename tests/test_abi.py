@@ -88,3 +88,25 @@ int main(void) {
             binding.LrpProblem2D.eps.offset, binding.LrpProblem2D.info.offset,
             binding.LrpRequest.eps.offset, binding.LrpRequest.Gx.offset]
     assert got == want
+
+
+def test_header_constants_match_binding():
+    src = open(HEADER).read()
+    defs = dict(re.findall(r"#define\s+(LRP_[A-Z0-9_]+)\s+(\d+)", src))
+    assert int(defs["LRP_MAX_N"]) == binding.MAX_N
+    assert int(defs["LRP_MAX_N3"]) == binding.MAX_N3
+    assert int(defs["LRP_MAX_RANK"]) == binding.MAX_RANK
+    codes = dict(re.findall(r"(LRP_E[A-Z]+|LRP_OK)\s*=\s*(-?\d+)", src))
+    for name, val in codes.items():
+        assert getattr(binding, name) == int(val), name
+
+
+def test_solve3d_null_context_rejected(lib):
+    P = ctypes.c_void_p
+    rank = (ctypes.c_int32 * 3)(2, 2, 2)
+    rmax = (ctypes.c_int32 * 3)(4, 4, 4)
+    out = (ctypes.c_int32 * 3)()
+    st = lib.lrpoisson_solve3d(None, 16, rank, P(1), P(1), P(1), 16, P(1), 1e-6,
+                               None, P(1), P(1), P(1), 16, P(1), rmax, out, None,
+                               None)
+    assert st == binding.LRP_EINVAL

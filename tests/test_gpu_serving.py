@@ -1,0 +1,131 @@
+"""GPU tests of the continuous-batching loop (lrp_submit / lrp_serve_step /
+lrp_poll): requests of mixed dimension, grid size, rank and tolerance are
+admitted while others run, share launches, and each result must equal the
+same request solved alone through the synchronous entry points (relative
+difference of the assembled solutions <= 1e-12) and match the oracle's full
+solution to 10 eps."""
+import numpy as np
+import pytest
+
+from oracle import metrics, poisson
+from paper_1306_2150_amd import binding, inputs
+
+from gpu_util import ctx, dev, host, log, rel
+
+pytestmark = pytest.mark.gpu
+
+MIX = [  # (dim, n, r, eps)
+    (2, 512, 12, 1e-8), (3, 48, 6, 1e-6), (2, 1024, 30, 1e-6), (2, 256, 4, 1e-8),
+    (3, 64, 10, 1e-8), (2, 512, 50, 1e-8), (3, 32, 4, 1e-6), (2, 1024, 8, 1e-8),
+    (3, 48, 12, 1e-8), (2, 256, 64, 1e-6), (3, 64, 5, 1e-6), (2, 512, 20, 1e-6),
+]
+
+
+def mix_requests():
+    return [inputs.Request(rid=i, arrival_s=0.0, dim=d, n=n, r=r, eps=e, seed=7000 + i)
+            for i, (d, n, r, e) in enumerate(MIX)]
+
+
+def assemble(dim, res):
+    if dim == 2:
+        Ux, Vx = res
+        return host(Ux) @ host(Vx).T
+    Xs, G = res
+    Us = [host(x) for x in Xs]
+    return poisson.tucker_full(np.asarray(host(G)), *Us)
+
+
+def served_result(dim, outs, ranks):
+    if dim == 2:
+        return (outs[0][:, :ranks[0]], outs[1][:, :ranks[0]])
+    R = ranks
+    G = outs[3][:R[0] * R[1] * R[2]].view(R[2], R[1], R[0]).permute(2, 1, 0)
+    return ([outs[d][:, :R[d]] for d in range(3)], G)
+
+
+def serve_all(reqs, facs, prec, per_tick):
+    c = ctx()
+    pending, done = {}, {}
+    nxt, ticks = 0, 0
+    while nxt < len(reqs) or pending:
+        for _ in range(per_tick):
+            if nxt < len(reqs):
+                q = reqs[nxt]
+                if q.dim == 2:
+                    t, outs = c.submit(facs[nxt][0], facs[nxt][1], q.eps, prec=prec)
+                else:
+                    t, outs = c.submit3d(*facs[nxt], q.eps, prec=prec)
+                pending[t] = (nxt, outs)
+                nxt += 1
+        c.serve_step()
+        ticks += 1
+        assert ticks < 1000
+        for t in list(pending):
+            r = c.poll(t)
+            if r is not None:
+                i, outs = pending.pop(t)
+                done[i] = (r, outs)
+    return done, ticks
+
+
+@pytest.mark.parametrize("prec", ["fp64", "auto"])
+def test_served_equals_alone(prec):
+    from paper_1306_2150_amd import serving
+    reqs = mix_requests()
+    facs = serving.prepare(reqs)
+    log("serve mix", prec, len(reqs))
+    done, ticks = serve_all(reqs, facs, prec, per_tick=2)
+    log("  ticks", ticks)
+    c = ctx()
+    nbit = 0
+    for i, q in enumerate(reqs):
+        (status, ranks, info), outs = done[i]
+        assert status == binding.LRP_OK, (i, status)
+        mine = assemble(q.dim, served_result(q.dim, outs, ranks))
+        if q.dim == 2:
+            Ux, Vx, _ = c.solve2d(facs[i][0], facs[i][1], q.eps, prec=prec)
+            alone = assemble(2, (Ux, Vx))
+            U, V = q.rhs()
+            full = poisson.full_solve2d_factors(U, V)
+        else:
+            Xs, G, _ = c.solve3d(*facs[i], q.eps, prec=prec)
+            alone = assemble(3, (Xs, G))
+            U1, U2, U3, G0 = q.rhs()
+            full = poisson.full_solve3d_tucker(U1, U2, U3, np.asarray(G0))
+        d = rel(mine, alone)
+        nbit += int(np.array_equal(mine, alone))
+        e = rel(mine, full)
+        log("  req", i, q.dim, q.n, q.r, q.eps, "ranks", ranks, "alone diff", d, "err", e)
+        assert d <= 1e-12, (i, d)
+        assert e <= 10 * q.eps, (i, e)
+    log("  bitwise equal:", nbit, "of", len(reqs))
+
+
+def test_served_errors_do_not_disturb_others():
+    reqs = mix_requests()[:4]
+    from paper_1306_2150_amd import serving
+    facs = serving.prepare(reqs)
+    log("serve errors")
+    c = ctx()
+    # a NaN right-hand side and a zero-rank 3D request among good ones
+    bad = dev(np.full((512, 3), np.nan))
+    tb, _ = c.submit(bad, bad, 1e-8)
+    z = dev(np.zeros((48, 0)))
+    tz, _ = c.submit3d(z, z, z, binding.fortran_core(np.zeros((0, 0, 0))), 1e-6)
+    done, _ = serve_all(reqs, facs, "fp64", per_tick=4)
+    res = {}
+    for _ in range(50):
+        for t in (tb, tz):
+            if t not in res:
+                r = c.poll(t)
+                if r is not None:
+                    res[t] = r
+        if len(res) == 2:
+            break
+        c.serve_step()
+    assert res[tb][0] == binding.LRP_ENONFINITE
+    assert res[tz][0] == binding.LRP_OK and res[tz][1] == [0, 0, 0]
+    for i in range(len(reqs)):
+        assert done[i][0][0] == binding.LRP_OK
+    with pytest.raises(binding.LrpError):
+        c.submit(bad, bad, 0.0)

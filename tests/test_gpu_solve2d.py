@@ -195,7 +195,8 @@ def test_solve2d_batch_same_as_alone():
 
 
 @pytest.mark.parametrize("prec,eps,bar", [("fp32", 1e-7, 1e-6), ("auto", 1e-8, 1e-7),
-                                          ("auto", 1e-6, 1e-5), ("bf16x3", 1e-5, 1e-4)])
+                                          ("auto", 1e-7, 1e-6), ("auto", 1e-6, 1e-5),
+                                          ("bf16x3", 1e-5, 1e-4)])
 def test_solve2d_mixed_precision(prec, eps, bar):
     log("solve2d mixed", prec, eps)
     U, V = inputs.workload_rhs(2, 1, n=4096)
