@@ -171,7 +171,9 @@ def main():
                                      "3D n in 128..512, r 4..64, eps 1e-6/1e-8",
                            "p50_ms": sv["auto"]["p50_ms"], "p99_ms": sv["auto"]["p99_ms"],
                            "solves_per_s": sv["auto"]["solves_per_s"],
-                           "fp64": {k: sv["fp64"][k] for k in ("p50_ms", "p99_ms", "solves_per_s")},
+                           "by_dim": sv["auto"]["by_dim"],
+                           "fp64": {k: sv["fp64"][k] for k in ("p50_ms", "p99_ms", "solves_per_s",
+                                                                "by_dim")},
                            "requests": args.serve_requests, "warmup": args.serve_warmup}
 
     if not args.no_cpu:

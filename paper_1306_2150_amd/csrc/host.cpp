@@ -211,7 +211,7 @@ lrp_status Group2D::init() {
   talloc_ = make_tree(std::max(n_, m_), KMAX);
   const Layout L = slot_layout(n_, m_, talloc_);
   per_slot_ = L.total;
-  cols_cap_ = cap_ * 2 * KMAX;
+  cols_cap_ = cap_ * 4 * KMAX;   // forward and inverse columns of one tick
   partial_elems_ = dst_partial_elems(n_, std::min(cols_cap_, 4 * KMAX));
   const size_t solves_b = ((size_t)cap_ * sizeof(Solve2D) + 255) & ~(size_t)255;
   const size_t cols_b = ((size_t)cols_cap_ * sizeof(DstCol) + 255) & ~(size_t)255;
@@ -352,12 +352,17 @@ lrp_status Group2D::dst_cols(std::vector<DstCol> &cols, int prec, hipStream_t st
   size_t done = 0;
   while (done < cols.size()) {
     const int cnt = (int)std::min(cols.size() - done, (size_t)cols_cap_);
-    // the staging buffer is reused: wait for the previous launch's copy
-    HIPCHK(hipStreamSynchronize(st));
-    std::memcpy(h_cols_, cols.data() + done, sizeof(DstCol) * cnt);
-    HIPCHK(hipMemcpyAsync(d_cols_, h_cols_, sizeof(DstCol) * cnt, hipMemcpyHostToDevice, st));
-    HIPCHK(timed_dst(ctx_, prec, n_, tabs_->tab, d_cols_, cnt, d_s_, d_partial_,
+    // the staging ring is reused only after the stream drained it
+    if (cols_used_ + cnt > cols_cap_) {
+      HIPCHK(hipStreamSynchronize(st));
+      cols_used_ = 0;
+    }
+    DstCol *h = h_cols_ + cols_used_, *d = d_cols_ + cols_used_;
+    std::memcpy(h, cols.data() + done, sizeof(DstCol) * cnt);
+    HIPCHK(hipMemcpyAsync(d, h, sizeof(DstCol) * cnt, hipMemcpyHostToDevice, st));
+    HIPCHK(timed_dst(ctx_, prec, n_, tabs_->tab, d, cnt, d_s_, d_partial_,
                      partial_elems_, st));
+    cols_used_ += cnt;
     done += cnt;
   }
   return LRP_OK;
@@ -608,6 +613,7 @@ lrp_status lrpoisson_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t count,
     slot = std::move(g);
   }
   Group2D &g = *slot;
+  g.begin_batch();
   std::vector<int> all;
   for (int i = 0; i < g.cap(); ++i) {
     if (i < count) {

@@ -1,6 +1,7 @@
 // Host-side runtime of the solver: context, per-grid tables, slot groups.
 #pragma once
 
+#include <array>
 #include <deque>
 #include <map>
 #include <memory>
@@ -10,6 +11,15 @@
 #include "lrp_internal.h"
 
 namespace lrp {
+
+// Serving-loop bookkeeping of one slot group (see serve.cpp).
+struct ServeInfo {
+  bool inflight = false;           // launches enqueued, completion not yet seen
+  std::vector<int> retiring;       // finished slots whose results are in flight
+  std::vector<uint64_t> ticket;    // request of each slot, 0 = free
+  std::vector<lrp_info> result;    // report of each retiring slot
+  std::vector<std::array<int32_t, 3>> ranks;
+};
 
 // Sine-transform tables and eigenvalues of one grid size n (device memory).
 struct GridTables {
@@ -56,6 +66,9 @@ class Group2D {
   // Inverse transform of the listed finished slots.
   lrp_status inverse(const std::vector<int> &slots, hipStream_t st);
 
+  // Start of a batch of launches on an idle stream: the transform-column
+  // staging ring may be reused from its start.
+  void begin_batch() { cols_used_ = 0; }
   // Sine transform of arbitrary columns; a column's `solve` index names a
   // slot of this group whose non-finite flag it sets.
   lrp_status transform(std::vector<DstCol> &cols, int prec, hipStream_t st) {
@@ -68,6 +81,7 @@ class Group2D {
   hipStream_t stream();
   const Plan &plan(int i) const { return plans_[i]; }
   std::vector<int> free_slots;
+  ServeInfo serve;
 
  private:
   lrp_status dst_cols(std::vector<DstCol> &cols, int prec, hipStream_t st);
@@ -79,7 +93,7 @@ class Group2D {
   char *ws_ = nullptr;
   Solve2D *d_s_ = nullptr, *h_s_ = nullptr;
   DstCol *d_cols_ = nullptr, *h_cols_ = nullptr;
-  int cols_cap_ = 0;
+  int cols_cap_ = 0, cols_used_ = 0;
   double *d_partial_ = nullptr;
   size_t partial_elems_ = 0;
   std::vector<Plan> plans_;
@@ -114,7 +128,9 @@ class Group3D {
   const Plan &plan(int i) const { return plans_[i]; }
   Group2D &modes() { return *inner_; }
   hipStream_t stream() { return inner_->stream(); }
+  void begin_batch() { inner_->begin_batch(); }
   std::vector<int> free_slots;
+  ServeInfo serve;
 
  private:
   struct IO {

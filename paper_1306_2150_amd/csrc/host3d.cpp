@@ -275,6 +275,7 @@ extern "C" lrp_status lrpoisson_solve3d(lrp_ctx *ctx, int64_t n, const int32_t r
     slot = std::move(g);
   }
   Group3D &g = *slot;
+  g.begin_batch();
   const Plan plan = make_plan(opts, eps, (int)n);
   const int r[3] = {rank[0], rank[1], rank[2]};
   const int rm[3] = {rmax[0], rmax[1], rmax[2]};

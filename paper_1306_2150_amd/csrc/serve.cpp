@@ -3,19 +3,23 @@
 // Requests wait in a FIFO until the group of their dimension and grid size
 // has a free slot (groups are created on demand inside the context's
 // device-memory budget, which is the admission limit; a 3D group holds as
-// many slots as fit a fixed share of it).  One tick (lrp_serve_step):
-//   1. admit: fill free slots, upload their state, forward transforms of all
-//      newly admitted requests (one launch per group and precision; 3D also
-//      forms its mode-unfolding factors);
-//   2. advance: for every group with work, on the group's own stream, one
-//      launch sequence that runs the initial column choice of the new slots
-//      and one cross sweep of every running slot -- requests admitted at
-//      different ticks share launches; 3D solves whose three mode crosses
-//      finished also get their core and its rounding in the same tick;
-//   3. retire: inverse transforms of the slots that finished, results
-//      recorded, slots freed for the next tick.
+// many slots as fit a fixed share of it).  Every group advances on its own
+// stream and at its own pace: lrp_serve_step never waits for the device.
+// For each group whose previously enqueued work has completed (a stream
+// query), one call
+//   1. reports the requests whose inverse transforms were in that work and
+//      frees their slots;
+//   2. reads the slot states fetched by that work: slots that finished get
+//      their inverse transforms (3D: of the three output factors);
+//   3. admits queued requests of the group into free slots (upload, forward
+//      transforms; 3D also forms its mode-unfolding factors);
+//   4. enqueues one step of every running slot -- the initial column choice
+//      of new slots and one cross sweep of the others, requests admitted at
+//      different times sharing every launch; 3D solves whose mode crosses
+//      finished also get their core and its rounding -- and the copy of the
+//      slot states back to the host.
+// A slow group (a large 3D grid) therefore never holds back a fast one.
 #include <algorithm>
-#include <chrono>
 #include <cstring>
 
 #include "host.h"
@@ -24,8 +28,7 @@ using namespace lrp;
 
 namespace {
 
-constexpr int SERVE_SLOTS = 32;   // slots per grid-size group
-
+constexpr int SERVE_SLOTS = 32;                      // slots per 2D group
 constexpr size_t SERVE3_SHARE = (size_t)16 << 30;   // bytes per 3D group
 
 lrp_status check_request(const lrp_request &q) {
@@ -53,6 +56,9 @@ Group2D *serve_group(lrp_ctx *ctx, int n, lrp_status *err) {
       ctx->serve_groups.erase(n);
       return nullptr;
     }
+    ng->serve.ticket.assign(ng->cap(), 0);
+    ng->serve.result.resize(ng->cap());
+    ng->serve.ranks.resize(ng->cap());
     g = std::move(ng);
   }
   return g.get();
@@ -70,6 +76,9 @@ Group3D *serve_group3(lrp_ctx *ctx, int n, lrp_status *err) {
       ctx->serve3_groups.erase(n);
       return nullptr;
     }
+    ng->serve.ticket.assign(ng->cap(), 0);
+    ng->serve.result.resize(ng->cap());
+    ng->serve.ranks.resize(ng->cap());
     g = std::move(ng);
   }
   return g.get();
@@ -78,6 +87,206 @@ Group3D *serve_group3(lrp_ctx *ctx, int n, lrp_status *err) {
 // A request that needs no device work (a zero Tucker rank): done at once.
 bool trivially_done(const lrp_request &q) {
   return q.dim == 3 && (q.rank[0] == 0 || q.rank[1] == 0 || q.rank[2] == 0);
+}
+
+Plan request_plan(const lrp_request &q) {
+  lrp_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.prec = q.prec;
+  return make_plan(&o, q.eps, (int)q.n);
+}
+
+void finish_request(lrp_ctx *ctx, uint64_t t, const lrp_info &info,
+                    const int32_t rank_out[3]) {
+  auto it = ctx->running.find(t);
+  if (it == ctx->running.end()) return;
+  ServeReq r = it->second;
+  ctx->running.erase(it);
+  r.state = 2;
+  r.status = info.status;
+  r.info = info;
+  for (int d = 0; d < 3; ++d) r.rank_out[d] = rank_out[d];
+  ctx->finished[t] = r;
+}
+
+// Has the group's previously enqueued work completed?  False while it runs
+// (or on a device error, then *err is set).
+bool group_idle(ServeInfo &sv, hipStream_t st, lrp_status *err) {
+  *err = LRP_OK;
+  if (!sv.inflight) return true;
+  const hipError_t q = hipStreamQuery(st);
+  if (q == hipErrorNotReady) return false;
+  if (q != hipSuccess) {
+    *err = LRP_EDEVICE;
+    return false;
+  }
+  sv.inflight = false;
+  return true;
+}
+
+// Moves the queued requests that `admit` takes (in arrival order) to the
+// running set.
+template <class Admit>
+lrp_status admit_queued(lrp_ctx *ctx, Admit admit) {
+  for (auto it = ctx->queue.begin(); it != ctx->queue.end();) {
+    int taken = 0;
+    lrp_status e = admit(*it, &taken);
+    if (e != LRP_OK) return e;
+    if (taken < 0) break;   // group full
+    if (taken) {
+      ctx->running[it->ticket] = *it;
+      it = ctx->queue.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  return LRP_OK;
+}
+
+lrp_status tick2d(lrp_ctx *ctx, Group2D *g) {
+  lrp_status e;
+  ServeInfo &sv = g->serve;
+  hipStream_t st = g->stream();
+  if (!st) return LRP_EDEVICE;
+  if (!group_idle(sv, st, &e)) return e;
+  g->begin_batch();
+  // 1. report what the completed work finished
+  for (int slot : sv.retiring) {
+    finish_request(ctx, sv.ticket[slot], sv.result[slot], sv.ranks[slot].data());
+    sv.ticket[slot] = 0;
+    g->free_slots.push_back(slot);
+  }
+  sv.retiring.clear();
+  // 2. slots that finished: their reports (the state copy of the next step
+  // overwrites the host mirror) and inverse transforms
+  std::vector<int> inv;
+  for (int slot = 0; slot < g->cap(); ++slot) {
+    if (!sv.ticket[slot]) continue;
+    const Solve2D &s = g->host(slot);
+    if (s.active != ACT_DONE) continue;
+    lrp_info &info = sv.result[slot];
+    std::memset(&info, 0, sizeof(info));
+    info.status = s.status;
+    info.sweeps = s.sweep;
+    info.k = s.k;
+    info.rank = s.R;
+    info.fwd_prec = g->plan(slot).fwd_prec;
+    info.inv_prec = g->plan(slot).inv_prec;
+    info.change = s.change;
+    if (s.status == LRP_ENONFINITE || s.r == 0) {
+      info.rank = 0;
+    } else if (s.R > s.rmax) {
+      info.status = LRP_ERANKCAP;
+    } else {
+      inv.push_back(slot);
+    }
+    sv.ranks[slot] = {info.rank, 0, 0};
+    sv.retiring.push_back(slot);
+  }
+  bool launched = false;
+  if (!inv.empty()) {
+    if ((e = g->inverse(inv, st)) != LRP_OK) return e;
+    launched = true;
+  }
+  // 3. admission
+  std::vector<int> fresh;
+  const int64_t n = g->n();
+  e = admit_queued(ctx, [&](ServeReq &r, int *taken) -> lrp_status {
+    const lrp_request &q = r.req;
+    if (q.dim != 2 || q.n != n) return LRP_OK;
+    if (g->free_slots.empty()) {
+      *taken = -1;
+      return LRP_OK;
+    }
+    const int slot = g->free_slots.back();
+    g->free_slots.pop_back();
+    g->setup_slot(slot, q.U[0], q.U[1], q.ld, q.rank[0], q.eps, q.X[0], q.X[1], q.ldx,
+                  q.rmax[0], request_plan(q));
+    lrp_status ee = g->upload_slot(slot, st);
+    if (ee != LRP_OK) return ee;
+    fresh.push_back(slot);
+    r.state = 1;
+    r.group = g;
+    r.group3 = nullptr;
+    r.group_slot = slot;
+    sv.ticket[slot] = r.ticket;
+    *taken = 1;
+    return LRP_OK;
+  });
+  if (e != LRP_OK) return e;
+  if (!fresh.empty() && (e = g->forward(fresh, st)) != LRP_OK) return e;
+  // 4. one step of every running slot and the state copy back
+  bool live = false;
+  for (int slot = 0; slot < g->cap(); ++slot)
+    live |= sv.ticket[slot] && g->host(slot).active != ACT_DONE;
+  if (live) {
+    if ((e = g->step(st)) != LRP_OK) return e;
+    if ((e = g->fetch(st, false)) != LRP_OK) return e;
+    launched = true;
+  }
+  sv.inflight = launched || !sv.retiring.empty();
+  return LRP_OK;
+}
+
+lrp_status tick3d(lrp_ctx *ctx, Group3D *g) {
+  lrp_status e;
+  ServeInfo &sv = g->serve;
+  hipStream_t st = g->stream();
+  if (!st) return LRP_EDEVICE;
+  if (!group_idle(sv, st, &e)) return e;
+  g->begin_batch();
+  for (int slot : sv.retiring) {
+    finish_request(ctx, sv.ticket[slot], sv.result[slot], sv.ranks[slot].data());
+    sv.ticket[slot] = 0;
+    g->host(slot).phase = P3_IDLE;
+    g->free_slots.push_back(slot);
+  }
+  sv.retiring.clear();
+  for (int slot = 0; slot < g->cap(); ++slot) {
+    if (!sv.ticket[slot] || g->host(slot).phase != P3_DONE) continue;
+    fill_info3d(*g, slot, sv.ranks[slot].data(), &sv.result[slot]);
+    sv.retiring.push_back(slot);
+  }
+  bool launched = false;
+  if (!sv.retiring.empty()) {
+    if ((e = g->finish(sv.retiring, st)) != LRP_OK) return e;
+    launched = true;
+  }
+  std::vector<int> fresh;
+  const int64_t n = g->n();
+  e = admit_queued(ctx, [&](ServeReq &r, int *taken) -> lrp_status {
+    const lrp_request &q = r.req;
+    if (q.dim != 3 || q.n != n) return LRP_OK;
+    if (g->free_slots.empty()) {
+      *taken = -1;
+      return LRP_OK;
+    }
+    const int slot = g->free_slots.back();
+    g->free_slots.pop_back();
+    const int rk[3] = {q.rank[0], q.rank[1], q.rank[2]};
+    const int rm[3] = {q.rmax[0], q.rmax[1], q.rmax[2]};
+    g->setup_slot(slot, q.U, q.ld, rk, q.G, q.eps, q.X, q.ldx, q.Gx, rm, request_plan(q));
+    fresh.push_back(slot);
+    r.state = 1;
+    r.group = nullptr;
+    r.group3 = g;
+    r.group_slot = slot;
+    sv.ticket[slot] = r.ticket;
+    *taken = 1;
+    return LRP_OK;
+  });
+  if (e != LRP_OK) return e;
+  if (!fresh.empty() && (e = g->start(fresh, st)) != LRP_OK) return e;
+  bool live = false;
+  for (int slot = 0; slot < g->cap(); ++slot)
+    live |= sv.ticket[slot] && g->host(slot).phase != P3_DONE && g->host(slot).phase != P3_IDLE;
+  if (live) {
+    if ((e = g->step(st)) != LRP_OK) return e;
+    if ((e = g->fetch(st, false)) != LRP_OK) return e;
+    launched = true;
+  }
+  sv.inflight = launched || !sv.retiring.empty();
+  return LRP_OK;
 }
 
 }  // namespace
@@ -98,7 +307,14 @@ lrp_status lrp_submit(lrp_ctx *ctx, const lrp_request *req, uint64_t *ticket) {
   r.group = nullptr;
   r.group3 = nullptr;
   r.status = LRP_ENOTREADY;
-  ctx->queue.push_back(r);
+  if (trivially_done(*req)) {
+    r.state = 2;
+    r.status = LRP_OK;
+    r.info.change = -1.0;
+    ctx->finished[r.ticket] = r;
+  } else {
+    ctx->queue.push_back(r);
+  }
   *ticket = r.ticket;
   return LRP_OK;
 }
@@ -108,146 +324,19 @@ lrp_status lrp_serve_step(lrp_ctx *ctx, int32_t *pending) {
   if (hipSetDevice(ctx->device) != hipSuccess) return LRP_EDEVICE;
   std::lock_guard<std::mutex> lock(ctx->mu);
   lrp_status e;
-  // 1. admission (FIFO per group: a request waits only for its own group)
-  std::map<Group2D *, std::vector<int>> fresh;
-  std::map<Group3D *, std::vector<int>> fresh3;
-  for (auto it = ctx->queue.begin(); it != ctx->queue.end();) {
-    const lrp_request &q = it->req;
-    ServeReq r = *it;
-    lrp_opts o;
-    std::memset(&o, 0, sizeof(o));
-    o.prec = q.prec;
-    const Plan plan = make_plan(&o, q.eps, (int)q.n);
-    if (trivially_done(q)) {
-      r.state = 2;
-      r.status = LRP_OK;
-      std::memset(&r.info, 0, sizeof(r.info));
-      r.info.change = -1.0;
-      ctx->finished[r.ticket] = r;
-      it = ctx->queue.erase(it);
-      continue;
+  // groups for queued requests are created on first use; a group that does
+  // not fit the budget yet leaves its requests queued
+  for (const auto &q : ctx->queue) {
+    if (q.req.dim == 3) {
+      if (!ctx->serve3_groups.count((int)q.req.n)) serve_group3(ctx, (int)q.req.n, &e);
+    } else if (!ctx->serve_groups.count((int)q.req.n)) {
+      serve_group(ctx, (int)q.req.n, &e);
     }
-    if (q.dim == 3) {
-      Group3D *g = serve_group3(ctx, (int)q.n, &e);
-      if (!g || g->free_slots.empty()) {
-        ++it;
-        continue;
-      }
-      const int slot = g->free_slots.back();
-      g->free_slots.pop_back();
-      const int rk[3] = {q.rank[0], q.rank[1], q.rank[2]};
-      const int rm[3] = {q.rmax[0], q.rmax[1], q.rmax[2]};
-      g->setup_slot(slot, q.U, q.ld, rk, q.G, q.eps, q.X, q.ldx, q.Gx, rm, plan);
-      fresh3[g].push_back(slot);
-      r.group3 = g;
-      r.group = nullptr;
-      r.group_slot = slot;
-    } else {
-      Group2D *g = serve_group(ctx, (int)q.n, &e);
-      if (!g || g->free_slots.empty()) {
-        ++it;
-        continue;
-      }
-      const int slot = g->free_slots.back();
-      g->free_slots.pop_back();
-      g->setup_slot(slot, q.U[0], q.U[1], q.ld, q.rank[0], q.eps, q.X[0], q.X[1],
-                    q.ldx, q.rmax[0], plan);
-      if (!g->stream()) return LRP_EDEVICE;
-      if ((e = g->upload_slot(slot, g->stream())) != LRP_OK) return e;
-      fresh[g].push_back(slot);
-      r.group = g;
-      r.group3 = nullptr;
-      r.group_slot = slot;
-    }
-    r.state = 1;
-    ctx->running[r.ticket] = r;
-    it = ctx->queue.erase(it);
   }
-  // 2. every group with live slots, on its own stream so that the groups'
-  // latency-bound launches overlap on the device
-  std::vector<Group2D *> live;
-  for (auto &kv : ctx->serve_groups) {
-    Group2D *g = kv.second.get();
-    if ((int)g->free_slots.size() < g->cap()) live.push_back(g);
-  }
-  std::vector<Group3D *> live3;
-  for (auto &kv : ctx->serve3_groups) {
-    Group3D *g = kv.second.get();
-    if ((int)g->free_slots.size() < g->cap()) live3.push_back(g);
-  }
-  for (Group2D *g : live) {
-    auto it = fresh.find(g);
-    if (it != fresh.end() && (e = g->forward(it->second, g->stream())) != LRP_OK) return e;
-    if ((e = g->step(g->stream())) != LRP_OK) return e;
-    if ((e = g->fetch(g->stream(), false)) != LRP_OK) return e;
-  }
-  for (Group3D *g : live3) {
-    if (!g->stream()) return LRP_EDEVICE;
-    auto it = fresh3.find(g);
-    if (it != fresh3.end() && (e = g->start(it->second, g->stream())) != LRP_OK) return e;
-    if ((e = g->step(g->stream())) != LRP_OK) return e;
-    if ((e = g->fetch(g->stream(), false)) != LRP_OK) return e;
-  }
-  for (Group2D *g : live)
-    if (hipStreamSynchronize(g->stream()) != hipSuccess) return LRP_EDEVICE;
-  for (Group3D *g : live3)
-    if (hipStreamSynchronize(g->stream()) != hipSuccess) return LRP_EDEVICE;
-  // 3. retirement
-  std::map<Group2D *, std::vector<int>> done;
-  std::map<Group3D *, std::vector<int>> done3;
-  std::vector<uint64_t> finished;
-  for (auto &kv : ctx->running) {
-    ServeReq &r = kv.second;
-    if (r.group3) {
-      if (r.group3->host(r.group_slot).phase != P3_DONE) continue;
-      done3[r.group3].push_back(r.group_slot);
-      finished.push_back(kv.first);
-      continue;
-    }
-    Solve2D &s = r.group->host(r.group_slot);
-    if (s.active != ACT_DONE) continue;
-    if (s.status == LRP_ENONFINITE || s.r == 0) {
-      s.R = 0;
-    } else if (s.R > s.rmax) {
-      s.status = LRP_ERANKCAP;
-    } else {
-      done[r.group].push_back(r.group_slot);
-    }
-    finished.push_back(kv.first);
-  }
-  for (auto &kv : done)
-    if ((e = kv.first->inverse(kv.second, kv.first->stream())) != LRP_OK) return e;
-  for (auto &kv : done3)
-    if ((e = kv.first->finish(kv.second, kv.first->stream())) != LRP_OK) return e;
-  for (auto &kv : done)
-    if (hipStreamSynchronize(kv.first->stream()) != hipSuccess) return LRP_EDEVICE;
-  for (auto &kv : done3)
-    if (hipStreamSynchronize(kv.first->stream()) != hipSuccess) return LRP_EDEVICE;
-  for (uint64_t t : finished) {
-    ServeReq r = ctx->running[t];
-    ctx->running.erase(t);
-    r.state = 2;
-    if (r.group3) {
-      Group3D *g = r.group3;
-      fill_info3d(*g, r.group_slot, r.rank_out, &r.info);
-      r.status = r.info.status;
-      g->host(r.group_slot).phase = P3_IDLE;
-      g->free_slots.push_back(r.group_slot);
-    } else {
-      Solve2D &s = r.group->host(r.group_slot);
-      r.status = s.status;
-      r.rank_out[0] = s.R;
-      r.info.status = s.status;
-      r.info.sweeps = s.sweep;
-      r.info.k = s.k;
-      r.info.rank = s.R;
-      r.info.fwd_prec = r.group->plan(r.group_slot).fwd_prec;
-      r.info.inv_prec = r.group->plan(r.group_slot).inv_prec;
-      r.info.change = s.change;
-      r.group->free_slots.push_back(r.group_slot);
-    }
-    ctx->finished[t] = r;
-  }
+  for (auto &kv : ctx->serve_groups)
+    if ((e = tick2d(ctx, kv.second.get())) != LRP_OK) return e;
+  for (auto &kv : ctx->serve3_groups)
+    if ((e = tick3d(ctx, kv.second.get())) != LRP_OK) return e;
   if (pending) *pending = (int32_t)(ctx->queue.size() + ctx->running.size());
   return LRP_OK;
 }

@@ -1,10 +1,10 @@
 """Drive the library's continuous-batching request loop with a timed stream.
 
 Requests arrive on a wall clock (Poisson arrivals from
-``inputs.serving_stream``); each tick submits every request whose arrival
-time has passed, runs one scheduling tick of the library
-(``lrp_serve_step``: admit into free slots, one cross sweep of every running
-solve, retire finished ones) and polls the outstanding tickets.  Latency is
+``inputs.serving_stream``); each pass submits every request whose arrival
+time has passed, calls the library's non-blocking scheduling step
+(``lrp_serve_step``: every group whose previous work completed retires,
+admits and enqueues its next sweep) and polls the outstanding tickets.  Latency is
 completion time minus arrival time.  The right-hand sides are uploaded to the
 device before the clock starts (factors resident on the device).
 """
@@ -86,7 +86,14 @@ def run_stream(ctx: binding.Context, requests, factors, prec="auto",
     lat = np.array([d["latency"] for d in meas])
     t_first = min(d["arrival"] for d in meas)
     t_last = max(d["finish"] for d in meas)
+    by_dim = {}
+    for dim in sorted(set(d["dim"] for d in meas)):
+        ld = np.array([d["latency"] for d in meas if d["dim"] == dim])
+        by_dim[f"{dim}d"] = dict(count=int(ld.size),
+                                 p50_ms=float(np.percentile(ld, 50) * 1e3),
+                                 p99_ms=float(np.percentile(ld, 99) * 1e3))
     return dict(
+        by_dim=by_dim,
         p50_ms=float(np.percentile(lat, 50) * 1e3),
         p99_ms=float(np.percentile(lat, 99) * 1e3),
         mean_ms=float(lat.mean() * 1e3),
