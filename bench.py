@@ -26,6 +26,10 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# The served stream runs one stream per slot group (up to eight groups); give
+# each its own hardware queue so that a long 3D launch never sits in front of
+# another group's short ones (HIP reads this when it initialises).
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15}
 METRIC = "2D n=4096 r=16 solves/s at rel err<=1e-7, mixed vs FP64 path; served p99 ms"

@@ -78,6 +78,11 @@ typedef enum {
  *  BF16X3  bfloat16 MFMA on a two-piece split of both operands, three
  *          products (hi*hi + hi*lo + lo*hi), float32 accumulation inside
  *          K blocks, float64 across blocks, both ways.
+ *  INT8    int8 MFMA on exact 7-bit integer slices of both operands (six
+ *          slices each, the products of slice levels <= 5, int32 sums,
+ *          float64 recombination: the error-free splitting of Ozaki et al.);
+ *          relative error ~1e-12 or below.  Grid sizes up to about 16000
+ *          (the sine record table lives in LDS); LRP_EINVAL beyond.
  *  AUTO    per-request plan from eps: forward transform BF16X3 when
  *          eps >= 1e-6, FP32 when eps >= 1e-7, else FP64; inverse transform
  *          FP32 when eps >= 1e-7, else FP64.  Every reduced-precision
@@ -91,7 +96,8 @@ typedef enum {
   LRP_PREC_FP64 = 0,
   LRP_PREC_AUTO = 1,
   LRP_PREC_FP32 = 2,
-  LRP_PREC_BF16X3 = 3
+  LRP_PREC_BF16X3 = 3,
+  LRP_PREC_INT8 = 4
 } lrp_precision;
 
 /* Optional knobs; pass NULL for defaults.  Zero fields take defaults. */

@@ -25,7 +25,7 @@ LRP_EDEVICE = -6
 LRP_EBUSY = -7
 LRP_ENOTREADY = -8
 
-PREC = {"fp64": 0, "auto": 1, "fp32": 2, "bf16x3": 3}
+PREC = {"fp64": 0, "auto": 1, "fp32": 2, "bf16x3": 3, "int8": 4}
 PREC_NAME = {v: k for k, v in PREC.items()}
 
 MAX_RANK = 64

@@ -306,7 +306,9 @@ __global__ __launch_bounds__(NTHR) void k_decide(Solve2D *S) {
   }
 }
 
-// Residual score of every column on the probe rows (rank growth).
+// Residual score of every column on the probe rows (rank growth); each
+// block reports its GROW_TOP best columns (score descending, ties: lower
+// column first; the current columns Jn score -1).
 template <int KM>
 __global__ __launch_bounds__(NTHR) void k_growth_score(Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
@@ -316,6 +318,9 @@ __global__ __launch_bounds__(NTHR) void k_growth_score(Solve2D *S) {
   __shared__ double uP[PQ * KMAX];
   __shared__ double aP[PQ * KMAX];
   __shared__ double lP[PQ];
+  __shared__ int jn[KMAX];
+  __shared__ double rv[4];
+  __shared__ int rk[4];
   const int kk = s.k, r = s.r, nq = min(s.kick, PQ);
   const long ldu = s.ldu, ldv = s.ldv;
   for (int e = threadIdx.x; e < nq * KMAX; e += NTHR) {
@@ -325,28 +330,50 @@ __global__ __launch_bounds__(NTHR) void k_growth_score(Solve2D *S) {
     aP[e] = (c < kk) ? s.A[p + (long)c * ldu] : 0.0;
   }
   for (int q = threadIdx.x; q < nq; q += NTHR) lP[q] = s.lam_r[clamp_row(s.probe[q], s.n)];
+  for (int t = threadIdx.x; t < kk; t += NTHR) jn[t] = s.Jn[t];
   __syncthreads();
   const int j = blockIdx.x * NTHR + threadIdx.x;
-  if (j >= s.m) return;
-  double num[PQ], skel[PQ];
+  double best = -2.0;   // past the end: never wins
+  if (j < s.m) {
+    double num[PQ], skel[PQ];
 #pragma unroll
-  for (int q = 0; q < PQ; ++q) num[q] = skel[q] = 0.0;
-  for (int c = 0; c < r; ++c) {
-    const double vc = s.Vh[j + (long)c * ldv];
+    for (int q = 0; q < PQ; ++q) num[q] = skel[q] = 0.0;
+    for (int c = 0; c < r; ++c) {
+      const double vc = s.Vh[j + (long)c * ldv];
 #pragma unroll
-    for (int q = 0; q < PQ; ++q) num[q] += uP[q * KMAX + c] * vc;
+      for (int q = 0; q < PQ; ++q) num[q] += uP[q * KMAX + c] * vc;
+    }
+    for (int c = 0; c < kk; ++c) {
+      const double bc = s.B[j + (long)c * ldv];
+#pragma unroll
+      for (int q = 0; q < PQ; ++q) skel[q] += aP[q * KMAX + c] * bc;
+    }
+    const double lj = s.lam_c[j];
+    best = 0.0;
+#pragma unroll
+    for (int q = 0; q < PQ; ++q)
+      if (q < nq) best = fmax(best, fabs(num[q] / (lP[q] + lj) - skel[q]));
+    for (int t = 0; t < kk; ++t)
+      if (jn[t] == j) best = -1.0;
   }
-  for (int c = 0; c < kk; ++c) {
-    const double bc = s.B[j + (long)c * ldv];
-#pragma unroll
-    for (int q = 0; q < PQ; ++q) skel[q] += aP[q * KMAX + c] * bc;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int t = 0; t < GROW_TOP; ++t) {
+    double v = best;
+    int key = (j < s.m) ? j : 0x7fffffff;
+    wave_argmax(v, key);
+    if (lane == 0) rv[wave] = v, rk[wave] = key;
+    __syncthreads();
+    double bv = rv[0];
+    int bk = rk[0];
+    for (int w = 1; w < 4; ++w)
+      if (rv[w] > bv || (rv[w] == bv && rk[w] < bk)) bv = rv[w], bk = rk[w];
+    if (threadIdx.x == 0) {
+      s.mv_val[(size_t)blockIdx.x * GROW_TOP + t] = bv;
+      s.mv_row[(size_t)blockIdx.x * GROW_TOP + t] = (bv > -1.5) ? bk : -1;
+    }
+    if (j == bk) best = -3.0;
+    __syncthreads();
   }
-  const double lj = s.lam_c[j];
-  double best = 0.0;
-#pragma unroll
-  for (int q = 0; q < PQ; ++q)
-    if (q < nq) best = fmax(best, fabs(num[q] / (lP[q] + lj) - skel[q]));
-  s.score[j] = best;
 }
 
 // Next column set and state swap (one workgroup / solve).
@@ -359,27 +386,33 @@ __global__ __launch_bounds__(NTHR) void k_finalize(Solve2D *S) {
   const int kk = s.k;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (s.next == NEXT_GROW) {
-    for (int t = threadIdx.x; t < kk; t += NTHR) s.score[clamp_row(s.Jn[t], m)] = -1.0;
-    __syncthreads();
+    // the kgrow best reported columns, picked in order (score descending,
+    // ties: lower column first): each pick is the best entry strictly after
+    // the previous one in that order
+    const int ntot = ceil_div(m, NTHR) * GROW_TOP;
+    double lastv = INFINITY;
+    int lastc = -1;
     for (int g = 0; g < s.kgrow; ++g) {
       double best = -2.0;
       int key = 0x7fffffff;
-      for (int j = threadIdx.x; j < m; j += NTHR) {
-        const double v = s.score[j];
-        if (v > best || (v == best && j < key)) best = v, key = j;
+      for (int e = threadIdx.x; e < ntot; e += NTHR) {
+        const int c = s.mv_row[e];
+        const double v = s.mv_val[e];
+        if (c < 0) continue;
+        if (v > lastv || (v == lastv && c <= lastc)) continue;
+        if (v > best || (v == best && c < key)) best = v, key = c;
       }
       wave_argmax(best, key);
       if (lane == 0) rv[wave] = best, rk[wave] = key;
       __syncthreads();
-      if (threadIdx.x == 0) {
-        double bv = rv[0];
-        int bk = rk[0];
-        for (int w = 1; w < 4; ++w)
-          if (rv[w] > bv || (rv[w] == bv && rk[w] < bk)) bv = rv[w], bk = rk[w];
-        s.J[kk + g] = bk;
-        s.score[bk] = -1.0;
-      }
+      double bv = rv[0];
+      int bk = rk[0];
+      for (int w = 1; w < 4; ++w)
+        if (rv[w] > bv || (rv[w] == bv && rk[w] < bk)) bv = rv[w], bk = rk[w];
       __syncthreads();
+      if (threadIdx.x == 0) s.J[kk + g] = clamp_row(bk, m);
+      lastv = bv;
+      lastc = bk;
     }
   }
   __syncthreads();
@@ -440,7 +473,7 @@ hipError_t launch_factors(int n, int m, Solve2D *s, int nsolves, int kmax,
   return hipGetLastError();
 }
 
-int change_blocks(int m) { return min(ceil_div(m, PANEL_M), 64); }
+int change_blocks(int m) { return min(ceil_div(m, PANEL_M), 256); }
 
 hipError_t launch_change(int n, int m, Solve2D *s, int nsolves, int kmax,
                          hipStream_t st) {

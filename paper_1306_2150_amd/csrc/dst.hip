@@ -17,6 +17,8 @@
 //   BF16X3  v_mfma_f32_16x16x32_bf16 on hi/lo bfloat16 splits of both
 //           operands, hi*hi + hi*lo + lo*hi, float32 inside 64-deep K runs,
 //           float64 across runs.
+//   INT8    v_mfma_i32_16x16x64_i8 on exact 7-bit integer slices
+//           (dst_i8.hip).
 #include <algorithm>
 
 #include "lrp_internal.h"
@@ -516,7 +518,10 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
   hipError_t e = hipSuccess;
   const char *base = (const char *)tab;
   const int Qp8 = (Q + 1) & ~1, Qp4 = (Q + 3) & ~3;
-  // table layout: [f64 x Qp8][f32 x Qp4][u32 x Qp4]
+  // table layout: [f64 x Qp8][f32 x Qp4][u32 x Qp4][int8 records]
+  if (prec == LRP_PREC_INT8)
+    return launch_dst_i8(n, base + (size_t)Qp8 * 8 + (size_t)Qp4 * 8, (DstCol *)cols, ncols,
+                         kchunk, solves, partial, partial_elems, st);
   const double *t64 = (const double *)base;
   const float *t32 = (const float *)(base + (size_t)Qp8 * 8);
   const uint32_t *tbf = (const uint32_t *)(base + (size_t)Qp8 * 8 + (size_t)Qp4 * 4);

@@ -1,0 +1,363 @@
+// Sine transform on the int8 matrix cores with exact integer products (the
+// error-free splitting of Ozaki, Ogita and Oishi, "Error-free transformations
+// of matrix multiplication by using fast routines of matrix multiplication",
+// 2012, with integer slices as in Ootomo, Ozaki and Yokota, 2024).
+//
+// Both operands are cut into 7-bit integer slices:
+//   sin(pi m/N) * 2^6   = T_0 + T_1 2^-7 + ... + T_5 2^-35 + r,  |r| <= 2^-36,
+//   x_k 2^(-e_c) * 2^6  = X_0 + X_1 2^-7 + ... + X_5 2^-35 + r,
+// with T_a, X_b in [-64, 64] and e_c the exponent of the column's largest
+// entry.  Every product T_a X_b is exact in int32, and so is every sum over
+// K (|sum| <= 2^12 K * 6 < 2^31 for K < 2^15).  The products of one level
+// t = a + b share an accumulator; levels t <= 5 are kept, so the dropped
+// terms are below 2^-42 of the leading one:
+//   y_j = sqrt(2/N) 2^(e_c - 12) sum_{t<=5} 2^(-7t) acc_t[j],
+//   acc_t[j] = sum_k sum_{a+b=t} T_a[j,k] X_b[k].
+//
+// MFMA formulation (v_mfma_i32_16x16x64_i8): the 64-deep MFMA K runs over 16
+// grid points k times 4 slice positions.  Lane (i, g) of the A operand holds,
+// for the four points 4g..4g+3, the 4 bytes [T_0 T_1 T_2 T_3] of
+// sin(pi j k/N) (one dword per point, read from an LDS record table with the
+// sign folded in); lane (c, g) of the B operand holds the 4 bytes
+// [X_t X_(t-1) X_(t-2) X_(t-3)] (zero for negative indices) of x_k, a byte
+// window of the reversed slice record [X_5 .. X_0 0 0 0] (v_alignbyte).  So
+// one MFMA per level t adds sum_{a<=3} T_a X_(t-a) into acc_t, and two more
+// with [T_4 T_5 0 0] add the a = 4, 5 terms to levels 4 and 5: 8 MFMAs per
+// 16 grid points and 16 x 16 output tile.
+//
+// K is cut into the same fixed chunks as the floating-point transforms; the
+// levels of a chunk are combined into float64 and the chunk values summed in
+// order, so results do not depend on how many columns share a launch.
+#include <algorithm>
+#include <cmath>
+
+#include "lrp_internal.h"
+
+namespace lrp {
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int TMI = 128;         // rows per workgroup: 4 waves x 2 x 16
+constexpr int KCI = 32;          // grid points staged per LDS buffer
+constexpr int XST = KCI * 2 + 4; // dwords per staged column (+4: bank skew)
+
+// Column scale: e_c with max|x| = f 2^e_c, f in [0.5, 1), stored in the
+// column's descriptor; non-finite columns raise their solve's flag.
+__global__ __launch_bounds__(NTHR) void k_col_scale(int n, DstCol *cols, int ncols,
+                                                    Solve2D *solves) {
+  const int c = blockIdx.x;
+  if (c >= ncols) return;
+  const double *x = cols[c].src;
+  double mx = 0.0;
+  bool bad = false;
+  for (int k = threadIdx.x; k < n; k += NTHR) {
+    const double v = x[k];
+    if (!isfinite(v)) bad = true;
+    mx = fmax(mx, fabs(v));
+  }
+  __shared__ double red[4];
+  __shared__ int badw[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // wave max via the argmax helper (keys unused)
+  int key = 0;
+  wave_argmax(mx, key);
+  const unsigned long long anyb = __ballot(bad);
+  if (lane == 0) {
+    red[wave] = mx;
+    badw[wave] = anyb != 0ull;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    int e = 0;
+    if (m > 0.0 && isfinite(m)) (void)frexp(m, &e);
+    cols[c].pad = e;
+    if ((badw[0] | badw[1] | badw[2] | badw[3]) && cols[c].solve >= 0)
+      solves[cols[c].solve].nonfinite = 1;
+  }
+}
+
+// Reversed 7-bit slice record of x * 2^-e: dword 0 = bytes [X5 X4 X3 X2],
+// dword 1 = [X1 X0 0 0].
+__device__ __forceinline__ uint2 slice_record(double x, int e) {
+  double w = ldexp(x, 6 - e);
+  if (!isfinite(w)) w = 0.0;
+  int s[6];
+#pragma unroll
+  for (int b = 0; b < 6; ++b) {
+    const double q = rint(w);
+    s[b] = (int)q;
+    w = (w - q) * 128.0;
+  }
+  uint2 r;
+  r.x = (uint32_t)(s[5] & 0xff) | ((uint32_t)(s[4] & 0xff) << 8) |
+        ((uint32_t)(s[3] & 0xff) << 16) | ((uint32_t)(s[2] & 0xff) << 24);
+  r.y = (uint32_t)(s[1] & 0xff) | ((uint32_t)(s[0] & 0xff) << 8);
+  return r;
+}
+
+template <int TN_>
+__global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__restrict__ rec,
+                                                const DstCol *__restrict__ cols, int ncols,
+                                                int kchunk, double *__restrict__ partial) {
+  constexpr int NB = TN_ / 16;
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint2 *tab = (uint2 *)smem;                    // [q][sign] records
+  uint32_t *xs0 = (uint32_t *)(tab + 2 * Q);     // [c][k] records x 2 buffers
+  const int N = n + 1, twoN = 2 * N;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int row0 = blockIdx.x * TMI, c0 = blockIdx.y * TN_;
+  int cb, ce;
+  if (gridDim.z > 1) {
+    cb = blockIdx.z;
+    ce = blockIdx.z + 1;
+  } else {
+    cb = 0;
+    ce = (n + kchunk - 1) / kchunk;
+  }
+  for (int i = tid; i < 2 * Q; i += NTHR) tab[i] = rec[i];
+  // staging share: thread stages grid points tk, columns tc0 + 8 t
+  constexpr int PER = KCI * TN_ / NTHR;
+  const int tk = tid & (KCI - 1), tc0 = tid / KCI;
+  const double *src[PER];
+  int ex[PER];
+#pragma unroll
+  for (int t = 0; t < PER; ++t) {
+    const int c = c0 + tc0 + (NTHR / KCI) * t;
+    src[t] = (c < ncols) ? cols[c].src : nullptr;
+    ex[t] = (c < ncols) ? cols[c].pad : 0;
+  }
+  const int kbeg = cb * kchunk, kend = min(n, ce * kchunk);
+  const int nst = (kend - kbeg + KCI - 1) / KCI;
+  double pre[PER];
+  auto fetch = [&](int st) {
+    const int k = kbeg + st * KCI + tk;
+#pragma unroll
+    for (int t = 0; t < PER; ++t) pre[t] = (src[t] && k < kend) ? src[t][k] : 0.0;
+  };
+  auto stash = [&](int st) {
+    uint32_t *xs = xs0 + (st & 1) * TN_ * XST;
+#pragma unroll
+    for (int t = 0; t < PER; ++t) {
+      const uint2 r = slice_record(pre[t], ex[t]);
+      const int c = tc0 + (NTHR / KCI) * t;
+      xs[c * XST + 2 * tk] = r.x;
+      xs[c * XST + 2 * tk + 1] = r.y;
+    }
+  };
+  // rows of this lane: j = row0 + 32 wave + 16 h + (lane & 15) + 1 (1-based)
+  const int g = lane >> 4, li = lane & 15;
+  int jr[2], d16[2], mk[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    jr[h] = row0 + 32 * wave + 16 * h + li + 1;
+    if (jr[h] > n) jr[h] = 0;    // rows past the end: sin(0) = 0
+    d16[h] = (int)(((long long)jr[h] * 16) % twoN);
+    // m = j k mod 2N at this lane's first grid point, k = kbeg + 4 g + 1
+    mk[h] = (int)(((long long)jr[h] * (kbeg + 4 * g + 1)) % twoN);
+  }
+  v4i acc[2][NB][6];
+  double res[2][NB][4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+      for (int t = 0; t < 6; ++t) acc[h][b][t] = (v4i){0, 0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) res[h][b][q] = 0.0;
+    }
+  const double sc0 = sqrt(2.0 / (double)N);
+  // fold the levels of a finished chunk into the float64 results
+  auto flush = [&]() {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int c = c0 + 16 * b + li;
+      const int e = (c < ncols) ? cols[c].pad : 0;
+      const double sc = ldexp(sc0, e - 12);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double v = (double)acc[h][b][5][q];
+          v = v * 0x1p-7 + (double)acc[h][b][4][q];
+          v = v * 0x1p-7 + (double)acc[h][b][3][q];
+          v = v * 0x1p-7 + (double)acc[h][b][2][q];
+          v = v * 0x1p-7 + (double)acc[h][b][1][q];
+          v = v * 0x1p-7 + (double)acc[h][b][0][q];
+          {
+            // the chunk value is rounded on its own (no fused multiply-add),
+            // as in the split-K path, so both paths add the same numbers
+#pragma clang fp contract(off)
+            const double cv = v * sc;
+            res[h][b][q] = res[h][b][q] + cv;
+          }
+#pragma unroll
+          for (int t = 0; t < 6; ++t) acc[h][b][t][q] = 0;
+        }
+    }
+  };
+  if (nst > 0) {
+    fetch(0);
+    stash(0);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int k0 = kbeg + st * KCI;
+    if (st > 0 && (k0 % kchunk) == 0) flush();
+    if (st + 1 < nst) fetch(st + 1);
+    const uint32_t *xs = xs0 + (st & 1) * TN_ * XST;
+    const int kcn = min(KCI, kend - k0);
+    for (int kk = 0; kk < kcn; kk += 16) {
+      // A operands: records of points k0 + kk + 4g + e (1-based k)
+      v4i ahi[2], alo[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        int m = mk[h];
+        mk[h] += d16[h];                 // the lane's first point of the next step
+        if (mk[h] >= twoN) mk[h] -= twoN;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          int mm = m, sg = 0;
+          if (mm >= N) {
+            mm -= N;
+            sg = 1;
+          }
+          if (2 * mm > N) mm = N - mm;
+          // points past the end of K contribute zero through the B side
+          const uint2 r = tab[2 * mm + sg];
+          ahi[h][e] = (int)r.x;
+          alo[h][e] = (int)r.y;
+          m += jr[h];
+          if (m >= twoN) m -= twoN;
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        // B records of points kk + 4g .. +3 of column 16 b + li
+        const uint32_t *xr = xs + (16 * b + li) * XST + 2 * (kk + 4 * g);
+        const uint4 p0 = *(const uint4 *)xr;        // points 0, 1
+        const uint4 p1 = *(const uint4 *)(xr + 4);  // points 2, 3
+        const uint32_t d0[4] = {p0.x, p0.z, p1.x, p1.z};
+        const uint32_t d1[4] = {p0.y, p0.w, p1.y, p1.w};
+        v4i w[6];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          w[5][e] = (int)d0[e];
+          w[4][e] = (int)__builtin_amdgcn_alignbyte(d1[e], d0[e], 1);
+          w[3][e] = (int)__builtin_amdgcn_alignbyte(d1[e], d0[e], 2);
+          w[2][e] = (int)__builtin_amdgcn_alignbyte(d1[e], d0[e], 3);
+          w[1][e] = (int)d1[e];
+          w[0][e] = (int)(d1[e] >> 8);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+          for (int t = 0; t < 6; ++t)
+            acc[h][b][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ahi[h], w[t], acc[h][b][t], 0, 0, 0);
+          acc[h][b][4] = __builtin_amdgcn_mfma_i32_16x16x64_i8(alo[h], w[0], acc[h][b][4], 0, 0, 0);
+          acc[h][b][5] = __builtin_amdgcn_mfma_i32_16x16x64_i8(alo[h], w[1], acc[h][b][5], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+    if (st + 1 < nst) stash(st + 1);
+    __syncthreads();
+  }
+  flush();
+  // D[i][c]: lane c + 16 (i / 4), register i % 4
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int c = c0 + 16 * b + li;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = row0 + 32 * wave + 16 * h + 4 * g + q;
+        if (row < n && c < ncols) {
+          if (partial)
+            partial[((size_t)blockIdx.z * ncols + c) * n + row] = res[h][b][q];
+          else
+            cols[c].dst[row] = res[h][b][q];
+        }
+      }
+    }
+}
+
+__global__ void k_dst_i8_reduce(int n, int ncols, int nz, const double *__restrict__ partial,
+                                const DstCol *__restrict__ cols) {
+  const int col = blockIdx.y;
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n || col >= ncols) return;
+  double s = 0.0;
+  for (int z = 0; z < nz; ++z) s += partial[((size_t)z * ncols + col) * n + row];
+  cols[col].dst[row] = s;
+}
+
+}  // namespace
+
+size_t dst_i8_table_bytes(int n) {
+  const int Q = (n + 1) / 2 + 1;
+  return (size_t)Q * 2 * 8;
+}
+
+// Records of sin(pi q/N), q = 0 .. N/2, and their negatives:
+// rec[2q + s] = bytes [T_0 T_1 T_2 T_3 | T_4 T_5 0 0] of (-1)^s sin(pi q/N).
+void dst_i8_table(int n, unsigned char *out) {
+  const int N = n + 1, Q = N / 2 + 1;
+  const long double pi = 3.14159265358979323846264338327950288L;
+  for (int q = 0; q < Q; ++q) {
+    const long double v = sinl(pi * (long double)q / (long double)N);
+    for (int sgn = 0; sgn < 2; ++sgn) {
+      long double w = (sgn ? -v : v) * 64.0L;
+      signed char sl[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (int a = 0; a < 6; ++a) {
+        const long double r = roundl(w);
+        sl[a] = (signed char)(long)r;
+        w = (w - r) * 128.0L;
+      }
+      unsigned char *o = out + ((size_t)2 * q + sgn) * 8;
+      for (int a = 0; a < 8; ++a) o[a] = (unsigned char)sl[a];
+    }
+  }
+}
+
+static size_t i8_lds(int n, int tn) {
+  const int Q = (n + 1) / 2 + 1;
+  return (size_t)Q * 2 * 8 + (size_t)2 * tn * XST * 4;
+}
+
+bool dst_i8_supported(int n) { return i8_lds(n, 32) <= 160 * 1024; }
+
+hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, int kchunk,
+                         Solve2D *solves, double *partial, size_t partial_elems,
+                         hipStream_t st) {
+  if (ncols <= 0) return hipSuccess;
+  if (!dst_i8_supported(n)) return hipErrorInvalidValue;
+  const int Q = (n + 1) / 2 + 1;
+  hipLaunchKernelGGL(k_col_scale, dim3(ncols), dim3(NTHR), 0, st, n, cols, ncols, solves);
+  const bool wide = ncols > 32 && i8_lds(n, 64) <= 160 * 1024;
+  const int tn = wide ? 64 : 32;
+  const int nchunk = ceil_div(n, kchunk);
+  dim3 g(ceil_div(n, TMI), ceil_div(ncols, tn), 1);
+  if (g.x * g.y < 512 && partial && partial_elems >= (size_t)nchunk * ncols * n) g.z = nchunk;
+  double *out_partial = g.z > 1 ? partial : nullptr;
+  const size_t lds = i8_lds(n, tn);
+  const void *fn = wide ? (const void *)k_dst_i8<64> : (const void *)k_dst_i8<32>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (wide)
+    hipLaunchKernelGGL(k_dst_i8<64>, g, dim3(NTHR), lds, st, n, Q, (const uint2 *)rec, cols,
+                       ncols, kchunk, out_partial);
+  else
+    hipLaunchKernelGGL(k_dst_i8<32>, g, dim3(NTHR), lds, st, n, Q, (const uint2 *)rec, cols,
+                       ncols, kchunk, out_partial);
+  e = hipGetLastError();
+  if (e != hipSuccess || g.z == 1) return e;
+  hipLaunchKernelGGL(k_dst_i8_reduce, dim3(ceil_div(n, 256), ncols), dim3(256), 0, st, n, ncols,
+                     (int)g.z, (const double *)partial, cols);
+  return hipGetLastError();
+}
+
+}  // namespace lrp

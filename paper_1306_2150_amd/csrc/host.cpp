@@ -75,8 +75,10 @@ const GridTables *get_tables(lrp_ctx *ctx, int n, lrp_status *err) {
   const int N = n + 1;
   const int Q = N / 2 + 1;
   const int Qp8 = (Q + 1) & ~1, Qp4 = (Q + 3) & ~3;
-  const size_t tab_bytes = (size_t)Qp8 * 8 + (size_t)Qp4 * 4 + (size_t)Qp4 * 4;
+  const size_t i8_bytes = dst_i8_table_bytes(n);
+  const size_t tab_bytes = (size_t)Qp8 * 8 + (size_t)Qp4 * 4 + (size_t)Qp4 * 4 + i8_bytes;
   std::vector<char> host(tab_bytes, 0);
+  dst_i8_table(n, (unsigned char *)host.data() + (size_t)Qp8 * 8 + (size_t)Qp4 * 8);
   double *t64 = (double *)host.data();
   float *t32 = (float *)(host.data() + (size_t)Qp8 * 8);
   uint32_t *tbf = (uint32_t *)(host.data() + (size_t)Qp8 * 8 + (size_t)Qp4 * 4);
@@ -139,8 +141,7 @@ Plan make_plan(const lrp_opts *o, double eps, int n) {
 // ------------------------------------------------------------- Group2D
 struct Layout {
   size_t off_Uh, off_Vh, off_upan, off_vpan, off_cpan, off_treeR, off_treeH,
-      off_treeTau, off_treeY, off_small, off_part, off_mvval, off_score,
-      off_ints, total;
+      off_treeTau, off_treeY, off_small, off_part, off_mvval, off_ints, total;
 };
 
 static size_t tree_nodes(const Tree &t, int from) {
@@ -174,9 +175,8 @@ static Layout slot_layout(int n, int m, const Tree &t) {
   L.off_treeY = take(tree_nodes(t, 0) * KMAX * KMAX * 8);
   L.off_small = take((size_t)(7 * KMAX * KMAX + 2 * KMAX) * 8);
   L.off_part = take(std::max<size_t>((size_t)change_blocks(m) * KMAX * KMAX, 2 * nb0) * 8);
-  L.off_mvval = take(nb0 * MV_TOP * 8);
-  L.off_score = take((size_t)m * 8);
-  L.off_ints = take((tree_nodes(t, 0) * KMAX + nb0 * MV_TOP + 4 * KMAX) * 4);
+  L.off_mvval = take(nb0 * BLOCK_TOP * 8);
+  L.off_ints = take((tree_nodes(t, 0) * KMAX + nb0 * BLOCK_TOP + 4 * KMAX) * 4);
   L.total = o;
   return L;
 }
@@ -272,12 +272,11 @@ lrp_status Group2D::init() {
     s.sigp = sm + 7 * k2 + KMAX;
     s.part = (double *)(b + L.off_part);
     s.mv_val = (double *)(b + L.off_mvval);
-    s.score = (double *)(b + L.off_score);
     int *ip = (int *)(b + L.off_ints);
     s.tree_piv = ip;
     ip += tree_nodes(talloc_, 0) * KMAX;
     s.mv_row = ip;
-    ip += (size_t)talloc_.nb[0] * MV_TOP;
+    ip += (size_t)talloc_.nb[0] * BLOCK_TOP;
     s.I = ip;
     s.J = ip + KMAX;
     s.Jn = ip + 2 * KMAX;
@@ -369,7 +368,7 @@ lrp_status Group2D::dst_cols(std::vector<DstCol> &cols, int prec, hipStream_t st
 }
 
 lrp_status Group2D::forward(const std::vector<int> &slots, hipStream_t st) {
-  for (int prec : {LRP_PREC_FP64, LRP_PREC_FP32, LRP_PREC_BF16X3}) {
+  for (int prec : {LRP_PREC_FP64, LRP_PREC_FP32, LRP_PREC_BF16X3, LRP_PREC_INT8}) {
     std::vector<DstCol> cols;
     for (int i : slots) {
       const Solve2D &s = h_s_[i];
@@ -435,7 +434,7 @@ lrp_status Group2D::fetch(hipStream_t st, bool sync) {
 }
 
 lrp_status Group2D::inverse(const std::vector<int> &slots, hipStream_t st) {
-  for (int prec : {LRP_PREC_FP64, LRP_PREC_FP32, LRP_PREC_BF16X3}) {
+  for (int prec : {LRP_PREC_FP64, LRP_PREC_FP32, LRP_PREC_BF16X3, LRP_PREC_INT8}) {
     std::vector<DstCol> cols;
     for (int i : slots) {
       const Solve2D &s = h_s_[i];
@@ -491,8 +490,10 @@ lrp_status lrp_sine_transform(lrp_ctx *ctx, int64_t n, int32_t ncols,
                               const double *src, int64_t lds, double *dst,
                               int64_t ldd, int32_t prec, void *stream) {
   if (!ctx || n < 1 || n > LRP_MAX_N || ncols < 0) return LRP_EINVAL;
-  if (prec != LRP_PREC_FP64 && prec != LRP_PREC_FP32 && prec != LRP_PREC_BF16X3)
+  if (prec != LRP_PREC_FP64 && prec != LRP_PREC_FP32 && prec != LRP_PREC_BF16X3 &&
+      prec != LRP_PREC_INT8)
     return LRP_EINVAL;
+  if (prec == LRP_PREC_INT8 && !dst_i8_supported((int)n)) return LRP_EINVAL;
   if (ncols == 0) return LRP_OK;
   if (!src || !dst || lds < n || ldd < n) return LRP_EINVAL;
   if (hipSetDevice(ctx->device) != hipSuccess) return LRP_EDEVICE;
@@ -544,7 +545,7 @@ lrp_status lrp_set_kernel_timing(lrp_ctx *ctx, int32_t enable) {
 
 lrp_status lrp_kernel_stats(lrp_ctx *ctx, int32_t prec, lrp_kernel_stat *out,
                             int32_t reset) {
-  if (!ctx || prec < 0 || prec > 3 || prec == LRP_PREC_AUTO) return LRP_EINVAL;
+  if (!ctx || prec < 0 || prec > LRP_PREC_INT8 || prec == LRP_PREC_AUTO) return LRP_EINVAL;
   std::lock_guard<std::mutex> lock(ctx->mu);
   if (hipSetDevice(ctx->device) != hipSuccess) return LRP_EDEVICE;
   for (auto &pt : ctx->pending_times) {
@@ -595,7 +596,7 @@ lrp_status lrpoisson_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t count,
                                    void *stream) {
   if (!ctx || !probs || count < 0) return LRP_EINVAL;
   if (n < 1 || n > LRP_MAX_N) return LRP_EINVAL;
-  if (opts && (opts->prec < 0 || opts->prec > LRP_PREC_BF16X3)) return LRP_EINVAL;
+  if (opts && (opts->prec < 0 || opts->prec > LRP_PREC_INT8)) return LRP_EINVAL;
   for (int i = 0; i < count; ++i) {
     lrp_status e = check_problem(n, probs[i]);
     if (e != LRP_OK) return e;

@@ -196,7 +196,7 @@ struct lrp_ctx {
     double flops;
   };
   std::vector<PendingTime> pending_times;
-  lrp_kernel_stat kstat[4] = {};
+  lrp_kernel_stat kstat[5] = {};
   std::mutex mu;
 };
 

@@ -16,6 +16,8 @@ constexpr int NTHR = 256;            // threads of every panel kernel
 constexpr int MV_TOP = 8;            // violator rows kept per block in maxvol
 constexpr int MV_CAND = 128;         // candidate rows of the maxvol swap kernel
 constexpr int MV_ROUNDS = 3;         // check/swap rounds launched per maxvol
+constexpr int GROW_TOP = 16;         // growth candidates kept per block (>= kick)
+constexpr int BLOCK_TOP = (MV_TOP > GROW_TOP) ? MV_TOP : GROW_TOP;
 
 // Solve phases / flags written by kernels.
 enum : int {
@@ -71,9 +73,8 @@ struct Solve2D {
   double *sig;              // KMAX   singular values (descending)
   double *sigp;             // KMAX   previous sweep's singular values
   double *part;             // nb0 * KMAX*KMAX  partial sums
-  double *mv_val;           // nb0 * MV_TOP  maxvol violators (|B|)
-  int *mv_row;              // nb0 * MV_TOP  maxvol violators (row)
-  double *score;            // m  growth scores
+  double *mv_val;           // nb0 * BLOCK_TOP  maxvol violators (|B|) or
+  int *mv_row;              //   growth candidates: value and row / column
   int *I, *J, *Jn;          // KMAX pivot sets
   int *probe;               // KMAX probe rows
   // ---- control
@@ -232,6 +233,13 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
                       int ncols, Solve2D *solves, double *partial,
                       size_t partial_elems, hipStream_t st);
 size_t dst_partial_elems(int n, int ncols);
+// int8 slice transform (dst_i8.hip): record table of the sines, support
+bool dst_i8_supported(int n);
+size_t dst_i8_table_bytes(int n);
+void dst_i8_table(int n, unsigned char *out);
+hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, int kchunk,
+                         Solve2D *solves, double *partial, size_t partial_elems,
+                         hipStream_t st);
 
 // Row counts: calls on the column side (Xh[:, J], Q0, A) cover the n rows,
 // calls on the row side (Xh[I, :]^T, Q1, B, Vh) the m columns.

@@ -243,22 +243,57 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
   int *cr = rows;
   if (threadIdx.x == 0) cnt[0] = 0;
   __syncthreads();
-  // rank-select the largest reported violators (ties: lower row first)
-  for (int e = threadIdx.x; e < ntot; e += NTHR) {
-    const double v = s.mv_val[e];
-    const int rr = s.mv_row[e];
-    if (rr < 0 || !(v > s.tau)) continue;
-    int rank = 0;
-    for (int f = 0; f < ntot; ++f) {
-      const double w = s.mv_val[f];
-      const int r2 = s.mv_row[f];
-      if (r2 < 0 || !(w > s.tau)) continue;
-      if (w > v || (w == v && r2 < rr)) ++rank;
+  // the MV_CAND largest reported violators in order (value descending,
+  // ties: lower row first; reported rows are distinct)
+  if (ntot <= 1024) {
+    // few reports: rank every one against all others
+    for (int e = threadIdx.x; e < ntot; e += NTHR) {
+      const double v = s.mv_val[e];
+      const int rr = s.mv_row[e];
+      if (rr < 0 || !(v > s.tau)) continue;
+      int rank = 0;
+      for (int f = 0; f < ntot; ++f) {
+        const double w = s.mv_val[f];
+        const int r2 = s.mv_row[f];
+        if (r2 < 0 || !(w > s.tau)) continue;
+        if (w > v || (w == v && r2 < rr)) ++rank;
+      }
+      if (rank < MV_CAND) {
+        cr[kk + rank] = rr;
+        atomicAdd(&cnt[0], 1);
+      }
     }
-    if (rank < MV_CAND) {
-      cr[kk + rank] = rr;
-      atomicAdd(&cnt[0], 1);
+  } else {
+    // many reports (tall column side): pick them one by one, each the
+    // largest entry strictly after the previous pick in that order
+    double lastv = INFINITY;
+    int lastr = -1, picked = 0;
+    const int lane0 = threadIdx.x & 63, wave0 = threadIdx.x >> 6;
+    for (int it = 0; it < MV_CAND; ++it) {
+      double best = -1.0;
+      int key = 0x7fffffff;
+      for (int e = threadIdx.x; e < ntot; e += NTHR) {
+        const double v = s.mv_val[e];
+        const int rr = s.mv_row[e];
+        if (rr < 0 || !(v > s.tau)) continue;
+        if (v > lastv || (v == lastv && rr <= lastr)) continue;
+        if (v > best || (v == best && rr < key)) best = v, key = rr;
+      }
+      wave_argmax(best, key);
+      if (lane0 == 0) rv[wave0] = best, rk[wave0] = key;
+      __syncthreads();
+      double bv = rv[0];
+      int bk = rk[0];
+      for (int w = 1; w < 4; ++w)
+        if (rv[w] > bv || (rv[w] == bv && rk[w] < bk)) bv = rv[w], bk = rk[w];
+      __syncthreads();
+      if (!(bv > s.tau)) break;          // uniform
+      if (threadIdx.x == 0) cr[kk + it] = bk;
+      lastv = bv;
+      lastr = bk;
+      ++picked;
     }
+    if (threadIdx.x == 0) cnt[0] = picked;
   }
   __syncthreads();
   const int nc = min(cnt[0], MV_CAND);

@@ -49,6 +49,33 @@ def test_dst_leading_dimension_and_involution():
     assert rel(host(Z), X) <= 1e-13
 
 
+@pytest.mark.parametrize("n,c", [(1, 1), (2, 3), (63, 5), (100, 70), (257, 17), (1000, 40),
+                                 (4096, 32), (4096, 200), (8191, 9), (12000, 3)])
+def test_dst_int8_slices_match_oracle(n, c):
+    """Exact-integer slice transform: the only errors are the six-slice
+    representations of the sines and of x (2^-42 of their largest entries)
+    and the dropped slice levels >= 6 (about 2^-42 each); a few 1e-13 to
+    2e-12 in the relative Frobenius norm of a column."""
+    log("dst int8", n, c)
+    rng = np.random.default_rng(n * 11 + c)
+    X = rng.standard_normal((n, c))
+    X[:, 0] *= 1e-30               # column scales are independent
+    Y = host(ctx().sine_transform(dev(X), "int8"))
+    R = poisson.dst(X)
+    for j in range(c):
+        assert rel(Y[:, j], R[:, j]) <= 1e-11, (j, rel(Y[:, j], R[:, j]))
+
+
+def test_dst_int8_columns_independent_of_batch():
+    log("dst int8 batch")
+    n = 3000
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((n, 300))
+    big = host(ctx().sine_transform(dev(X), "int8"))        # wide tiles, no K split
+    small = host(ctx().sine_transform(dev(X[:, 7:9]), "int8"))   # K split
+    assert np.array_equal(big[:, 7:9], small)
+
+
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("bf16x3", 5e-5)])
 def test_dst_reduced_precision_error_bound(prec, tol):
     log("dst", prec)
@@ -196,7 +223,8 @@ def test_solve2d_batch_same_as_alone():
 
 @pytest.mark.parametrize("prec,eps,bar", [("fp32", 1e-7, 1e-6), ("auto", 1e-8, 1e-7),
                                           ("auto", 1e-7, 1e-6), ("auto", 1e-6, 1e-5),
-                                          ("bf16x3", 1e-5, 1e-4)])
+                                          ("bf16x3", 1e-5, 1e-4), ("int8", 1e-8, 1e-7),
+                                          ("int8", 1e-10, 1e-9)])
 def test_solve2d_mixed_precision(prec, eps, bar):
     log("solve2d mixed", prec, eps)
     U, V = inputs.workload_rhs(2, 1, n=4096)
