@@ -6,8 +6,9 @@ points per axis, RHS = sum of r = 16 separable Gaussian bumps, eps = 1e-8
 solution).  One step = one batched call that runs the whole path (forward
 sine transform of the factors, cross sweeps with maxvol, rounding, inverse
 transform) for a batch of B distinct right-hand sides already resident in
-device memory.  `value` is the mixed-precision plan (AUTO: forward transform
-float32, inverse float64 at this eps); the float64 plan is timed beside it.
+device memory.  `value` is the mixed-precision plan (AUTO: both transforms on
+the int8 matrix cores with exact 7-bit slices, everything else float64); the
+plain float64 plan is timed beside it.
 Every distinct RHS of the batch is checked against the CPU oracle.
 
 Also reported: served p50/p99 latency of a Poisson-arrival request stream
@@ -31,7 +32,7 @@ sys.path.insert(0, ROOT)
 # another group's short ones (HIP reads this when it initialises).
 os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
-PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15}
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "int8": 5.0e15}
 METRIC = "2D n=4096 r=16 solves/s at rel err<=1e-7, mixed vs FP64 path; served p99 ms"
 
 
@@ -55,8 +56,8 @@ def timed_steps(ctx, problems, prec, steps, warmup):
     for _ in range(warmup):
         res = ctx.solve2d_batch(problems, prec=prec)
     torch.cuda.synchronize()
-    ctx.kernel_stats("fp64", reset=True)
-    ctx.kernel_stats("fp32", reset=True)
+    for p in ("fp64", "fp32", "bf16x3", "int8"):
+        ctx.kernel_stats(p, reset=True)
     ctx.set_kernel_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -65,7 +66,7 @@ def timed_steps(ctx, problems, prec, steps, warmup):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ctx.set_kernel_timing(False)
-    ks = {p: ctx.kernel_stats(p, reset=True) for p in ("fp64", "fp32")}
+    ks = {p: ctx.kernel_stats(p, reset=True) for p in ("fp64", "fp32", "bf16x3", "int8")}
     return dt, res, ks
 
 
@@ -117,23 +118,28 @@ def main():
     print("[bench] rel err per instance auto: " +
           " ".join(f"{e:.2e}" for e in errs["auto"]), file=sys.stderr, flush=True)
 
-    # roofline of the dominant kernel: the float64 transform GEMM
-    k64 = out["auto"]["ks"]["fp64"]
-    avg_ms = k64["ms"] / max(1, k64["launches"])
-    flops_per_launch = k64["flops"] / max(1, k64["launches"])
-    achieved = flops_per_launch / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
-    roofline = {"kernel": "k_dst_f64", "bound": "mfma", "achieved": achieved / 1e12,
-                "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / PEAK["fp64"], "traffic": None,
-                "avg_launch_ms": avg_ms, "launches": k64["launches"],
-                "columns_per_launch": k64["columns"] / max(1, k64["launches"]),
-                "flops_per_launch": flops_per_launch}
-    k32 = out["auto"]["ks"]["fp32"]
-    if k32["launches"]:
-        a32 = k32["flops"] / (k32["ms"] * 1e-3)
-        roofline["fp32_transform"] = {"achieved": a32 / 1e12, "peak": PEAK["fp32"] / 1e12,
-                                      "frac": a32 / PEAK["fp32"],
-                                      "avg_launch_ms": k32["ms"] / k32["launches"]}
+    # roofline of the dominant kernel of the measured (AUTO) step: the int8
+    # slice transform (the float64 transform of the FP64 plan beside it).
+    # Algorithmic work per transformed column of length n: the dense DST GEMM
+    # is 2 n^2 flops; the int8 slice scheme executes it as 8 v_mfma_i32_16x16x64
+    # per 16 grid points and 16 x 16 output tile, i.e. 32 x 2 n^2 int8 ops.
+    def kstat_roof(ks, name, peak, unit, ops_per_flop):
+        launches = max(1, ks["launches"])
+        avg_ms = ks["ms"] / launches
+        flops = ks["flops"] / launches
+        ach = flops * ops_per_flop / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
+        return {"kernel": name, "bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12,
+                "unit": unit, "frac": ach / peak, "traffic": None,
+                "avg_launch_ms": avg_ms, "launches": ks["launches"],
+                "columns_per_launch": ks["columns"] / launches,
+                "dense_equiv_tflops": (flops / (avg_ms * 1e-3) / 1e12) if avg_ms > 0 else 0.0}
+    kauto = out["auto"]["ks"]
+    if kauto["int8"]["launches"]:
+        roofline = kstat_roof(kauto["int8"], "k_dst_i8", PEAK["int8"], "TOP/s", 32.0)
+    else:
+        roofline = kstat_roof(kauto["fp64"], "k_dst_f64", PEAK["fp64"], "TFLOP/s", 1.0)
+    roofline["fp64_plan_kernel"] = kstat_roof(out["fp64"]["ks"]["fp64"], "k_dst_f64",
+                                              PEAK["fp64"], "TFLOP/s", 1.0)
 
     line = {
         "metric": METRIC,
@@ -146,7 +152,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64",
+        "dtype": "i8-slices+f64",
         "data": "synthetic",
         "config": {"workload": "2D Poisson n=4096 r=16 eps=1e-8 Gaussian-bump RHS",
                    "n": n, "r": r, "eps": eps, "batch": B,

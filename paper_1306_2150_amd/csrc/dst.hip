@@ -198,19 +198,38 @@ __global__ __launch_bounds__(NTHR) void k_dst_f64(
     if (st + 1 < nst) fetch(st + 1);
     const double *xs = xs0 + (st & 1) * TN_ * LDT;
     const int kcn = min(KC64, kend - k0);
+    // software pipelined: the operands of step kc + 4 are read from LDS
+    // while the MFMAs of step kc run
+    double aA = sine_lookup(tab, mA, N), aB = sine_lookup(tab, mB, N), bv[NB];
+    mA += stepA;
+    if (mA >= twoN) mA -= twoN;
+    mB += stepB;
+    if (mB >= twoN) mB -= twoN;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) bv[b] = xs[(b * 16 + (lane & 15)) * LDT + kk];
     for (int kc = 0; kc < kcn; kc += 4) {
-      const double aA = sine_lookup(tab, mA, N);
-      const double aB = sine_lookup(tab, mB, N);
-      mA += stepA;
-      if (mA >= twoN) mA -= twoN;
-      mB += stepB;
-      if (mB >= twoN) mB -= twoN;
+      double nA = 0.0, nB = 0.0, nb[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) nb[b] = 0.0;
+      if (kc + 4 < kcn) {
+        nA = sine_lookup(tab, mA, N);
+        nB = sine_lookup(tab, mB, N);
+        mA += stepA;
+        if (mA >= twoN) mA -= twoN;
+        mB += stepB;
+        if (mB >= twoN) mB -= twoN;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) nb[b] = xs[(b * 16 + (lane & 15)) * LDT + kc + 4 + kk];
+      }
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const double bv = xs[(b * 16 + (lane & 15)) * LDT + kc + kk];
-        part[0][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aA, bv, part[0][b], 0, 0, 0);
-        part[1][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aB, bv, part[1][b], 0, 0, 0);
+        part[0][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aA, bv[b], part[0][b], 0, 0, 0);
+        part[1][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aB, bv[b], part[1][b], 0, 0, 0);
       }
+      aA = nA;
+      aB = nB;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) bv[b] = nb[b];
     }
     if (st + 1 < nst) stash(st + 1);
     __syncthreads();
@@ -333,19 +352,36 @@ __global__ __launch_bounds__(NTHR) void k_dst_f32(
     if (st + 1 < nst) fetch(st + 1);
     const float *xs = xs0 + (st & 1) * TN_ * LDT32;
     const int kcn = min(KC64, kend - k0);
+    float aA = sine_lookup(tab, mA, N), aB = sine_lookup(tab, mB, N), bv[NB];
+    mA += stepA;
+    if (mA >= twoN) mA -= twoN;
+    mB += stepB;
+    if (mB >= twoN) mB -= twoN;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) bv[b] = xs[(b * 16 + (lane & 15)) * LDT32 + kk];
     for (int kc = 0; kc < kcn; kc += 4) {
-      const float aA = sine_lookup(tab, mA, N);
-      const float aB = sine_lookup(tab, mB, N);
-      mA += stepA;
-      if (mA >= twoN) mA -= twoN;
-      mB += stepB;
-      if (mB >= twoN) mB -= twoN;
+      float nA = 0.f, nB = 0.f, nb[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) nb[b] = 0.f;
+      if (kc + 4 < kcn) {
+        nA = sine_lookup(tab, mA, N);
+        nB = sine_lookup(tab, mB, N);
+        mA += stepA;
+        if (mA >= twoN) mA -= twoN;
+        mB += stepB;
+        if (mB >= twoN) mB -= twoN;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) nb[b] = xs[(b * 16 + (lane & 15)) * LDT32 + kc + 4 + kk];
+      }
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        const float bv = xs[(b * 16 + (lane & 15)) * LDT32 + kc + kk];
-        run[0][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aA, bv, run[0][b], 0, 0, 0);
-        run[1][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aB, bv, run[1][b], 0, 0, 0);
+        run[0][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aA, bv[b], run[0][b], 0, 0, 0);
+        run[1][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aB, bv[b], run[1][b], 0, 0, 0);
       }
+      aA = nA;
+      aB = nB;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) bv[b] = nb[b];
     }
     // a stage is one 32-deep float32 run
 #pragma unroll
@@ -500,7 +536,8 @@ size_t dst_partial_elems(int n, int ncols) {
 
 hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
                       int ncols, Solve2D *solves, double *partial,
-                      size_t partial_elems, hipStream_t st) {
+                      size_t partial_elems, void *work, size_t work_bytes,
+                      hipStream_t st) {
   if (ncols <= 0) return hipSuccess;
   const int Q = quarter_len(n);
   const int gx = ceil_div(n, TM), gy = ceil_div(ncols, TN);
@@ -521,7 +558,7 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
   // table layout: [f64 x Qp8][f32 x Qp4][u32 x Qp4][int8 records]
   if (prec == LRP_PREC_INT8)
     return launch_dst_i8(n, base + (size_t)Qp8 * 8 + (size_t)Qp4 * 8, (DstCol *)cols, ncols,
-                         kchunk, solves, partial, partial_elems, st);
+                         kchunk, solves, partial, partial_elems, work, work_bytes, st);
   const double *t64 = (const double *)base;
   const float *t32 = (const float *)(base + (size_t)Qp8 * 8);
   const uint32_t *tbf = (const uint32_t *)(base + (size_t)Qp8 * 8 + (size_t)Qp4 * 4);

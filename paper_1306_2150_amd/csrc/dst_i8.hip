@@ -14,6 +14,10 @@
 //   y_j = sqrt(2/N) 2^(e_c - 12) sum_{t<=5} 2^(-7t) acc_t[j],
 //   acc_t[j] = sum_k sum_{a+b=t} T_a[j,k] X_b[k].
 //
+// A first pass writes every column's reversed slice records (8 bytes per
+// point); the GEMM stages them in LDS as the six byte windows below, so its
+// inner loop only reads ready MFMA operands.
+//
 // MFMA formulation (v_mfma_i32_16x16x64_i8): the 64-deep MFMA K runs over 16
 // grid points k times 4 slice positions.  Lane (i, g) of the A operand holds,
 // for the four points 4g..4g+3, the 4 bytes [T_0 T_1 T_2 T_3] of
@@ -40,43 +44,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int TMI = 128;         // rows per workgroup: 4 waves x 2 x 16
 constexpr int KCI = 32;          // grid points staged per LDS buffer
-constexpr int XST = KCI * 2 + 4; // dwords per staged column (+4: bank skew)
-
-// Column scale: e_c with max|x| = f 2^e_c, f in [0.5, 1), stored in the
-// column's descriptor; non-finite columns raise their solve's flag.
-__global__ __launch_bounds__(NTHR) void k_col_scale(int n, DstCol *cols, int ncols,
-                                                    Solve2D *solves) {
-  const int c = blockIdx.x;
-  if (c >= ncols) return;
-  const double *x = cols[c].src;
-  double mx = 0.0;
-  bool bad = false;
-  for (int k = threadIdx.x; k < n; k += NTHR) {
-    const double v = x[k];
-    if (!isfinite(v)) bad = true;
-    mx = fmax(mx, fabs(v));
-  }
-  __shared__ double red[4];
-  __shared__ int badw[4];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // wave max via the argmax helper (keys unused)
-  int key = 0;
-  wave_argmax(mx, key);
-  const unsigned long long anyb = __ballot(bad);
-  if (lane == 0) {
-    red[wave] = mx;
-    badw[wave] = anyb != 0ull;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    int e = 0;
-    if (m > 0.0 && isfinite(m)) (void)frexp(m, &e);
-    cols[c].pad = e;
-    if ((badw[0] | badw[1] | badw[2] | badw[3]) && cols[c].solve >= 0)
-      solves[cols[c].solve].nonfinite = 1;
-  }
-}
+constexpr int XST = KCI + 4;     // dwords per staged column and level (+4: bank skew)
 
 // Reversed 7-bit slice record of x * 2^-e: dword 0 = bytes [X5 X4 X3 X2],
 // dword 1 = [X1 X0 0 0].
@@ -97,14 +65,57 @@ __device__ __forceinline__ uint2 slice_record(double x, int e) {
   return r;
 }
 
+// One block per column: e_c with max|x| = f 2^e_c, f in [0.5, 1) (kept in
+// the column's descriptor), then the slice records of all npad points
+// (zero past n).  Non-finite columns raise their solve's flag.
+__global__ __launch_bounds__(NTHR) void k_x_slices(int n, int npad, DstCol *cols, int ncols,
+                                                   uint2 *__restrict__ out, Solve2D *solves) {
+  const int c = blockIdx.x;
+  if (c >= ncols) return;
+  const double *x = cols[c].src;
+  double mx = 0.0;
+  bool bad = false;
+  for (int k = threadIdx.x; k < n; k += NTHR) {
+    const double v = x[k];
+    if (!isfinite(v)) bad = true;
+    mx = fmax(mx, fabs(v));
+  }
+  __shared__ double red[4];
+  __shared__ int badw[4];
+  __shared__ int ex;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int key = 0;
+  wave_argmax(mx, key);                 // wave maximum (keys unused)
+  const unsigned long long anyb = __ballot(bad);
+  if (lane == 0) {
+    red[wave] = mx;
+    badw[wave] = anyb != 0ull;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    int e = 0;
+    if (m > 0.0 && isfinite(m)) (void)frexp(m, &e);
+    ex = e;
+    cols[c].pad = e;
+    if ((badw[0] | badw[1] | badw[2] | badw[3]) && cols[c].solve >= 0)
+      solves[cols[c].solve].nonfinite = 1;
+  }
+  __syncthreads();
+  const int e = ex;
+  uint2 *o = out + (size_t)c * npad;
+  for (int k = threadIdx.x; k < npad; k += NTHR) o[k] = slice_record(k < n ? x[k] : 0.0, e);
+}
+
 template <int TN_>
 __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__restrict__ rec,
                                                 const DstCol *__restrict__ cols, int ncols,
-                                                int kchunk, double *__restrict__ partial) {
+                                                int kchunk, const uint2 *__restrict__ xrec,
+                                                int npad, double *__restrict__ partial) {
   constexpr int NB = TN_ / 16;
   extern __shared__ __align__(16) unsigned char smem[];
   uint2 *tab = (uint2 *)smem;                    // [q][sign] records
-  uint32_t *xs0 = (uint32_t *)(tab + 2 * Q);     // [c][k] records x 2 buffers
+  uint32_t *xs0 = (uint32_t *)(tab + 2 * Q);     // [level][c][k] windows x 2 buffers
   const int N = n + 1, twoN = 2 * N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int row0 = blockIdx.x * TMI, c0 = blockIdx.y * TN_;
@@ -119,31 +130,36 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
   for (int i = tid; i < 2 * Q; i += NTHR) tab[i] = rec[i];
   // staging share: thread stages grid points tk, columns tc0 + 8 t
   constexpr int PER = KCI * TN_ / NTHR;
+  constexpr int LVL = TN_ * XST;                 // dwords per level and buffer
   const int tk = tid & (KCI - 1), tc0 = tid / KCI;
-  const double *src[PER];
-  int ex[PER];
+  const uint2 *src[PER];
 #pragma unroll
   for (int t = 0; t < PER; ++t) {
     const int c = c0 + tc0 + (NTHR / KCI) * t;
-    src[t] = (c < ncols) ? cols[c].src : nullptr;
-    ex[t] = (c < ncols) ? cols[c].pad : 0;
+    src[t] = (c < ncols) ? xrec + (size_t)c * npad : nullptr;
   }
   const int kbeg = cb * kchunk, kend = min(n, ce * kchunk);
   const int nst = (kend - kbeg + KCI - 1) / KCI;
-  double pre[PER];
+  uint2 pre[PER];
   auto fetch = [&](int st) {
     const int k = kbeg + st * KCI + tk;
 #pragma unroll
-    for (int t = 0; t < PER; ++t) pre[t] = (src[t] && k < kend) ? src[t][k] : 0.0;
+    for (int t = 0; t < PER; ++t)
+      pre[t] = (src[t] && k < kend) ? src[t][k] : make_uint2(0u, 0u);
   };
+  // windows t of [X5 .. X0 0 0 0]: bytes [X_t X_(t-1) X_(t-2) X_(t-3)]
   auto stash = [&](int st) {
-    uint32_t *xs = xs0 + (st & 1) * TN_ * XST;
+    uint32_t *xs = xs0 + (st & 1) * 6 * LVL;
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
-      const uint2 r = slice_record(pre[t], ex[t]);
-      const int c = tc0 + (NTHR / KCI) * t;
-      xs[c * XST + 2 * tk] = r.x;
-      xs[c * XST + 2 * tk + 1] = r.y;
+      const uint32_t d0 = pre[t].x, d1 = pre[t].y;
+      uint32_t *p = xs + (tc0 + (NTHR / KCI) * t) * XST + tk;
+      p[5 * LVL] = d0;
+      p[4 * LVL] = __builtin_amdgcn_alignbyte(d1, d0, 1);
+      p[3 * LVL] = __builtin_amdgcn_alignbyte(d1, d0, 2);
+      p[2 * LVL] = __builtin_amdgcn_alignbyte(d1, d0, 3);
+      p[1 * LVL] = d1;
+      p[0] = d1 >> 8;
     }
   };
   // rows of this lane: j = row0 + 32 wave + 16 h + (lane & 15) + 1 (1-based)
@@ -207,7 +223,7 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
     const int k0 = kbeg + st * KCI;
     if (st > 0 && (k0 % kchunk) == 0) flush();
     if (st + 1 < nst) fetch(st + 1);
-    const uint32_t *xs = xs0 + (st & 1) * TN_ * XST;
+    const uint32_t *xs = xs0 + (st & 1) * 6 * LVL;
     const int kcn = min(KCI, kend - k0);
     for (int kk = 0; kk < kcn; kk += 16) {
       // A operands: records of points k0 + kk + 4g + e (1-based k)
@@ -235,22 +251,11 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
       }
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        // B records of points kk + 4g .. +3 of column 16 b + li
-        const uint32_t *xr = xs + (16 * b + li) * XST + 2 * (kk + 4 * g);
-        const uint4 p0 = *(const uint4 *)xr;        // points 0, 1
-        const uint4 p1 = *(const uint4 *)(xr + 4);  // points 2, 3
-        const uint32_t d0[4] = {p0.x, p0.z, p1.x, p1.z};
-        const uint32_t d1[4] = {p0.y, p0.w, p1.y, p1.w};
+        // window t of points kk + 4g .. +3 of column 16 b + li
+        const uint32_t *xw = xs + (16 * b + li) * XST + kk + 4 * g;
         v4i w[6];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          w[5][e] = (int)d0[e];
-          w[4][e] = (int)__builtin_amdgcn_alignbyte(d1[e], d0[e], 1);
-          w[3][e] = (int)__builtin_amdgcn_alignbyte(d1[e], d0[e], 2);
-          w[2][e] = (int)__builtin_amdgcn_alignbyte(d1[e], d0[e], 3);
-          w[1][e] = (int)d1[e];
-          w[0][e] = (int)(d1[e] >> 8);
-        }
+        for (int t = 0; t < 6; ++t) w[t] = *(const v4i *)(xw + t * LVL);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -325,39 +330,58 @@ void dst_i8_table(int n, unsigned char *out) {
 
 static size_t i8_lds(int n, int tn) {
   const int Q = (n + 1) / 2 + 1;
-  return (size_t)Q * 2 * 8 + (size_t)2 * tn * XST * 4;
+  return (size_t)Q * 2 * 8 + (size_t)2 * 6 * tn * XST * 4;
 }
 
 bool dst_i8_supported(int n) { return i8_lds(n, 32) <= 160 * 1024; }
+bool dst_i8_fast(int n) { return i8_lds(n, 64) <= 160 * 1024; }
+
+size_t dst_i8_work_bytes(int n, int ncols) {
+  const int npad = ceil_div(n, KCI) * KCI;
+  return (size_t)ncols * npad * 8;
+}
 
 hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, int kchunk,
                          Solve2D *solves, double *partial, size_t partial_elems,
-                         hipStream_t st) {
+                         void *work, size_t work_bytes, hipStream_t st) {
   if (ncols <= 0) return hipSuccess;
   if (!dst_i8_supported(n)) return hipErrorInvalidValue;
   const int Q = (n + 1) / 2 + 1;
-  hipLaunchKernelGGL(k_col_scale, dim3(ncols), dim3(NTHR), 0, st, n, cols, ncols, solves);
-  const bool wide = ncols > 32 && i8_lds(n, 64) <= 160 * 1024;
-  const int tn = wide ? 64 : 32;
-  const int nchunk = ceil_div(n, kchunk);
-  dim3 g(ceil_div(n, TMI), ceil_div(ncols, tn), 1);
-  if (g.x * g.y < 512 && partial && partial_elems >= (size_t)nchunk * ncols * n) g.z = nchunk;
-  double *out_partial = g.z > 1 ? partial : nullptr;
-  const size_t lds = i8_lds(n, tn);
-  const void *fn = wide ? (const void *)k_dst_i8<64> : (const void *)k_dst_i8<32>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  if (wide)
-    hipLaunchKernelGGL(k_dst_i8<64>, g, dim3(NTHR), lds, st, n, Q, (const uint2 *)rec, cols,
-                       ncols, kchunk, out_partial);
-  else
-    hipLaunchKernelGGL(k_dst_i8<32>, g, dim3(NTHR), lds, st, n, Q, (const uint2 *)rec, cols,
-                       ncols, kchunk, out_partial);
-  e = hipGetLastError();
-  if (e != hipSuccess || g.z == 1) return e;
-  hipLaunchKernelGGL(k_dst_i8_reduce, dim3(ceil_div(n, 256), ncols), dim3(256), 0, st, n, ncols,
-                     (int)g.z, (const double *)partial, cols);
-  return hipGetLastError();
+  const int npad = ceil_div(n, KCI) * KCI;
+  // the slice records of a launch's columns must fit the work buffer; larger
+  // column sets run in several launches (results per column are unchanged)
+  const int per = (int)std::min<size_t>((size_t)ncols, work_bytes / ((size_t)npad * 8));
+  if (per <= 0) return hipErrorInvalidValue;
+  for (int c0 = 0; c0 < ncols; c0 += per) {
+    const int nc = std::min(per, ncols - c0);
+    DstCol *cc = cols + c0;
+    hipLaunchKernelGGL(k_x_slices, dim3(nc), dim3(NTHR), 0, st, n, npad, cc, nc, (uint2 *)work,
+                       solves);
+    const bool wide = nc > 32 && i8_lds(n, 64) <= 160 * 1024;
+    const int tn = wide ? 64 : 32;
+    const int nchunk = ceil_div(n, kchunk);
+    dim3 g(ceil_div(n, TMI), ceil_div(nc, tn), 1);
+    if (g.x * g.y < 512 && partial && partial_elems >= (size_t)nchunk * nc * n) g.z = nchunk;
+    double *out_partial = g.z > 1 ? partial : nullptr;
+    const size_t lds = i8_lds(n, tn);
+    const void *fn = wide ? (const void *)k_dst_i8<64> : (const void *)k_dst_i8<32>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (wide)
+      hipLaunchKernelGGL(k_dst_i8<64>, g, dim3(NTHR), lds, st, n, Q, (const uint2 *)rec, cc, nc,
+                         kchunk, (const uint2 *)work, npad, out_partial);
+    else
+      hipLaunchKernelGGL(k_dst_i8<32>, g, dim3(NTHR), lds, st, n, Q, (const uint2 *)rec, cc, nc,
+                         kchunk, (const uint2 *)work, npad, out_partial);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (g.z > 1) {
+      hipLaunchKernelGGL(k_dst_i8_reduce, dim3(ceil_div(n, 256), nc), dim3(256), 0, st, n, nc,
+                         (int)g.z, (const double *)partial, cc);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
 }
 
 }  // namespace lrp

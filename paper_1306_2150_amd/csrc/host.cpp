@@ -34,15 +34,18 @@ void dev_free(lrp_ctx *ctx, void *p, size_t bytes) {
 
 hipError_t timed_dst(lrp_ctx *ctx, int prec, int n, const void *tab,
                      const DstCol *cols, int ncols, Solve2D *solves,
-                     double *partial, size_t partial_elems, hipStream_t st) {
+                     double *partial, size_t partial_elems, void *work,
+                     size_t work_bytes, hipStream_t st) {
   if (!ctx->timing)
-    return launch_dst(prec, n, tab, cols, ncols, solves, partial, partial_elems, st);
+    return launch_dst(prec, n, tab, cols, ncols, solves, partial, partial_elems, work,
+                      work_bytes, st);
   lrp_ctx::PendingTime pt;
   hipError_t e = hipEventCreate(&pt.a);
   if (e != hipSuccess) return e;
   if ((e = hipEventCreate(&pt.b)) != hipSuccess) return e;
   if ((e = hipEventRecord(pt.a, st)) != hipSuccess) return e;
-  e = launch_dst(prec, n, tab, cols, ncols, solves, partial, partial_elems, st);
+  e = launch_dst(prec, n, tab, cols, ncols, solves, partial, partial_elems, work, work_bytes,
+                 st);
   if (e != hipSuccess) return e;
   if ((e = hipEventRecord(pt.b, st)) != hipSuccess) return e;
   pt.prec = prec;
@@ -126,10 +129,17 @@ Plan make_plan(const lrp_opts *o, double eps, int n) {
   p.min_slack = std::max(1, p.kick / 2);
   p.tau = (o && o->maxvol_tau > 1.0) ? o->maxvol_tau : 1.05;
   if (prec == LRP_PREC_AUTO) {
-    // the inverse transform's relative error reaches the result undamped;
-    // the forward one is damped by the eigenvalue division
-    p.fwd_prec = eps >= 1e-6 ? LRP_PREC_BF16X3 : (eps >= 1e-7 ? LRP_PREC_FP32 : LRP_PREC_FP64);
-    p.inv_prec = eps >= 1e-7 ? LRP_PREC_FP32 : LRP_PREC_FP64;
+    if (dst_i8_fast(n)) {
+      // exact int8 slices: about 1e-12 and at least as fast as the float32
+      // and split-bfloat16 transforms wherever their wide tiles fit in LDS
+      p.fwd_prec = p.inv_prec = LRP_PREC_INT8;
+    } else {
+      // the inverse transform's relative error reaches the result undamped;
+      // the forward one is damped by the eigenvalue division, not enough
+      // for 10 eps below 1e-7
+      p.fwd_prec = eps >= 1e-6 ? LRP_PREC_BF16X3 : (eps >= 1e-7 ? LRP_PREC_FP32 : LRP_PREC_FP64);
+      p.inv_prec = eps >= 1e-7 ? LRP_PREC_FP32 : LRP_PREC_FP64;
+    }
   } else if (prec == LRP_PREC_FP32 || prec == LRP_PREC_BF16X3) {
     p.fwd_prec = p.inv_prec = prec;
   } else {
@@ -194,6 +204,7 @@ Group2D::~Group2D() {
     (void)hipStreamDestroy(stream_);
   }
   dev_free(ctx_, ws_, bytes_);
+  dev_free(ctx_, d_work_, work_bytes_);
   if (h_s_) (void)hipHostFree(h_s_);
   if (h_cols_) (void)hipHostFree(h_cols_);
 }
@@ -348,6 +359,12 @@ lrp_status Group2D::upload_all(int count, hipStream_t st) {
 }
 
 lrp_status Group2D::dst_cols(std::vector<DstCol> &cols, int prec, hipStream_t st) {
+  if (prec == LRP_PREC_INT8 && !d_work_) {
+    const size_t wb = dst_i8_work_bytes(n_, std::min(cols_cap_, 1024));
+    lrp_status e = dev_alloc(ctx_, &d_work_, wb);
+    if (e != LRP_OK) return e;
+    work_bytes_ = wb;
+  }
   size_t done = 0;
   while (done < cols.size()) {
     const int cnt = (int)std::min(cols.size() - done, (size_t)cols_cap_);
@@ -360,7 +377,7 @@ lrp_status Group2D::dst_cols(std::vector<DstCol> &cols, int prec, hipStream_t st
     std::memcpy(h, cols.data() + done, sizeof(DstCol) * cnt);
     HIPCHK(hipMemcpyAsync(d, h, sizeof(DstCol) * cnt, hipMemcpyHostToDevice, st));
     HIPCHK(timed_dst(ctx_, prec, n_, tabs_->tab, d, cnt, d_s_, d_partial_,
-                     partial_elems_, st));
+                     partial_elems_, d_work_, work_bytes_, st));
     cols_used_ += cnt;
     done += cnt;
   }
@@ -521,6 +538,19 @@ lrp_status lrp_sine_transform(lrp_ctx *ctx, int64_t n, int32_t ncols,
       return LRP_ENOMEM;
     ctx->tx_cap = chunk;
   }
+  if (prec == LRP_PREC_INT8 && !ctx->tx_work) {
+    const size_t wb = dst_i8_work_bytes((int)n, chunk);
+    if ((err = dev_alloc(ctx, &ctx->tx_work, wb)) != LRP_OK) return err;
+    ctx->tx_work_bytes = wb;
+  }
+  if (prec == LRP_PREC_INT8 && ctx->tx_work_bytes < dst_i8_work_bytes((int)n, chunk)) {
+    dev_free(ctx, ctx->tx_work, ctx->tx_work_bytes);
+    ctx->tx_work = nullptr;
+    ctx->tx_work_bytes = 0;
+    const size_t wb = dst_i8_work_bytes((int)n, chunk);
+    if ((err = dev_alloc(ctx, &ctx->tx_work, wb)) != LRP_OK) return err;
+    ctx->tx_work_bytes = wb;
+  }
   for (int c0 = 0; c0 < ncols; c0 += chunk) {
     const int cnt = std::min(chunk, ncols - c0);
     if (hipStreamSynchronize(st) != hipSuccess) return LRP_EDEVICE;
@@ -530,7 +560,8 @@ lrp_status lrp_sine_transform(lrp_ctx *ctx, int64_t n, int32_t ncols,
                        hipMemcpyHostToDevice, st) != hipSuccess)
       return LRP_EDEVICE;
     if (timed_dst(ctx, prec, (int)n, t->tab, ctx->tx_dcols, cnt, nullptr,
-                  ctx->tx_partial, ctx->tx_partial_elems, st) != hipSuccess)
+                  ctx->tx_partial, ctx->tx_partial_elems, ctx->tx_work, ctx->tx_work_bytes,
+                  st) != hipSuccess)
       return LRP_EDEVICE;
   }
   return LRP_OK;
@@ -572,6 +603,7 @@ lrp_status lrp_destroy(lrp_ctx *ctx) {
   (void)hipDeviceSynchronize();
   if (ctx->tx_dcols) dev_free(ctx, ctx->tx_dcols, ctx->tx_bytes);
   if (ctx->tx_hcols) (void)hipHostFree(ctx->tx_hcols);
+  if (ctx->tx_work) dev_free(ctx, ctx->tx_work, ctx->tx_work_bytes);
   ctx->batch_groups.clear();
   ctx->batch3_groups.clear();
   ctx->serve_groups.clear();

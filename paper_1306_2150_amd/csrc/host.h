@@ -96,6 +96,8 @@ class Group2D {
   int cols_cap_ = 0, cols_used_ = 0;
   double *d_partial_ = nullptr;
   size_t partial_elems_ = 0;
+  void *d_work_ = nullptr;         // int8 slice records (allocated on first use)
+  size_t work_bytes_ = 0;
   std::vector<Plan> plans_;
   std::vector<int> kin_;
   const GridTables *tabs_ = nullptr;
@@ -187,6 +189,8 @@ struct lrp_ctx {
   int tx_cap = 0;
   double *tx_partial = nullptr;
   size_t tx_partial_elems = 0, tx_bytes = 0;
+  void *tx_work = nullptr;
+  size_t tx_work_bytes = 0;
   // transform kernel timing (events recorded around each launch)
   bool timing = false;
   struct PendingTime {
@@ -207,7 +211,8 @@ lrp_status dev_alloc(lrp_ctx *ctx, void **p, size_t bytes);
 // launch_dst with optional event timing for the context
 hipError_t timed_dst(lrp_ctx *ctx, int prec, int n, const void *tab,
                      const DstCol *cols, int ncols, Solve2D *solves,
-                     double *partial, size_t partial_elems, hipStream_t st);
+                     double *partial, size_t partial_elems, void *work,
+                     size_t work_bytes, hipStream_t st);
 void dev_free(lrp_ctx *ctx, void *p, size_t bytes);
 // 3D helpers shared by the synchronous call and the serving loop
 lrp_status check_problem3d(int64_t n, const int32_t rank[3], const double *const U[3],

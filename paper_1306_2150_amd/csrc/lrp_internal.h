@@ -229,17 +229,22 @@ __device__ __forceinline__ int clamp_row(int i, int n) {
 
 // ----------------------------------------------------------- launchers
 // Each .hip file defines the host launchers for its kernels.
+// `work` (work_bytes) holds the int8 slice records of the columns of one
+// launch (LRP_PREC_INT8 only, see dst_i8_work_bytes).
 hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
                       int ncols, Solve2D *solves, double *partial,
-                      size_t partial_elems, hipStream_t st);
+                      size_t partial_elems, void *work, size_t work_bytes,
+                      hipStream_t st);
 size_t dst_partial_elems(int n, int ncols);
 // int8 slice transform (dst_i8.hip): record table of the sines, support
 bool dst_i8_supported(int n);
+bool dst_i8_fast(int n);   // the 64-column tiles fit (n up to about 6600)
 size_t dst_i8_table_bytes(int n);
 void dst_i8_table(int n, unsigned char *out);
+size_t dst_i8_work_bytes(int n, int ncols);
 hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, int kchunk,
                          Solve2D *solves, double *partial, size_t partial_elems,
-                         hipStream_t st);
+                         void *work, size_t work_bytes, hipStream_t st);
 
 // Row counts: calls on the column side (Xh[:, J], Q0, A) cover the n rows,
 // calls on the row side (Xh[I, :]^T, Q1, B, Vh) the m columns.

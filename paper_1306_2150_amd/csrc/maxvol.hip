@@ -8,7 +8,8 @@
 //  1. starting rows: Gaussian elimination with partial pivoting run as a
 //     tournament -- every 256-row block selects its pivot rows, internal
 //     nodes run the elimination again on the union of their children's
-//     candidates;
+//     candidates (first sweep and after rank growth; otherwise the rows of
+//     the same maxvol in the previous sweep);
 //  2. Inv = Q[I,:]^-1 (Gauss-Jordan, partial pivoting), then rounds of:
 //     every block forms its rows of B = Q Inv and reports its largest
 //     entries above tau; one workgroup runs the classical swap loop (swap the
@@ -37,6 +38,14 @@ __device__ inline int mv_phase(int which) {
   return which == MV_Q1_TO_J ? ACT_INIT : ACT_SWEEP;
 }
 
+// A sweep that kept the cross rank starts its maxvol from the rows the same
+// maxvol chose in the previous sweep (the bases move little between sweeps,
+// so those rows are nearly maximal-volume already); the tournament only
+// runs on the first sweep and after the rank grew.
+__device__ inline bool mv_warm(const Solve2D &s, int which) {
+  return which != MV_Q1_TO_J && s.sweep >= 1 && s.kp == s.k;
+}
+
 __device__ inline size_t piv_off(const Tree &t, int l) {
   size_t o = 0;
   for (int i = 0; i < l; ++i) o += (size_t)t.nb[i] * KMAX;
@@ -53,7 +62,8 @@ __global__ __launch_bounds__(NTHR) void k_mv_leaf(int which, int n, Tree tr,
   __shared__ int shp[2];
   __shared__ int piv[KMAX];
   const int kk = s.k;
-  if (threadIdx.x == 0) s.mv_done = 0, s.mv_swaps = 0;
+  if (threadIdx.x == 0 && blockIdx.x == 0) s.mv_done = 0, s.mv_swaps = 0;
+  if (mv_warm(s, which)) return;
   const MvIO io = mv_io(which, s);
   const int b = blockIdx.x, r0 = b * PANEL_M;
   const int m = min(PANEL_M, n - r0);
@@ -70,7 +80,7 @@ template <int NS>
 __global__ __launch_bounds__(NTHR) void k_mv_node(int which, int n, int lev,
                                                  Tree tr, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
-  if (s.active != mv_phase(which)) return;
+  if (s.active != mv_phase(which) || mv_warm(s, which)) return;
   __shared__ double lbuf[2 * PANEL_M];
   __shared__ int shp[2];
   __shared__ int piv[KMAX];

@@ -98,7 +98,7 @@ def solve_and_check(U, V, eps, prec="fp64", bar=None, **kw):
     assert e <= bar, (e, info)
     if Vx.shape[1]:
         # orthonormal to the precision of the inverse transform
-        otol = {"fp64": 1e-10, "fp32": 1e-6, "bf16x3": 1e-4}[info["inv_prec"]]
+        otol = {"fp64": 1e-10, "int8": 1e-10, "fp32": 1e-6, "bf16x3": 1e-4}[info["inv_prec"]]
         assert np.max(np.abs(Vx.T @ Vx - np.eye(Vx.shape[1]))) < otol
     return e, info
 
