@@ -15,8 +15,8 @@
 //   acc_t[j] = sum_k sum_{a+b=t} T_a[j,k] X_b[k].
 //
 // A first pass writes every column's reversed slice records (8 bytes per
-// point); the GEMM stages them in LDS as the six byte windows below, so its
-// inner loop only reads ready MFMA operands.
+// point); the GEMM stages them in LDS as two dword planes and forms the six
+// byte windows below in registers (v_alignbyte).
 //
 // MFMA formulation (v_mfma_i32_16x16x64_i8): the 64-deep MFMA K runs over 16
 // grid points k times 4 slice positions.  Lane (i, g) of the A operand holds,
@@ -107,16 +107,19 @@ __global__ __launch_bounds__(NTHR) void k_x_slices(int n, int npad, DstCol *cols
   for (int k = threadIdx.x; k < npad; k += NTHR) o[k] = slice_record(k < n ? x[k] : 0.0, e);
 }
 
-template <int TN_>
+// FULL: the LDS table holds the records of all m in [0, 2N) (no folding in
+// the inner loop); otherwise the quarter wave q in [0, N/2] with both signs.
+template <int TN_, bool FULL>
 __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__restrict__ rec,
                                                 const DstCol *__restrict__ cols, int ncols,
                                                 int kchunk, const uint2 *__restrict__ xrec,
                                                 int npad, double *__restrict__ partial) {
   constexpr int NB = TN_ / 16;
   extern __shared__ __align__(16) unsigned char smem[];
-  uint2 *tab = (uint2 *)smem;                    // [q][sign] records
-  uint32_t *xs0 = (uint32_t *)(tab + 2 * Q);     // [level][c][k] windows x 2 buffers
   const int N = n + 1, twoN = 2 * N;
+  const int ntab = FULL ? twoN : 2 * Q;
+  uint2 *tab = (uint2 *)smem;                    // records, see FULL
+  uint32_t *xs0 = (uint32_t *)(tab + ntab);      // record planes [c][k] x 2 buffers
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int row0 = blockIdx.x * TMI, c0 = blockIdx.y * TN_;
   int cb, ce;
@@ -127,10 +130,10 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
     cb = 0;
     ce = (n + kchunk - 1) / kchunk;
   }
-  for (int i = tid; i < 2 * Q; i += NTHR) tab[i] = rec[i];
+  for (int i = tid; i < ntab; i += NTHR) tab[i] = rec[i];
   // staging share: thread stages grid points tk, columns tc0 + 8 t
   constexpr int PER = KCI * TN_ / NTHR;
-  constexpr int LVL = TN_ * XST;                 // dwords per level and buffer
+  constexpr int LVL = TN_ * XST;                 // dwords per record plane and buffer
   const int tk = tid & (KCI - 1), tc0 = tid / KCI;
   const uint2 *src[PER];
 #pragma unroll
@@ -147,19 +150,15 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
     for (int t = 0; t < PER; ++t)
       pre[t] = (src[t] && k < kend) ? src[t][k] : make_uint2(0u, 0u);
   };
-  // windows t of [X5 .. X0 0 0 0]: bytes [X_t X_(t-1) X_(t-2) X_(t-3)]
+  // the two dwords of the records in two planes [c][k], so that one 16-byte
+  // read gives a dword of four consecutive points
   auto stash = [&](int st) {
-    uint32_t *xs = xs0 + (st & 1) * 6 * LVL;
+    uint32_t *xs = xs0 + (st & 1) * 2 * LVL;
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
-      const uint32_t d0 = pre[t].x, d1 = pre[t].y;
       uint32_t *p = xs + (tc0 + (NTHR / KCI) * t) * XST + tk;
-      p[5 * LVL] = d0;
-      p[4 * LVL] = __builtin_amdgcn_alignbyte(d1, d0, 1);
-      p[3 * LVL] = __builtin_amdgcn_alignbyte(d1, d0, 2);
-      p[2 * LVL] = __builtin_amdgcn_alignbyte(d1, d0, 3);
-      p[1 * LVL] = d1;
-      p[0] = d1 >> 8;
+      p[0] = pre[t].x;
+      p[LVL] = pre[t].y;
     }
   };
   // rows of this lane: j = row0 + 32 wave + 16 h + (lane & 15) + 1 (1-based)
@@ -223,7 +222,7 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
     const int k0 = kbeg + st * KCI;
     if (st > 0 && (k0 % kchunk) == 0) flush();
     if (st + 1 < nst) fetch(st + 1);
-    const uint32_t *xs = xs0 + (st & 1) * 6 * LVL;
+    const uint32_t *xs = xs0 + (st & 1) * 2 * LVL;
     const int kcn = min(KCI, kend - k0);
     for (int kk = 0; kk < kcn; kk += 16) {
       // A operands: records of points k0 + kk + 4g + e (1-based k)
@@ -235,14 +234,19 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
         if (mk[h] >= twoN) mk[h] -= twoN;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          int mm = m, sg = 0;
-          if (mm >= N) {
-            mm -= N;
-            sg = 1;
+          uint2 r;
+          if (FULL) {
+            r = tab[m];
+          } else {
+            int mm = m, sg = 0;
+            if (mm >= N) {
+              mm -= N;
+              sg = 1;
+            }
+            if (2 * mm > N) mm = N - mm;
+            r = tab[2 * mm + sg];
           }
-          if (2 * mm > N) mm = N - mm;
           // points past the end of K contribute zero through the B side
-          const uint2 r = tab[2 * mm + sg];
           ahi[h][e] = (int)r.x;
           alo[h][e] = (int)r.y;
           m += jr[h];
@@ -251,11 +255,20 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
       }
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        // window t of points kk + 4g .. +3 of column 16 b + li
+        // records of points kk + 4g .. +3 of column 16 b + li, and their
+        // windows t of [X5 .. X0 0 0 0]: bytes [X_t X_(t-1) X_(t-2) X_(t-3)]
         const uint32_t *xw = xs + (16 * b + li) * XST + kk + 4 * g;
+        const v4i d0 = *(const v4i *)xw, d1 = *(const v4i *)(xw + LVL);
         v4i w[6];
+        w[5] = d0;
+        w[1] = d1;
 #pragma unroll
-        for (int t = 0; t < 6; ++t) w[t] = *(const v4i *)(xw + t * LVL);
+        for (int e = 0; e < 4; ++e) {
+          w[4][e] = (int)__builtin_amdgcn_alignbyte((uint32_t)d1[e], (uint32_t)d0[e], 1);
+          w[3][e] = (int)__builtin_amdgcn_alignbyte((uint32_t)d1[e], (uint32_t)d0[e], 2);
+          w[2][e] = (int)__builtin_amdgcn_alignbyte((uint32_t)d1[e], (uint32_t)d0[e], 3);
+          w[0][e] = (int)((uint32_t)d1[e] >> 8);
+        }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
 #pragma unroll
@@ -302,39 +315,55 @@ __global__ void k_dst_i8_reduce(int n, int ncols, int nz, const double *__restri
 
 }  // namespace
 
-size_t dst_i8_table_bytes(int n) {
-  const int Q = (n + 1) / 2 + 1;
-  return (size_t)Q * 2 * 8;
+// Two record tables of sin(pi m/N) slices, bytes [T_0 T_1 T_2 T_3 | T_4 T_5 0 0]:
+// the quarter wave with both signs, rec[2q + s] for q = 0 .. N/2, followed by
+// the full period, rec[m] for m = 0 .. 2N-1.
+static size_t i8_quarter_bytes(int n) { return (size_t)((n + 1) / 2 + 1) * 2 * 8; }
+static size_t i8_full_bytes(int n) { return (size_t)2 * (n + 1) * 8; }
+
+size_t dst_i8_table_bytes(int n) { return i8_quarter_bytes(n) + i8_full_bytes(n); }
+
+static void slice_sine(long double v, unsigned char *o) {
+  long double w = v * 64.0L;
+  signed char sl[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int a = 0; a < 6; ++a) {
+    const long double r = roundl(w);
+    sl[a] = (signed char)(long)r;
+    w = (w - r) * 128.0L;
+  }
+  for (int a = 0; a < 8; ++a) o[a] = (unsigned char)sl[a];
 }
 
-// Records of sin(pi q/N), q = 0 .. N/2, and their negatives:
-// rec[2q + s] = bytes [T_0 T_1 T_2 T_3 | T_4 T_5 0 0] of (-1)^s sin(pi q/N).
 void dst_i8_table(int n, unsigned char *out) {
   const int N = n + 1, Q = N / 2 + 1;
   const long double pi = 3.14159265358979323846264338327950288L;
   for (int q = 0; q < Q; ++q) {
     const long double v = sinl(pi * (long double)q / (long double)N);
-    for (int sgn = 0; sgn < 2; ++sgn) {
-      long double w = (sgn ? -v : v) * 64.0L;
-      signed char sl[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-      for (int a = 0; a < 6; ++a) {
-        const long double r = roundl(w);
-        sl[a] = (signed char)(long)r;
-        w = (w - r) * 128.0L;
-      }
-      unsigned char *o = out + ((size_t)2 * q + sgn) * 8;
-      for (int a = 0; a < 8; ++a) o[a] = (unsigned char)sl[a];
+    slice_sine(v, out + ((size_t)2 * q) * 8);
+    slice_sine(-v, out + ((size_t)2 * q + 1) * 8);
+  }
+  unsigned char *full = out + i8_quarter_bytes(n);
+  for (int m = 0; m < 2 * N; ++m) {
+    // sin(pi m/N) from the quarter wave, so both tables hold identical slices
+    int mm = m;
+    bool neg = false;
+    if (mm >= N) {
+      mm -= N;
+      neg = true;
     }
+    if (2 * mm > N) mm = N - mm;
+    const long double v = sinl(pi * (long double)mm / (long double)N);
+    slice_sine(neg ? -v : v, full + (size_t)m * 8);
   }
 }
 
-static size_t i8_lds(int n, int tn) {
-  const int Q = (n + 1) / 2 + 1;
-  return (size_t)Q * 2 * 8 + (size_t)2 * 6 * tn * XST * 4;
+static size_t i8_lds(int n, int tn, bool full) {
+  return (full ? i8_full_bytes(n) : i8_quarter_bytes(n)) + (size_t)2 * 2 * tn * XST * 4;
 }
 
-bool dst_i8_supported(int n) { return i8_lds(n, 32) <= 160 * 1024; }
-bool dst_i8_fast(int n) { return i8_lds(n, 64) <= 160 * 1024; }
+constexpr size_t LDS_MAX = 160 * 1024;
+bool dst_i8_supported(int n) { return i8_lds(n, 32, false) <= LDS_MAX; }
+bool dst_i8_fast(int n) { return i8_lds(n, 64, false) <= LDS_MAX; }
 
 size_t dst_i8_work_bytes(int n, int ncols) {
   const int npad = ceil_div(n, KCI) * KCI;
@@ -357,22 +386,28 @@ hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, int kc
     DstCol *cc = cols + c0;
     hipLaunchKernelGGL(k_x_slices, dim3(nc), dim3(NTHR), 0, st, n, npad, cc, nc, (uint2 *)work,
                        solves);
-    const bool wide = nc > 32 && i8_lds(n, 64) <= 160 * 1024;
+    const bool wide = nc > 32 && i8_lds(n, 64, false) <= LDS_MAX;
     const int tn = wide ? 64 : 32;
+    const bool full = i8_lds(n, tn, true) <= LDS_MAX;
+    const unsigned char *tabs = (const unsigned char *)rec;
+    const uint2 *trec = (const uint2 *)(full ? tabs + i8_quarter_bytes(n) : tabs);
     const int nchunk = ceil_div(n, kchunk);
     dim3 g(ceil_div(n, TMI), ceil_div(nc, tn), 1);
     if (g.x * g.y < 512 && partial && partial_elems >= (size_t)nchunk * nc * n) g.z = nchunk;
     double *out_partial = g.z > 1 ? partial : nullptr;
-    const size_t lds = i8_lds(n, tn);
-    const void *fn = wide ? (const void *)k_dst_i8<64> : (const void *)k_dst_i8<32>;
+    const size_t lds = i8_lds(n, tn, full);
+    const void *fn = wide ? (full ? (const void *)k_dst_i8<64, true> : (const void *)k_dst_i8<64, false>)
+                          : (full ? (const void *)k_dst_i8<32, true> : (const void *)k_dst_i8<32, false>);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    if (wide)
-      hipLaunchKernelGGL(k_dst_i8<64>, g, dim3(NTHR), lds, st, n, Q, (const uint2 *)rec, cc, nc,
-                         kchunk, (const uint2 *)work, npad, out_partial);
-    else
-      hipLaunchKernelGGL(k_dst_i8<32>, g, dim3(NTHR), lds, st, n, Q, (const uint2 *)rec, cc, nc,
-                         kchunk, (const uint2 *)work, npad, out_partial);
+#define LRP_I8_LAUNCH(TNV, FV)                                                              \
+  hipLaunchKernelGGL((k_dst_i8<TNV, FV>), g, dim3(NTHR), lds, st, n, Q, trec, cc, nc, kchunk, \
+                     (const uint2 *)work, npad, out_partial)
+    if (wide && full) LRP_I8_LAUNCH(64, true);
+    else if (wide) LRP_I8_LAUNCH(64, false);
+    else if (full) LRP_I8_LAUNCH(32, true);
+    else LRP_I8_LAUNCH(32, false);
+#undef LRP_I8_LAUNCH
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (g.z > 1) {
