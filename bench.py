@@ -30,9 +30,43 @@ sys.path.insert(0, ROOT)
 # The served stream runs one stream per slot group (up to eight groups); give
 # each its own hardware queue so that a long 3D launch never sits in front of
 # another group's short ones (HIP reads this when it initialises).
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+if int(os.environ.get("GPU_MAX_HW_QUEUES") or 0) < 16:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "int8": 5.0e15}
+
+# HBM bytes moved per launch of a transform kernel in this workload, from two
+# rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
+# dispatch averaged over the kernel's dispatches), each scaled by what the same
+# counter reads for a plain device copy of 1 GiB (FETCH_SIZE reads half the
+# copied bytes: x2; WRITE_SIZE reads them exactly: x1).  A figure holds only
+# for the kernel source it was taken on (the sha1 over the listed sources must
+# match) and for launches of the same average column count (batch 256 of the
+# default workload); otherwise the traffic is reported as null.
+TRAFFIC = {
+    "k_dst_i8": {"sources": ["dst_i8.hip", "lrp_internal.h"],
+                 "sha1": "2728fdbb738b0c3194311ca190bdbec3e27e057f",
+                 "columns": 10488, "fetch_kib": 172332.6, "write_kib": 335616.0},
+    "k_dst_f64": {"sources": ["dst.hip", "lrp_internal.h"],
+                  "sha1": "a5b9b596caeea7760e4d6a641ee4dc2d33332d59",
+                  "columns": 10500, "fetch_kib": 1346979.3, "write_kib": 336000.1},
+}
+
+
+def traffic_bytes(kernel, columns):
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if not t or t["sha1"] is None or abs(columns - t["columns"]) > 0.5:
+        return None
+    h = hashlib.sha1()
+    for f in t["sources"]:
+        with open(os.path.join(ROOT, "paper_1306_2150_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != t["sha1"]:
+        return None
+    return (2.0 * t["fetch_kib"] + 1.0 * t["write_kib"]) * 1024.0
+
+
 METRIC = "2D n=4096 r=16 solves/s at rel err<=1e-7, mixed vs FP64 path; served p99 ms"
 
 
@@ -48,6 +82,8 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=6)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="copy this many MiB once first (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -83,6 +119,13 @@ def main():
     from paper_1306_2150_amd import binding, inputs
 
     torch.cuda.set_device(0)
+    if args.copy_probe_mb:
+        # a plain device copy of known size, for scaling the HBM byte counters
+        a = torch.ones(args.copy_probe_mb << 17, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     ctx = binding.Context(0, workspace_bytes=64 << 30)
     n, r, eps = 4096, 16, 1e-8
     B = args.batch
@@ -136,10 +179,18 @@ def main():
     kauto = out["auto"]["ks"]
     if kauto["int8"]["launches"]:
         roofline = kstat_roof(kauto["int8"], "k_dst_i8", PEAK["int8"], "TOP/s", 32.0)
+        # algorithmic HBM bytes of one launch: each column's slice records
+        # (8 bytes per padded grid point) in, its float64 transform out
+        npad = -(-n // 32) * 32
+        roofline["algorithmic_bytes"] = roofline["columns_per_launch"] * (npad * 8 + n * 8)
+        roofline["traffic"] = traffic_bytes("k_dst_i8", roofline["columns_per_launch"])
     else:
         roofline = kstat_roof(kauto["fp64"], "k_dst_f64", PEAK["fp64"], "TFLOP/s", 1.0)
     roofline["fp64_plan_kernel"] = kstat_roof(out["fp64"]["ks"]["fp64"], "k_dst_f64",
                                               PEAK["fp64"], "TFLOP/s", 1.0)
+    f64 = roofline["fp64_plan_kernel"]
+    f64["algorithmic_bytes"] = f64["columns_per_launch"] * n * 16
+    f64["traffic"] = traffic_bytes("k_dst_f64", f64["columns_per_launch"])
 
     line = {
         "metric": METRIC,

@@ -124,7 +124,9 @@ __global__ __launch_bounds__(NTHR) void k_dst_f64(
   double *xs0 = tab + Qp;                         // [TN][LDT] x 2 buffers
   const int N = n + 1, twoN = 2 * N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int row0 = blockIdx.x * TM64, c0 = blockIdx.y * TN_;
+  int rt, ct;
+  if (!tile_of(ceil_div(n, TM64), ceil_div(ncols, TN_), false, rt, ct)) return;
+  const int row0 = rt * TM64, c0 = ct * TN_;
   int cb, ce;
   chunk_range(n, kchunk, cb, ce);
   for (int i = tid; i < Q; i += NTHR) tab[i] = qtab[i];
@@ -273,7 +275,9 @@ __global__ __launch_bounds__(NTHR) void k_dst_f32(
   float *xs0 = tab + Qp;                          // [TN][LDT32] x 2 buffers
   const int N = n + 1, twoN = 2 * N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int row0 = blockIdx.x * TM64, c0 = blockIdx.y * TN_;
+  int rt, ct;
+  if (!tile_of(ceil_div(n, TM64), ceil_div(ncols, TN_), false, rt, ct)) return;
+  const int row0 = rt * TM64, c0 = ct * TN_;
   int cb, ce;
   chunk_range(n, kchunk, cb, ce);
   for (int i = tid; i < Q; i += NTHR) tab[i] = qtab[i];
@@ -425,7 +429,9 @@ __global__ __launch_bounds__(NTHR) void k_dst_bf16x3(
   uint16_t *xlo = xhi + TN * KC;
   const int N = n + 1, twoN = 2 * N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int row0 = blockIdx.x * TM, c0 = blockIdx.y * TN;
+  int rt, ct;
+  if (!tile_of(ceil_div(n, TM), ceil_div(ncols, TN), true, rt, ct)) return;
+  const int row0 = rt * TM, c0 = ct * TN;
   int cb, ce;
   chunk_range(n, kchunk, cb, ce);
   for (int i = tid; i < Q; i += NTHR) tab[i] = qtab[i];
@@ -537,7 +543,7 @@ size_t dst_partial_elems(int n, int ncols) {
 hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
                       int ncols, Solve2D *solves, double *partial,
                       size_t partial_elems, void *work, size_t work_bytes,
-                      hipStream_t st) {
+                      hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (ncols <= 0) return hipSuccess;
   const int Q = quarter_len(n);
   const int gx = ceil_div(n, TM), gy = ceil_div(ncols, TN);
@@ -550,7 +556,7 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
       partial_elems < (size_t)split * (size_t)ncols * (size_t)n)
     split = 1;
   double *out_partial = split > 1 ? partial : nullptr;
-  dim3 grid(gx, gy, split), block(NTHR);
+  dim3 grid(tile_grid(gx, gy, true), 1, split), block(NTHR);
   size_t lds = 0;
   hipError_t e = hipSuccess;
   const char *base = (const char *)tab;
@@ -558,20 +564,23 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
   // table layout: [f64 x Qp8][f32 x Qp4][u32 x Qp4][int8 records]
   if (prec == LRP_PREC_INT8)
     return launch_dst_i8(n, base + (size_t)Qp8 * 8 + (size_t)Qp4 * 8, (DstCol *)cols, ncols,
-                         kchunk, solves, partial, partial_elems, work, work_bytes, st);
+                         kchunk, solves, partial, partial_elems, work, work_bytes, st, ev0,
+                         ev1);
   const double *t64 = (const double *)base;
   const float *t32 = (const float *)(base + (size_t)Qp8 * 8);
   const uint32_t *tbf = (const uint32_t *)(base + (size_t)Qp8 * 8 + (size_t)Qp4 * 4);
   if (prec == LRP_PREC_FP64) {
     const bool wide = ncols > 32;
     const int tn = wide ? 64 : 32;
-    dim3 g64(ceil_div(n, TM64), ceil_div(ncols, tn), grid.z);
-    if (g64.x * g64.y >= 512) g64.z = 1;
+    const int R64 = ceil_div(n, TM64), C64 = ceil_div(ncols, tn);
+    dim3 g64(tile_grid(R64, C64, false), 1, grid.z);
+    if (R64 * C64 >= 512) g64.z = 1;
     if (g64.z == 1) out_partial = nullptr;
     lds = (size_t)Qp8 * 8 + (size_t)2 * tn * LDT * 8;
     const void *fn = wide ? (const void *)k_dst_f64<64> : (const void *)k_dst_f64<32>;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
+    if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
     if (wide)
       hipLaunchKernelGGL(k_dst_f64<64>, g64, block, lds, st, n, Q, t64, cols, ncols,
                          kchunk, out_partial, solves);
@@ -582,13 +591,15 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
   } else if (prec == LRP_PREC_FP32) {
     const bool wide = ncols > 32;
     const int tn = wide ? 64 : 32;
-    dim3 g32(ceil_div(n, TM64), ceil_div(ncols, tn), grid.z);
-    if (g32.x * g32.y >= 512) g32.z = 1;
+    const int R32 = ceil_div(n, TM64), C32 = ceil_div(ncols, tn);
+    dim3 g32(tile_grid(R32, C32, false), 1, grid.z);
+    if (R32 * C32 >= 512) g32.z = 1;
     if (g32.z == 1) out_partial = nullptr;
     lds = (size_t)Qp4 * 4 + (size_t)2 * tn * LDT32 * 4;
     const void *fn = wide ? (const void *)k_dst_f32<64> : (const void *)k_dst_f32<32>;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
+    if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
     if (wide)
       hipLaunchKernelGGL(k_dst_f32<64>, g32, block, lds, st, n, Q, t32, cols, ncols,
                          kchunk, out_partial, solves);
@@ -601,11 +612,14 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
     e = hipFuncSetAttribute((const void *)k_dst_bf16x3,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
+    if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_dst_bf16x3, grid, block, lds, st, n, Q, tbf, cols,
                        ncols, kchunk, out_partial, solves);
   }
   e = hipGetLastError();
-  if (e != hipSuccess || split == 1) return e;
+  if (e != hipSuccess) return e;
+  if (ev1 && (e = hipEventRecord(ev1, st)) != hipSuccess) return e;
+  if (split == 1) return e;
   dim3 rg(ceil_div(n, 256), ncols);
   hipLaunchKernelGGL(k_dst_reduce, rg, dim3(256), 0, st, n, ncols, split,
                      (const double *)partial, cols);

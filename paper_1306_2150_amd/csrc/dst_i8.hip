@@ -121,7 +121,9 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
   uint2 *tab = (uint2 *)smem;                    // records, see FULL
   uint32_t *xs0 = (uint32_t *)(tab + ntab);      // record planes [c][k] x 2 buffers
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int row0 = blockIdx.x * TMI, c0 = blockIdx.y * TN_;
+  int rt, ct;
+  if (!tile_of(ceil_div(n, TMI), ceil_div(ncols, TN_), true, rt, ct)) return;
+  const int row0 = rt * TMI, c0 = ct * TN_;
   int cb, ce;
   if (gridDim.z > 1) {
     cb = blockIdx.z;
@@ -370,9 +372,16 @@ size_t dst_i8_work_bytes(int n, int ncols) {
   return (size_t)ncols * npad * 8;
 }
 
+int dst_i8_work_cols(int n, int want) {
+  const size_t per = (size_t)ceil_div(n, KCI) * KCI * 8;
+  const int cap = (int)std::max<size_t>(1024, ((size_t)512 << 20) / per);
+  return std::min(want, cap);
+}
+
 hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, int kchunk,
                          Solve2D *solves, double *partial, size_t partial_elems,
-                         void *work, size_t work_bytes, hipStream_t st) {
+                         void *work, size_t work_bytes, hipStream_t st, hipEvent_t ev0,
+                         hipEvent_t ev1) {
   if (ncols <= 0) return hipSuccess;
   if (!dst_i8_supported(n)) return hipErrorInvalidValue;
   const int Q = (n + 1) / 2 + 1;
@@ -392,14 +401,16 @@ hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, int kc
     const unsigned char *tabs = (const unsigned char *)rec;
     const uint2 *trec = (const uint2 *)(full ? tabs + i8_quarter_bytes(n) : tabs);
     const int nchunk = ceil_div(n, kchunk);
-    dim3 g(ceil_div(n, TMI), ceil_div(nc, tn), 1);
-    if (g.x * g.y < 512 && partial && partial_elems >= (size_t)nchunk * nc * n) g.z = nchunk;
+    const int R = ceil_div(n, TMI), C = ceil_div(nc, tn);
+    dim3 g(tile_grid(R, C, true), 1, 1);
+    if (R * C < 512 && partial && partial_elems >= (size_t)nchunk * nc * n) g.z = nchunk;
     double *out_partial = g.z > 1 ? partial : nullptr;
     const size_t lds = i8_lds(n, tn, full);
     const void *fn = wide ? (full ? (const void *)k_dst_i8<64, true> : (const void *)k_dst_i8<64, false>)
                           : (full ? (const void *)k_dst_i8<32, true> : (const void *)k_dst_i8<32, false>);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
+    if (ev0 && c0 == 0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
 #define LRP_I8_LAUNCH(TNV, FV)                                                              \
   hipLaunchKernelGGL((k_dst_i8<TNV, FV>), g, dim3(NTHR), lds, st, n, Q, trec, cc, nc, kchunk, \
                      (const uint2 *)work, npad, out_partial)
@@ -410,6 +421,7 @@ hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, int kc
 #undef LRP_I8_LAUNCH
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (ev1 && c0 + nc >= ncols && (e = hipEventRecord(ev1, st)) != hipSuccess) return e;
     if (g.z > 1) {
       hipLaunchKernelGGL(k_dst_i8_reduce, dim3(ceil_div(n, 256), nc), dim3(256), 0, st, n, nc,
                          (int)g.z, (const double *)partial, cc);

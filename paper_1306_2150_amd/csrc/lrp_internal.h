@@ -221,6 +221,36 @@ __device__ __forceinline__ double bcast_f64(double v, int src) {
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// Tile order of a GEMM-like launch of R x C tiles (R row tiles, C column
+// tiles) on a 1D grid.  Workgroup L is dispatched to XCD L mod 8, and each
+// XCD has its own L2.
+//  - XCD order (xcd = true): the tiles, numbered column tile by column tile
+//    (t = ct * R + rt), are cut into 8 contiguous ranges and XCD x runs range
+//    x in order.  The row tiles of a column tile then share one L2, so a
+//    column's data is fetched from HBM about once instead of once per XCD;
+//    with fewer than 8 column tiles the row tiles of one column tile are
+//    spread over all XCDs.
+//  - plain order (xcd = false): tile t = L, i.e. consecutive workgroups take
+//    consecutive row tiles and every XCD sees every column tile.
+// Returns false for the padding workgroups of the XCD order.
+__device__ __forceinline__ bool tile_of(int R, int C, bool xcd, int &rt, int &ct) {
+  const int L = blockIdx.x, T = R * C;
+  int t = L;
+  if (xcd) {
+    const int per = (T + 7) >> 3;
+    const int j = L >> 3;
+    t = (L & 7) * per + j;
+    if (j >= per) return false;
+  }
+  if (t >= T) return false;
+  rt = t % R;
+  ct = t / R;
+  return true;
+}
+inline int tile_grid(int R, int C, bool xcd) {
+  return xcd ? 8 * ceil_div(R * C, 8) : R * C;
+}
+
 // Row index from a pivot array, kept inside [0, n) so that a bookkeeping
 // error can never turn into an out-of-bounds access.
 __device__ __forceinline__ int clamp_row(int i, int n) {
@@ -230,11 +260,14 @@ __device__ __forceinline__ int clamp_row(int i, int n) {
 // ----------------------------------------------------------- launchers
 // Each .hip file defines the host launchers for its kernels.
 // `work` (work_bytes) holds the int8 slice records of the columns of one
-// launch (LRP_PREC_INT8 only, see dst_i8_work_bytes).
+// launch (LRP_PREC_INT8 only, see dst_i8_work_bytes).  When ev0/ev1 are
+// given they are recorded on `st` right before the first and right after the
+// last launch of the transform's GEMM kernel (slicing and split-K reduction
+// outside the window when the columns fit one launch).
 hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
                       int ncols, Solve2D *solves, double *partial,
                       size_t partial_elems, void *work, size_t work_bytes,
-                      hipStream_t st);
+                      hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 size_t dst_partial_elems(int n, int ncols);
 // int8 slice transform (dst_i8.hip): record table of the sines, support
 bool dst_i8_supported(int n);
@@ -242,9 +275,13 @@ bool dst_i8_fast(int n);   // the 64-column tiles fit (n up to about 6600)
 size_t dst_i8_table_bytes(int n);
 void dst_i8_table(int n, unsigned char *out);
 size_t dst_i8_work_bytes(int n, int ncols);
+// columns whose slice records one work buffer holds: `want`, capped so that
+// the buffer stays within 512 MiB, but never below 1024
+int dst_i8_work_cols(int n, int want);
 hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, int kchunk,
                          Solve2D *solves, double *partial, size_t partial_elems,
-                         void *work, size_t work_bytes, hipStream_t st);
+                         void *work, size_t work_bytes, hipStream_t st,
+                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
 // Row counts: calls on the column side (Xh[:, J], Q0, A) cover the n rows,
 // calls on the row side (Xh[I, :]^T, Q1, B, Vh) the m columns.
