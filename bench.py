@@ -45,11 +45,11 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "int8": 5.0e15}
 # default workload); otherwise the traffic is reported as null.
 TRAFFIC = {
     "k_dst_i8": {"sources": ["dst_i8.hip", "lrp_internal.h"],
-                 "sha1": "2728fdbb738b0c3194311ca190bdbec3e27e057f",
-                 "columns": 10488, "fetch_kib": 172332.6, "write_kib": 335616.0},
+                 "sha1": "135ee5de7d9c45f71658324ec5dc30cdf12bcf4d",
+                 "columns": 10492, "fetch_kib": 173894.9, "write_kib": 372218.7},
     "k_dst_f64": {"sources": ["dst.hip", "lrp_internal.h"],
-                  "sha1": "a5b9b596caeea7760e4d6a641ee4dc2d33332d59",
-                  "columns": 10500, "fetch_kib": 1346979.3, "write_kib": 336000.1},
+                  "sha1": "bcfb909f2c68f0231a2a7e6230cce57896723240",
+                  "columns": 10492, "fetch_kib": 169046.4, "write_kib": 335744.0},
 }
 
 
@@ -163,26 +163,31 @@ def main():
 
     # roofline of the dominant kernel of the measured (AUTO) step: the int8
     # slice transform (the float64 transform of the FP64 plan beside it).
-    # Algorithmic work per transformed column of length n: the dense DST GEMM
-    # is 2 n^2 flops; the int8 slice scheme executes it as 8 v_mfma_i32_16x16x64
-    # per 16 grid points and 16 x 16 output tile, i.e. 32 x 2 n^2 int8 ops.
+    # Algorithmic work per transformed column of length n: the folded DST is
+    # two half-size GEMMs, 2 (H0^2 + H1^2) flops with H0 = ceil(n/2), H1 =
+    # floor(n/2) (the library's flop count); the int8 slice scheme executes it
+    # as 8 v_mfma_i32_16x16x64 per 16 grid points and 16 x 16 output tile,
+    # i.e. 32 int8 ops per flop.  dense_equiv_tflops counts the unfolded
+    # 2 n^2 flops per column.
     def kstat_roof(ks, name, peak, unit, ops_per_flop):
         launches = max(1, ks["launches"])
         avg_ms = ks["ms"] / launches
         flops = ks["flops"] / launches
+        cols = ks["columns"] / launches
         ach = flops * ops_per_flop / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
+        dense = 2.0 * n * n * cols / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
         return {"kernel": name, "bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12,
                 "unit": unit, "frac": ach / peak, "traffic": None,
                 "avg_launch_ms": avg_ms, "launches": ks["launches"],
-                "columns_per_launch": ks["columns"] / launches,
-                "dense_equiv_tflops": (flops / (avg_ms * 1e-3) / 1e12) if avg_ms > 0 else 0.0}
+                "columns_per_launch": cols, "dense_equiv_tflops": dense}
     kauto = out["auto"]["ks"]
     if kauto["int8"]["launches"]:
         roofline = kstat_roof(kauto["int8"], "k_dst_i8", PEAK["int8"], "TOP/s", 32.0)
-        # algorithmic HBM bytes of one launch: each column's slice records
-        # (8 bytes per padded grid point) in, its float64 transform out
-        npad = -(-n // 32) * 32
-        roofline["algorithmic_bytes"] = roofline["columns_per_launch"] * (npad * 8 + n * 8)
+        # algorithmic HBM bytes of one launch: each column's two parity slice
+        # records (8 bytes per point, each padded to 32 points) and their two
+        # exponents in, its float64 transform out
+        hpad = -(-((n + 1) // 2) // 32) * 32
+        roofline["algorithmic_bytes"] = roofline["columns_per_launch"] * (2 * hpad * 8 + 8 + n * 8)
         roofline["traffic"] = traffic_bytes("k_dst_i8", roofline["columns_per_launch"])
     else:
         roofline = kstat_roof(kauto["fp64"], "k_dst_f64", PEAK["fp64"], "TFLOP/s", 1.0)

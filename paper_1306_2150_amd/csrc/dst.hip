@@ -5,10 +5,16 @@
 // generates its 16 x K tile on the fly from a quarter-wave table in LDS with
 // exact integer argument reduction m = j k mod 2(n+1).
 //
+// Folding: with N = n + 1, sin(pi j (N-k)/N) = (-1)^(j+1) sin(pi j k/N), so
+// the odd rows j take u_k = x_k + x_(N-k) and the even rows w_k = x_k -
+// x_(N-k) over k <= n/2 (the middle point x_(N/2) of an even N joins u):
+// two half-size GEMMs, half the work of the dense product.  A column tile
+// holds one parity (the "parity" of its rows); the sources are folded while
+// they are staged.
+//
 // One launch covers any set of columns with the same n (all columns of all
-// solves of a batch), tiled 64 rows x 32 columns per workgroup; K is split
-// across workgroups when the tile count alone cannot fill the chip, with a
-// deterministic fixed-order reduction.
+// solves of a batch); K is split across workgroups when the tile count alone
+// cannot fill the chip, with a deterministic fixed-order reduction.
 //
 // Precisions (lrp_precision):
 //   FP64    v_mfma_f64_16x16x4   (float64 products and sums)
@@ -55,23 +61,48 @@ __device__ __forceinline__ float bf16_to_float(uint32_t b) {
   return __uint_as_float(b << 16);
 }
 
-// Stage the K x TN tile of the sources in LDS (transposed to [k][c]).
-// Values past the end of K or past the last column are zero.
-template <typename F>
-__device__ __forceinline__ void load_tile(const DstCol *__restrict__ cols,
-                                          int ncols, int c0, int k0, int ke,
-                                          Solve2D *solves, F store) {
-  for (int idx = threadIdx.x; idx < KC * TN; idx += NTHR) {
-    const int c = idx / KC, kc = idx - c * KC;
-    const int k = k0 + kc;
-    double v = 0.0;
-    if (k < ke && c0 + c < ncols) {
-      const DstCol dc = cols[c0 + c];
-      v = dc.src[k];
-      if (!isfinite(v) && dc.solve >= 0) solves[dc.solve].nonfinite = 1;
-    }
-    store(kc, c, v);
+// Folded source value of parity par at 0-based point i (grid point i + 1):
+// x_i + x_(n-1-i) (par 0) or x_i - x_(n-1-i) (par 1); x_i alone at the middle
+// point of an even N (par 0 only).  Two steps, so that the loads can be in
+// flight while other work runs: fold_load issues them (zero past kend or
+// without a source), fold_combine forms the value once they have arrived and
+// raises `bad` for a non-finite input.
+__device__ __forceinline__ void fold_load(const double *x, int i, int kend, int n, double &a,
+                                          double &b) {
+  a = 0.0;
+  b = 0.0;
+  if (x && i < kend) {
+    a = x[i];
+    if (2 * i + 1 < n) b = x[n - 1 - i];
   }
+}
+__device__ __forceinline__ double fold_combine(double a, double b, int i, int n, int par,
+                                               bool &bad) {
+  if (!isfinite(a) || !isfinite(b)) bad = true;
+  if (2 * i + 1 >= n) return a;          // middle point (or past the end: zero)
+  return par ? a - b : a + b;
+}
+
+// Tile of a folded launch: R = ceil(H0 / tm) row tiles (rows a of the half
+// problem, grid row j = 2a + 1 + par) times 2 ceil(ncols / tn) column tiles;
+// column tile ct holds parity ct & 1 of columns (ct >> 1) tn .. + tn - 1.
+struct FoldTile {
+  int row0, c0, par, Kp, H0;
+};
+__device__ __forceinline__ bool fold_tile(int n, int ncols, int tm, int tn, bool xcd,
+                                          FoldTile &t) {
+  t.H0 = (n + 1) / 2;
+  int rt, ct;
+  if (!tile_of(ceil_div(t.H0, tm), 2 * ceil_div(ncols, tn), xcd, rt, ct)) return false;
+  t.par = ct & 1;
+  t.Kp = t.par ? n / 2 : t.H0;
+  t.row0 = rt * tm;
+  t.c0 = (ct >> 1) * tn;
+  return true;
+}
+// 1-based grid row of half-row a (0 past the end: a zero sine row)
+__device__ __forceinline__ int fold_row(int a, const FoldTile &t) {
+  return a < t.Kp ? 2 * a + 1 + t.par : 0;
 }
 
 // K is cut into fixed chunks that depend on n only; each chunk is summed
@@ -89,15 +120,16 @@ __device__ __forceinline__ void chunk_range(int n, int kchunk, int &cb, int &ce)
   }
 }
 
-// Write a 16x16 block held in MFMA layout.  rowOf(reg) gives the row offset.
-__device__ __forceinline__ void store_out(double v, int row, int col, int n,
+// Store the result of half-row a of a folded tile: grid row 2a + par of the
+// column, or the chunk's partial sum (layout [z][2 col + par][a], a < H0).
+__device__ __forceinline__ void store_out(double v, int a, int col, const FoldTile &t,
                                           int ncols, const DstCol *cols,
                                           double *partial, int z) {
-  if (row < n && col < ncols) {
+  if (a < t.Kp && col < ncols) {
     if (partial)
-      partial[((size_t)z * ncols + col) * n + row] = v;
+      partial[((size_t)z * 2 * ncols + 2 * col + t.par) * t.H0 + a] = v;
     else
-      cols[col].dst[row] = v;
+      cols[col].dst[2 * a + t.par] = v;
   }
 }
 
@@ -124,11 +156,11 @@ __global__ __launch_bounds__(NTHR) void k_dst_f64(
   double *xs0 = tab + Qp;                         // [TN][LDT] x 2 buffers
   const int N = n + 1, twoN = 2 * N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int rt, ct;
-  if (!tile_of(ceil_div(n, TM64), ceil_div(ncols, TN_), false, rt, ct)) return;
-  const int row0 = rt * TM64, c0 = ct * TN_;
+  FoldTile ft;
+  if (!fold_tile(n, ncols, TM64, TN_, true, ft)) return;
+  const int row0 = ft.row0, c0 = ft.c0;
   int cb, ce;
-  chunk_range(n, kchunk, cb, ce);
+  chunk_range(ft.H0, kchunk, cb, ce);
   for (int i = tid; i < Q; i += NTHR) tab[i] = qtab[i];
 
   // this thread's share of a K stage: k offset tk (32 lanes read 32
@@ -147,35 +179,36 @@ __global__ __launch_bounds__(NTHR) void k_dst_f64(
       sidx[t] = dc.solve;
     }
   }
-  const int kbeg = cb * kchunk, kend = min(n, ce * kchunk);
+  const int kbeg = cb * kchunk, kend = min(ft.Kp, ce * kchunk);
   const int nst = (kend - kbeg + KC64 - 1) / KC64;
-  double pre[PER];
+  // a stage's loads are issued before the MFMAs of the previous stage and
+  // combined (folded) only when they are stashed in LDS after them
+  double pa[PER], pb[PER];
   unsigned bad = 0;
+  int kf = 0;
   auto fetch = [&](int st) {
-    const int k = kbeg + st * KC64 + tk;
+    kf = kbeg + st * KC64 + tk;
 #pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      double v = 0.0;
-      if (src[t] && k < kend) {
-        v = src[t][k];
-        if (!isfinite(v)) bad |= 1u << t;
-      }
-      pre[t] = v;
-    }
+    for (int t = 0; t < PER; ++t) fold_load(src[t], kf, kend, n, pa[t], pb[t]);
   };
   auto stash = [&](int st) {
     double *xs = xs0 + (st & 1) * TN_ * LDT;
 #pragma unroll
-    for (int t = 0; t < PER; ++t) xs[(tc0 + 8 * t) * LDT + tk] = pre[t];
+    for (int t = 0; t < PER; ++t) {
+      bool b = false;
+      xs[(tc0 + 8 * t) * LDT + tk] = fold_combine(pa[t], pb[t], kf, n, ft.par, b);
+      if (b) bad |= 1u << t;
+    }
   };
 
-  const int jA = row0 + wave * 32 + (lane & 15);  // S rows jA+1, jA+17
-  const int jB = jA + 16;
+  // grid rows (1-based) of half-rows a and a + 16
+  const int jA = fold_row(row0 + wave * 32 + (lane & 15), ft);
+  const int jB = fold_row(row0 + wave * 32 + (lane & 15) + 16, ft);
   const int kk = lane >> 4;
-  const int stepA = (int)((4LL * (jA + 1)) % twoN);
-  const int stepB = (int)((4LL * (jB + 1)) % twoN);
-  int mA = (int)(((long long)(jA + 1) * (kbeg + kk + 1)) % twoN);
-  int mB = (int)(((long long)(jB + 1) * (kbeg + kk + 1)) % twoN);
+  const int stepA = (int)((4LL * jA) % twoN);
+  const int stepB = (int)((4LL * jB) % twoN);
+  int mA = (int)(((long long)jA * (kbeg + kk + 1)) % twoN);
+  int mB = (int)(((long long)jB * (kbeg + kk + 1)) % twoN);
   d4 acc[2][NB], part[2][NB];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
@@ -250,9 +283,9 @@ __global__ __launch_bounds__(NTHR) void k_dst_f64(
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = row0 + wave * 32 + h * 16 + (lane >> 4) + 4 * r;
+        const int a = row0 + wave * 32 + h * 16 + (lane >> 4) + 4 * r;
         const int col = c0 + b * 16 + (lane & 15);
-        store_out(acc[h][b][r], row, col, n, ncols, cols, partial, blockIdx.z);
+        store_out(acc[h][b][r], a, col, ft, ncols, cols, partial, blockIdx.z);
       }
 }
 
@@ -275,11 +308,11 @@ __global__ __launch_bounds__(NTHR) void k_dst_f32(
   float *xs0 = tab + Qp;                          // [TN][LDT32] x 2 buffers
   const int N = n + 1, twoN = 2 * N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int rt, ct;
-  if (!tile_of(ceil_div(n, TM64), ceil_div(ncols, TN_), false, rt, ct)) return;
-  const int row0 = rt * TM64, c0 = ct * TN_;
+  FoldTile ft;
+  if (!fold_tile(n, ncols, TM64, TN_, true, ft)) return;
+  const int row0 = ft.row0, c0 = ft.c0;
   int cb, ce;
-  chunk_range(n, kchunk, cb, ce);
+  chunk_range(ft.H0, kchunk, cb, ce);
   for (int i = tid; i < Q; i += NTHR) tab[i] = qtab[i];
 
   const int tk = tid & 31, tc0 = tid >> 5;
@@ -296,35 +329,33 @@ __global__ __launch_bounds__(NTHR) void k_dst_f32(
       sidx[t] = dc.solve;
     }
   }
-  const int kbeg = cb * kchunk, kend = min(n, ce * kchunk);
+  const int kbeg = cb * kchunk, kend = min(ft.Kp, ce * kchunk);
   const int nst = (kend - kbeg + KC64 - 1) / KC64;
-  float pre[PER];
+  double pa[PER], pb[PER];
   unsigned bad = 0;
+  int kf = 0;
   auto fetch = [&](int st) {
-    const int k = kbeg + st * KC64 + tk;
+    kf = kbeg + st * KC64 + tk;
 #pragma unroll
-    for (int t = 0; t < PER; ++t) {
-      double v = 0.0;
-      if (src[t] && k < kend) {
-        v = src[t][k];
-        if (!isfinite(v)) bad |= 1u << t;
-      }
-      pre[t] = (float)v;
-    }
+    for (int t = 0; t < PER; ++t) fold_load(src[t], kf, kend, n, pa[t], pb[t]);
   };
   auto stash = [&](int st) {
     float *xs = xs0 + (st & 1) * TN_ * LDT32;
 #pragma unroll
-    for (int t = 0; t < PER; ++t) xs[(tc0 + 8 * t) * LDT32 + tk] = pre[t];
+    for (int t = 0; t < PER; ++t) {
+      bool b = false;
+      xs[(tc0 + 8 * t) * LDT32 + tk] = (float)fold_combine(pa[t], pb[t], kf, n, ft.par, b);
+      if (b) bad |= 1u << t;
+    }
   };
 
-  const int jA = row0 + wave * 32 + (lane & 15);
-  const int jB = jA + 16;
+  const int jA = fold_row(row0 + wave * 32 + (lane & 15), ft);
+  const int jB = fold_row(row0 + wave * 32 + (lane & 15) + 16, ft);
   const int kk = lane >> 4;
-  const int stepA = (int)((4LL * (jA + 1)) % twoN);
-  const int stepB = (int)((4LL * (jB + 1)) % twoN);
-  int mA = (int)(((long long)(jA + 1) * (kbeg + kk + 1)) % twoN);
-  int mB = (int)(((long long)(jB + 1) * (kbeg + kk + 1)) % twoN);
+  const int stepA = (int)((4LL * jA) % twoN);
+  const int stepB = (int)((4LL * jB) % twoN);
+  int mA = (int)(((long long)jA * (kbeg + kk + 1)) % twoN);
+  int mB = (int)(((long long)jB * (kbeg + kk + 1)) % twoN);
   f4 run[2][NB];
   double acc[2][NB][4], part[2][NB][4];
 #pragma unroll
@@ -409,63 +440,110 @@ __global__ __launch_bounds__(NTHR) void k_dst_f32(
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = row0 + wave * 32 + h * 16 + 4 * (lane >> 4) + r;
+        const int a = row0 + wave * 32 + h * 16 + 4 * (lane >> 4) + r;
         const int col = c0 + b * 16 + (lane & 15);
-        store_out(acc[h][b][r] + part[h][b][r], row, col, n, ncols, cols, partial,
+        store_out(acc[h][b][r] + part[h][b][r], a, col, ft, ncols, cols, partial,
                   blockIdx.z);
       }
 }
 
 // ---------------------------------------------------------------- BF16x3
-// Table entries are packed (hi | lo << 16) bfloat16 splits of the sine.
+// Table entries are packed (hi | lo << 16) bfloat16 splits of the sine.  64
+// rows (4 waves x 16) x TN columns per workgroup; the folded sources of the
+// next 64-deep K stage are loaded into registers while the MFMAs run on the
+// current one, then split into bfloat16 hi/lo and stashed in the other LDS
+// buffer.  A stage is one float32 run, added into the float64 chunk sum.
 __global__ __launch_bounds__(NTHR) void k_dst_bf16x3(
     int n, int Q, const uint32_t *__restrict__ qtab,
     const DstCol *__restrict__ cols, int ncols, int kchunk,
     double *__restrict__ partial, Solve2D *solves) {
+  constexpr int PER = KC * TN / NTHR;            // tile values per thread
+  constexpr int NB = TN / 16;
   extern __shared__ __align__(16) unsigned char smem[];
   const int Qp = (Q + 3) & ~3;
   uint32_t *tab = (uint32_t *)smem;
-  uint16_t *xhi = (uint16_t *)(tab + Qp);        // [TN][KC]
-  uint16_t *xlo = xhi + TN * KC;
+  uint16_t *xb0 = (uint16_t *)(tab + Qp);       // [hi|lo][TN][KC] x 2 buffers
   const int N = n + 1, twoN = 2 * N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int rt, ct;
-  if (!tile_of(ceil_div(n, TM), ceil_div(ncols, TN), true, rt, ct)) return;
-  const int row0 = rt * TM, c0 = ct * TN;
+  FoldTile ft;
+  if (!fold_tile(n, ncols, TM, TN, true, ft)) return;
+  const int row0 = ft.row0, c0 = ft.c0;
   int cb, ce;
-  chunk_range(n, kchunk, cb, ce);
+  chunk_range(ft.H0, kchunk, cb, ce);
   for (int i = tid; i < Q; i += NTHR) tab[i] = qtab[i];
 
-  const int j = row0 + wave * 16 + (lane & 15);
-  const int kq = lane >> 4;                      // k offset 8*kq .. 8*kq+7
-  const int jm = (j + 1) % twoN;
-  const int step = (int)((32LL * (j + 1)) % twoN);
-  double acc[TN / 16][4], part[TN / 16][4];
-  f4 run[TN / 16];
+  // this thread stages point k0 + lane of columns wave + 4 t
+  const double *src[PER];
+  int sidx[PER];
 #pragma unroll
-  for (int b = 0; b < TN / 16; ++b) {
-    run[b] = (f4){0, 0, 0, 0};
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc[b][r] = 0.0;
+  for (int t = 0; t < PER; ++t) {
+    const int c = c0 + wave + 4 * t;
+    src[t] = nullptr;
+    sidx[t] = -1;
+    if (c < ncols) {
+      const DstCol dc = cols[c];
+      src[t] = dc.src;
+      sidx[t] = dc.solve;
+    }
   }
-  for (int ch = cb; ch < ce; ++ch) {
-  const int kb = ch * kchunk, ke = min(n, kb + kchunk);
-  // m for k = kb + 8 kq (1-based k + 1); advances by 32 (j+1) per step
-  int m = (int)(((long long)(j + 1) * (kb + 8 * kq + 1)) % twoN);
+  const int kbeg = cb * kchunk, kend = min(ft.Kp, ce * kchunk);
+  const int nst = (kend - kbeg + KC - 1) / KC;
+  double pa[PER], pb[PER];
+  unsigned bad = 0;
+  int kf = 0;
+  auto fetch = [&](int st) {
+    kf = kbeg + st * KC + lane;
 #pragma unroll
-  for (int b = 0; b < TN / 16; ++b)
+    for (int t = 0; t < PER; ++t) fold_load(src[t], kf, kend, n, pa[t], pb[t]);
+  };
+  auto stash = [&](int st) {
+    uint16_t *xh = xb0 + (st & 1) * 2 * TN * KC, *xl = xh + TN * KC;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) part[b][r] = 0.0;
-  for (int k0 = kb; k0 < ke; k0 += KC) {
-    __syncthreads();
-    load_tile(cols, ncols, c0, k0, ke, solves, [&](int kc, int c, double v) {
+    for (int t = 0; t < PER; ++t) {
+      bool b = false;
+      const double v = fold_combine(pa[t], pb[t], kf, n, ft.par, b);
+      if (b) bad |= 1u << t;
       const uint32_t h = bf16_bits_rne((float)v);
       const uint32_t l = bf16_bits_rne((float)(v - (double)bf16_to_float(h)));
-      xhi[c * KC + kc] = (uint16_t)h;
-      xlo[c * KC + kc] = (uint16_t)l;
-    });
-    __syncthreads();
-    const int kcn = min(KC, ke - k0);
+      const int c = wave + 4 * t;
+      xh[c * KC + lane] = (uint16_t)h;
+      xl[c * KC + lane] = (uint16_t)l;
+    }
+  };
+
+  const int j = fold_row(row0 + wave * 16 + (lane & 15), ft);   // 1-based grid row
+  const int kq = lane >> 4;                      // k offset 8*kq .. 8*kq+7
+  const int jm = j % twoN;
+  const int step = (int)((32LL * j) % twoN);
+  // m for the lane's first point k = kbeg + 8 kq (1-based k + 1); advances
+  // by 32 j per 32-deep MFMA step
+  int m = (int)(((long long)j * (kbeg + 8 * kq + 1)) % twoN);
+  double acc[NB][4], part[NB][4];
+  f4 run[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    run[b] = (f4){0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[b][r] = part[b][r] = 0.0;
+  }
+  fetch(0);
+  __syncthreads();                               // table in LDS
+  stash(0);
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int k0 = kbeg + st * KC;
+    if (st > 0 && (k0 % kchunk) == 0) {          // a new K chunk starts
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          acc[b][r] += part[b][r];
+          part[b][r] = 0.0;
+        }
+    }
+    if (st + 1 < nst) fetch(st + 1);
+    const uint16_t *xh = xb0 + (st & 1) * 2 * TN * KC, *xl = xh + TN * KC;
+    const int kcn = min(KC, kend - k0);
     for (int kc = 0; kc < kcn; kc += 32) {
       bf8 ah, al;
       int mm = m;
@@ -488,34 +566,34 @@ __global__ __launch_bounds__(NTHR) void k_dst_bf16x3(
       m += step;
       if (m >= twoN) m -= twoN;
 #pragma unroll
-      for (int b = 0; b < TN / 16; ++b) {
+      for (int b = 0; b < NB; ++b) {
         const int c = b * 16 + (lane & 15);
-        const bf8 bh = *(const bf8 *)(xhi + c * KC + kc + 8 * kq);
-        const bf8 bl = *(const bf8 *)(xlo + c * KC + kc + 8 * kq);
+        const bf8 bh = *(const bf8 *)(xh + c * KC + kc + 8 * kq);
+        const bf8 bl = *(const bf8 *)(xl + c * KC + kc + 8 * kq);
         run[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, run[b], 0, 0, 0);
         run[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, run[b], 0, 0, 0);
         run[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, run[b], 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int b = 0; b < TN / 16; ++b) {
+    for (int b = 0; b < NB; ++b) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) part[b][r] += (double)run[b][r];
       run[b] = (f4){0, 0, 0, 0};
     }
+    if (st + 1 < nst) stash(st + 1);
+    __syncthreads();
   }
 #pragma unroll
-  for (int b = 0; b < TN / 16; ++b)
+  for (int t = 0; t < PER; ++t)
+    if (((bad >> t) & 1u) && sidx[t] >= 0) solves[sidx[t]].nonfinite = 1;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[b][r] += part[b][r];
-  }
-#pragma unroll
-  for (int b = 0; b < TN / 16; ++b)
+  for (int b = 0; b < NB; ++b)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = row0 + wave * 16 + 4 * (lane >> 4) + r;
+      const int a = row0 + wave * 16 + 4 * (lane >> 4) + r;
       const int col = c0 + b * 16 + (lane & 15);
-      store_out(acc[b][r], row, col, n, ncols, cols, partial, blockIdx.z);
+      store_out(acc[b][r] + part[b][r], a, col, ft, ncols, cols, partial, blockIdx.z);
     }
 }
 
@@ -526,8 +604,9 @@ __global__ void k_dst_reduce(int n, int ncols, int nz,
   const int col = blockIdx.y;
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= n || col >= ncols) return;
+  const int H0 = (n + 1) / 2, par = row & 1, a = row >> 1;
   double s = 0.0;
-  for (int z = 0; z < nz; ++z) s += partial[((size_t)z * ncols + col) * n + row];
+  for (int z = 0; z < nz; ++z) s += partial[((size_t)z * 2 * ncols + 2 * col + par) * H0 + a];
   cols[col].dst[row] = s;
 }
 
@@ -546,74 +625,72 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
                       hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (ncols <= 0) return hipSuccess;
   const int Q = quarter_len(n);
-  const int gx = ceil_div(n, TM), gy = ceil_div(ncols, TN);
-  // Fixed K chunks (at most 8, at least 256 deep); one workgroup per chunk
-  // when the tiles alone leave the 256 CUs under-filled.
-  const int kchunk = std::max(256, ceil_div(ceil_div(n, 8), KC) * KC);
-  const int nchunk = ceil_div(n, kchunk);
-  int split = (gx * gy < 512) ? nchunk : 1;
-  if (partial == nullptr ||
-      partial_elems < (size_t)split * (size_t)ncols * (size_t)n)
-    split = 1;
-  double *out_partial = split > 1 ? partial : nullptr;
-  dim3 grid(tile_grid(gx, gy, true), 1, split), block(NTHR);
-  size_t lds = 0;
-  hipError_t e = hipSuccess;
   const char *base = (const char *)tab;
   const int Qp8 = (Q + 1) & ~1, Qp4 = (Q + 3) & ~3;
   // table layout: [f64 x Qp8][f32 x Qp4][u32 x Qp4][int8 records]
   if (prec == LRP_PREC_INT8)
     return launch_dst_i8(n, base + (size_t)Qp8 * 8 + (size_t)Qp4 * 8, (DstCol *)cols, ncols,
-                         kchunk, solves, partial, partial_elems, work, work_bytes, st, ev0,
-                         ev1);
+                         solves, partial, partial_elems, work, work_bytes, st, ev0, ev1);
   const double *t64 = (const double *)base;
   const float *t32 = (const float *)(base + (size_t)Qp8 * 8);
   const uint32_t *tbf = (const uint32_t *)(base + (size_t)Qp8 * 8 + (size_t)Qp4 * 4);
+  // folded length, and fixed K chunks of it that depend on n only (at most
+  // 4, at least 256 deep, a multiple of every kernel's K stage)
+  const int H0 = (n + 1) / 2;
+  const int kchunk = std::max(256, ceil_div(ceil_div(H0, 4), KC) * KC);
+  const int nchunk = ceil_div(H0, kchunk);
+  // tiles of the chosen kernel; one workgroup per K chunk when the tiles
+  // alone leave the 256 CUs under-filled
+  const bool wide = ncols > 32;
+  int tm, tn;
+  if (prec == LRP_PREC_BF16X3) {
+    tm = TM;
+    tn = TN;
+  } else {
+    tm = TM64;
+    tn = wide ? 64 : 32;
+  }
+  const int R = ceil_div(H0, tm), C = 2 * ceil_div(ncols, tn);
+  int split = (R * C < 512) ? nchunk : 1;
+  if (partial == nullptr || partial_elems < (size_t)split * 2 * ncols * H0) split = 1;
+  double *out_partial = split > 1 ? partial : nullptr;
+  const dim3 block(NTHR);
+  size_t lds = 0;
+  hipError_t e = hipSuccess;
   if (prec == LRP_PREC_FP64) {
-    const bool wide = ncols > 32;
-    const int tn = wide ? 64 : 32;
-    const int R64 = ceil_div(n, TM64), C64 = ceil_div(ncols, tn);
-    dim3 g64(tile_grid(R64, C64, false), 1, grid.z);
-    if (R64 * C64 >= 512) g64.z = 1;
-    if (g64.z == 1) out_partial = nullptr;
+    const dim3 g(tile_grid(R, C, true), 1, split);
     lds = (size_t)Qp8 * 8 + (size_t)2 * tn * LDT * 8;
     const void *fn = wide ? (const void *)k_dst_f64<64> : (const void *)k_dst_f64<32>;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
     if (wide)
-      hipLaunchKernelGGL(k_dst_f64<64>, g64, block, lds, st, n, Q, t64, cols, ncols,
+      hipLaunchKernelGGL(k_dst_f64<64>, g, block, lds, st, n, Q, t64, cols, ncols,
                          kchunk, out_partial, solves);
     else
-      hipLaunchKernelGGL(k_dst_f64<32>, g64, block, lds, st, n, Q, t64, cols, ncols,
+      hipLaunchKernelGGL(k_dst_f64<32>, g, block, lds, st, n, Q, t64, cols, ncols,
                          kchunk, out_partial, solves);
-    split = g64.z;
   } else if (prec == LRP_PREC_FP32) {
-    const bool wide = ncols > 32;
-    const int tn = wide ? 64 : 32;
-    const int R32 = ceil_div(n, TM64), C32 = ceil_div(ncols, tn);
-    dim3 g32(tile_grid(R32, C32, false), 1, grid.z);
-    if (R32 * C32 >= 512) g32.z = 1;
-    if (g32.z == 1) out_partial = nullptr;
+    const dim3 g(tile_grid(R, C, true), 1, split);
     lds = (size_t)Qp4 * 4 + (size_t)2 * tn * LDT32 * 4;
     const void *fn = wide ? (const void *)k_dst_f32<64> : (const void *)k_dst_f32<32>;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
     if (wide)
-      hipLaunchKernelGGL(k_dst_f32<64>, g32, block, lds, st, n, Q, t32, cols, ncols,
+      hipLaunchKernelGGL(k_dst_f32<64>, g, block, lds, st, n, Q, t32, cols, ncols,
                          kchunk, out_partial, solves);
     else
-      hipLaunchKernelGGL(k_dst_f32<32>, g32, block, lds, st, n, Q, t32, cols, ncols,
+      hipLaunchKernelGGL(k_dst_f32<32>, g, block, lds, st, n, Q, t32, cols, ncols,
                          kchunk, out_partial, solves);
-    split = g32.z;
   } else {
-    lds = (size_t)Qp4 * 4 + (size_t)KC * TN * 2 * 2;
+    const dim3 g(tile_grid(R, C, true), 1, split);
+    lds = (size_t)Qp4 * 4 + (size_t)2 * 2 * KC * TN * 2;
     e = hipFuncSetAttribute((const void *)k_dst_bf16x3,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dst_bf16x3, grid, block, lds, st, n, Q, tbf, cols,
+    hipLaunchKernelGGL(k_dst_bf16x3, g, block, lds, st, n, Q, tbf, cols,
                        ncols, kchunk, out_partial, solves);
   }
   e = hipGetLastError();

@@ -29,9 +29,17 @@
 // with [T_4 T_5 0 0] add the a = 4, 5 terms to levels 4 and 5: 8 MFMAs per
 // 16 grid points and 16 x 16 output tile.
 //
-// K is cut into the same fixed chunks as the floating-point transforms; the
-// levels of a chunk are combined into float64 and the chunk values summed in
-// order, so results do not depend on how many columns share a launch.
+// Folding: with N = n + 1, sin(pi j (N-k)/N) = (-1)^(j+1) sin(pi j k/N), so
+//   y_j = sum_{k=1}^{H0} sin(pi j k/N) u_k  (j odd),   u_k = x_k + x_(N-k),
+//   y_j = sum_{k=1}^{H1} sin(pi j k/N) w_k  (j even),  w_k = x_k - x_(N-k),
+// with H0 = ceil(n/2), H1 = floor(n/2) and, for even N, the middle point
+// u_(N/2) = x_(N/2).  The transform is two half-size GEMMs (half the work of
+// the dense one): a column becomes two "parity columns", u with the odd
+// rows and w with the even rows, each sliced with its own exponent.
+//
+// K is cut into fixed chunks; the levels of a chunk are combined into float64
+// and the chunk values summed in order, so results do not depend on how many
+// columns share a launch.
 #include <algorithm>
 #include <cmath>
 
@@ -65,55 +73,88 @@ __device__ __forceinline__ uint2 slice_record(double x, int e) {
   return r;
 }
 
-// One block per column: e_c with max|x| = f 2^e_c, f in [0.5, 1) (kept in
-// the column's descriptor), then the slice records of all npad points
-// (zero past n).  Non-finite columns raise their solve's flag.
-__global__ __launch_bounds__(NTHR) void k_x_slices(int n, int npad, DstCol *cols, int ncols,
-                                                   uint2 *__restrict__ out, Solve2D *solves) {
+// One block per column c: its parity vectors u (k = 1..H0) and w (k =
+// 1..H1), their exponents e with max|v| = f 2^e, f in [0.5, 1) (ex[2c + p],
+// p = 0 for u, 1 for w), then the slice records of both, hpad points each
+// (zero past H_p), at out + (2c + p) hpad.  Non-finite columns raise their
+// solve's flag.
+__global__ __launch_bounds__(NTHR) void k_x_slices(int n, int hpad, const DstCol *cols,
+                                                   int ncols, uint2 *__restrict__ out,
+                                                   int *__restrict__ ex, Solve2D *solves) {
   const int c = blockIdx.x;
   if (c >= ncols) return;
   const double *x = cols[c].src;
-  double mx = 0.0;
+  const int N = n + 1, H0 = (n + 1) / 2, H1 = n / 2;
+  // parity values at point k (1-based), k <= H0
+  auto fold = [&](int k, double &u, double &w) {
+    const double a = x[k - 1];
+    if (2 * k < N) {
+      const double b = x[N - k - 1];
+      u = a + b;
+      w = a - b;
+    } else {
+      u = a;          // the middle point of an even N
+      w = 0.0;
+    }
+  };
+  double mu = 0.0, mw = 0.0;
   bool bad = false;
-  for (int k = threadIdx.x; k < n; k += NTHR) {
-    const double v = x[k];
-    if (!isfinite(v)) bad = true;
-    mx = fmax(mx, fabs(v));
+  for (int k = threadIdx.x; k < n; k += NTHR)
+    if (!isfinite(x[k])) bad = true;
+  for (int k = threadIdx.x + 1; k <= H0; k += NTHR) {
+    double u, w;
+    fold(k, u, w);
+    mu = fmax(mu, fabs(u));
+    mw = fmax(mw, fabs(w));
   }
-  __shared__ double red[4];
+  __shared__ double red[2][4];
   __shared__ int badw[4];
-  __shared__ int ex;
+  __shared__ int exs[2];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int key = 0;
-  wave_argmax(mx, key);                 // wave maximum (keys unused)
+  wave_argmax(mu, key);                 // wave maxima (keys unused)
+  wave_argmax(mw, key);
   const unsigned long long anyb = __ballot(bad);
   if (lane == 0) {
-    red[wave] = mx;
+    red[0][wave] = mu;
+    red[1][wave] = mw;
     badw[wave] = anyb != 0ull;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  if (threadIdx.x < 2) {
+    const int p = threadIdx.x;
+    const double m = fmax(fmax(red[p][0], red[p][1]), fmax(red[p][2], red[p][3]));
     int e = 0;
     if (m > 0.0 && isfinite(m)) (void)frexp(m, &e);
-    ex = e;
-    cols[c].pad = e;
-    if ((badw[0] | badw[1] | badw[2] | badw[3]) && cols[c].solve >= 0)
+    exs[p] = e;
+    ex[2 * c + p] = e;
+    if (p == 0 && (badw[0] | badw[1] | badw[2] | badw[3]) && cols[c].solve >= 0)
       solves[cols[c].solve].nonfinite = 1;
   }
   __syncthreads();
-  const int e = ex;
-  uint2 *o = out + (size_t)c * npad;
-  for (int k = threadIdx.x; k < npad; k += NTHR) o[k] = slice_record(k < n ? x[k] : 0.0, e);
+  const int e0 = exs[0], e1 = exs[1];
+  uint2 *o0 = out + (size_t)(2 * c) * hpad, *o1 = o0 + hpad;
+  for (int k = threadIdx.x + 1; k <= hpad; k += NTHR) {
+    double u = 0.0, w = 0.0;
+    if (k <= H0) fold(k, u, w);
+    o0[k - 1] = slice_record(u, e0);
+    o1[k - 1] = slice_record(k <= H1 ? w : 0.0, e1);
+  }
 }
 
 // FULL: the LDS table holds the records of all m in [0, 2N) (no folding in
 // the inner loop); otherwise the quarter wave q in [0, N/2] with both signs.
+// Tiles: TMI rows of one parity (rows a of the half problem, grid row
+// j = 2a + 1 + p) times TN_ columns; column tile ct holds parity p = ct & 1
+// of columns (ct >> 1) TN_ .. +TN_-1, so both parities of a column block sit
+// next to each other in the XCD order and their interleaved output rows
+// meet in one L2.
 template <int TN_, bool FULL>
 __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__restrict__ rec,
                                                 const DstCol *__restrict__ cols, int ncols,
                                                 int kchunk, const uint2 *__restrict__ xrec,
-                                                int npad, double *__restrict__ partial) {
+                                                int hpad, const int *__restrict__ xex,
+                                                double *__restrict__ partial) {
   constexpr int NB = TN_ / 16;
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = n + 1, twoN = 2 * N;
@@ -121,16 +162,19 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
   uint2 *tab = (uint2 *)smem;                    // records, see FULL
   uint32_t *xs0 = (uint32_t *)(tab + ntab);      // record planes [c][k] x 2 buffers
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int H0 = (n + 1) / 2;
   int rt, ct;
-  if (!tile_of(ceil_div(n, TMI), ceil_div(ncols, TN_), true, rt, ct)) return;
-  const int row0 = rt * TMI, c0 = ct * TN_;
+  if (!tile_of(ceil_div(H0, TMI), 2 * ceil_div(ncols, TN_), true, rt, ct)) return;
+  const int par = ct & 1;
+  const int Kp = par ? n / 2 : H0;               // points and rows of this parity
+  const int row0 = rt * TMI, c0 = (ct >> 1) * TN_;
   int cb, ce;
   if (gridDim.z > 1) {
     cb = blockIdx.z;
     ce = blockIdx.z + 1;
   } else {
     cb = 0;
-    ce = (n + kchunk - 1) / kchunk;
+    ce = (H0 + kchunk - 1) / kchunk;
   }
   for (int i = tid; i < ntab; i += NTHR) tab[i] = rec[i];
   // staging share: thread stages grid points tk, columns tc0 + 8 t
@@ -141,9 +185,9 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
 #pragma unroll
   for (int t = 0; t < PER; ++t) {
     const int c = c0 + tc0 + (NTHR / KCI) * t;
-    src[t] = (c < ncols) ? xrec + (size_t)c * npad : nullptr;
+    src[t] = (c < ncols) ? xrec + (size_t)(2 * c + par) * hpad : nullptr;
   }
-  const int kbeg = cb * kchunk, kend = min(n, ce * kchunk);
+  const int kbeg = cb * kchunk, kend = min(Kp, ce * kchunk);
   const int nst = (kend - kbeg + KCI - 1) / KCI;
   uint2 pre[PER];
   auto fetch = [&](int st) {
@@ -163,13 +207,14 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
       p[LVL] = pre[t].y;
     }
   };
-  // rows of this lane: j = row0 + 32 wave + 16 h + (lane & 15) + 1 (1-based)
+  // rows of this lane: a = row0 + 32 wave + 16 h + (lane & 15), grid row
+  // j = 2 a + 1 + par (1-based)
   const int g = lane >> 4, li = lane & 15;
   int jr[2], d16[2], mk[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    jr[h] = row0 + 32 * wave + 16 * h + li + 1;
-    if (jr[h] > n) jr[h] = 0;    // rows past the end: sin(0) = 0
+    const int a = row0 + 32 * wave + 16 * h + li;
+    jr[h] = (a < Kp) ? 2 * a + 1 + par : 0;    // rows past the end: sin(0) = 0
     d16[h] = (int)(((long long)jr[h] * 16) % twoN);
     // m = j k mod 2N at this lane's first grid point, k = kbeg + 4 g + 1
     mk[h] = (int)(((long long)jr[h] * (kbeg + 4 * g + 1)) % twoN);
@@ -191,7 +236,7 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       const int c = c0 + 16 * b + li;
-      const int e = (c < ncols) ? cols[c].pad : 0;
+      const int e = (c < ncols) ? xex[2 * c + par] : 0;
       const double sc = ldexp(sc0, e - 12);
 #pragma unroll
       for (int h = 0; h < 2; ++h)
@@ -294,12 +339,12 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
       const int c = c0 + 16 * b + li;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int row = row0 + 32 * wave + 16 * h + 4 * g + q;
-        if (row < n && c < ncols) {
+        const int a = row0 + 32 * wave + 16 * h + 4 * g + q;
+        if (a < Kp && c < ncols) {
           if (partial)
-            partial[((size_t)blockIdx.z * ncols + c) * n + row] = res[h][b][q];
+            partial[((size_t)blockIdx.z * 2 * ncols + 2 * c + par) * H0 + a] = res[h][b][q];
           else
-            cols[c].dst[row] = res[h][b][q];
+            cols[c].dst[2 * a + par] = res[h][b][q];
         }
       }
     }
@@ -310,8 +355,9 @@ __global__ void k_dst_i8_reduce(int n, int ncols, int nz, const double *__restri
   const int col = blockIdx.y;
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= n || col >= ncols) return;
+  const int H0 = (n + 1) / 2, par = row & 1, a = row >> 1;
   double s = 0.0;
-  for (int z = 0; z < nz; ++z) s += partial[((size_t)z * ncols + col) * n + row];
+  for (int z = 0; z < nz; ++z) s += partial[((size_t)z * 2 * ncols + 2 * col + par) * H0 + a];
   cols[col].dst[row] = s;
 }
 
@@ -367,43 +413,47 @@ constexpr size_t LDS_MAX = 160 * 1024;
 bool dst_i8_supported(int n) { return i8_lds(n, 32, false) <= LDS_MAX; }
 bool dst_i8_fast(int n) { return i8_lds(n, 64, false) <= LDS_MAX; }
 
-size_t dst_i8_work_bytes(int n, int ncols) {
-  const int npad = ceil_div(n, KCI) * KCI;
-  return (size_t)ncols * npad * 8;
-}
+// work per column: two parity records of hpad points, then two exponents
+static int i8_hpad(int n) { return ceil_div((n + 1) / 2, KCI) * KCI; }
+static size_t i8_col_bytes(int n) { return (size_t)2 * i8_hpad(n) * 8 + 8; }
+
+size_t dst_i8_work_bytes(int n, int ncols) { return (size_t)ncols * i8_col_bytes(n); }
 
 int dst_i8_work_cols(int n, int want) {
-  const size_t per = (size_t)ceil_div(n, KCI) * KCI * 8;
+  const size_t per = i8_col_bytes(n);
   const int cap = (int)std::max<size_t>(1024, ((size_t)512 << 20) / per);
   return std::min(want, cap);
 }
 
-hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, int kchunk,
-                         Solve2D *solves, double *partial, size_t partial_elems,
-                         void *work, size_t work_bytes, hipStream_t st, hipEvent_t ev0,
-                         hipEvent_t ev1) {
+hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, Solve2D *solves,
+                         double *partial, size_t partial_elems, void *work,
+                         size_t work_bytes, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   if (ncols <= 0) return hipSuccess;
   if (!dst_i8_supported(n)) return hipErrorInvalidValue;
   const int Q = (n + 1) / 2 + 1;
-  const int npad = ceil_div(n, KCI) * KCI;
+  const int H0 = (n + 1) / 2, hpad = i8_hpad(n);
+  // fixed K chunks of the folded length (at most 4, at least 256 deep)
+  const int kchunk = std::max(256, ceil_div(ceil_div(H0, 4), KCI) * KCI);
+  const int nchunk = ceil_div(H0, kchunk);
   // the slice records of a launch's columns must fit the work buffer; larger
   // column sets run in several launches (results per column are unchanged)
-  const int per = (int)std::min<size_t>((size_t)ncols, work_bytes / ((size_t)npad * 8));
+  const int per = (int)std::min<size_t>((size_t)ncols, work_bytes / i8_col_bytes(n));
   if (per <= 0) return hipErrorInvalidValue;
   for (int c0 = 0; c0 < ncols; c0 += per) {
     const int nc = std::min(per, ncols - c0);
     DstCol *cc = cols + c0;
-    hipLaunchKernelGGL(k_x_slices, dim3(nc), dim3(NTHR), 0, st, n, npad, cc, nc, (uint2 *)work,
+    uint2 *xrec = (uint2 *)work;
+    int *xex = (int *)(xrec + (size_t)2 * nc * hpad);
+    hipLaunchKernelGGL(k_x_slices, dim3(nc), dim3(NTHR), 0, st, n, hpad, cc, nc, xrec, xex,
                        solves);
     const bool wide = nc > 32 && i8_lds(n, 64, false) <= LDS_MAX;
     const int tn = wide ? 64 : 32;
     const bool full = i8_lds(n, tn, true) <= LDS_MAX;
     const unsigned char *tabs = (const unsigned char *)rec;
     const uint2 *trec = (const uint2 *)(full ? tabs + i8_quarter_bytes(n) : tabs);
-    const int nchunk = ceil_div(n, kchunk);
-    const int R = ceil_div(n, TMI), C = ceil_div(nc, tn);
+    const int R = ceil_div(H0, TMI), C = 2 * ceil_div(nc, tn);
     dim3 g(tile_grid(R, C, true), 1, 1);
-    if (R * C < 512 && partial && partial_elems >= (size_t)nchunk * nc * n) g.z = nchunk;
+    if (R * C < 512 && partial && partial_elems >= (size_t)nchunk * 2 * nc * H0) g.z = nchunk;
     double *out_partial = g.z > 1 ? partial : nullptr;
     const size_t lds = i8_lds(n, tn, full);
     const void *fn = wide ? (full ? (const void *)k_dst_i8<64, true> : (const void *)k_dst_i8<64, false>)
@@ -413,7 +463,7 @@ hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, int kc
     if (ev0 && c0 == 0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
 #define LRP_I8_LAUNCH(TNV, FV)                                                              \
   hipLaunchKernelGGL((k_dst_i8<TNV, FV>), g, dim3(NTHR), lds, st, n, Q, trec, cc, nc, kchunk, \
-                     (const uint2 *)work, npad, out_partial)
+                     xrec, hpad, xex, out_partial)
     if (wide && full) LRP_I8_LAUNCH(64, true);
     else if (wide) LRP_I8_LAUNCH(64, false);
     else if (full) LRP_I8_LAUNCH(32, true);

@@ -49,7 +49,9 @@ hipError_t timed_dst(lrp_ctx *ctx, int prec, int n, const void *tab,
   if (e != hipSuccess) return e;
   pt.prec = prec;
   pt.cols = ncols;
-  pt.flops = 2.0 * (double)n * (double)n * (double)ncols;
+  // the folded transform: two half-size GEMMs of H0 = ceil(n/2), H1 = floor(n/2)
+  const double h0 = (double)((n + 1) / 2), h1 = (double)(n / 2);
+  pt.flops = 2.0 * (h0 * h0 + h1 * h1) * (double)ncols;
   ctx->pending_times.push_back(pt);
   return hipSuccess;
 }

@@ -271,17 +271,17 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
 size_t dst_partial_elems(int n, int ncols);
 // int8 slice transform (dst_i8.hip): record table of the sines, support
 bool dst_i8_supported(int n);
-bool dst_i8_fast(int n);   // the 64-column tiles fit (n up to about 6600)
+bool dst_i8_fast(int n);   // the 64-column tiles fit (n up to about 15800)
 size_t dst_i8_table_bytes(int n);
 void dst_i8_table(int n, unsigned char *out);
 size_t dst_i8_work_bytes(int n, int ncols);
 // columns whose slice records one work buffer holds: `want`, capped so that
 // the buffer stays within 512 MiB, but never below 1024
 int dst_i8_work_cols(int n, int want);
-hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, int kchunk,
-                         Solve2D *solves, double *partial, size_t partial_elems,
-                         void *work, size_t work_bytes, hipStream_t st,
-                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, Solve2D *solves,
+                         double *partial, size_t partial_elems, void *work,
+                         size_t work_bytes, hipStream_t st, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
 
 // Row counts: calls on the column side (Xh[:, J], Q0, A) cover the n rows,
 // calls on the row side (Xh[I, :]^T, Q1, B, Vh) the m columns.

@@ -76,6 +76,33 @@ def test_dst_int8_columns_independent_of_batch():
     assert np.array_equal(big[:, 7:9], small)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_dst_columns_independent_of_batch(prec):
+    """The folded transform's K chunks depend on n only: a column's result is
+    the same bits whether its launch splits K over workgroups (few columns)
+    or not (many columns)."""
+    log("dst batch", prec)
+    n = 3001
+    rng = np.random.default_rng(6)
+    X = rng.standard_normal((n, 300))
+    big = host(ctx().sine_transform(dev(X), prec))
+    small = host(ctx().sine_transform(dev(X[:, 7:9]), prec))
+    assert np.array_equal(big[:, 7:9], small)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("bf16x3", 5e-5)])
+@pytest.mark.parametrize("n,c", [(1, 1), (2, 3), (3, 2), (64, 5), (65, 40), (1001, 33)])
+def test_dst_reduced_precision_odd_even_sizes(prec, tol, n, c):
+    """Both parities of the folded transform, odd and even n (with and
+    without the middle point), one- and two-point grids."""
+    log("dst", prec, n, c)
+    rng = np.random.default_rng(n * 13 + c)
+    X = rng.standard_normal((n, c))
+    Y = host(ctx().sine_transform(dev(X), prec))
+    e = rel(Y, poisson.dst(X))
+    assert e <= tol, e
+
+
 @pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("bf16x3", 5e-5)])
 def test_dst_reduced_precision_error_bound(prec, tol):
     log("dst", prec)
