@@ -83,9 +83,9 @@ typedef enum {
  *          float64 recombination: the error-free splitting of Ozaki et al.);
  *          relative error ~1e-12 or below.  Grid sizes up to about 16000
  *          (the sine record table lives in LDS); LRP_EINVAL beyond.
- *  AUTO    per-request plan: INT8 both ways where its 64-column tiles fit
- *          (n up to about 6600; there it is as fast as FP32 and BF16X3 and
- *          accurate to ~1e-12).  Larger grids: forward transform BF16X3 when
+ *  AUTO    per-request plan: INT8 both ways wherever it is supported (n up
+ *          to about 18000; there it is faster than FP64 and FP32 and accurate
+ *          to ~1e-12).  Larger grids: forward transform BF16X3 when
  *          eps >= 1e-6, FP32 when eps >= 1e-7, else FP64; inverse transform
  *          FP32 when eps >= 1e-7, else FP64.  Every floating reduced-precision
  *          transform adds a relative error near its floor (measured: FP32

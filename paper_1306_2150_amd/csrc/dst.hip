@@ -615,8 +615,9 @@ int quarter_len(int n) { return (n + 1) / 2 + 1; }
 }  // namespace
 
 size_t dst_partial_elems(int n, int ncols) {
-  // room for a split of up to 8
-  return (size_t)8 * (size_t)ncols * (size_t)n;
+  // room for a split of the folded K into up to 4 chunks: one float64 per
+  // output and chunk, or six int32 level sums (int8)
+  return (size_t)16 * (size_t)ncols * (size_t)n;
 }
 
 hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,

@@ -37,9 +37,9 @@
 // the dense one): a column becomes two "parity columns", u with the odd
 // rows and w with the even rows, each sliced with its own exponent.
 //
-// K is cut into fixed chunks; the levels of a chunk are combined into float64
-// and the chunk values summed in order, so results do not depend on how many
-// columns share a launch.
+// The level sums are exact integers, so a split of K over workgroups (used
+// when the tiles alone cannot fill the chip) changes nothing: results do not
+// depend on how many columns share a launch.
 #include <algorithm>
 #include <cmath>
 
@@ -51,6 +51,7 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int TMI = 128;         // rows per workgroup: 4 waves x 2 x 16
+constexpr int TNI = 32;          // columns per workgroup
 constexpr int KCI = 32;          // grid points staged per LDS buffer
 constexpr int XST = KCI + 4;     // dwords per staged column and level (+4: bank skew)
 
@@ -142,19 +143,35 @@ __global__ __launch_bounds__(NTHR) void k_x_slices(int n, int hpad, const DstCol
   }
 }
 
+// Value of an output from its exact level sums: Horner in powers of 2^-7
+// (every step but the last two is exact), then the column scale.  The GEMM
+// and the split-K reduction both call this on the same integers, so a
+// result does not depend on how K was split.
+__device__ __forceinline__ double recombine(const int (&acc)[6], double sc) {
+#pragma clang fp contract(off)
+  double v = (double)acc[5];
+  v = v * 0x1p-7 + (double)acc[4];
+  v = v * 0x1p-7 + (double)acc[3];
+  v = v * 0x1p-7 + (double)acc[2];
+  v = v * 0x1p-7 + (double)acc[1];
+  v = v * 0x1p-7 + (double)acc[0];
+  return v * sc;
+}
+
 // FULL: the LDS table holds the records of all m in [0, 2N) (no folding in
 // the inner loop); otherwise the quarter wave q in [0, N/2] with both signs.
-// Tiles: TMI rows of one parity (rows a of the half problem, grid row
-// j = 2a + 1 + p) times TN_ columns; column tile ct holds parity p = ct & 1
-// of columns (ct >> 1) TN_ .. +TN_-1, so both parities of a column block sit
-// next to each other in the XCD order and their interleaved output rows
-// meet in one L2.
+//
+// The level sums over all of K are exact in int32 (|sum| <= 6 2^12 K < 2^31
+// for K < 87000), so one pass needs no intermediate rounding.  With a K
+// split (gridDim.z > 1) workgroup z sums chunk z and writes its six level
+// sums as int32 to `partial` ([z][p][level][a][c], consecutive lanes on
+// consecutive columns); k_dst_i8_reduce adds them exactly and recombines.
 template <int TN_, bool FULL>
 __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__restrict__ rec,
                                                 const DstCol *__restrict__ cols, int ncols,
                                                 int kchunk, const uint2 *__restrict__ xrec,
                                                 int hpad, const int *__restrict__ xex,
-                                                double *__restrict__ partial) {
+                                                int *__restrict__ partial) {
   constexpr int NB = TN_ / 16;
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = n + 1, twoN = 2 * N;
@@ -168,33 +185,26 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
   const int par = ct & 1;
   const int Kp = par ? n / 2 : H0;               // points and rows of this parity
   const int row0 = rt * TMI, c0 = (ct >> 1) * TN_;
-  int cb, ce;
-  if (gridDim.z > 1) {
-    cb = blockIdx.z;
-    ce = blockIdx.z + 1;
-  } else {
-    cb = 0;
-    ce = (H0 + kchunk - 1) / kchunk;
-  }
+  const bool split = gridDim.z > 1;
+  const int kbeg = split ? blockIdx.z * kchunk : 0;
+  const int kend = split ? min(Kp, kbeg + kchunk) : Kp;
   for (int i = tid; i < ntab; i += NTHR) tab[i] = rec[i];
-  // staging share: thread stages grid points tk, columns tc0 + 8 t
+  // staging share: thread stages grid points tk of columns tc0 + 8 t; the
+  // columns' records lie 2 hpad apart
   constexpr int PER = KCI * TN_ / NTHR;
+  constexpr int CSTEP = NTHR / KCI;
   constexpr int LVL = TN_ * XST;                 // dwords per record plane and buffer
   const int tk = tid & (KCI - 1), tc0 = tid / KCI;
-  const uint2 *src[PER];
-#pragma unroll
-  for (int t = 0; t < PER; ++t) {
-    const int c = c0 + tc0 + (NTHR / KCI) * t;
-    src[t] = (c < ncols) ? xrec + (size_t)(2 * c + par) * hpad : nullptr;
-  }
-  const int kbeg = cb * kchunk, kend = min(Kp, ce * kchunk);
+  const int nsrc = max(0, min(PER, ceil_div(ncols - c0 - tc0, CSTEP)));
+  const uint2 *xsrc = xrec + (size_t)(2 * (c0 + tc0) + par) * hpad;
+  const size_t sstep = (size_t)2 * CSTEP * hpad;
   const int nst = (kend - kbeg + KCI - 1) / KCI;
   uint2 pre[PER];
   auto fetch = [&](int st) {
     const int k = kbeg + st * KCI + tk;
 #pragma unroll
     for (int t = 0; t < PER; ++t)
-      pre[t] = (src[t] && k < kend) ? src[t][k] : make_uint2(0u, 0u);
+      pre[t] = (t < nsrc && k < kend) ? xsrc[t * sstep + k] : make_uint2(0u, 0u);
   };
   // the two dwords of the records in two planes [c][k], so that one 16-byte
   // read gives a dword of four consecutive points
@@ -202,7 +212,7 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
     uint32_t *xs = xs0 + (st & 1) * 2 * LVL;
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
-      uint32_t *p = xs + (tc0 + (NTHR / KCI) * t) * XST + tk;
+      uint32_t *p = xs + (tc0 + CSTEP * t) * XST + tk;
       p[0] = pre[t].x;
       p[LVL] = pre[t].y;
     }
@@ -220,46 +230,12 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
     mk[h] = (int)(((long long)jr[h] * (kbeg + 4 * g + 1)) % twoN);
   }
   v4i acc[2][NB][6];
-  double res[2][NB][4];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int t = 0; t < 6; ++t) acc[h][b][t] = (v4i){0, 0, 0, 0};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) res[h][b][q] = 0.0;
-    }
-  const double sc0 = sqrt(2.0 / (double)N);
-  // fold the levels of a finished chunk into the float64 results
-  auto flush = [&]() {
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int c = c0 + 16 * b + li;
-      const int e = (c < ncols) ? xex[2 * c + par] : 0;
-      const double sc = ldexp(sc0, e - 12);
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          double v = (double)acc[h][b][5][q];
-          v = v * 0x1p-7 + (double)acc[h][b][4][q];
-          v = v * 0x1p-7 + (double)acc[h][b][3][q];
-          v = v * 0x1p-7 + (double)acc[h][b][2][q];
-          v = v * 0x1p-7 + (double)acc[h][b][1][q];
-          v = v * 0x1p-7 + (double)acc[h][b][0][q];
-          {
-            // the chunk value is rounded on its own (no fused multiply-add),
-            // as in the split-K path, so both paths add the same numbers
-#pragma clang fp contract(off)
-            const double cv = v * sc;
-            res[h][b][q] = res[h][b][q] + cv;
-          }
-#pragma unroll
-          for (int t = 0; t < 6; ++t) acc[h][b][t][q] = 0;
-        }
-    }
-  };
   if (nst > 0) {
     fetch(0);
     stash(0);
@@ -267,7 +243,6 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
   __syncthreads();
   for (int st = 0; st < nst; ++st) {
     const int k0 = kbeg + st * KCI;
-    if (st > 0 && (k0 % kchunk) == 0) flush();
     if (st + 1 < nst) fetch(st + 1);
     const uint32_t *xs = xs0 + (st & 1) * 2 * LVL;
     const int kcn = min(KCI, kend - k0);
@@ -330,35 +305,55 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
     if (st + 1 < nst) stash(st + 1);
     __syncthreads();
   }
-  flush();
   // D[i][c]: lane c + 16 (i / 4), register i % 4
+  const double sc0 = sqrt(2.0 / (double)N);
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int b = 0; b < NB; ++b) {
+    const int c = c0 + 16 * b + li;
+    const int e = (c < ncols) ? xex[2 * c + par] : 0;
+    const double sc = ldexp(sc0, e - 12);
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int c = c0 + 16 * b + li;
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int a = row0 + 32 * wave + 16 * h + 4 * g + q;
         if (a < Kp && c < ncols) {
-          if (partial)
-            partial[((size_t)blockIdx.z * 2 * ncols + 2 * c + par) * H0 + a] = res[h][b][q];
-          else
-            cols[c].dst[2 * a + par] = res[h][b][q];
+          if (split) {
+            int *pp = partial + (((size_t)blockIdx.z * 2 + par) * 6 * H0 + a) * ncols + c;
+#pragma unroll
+            for (int t = 0; t < 6; ++t) pp[(size_t)t * H0 * ncols] = acc[h][b][t][q];
+          } else {
+            int lv[6];
+#pragma unroll
+            for (int t = 0; t < 6; ++t) lv[t] = acc[h][b][t][q];
+            cols[c].dst[2 * a + par] = recombine(lv, sc);
+          }
         }
       }
-    }
+  }
 }
 
-__global__ void k_dst_i8_reduce(int n, int ncols, int nz, const double *__restrict__ partial,
-                                const DstCol *__restrict__ cols) {
-  const int col = blockIdx.y;
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+// Exact sum of the split-K level sums, then the same recombination as the
+// GEMM's.
+// Threads run along columns (x) so that the partial reads coalesce.
+__global__ void k_dst_i8_reduce(int n, int ncols, int nz, const int *__restrict__ partial,
+                                const int *__restrict__ xex, const DstCol *__restrict__ cols) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = blockIdx.y * blockDim.y + threadIdx.y;
   if (row >= n || col >= ncols) return;
   const int H0 = (n + 1) / 2, par = row & 1, a = row >> 1;
-  double s = 0.0;
-  for (int z = 0; z < nz; ++z) s += partial[((size_t)z * 2 * ncols + 2 * col + par) * H0 + a];
-  cols[col].dst[row] = s;
+  long long s[6] = {0, 0, 0, 0, 0, 0};
+  for (int z = 0; z < nz; ++z) {
+    const int *pp = partial + (((size_t)z * 2 + par) * 6 * H0 + a) * ncols + col;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) s[t] += pp[(size_t)t * H0 * ncols];
+  }
+  // the total over K is bounded like one pass's sum, so it fits int32
+  int lv[6];
+#pragma unroll
+  for (int t = 0; t < 6; ++t) lv[t] = (int)s[t];
+  const double sc = ldexp(sqrt(2.0 / (double)(n + 1)), xex[2 * col + par] - 12);
+  cols[col].dst[row] = recombine(lv, sc);
 }
 
 }  // namespace
@@ -410,8 +405,7 @@ static size_t i8_lds(int n, int tn, bool full) {
 }
 
 constexpr size_t LDS_MAX = 160 * 1024;
-bool dst_i8_supported(int n) { return i8_lds(n, 32, false) <= LDS_MAX; }
-bool dst_i8_fast(int n) { return i8_lds(n, 64, false) <= LDS_MAX; }
+bool dst_i8_supported(int n) { return i8_lds(n, TNI, false) <= LDS_MAX; }
 
 // work per column: two parity records of hpad points, then two exponents
 static int i8_hpad(int n) { return ceil_div((n + 1) / 2, KCI) * KCI; }
@@ -446,35 +440,35 @@ hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, Solve2
     int *xex = (int *)(xrec + (size_t)2 * nc * hpad);
     hipLaunchKernelGGL(k_x_slices, dim3(nc), dim3(NTHR), 0, st, n, hpad, cc, nc, xrec, xex,
                        solves);
-    const bool wide = nc > 32 && i8_lds(n, 64, false) <= LDS_MAX;
-    const int tn = wide ? 64 : 32;
+    // 32-column tiles: two waves per SIMD (their registers fit twice); as
+    // fast as 64-column tiles on large launches, twice the tiles on small
+    constexpr int tn = TNI;
     const bool full = i8_lds(n, tn, true) <= LDS_MAX;
     const unsigned char *tabs = (const unsigned char *)rec;
     const uint2 *trec = (const uint2 *)(full ? tabs + i8_quarter_bytes(n) : tabs);
     const int R = ceil_div(H0, TMI), C = 2 * ceil_div(nc, tn);
     dim3 g(tile_grid(R, C, true), 1, 1);
-    if (R * C < 512 && partial && partial_elems >= (size_t)nchunk * 2 * nc * H0) g.z = nchunk;
-    double *out_partial = g.z > 1 ? partial : nullptr;
+    // split-K partials: six int32 level sums per output and chunk
+    if (R * C < 512 && partial && partial_elems * 2 >= (size_t)nchunk * 2 * nc * 6 * H0)
+      g.z = nchunk;
+    int *out_partial = g.z > 1 ? (int *)partial : nullptr;
     const size_t lds = i8_lds(n, tn, full);
-    const void *fn = wide ? (full ? (const void *)k_dst_i8<64, true> : (const void *)k_dst_i8<64, false>)
-                          : (full ? (const void *)k_dst_i8<32, true> : (const void *)k_dst_i8<32, false>);
+    const void *fn = full ? (const void *)k_dst_i8<tn, true> : (const void *)k_dst_i8<tn, false>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (ev0 && c0 == 0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
 #define LRP_I8_LAUNCH(TNV, FV)                                                              \
   hipLaunchKernelGGL((k_dst_i8<TNV, FV>), g, dim3(NTHR), lds, st, n, Q, trec, cc, nc, kchunk, \
                      xrec, hpad, xex, out_partial)
-    if (wide && full) LRP_I8_LAUNCH(64, true);
-    else if (wide) LRP_I8_LAUNCH(64, false);
-    else if (full) LRP_I8_LAUNCH(32, true);
-    else LRP_I8_LAUNCH(32, false);
+    if (full) LRP_I8_LAUNCH(tn, true);
+    else LRP_I8_LAUNCH(tn, false);
 #undef LRP_I8_LAUNCH
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (ev1 && c0 + nc >= ncols && (e = hipEventRecord(ev1, st)) != hipSuccess) return e;
     if (g.z > 1) {
-      hipLaunchKernelGGL(k_dst_i8_reduce, dim3(ceil_div(n, 256), nc), dim3(256), 0, st, n, nc,
-                         (int)g.z, (const double *)partial, cc);
+      hipLaunchKernelGGL(k_dst_i8_reduce, dim3(ceil_div(nc, 64), ceil_div(n, 4)), dim3(64, 4), 0,
+                         st, n, nc, (int)g.z, (const int *)partial, (const int *)xex, cc);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
   }

@@ -130,9 +130,9 @@ Plan make_plan(const lrp_opts *o, double eps, int n) {
   p.min_slack = std::max(1, p.kick / 2);
   p.tau = (o && o->maxvol_tau > 1.0) ? o->maxvol_tau : 1.05;
   if (prec == LRP_PREC_AUTO) {
-    if (dst_i8_fast(n)) {
-      // exact int8 slices: about 1e-12 and at least as fast as the float32
-      // and split-bfloat16 transforms wherever their wide tiles fit in LDS
+    if (dst_i8_supported(n)) {
+      // exact int8 slices: about 1e-12, faster than the float64 and float32
+      // transforms wherever the sine record table fits in LDS
       p.fwd_prec = p.inv_prec = LRP_PREC_INT8;
     } else {
       // the inverse transform's relative error reaches the result undamped;

@@ -270,8 +270,7 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
                       hipStream_t st, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 size_t dst_partial_elems(int n, int ncols);
 // int8 slice transform (dst_i8.hip): record table of the sines, support
-bool dst_i8_supported(int n);
-bool dst_i8_fast(int n);   // the 64-column tiles fit (n up to about 15800)
+bool dst_i8_supported(int n);   // the sine record table fits LDS (n up to about 18000)
 size_t dst_i8_table_bytes(int n);
 void dst_i8_table(int n, unsigned char *out);
 size_t dst_i8_work_bytes(int n, int ncols);
