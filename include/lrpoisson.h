@@ -209,11 +209,13 @@ lrp_status lrp_sine_transform(lrp_ctx *ctx, int64_t n, int32_t ncols,
  * events recorded on the stream it runs on (the int8 slicing pass and a
  * split-K reduction stay outside); lrp_kernel_stats() waits for them and
  * returns, per precision (index = lrp_precision: 0 FP64, 2 FP32, 3 BF16X3,
- * 4 INT8), the number of calls, columns, their summed duration in ms and the
+ * 4 INT8), the number of timed GEMM dispatches (an int8 transform of more
+ * columns than its work buffer holds runs several), columns, their summed
+ * duration in ms and the
  * summed algorithmic work of the folded transform (two half-size GEMMs:
  * 2 (H0^2 + H1^2) flops per column, H0 = ceil(n/2), H1 = floor(n/2); the
  * dense product would be 2 n^2).  reset != 0 clears the counters after
- * reading.  Timing adds two event records per call. */
+ * reading.  Timing adds two event records per dispatch. */
 typedef struct {
   int64_t launches;
   int64_t columns;

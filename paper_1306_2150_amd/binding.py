@@ -185,6 +185,55 @@ def _stream(stream):
     return ctypes.c_void_p(int(s.cuda_stream))
 
 
+class Batch2D:
+    """Arguments of one lrpoisson_solve2d_batch call, kept for repeated runs:
+    problems (U, V, eps) on one grid size, one (Ux, Vx) output pair of rmax
+    columns per problem (the views of the last run's results stay valid until
+    the next run overwrites them)."""
+
+    def __init__(self, ctx, problems, prec, rmax, kw):
+        import torch
+        self.ctx = ctx
+        self.n = n = problems[0][0].shape[0] if problems else 0
+        self.rmax = rmax = MAX_RANK if rmax is None else rmax
+        nb = len(problems)
+        dev = problems[0][0].device if problems else "cuda"
+        # all outputs in two allocations: Ux of problem i = columns
+        # [i rmax, (i+1) rmax) of one n x (nb rmax) column-major block
+        w = max(rmax, 1)
+        self._ux = torch.empty((nb * w, max(n, 1)), dtype=torch.float64, device=dev)
+        self._vx = torch.empty((nb * w, max(n, 1)), dtype=torch.float64, device=dev)
+        self.outs = [(self._ux[i * w:i * w + rmax].T, self._vx[i * w:i * w + rmax].T)
+                     for i in range(nb)]
+        self.arr = (LrpProblem2D * nb)()
+        for i, (U, V, eps) in enumerate(problems):
+            Ux, Vx = self.outs[i]
+            r = U.shape[1]
+            self.arr[i] = LrpProblem2D(_ptr(U), _ptr(V), _ld(U) if r else n, r, rmax,
+                                       eps, Ux.data_ptr(), Vx.data_ptr(), max(n, 1), 0,
+                                       LrpInfo())
+        self.opts = _opts(prec, **kw)
+        self.inputs = problems            # keeps the inputs alive
+
+    def run(self, stream=None, results=True):
+        """Solve every problem; returns [(Ux, Vx, info)] (views of the
+        reused outputs) or, with results=False, None."""
+        nb = len(self.arr)
+        if nb == 0:
+            return []
+        st = self.ctx.lib.lrpoisson_solve2d_batch(self.ctx.h, self.n, nb, self.arr,
+                                                  ctypes.byref(self.opts), _stream(stream))
+        if st in (LRP_EINVAL, LRP_EDEVICE, LRP_ENOMEM):
+            raise LrpError(st, "lrpoisson_solve2d_batch")
+        if not results:
+            return None
+        res = []
+        for i, (Ux, Vx) in enumerate(self.outs):
+            R = self.arr[i].rank_out
+            res.append((Ux[:, :R], Vx[:, :R], self.arr[i].info.as_dict()))
+        return res
+
+
 class Context:
     """Solver context on one GPU (owns tables and workspace)."""
 
@@ -234,28 +283,13 @@ class Context:
         (Ux, Vx, info)."""
         if not problems:
             return []
-        n = problems[0][0].shape[0]
-        rmax = MAX_RANK if rmax is None else rmax
-        arr = (LrpProblem2D * len(problems))()
-        outs = []
-        for i, (U, V, eps) in enumerate(problems):
-            Ux = empty_colmajor(n, rmax, U.device)
-            Vx = empty_colmajor(n, rmax, U.device)
-            outs.append((Ux, Vx))
-            r = U.shape[1]
-            arr[i] = LrpProblem2D(_ptr(U), _ptr(V), _ld(U) if r else n, r, rmax,
-                                  eps, _ptr(Ux), _ptr(Vx), n, 0, LrpInfo())
-        opts = _opts(prec, **kw)
-        st = self.lib.lrpoisson_solve2d_batch(self.h, n, len(problems), arr,
-                                              ctypes.byref(opts), _stream(stream))
-        if st in (LRP_EINVAL, LRP_EDEVICE, LRP_ENOMEM):
-            raise LrpError(st, "lrpoisson_solve2d_batch")
-        res = []
-        for i, (Ux, Vx) in enumerate(outs):
-            R = arr[i].rank_out
-            d = arr[i].info.as_dict()
-            res.append((Ux[:, :R], Vx[:, :R], d))
-        return res
+        return self.batch2d(problems, prec=prec, rmax=rmax, **kw).run(stream)
+
+    def batch2d(self, problems, prec="fp64", rmax=None, **kw):
+        """A prepared batch: the argument array and the output factors are
+        built once and reused by every ``run()`` (each run solves every
+        problem of the batch from its inputs)."""
+        return Batch2D(self, problems, prec, rmax, kw)
 
     # ---- 3D
     def solve3d(self, U1, U2, U3, G, eps, rmax=None, prec="fp64", stream=None,

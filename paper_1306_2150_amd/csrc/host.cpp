@@ -39,20 +39,30 @@ hipError_t timed_dst(lrp_ctx *ctx, int prec, int n, const void *tab,
   if (!ctx->timing)
     return launch_dst(prec, n, tab, cols, ncols, solves, partial, partial_elems, work,
                       work_bytes, st);
-  lrp_ctx::PendingTime pt;
-  hipError_t e = hipEventCreate(&pt.a);
-  if (e != hipSuccess) return e;
-  if ((e = hipEventCreate(&pt.b)) != hipSuccess) return e;
-  // the window covers the GEMM kernel only, as a kernel trace reports it
-  e = launch_dst(prec, n, tab, cols, ncols, solves, partial, partial_elems, work, work_bytes,
-                 st, pt.a, pt.b);
-  if (e != hipSuccess) return e;
-  pt.prec = prec;
-  pt.cols = ncols;
+  // one timing window per GEMM dispatch: the int8 transform runs one
+  // dispatch per work-buffer load of columns, so it is called per load here
+  int per = ncols;
+  if (prec == LRP_PREC_INT8) {
+    const size_t cb = dst_i8_work_bytes(n, 1);
+    per = (int)std::max<size_t>(1, std::min<size_t>((size_t)ncols, work_bytes / cb));
+  }
   // the folded transform: two half-size GEMMs of H0 = ceil(n/2), H1 = floor(n/2)
   const double h0 = (double)((n + 1) / 2), h1 = (double)(n / 2);
-  pt.flops = 2.0 * (h0 * h0 + h1 * h1) * (double)ncols;
-  ctx->pending_times.push_back(pt);
+  for (int c0 = 0; c0 < ncols; c0 += per) {
+    const int cnt = std::min(per, ncols - c0);
+    lrp_ctx::PendingTime pt;
+    hipError_t e = hipEventCreate(&pt.a);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventCreate(&pt.b)) != hipSuccess) return e;
+    // the window covers the GEMM kernel only, as a kernel trace reports it
+    e = launch_dst(prec, n, tab, cols + c0, cnt, solves, partial, partial_elems, work,
+                   work_bytes, st, pt.a, pt.b);
+    if (e != hipSuccess) return e;
+    pt.prec = prec;
+    pt.cols = cnt;
+    pt.flops = 2.0 * (h0 * h0 + h1 * h1) * (double)cnt;
+    ctx->pending_times.push_back(pt);
+  }
   return hipSuccess;
 }
 
