@@ -23,6 +23,8 @@
 namespace lrp {
 namespace {
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 template <int KM>
 __global__ __launch_bounds__(NTHR) void k_eval(int which, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
@@ -102,55 +104,77 @@ __global__ __launch_bounds__(NTHR) void k_factors(Solve2D *S) {
     if (c < kk) out[i + (long)c * ld] = acc[c];
 }
 
-// Partial M = Bp^T B: block b sums the 256-row chunks b, b + nbm, ... of the
-// m rows (nbm = change_blocks(m), a function of m only, so the summation
-// order of a slot never depends on the batch); each thread owns a 4 x 4
-// tile of the (<= 64 x 64) result.
+// Block b of Mc = Bp^T B (kp x k, the previous sweep's row factor against
+// this one's): rows [256 b, 256 b + 256) + 256 nbm t of the m rows (nbm =
+// change_blocks(m), a function of m only, so the summation order of a slot
+// never depends on the batch).  Float64 matrix cores (v_mfma_f64_16x16x4):
+// wave w takes rows 64 w .. 64 w + 63 of each 256-row slab, eight rows per
+// step with lane group g on rows 2 g and 2 g + 1 of the step (the K order of
+// the two operands is the same, so any such order gives the sum); the four
+// waves' partial sums are added in LDS in wave order.
+template <int KM>
 __global__ __launch_bounds__(NTHR) void k_change_M(int nbm, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (s.active != ACT_SWEEP || s.kp == 0) return;
-  __shared__ double bp[64 * KMAX];   // [row][col]
-  __shared__ double bb[64 * KMAX];
+  constexpr int NB = KM / 16;
+  __shared__ double red[KMAX * KMAX];
   const int kk = s.k, kq = s.kp, m = s.m;
   const long ld = s.ldv;
-  const int ta = (threadIdx.x >> 4) * 4, tc = (threadIdx.x & 15) * 4;
-  double acc[4][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const double *bp[NB], *bb[NB];
 #pragma unroll
-  for (int x = 0; x < 4; ++x)
+  for (int t = 0; t < NB; ++t) {
+    const int c = 16 * t + li;
+    bp[t] = (c < kq) ? s.Bp + (long)c * ld : nullptr;
+    bb[t] = (c < kk) ? s.B + (long)c * ld : nullptr;
+  }
+  d4 acc[NB][NB];
 #pragma unroll
-    for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+  for (int a = 0; a < NB; ++a)
+#pragma unroll
+    for (int c = 0; c < NB; ++c) acc[a][c] = (d4){0, 0, 0, 0};
   for (int r0 = blockIdx.x * PANEL_M; r0 < m; r0 += nbm * PANEL_M) {
-    for (int ch = 0; ch < PANEL_M / 64; ++ch) {
-      const int rb = r0 + ch * 64;
-      __syncthreads();
-      for (int e = threadIdx.x; e < 64 * KMAX; e += NTHR) {
-        const int c = e >> 6, rr = e & 63;
-        const int row = rb + rr;
-        const bool ok = row < m;
-        bp[rr * KMAX + c] = (ok && c < kq) ? s.Bp[row + (long)c * ld] : 0.0;
-        bb[rr * KMAX + c] = (ok && c < kk) ? s.B[row + (long)c * ld] : 0.0;
-      }
-      __syncthreads();
-      for (int rr = 0; rr < 64; ++rr) {
-        double x[4], y[4];
+    for (int st = 0; st < 8; ++st) {
+      const int row = r0 + 64 * wave + 8 * st + 2 * g;
+      double xa[NB][2], xb[NB][2];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          x[t] = bp[rr * KMAX + ta + t];
-          y[t] = bb[rr * KMAX + tc + t];
+      for (int t = 0; t < NB; ++t)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const bool ok = row + e < m;
+          xa[t][e] = (bp[t] && ok) ? bp[t][row + e] : 0.0;
+          xb[t][e] = (bb[t] && ok) ? bb[t][row + e] : 0.0;
         }
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+      for (int e = 0; e < 2; ++e)
 #pragma unroll
-          for (int c = 0; c < 4; ++c) acc[a][c] += x[a] * y[c];
-      }
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+          for (int c = 0; c < NB; ++c)
+            acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa[a][e], xb[c][e], acc[a][c], 0, 0, 0);
     }
   }
+  // D[i][j]: lane j + 16 (i % 4), register i / 4
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int a = 0; a < NB; ++a)
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int e = (16 * a + 4 * r + g) * KMAX + 16 * c + li;
+            red[e] = (w == 0) ? acc[a][c][r] : red[e] + acc[a][c][r];
+          }
+    }
+    __syncthreads();
+  }
   double *P = s.part + (size_t)blockIdx.x * KMAX * KMAX;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-      if (ta + a < kq && tc + c < kk) P[(ta + a) * kk + tc + c] = acc[a][c];
+  for (int e = threadIdx.x; e < kq * kk; e += NTHR) {
+    const int a = e / kk, c = e - a * kk;
+    P[e] = red[a * KMAX + c];
+  }
 }
 
 __global__ __launch_bounds__(NTHR) void k_change_reduce(int nbm, Solve2D *S) {
@@ -478,7 +502,7 @@ int change_blocks(int m) { return min(ceil_div(m, PANEL_M), 256); }
 hipError_t launch_change(int n, int m, Solve2D *s, int nsolves, int kmax,
                          hipStream_t st) {
   const int nbm = change_blocks(m);
-  hipLaunchKernelGGL(k_change_M, dim3(nbm, nsolves), dim3(NTHR), 0, st, nbm, s);
+  LRP_BUCKET(k_change_M, dim3(nbm, nsolves), nbm, s);
   hipLaunchKernelGGL(k_change_reduce, dim3(nsolves), dim3(NTHR), 0, st, nbm, s);
   dim3 g(ceil_div(max(n, m), NTHR), nsolves);
   LRP_BUCKET(k_change_norms, g, s);

@@ -22,6 +22,8 @@
 namespace lrp {
 namespace {
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 struct MvIO {
   const double *Q;
   long ld;
@@ -180,36 +182,77 @@ __global__ __launch_bounds__(NTHR) void k_mv_inv(int which, int n, int force,
     for (int c = cl; c < kk; c += 64) io.inv[t + c * KMAX] = a[pivrow[t]][kk + c];
 }
 
-// ---- per block: rows of B = Q Inv, report the MV_TOP largest rows > tau
+// ---- per block: rows of B = Q Inv, report the MV_TOP largest rows > tau.
+// B is formed on the float64 matrix cores (v_mfma_f64_16x16x4): wave w
+// takes rows 64 w .. 64 w + 63 of the block as four 16-row blocks; the
+// B operand (Inv, zero past k) stays in registers for the whole K loop.
+// Operand layouts: A[i][kq] in lane i + 16 kq, B[kq][j] in lane j + 16 kq,
+// D[i][j] in lane j + 16 (i % 4), register i / 4.
 template <int KM>
 __global__ __launch_bounds__(NTHR) void k_mv_check(int which, int n, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (s.active != mv_phase(which) || s.mv_done) return;
-  __shared__ double inv[KMAX * KMAX];
+  constexpr int NC = KM / 16;                   // 16-column blocks of B
+  constexpr int NK = KM / 4;                    // K steps
+  __shared__ double rowmax[NTHR];
   __shared__ double rv[4];
   __shared__ int rk[4];
   const int kk = s.k;
   const MvIO io = mv_io(which, s);
-  for (int i = threadIdx.x >> 6; i < kk; i += 4)
-    for (int c = threadIdx.x & 63; c < kk; c += 64) inv[i * KMAX + c] = io.inv[i + c * KMAX];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  double binv[NK][NC];
+#pragma unroll
+  for (int kb = 0; kb < NK; ++kb)
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) {
+      const int r = 4 * kb + g, c = 16 * cb + li;
+      binv[kb][cb] = (r < kk && c < kk) ? io.inv[r + c * KMAX] : 0.0;
+    }
+  const int rw0 = blockIdx.x * NTHR + 64 * wave + li;   // + 16 rb
+  d4 acc[4][NC];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) acc[rb][cb] = (d4){0, 0, 0, 0};
+#pragma unroll
+  for (int kb = 0; kb < NK; ++kb) {
+    const int col = 4 * kb + g;
+    double a[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+      const int row = rw0 + 16 * rb;
+      a[rb] = (row < n && col < kk) ? io.Q[row + (long)col * io.ld] : 0.0;
+    }
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb)
+        acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], binv[kb][cb], acc[rb][cb], 0, 0, 0);
+  }
+  // largest |B| of each row: over the column blocks in the lane, then over
+  // the 16 lanes (one DPP row) that hold the row's columns; lane 15 of the
+  // DPP row ends with the row's value
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double v = 0.0;
+#pragma unroll
+      for (int cb = 0; cb < NC; ++cb) v = fmax(v, fabs(acc[rb][cb][r]));
+      v = fmax(v, dpp_f64<DPP_QUAD_1032>(v));
+      v = fmax(v, dpp_f64<DPP_QUAD_2301>(v));
+      v = fmax(v, dpp_f64<DPP_ROW_SHR4>(v));
+      v = fmax(v, dpp_f64<DPP_ROW_SHR8>(v));
+      if (li == 15) rowmax[64 * wave + 16 * rb + 4 * r + g] = v;
+    }
   __syncthreads();
   const int row = blockIdx.x * NTHR + threadIdx.x;
   double mx = -1.0;
   if (row < n) {
-    double acc[KM];
-#pragma unroll
-    for (int c = 0; c < KM; ++c) acc[c] = 0.0;
-    for (int j = 0; j < kk; ++j) {
-      const double q = io.Q[row + (long)j * io.ld];
-#pragma unroll
-      for (int c = 0; c < KM; ++c) acc[c] += q * inv[j * KMAX + c];
-    }
-#pragma unroll
-    for (int c = 0; c < KM; ++c)
-      if (c < kk) mx = fmax(mx, fabs(acc[c]));
+    mx = rowmax[threadIdx.x];
     if (!(mx > s.tau)) mx = -1.0;   // only violators compete
   }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int t = 0; t < MV_TOP; ++t) {
     double v = mx;
     int key = (row < n) ? row : 0x7fffffff;
