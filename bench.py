@@ -47,11 +47,11 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "int8": 5.0e15}
 # workload and batch); otherwise the traffic is reported as null.
 TRAFFIC = {
     "k_dst_i8": {"sources": ["dst_i8.hip", "lrp_internal.h"],
-                 "sha1": "65311813afca2ecbcfaf0abcad939cf332115f81",
-                 "columns": 11990.857, "fetch_kib": 192646.2, "write_kib": 384146.6},
+                 "sha1": "6ef1a39ee0054932177f4e9201995b3ff5c8dcaa",
+                 "columns": 11990.857, "fetch_kib": 196880.8, "write_kib": 384149.7},
     "k_dst_f64": {"sources": ["dst.hip", "lrp_internal.h"],
                   "sha1": "89ceb79ba3dffd97494429b4422404ae52ec9fd4",
-                  "columns": 41968, "fetch_kib": 675665.8, "write_kib": 1342976.0},
+                  "columns": 41968, "fetch_kib": 675671.7, "write_kib": 1342976.0},
 }
 
 

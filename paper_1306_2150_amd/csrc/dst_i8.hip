@@ -440,28 +440,34 @@ hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, Solve2
     int *xex = (int *)(xrec + (size_t)2 * nc * hpad);
     hipLaunchKernelGGL(k_x_slices, dim3(nc), dim3(NTHR), 0, st, n, hpad, cc, nc, xrec, xex,
                        solves);
-    // 32-column tiles: two waves per SIMD (their registers fit twice); as
-    // fast as 64-column tiles on large launches, twice the tiles on small
-    constexpr int tn = TNI;
+    // 64-column tiles (one wave per SIMD, 20-25 % faster on large launches
+    // than 32-column tiles at two waves per SIMD) when they alone give every
+    // CU a workgroup; 32-column tiles, twice as many, on small launches
+    const int R = ceil_div(H0, TMI);
+    const bool wide = R * 2 * ceil_div(nc, 64) >= 256 && i8_lds(n, 64, false) <= LDS_MAX;
+    const int tn = wide ? 64 : TNI;
     const bool full = i8_lds(n, tn, true) <= LDS_MAX;
     const unsigned char *tabs = (const unsigned char *)rec;
     const uint2 *trec = (const uint2 *)(full ? tabs + i8_quarter_bytes(n) : tabs);
-    const int R = ceil_div(H0, TMI), C = 2 * ceil_div(nc, tn);
+    const int C = 2 * ceil_div(nc, tn);
     dim3 g(tile_grid(R, C, true), 1, 1);
     // split-K partials: six int32 level sums per output and chunk
     if (R * C < 512 && partial && partial_elems * 2 >= (size_t)nchunk * 2 * nc * 6 * H0)
       g.z = nchunk;
     int *out_partial = g.z > 1 ? (int *)partial : nullptr;
     const size_t lds = i8_lds(n, tn, full);
-    const void *fn = full ? (const void *)k_dst_i8<tn, true> : (const void *)k_dst_i8<tn, false>;
+    const void *fn = wide ? (full ? (const void *)k_dst_i8<64, true> : (const void *)k_dst_i8<64, false>)
+                          : (full ? (const void *)k_dst_i8<TNI, true> : (const void *)k_dst_i8<TNI, false>);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (ev0 && c0 == 0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
 #define LRP_I8_LAUNCH(TNV, FV)                                                              \
   hipLaunchKernelGGL((k_dst_i8<TNV, FV>), g, dim3(NTHR), lds, st, n, Q, trec, cc, nc, kchunk, \
                      xrec, hpad, xex, out_partial)
-    if (full) LRP_I8_LAUNCH(tn, true);
-    else LRP_I8_LAUNCH(tn, false);
+    if (wide && full) LRP_I8_LAUNCH(64, true);
+    else if (wide) LRP_I8_LAUNCH(64, false);
+    else if (full) LRP_I8_LAUNCH(TNI, true);
+    else LRP_I8_LAUNCH(TNI, false);
 #undef LRP_I8_LAUNCH
     e = hipGetLastError();
     if (e != hipSuccess) return e;
