@@ -84,6 +84,9 @@ def parse():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=6)
+    ap.add_argument("--batch-sweep", type=str, default="",
+                    help="comma-separated batch sizes: also report solves/s of both "
+                         "plans at each (e.g. 1,8,32,128,256,512,1024)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="copy this many MiB once first (HBM counter calibration)")
     return ap.parse_args()
@@ -225,6 +228,22 @@ def main():
                      "checked": len(hostrhs)},
         "roofline": roofline,
     }
+
+    if args.batch_sweep:
+        sweep = []
+        for b in [int(x) for x in args.batch_sweep.split(",") if x]:
+            probs = [(devrhs[i % args.distinct][0], devrhs[i % args.distinct][1], eps)
+                     for i in range(b)]
+            rec = {"batch": b}
+            for plan in ("auto", "fp64"):
+                steps = max(2, min(20, 2048 // max(b, 1)))
+                dt, _, _ = timed_steps(ctx, probs, plan, steps, 1)
+                rec[plan] = {"solves_per_s": b * steps / dt, "ms_per_step": dt / steps * 1e3}
+            print(f"[bench] batch {b}: auto {rec['auto']['solves_per_s']:.1f} solves/s "
+                  f"({rec['auto']['ms_per_step']:.2f} ms), fp64 "
+                  f"{rec['fp64']['solves_per_s']:.1f}", file=sys.stderr, flush=True)
+            sweep.append(rec)
+        line["batch_sweep"] = sweep
 
     if not args.no_serve:
         from paper_1306_2150_amd import serving

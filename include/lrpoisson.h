@@ -81,7 +81,7 @@ typedef enum {
  *  INT8    int8 MFMA on exact 7-bit integer slices of both operands (six
  *          slices each, the products of slice levels <= 5, int32 sums,
  *          float64 recombination: the error-free splitting of Ozaki et al.);
- *          relative error ~1e-12 or below.  Grid sizes up to about 16000
+ *          relative error ~1e-12 or below.  Grid sizes up to about 18000
  *          (the sine record table lives in LDS); LRP_EINVAL beyond.
  *  AUTO    per-request plan: INT8 both ways wherever it is supported (n up
  *          to about 18000; there it is faster than FP64 and FP32 and accurate

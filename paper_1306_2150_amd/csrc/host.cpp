@@ -151,8 +151,8 @@ Plan make_plan(const lrp_opts *o, double eps, int n) {
       p.fwd_prec = eps >= 1e-6 ? LRP_PREC_BF16X3 : (eps >= 1e-7 ? LRP_PREC_FP32 : LRP_PREC_FP64);
       p.inv_prec = eps >= 1e-7 ? LRP_PREC_FP32 : LRP_PREC_FP64;
     }
-  } else if (prec == LRP_PREC_FP32 || prec == LRP_PREC_BF16X3) {
-    p.fwd_prec = p.inv_prec = prec;
+  } else if (prec == LRP_PREC_FP32 || prec == LRP_PREC_BF16X3 || prec == LRP_PREC_INT8) {
+    p.fwd_prec = p.inv_prec = prec;      // INT8 callers check dst_i8_supported(n)
   } else {
     p.fwd_prec = p.inv_prec = LRP_PREC_FP64;
   }
@@ -640,6 +640,7 @@ lrp_status lrpoisson_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t count,
   if (!ctx || !probs || count < 0) return LRP_EINVAL;
   if (n < 1 || n > LRP_MAX_N) return LRP_EINVAL;
   if (opts && (opts->prec < 0 || opts->prec > LRP_PREC_INT8)) return LRP_EINVAL;
+  if (opts && opts->prec == LRP_PREC_INT8 && !dst_i8_supported((int)n)) return LRP_EINVAL;
   for (int i = 0; i < count; ++i) {
     lrp_status e = check_problem(n, probs[i]);
     if (e != LRP_OK) return e;

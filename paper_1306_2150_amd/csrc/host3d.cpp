@@ -255,6 +255,7 @@ extern "C" lrp_status lrpoisson_solve3d(lrp_ctx *ctx, int64_t n, const int32_t r
                                         int32_t rank_out[3], lrp_info *info, void *stream) {
   if (!ctx || !rank_out) return LRP_EINVAL;
   if (opts && (opts->prec < 0 || opts->prec > LRP_PREC_INT8)) return LRP_EINVAL;
+  if (opts && opts->prec == LRP_PREC_INT8 && !dst_i8_supported((int)n)) return LRP_EINVAL;
   const double *U[3] = {U1, U2, U3};
   double *X[3] = {U1x, U2x, U3x};
   lrp_status e = check_problem3d(n, rank, U, ld, G, eps, X, ldx, Gx, rmax);

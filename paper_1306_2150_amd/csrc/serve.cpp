@@ -33,6 +33,8 @@ constexpr size_t SERVE3_SHARE = (size_t)16 << 30;   // bytes per 3D group
 
 lrp_status check_request(const lrp_request &q) {
   if (q.prec < 0 || q.prec > LRP_PREC_INT8) return LRP_EINVAL;
+  if (q.prec == LRP_PREC_INT8 && (q.n < 1 || q.n > LRP_MAX_N || !dst_i8_supported((int)q.n)))
+    return LRP_EINVAL;
   if (q.dim == 3) {
     const int32_t *rk = q.rank, *rm = q.rmax;
     return check_problem3d(q.n, rk, q.U, q.ld, q.G, q.eps, q.X, q.ldx, q.Gx, rm);

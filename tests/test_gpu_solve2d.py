@@ -280,3 +280,47 @@ def test_solve2d_mixed_precision(prec, eps, bar):
     log("solve2d mixed", prec, eps)
     U, V = inputs.workload_rhs(2, 1, n=4096)
     solve_and_check(U, V, eps, prec=prec, bar=bar)
+
+
+# ---------------------------------------------- precision workload, n = 16384
+@pytest.fixture(scope="module")
+def n16384_case():
+    """The 16384-point rank-32 bump workload at eps = 1e-7 and its float64
+    full-grid solution (2 GiB, computed once)."""
+    U, V = inputs.workload_rhs(4, 1)
+    X = poisson.full_solve2d_factors(U, V, workers=16)
+    return U, V, X
+
+
+@pytest.mark.parametrize("prec,bar", [("fp64", 1e-6), ("auto", 1e-6), ("int8", 1e-6),
+                                      ("fp32", 1e-6), ("bf16x3", 5e-5)])
+def test_precision_workload_n16384(n16384_case, prec, bar):
+    """Error of every transform precision against the float64 full solve at
+    n = 16384, r = 32, eps = 1e-7 (the acceptance bar 10 eps = 1e-6 for the
+    float64, int8 and FP32 plans; BF16x3 transforms have a relative error
+    floor near 5e-6, so their bar is that floor's order)."""
+    U, V, X = n16384_case
+    log("precision n=16384", prec)
+    Ux, Vx, info = ctx().solve2d(dev(U), dev(V), 1e-7, prec=prec)
+    e = metrics.rel_err_factored(host(Ux), host(Vx), X)
+    log("  fwd", info["fwd_prec"], "inv", info["inv_prec"], "rank", info["rank"],
+        "sweeps", info["sweeps"], "err", e)
+    assert info["status_code"] == binding.LRP_OK
+    if prec != "auto":
+        assert info["fwd_prec"] == prec and info["inv_prec"] == prec, info
+    assert e <= bar, e
+
+
+def test_int8_plan_limits():
+    """An explicit INT8 plan runs the int8 transforms both ways, and a grid
+    too large for its sine record table is refused (LRP_EINVAL) rather than
+    solved another way."""
+    log("int8 plan")
+    U, V = inputs.workload_rhs(2, 1, n=1000)
+    Ux, Vx, info = ctx().solve2d(dev(U), dev(V), 1e-8, prec="int8")
+    assert info["fwd_prec"] == "int8" and info["inv_prec"] == "int8"
+    n = 20000
+    big = dev(np.ones((n, 1)))
+    with pytest.raises(binding.LrpError) as ei:
+        ctx().solve2d(big, big, 1e-6, prec="int8")
+    assert ei.value.status == binding.LRP_EINVAL
