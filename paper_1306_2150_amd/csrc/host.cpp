@@ -448,7 +448,7 @@ lrp_status Group2D::step(hipStream_t st) {
   HIPCHK(launch_eval(EV_ROWS, m_, d_s_, hi, kev, st));
   HIPCHK(launch_tsqr(TS_C_TO_Q1, m_, tm, d_s_, hi, km, st));
   HIPCHK(launch_maxvol(MV_Q1_TO_JN, m_, tm, d_s_, hi, km, st));
-  HIPCHK(launch_core(ACT_SWEEP, d_s_, hi, st));
+  HIPCHK(launch_core(ACT_SWEEP, d_s_, hi, km, st));
   HIPCHK(launch_factors(n_, m_, d_s_, hi, km, st));
   HIPCHK(launch_change(n_, m_, d_s_, hi, km, st));
   HIPCHK(launch_decide(n_, m_, d_s_, hi, kev, st));

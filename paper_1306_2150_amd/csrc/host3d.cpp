@@ -160,7 +160,7 @@ lrp_status Group3D::step(hipStream_t st) {
   HIPCHK3(launch_core_build(d_s_, hi, st));
   HIPCHK3(launch_core_unfold(d_s_, hi, P, st));
   HIPCHK3(launch_tsqr(TS_CORE, P, tp, inner_->dev_solves(), 3 * hi, KMAX, st));
-  HIPCHK3(launch_core(ACT_CORE, inner_->dev_solves(), 3 * hi, st));
+  HIPCHK3(launch_core(ACT_CORE, inner_->dev_solves(), 3 * hi, KMAX, st));
   HIPCHK3(launch_tucker_out(d_s_, hi, n_, st));
   return LRP_OK;
 }

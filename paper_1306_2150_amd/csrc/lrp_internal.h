@@ -298,7 +298,8 @@ enum : int { MV_Q0_TO_I = 0, MV_Q1_TO_JN = 1, MV_Q1_TO_J = 2 };
 hipError_t launch_maxvol(int which, int rows, const Tree &tr, Solve2D *s,
                          int nsolves, int kmax, hipStream_t st);
 
-hipError_t launch_core(int phase, Solve2D *s, int nsolves, hipStream_t st);
+// kmax: the largest k of the launch's solves (selects the LDS bucket)
+hipError_t launch_core(int phase, Solve2D *s, int nsolves, int kmax, hipStream_t st);
 hipError_t launch_factors(int n, int m, Solve2D *s, int nsolves, int kmax,
                           hipStream_t st);
 // blocks of the change's partial Gram sums over m rows (fixed per m)

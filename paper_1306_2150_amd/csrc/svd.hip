@@ -8,14 +8,13 @@
 // The core SVD is one-sided (Hestenes) Jacobi, which keeps small singular
 // values to high relative accuracy (needed for tail truncation at 1e-10);
 // one 256-thread workgroup per solve, K and the accumulated right rotations
-// in LDS, rotations applied to disjoint column pairs in parallel
-// (round-robin ordering).
+// in LDS (sized for the launch's rank bucket, so several workgroups share a
+// CU), rotations applied to disjoint column pairs in parallel (round-robin
+// ordering).
 #include "lrp_internal.h"
 
 namespace lrp {
 namespace {
-
-constexpr int LD = KMAX + 1;
 
 // Sum over one 16-lane DPP row; every lane of the row gets the total.
 __device__ __forceinline__ double row_sum16(double v) {
@@ -29,31 +28,32 @@ __device__ __forceinline__ double row_sum16(double v) {
 // phase ACT_SWEEP: K = InvC Rfin^T (the cross core); phase ACT_CORE (3D
 // path): K = Rfin^T, whose left singular vectors W are those of the Tucker
 // core unfolding that the preceding TSQR factored.
+template <int KM>
 __global__ __launch_bounds__(NTHR) void k_core(int phase, Solve2D *S) {
+  constexpr int LD = KM + 1;
   Solve2D &s = S[blockIdx.x];
   if (s.active != phase) return;
   const bool plain = phase == ACT_CORE;
-  __shared__ double K[KMAX * LD];   // column c at K[c*LD + i]
-  __shared__ double V[KMAX * LD];
-  __shared__ double Rs[KMAX * LD];  // Rfin, then unused
-  __shared__ double sg[KMAX];
-  __shared__ int perm[KMAX];
+  __shared__ double K[KM * LD];   // column c at K[c*LD + i]
+  __shared__ double V[KM * LD];
+  __shared__ double sg[KM];
+  __shared__ int perm[KM];
   __shared__ int rot;
   const int kk = s.k;
+  if (kk > KM) return;            // the launch's bucket covers every k
   const int kp = (kk + 1) & ~1;   // even number of players
-  // stage InvC (in V) and Rfin (in Rs); element e -> (e >> 6, e & 63)
+  // stage InvC (in V); element e -> (e >> 6, e & 63)
   for (int j = threadIdx.x >> 6; j < kk; j += 4)
-    for (int i = threadIdx.x & 63; i < kk; i += 64) {
+    for (int i = threadIdx.x & 63; i < kk; i += 64)
       V[j * LD + i] = plain ? (i == j ? 1.0 : 0.0) : s.InvC[i + j * KMAX];
-      Rs[j * LD + i] = s.Rfin[i + j * KMAX];
-    }
   __syncthreads();
-  // K[i][c] = sum_{j >= c} InvC[i][j] * Rfin[c][j]   (Rfin upper triangular)
+  // K[i][c] = sum_{j >= c} InvC[i][j] * Rfin[c][j]   (Rfin upper triangular;
+  // its entries are read from global memory, the same one by a whole wave)
   for (int c = threadIdx.x >> 6; c < kp; c += 4)
     for (int i = threadIdx.x & 63; i < kp; i += 64) {
       double v = 0.0;
       if (i < kk && c < kk)
-        for (int j = c; j < kk; ++j) v += V[j * LD + i] * Rs[j * LD + c];
+        for (int j = c; j < kk; ++j) v += V[j * LD + i] * s.Rfin[c + j * KMAX];
       K[c * LD + i] = v;
     }
   __syncthreads();
@@ -132,8 +132,11 @@ __global__ __launch_bounds__(NTHR) void k_core(int phase, Solve2D *S) {
 
 }  // namespace
 
-hipError_t launch_core(int phase, Solve2D *s, int nsolves, hipStream_t st) {
-  hipLaunchKernelGGL(k_core, dim3(nsolves), dim3(NTHR), 0, st, phase, s);
+hipError_t launch_core(int phase, Solve2D *s, int nsolves, int kmax, hipStream_t st) {
+  if (kmax <= 16) hipLaunchKernelGGL(k_core<16>, dim3(nsolves), dim3(NTHR), 0, st, phase, s);
+  else if (kmax <= 32) hipLaunchKernelGGL(k_core<32>, dim3(nsolves), dim3(NTHR), 0, st, phase, s);
+  else if (kmax <= 48) hipLaunchKernelGGL(k_core<48>, dim3(nsolves), dim3(NTHR), 0, st, phase, s);
+  else hipLaunchKernelGGL(k_core<64>, dim3(nsolves), dim3(NTHR), 0, st, phase, s);
   return hipGetLastError();
 }
 
