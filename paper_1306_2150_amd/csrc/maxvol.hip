@@ -276,20 +276,30 @@ __global__ __launch_bounds__(NTHR) void k_mv_check(int which, int n, Solve2D *S)
 }
 
 // ---- one workgroup: swap loop on I plus the reported rows
+// LDS bytes of k_mv_swap<KM>
+constexpr size_t mv_swap_lds(int km) {
+  return (size_t)(km + MV_CAND) * km * 8 + (size_t)km * km * 8 + (size_t)2 * km * 8 +
+         (size_t)(km + MV_CAND) * 8 + (size_t)(km + MV_CAND) * 4 + 16;
+}
+
+// KM: the launch's rank bucket; the LDS arrays have row length KM, so that
+// small ranks leave room for more workgroups per CU.
+template <int KM>
 __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
                                                  Solve2D *S) {
   Solve2D &s = S[blockIdx.x];
   if (s.active != mv_phase(which) || s.mv_done) return;
   extern __shared__ __align__(16) unsigned char smem[];
   const int kk = s.k;
+  if (kk > KM) return;                              // the bucket covers every k
   const MvIO io = mv_io(which, s);
-  double *Bm = (double *)smem;                      // (KMAX+MV_CAND) x KMAX
-  double *inv = Bm + (KMAX + MV_CAND) * KMAX;       // KMAX x KMAX
-  double *prow = inv + KMAX * KMAX;                 // KMAX
-  double *icol = prow + KMAX;                       // KMAX
-  double *pcol = icol + KMAX;                       // KMAX + MV_CAND
-  int *rows = (int *)(pcol + KMAX + MV_CAND);       // KMAX + MV_CAND
-  int *cnt = rows + KMAX + MV_CAND;                 // [0] count, [1] argmax, [2] swaps
+  double *Bm = (double *)smem;                      // (KM+MV_CAND) x KM
+  double *inv = Bm + (KM + MV_CAND) * KM;           // KM x KM
+  double *prow = inv + KM * KM;                     // KM
+  double *icol = prow + KM;                         // KM
+  double *pcol = icol + KM;                         // KM + MV_CAND
+  int *rows = (int *)(pcol + KM + MV_CAND);         // KM + MV_CAND
+  int *cnt = rows + KM + MV_CAND;                   // [0] count, [1] argmax, [2] swaps
   __shared__ double rv[4];
   __shared__ int rk[4];
   const int ntot = nb0 * MV_TOP;
@@ -357,13 +367,13 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
   const int nr = kk + nc;
   for (int j = threadIdx.x; j < kk; j += NTHR) rows[j] = clamp_row(io.out[j], n);
   for (int i = threadIdx.x >> 6; i < kk; i += 4)
-    for (int c = threadIdx.x & 63; c < kk; c += 64) inv[i * KMAX + c] = io.inv[i + c * KMAX];
+    for (int c = threadIdx.x & 63; c < kk; c += 64) inv[i * KM + c] = io.inv[i + c * KMAX];
   __syncthreads();
   // B rows: identity for I, Q[row,:] Inv for the candidates.  Element e ->
-  // (row position e >> 6, column e & 63).
-  const int nrk = nr * KMAX;
+  // (row position e / KM, column e % KM).
+  const int nrk = nr * KM;
   for (int e = threadIdx.x; e < nrk; e += NTHR) {
-    const int t = e >> 6, c = e & (KMAX - 1);
+    const int t = e / KM, c = e - t * KM;
     if (c >= kk) continue;
     double v;
     if (t < kk) {
@@ -371,7 +381,7 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
     } else {
       v = 0.0;
       const int rr = clamp_row(rows[t], n);
-      for (int j = 0; j < kk; ++j) v += io.Q[rr + (long)j * io.ld] * inv[j * KMAX + c];
+      for (int j = 0; j < kk; ++j) v += io.Q[rr + (long)j * io.ld] * inv[j * KM + c];
     }
     Bm[e] = v;
   }
@@ -382,7 +392,7 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
     double best = -1.0;
     int key = 0x7fffffff;
     for (int e = threadIdx.x; e < nrk; e += NTHR) {
-      const int t = e >> 6, c = e & (KMAX - 1);
+      const int t = e / KM, c = e - t * KM;
       if (c >= kk) continue;
       const double av = fabs(Bm[e]);
       const int kv = rows[t] * KMAX + c;
@@ -400,21 +410,21 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
     int ts = 0;
     for (int t = 0; t < nr; ++t)
       if (rows[t] == gr) ts = t;          // rows are distinct
-    const double piv = Bm[ts * KMAX + cs];
+    const double piv = Bm[ts * KM + cs];
     __syncthreads();
     for (int c = threadIdx.x; c < kk; c += NTHR)
-      prow[c] = (Bm[ts * KMAX + c] - (c == cs ? 1.0 : 0.0)) / piv;
-    for (int t = threadIdx.x; t < nr; t += NTHR) pcol[t] = Bm[t * KMAX + cs];
-    for (int i = threadIdx.x; i < kk; i += NTHR) icol[i] = inv[i * KMAX + cs];
+      prow[c] = (Bm[ts * KM + c] - (c == cs ? 1.0 : 0.0)) / piv;
+    for (int t = threadIdx.x; t < nr; t += NTHR) pcol[t] = Bm[t * KM + cs];
+    for (int i = threadIdx.x; i < kk; i += NTHR) icol[i] = inv[i * KM + cs];
     __syncthreads();
     for (int e = threadIdx.x; e < nrk; e += NTHR) {
-      const int t = e >> 6, c = e & (KMAX - 1);
+      const int t = e / KM, c = e - t * KM;
       if (c < kk) Bm[e] -= pcol[t] * prow[c];
     }
     // the same rank-1 update keeps Inv = Q[I,:]^-1 for the new rows:
     // B = Q Inv, so Inv' = Inv - Inv[:, cs] prow gives B' = Q Inv'
-    for (int e = threadIdx.x; e < kk * KMAX; e += NTHR) {
-      const int i = e >> 6, c = e & (KMAX - 1);
+    for (int e = threadIdx.x; e < kk * KM; e += NTHR) {
+      const int i = e / KM, c = e - i * KM;
       if (c < kk) inv[e] -= icol[i] * prow[c];
     }
     if (threadIdx.x == 0) {
@@ -426,7 +436,7 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
   const int swaps = cnt[2];
   if (swaps > 0)
     for (int i = threadIdx.x >> 6; i < kk; i += 4)
-      for (int c = threadIdx.x & 63; c < kk; c += 64) io.inv[i + c * KMAX] = inv[i * KMAX + c];
+      for (int c = threadIdx.x & 63; c < kk; c += 64) io.inv[i + c * KMAX] = inv[i * KM + c];
   if (threadIdx.x == 0) {
     s.mv_swaps += swaps;
     if (swaps == 0) s.mv_done = 1;
@@ -462,14 +472,16 @@ hipError_t launch_maxvol(int which, int rows, const Tree &tr, Solve2D *s,
   else if (kmax <= 48) e = run_tournament<12>(which, n, tr, s, nsolves, st);
   else e = run_tournament<16>(which, n, tr, s, nsolves, st);
   if (e != hipSuccess) return e;
-  const size_t swap_lds = (size_t)(KMAX + MV_CAND) * KMAX * 8 + (size_t)KMAX * KMAX * 8 +
-                          (size_t)2 * KMAX * 8 + (size_t)(KMAX + MV_CAND) * 8 +
-                          (size_t)(KMAX + MV_CAND) * 4 + 16;
   static bool attr = false;
   if (!attr) {
-    e = hipFuncSetAttribute((const void *)k_mv_swap,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)swap_lds);
-    if (e != hipSuccess) return e;
+    const void *fns[4] = {(const void *)k_mv_swap<16>, (const void *)k_mv_swap<32>,
+                          (const void *)k_mv_swap<48>, (const void *)k_mv_swap<64>};
+    const int kms[4] = {16, 32, 48, 64};
+    for (int t = 0; t < 4; ++t) {
+      e = hipFuncSetAttribute(fns[t], hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)mv_swap_lds(kms[t]));
+      if (e != hipSuccess) return e;
+    }
     attr = true;
   }
   // one explicit inverse of the tournament's rows; the swap rounds keep it
@@ -480,8 +492,18 @@ hipError_t launch_maxvol(int which, int rows, const Tree &tr, Solve2D *s,
     else if (kmax <= 32) run_check<32>(which, n, tr, s, nsolves, st);
     else if (kmax <= 48) run_check<48>(which, n, tr, s, nsolves, st);
     else run_check<64>(which, n, tr, s, nsolves, st);
-    hipLaunchKernelGGL(k_mv_swap, dim3(nsolves), dim3(NTHR), swap_lds, st, which,
-                       n, tr.nb[0], s);
+    if (kmax <= 16)
+      hipLaunchKernelGGL(k_mv_swap<16>, dim3(nsolves), dim3(NTHR), mv_swap_lds(16), st, which,
+                         n, tr.nb[0], s);
+    else if (kmax <= 32)
+      hipLaunchKernelGGL(k_mv_swap<32>, dim3(nsolves), dim3(NTHR), mv_swap_lds(32), st, which,
+                         n, tr.nb[0], s);
+    else if (kmax <= 48)
+      hipLaunchKernelGGL(k_mv_swap<48>, dim3(nsolves), dim3(NTHR), mv_swap_lds(48), st, which,
+                         n, tr.nb[0], s);
+    else
+      hipLaunchKernelGGL(k_mv_swap<64>, dim3(nsolves), dim3(NTHR), mv_swap_lds(64), st, which,
+                         n, tr.nb[0], s);
   }
   return hipGetLastError();
 }
