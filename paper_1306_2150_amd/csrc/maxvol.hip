@@ -128,27 +128,29 @@ __global__ __launch_bounds__(NTHR) void k_mv_node(int which, int n, int lev,
 // all other rows are eliminated against it; at the end row p_j of the right
 // half is row j of the inverse.  Threads: column cl = tid & 63 (and
 // cl + 64), rows i0 = tid >> 6 stepping by 4.
+template <int KM>
 __global__ __launch_bounds__(NTHR) void k_mv_inv(int which, int n, int force,
                                                 Solve2D *S) {
   Solve2D &s = S[blockIdx.x];
   if (s.active != mv_phase(which)) return;
   if (!force && s.mv_done) return;
-  constexpr int W2 = 2 * KMAX;                 // augmented row length
-  __shared__ double a[KMAX][W2 + 1];
+  constexpr int W2 = 2 * KM;                   // augmented row length
+  __shared__ double a[KM][W2 + 1];
   __shared__ double prow[W2];
-  __shared__ double f[KMAX];
-  __shared__ int pivrow[KMAX];
-  __shared__ int used[KMAX];
+  __shared__ double f[KM];
+  __shared__ int pivrow[KM];
+  __shared__ int used[KM];
   __shared__ int shp;
   __shared__ double sip;
   const int kk = s.k, w2 = 2 * kk;
+  if (kk > KM) return;                         // the bucket covers every k
   const int cl = threadIdx.x & 63, i0 = threadIdx.x >> 6;
   const MvIO io = mv_io(which, s);
   for (int i = i0; i < kk; i += 4)
     for (int c = cl; c < w2; c += 64)
       a[i][c] = (c < kk) ? io.Q[clamp_row(io.out[i], n) + (long)c * io.ld]
                          : ((c - kk == i) ? 1.0 : 0.0);
-  if (threadIdx.x < KMAX) used[threadIdx.x] = 0;
+  if (threadIdx.x < KM) used[threadIdx.x] = 0;
   __syncthreads();
   for (int j = 0; j < kk; ++j) {
     if (threadIdx.x < 64) {
@@ -269,6 +271,15 @@ __global__ __launch_bounds__(NTHR) void k_mv_check(int which, int n, Solve2D *S)
     if (threadIdx.x == 0) {
       s.mv_val[(size_t)blockIdx.x * MV_TOP + t] = bv;
       s.mv_row[(size_t)blockIdx.x * MV_TOP + t] = (bv > 0.0) ? bk : -1;
+    }
+    if (!(bv > 0.0)) {
+      // no violator left in the block (uniform): the other slots report none
+      if (threadIdx.x == 0)
+        for (int u = t + 1; u < MV_TOP; ++u) {
+          s.mv_val[(size_t)blockIdx.x * MV_TOP + u] = -1.0;
+          s.mv_row[(size_t)blockIdx.x * MV_TOP + u] = -1;
+        }
+      break;
     }
     if (row == bk) mx = -1.0;
     __syncthreads();
@@ -486,7 +497,10 @@ hipError_t launch_maxvol(int which, int rows, const Tree &tr, Solve2D *s,
   }
   // one explicit inverse of the tournament's rows; the swap rounds keep it
   // current with the rank-1 updates of their swaps
-  hipLaunchKernelGGL(k_mv_inv, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
+  if (kmax <= 16) hipLaunchKernelGGL(k_mv_inv<16>, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
+  else if (kmax <= 32) hipLaunchKernelGGL(k_mv_inv<32>, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
+  else if (kmax <= 48) hipLaunchKernelGGL(k_mv_inv<48>, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
+  else hipLaunchKernelGGL(k_mv_inv<64>, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
   for (int round = 0; round < MV_ROUNDS; ++round) {
     if (kmax <= 16) run_check<16>(which, n, tr, s, nsolves, st);
     else if (kmax <= 32) run_check<32>(which, n, tr, s, nsolves, st);
