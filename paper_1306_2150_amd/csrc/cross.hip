@@ -177,16 +177,21 @@ __global__ __launch_bounds__(NTHR) void k_change_M(int nbm, Solve2D *S) {
   }
 }
 
-__global__ __launch_bounds__(NTHR) void k_change_reduce(int nbm, Solve2D *S) {
-  Solve2D &s = S[blockIdx.x];
+// Mc = the sum of the nbm block partials, in block order; one thread per
+// entry (grid x covers the kp x k entries, 64 per workgroup), its loads
+// independent so that many are in flight.
+__global__ __launch_bounds__(64) void k_change_reduce(int nbm, Solve2D *S) {
+  Solve2D &s = S[blockIdx.y];
   if (s.active != ACT_SWEEP || s.kp == 0) return;
   const int kk = s.k, kq = s.kp;
-  for (int o = threadIdx.x; o < kq * kk; o += NTHR) {
-    double v = 0.0;
-    for (int b = 0; b < nbm; ++b) v += s.part[(size_t)b * KMAX * KMAX + o];
-    const int a = o / kk, c = o - a * kk;
-    s.Mc[a * KMAX + c] = v;
-  }
+  const int o = blockIdx.x * 64 + threadIdx.x;
+  if (o >= kq * kk) return;
+  const double *p = s.part + o;
+  double v = 0.0;
+#pragma unroll 8
+  for (int b = 0; b < nbm; ++b) v += p[(size_t)b * KMAX * KMAX];
+  const int a = o / kk, c = o - a * kk;
+  s.Mc[a * KMAX + c] = v;
 }
 
 // Block b: rows [256 b, 256 b + 256) of ||A - Ap M||^2 (n rows) and of
@@ -503,7 +508,7 @@ hipError_t launch_change(int n, int m, Solve2D *s, int nsolves, int kmax,
                          hipStream_t st) {
   const int nbm = change_blocks(m);
   LRP_BUCKET(k_change_M, dim3(nbm, nsolves), nbm, s);
-  hipLaunchKernelGGL(k_change_reduce, dim3(nsolves), dim3(NTHR), 0, st, nbm, s);
+  hipLaunchKernelGGL(k_change_reduce, dim3(KMAX * KMAX / 64, nsolves), dim3(64), 0, st, nbm, s);
   dim3 g(ceil_div(max(n, m), NTHR), nsolves);
   LRP_BUCKET(k_change_norms, g, s);
   return hipGetLastError();

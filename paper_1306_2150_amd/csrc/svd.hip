@@ -28,9 +28,18 @@ __device__ __forceinline__ double row_sum16(double v) {
 // phase ACT_SWEEP: K = InvC Rfin^T (the cross core); phase ACT_CORE (3D
 // path): K = Rfin^T, whose left singular vectors W are those of the Tucker
 // core unfolding that the preceding TSQR factored.
+// NT = 16 threads per column pair (one DPP row), all pairs of the bucket in
+// flight at once: 256 threads up to k = 32, 384 and 512 for the larger
+// buckets (few-solve launches, as in the 3D path and serving, are bound by
+// the latency of the rounds, not by occupancy).
 template <int KM>
-__global__ __launch_bounds__(NTHR) void k_core(int phase, Solve2D *S) {
+constexpr int core_threads() { return KM / 2 * 16 < NTHR ? NTHR : KM / 2 * 16; }
+
+template <int KM>
+__global__ __launch_bounds__(core_threads<KM>()) void k_core(int phase, Solve2D *S) {
   constexpr int LD = KM + 1;
+  constexpr int NT = core_threads<KM>();
+  constexpr int NW = NT / 64;     // waves
   Solve2D &s = S[blockIdx.x];
   if (s.active != phase) return;
   const bool plain = phase == ACT_CORE;
@@ -43,13 +52,13 @@ __global__ __launch_bounds__(NTHR) void k_core(int phase, Solve2D *S) {
   if (kk > KM) return;            // the launch's bucket covers every k
   const int kp = (kk + 1) & ~1;   // even number of players
   // stage InvC (in V); element e -> (e >> 6, e & 63)
-  for (int j = threadIdx.x >> 6; j < kk; j += 4)
+  for (int j = threadIdx.x >> 6; j < kk; j += NW)
     for (int i = threadIdx.x & 63; i < kk; i += 64)
       V[j * LD + i] = plain ? (i == j ? 1.0 : 0.0) : s.InvC[i + j * KMAX];
   __syncthreads();
   // K[i][c] = sum_{j >= c} InvC[i][j] * Rfin[c][j]   (Rfin upper triangular;
   // its entries are read from global memory, the same one by a whole wave)
-  for (int c = threadIdx.x >> 6; c < kp; c += 4)
+  for (int c = threadIdx.x >> 6; c < kp; c += NW)
     for (int i = threadIdx.x & 63; i < kp; i += 64) {
       double v = 0.0;
       if (i < kk && c < kk)
@@ -57,18 +66,19 @@ __global__ __launch_bounds__(NTHR) void k_core(int phase, Solve2D *S) {
       K[c * LD + i] = v;
     }
   __syncthreads();
-  for (int c = threadIdx.x >> 6; c < kp; c += 4)
+  for (int c = threadIdx.x >> 6; c < kp; c += NW)
     for (int i = threadIdx.x & 63; i < kp; i += 64) V[c * LD + i] = (i == c) ? 1.0 : 0.0;
   __syncthreads();
   const int npairs = kp / 2;
-  // 16 threads (one DPP row) per column pair, 16 pairs in flight
+  // 16 threads (one DPP row) per column pair, NT / 16 pairs in flight
+  constexpr int NP = NT / 16;
   const int pr0 = threadIdx.x >> 4, gl = threadIdx.x & 15;
   const double tol = 1e-15;
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (threadIdx.x == 0) rot = 0;
     __syncthreads();
     for (int st = 0; st < kp - 1; ++st) {
-      for (int pr = pr0; pr < ((npairs + 15) & ~15); pr += 16) {
+      for (int pr = pr0; pr < ((npairs + NP - 1) / NP) * NP; pr += NP) {
         const bool live = pr < npairs;
         const int pa = pr, pb = kp - 1 - pr;
         const int a = live ? ((pa == 0) ? 0 : 1 + (pa - 1 + st) % (kp - 1)) : 0;
@@ -120,7 +130,7 @@ __global__ __launch_bounds__(NTHR) void k_core(int phase, Solve2D *S) {
     perm[rank] = c;
   }
   __syncthreads();
-  for (int t = threadIdx.x >> 6; t < kk; t += 4)
+  for (int t = threadIdx.x >> 6; t < kk; t += NW)
     for (int i = threadIdx.x & 63; i < kk; i += 64) {
       const int c = perm[t];
       const double sv = sg[c];
@@ -133,10 +143,14 @@ __global__ __launch_bounds__(NTHR) void k_core(int phase, Solve2D *S) {
 }  // namespace
 
 hipError_t launch_core(int phase, Solve2D *s, int nsolves, int kmax, hipStream_t st) {
-  if (kmax <= 16) hipLaunchKernelGGL(k_core<16>, dim3(nsolves), dim3(NTHR), 0, st, phase, s);
-  else if (kmax <= 32) hipLaunchKernelGGL(k_core<32>, dim3(nsolves), dim3(NTHR), 0, st, phase, s);
-  else if (kmax <= 48) hipLaunchKernelGGL(k_core<48>, dim3(nsolves), dim3(NTHR), 0, st, phase, s);
-  else hipLaunchKernelGGL(k_core<64>, dim3(nsolves), dim3(NTHR), 0, st, phase, s);
+  if (kmax <= 16)
+    hipLaunchKernelGGL(k_core<16>, dim3(nsolves), dim3(core_threads<16>()), 0, st, phase, s);
+  else if (kmax <= 32)
+    hipLaunchKernelGGL(k_core<32>, dim3(nsolves), dim3(core_threads<32>()), 0, st, phase, s);
+  else if (kmax <= 48)
+    hipLaunchKernelGGL(k_core<48>, dim3(nsolves), dim3(core_threads<48>()), 0, st, phase, s);
+  else
+    hipLaunchKernelGGL(k_core<64>, dim3(nsolves), dim3(core_threads<64>()), 0, st, phase, s);
   return hipGetLastError();
 }
 
