@@ -310,7 +310,7 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
   double *icol = prow + KM;                         // KM
   double *pcol = icol + KM;                         // KM + MV_CAND
   int *rows = (int *)(pcol + KM + MV_CAND);         // KM + MV_CAND
-  int *cnt = rows + KM + MV_CAND;                   // [0] count, [1] argmax, [2] swaps
+  int *cnt = rows + KM + MV_CAND;                   // [0] count, [1] gathered, [2] swaps
   __shared__ double rv[4];
   __shared__ int rk[4];
   const int ntot = nb0 * MV_TOP;
@@ -318,28 +318,43 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
   if (threadIdx.x == 0) cnt[0] = 0;
   __syncthreads();
   // the MV_CAND largest reported violators in order (value descending,
-  // ties: lower row first; reported rows are distinct)
-  if (ntot <= 1024) {
-    // few reports: rank every one against all others
-    for (int e = threadIdx.x; e < ntot; e += NTHR) {
-      const double v = s.mv_val[e];
-      const int rr = s.mv_row[e];
-      if (rr < 0 || !(v > s.tau)) continue;
-      int rank = 0;
-      for (int f = 0; f < ntot; ++f) {
-        const double w = s.mv_val[f];
-        const int r2 = s.mv_row[f];
-        if (r2 < 0 || !(w > s.tau)) continue;
-        if (w > v || (w == v && r2 < rr)) ++rank;
-      }
-      if (rank < MV_CAND) {
-        cr[kk + rank] = rr;
-        atomicAdd(&cnt[0], 1);
-      }
+  // ties: lower row first; reported rows are distinct).  The violators are
+  // first gathered into LDS (the Bm region, built only afterwards); each then
+  // finds its rank among them.  Gathering order does not matter: ranks only
+  // compare values and rows.
+  constexpr int CMAX = 1024;                        // 12 KB, within Bm for every KM
+  static_assert((size_t)(KM + MV_CAND) * KM * 8 >= (size_t)CMAX * 12, "gather area");
+  double *cv = Bm;
+  int *crow = (int *)(Bm + CMAX);
+  if (threadIdx.x == 0) cnt[1] = 0;
+  __syncthreads();
+  for (int e = threadIdx.x; e < ntot; e += NTHR) {
+    const double v = s.mv_val[e];
+    const int rr = s.mv_row[e];
+    if (rr < 0 || !(v > s.tau)) continue;
+    const int slot = atomicAdd(&cnt[1], 1);
+    if (slot < CMAX) {
+      cv[slot] = v;
+      crow[slot] = rr;
     }
+  }
+  __syncthreads();
+  const int nv = cnt[1];
+  if (nv <= CMAX) {
+    for (int e = threadIdx.x; e < nv; e += NTHR) {
+      const double v = cv[e];
+      const int rr = crow[e];
+      int rank = 0;
+      for (int f = 0; f < nv; ++f) {
+        const double w = cv[f];
+        if (w > v || (w == v && crow[f] < rr)) ++rank;
+      }
+      if (rank < MV_CAND) cr[kk + rank] = rr;
+    }
+    if (threadIdx.x == 0) cnt[0] = min(nv, MV_CAND);
   } else {
-    // many reports (tall column side): pick them one by one, each the
-    // largest entry strictly after the previous pick in that order
+    // very many violators: pick them one by one, each the largest entry
+    // strictly after the previous pick in that order
     double lastv = INFINITY;
     int lastr = -1, picked = 0;
     const int lane0 = threadIdx.x & 63, wave0 = threadIdx.x >> 6;
