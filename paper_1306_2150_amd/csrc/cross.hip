@@ -5,9 +5,9 @@
 // take the general rectangular form Xh_ij = (Uh_i . Vh_j) / (lam_r[i] +
 // lam_c[j]), i < n, j < m, which the 3D path uses for the unfoldings of its
 // divided spectrum.  A sweep with
-// column set J evaluates the columns Xh[:, J] (k_eval, EV_COLS), orthonormalises
-// them, picks rows I by maxvol, evaluates the rows Xh[I, :] (EV_ROWS),
-// orthonormalises those, picks the next columns Jn by maxvol, and rounds the
+// column set J evaluates the columns Xh[:, J] and orthonormalises them (both
+// in the TSQR, tsqr.hip), picks rows I by maxvol, evaluates and
+// orthonormalises the rows Xh[I, :], picks the next columns Jn by maxvol, and rounds the
 // skeleton through the k x k core (svd.hip).  This file also holds the
 // per-sweep bookkeeping: the skeleton factors A = Q0 W S, B = Q1 Z, the change
 // ||A B^T - Ap Bp^T||_F against the previous sweep, the truncation rank, the
@@ -24,47 +24,6 @@ namespace lrp {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
-
-template <int KM>
-__global__ __launch_bounds__(NTHR) void k_eval(int which, Solve2D *S) {
-  Solve2D &s = S[blockIdx.y];
-  if (s.active != ACT_SWEEP) return;
-  __shared__ double qs[KMAX * KMAX];   // [alpha][l]
-  __shared__ double ls[KMAX];
-  // columns: rows i < n of Uh against Vh[J]; rows: rows j < m of Vh against Uh[I]
-  const bool cols = which == EV_COLS;
-  const double *P = cols ? s.Uh : s.Vh, *Qm = cols ? s.Vh : s.Uh;
-  const long ldp = cols ? s.ldu : s.ldv, ldq = cols ? s.ldv : s.ldu;
-  const double *lp = cols ? s.lam_r : s.lam_c, *lq = cols ? s.lam_c : s.lam_r;
-  const int *sel = cols ? s.J : s.I;
-  const int rows = cols ? s.n : s.m, other = cols ? s.m : s.n;
-  const int kk = s.k, r = s.r;
-  for (int a = threadIdx.x >> 6; a < r; a += 4)
-    for (int l = threadIdx.x & 63; l < kk; l += 64)
-      qs[a * KMAX + l] = Qm[clamp_row(sel[l], other) + (long)a * ldq];
-  for (int l = threadIdx.x; l < kk; l += NTHR) ls[l] = lq[clamp_row(sel[l], other)];
-  __syncthreads();
-  const int i = blockIdx.x * NTHR + threadIdx.x;
-  if (i >= rows) return;
-  double acc[KM];
-#pragma unroll
-  for (int l = 0; l < KM; ++l) acc[l] = 0.0;
-  for (int a0 = 0; a0 < r; a0 += 8) {
-    double p[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) p[t] = (a0 + t < r) ? P[i + (long)(a0 + t) * ldp] : 0.0;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-      if (a0 + t >= r) break;
-#pragma unroll
-      for (int l = 0; l < KM; ++l) acc[l] += p[t] * qs[(a0 + t) * KMAX + l];
-    }
-  }
-  const double li = lp[i];
-#pragma unroll
-  for (int l = 0; l < KM; ++l)
-    if (l < kk) s.C[i + (long)l * s.ldc] = acc[l] / (li + ls[l]);
-}
 
 // A = Q0 (W diag(sig))  (z = 0, n rows),  B = Q1 Z  (z = 1, m rows), all k
 // columns.
@@ -487,13 +446,6 @@ __global__ void k_init_J(Solve2D *S) {
     else if (kmax <= 48) hipLaunchKernelGGL((KERN<48>), GRID, dim3(NTHR), 0, st, __VA_ARGS__); \
     else hipLaunchKernelGGL((KERN<64>), GRID, dim3(NTHR), 0, st, __VA_ARGS__); \
   } while (0)
-
-hipError_t launch_eval(int which, int rows, Solve2D *s, int nsolves, int kmax,
-                       hipStream_t st) {
-  dim3 g(ceil_div(rows, NTHR), nsolves);
-  LRP_BUCKET(k_eval, g, which, s);
-  return hipGetLastError();
-}
 
 hipError_t launch_factors(int n, int m, Solve2D *s, int nsolves, int kmax,
                           hipStream_t st) {

@@ -442,10 +442,8 @@ lrp_status Group2D::step(hipStream_t st) {
   // k of a slot only grows at the end of a sweep, so kmax bounds this sweep
   const int km = std::max(kmax, 1);
   const int kev = std::max(km, rmax);
-  HIPCHK(launch_eval(EV_COLS, n_, d_s_, hi, kev, st));
   HIPCHK(launch_tsqr(TS_C_TO_Q0, n_, tn, d_s_, hi, km, st));
   HIPCHK(launch_maxvol(MV_Q0_TO_I, n_, tn, d_s_, hi, km, st));
-  HIPCHK(launch_eval(EV_ROWS, m_, d_s_, hi, kev, st));
   HIPCHK(launch_tsqr(TS_C_TO_Q1, m_, tm, d_s_, hi, km, st));
   HIPCHK(launch_maxvol(MV_Q1_TO_JN, m_, tm, d_s_, hi, km, st));
   HIPCHK(launch_core(ACT_SWEEP, d_s_, hi, km, st));

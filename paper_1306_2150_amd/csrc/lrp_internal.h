@@ -55,7 +55,7 @@ struct Solve2D {
   // column-side panels (m rows) ldv, the shared ones (C, Hv) ldc >= both.
   long ldu, ldv, ldc;
   double *Uh, *Vh;          // n x r, m x r  transformed input factors
-  double *C;                // evaluated columns / rows (ldc)
+  double *C;                // 3D core unfolding for TS_CORE (ldc)
   double *Hv;               // leaf Householder vectors (ldc)
   double *Q0, *Q1;          // orthonormal bases: columns (n rows), rows (m rows)
   double *A, *B;            // skeleton factors, this sweep (n rows, m rows)
@@ -284,12 +284,10 @@ hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, Solve2
 
 // Row counts: calls on the column side (Xh[:, J], Q0, A) cover the n rows,
 // calls on the row side (Xh[I, :]^T, Q1, B, Vh) the m columns.
-enum : int { EV_COLS = 0, EV_ROWS = 1 };
-hipError_t launch_eval(int which, int rows, Solve2D *s, int nsolves, int kmax,
-                       hipStream_t st);
-
-// TSQR inputs/outputs.  TS_CORE factors the panel in C with `rows` rows and
-// keeps only R (in Rfin); it acts on slots in the ACT_CORE phase.
+// TSQR inputs/outputs.  TS_C_TO_Q0 / TS_C_TO_Q1 evaluate the cross columns
+// Xh[:, J] / rows Xh[I, :]^T in the leaf kernel itself and orthonormalise
+// them.  TS_CORE factors the panel in C with `rows` rows and keeps only R
+// (in Rfin); it acts on slots in the ACT_CORE phase.
 enum : int { TS_C_TO_Q0 = 0, TS_C_TO_Q1 = 1, TS_VH_TO_Q1 = 2, TS_CORE = 3 };
 hipError_t launch_tsqr(int which, int rows, const Tree &tr, Solve2D *s,
                        int nsolves, int kmax, hipStream_t st);

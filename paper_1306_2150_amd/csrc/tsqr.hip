@@ -33,8 +33,9 @@ struct TsIO {
   long ldout;
 };
 __device__ inline TsIO ts_io(int which, const Solve2D &s) {
-  if (which == TS_C_TO_Q0) return {s.C, s.ldc, s.Q0, s.ldu};
-  if (which == TS_C_TO_Q1) return {s.C, s.ldc, s.Q1, s.ldv};
+  // the cross panels are evaluated in the leaf (cross_panel), not loaded
+  if (which == TS_C_TO_Q0) return {nullptr, 0, s.Q0, s.ldu};
+  if (which == TS_C_TO_Q1) return {nullptr, 0, s.Q1, s.ldv};
   if (which == TS_VH_TO_Q1) return {s.Vh, s.ldv, s.Q1, s.ldv};
   return {s.C, s.ldc, nullptr, 0};   // TS_CORE: R only
 }
@@ -43,21 +44,90 @@ __device__ inline int ts_phase(int which) {
   return which == TS_VH_TO_Q1 ? ACT_INIT : (which == TS_CORE ? ACT_CORE : ACT_SWEEP);
 }
 
+// Rows [r0, r0 + m) of the cross columns Xh[:, J] (TS_C_TO_Q0: rows of Uh
+// against Vh[J]) or of the cross rows Xh[I, :]^T (TS_C_TO_Q1: rows of Vh
+// against Uh[I]), evaluated straight into the register panel instead of
+// being written to and read back from memory:
+//     y(i, c) = (P_i . Qm_sel[c]) / (lp[i] + lq[sel[c]]),
+// the rank-r numerator summed in ascending order.  The selected rows of Qm
+// and their eigenvalues are staged in LDS (qs: [alpha][c], NC columns);
+// every wave reads the same P rows, which the vector cache serves.
 template <int NS>
+__device__ __forceinline__ void cross_panel(double (&y)[NS][4], int which,
+                                            const Solve2D &s, int r0, int m,
+                                            double *qs, double *ls) {
+  constexpr int NC = 4 * NS;
+  const bool cols = which == TS_C_TO_Q0;
+  const double *P = cols ? s.Uh : s.Vh, *Qm = cols ? s.Vh : s.Uh;
+  const long ldp = cols ? s.ldu : s.ldv, ldq = cols ? s.ldv : s.ldu;
+  const double *lp = cols ? s.lam_r : s.lam_c, *lq = cols ? s.lam_c : s.lam_r;
+  const int *sel = cols ? s.J : s.I;
+  const int other = cols ? s.m : s.n;
+  const int kk = s.k, r = s.r;
+  for (int e = threadIdx.x; e < r * NC; e += NTHR) {
+    const int a = e / NC, c = e - a * NC;
+    qs[e] = (c < kk) ? Qm[clamp_row(sel[c], other) + (long)a * ldq] : 0.0;
+  }
+  for (int c = threadIdx.x; c < NC; c += NTHR)
+    ls[c] = (c < kk) ? lq[clamp_row(sel[c], other)] : 1.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double *Pr = P + r0 + lane;
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) y[sl][q] = 0.0;
+  for (int a0 = 0; a0 < r; a0 += 4) {
+    double p[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        p[t][q] = (a0 + t < r && lane + 64 * q < m) ? Pr[64 * q + (long)(a0 + t) * ldp] : 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (a0 + t >= r) break;
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) {
+        const double qv = qs[(a0 + t) * NC + wave + 4 * sl];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) y[sl][q] += p[t][q] * qv;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int i = lane + 64 * q;
+    const double li = (i < m) ? lp[r0 + i] : 1.0;
+#pragma unroll
+    for (int sl = 0; sl < NS; ++sl) {
+      const int c = wave + 4 * sl;
+      y[sl][q] = (c < kk && i < m) ? y[sl][q] / (li + ls[c]) : 0.0;
+    }
+  }
+}
+
+template <int NS, bool CROSS>
 __global__ __launch_bounds__(NTHR) void k_tsqr_leaf(int which, int n, Tree tr,
                                                    Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (s.active != ts_phase(which)) return;
   __shared__ double vbuf[2 * PANEL_M];
   __shared__ double taus[KMAX];
+  __shared__ double qs[CROSS ? KMAX * 4 * NS : 1];
+  __shared__ double ls[CROSS ? 4 * NS : 1];
   const int kk = s.k;
   const int b = blockIdx.x;
   const int r0 = b * PANEL_M;
   const int m = min(PANEL_M, n - r0);
   const int mp = max(m, kk);
-  const TsIO io = ts_io(which, s);
   double y[NS][4];
-  panel_load(y, io.in + r0, io.ldin, m, kk);
+  if constexpr (CROSS) {
+    cross_panel(y, which, s, r0, m, qs, ls);
+  } else {
+    const TsIO io = ts_io(which, s);
+    panel_load(y, io.in + r0, io.ldin, m, kk);
+  }
   hh_qr_regs(y, mp, kk, vbuf, taus);
   panel_store(y, s.Hv + r0, s.ldc, m, kk);
   double *R = s.tree_R + lev_off(tr, 0, (size_t)KMAX * KMAX) + (size_t)b * KMAX * KMAX;
@@ -210,8 +280,12 @@ template <int NS>
 hipError_t run_tsqr(int which, int n, const Tree &tr, Solve2D *s, int ns,
                     hipStream_t st) {
   dim3 blk(NTHR);
-  hipLaunchKernelGGL((k_tsqr_leaf<NS>), dim3(tr.nb[0], ns), blk, 0, st, which,
-                     n, tr, s);
+  if (which == TS_C_TO_Q0 || which == TS_C_TO_Q1)
+    hipLaunchKernelGGL((k_tsqr_leaf<NS, true>), dim3(tr.nb[0], ns), blk, 0, st,
+                       which, n, tr, s);
+  else
+    hipLaunchKernelGGL((k_tsqr_leaf<NS, false>), dim3(tr.nb[0], ns), blk, 0, st,
+                       which, n, tr, s);
   for (int l = 1; l < tr.nlev; ++l)
     hipLaunchKernelGGL((k_tsqr_node<NS>), dim3(tr.nb[l], ns), blk, 0, st, which, l,
                        tr, s);
