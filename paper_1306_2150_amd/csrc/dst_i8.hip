@@ -52,8 +52,11 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 constexpr int TMI = 128;         // rows per workgroup: 4 waves x 2 x 16
 constexpr int TNI = 32;          // columns per workgroup
-constexpr int KCI = 32;          // grid points staged per LDS buffer
-constexpr int XST = KCI + 4;     // dwords per staged column and level (+4: bank skew)
+// Grid points staged per LDS buffer: KC = 64 for the 64-column tiles where
+// the planes fit beside the table (half the barriers of KC = 32), else 32.
+// Staged columns are KC + 4 dwords apart (bank skew).
+constexpr int KCW = 64, KCN = 32;
+constexpr int KPAD = 64;         // the parity records are padded to a multiple of this
 
 // Reversed 7-bit slice record of x * 2^-e: dword 0 = bytes [X5 X4 X3 X2],
 // dword 1 = [X1 X0 0 0].
@@ -166,13 +169,14 @@ __device__ __forceinline__ double recombine(const int (&acc)[6], double sc) {
 // split (gridDim.z > 1) workgroup z sums chunk z and writes its six level
 // sums as int32 to `partial` ([z][p][level][a][c], consecutive lanes on
 // consecutive columns); k_dst_i8_reduce adds them exactly and recombines.
-template <int TN_, bool FULL>
+template <int TN_, int KC, bool FULL>
 __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__restrict__ rec,
                                                 const DstCol *__restrict__ cols, int ncols,
                                                 int kchunk, const uint2 *__restrict__ xrec,
                                                 int hpad, const int *__restrict__ xex,
                                                 int *__restrict__ partial) {
   constexpr int NB = TN_ / 16;
+  constexpr int XST = KC + 4;
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = n + 1, twoN = 2 * N;
   const int ntab = FULL ? twoN : 2 * Q;
@@ -188,20 +192,33 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
   const bool split = gridDim.z > 1;
   const int kbeg = split ? blockIdx.z * kchunk : 0;
   const int kend = split ? min(Kp, kbeg + kchunk) : Kp;
-  for (int i = tid; i < ntab; i += NTHR) tab[i] = rec[i];
+  // table copy, eight loads in flight per thread
+  for (int i0 = 0; i0 < ntab; i0 += 8 * NTHR) {
+    uint2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * NTHR + tid;
+      v[u] = (i < ntab) ? rec[i] : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * NTHR + tid;
+      if (i < ntab) tab[i] = v[u];
+    }
+  }
   // staging share: thread stages grid points tk of columns tc0 + 8 t; the
   // columns' records lie 2 hpad apart
-  constexpr int PER = KCI * TN_ / NTHR;
-  constexpr int CSTEP = NTHR / KCI;
+  constexpr int PER = KC * TN_ / NTHR;
+  constexpr int CSTEP = NTHR / KC;
   constexpr int LVL = TN_ * XST;                 // dwords per record plane and buffer
-  const int tk = tid & (KCI - 1), tc0 = tid / KCI;
+  const int tk = tid & (KC - 1), tc0 = tid / KC;
   const int nsrc = max(0, min(PER, ceil_div(ncols - c0 - tc0, CSTEP)));
   const uint2 *xsrc = xrec + (size_t)(2 * (c0 + tc0) + par) * hpad;
   const size_t sstep = (size_t)2 * CSTEP * hpad;
-  const int nst = (kend - kbeg + KCI - 1) / KCI;
+  const int nst = (kend - kbeg + KC - 1) / KC;
   uint2 pre[PER];
   auto fetch = [&](int st) {
-    const int k = kbeg + st * KCI + tk;
+    const int k = kbeg + st * KC + tk;
 #pragma unroll
     for (int t = 0; t < PER; ++t)
       pre[t] = (t < nsrc && k < kend) ? xsrc[t * sstep + k] : make_uint2(0u, 0u);
@@ -242,10 +259,10 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
   }
   __syncthreads();
   for (int st = 0; st < nst; ++st) {
-    const int k0 = kbeg + st * KCI;
+    const int k0 = kbeg + st * KC;
     if (st + 1 < nst) fetch(st + 1);
     const uint32_t *xs = xs0 + (st & 1) * 2 * LVL;
-    const int kcn = min(KCI, kend - k0);
+    const int kcn = min(KC, kend - k0);
     for (int kk = 0; kk < kcn; kk += 16) {
       // A operands: records of points k0 + kk + 4g + e (1-based k)
       v4i ahi[2], alo[2];
@@ -400,15 +417,15 @@ void dst_i8_table(int n, unsigned char *out) {
   }
 }
 
-static size_t i8_lds(int n, int tn, bool full) {
-  return (full ? i8_full_bytes(n) : i8_quarter_bytes(n)) + (size_t)2 * 2 * tn * XST * 4;
+static size_t i8_lds(int n, int tn, int kc, bool full) {
+  return (full ? i8_full_bytes(n) : i8_quarter_bytes(n)) + (size_t)2 * 2 * tn * (kc + 4) * 4;
 }
 
 constexpr size_t LDS_MAX = 160 * 1024;
-bool dst_i8_supported(int n) { return i8_lds(n, TNI, false) <= LDS_MAX; }
+bool dst_i8_supported(int n) { return i8_lds(n, TNI, KCN, false) <= LDS_MAX; }
 
 // work per column: two parity records of hpad points, then two exponents
-static int i8_hpad(int n) { return ceil_div((n + 1) / 2, KCI) * KCI; }
+static int i8_hpad(int n) { return ceil_div((n + 1) / 2, KPAD) * KPAD; }
 static size_t i8_col_bytes(int n) { return (size_t)2 * i8_hpad(n) * 8 + 8; }
 
 size_t dst_i8_work_bytes(int n, int ncols) { return (size_t)ncols * i8_col_bytes(n); }
@@ -427,7 +444,7 @@ hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, Solve2
   const int Q = (n + 1) / 2 + 1;
   const int H0 = (n + 1) / 2, hpad = i8_hpad(n);
   // fixed K chunks of the folded length (at most 4, at least 256 deep)
-  const int kchunk = std::max(256, ceil_div(ceil_div(H0, 4), KCI) * KCI);
+  const int kchunk = std::max(256, ceil_div(ceil_div(H0, 4), KPAD) * KPAD);
   const int nchunk = ceil_div(H0, kchunk);
   // the slice records of a launch's columns must fit the work buffer; larger
   // column sets run in several launches (results per column are unchanged)
@@ -444,9 +461,10 @@ hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, Solve2
     // than 32-column tiles at two waves per SIMD) when they alone give every
     // CU a workgroup; 32-column tiles, twice as many, on small launches
     const int R = ceil_div(H0, TMI);
-    const bool wide = R * 2 * ceil_div(nc, 64) >= 256 && i8_lds(n, 64, false) <= LDS_MAX;
+    const bool wide = R * 2 * ceil_div(nc, 64) >= 256 && i8_lds(n, 64, KCN, false) <= LDS_MAX;
     const int tn = wide ? 64 : TNI;
-    const bool full = i8_lds(n, tn, true) <= LDS_MAX;
+    const int kc = (wide && i8_lds(n, 64, KCW, false) <= LDS_MAX) ? KCW : KCN;
+    const bool full = i8_lds(n, tn, kc, true) <= LDS_MAX;
     const unsigned char *tabs = (const unsigned char *)rec;
     const uint2 *trec = (const uint2 *)(full ? tabs + i8_quarter_bytes(n) : tabs);
     const int C = 2 * ceil_div(nc, tn);
@@ -455,19 +473,31 @@ hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, Solve2
     if (R * C < 512 && partial && partial_elems * 2 >= (size_t)nchunk * 2 * nc * 6 * H0)
       g.z = nchunk;
     int *out_partial = g.z > 1 ? (int *)partial : nullptr;
-    const size_t lds = i8_lds(n, tn, full);
-    const void *fn = wide ? (full ? (const void *)k_dst_i8<64, true> : (const void *)k_dst_i8<64, false>)
-                          : (full ? (const void *)k_dst_i8<TNI, true> : (const void *)k_dst_i8<TNI, false>);
+    const size_t lds = i8_lds(n, tn, kc, full);
+    const void *fn = nullptr;
+    if (wide && kc == KCW)
+      fn = full ? (const void *)k_dst_i8<64, KCW, true> : (const void *)k_dst_i8<64, KCW, false>;
+    else if (wide)
+      fn = full ? (const void *)k_dst_i8<64, KCN, true> : (const void *)k_dst_i8<64, KCN, false>;
+    else
+      fn = full ? (const void *)k_dst_i8<TNI, KCN, true> : (const void *)k_dst_i8<TNI, KCN, false>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (ev0 && c0 == 0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
-#define LRP_I8_LAUNCH(TNV, FV)                                                              \
-  hipLaunchKernelGGL((k_dst_i8<TNV, FV>), g, dim3(NTHR), lds, st, n, Q, trec, cc, nc, kchunk, \
-                     xrec, hpad, xex, out_partial)
-    if (wide && full) LRP_I8_LAUNCH(64, true);
-    else if (wide) LRP_I8_LAUNCH(64, false);
-    else if (full) LRP_I8_LAUNCH(TNI, true);
-    else LRP_I8_LAUNCH(TNI, false);
+#define LRP_I8_LAUNCH(TNV, KCV, FV)                                                         \
+  hipLaunchKernelGGL((k_dst_i8<TNV, KCV, FV>), g, dim3(NTHR), lds, st, n, Q, trec, cc, nc,  \
+                     kchunk, xrec, hpad, xex, out_partial)
+    if (wide && kc == KCW) {
+      if (full) LRP_I8_LAUNCH(64, KCW, true);
+      else LRP_I8_LAUNCH(64, KCW, false);
+    } else if (wide) {
+      if (full) LRP_I8_LAUNCH(64, KCN, true);
+      else LRP_I8_LAUNCH(64, KCN, false);
+    } else if (full) {
+      LRP_I8_LAUNCH(TNI, KCN, true);
+    } else {
+      LRP_I8_LAUNCH(TNI, KCN, false);
+    }
 #undef LRP_I8_LAUNCH
     e = hipGetLastError();
     if (e != hipSuccess) return e;
