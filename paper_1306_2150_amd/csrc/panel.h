@@ -127,31 +127,164 @@ __device__ void hh_qr_regs(double (&y)[NS][4], int mp, int kk, double *vbuf,
   }
 }
 
-// y <- H_0 H_1 ... H_{kr-1} y for reflectors stored below the diagonal of V
-// (global memory, leading dimension ldv, rows >= m are zero) and taus tau[].
+typedef double wy_d4 __attribute__((ext_vector_type(4)));
+
+// LDS doubles that hh_apply_wy needs for rank bucket KM: a 64-row chunk of V
+// (later the Gram matrix) and the KM x KM block Y (later Z, then M).
+template <int KM>
+constexpr int wy_lds() { return (64 + KM) * (KM + 1); }
+
+// Entry (i, a) of the reflector matrix: zero above the diagonal and for
+// a >= kr, one on it (also on the zero rows that pad a panel of m < k rows),
+// the stored vector below it for i < m.
+__device__ __forceinline__ double wy_v(const double *V, long ldv, int m, int kr, int i,
+                                       int a) {
+  if (a >= kr || i < a) return 0.0;
+  if (i == a) return 1.0;
+  return (i < m) ? V[i + (long)a * ldv] : 0.0;
+}
+
+// y <- H_0 H_1 ... H_{kr-1} [Y; 0], the k x k block Y (Y == nullptr: the
+// identity) on top of zero rows, in compact WY form.  With V = [v_0 ..
+// v_{kr-1}], applying H_{kr-1} first gives
+//     H_0 ... H_{kr-1} [Y; 0] = [Y; 0] - V M,
+//     m_j = tau_j (z_j - sum_{l > j} (v_j . v_l) m_l),   z_j = v_j^T [Y; 0],
+// rows m_j of M by back substitution from the last.  The Gram matrix V^T V
+// (a reduction over the panel rows) and Z = V^T [Y; 0] (only the top kk rows)
+// run on the float64 matrix cores, so the per-reflector reductions over all
+// rows of the sequential form disappear.  y is written in full (rows of the
+// m-row panel, columns < kk).  lds: wy_lds<4 NS>() doubles.
 template <int NS>
-__device__ void hh_apply_regs(double (&y)[NS][4], int m, int kr, int kk,
-                              const double *V, long ldv, const double *tau) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int j = kr - 1; j >= 0; --j) {
-    const double tj = tau[j];
-    if (tj == 0.0) continue;
-    double vv[4];
+__device__ void hh_apply_wy(double (&y)[NS][4], int m, int kr, int kk, const double *V,
+                            long ldv, const double *tau, const double *Y, long ldy,
+                            double *lds) {
+  constexpr int KM = 4 * NS, LD = KM + 1, NT = KM / 16, NTT = NT * NT;
+  constexpr int TPW = (NTT + 3) / 4;   // Gram / Z tiles per wave
+  double *sV = lds;                    // [64][LD] chunk of V, then G [KM][LD]
+  double *sY = lds + 64 * LD;          // [KM][LD] Y, then Z, then M
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  // the thread's share of V, all loads in flight at once: rows lane + 64 q,
+  // columns wave + 4 u (the register-panel layout)
+  double vr[NS][4];
+#pragma unroll
+  for (int u = 0; u < NS; ++u)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) vr[u][q] = wy_v(V, ldv, m, kr, lane + 64 * q, wave + 4 * u);
+  for (int e = tid; e < KM * KM; e += NTHR) {
+    const int r = e / KM, c = e - r * KM;
+    double v = 0.0;
+    if (r < kk && c < kk) v = Y ? Y[r + (long)c * ldy] : (r == c ? 1.0 : 0.0);
+    sY[r * LD + c] = v;
+  }
+  wy_d4 gacc[TPW], zacc[TPW];
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    gacc[u] = (wy_d4){0.0, 0.0, 0.0, 0.0};
+    zacc[u] = (wy_d4){0.0, 0.0, 0.0, 0.0};
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (64 * q >= m) break;
+    __syncthreads();   // the previous chunk is consumed (and sY is written)
+#pragma unroll
+    for (int u = 0; u < NS; ++u) sV[lane * LD + wave + 4 * u] = vr[u][q];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+      const int t = wave + 4 * u;
+      if (t < NTT) {
+        const int ta = t / NT, tb = t - ta * NT;
+        // A[i][k] = V(row 4 ks + k, col 16 ta + i): lane i + 16 k; B likewise
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+          const double a = sV[(4 * ks + g) * LD + 16 * ta + li];
+          const double b = sV[(4 * ks + g) * LD + 16 * tb + li];
+          gacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, gacc[u], 0, 0, 0);
+        }
+        if (q == 0) {
+#pragma unroll
+          for (int ks = 0; ks < KM / 4; ++ks) {
+            const double a = sV[(4 * ks + g) * LD + 16 * ta + li];
+            const double b = sY[(4 * ks + g) * LD + 16 * tb + li];
+            zacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, zacc[u], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // D[i][j]: lane j + 16 (i % 4), register i / 4
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    const int t = wave + 4 * u;
+    if (t < NTT) {
+      const int ta = t / NT, tb = t - ta * NT;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int e = (16 * ta + 4 * r + g) * LD + 16 * tb + li;
+        sV[e] = gacc[u][r];
+        sY[e] = zacc[u][r];
+      }
+    }
+  }
+  __syncthreads();
+  // M in place of Z, by 16-row blocks from the last.  In a block one lane
+  // per column solves the rows with the block's M values in registers; then
+  // all threads take the block's part out of the rows above it.
+  for (int j0 = ((kr - 1) / 16) * 16; j0 >= 0; j0 -= 16) {
+    const int j1 = min(kr, j0 + 16);
+    if (wave == 0 && lane < kk) {
+      double mb[16];
+#pragma unroll
+      for (int jj = 15; jj >= 0; --jj) {
+        const int j = j0 + jj;
+        double v = 0.0;
+        if (j < j1) {
+          double acc = 0.0;
+#pragma unroll
+          for (int ll = jj + 1; ll < 16; ++ll) acc += sV[j * LD + j0 + ll] * mb[ll];
+          v = tau[j] * (sY[j * LD + lane] - acc);
+          sY[j * LD + lane] = v;
+        }
+        mb[jj] = v;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < j0 * kk; e += NTHR) {
+      const int jr = e / kk, c = e - jr * kk;
+      double acc = 0.0;
+      for (int l = j0; l < j1; ++l) acc += sV[jr * LD + l] * sY[l * LD + c];
+      sY[jr * LD + c] -= acc;
+    }
+    __syncthreads();
+  }
+  // y = [Y; 0] - V M  (columns >= kk of M are zero)
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int c = wave + 4 * sl;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = lane + 64 * q;
-      vv[q] = (i == j) ? 1.0 : ((i > j && i < m) ? V[i + (long)j * ldv] : 0.0);
+      double v = 0.0;
+      if (c < kk && i < kk) v = Y ? Y[i + (long)c * ldy] : (i == c ? 1.0 : 0.0);
+      y[sl][q] = v;
     }
+  }
+  for (int a0 = 0; a0 < kr; a0 += 4) {
+    double v[4][4];
 #pragma unroll
-    for (int s2 = 0; s2 < NS; ++s2) {
-      const int c = wave + 4 * s2;
-      if (c < kk) {
-        double d = 0.0;
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) d += vv[q] * y[s2][q];
-        d = wave_sum(d) * tj;
+      for (int q = 0; q < 4; ++q) v[t][q] = wy_v(V, ldv, m, kr, lane + 64 * q, a0 + t);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) y[s2][q] -= d * vv[q];
+    for (int t = 0; t < 4; ++t) {
+      if (a0 + t >= kr) break;
+#pragma unroll
+      for (int sl = 0; sl < NS; ++sl) {
+        const double mv = sY[(a0 + t) * LD + wave + 4 * sl];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) y[sl][q] -= v[t][q] * mv;
       }
     }
   }

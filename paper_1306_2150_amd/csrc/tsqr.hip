@@ -229,7 +229,8 @@ __global__ __launch_bounds__(NTHR) void k_tsqr_node_apply(int which, int lev,
   }
   const double *H = s.tree_H + hlev_off(tr, lev) + (size_t)t * PANEL_M * KMAX;
   const double *T = s.tree_tau + lev_off(tr, lev, KMAX) + (size_t)t * KMAX;
-  hh_apply_regs(y, mp, min(mp, kk), kk, H, PANEL_M, T);
+  __shared__ double wy[wy_lds<4 * NS>()];
+  hh_apply_wy(y, mp, min(mp, kk), kk, H, PANEL_M, T, top ? nullptr : Yin, KMAX, wy);
   double *Yc = s.tree_Y + lev_off(tr, lev - 1, (size_t)KMAX * KMAX);
 #pragma unroll
   for (int sl = 0; sl < NS; ++sl) {
@@ -271,7 +272,8 @@ __global__ __launch_bounds__(NTHR) void k_tsqr_leaf_apply(int which, int n,
     }
   }
   const double *T = s.tree_tau + (size_t)b * KMAX;
-  hh_apply_regs(y, m, min(mp, kk), kk, s.Hv + r0, s.ldc, T);
+  __shared__ double wy[wy_lds<4 * NS>()];
+  hh_apply_wy(y, m, min(mp, kk), kk, s.Hv + r0, s.ldc, T, top ? nullptr : Yin, KMAX, wy);
   const TsIO io = ts_io(which, s);
   panel_store(y, io.out + r0, io.ldout, m, kk);
 }
