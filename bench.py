@@ -47,11 +47,11 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "int8": 5.0e15}
 # workload and batch); otherwise the traffic is reported as null.
 TRAFFIC = {
     "k_dst_i8": {"sources": ["dst_i8.hip", "lrp_internal.h"],
-                 "sha1": "533378d78f16408d98f3255a20e669a04f5ce839",
-                 "columns": 11990.857, "fetch_kib": 196866.7, "write_kib": 384111.2},
+                 "sha1": "90ab2dde4171ec452c30c86ddd4adb8adfc2484d",
+                 "columns": 11990.857, "fetch_kib": 196886.0, "write_kib": 384133.2},
     "k_dst_f64": {"sources": ["dst.hip", "lrp_internal.h"],
-                  "sha1": "05ceaddfdda8d251e6de9d7e3e3bd1828840db62",
-                  "columns": 41968, "fetch_kib": 675673.2, "write_kib": 1342976.0},
+                  "sha1": "cbc0ed39143efc5a7870b0bdd2593c28e400340e",
+                  "columns": 41968, "fetch_kib": 675688.9, "write_kib": 1342976.0},
 }
 
 
