@@ -162,7 +162,7 @@ Plan make_plan(const lrp_opts *o, double eps, int n) {
 // ------------------------------------------------------------- Group2D
 struct Layout {
   size_t off_Uh, off_Vh, off_upan, off_vpan, off_cpan, off_treeR, off_treeH,
-      off_treeTau, off_treeY, off_small, off_part, off_mvval, off_ints, total;
+      off_treeTau, off_treeY, off_small, off_part, off_mvval, off_ints, off_qf, total;
 };
 
 static size_t tree_nodes(const Tree &t, int from) {
@@ -198,6 +198,7 @@ static Layout slot_layout(int n, int m, const Tree &t) {
   L.off_part = take(std::max<size_t>((size_t)change_blocks(m) * KMAX * KMAX, 2 * nb0) * 8);
   L.off_mvval = take(nb0 * BLOCK_TOP * 8);
   L.off_ints = take((tree_nodes(t, 0) * KMAX + nb0 * BLOCK_TOP + 4 * KMAX) * 4);
+  L.off_qf = take((size_t)(n + m) * KMAX * 4);
   L.total = o;
   return L;
 }
@@ -274,6 +275,8 @@ lrp_status Group2D::init() {
     s.A = up + nk;
     s.Ap = up + 2 * nk;
     s.Q1 = vp;
+    s.Q0f = (float *)(b + L.off_qf);
+    s.Q1f = s.Q0f + nk;
     s.B = vp + mk;
     s.Bp = vp + 2 * mk;
     s.C = cp;

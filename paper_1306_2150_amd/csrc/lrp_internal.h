@@ -58,6 +58,7 @@ struct Solve2D {
   double *C;                // 3D core unfolding for TS_CORE (ldc)
   double *Hv;               // leaf Householder vectors (ldc)
   double *Q0, *Q1;          // orthonormal bases: columns (n rows), rows (m rows)
+  float *Q0f, *Q1f;         // their float copies (ldu, ldv), read by the maxvol check
   double *A, *B;            // skeleton factors, this sweep (n rows, m rows)
   double *Ap, *Bp;          // skeleton factors, previous sweep
   double *tree_R;           // sum_l nb[l] * KMAX*KMAX  R factors per node

@@ -22,18 +22,19 @@
 namespace lrp {
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
 struct MvIO {
   const double *Q;
+  const float *Qf;   // float copy of Q (leading dimension ld), for the check
   long ld;
   int *out;
   double *inv;
 };
 __device__ inline MvIO mv_io(int which, Solve2D &s) {
-  if (which == MV_Q0_TO_I) return {s.Q0, s.ldu, s.I, s.InvC};
-  if (which == MV_Q1_TO_JN) return {s.Q1, s.ldv, s.Jn, s.Inv};
-  return {s.Q1, s.ldv, s.J, s.Inv};   // MV_Q1_TO_J
+  if (which == MV_Q0_TO_I) return {s.Q0, s.Q0f, s.ldu, s.I, s.InvC};
+  if (which == MV_Q1_TO_JN) return {s.Q1, s.Q1f, s.ldv, s.Jn, s.Inv};
+  return {s.Q1, s.Q1f, s.ldv, s.J, s.Inv};   // MV_Q1_TO_J
 }
 
 __device__ inline int mv_phase(int which) {
@@ -185,11 +186,16 @@ __global__ __launch_bounds__(NTHR) void k_mv_inv(int which, int n, int force,
 }
 
 // ---- per block: rows of B = Q Inv, report the MV_TOP largest rows > tau.
-// B is formed on the float64 matrix cores (v_mfma_f64_16x16x4): wave w
-// takes rows 64 w .. 64 w + 63 of the block as four 16-row blocks; the
-// B operand (Inv, zero past k) stays in registers for the whole K loop.
-// Operand layouts: A[i][kq] in lane i + 16 kq, B[kq][j] in lane j + 16 kq,
-// D[i][j] in lane j + 16 (i % 4), register i / 4.
+// The check only selects candidates: the swap loop recomputes every
+// reported row in float64 and swaps only on those values, so B is formed
+// here from the float copy of Q on the float32 matrix cores
+// (v_mfma_f32_16x16x4f32; half the bytes of Q, twice the rate).  A row
+// within the float32 rounding of B of tau may go unreported; maxvol then
+// stops with max |B| above tau by at most that rounding.  Wave w takes rows
+// 64 w .. 64 w + 63 of the block as four 16-row blocks; the B operand (Inv,
+// zero past k) stays in registers for the whole K loop.  Operand layouts:
+// A[i][kq] in lane i + 16 kq, B[kq][j] in lane j + 16 kq, D[i][j] in lane
+// j + 16 (i / 4), register i % 4.
 template <int KM>
 __global__ __launch_bounds__(NTHR) void k_mv_check(int which, int n, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
@@ -203,34 +209,34 @@ __global__ __launch_bounds__(NTHR) void k_mv_check(int which, int n, Solve2D *S)
   const MvIO io = mv_io(which, s);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
-  double binv[NK][NC];
+  float binv[NK][NC];
 #pragma unroll
   for (int kb = 0; kb < NK; ++kb)
 #pragma unroll
     for (int cb = 0; cb < NC; ++cb) {
       const int r = 4 * kb + g, c = 16 * cb + li;
-      binv[kb][cb] = (r < kk && c < kk) ? io.inv[r + c * KMAX] : 0.0;
+      binv[kb][cb] = (r < kk && c < kk) ? (float)io.inv[r + c * KMAX] : 0.0f;
     }
   const int rw0 = blockIdx.x * NTHR + 64 * wave + li;   // + 16 rb
-  d4 acc[4][NC];
+  f4 acc[4][NC];
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < NC; ++cb) acc[rb][cb] = (d4){0, 0, 0, 0};
+    for (int cb = 0; cb < NC; ++cb) acc[rb][cb] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int kb = 0; kb < NK; ++kb) {
     const int col = 4 * kb + g;
-    double a[4];
+    float a[4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
       const int row = rw0 + 16 * rb;
-      a[rb] = (row < n && col < kk) ? io.Q[row + (long)col * io.ld] : 0.0;
+      a[rb] = (row < n && col < kk) ? io.Qf[row + (long)col * io.ld] : 0.0f;
     }
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int cb = 0; cb < NC; ++cb)
-        acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[rb], binv[kb][cb], acc[rb][cb], 0, 0, 0);
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb], binv[kb][cb], acc[rb][cb], 0, 0, 0);
   }
   // largest |B| of each row: over the column blocks in the lane, then over
   // the 16 lanes (one DPP row) that hold the row's columns; lane 15 of the
@@ -241,12 +247,12 @@ __global__ __launch_bounds__(NTHR) void k_mv_check(int which, int n, Solve2D *S)
     for (int r = 0; r < 4; ++r) {
       double v = 0.0;
 #pragma unroll
-      for (int cb = 0; cb < NC; ++cb) v = fmax(v, fabs(acc[rb][cb][r]));
+      for (int cb = 0; cb < NC; ++cb) v = fmax(v, (double)fabsf(acc[rb][cb][r]));
       v = fmax(v, dpp_f64<DPP_QUAD_1032>(v));
       v = fmax(v, dpp_f64<DPP_QUAD_2301>(v));
       v = fmax(v, dpp_f64<DPP_ROW_SHR4>(v));
       v = fmax(v, dpp_f64<DPP_ROW_SHR8>(v));
-      if (li == 15) rowmax[64 * wave + 16 * rb + 4 * r + g] = v;
+      if (li == 15) rowmax[64 * wave + 16 * rb + 4 * g + r] = v;
     }
   __syncthreads();
   const int row = blockIdx.x * NTHR + threadIdx.x;

@@ -27,8 +27,8 @@ __device__ __forceinline__ void panel_load(double (&y)[NS][4], const double *src
   }
 }
 
-template <int NS>
-__device__ __forceinline__ void panel_store(const double (&y)[NS][4], double *dst,
+template <int NS, typename T>
+__device__ __forceinline__ void panel_store(const double (&y)[NS][4], T *dst,
                                             long ld, int m, int kk) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -37,7 +37,7 @@ __device__ __forceinline__ void panel_store(const double (&y)[NS][4], double *ds
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = lane + 64 * q;
-      if (c < kk && i < m) dst[i + (long)c * ld] = y[s][q];
+      if (c < kk && i < m) dst[i + (long)c * ld] = (T)y[s][q];
     }
   }
 }

@@ -31,13 +31,14 @@ struct TsIO {
   long ldin;
   double *out;
   long ldout;
+  float *outf;   // float copy of out (same leading dimension), or null
 };
 __device__ inline TsIO ts_io(int which, const Solve2D &s) {
   // the cross panels are evaluated in the leaf (cross_panel), not loaded
-  if (which == TS_C_TO_Q0) return {nullptr, 0, s.Q0, s.ldu};
-  if (which == TS_C_TO_Q1) return {nullptr, 0, s.Q1, s.ldv};
-  if (which == TS_VH_TO_Q1) return {s.Vh, s.ldv, s.Q1, s.ldv};
-  return {s.C, s.ldc, nullptr, 0};   // TS_CORE: R only
+  if (which == TS_C_TO_Q0) return {nullptr, 0, s.Q0, s.ldu, s.Q0f};
+  if (which == TS_C_TO_Q1) return {nullptr, 0, s.Q1, s.ldv, s.Q1f};
+  if (which == TS_VH_TO_Q1) return {s.Vh, s.ldv, s.Q1, s.ldv, s.Q1f};
+  return {s.C, s.ldc, nullptr, 0, nullptr};   // TS_CORE: R only
 }
 
 __device__ inline int ts_phase(int which) {
@@ -276,6 +277,7 @@ __global__ __launch_bounds__(NTHR) void k_tsqr_leaf_apply(int which, int n,
   hh_apply_wy(y, m, min(mp, kk), kk, s.Hv + r0, s.ldc, T, top ? nullptr : Yin, KMAX, wy);
   const TsIO io = ts_io(which, s);
   panel_store(y, io.out + r0, io.ldout, m, kk);
+  if (io.outf) panel_store(y, io.outf + r0, io.ldout, m, kk);
 }
 
 template <int NS>
