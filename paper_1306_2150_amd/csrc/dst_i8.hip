@@ -50,7 +50,7 @@ namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-constexpr int TMI = 128;         // rows per workgroup: 4 waves x 2 x 16
+constexpr int TMI = 128;         // rows per workgroup: 512 / HW threads, HW 16-row blocks per wave
 constexpr int TNI = 32;          // columns per workgroup
 // Grid points staged per LDS buffer: KC = 64 for the 64-column tiles where
 // the planes fit beside the table (half the barriers of KC = 32), else 32.
@@ -169,14 +169,19 @@ __device__ __forceinline__ double recombine(const int (&acc)[6], double sc) {
 // split (gridDim.z > 1) workgroup z sums chunk z and writes its six level
 // sums as int32 to `partial` ([z][p][level][a][c], consecutive lanes on
 // consecutive columns); k_dst_i8_reduce adds them exactly and recombines.
-template <int TN_, int KC, bool FULL>
-__global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__restrict__ rec,
+//
+// HW: 16-row blocks per wave.  HW = 2: four waves of 32 rows (256 threads);
+// HW = 1: eight waves of 16 rows (512 threads), half the accumulators per
+// wave, so that the 64-column tiles run two waves per SIMD.
+template <int TN_, int KC, bool FULL, int HW = 2>
+__global__ __launch_bounds__(512 / HW) void k_dst_i8(int n, int Q, const uint2 *__restrict__ rec,
                                                 const DstCol *__restrict__ cols, int ncols,
                                                 int kchunk, const uint2 *__restrict__ xrec,
                                                 int hpad, const int *__restrict__ xex,
                                                 int *__restrict__ partial) {
   constexpr int NB = TN_ / 16;
   constexpr int XST = KC + 4;
+  constexpr int NT = 512 / HW;
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = n + 1, twoN = 2 * N;
   const int ntab = FULL ? twoN : 2 * Q;
@@ -193,23 +198,23 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
   const int kbeg = split ? blockIdx.z * kchunk : 0;
   const int kend = split ? min(Kp, kbeg + kchunk) : Kp;
   // table copy, eight loads in flight per thread
-  for (int i0 = 0; i0 < ntab; i0 += 8 * NTHR) {
+  for (int i0 = 0; i0 < ntab; i0 += 8 * NT) {
     uint2 v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int i = i0 + u * NTHR + tid;
+      const int i = i0 + u * NT + tid;
       v[u] = (i < ntab) ? rec[i] : make_uint2(0u, 0u);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int i = i0 + u * NTHR + tid;
+      const int i = i0 + u * NT + tid;
       if (i < ntab) tab[i] = v[u];
     }
   }
   // staging share: thread stages grid points tk of columns tc0 + 8 t; the
   // columns' records lie 2 hpad apart
-  constexpr int PER = KC * TN_ / NTHR;
-  constexpr int CSTEP = NTHR / KC;
+  constexpr int PER = KC * TN_ / NT;
+  constexpr int CSTEP = NT / KC;
   constexpr int LVL = TN_ * XST;                 // dwords per record plane and buffer
   const int tk = tid & (KC - 1), tc0 = tid / KC;
   const int nsrc = max(0, min(PER, ceil_div(ncols - c0 - tc0, CSTEP)));
@@ -234,21 +239,21 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
       p[LVL] = pre[t].y;
     }
   };
-  // rows of this lane: a = row0 + 32 wave + 16 h + (lane & 15), grid row
+  // rows of this lane: a = row0 + 16 HW wave + 16 h + (lane & 15), grid row
   // j = 2 a + 1 + par (1-based)
   const int g = lane >> 4, li = lane & 15;
-  int jr[2], d16[2], mk[2];
+  int jr[HW], d16[HW], mk[HW];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int a = row0 + 32 * wave + 16 * h + li;
+  for (int h = 0; h < HW; ++h) {
+    const int a = row0 + 16 * HW * wave + 16 * h + li;
     jr[h] = (a < Kp) ? 2 * a + 1 + par : 0;    // rows past the end: sin(0) = 0
     d16[h] = (int)(((long long)jr[h] * 16) % twoN);
     // m = j k mod 2N at this lane's first grid point, k = kbeg + 4 g + 1
     mk[h] = (int)(((long long)jr[h] * (kbeg + 4 * g + 1)) % twoN);
   }
-  v4i acc[2][NB][6];
+  v4i acc[HW][NB][6];
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < HW; ++h)
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -265,9 +270,9 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
     const int kcn = min(KC, kend - k0);
     for (int kk = 0; kk < kcn; kk += 16) {
       // A operands: records of points k0 + kk + 4g + e (1-based k)
-      v4i ahi[2], alo[2];
+      v4i ahi[HW], alo[HW];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
+      for (int h = 0; h < HW; ++h) {
         int m = mk[h];
         mk[h] += d16[h];                 // the lane's first point of the next step
         if (mk[h] >= twoN) mk[h] -= twoN;
@@ -309,7 +314,7 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
           w[0][e] = (int)((uint32_t)d1[e] >> 8);
         }
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < HW; ++h) {
 #pragma unroll
           for (int t = 0; t < 6; ++t)
             acc[h][b][t] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ahi[h], w[t], acc[h][b][t], 0, 0, 0);
@@ -330,10 +335,10 @@ __global__ __launch_bounds__(NTHR) void k_dst_i8(int n, int Q, const uint2 *__re
     const int e = (c < ncols) ? xex[2 * c + par] : 0;
     const double sc = ldexp(sc0, e - 12);
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < HW; ++h)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int a = row0 + 32 * wave + 16 * h + 4 * g + q;
+        const int a = row0 + 16 * HW * wave + 16 * h + 4 * g + q;
         if (a < Kp && c < ncols) {
           if (split) {
             int *pp = partial + (((size_t)blockIdx.z * 2 + par) * 6 * H0 + a) * ncols + c;
@@ -457,9 +462,10 @@ hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, Solve2
     int *xex = (int *)(xrec + (size_t)2 * nc * hpad);
     hipLaunchKernelGGL(k_x_slices, dim3(nc), dim3(NTHR), 0, st, n, hpad, cc, nc, xrec, xex,
                        solves);
-    // 64-column tiles (one wave per SIMD, 20-25 % faster on large launches
-    // than 32-column tiles at two waves per SIMD) when they alone give every
-    // CU a workgroup; 32-column tiles, twice as many, on small launches
+    // 64-column tiles (eight waves of 16 rows where the 64-point stages fit,
+    // two waves per SIMD; faster on large launches than 32-column tiles)
+    // when they alone give every CU a workgroup; 32-column tiles, twice as
+    // many, on small launches
     const int R = ceil_div(H0, TMI);
     const bool wide = R * 2 * ceil_div(nc, 64) >= 256 && i8_lds(n, 64, KCN, false) <= LDS_MAX;
     const int tn = wide ? 64 : TNI;
@@ -476,7 +482,7 @@ hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, Solve2
     const size_t lds = i8_lds(n, tn, kc, full);
     const void *fn = nullptr;
     if (wide && kc == KCW)
-      fn = full ? (const void *)k_dst_i8<64, KCW, true> : (const void *)k_dst_i8<64, KCW, false>;
+      fn = full ? (const void *)k_dst_i8<64, KCW, true, 1> : (const void *)k_dst_i8<64, KCW, false, 1>;
     else if (wide)
       fn = full ? (const void *)k_dst_i8<64, KCN, true> : (const void *)k_dst_i8<64, KCN, false>;
     else
@@ -488,8 +494,12 @@ hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, Solve2
   hipLaunchKernelGGL((k_dst_i8<TNV, KCV, FV>), g, dim3(NTHR), lds, st, n, Q, trec, cc, nc,  \
                      kchunk, xrec, hpad, xex, out_partial)
     if (wide && kc == KCW) {
-      if (full) LRP_I8_LAUNCH(64, KCW, true);
-      else LRP_I8_LAUNCH(64, KCW, false);
+      if (full)
+        hipLaunchKernelGGL((k_dst_i8<64, KCW, true, 1>), g, dim3(512), lds, st, n, Q, trec, cc, nc,
+                           kchunk, xrec, hpad, xex, out_partial);
+      else
+        hipLaunchKernelGGL((k_dst_i8<64, KCW, false, 1>), g, dim3(512), lds, st, n, Q, trec, cc, nc,
+                           kchunk, xrec, hpad, xex, out_partial);
     } else if (wide) {
       if (full) LRP_I8_LAUNCH(64, KCN, true);
       else LRP_I8_LAUNCH(64, KCN, false);
