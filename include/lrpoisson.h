@@ -255,7 +255,11 @@ lrp_status lrp_submit(lrp_ctx *ctx, const lrp_request *req, uint64_t *ticket);
 
 /* Run one scheduling tick (admission, one step of every running request,
  * retirement).  Returns the number of requests still queued or running in
- * *pending. */
+ * *pending.  Requests of one dimension and grid size share a group of slots
+ * created on first use and kept for the context's lifetime.  If a group does
+ * not fit the budget, the groups the context caches for its synchronous
+ * calls are freed first; if it still does not fit, the queued requests of
+ * that shape finish with LRP_ENOMEM (reported by lrp_poll / lrp_wait). */
 lrp_status lrp_serve_step(lrp_ctx *ctx, int32_t *pending);
 
 /* Non-blocking completion check.  LRP_ENOTREADY while the request is queued

@@ -20,6 +20,7 @@
 //      slot states back to the host.
 // A slow group (a large 3D grid) therefore never holds back a fast one.
 #include <algorithm>
+#include <map>
 #include <cstring>
 
 #include "host.h"
@@ -326,14 +327,38 @@ lrp_status lrp_serve_step(lrp_ctx *ctx, int32_t *pending) {
   if (hipSetDevice(ctx->device) != hipSuccess) return LRP_EDEVICE;
   std::lock_guard<std::mutex> lock(ctx->mu);
   lrp_status e;
-  // groups for queued requests are created on first use; a group that does
-  // not fit the budget yet leaves its requests queued
+  // Groups for queued requests are created on first use.  A group that does
+  // not fit the budget first frees the groups that the context caches for
+  // its synchronous calls (they are rebuilt when next needed).  Serving
+  // groups are kept for the context's lifetime, so a group that still does
+  // not fit never will: the queued requests of its shape finish with that
+  // error instead of waiting for memory that cannot free up.
+  std::map<std::pair<int, int>, lrp_status> failed;   // (dim, n) -> status
+  auto make = [&](int dim, int n) -> bool {
+    return dim == 3 ? serve_group3(ctx, n, &e) != nullptr : serve_group(ctx, n, &e) != nullptr;
+  };
   for (const auto &q : ctx->queue) {
-    if (q.req.dim == 3) {
-      if (!ctx->serve3_groups.count((int)q.req.n)) serve_group3(ctx, (int)q.req.n, &e);
-    } else if (!ctx->serve_groups.count((int)q.req.n)) {
-      serve_group(ctx, (int)q.req.n, &e);
+    const int dim = q.req.dim, n = (int)q.req.n;
+    const bool have = dim == 3 ? ctx->serve3_groups.count(n) > 0 : ctx->serve_groups.count(n) > 0;
+    if (have || failed.count({dim, n})) continue;
+    if (make(dim, n)) continue;
+    if (e == LRP_ENOMEM && (!ctx->batch_groups.empty() || !ctx->batch3_groups.empty())) {
+      ctx->batch_groups.clear();
+      ctx->batch3_groups.clear();
+      if (make(dim, n)) continue;
     }
+    failed[{dim, n}] = e;
+  }
+  for (auto it = ctx->queue.begin(); it != ctx->queue.end();) {
+    auto f = failed.find({it->req.dim, (int)it->req.n});
+    if (f == failed.end()) {
+      ++it;
+      continue;
+    }
+    it->state = 2;
+    it->status = f->second;
+    ctx->finished[it->ticket] = *it;
+    it = ctx->queue.erase(it);
   }
   for (auto &kv : ctx->serve_groups)
     if ((e = tick2d(ctx, kv.second.get())) != LRP_OK) return e;

@@ -135,3 +135,83 @@ def test_served_errors_do_not_disturb_others():
         assert done[i][0][0] == binding.LRP_OK
     with pytest.raises(binding.LrpError):
         c.submit(bad, bad, 0.0)
+
+
+def _serve_until_done(c, tickets, limit_s=60):
+    import time
+    res = {}
+    t0 = time.time()
+    while len(res) < len(tickets):
+        assert time.time() - t0 < limit_s, "serving loop made no progress"
+        c.serve_step()
+        for t in tickets:
+            if t not in res:
+                r = c.poll(t)
+                if r is not None:
+                    res[t] = r
+    return res
+
+
+def test_served_group_over_budget_reports_enomem():
+    """A request whose slot group can never fit the context's budget finishes
+    with LRP_ENOMEM instead of staying queued."""
+    log("serve over budget")
+    c = binding.Context(0, workspace_bytes=64 << 20)
+    try:
+        rng = np.random.default_rng(5)
+        U = dev(rng.standard_normal((1024, 4)))
+        V = dev(rng.standard_normal((1024, 4)))
+        t, _ = c.submit(U, V, 1e-8, prec="fp64")
+        res = _serve_until_done(c, [t])
+        assert res[t][0] == binding.LRP_ENOMEM, res[t]
+    finally:
+        c.close()
+
+
+def test_served_frees_cached_batch_groups():
+    """Serving a shape whose slot group does not fit beside the group that a
+    synchronous batch call left cached frees that cache and then runs, with
+    the batch's result."""
+    n, count, eps = 1024, 256, 1e-8
+    rng = np.random.default_rng(6)
+    x = np.linspace(0.0, 1.0, n + 2)[1:-1]
+    U = dev(np.stack([np.exp(-(x - a) ** 2 / 0.01) for a in (0.3, 0.5, 0.7)], 1))
+    V = dev(np.stack([np.exp(-(x - a) ** 2 / 0.02) * w for a, w in
+                      ((0.4, 1.0), (0.6, -0.5), (0.2, 0.3))], 1))
+    problems = [(U, V, eps)] * count
+
+    def batch_fits(budget):
+        c = binding.Context(0, workspace_bytes=budget)
+        try:
+            c.batch2d(problems, prec="fp64").run(results=False)
+            return True
+        except binding.LrpError as e:
+            assert e.status == binding.LRP_ENOMEM, e
+            return False
+        finally:
+            c.close()
+
+    # the smallest budget that holds the batch's group, to 1/64 of it
+    lo, hi = 16 << 20, 8 << 30
+    assert batch_fits(hi)
+    while hi - lo > hi >> 6:
+        mid = (lo + hi) // 2
+        if batch_fits(mid):
+            hi = mid
+        else:
+            lo = mid
+    log("serve after batch: batch needs <=", hi >> 20, "MiB")
+    # room for the batch's group, not for a 32-slot group beside it
+    c = binding.Context(0, workspace_bytes=hi + (hi >> 5))
+    try:
+        (Ub, Vb, _), = c.batch2d(problems[:1] * count, prec="fp64").run()[:1]
+        want = host(Ub) @ host(Vb).T
+        t, outs = c.submit(U, V, eps, prec="fp64")
+        status, ranks, _ = _serve_until_done(c, [t])[t]
+        assert status == binding.LRP_OK, status
+        got = assemble(2, served_result(2, outs, ranks))
+        d = rel(got, want)
+        log("  served vs batch", d)
+        assert d <= 1e-12, d
+    finally:
+        c.close()
