@@ -47,11 +47,11 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "int8": 5.0e15}
 # workload and batch); otherwise the traffic is reported as null.
 TRAFFIC = {
     "k_dst_i8": {"sources": ["dst_i8.hip", "lrp_internal.h"],
-                 "sha1": "90ab2dde4171ec452c30c86ddd4adb8adfc2484d",
-                 "columns": 11990.857, "fetch_kib": 196886.0, "write_kib": 384133.2},
+                 "sha1": "f40393ab08ce5dfe24b9dfb49eb9db5a9a24f251",
+                 "columns": 11990.857, "fetch_kib": 196755.0, "write_kib": 384109.7},
     "k_dst_f64": {"sources": ["dst.hip", "lrp_internal.h"],
-                  "sha1": "cbc0ed39143efc5a7870b0bdd2593c28e400340e",
-                  "columns": 41968, "fetch_kib": 675688.9, "write_kib": 1342976.0},
+                  "sha1": "871c78f909deb4a14a92ef056e68a56ace6e78ff",
+                  "columns": 41968, "fetch_kib": 675660.6, "write_kib": 1342976.0},
 }
 
 
