@@ -134,7 +134,9 @@ __device__ __forceinline__ void store_out(double v, int a, int col, const FoldTi
 }
 
 // ------------------------------------------------------------------ FP64
-// 128 rows (4 waves x 32) x TN columns per workgroup.  The source tile is
+// 128 rows x TN columns per workgroup: HW 16-row blocks per wave (HW = 2:
+// four waves of 32 rows; HW = 1: eight waves of 16 rows, half the
+// accumulators per wave, so two waves share a SIMD).  The source tile is
 // staged in LDS as [column][k] with one double of padding per column (the
 // 16 lanes that read one k for 16 columns then hit distinct banks), double
 // buffered: the next K stage is fetched into registers while the MFMAs run on
@@ -143,13 +145,15 @@ constexpr int TM64 = 128;
 constexpr int KC64 = 32;
 constexpr int LDT = KC64 + 1;
 
-template <int TN_>
-__global__ __launch_bounds__(NTHR) void k_dst_f64(
+template <int TN_, int HW = 2>
+__global__ __launch_bounds__(512 / HW) void k_dst_f64(
     int n, int Q, const double *__restrict__ qtab,
     const DstCol *__restrict__ cols, int ncols, int kchunk,
     double *__restrict__ partial, Solve2D *solves) {
+  constexpr int NT = 512 / HW;                    // threads
   constexpr int NB = TN_ / 16;                    // column blocks per wave
-  constexpr int PER = KC64 * TN_ / NTHR;          // tile values per thread
+  constexpr int PER = KC64 * TN_ / NT;            // tile values per thread
+  constexpr int CSTEP = NT / KC64;                // staged columns per pass
   extern __shared__ __align__(16) unsigned char smem[];
   const int Qp = (Q + 1) & ~1;
   double *tab = (double *)smem;
@@ -161,16 +165,29 @@ __global__ __launch_bounds__(NTHR) void k_dst_f64(
   const int row0 = ft.row0, c0 = ft.c0;
   int cb, ce;
   chunk_range(ft.H0, kchunk, cb, ce);
-  for (int i = tid; i < Q; i += NTHR) tab[i] = qtab[i];
+  // table copy, eight loads in flight per thread
+  for (int i0 = 0; i0 < Q; i0 += 8 * NT) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * NT + tid;
+      v[u] = (i < Q) ? qtab[i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * NT + tid;
+      if (i < Q) tab[i] = v[u];
+    }
+  }
 
   // this thread's share of a K stage: k offset tk (32 lanes read 32
-  // consecutive k of one column), columns tc0 + 8 t
-  const int tk = tid & 31, tc0 = tid >> 5;
+  // consecutive k of one column), columns tc0 + CSTEP t
+  const int tk = tid & (KC64 - 1), tc0 = tid / KC64;
   const double *src[PER];
   int sidx[PER];
 #pragma unroll
   for (int t = 0; t < PER; ++t) {
-    const int c = c0 + tc0 + 8 * t;
+    const int c = c0 + tc0 + CSTEP * t;
     src[t] = nullptr;
     sidx[t] = -1;
     if (c < ncols) {
@@ -196,22 +213,23 @@ __global__ __launch_bounds__(NTHR) void k_dst_f64(
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
       bool b = false;
-      xs[(tc0 + 8 * t) * LDT + tk] = fold_combine(pa[t], pb[t], kf, n, ft.par, b);
+      xs[(tc0 + CSTEP * t) * LDT + tk] = fold_combine(pa[t], pb[t], kf, n, ft.par, b);
       if (b) bad |= 1u << t;
     }
   };
 
-  // grid rows (1-based) of half-rows a and a + 16
-  const int jA = fold_row(row0 + wave * 32 + (lane & 15), ft);
-  const int jB = fold_row(row0 + wave * 32 + (lane & 15) + 16, ft);
+  // grid rows (1-based) of the lane's half-rows row0 + 16 HW wave + 16 h + li
   const int kk = lane >> 4;
-  const int stepA = (int)((4LL * jA) % twoN);
-  const int stepB = (int)((4LL * jB) % twoN);
-  int mA = (int)(((long long)jA * (kbeg + kk + 1)) % twoN);
-  int mB = (int)(((long long)jB * (kbeg + kk + 1)) % twoN);
-  d4 acc[2][NB], part[2][NB];
+  int jr[HW], step[HW], mm[HW];
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < HW; ++h) {
+    jr[h] = fold_row(row0 + wave * 16 * HW + 16 * h + (lane & 15), ft);
+    step[h] = (int)((4LL * jr[h]) % twoN);
+    mm[h] = (int)(((long long)jr[h] * (kbeg + kk + 1)) % twoN);
+  }
+  d4 acc[HW][NB], part[HW][NB];
+#pragma unroll
+  for (int h = 0; h < HW; ++h)
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[h][b] = part[h][b] = (d4){0, 0, 0, 0};
 
@@ -223,7 +241,7 @@ __global__ __launch_bounds__(NTHR) void k_dst_f64(
     const int k0 = kbeg + st * KC64;
     if (st > 0 && (k0 % kchunk) == 0) {           // a new K chunk starts
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < HW; ++h)
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           acc[h][b] += part[h][b];
@@ -235,34 +253,38 @@ __global__ __launch_bounds__(NTHR) void k_dst_f64(
     const int kcn = min(KC64, kend - k0);
     // software pipelined: the operands of step kc + 4 are read from LDS
     // while the MFMAs of step kc run
-    double aA = sine_lookup(tab, mA, N), aB = sine_lookup(tab, mB, N), bv[NB];
-    mA += stepA;
-    if (mA >= twoN) mA -= twoN;
-    mB += stepB;
-    if (mB >= twoN) mB -= twoN;
+    double av[HW], bv[NB];
+#pragma unroll
+    for (int h = 0; h < HW; ++h) {
+      av[h] = sine_lookup(tab, mm[h], N);
+      mm[h] += step[h];
+      if (mm[h] >= twoN) mm[h] -= twoN;
+    }
 #pragma unroll
     for (int b = 0; b < NB; ++b) bv[b] = xs[(b * 16 + (lane & 15)) * LDT + kk];
     for (int kc = 0; kc < kcn; kc += 4) {
-      double nA = 0.0, nB = 0.0, nb[NB];
+      double na[HW], nb[NB];
+#pragma unroll
+      for (int h = 0; h < HW; ++h) na[h] = 0.0;
 #pragma unroll
       for (int b = 0; b < NB; ++b) nb[b] = 0.0;
       if (kc + 4 < kcn) {
-        nA = sine_lookup(tab, mA, N);
-        nB = sine_lookup(tab, mB, N);
-        mA += stepA;
-        if (mA >= twoN) mA -= twoN;
-        mB += stepB;
-        if (mB >= twoN) mB -= twoN;
+#pragma unroll
+        for (int h = 0; h < HW; ++h) {
+          na[h] = sine_lookup(tab, mm[h], N);
+          mm[h] += step[h];
+          if (mm[h] >= twoN) mm[h] -= twoN;
+        }
 #pragma unroll
         for (int b = 0; b < NB; ++b) nb[b] = xs[(b * 16 + (lane & 15)) * LDT + kc + 4 + kk];
       }
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        part[0][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aA, bv[b], part[0][b], 0, 0, 0);
-        part[1][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(aB, bv[b], part[1][b], 0, 0, 0);
-      }
-      aA = nA;
-      aB = nB;
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int h = 0; h < HW; ++h)
+          part[h][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[h], bv[b], part[h][b], 0, 0, 0);
+#pragma unroll
+      for (int h = 0; h < HW; ++h) av[h] = na[h];
 #pragma unroll
       for (int b = 0; b < NB; ++b) bv[b] = nb[b];
     }
@@ -273,17 +295,17 @@ __global__ __launch_bounds__(NTHR) void k_dst_f64(
   for (int t = 0; t < PER; ++t)
     if (((bad >> t) & 1u) && sidx[t] >= 0) solves[sidx[t]].nonfinite = 1;
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < HW; ++h)
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc[h][b] += part[h][b];
   // f64 layout: D[i][jj] at lane jj + 16 (i % 4), register i / 4
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < HW; ++h)
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int a = row0 + wave * 32 + h * 16 + (lane >> 4) + 4 * r;
+        const int a = row0 + wave * 16 * HW + h * 16 + (lane >> 4) + 4 * r;
         const int col = c0 + b * 16 + (lane & 15);
         store_out(acc[h][b][r], a, col, ft, ncols, cols, partial, blockIdx.z);
       }
@@ -661,15 +683,16 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
   if (prec == LRP_PREC_FP64) {
     const dim3 g(tile_grid(R, C, true), 1, split);
     lds = (size_t)Qp8 * 8 + (size_t)2 * tn * LDT * 8;
-    const void *fn = wide ? (const void *)k_dst_f64<64> : (const void *)k_dst_f64<32>;
+    // 64-column tiles as eight waves of 16 rows (two waves per SIMD)
+    const void *fn = wide ? (const void *)k_dst_f64<64, 1> : (const void *)k_dst_f64<32, 2>;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
     if (wide)
-      hipLaunchKernelGGL(k_dst_f64<64>, g, block, lds, st, n, Q, t64, cols, ncols,
+      hipLaunchKernelGGL((k_dst_f64<64, 1>), g, dim3(512), lds, st, n, Q, t64, cols, ncols,
                          kchunk, out_partial, solves);
     else
-      hipLaunchKernelGGL(k_dst_f64<32>, g, block, lds, st, n, Q, t64, cols, ncols,
+      hipLaunchKernelGGL((k_dst_f64<32, 2>), g, dim3(256), lds, st, n, Q, t64, cols, ncols,
                          kchunk, out_partial, solves);
   } else if (prec == LRP_PREC_FP32) {
     const dim3 g(tile_grid(R, C, true), 1, split);
