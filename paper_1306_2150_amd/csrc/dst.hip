@@ -312,18 +312,21 @@ __global__ __launch_bounds__(512 / HW) void k_dst_f64(
 }
 
 // ------------------------------------------------------------------ FP32
-// Same tiling as the float64 kernel with float32 operands; the MFMA sums run
-// in float32 over 32-deep K runs that are flushed into float64 chunk sums.
+// Same tiling as the float64 kernel (HW 16-row blocks per wave) with float32
+// operands; the MFMA sums run in float32 over 32-deep K runs that are
+// flushed into float64 chunk sums.
 constexpr int F32_RUN = 32;   // K depth accumulated in float32
 constexpr int LDT32 = KC64 + 1;
 
-template <int TN_>
-__global__ __launch_bounds__(NTHR) void k_dst_f32(
+template <int TN_, int HW = 2>
+__global__ __launch_bounds__(512 / HW) void k_dst_f32(
     int n, int Q, const float *__restrict__ qtab,
     const DstCol *__restrict__ cols, int ncols, int kchunk,
     double *__restrict__ partial, Solve2D *solves) {
+  constexpr int NT = 512 / HW;
   constexpr int NB = TN_ / 16;
-  constexpr int PER = KC64 * TN_ / NTHR;
+  constexpr int PER = KC64 * TN_ / NT;
+  constexpr int CSTEP = NT / KC64;
   extern __shared__ __align__(16) unsigned char smem[];
   const int Qp = (Q + 3) & ~3;
   float *tab = (float *)smem;
@@ -335,14 +338,27 @@ __global__ __launch_bounds__(NTHR) void k_dst_f32(
   const int row0 = ft.row0, c0 = ft.c0;
   int cb, ce;
   chunk_range(ft.H0, kchunk, cb, ce);
-  for (int i = tid; i < Q; i += NTHR) tab[i] = qtab[i];
+  // table copy, eight loads in flight per thread
+  for (int i0 = 0; i0 < Q; i0 += 8 * NT) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * NT + tid;
+      v[u] = (i < Q) ? qtab[i] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * NT + tid;
+      if (i < Q) tab[i] = v[u];
+    }
+  }
 
-  const int tk = tid & 31, tc0 = tid >> 5;
+  const int tk = tid & (KC64 - 1), tc0 = tid / KC64;
   const double *src[PER];
   int sidx[PER];
 #pragma unroll
   for (int t = 0; t < PER; ++t) {
-    const int c = c0 + tc0 + 8 * t;
+    const int c = c0 + tc0 + CSTEP * t;
     src[t] = nullptr;
     sidx[t] = -1;
     if (c < ncols) {
@@ -366,22 +382,23 @@ __global__ __launch_bounds__(NTHR) void k_dst_f32(
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
       bool b = false;
-      xs[(tc0 + 8 * t) * LDT32 + tk] = (float)fold_combine(pa[t], pb[t], kf, n, ft.par, b);
+      xs[(tc0 + CSTEP * t) * LDT32 + tk] = (float)fold_combine(pa[t], pb[t], kf, n, ft.par, b);
       if (b) bad |= 1u << t;
     }
   };
 
-  const int jA = fold_row(row0 + wave * 32 + (lane & 15), ft);
-  const int jB = fold_row(row0 + wave * 32 + (lane & 15) + 16, ft);
   const int kk = lane >> 4;
-  const int stepA = (int)((4LL * jA) % twoN);
-  const int stepB = (int)((4LL * jB) % twoN);
-  int mA = (int)(((long long)jA * (kbeg + kk + 1)) % twoN);
-  int mB = (int)(((long long)jB * (kbeg + kk + 1)) % twoN);
-  f4 run[2][NB];
-  double acc[2][NB][4], part[2][NB][4];
+  int jr[HW], step[HW], mm[HW];
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < HW; ++h) {
+    jr[h] = fold_row(row0 + wave * 16 * HW + 16 * h + (lane & 15), ft);
+    step[h] = (int)((4LL * jr[h]) % twoN);
+    mm[h] = (int)(((long long)jr[h] * (kbeg + kk + 1)) % twoN);
+  }
+  f4 run[HW][NB];
+  double acc[HW][NB][4], part[HW][NB][4];
+#pragma unroll
+  for (int h = 0; h < HW; ++h)
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       run[h][b] = (f4){0, 0, 0, 0};
@@ -397,7 +414,7 @@ __global__ __launch_bounds__(NTHR) void k_dst_f32(
     const int k0 = kbeg + st * KC64;
     if (st > 0 && (k0 % kchunk) == 0) {
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int h = 0; h < HW; ++h)
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
@@ -409,40 +426,44 @@ __global__ __launch_bounds__(NTHR) void k_dst_f32(
     if (st + 1 < nst) fetch(st + 1);
     const float *xs = xs0 + (st & 1) * TN_ * LDT32;
     const int kcn = min(KC64, kend - k0);
-    float aA = sine_lookup(tab, mA, N), aB = sine_lookup(tab, mB, N), bv[NB];
-    mA += stepA;
-    if (mA >= twoN) mA -= twoN;
-    mB += stepB;
-    if (mB >= twoN) mB -= twoN;
+    float av[HW], bv[NB];
+#pragma unroll
+    for (int h = 0; h < HW; ++h) {
+      av[h] = sine_lookup(tab, mm[h], N);
+      mm[h] += step[h];
+      if (mm[h] >= twoN) mm[h] -= twoN;
+    }
 #pragma unroll
     for (int b = 0; b < NB; ++b) bv[b] = xs[(b * 16 + (lane & 15)) * LDT32 + kk];
     for (int kc = 0; kc < kcn; kc += 4) {
-      float nA = 0.f, nB = 0.f, nb[NB];
+      float na[HW], nb[NB];
+#pragma unroll
+      for (int h = 0; h < HW; ++h) na[h] = 0.f;
 #pragma unroll
       for (int b = 0; b < NB; ++b) nb[b] = 0.f;
       if (kc + 4 < kcn) {
-        nA = sine_lookup(tab, mA, N);
-        nB = sine_lookup(tab, mB, N);
-        mA += stepA;
-        if (mA >= twoN) mA -= twoN;
-        mB += stepB;
-        if (mB >= twoN) mB -= twoN;
+#pragma unroll
+        for (int h = 0; h < HW; ++h) {
+          na[h] = sine_lookup(tab, mm[h], N);
+          mm[h] += step[h];
+          if (mm[h] >= twoN) mm[h] -= twoN;
+        }
 #pragma unroll
         for (int b = 0; b < NB; ++b) nb[b] = xs[(b * 16 + (lane & 15)) * LDT32 + kc + 4 + kk];
       }
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        run[0][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aA, bv[b], run[0][b], 0, 0, 0);
-        run[1][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(aB, bv[b], run[1][b], 0, 0, 0);
-      }
-      aA = nA;
-      aB = nB;
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int h = 0; h < HW; ++h)
+          run[h][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[h], bv[b], run[h][b], 0, 0, 0);
+#pragma unroll
+      for (int h = 0; h < HW; ++h) av[h] = na[h];
 #pragma unroll
       for (int b = 0; b < NB; ++b) bv[b] = nb[b];
     }
     // a stage is one 32-deep float32 run
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < HW; ++h)
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
 #pragma unroll
@@ -457,12 +478,12 @@ __global__ __launch_bounds__(NTHR) void k_dst_f32(
     if (((bad >> t) & 1u) && sidx[t] >= 0) solves[sidx[t]].nonfinite = 1;
   // f32 layout: D[i][jj] at lane jj + 16 (i / 4), register i % 4
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < HW; ++h)
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int a = row0 + wave * 32 + h * 16 + 4 * (lane >> 4) + r;
+        const int a = row0 + wave * 16 * HW + h * 16 + 4 * (lane >> 4) + r;
         const int col = c0 + b * 16 + (lane & 15);
         store_out(acc[h][b][r] + part[h][b][r], a, col, ft, ncols, cols, partial,
                   blockIdx.z);
@@ -697,15 +718,15 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
   } else if (prec == LRP_PREC_FP32) {
     const dim3 g(tile_grid(R, C, true), 1, split);
     lds = (size_t)Qp4 * 4 + (size_t)2 * tn * LDT32 * 4;
-    const void *fn = wide ? (const void *)k_dst_f32<64> : (const void *)k_dst_f32<32>;
+    const void *fn = wide ? (const void *)k_dst_f32<64, 1> : (const void *)k_dst_f32<32, 2>;
     e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
     if (wide)
-      hipLaunchKernelGGL(k_dst_f32<64>, g, block, lds, st, n, Q, t32, cols, ncols,
+      hipLaunchKernelGGL((k_dst_f32<64, 1>), g, dim3(512), lds, st, n, Q, t32, cols, ncols,
                          kchunk, out_partial, solves);
     else
-      hipLaunchKernelGGL(k_dst_f32<32>, g, block, lds, st, n, Q, t32, cols, ncols,
+      hipLaunchKernelGGL((k_dst_f32<32, 2>), g, dim3(256), lds, st, n, Q, t32, cols, ncols,
                          kchunk, out_partial, solves);
   } else {
     const dim3 g(tile_grid(R, C, true), 1, split);
