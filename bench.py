@@ -48,10 +48,10 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "int8": 5.0e15}
 TRAFFIC = {
     "k_dst_i8": {"sources": ["dst_i8.hip", "lrp_internal.h"],
                  "sha1": "f40393ab08ce5dfe24b9dfb49eb9db5a9a24f251",
-                 "columns": 11990.857, "fetch_kib": 196755.0, "write_kib": 384109.7},
+                 "columns": 11990.857, "fetch_kib": 196763.8, "write_kib": 384159.0},
     "k_dst_f64": {"sources": ["dst.hip", "lrp_internal.h"],
-                  "sha1": "871c78f909deb4a14a92ef056e68a56ace6e78ff",
-                  "columns": 41968, "fetch_kib": 675660.6, "write_kib": 1342976.0},
+                  "sha1": "0331c097f33f67d56d91b7fbf8a11a879af7d62a",
+                  "columns": 41968, "fetch_kib": 675064.2, "write_kib": 1379926.9},
 }
 
 
