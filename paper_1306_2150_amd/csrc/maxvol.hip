@@ -88,24 +88,30 @@ __global__ __launch_bounds__(NTHR) void k_mv_node(int which, int n, int lev,
   __shared__ int shp[2];
   __shared__ int piv[KMAX];
   __shared__ int rows[PANEL_M];
-  __shared__ int nrows;
+  __shared__ int wcnt[4];
   const int kk = s.k;
   const MvIO io = mv_io(which, s);
   const int t = blockIdx.x, c0 = t * tr.fan;
   const int nch = min(tr.fan, tr.nb[lev - 1] - c0);
   const int *cp = s.tree_piv + piv_off(tr, lev - 1) + (size_t)c0 * KMAX;
-  if (threadIdx.x == 0) {
-    int cnt = 0;
-    for (int i = 0; i < nch * kk; ++i) {
-      const int ch = i / kk, ii = i - ch * kk;
-      const int rr = cp[(size_t)ch * KMAX + ii];
-      if (rr >= 0) rows[cnt++] = rr;
-    }
-    nrows = cnt;
-  }
-  __syncthreads();
-  const int mp = nrows;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // the children's candidate rows in child order, the empty slots (-1)
+  // dropped: one entry per thread (fan * kmax <= PANEL_M = NTHR), all loads
+  // in flight at once, compacted by a ballot prefix count
+  static_assert(PANEL_M == NTHR, "one candidate per thread");
+  int rr = -1;
+  if (threadIdx.x < nch * kk) {
+    const int ch = threadIdx.x / kk, ii = threadIdx.x - ch * kk;
+    rr = cp[(size_t)ch * KMAX + ii];
+  }
+  const unsigned long long keep = __ballot(rr >= 0);
+  if (lane == 0) wcnt[wave] = __popcll(keep);
+  __syncthreads();
+  int off = 0;
+  for (int w = 0; w < wave; ++w) off += wcnt[w];
+  if (rr >= 0) rows[off + __popcll(keep & ((1ull << lane) - 1ull))] = rr;
+  const int mp = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+  __syncthreads();
   double y[NS][4];
 #pragma unroll
   for (int sl = 0; sl < NS; ++sl) {
@@ -203,41 +209,60 @@ __global__ __launch_bounds__(NTHR) void k_mv_check(int which, int n, Solve2D *S)
   constexpr int NC = KM / 16;                   // 16-column blocks of B
   constexpr int NK = KM / 4;                    // K steps
   __shared__ double rowmax[NTHR];
+  __shared__ double sinv[KM * KM];
   __shared__ double rv[4];
   __shared__ int rk[4];
   const int kk = s.k;
   const MvIO io = mv_io(which, s);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, g = lane >> 4;
+  // the inverse staged through LDS: every thread's loads in flight at once
+  // (indices below KM <= KMAX, so always inside the buffer), masked after
+  {
+    constexpr int PT = KM * KM / NTHR;
+    double tv[PT];
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int e = threadIdx.x + u * NTHR, r = e / KM, c = e - r * KM;
+      tv[u] = io.inv[r + c * KMAX];
+    }
+#pragma unroll
+    for (int u = 0; u < PT; ++u) {
+      const int e = threadIdx.x + u * NTHR, r = e / KM, c = e - r * KM;
+      sinv[e] = (r < kk && c < kk) ? tv[u] : 0.0;
+    }
+  }
+  __syncthreads();
   float binv[NK][NC];
 #pragma unroll
   for (int kb = 0; kb < NK; ++kb)
 #pragma unroll
-    for (int cb = 0; cb < NC; ++cb) {
-      const int r = 4 * kb + g, c = 16 * cb + li;
-      binv[kb][cb] = (r < kk && c < kk) ? (float)io.inv[r + c * KMAX] : 0.0f;
-    }
+    for (int cb = 0; cb < NC; ++cb) binv[kb][cb] = (float)sinv[(4 * kb + g) * KM + 16 * cb + li];
   const int rw0 = blockIdx.x * NTHR + 64 * wave + li;   // + 16 rb
   f4 acc[4][NC];
 #pragma unroll
   for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
     for (int cb = 0; cb < NC; ++cb) acc[rb][cb] = (f4){0.0f, 0.0f, 0.0f, 0.0f};
+  // every load of the block first (one memory latency per workgroup), then
+  // the matrix-core steps
+  float a[NK][4];
 #pragma unroll
   for (int kb = 0; kb < NK; ++kb) {
     const int col = 4 * kb + g;
-    float a[4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
       const int row = rw0 + 16 * rb;
-      a[rb] = (row < n && col < kk) ? io.Qf[row + (long)col * io.ld] : 0.0f;
+      a[kb][rb] = (row < n && col < kk) ? io.Qf[row + (long)col * io.ld] : 0.0f;
     }
+  }
+#pragma unroll
+  for (int kb = 0; kb < NK; ++kb)
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
       for (int cb = 0; cb < NC; ++cb)
-        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rb], binv[kb][cb], acc[rb][cb], 0, 0, 0);
-  }
+        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kb][rb], binv[kb][cb], acc[rb][cb], 0, 0, 0);
   // largest |B| of each row: over the column blocks in the lane, then over
   // the 16 lanes (one DPP row) that hold the row's columns; lane 15 of the
   // DPP row ends with the row's value

@@ -132,7 +132,7 @@ typedef double wy_d4 __attribute__((ext_vector_type(4)));
 // LDS doubles that hh_apply_wy needs for rank bucket KM: a 64-row chunk of V
 // (later the Gram matrix) and the KM x KM block Y (later Z, then M).
 template <int KM>
-constexpr int wy_lds() { return (64 + KM) * (KM + 1); }
+constexpr int wy_lds() { return (64 + KM) * (KM + 1) + KM; }
 
 // Entry (i, a) of the reflector matrix: zero above the diagonal and for
 // a >= kr, one on it (also on the zero rows that pad a panel of m < k rows),
@@ -162,6 +162,7 @@ __device__ void hh_apply_wy(double (&y)[NS][4], int m, int kr, int kk, const dou
   constexpr int TPW = (NTT + 3) / 4;   // Gram / Z tiles per wave
   double *sV = lds;                    // [64][LD] chunk of V, then G [KM][LD]
   double *sY = lds + 64 * LD;          // [KM][LD] Y, then Z, then M
+  double *stau = sY + KM * LD;         // [KM] the reflectors' tau
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, g = lane >> 4;
   // the thread's share of V, all loads in flight at once: rows lane + 64 q,
@@ -171,11 +172,23 @@ __device__ void hh_apply_wy(double (&y)[NS][4], int m, int kr, int kk, const dou
   for (int u = 0; u < NS; ++u)
 #pragma unroll
     for (int q = 0; q < 4; ++q) vr[u][q] = wy_v(V, ldv, m, kr, lane + 64 * q, wave + 4 * u);
-  for (int e = tid; e < KM * KM; e += NTHR) {
-    const int r = e / KM, c = e - r * KM;
-    double v = 0.0;
-    if (r < kk && c < kk) v = Y ? Y[r + (long)c * ldy] : (r == c ? 1.0 : 0.0);
-    sY[r * LD + c] = v;
+  // Y and tau to LDS, every load in flight at once (r, c < KM <= the Y
+  // block's KMAX rows and columns, so the unmasked loads stay inside it)
+  {
+    constexpr int PY = KM * KM / NTHR;
+    double yv[PY];
+#pragma unroll
+    for (int u = 0; u < PY; ++u) {
+      const int e = tid + u * NTHR, r = e / KM, c = e - r * KM;
+      yv[u] = Y ? Y[r + (long)c * ldy] : (r == c ? 1.0 : 0.0);
+    }
+    const double tv = (tid < kr) ? tau[tid] : 0.0;
+#pragma unroll
+    for (int u = 0; u < PY; ++u) {
+      const int e = tid + u * NTHR, r = e / KM, c = e - r * KM;
+      sY[r * LD + c] = (r < kk && c < kk) ? yv[u] : 0.0;
+    }
+    if (tid < KM) stau[tid] = tv;
   }
   wy_d4 gacc[TPW], zacc[TPW];
 #pragma unroll
@@ -244,7 +257,7 @@ __device__ void hh_apply_wy(double (&y)[NS][4], int m, int kr, int kk, const dou
           double acc = 0.0;
 #pragma unroll
           for (int ll = jj + 1; ll < 16; ++ll) acc += sV[j * LD + j0 + ll] * mb[ll];
-          v = tau[j] * (sY[j * LD + lane] - acc);
+          v = stau[j] * (sY[j * LD + lane] - acc);
           sY[j * LD + lane] = v;
         }
         mb[jj] = v;
@@ -259,17 +272,16 @@ __device__ void hh_apply_wy(double (&y)[NS][4], int m, int kr, int kk, const dou
     }
     __syncthreads();
   }
-  // y = [Y; 0] - V M  (columns >= kk of M are zero)
+  // y = [Y; 0] - V M  (columns >= kk of M are zero).  Y has kk <= 64 rows,
+  // all in the first row slot; lane, c < KMAX stay inside the Y block, so
+  // the loads go unmasked and all at once.
 #pragma unroll
   for (int sl = 0; sl < NS; ++sl) {
     const int c = wave + 4 * sl;
+    const double yv = Y ? Y[lane + (long)c * ldy] : (lane == c ? 1.0 : 0.0);
+    y[sl][0] = (c < kk && lane < kk) ? yv : 0.0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = lane + 64 * q;
-      double v = 0.0;
-      if (c < kk && i < kk) v = Y ? Y[i + (long)c * ldy] : (i == c ? 1.0 : 0.0);
-      y[sl][q] = v;
-    }
+    for (int q = 1; q < 4; ++q) y[sl][q] = 0.0;
   }
   for (int a0 = 0; a0 < kr; a0 += 4) {
     double v[4][4];
