@@ -38,9 +38,24 @@ __global__ __launch_bounds__(NTHR) void k_factors(Solve2D *S) {
   const long ld = z ? s.ldv : s.ldu;
   const int rows = z ? s.m : s.n;
   if (blockIdx.x * NTHR >= rows) return;
-  for (int j = threadIdx.x >> 6; j < kk; j += 4)
-    for (int c = threadIdx.x & 63; c < kk; c += 64)
-      M[j * KMAX + c] = z ? s.Z[j + c * KMAX] : s.W[j + c * KMAX] * s.sig[c];
+  // rows j < KM of M, every thread's loads in flight at once (j, c < KMAX
+  // stay inside the buffers), entries past k zero
+  {
+    constexpr int PM = KM * KMAX / NTHR;
+    const double *src = z ? s.Z : s.W;
+    double tv[PM], sg[PM];
+#pragma unroll
+    for (int u = 0; u < PM; ++u) {
+      const int e = threadIdx.x + u * NTHR, j = e / KMAX, c = e - j * KMAX;
+      tv[u] = src[j + c * KMAX];
+      sg[u] = s.sig[c];
+    }
+#pragma unroll
+    for (int u = 0; u < PM; ++u) {
+      const int e = threadIdx.x + u * NTHR, j = e / KMAX, c = e - j * KMAX;
+      M[e] = (j < kk && c < kk) ? (z ? tv[u] : tv[u] * sg[u]) : 0.0;
+    }
+  }
   __syncthreads();
   const int i = blockIdx.x * NTHR + threadIdx.x;
   if (i >= rows) return;
@@ -164,8 +179,21 @@ __global__ __launch_bounds__(NTHR) void k_change_norms(Solve2D *S) {
   __shared__ double red[2][4];
   const int kk = s.k, kq = s.kp;
   if (blockIdx.x * NTHR >= max(s.n, s.m)) return;
-  for (int e = threadIdx.x; e < KMAX * KMAX; e += NTHR) M[e] = s.Mc[e];
-  for (int a = threadIdx.x; a < kq; a += NTHR) sp2[a] = s.sigp[a] * s.sigp[a];
+  // rows a < KM of M = Bp^T B, every thread's loads in flight at once
+  // (inside the KMAX x KMAX buffer), entries past kp x k zero
+  {
+    constexpr int PM = KM * KMAX / NTHR;
+    double tv[PM];
+#pragma unroll
+    for (int u = 0; u < PM; ++u) tv[u] = s.Mc[threadIdx.x + u * NTHR];
+    const double sv = s.sigp[threadIdx.x & (KMAX - 1)];
+#pragma unroll
+    for (int u = 0; u < PM; ++u) {
+      const int e = threadIdx.x + u * NTHR, a = e / KMAX, c = e - a * KMAX;
+      M[e] = (a < kq && c < kk) ? tv[u] : 0.0;
+    }
+    if (threadIdx.x < KMAX) sp2[threadIdx.x] = (threadIdx.x < kq) ? sv * sv : 0.0;
+  }
   __syncthreads();
   const int i = blockIdx.x * NTHR + threadIdx.x;
   double n1 = 0.0, n2 = 0.0;
@@ -311,11 +339,24 @@ __global__ __launch_bounds__(NTHR) void k_growth_score(Solve2D *S) {
   __shared__ int rk[4];
   const int kk = s.k, r = s.r, nq = min(s.kick, PQ);
   const long ldu = s.ldu, ldv = s.ldv;
-  for (int e = threadIdx.x; e < nq * KMAX; e += NTHR) {
-    const int q = e / KMAX, c = e - q * KMAX;
-    const int p = clamp_row(s.probe[q], s.n);
-    uP[e] = (c < r) ? s.Uh[p + (long)c * ldu] : 0.0;
-    aP[e] = (c < kk) ? s.A[p + (long)c * ldu] : 0.0;
+  // probe rows of Uh and A, every thread's loads in flight at once (rows
+  // clamped into [0, n), columns < KMAX), masked after
+  {
+    constexpr int PP = PQ * KMAX / NTHR;
+    double tu[PP], ta[PP];
+#pragma unroll
+    for (int u = 0; u < PP; ++u) {
+      const int e = threadIdx.x + u * NTHR, q = e / KMAX, c = e - q * KMAX;
+      const int p = clamp_row(s.probe[q < nq ? q : 0], s.n);
+      tu[u] = s.Uh[p + (long)c * ldu];
+      ta[u] = s.A[p + (long)c * ldu];
+    }
+#pragma unroll
+    for (int u = 0; u < PP; ++u) {
+      const int e = threadIdx.x + u * NTHR, q = e / KMAX, c = e - q * KMAX;
+      uP[e] = (q < nq && c < r) ? tu[u] : 0.0;
+      aP[e] = (q < nq && c < kk) ? ta[u] : 0.0;
+    }
   }
   for (int q = threadIdx.x; q < nq; q += NTHR) lP[q] = s.lam_r[clamp_row(s.probe[q], s.n)];
   for (int t = threadIdx.x; t < kk; t += NTHR) jn[t] = s.Jn[t];
@@ -326,15 +367,28 @@ __global__ __launch_bounds__(NTHR) void k_growth_score(Solve2D *S) {
     double num[PQ], skel[PQ];
 #pragma unroll
     for (int q = 0; q < PQ; ++q) num[q] = skel[q] = 0.0;
-    for (int c = 0; c < r; ++c) {
-      const double vc = s.Vh[j + (long)c * ldv];
+    // eight column loads in flight per step
+    for (int c0 = 0; c0 < r; c0 += 8) {
+      double vc[8];
 #pragma unroll
-      for (int q = 0; q < PQ; ++q) num[q] += uP[q * KMAX + c] * vc;
+      for (int t = 0; t < 8; ++t) vc[t] = (c0 + t < r) ? s.Vh[j + (long)(c0 + t) * ldv] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (c0 + t >= r) break;
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) num[q] += uP[q * KMAX + c0 + t] * vc[t];
+      }
     }
-    for (int c = 0; c < kk; ++c) {
-      const double bc = s.B[j + (long)c * ldv];
+    for (int c0 = 0; c0 < kk; c0 += 8) {
+      double bc[8];
 #pragma unroll
-      for (int q = 0; q < PQ; ++q) skel[q] += aP[q * KMAX + c] * bc;
+      for (int t = 0; t < 8; ++t) bc[t] = (c0 + t < kk) ? s.B[j + (long)(c0 + t) * ldv] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        if (c0 + t >= kk) break;
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) skel[q] += aP[q * KMAX + c0 + t] * bc[t];
+      }
     }
     const double lj = s.lam_c[j];
     best = 0.0;

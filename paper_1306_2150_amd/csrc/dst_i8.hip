@@ -89,27 +89,39 @@ __global__ __launch_bounds__(NTHR) void k_x_slices(int n, int hpad, const DstCol
   if (c >= ncols) return;
   const double *x = cols[c].src;
   const int N = n + 1, H0 = (n + 1) / 2, H1 = n / 2;
-  // parity values at point k (1-based), k <= H0
-  auto fold = [&](int k, double &u, double &w) {
-    const double a = x[k - 1];
-    if (2 * k < N) {
-      const double b = x[N - k - 1];
-      u = a + b;
-      w = a - b;
-    } else {
-      u = a;          // the middle point of an even N
-      w = 0.0;
+  // parity values at points k = k0 + t NTHR (1-based) for t < FP, all loads
+  // in flight at once: indices are clamped into the column (k <= H0, so
+  // N - k - 1 >= 0) and the values past H0 masked
+  constexpr int FP = 4;
+  auto fold4 = [&](int k0, double (&u)[FP], double (&w)[FP], bool &bad) {
+    double a[FP], b[FP];
+#pragma unroll
+    for (int t = 0; t < FP; ++t) {
+      const int k = min(k0 + t * NTHR, H0);
+      a[t] = x[k - 1];
+      b[t] = x[N - k - 1];
+    }
+#pragma unroll
+    for (int t = 0; t < FP; ++t) {
+      const int k = k0 + t * NTHR;
+      const bool in = k <= H0, pair = 2 * k < N;   // pair: not the middle point
+      if (in && (!isfinite(a[t]) || (pair && !isfinite(b[t])))) bad = true;
+      u[t] = in ? (pair ? a[t] + b[t] : a[t]) : 0.0;
+      w[t] = (in && pair) ? a[t] - b[t] : 0.0;
     }
   };
+  // every entry of x is read by the fold (x[k-1] for k <= H0, x[N-k-1] for
+  // 2k < N), which also finds the non-finite ones
   double mu = 0.0, mw = 0.0;
   bool bad = false;
-  for (int k = threadIdx.x; k < n; k += NTHR)
-    if (!isfinite(x[k])) bad = true;
-  for (int k = threadIdx.x + 1; k <= H0; k += NTHR) {
-    double u, w;
-    fold(k, u, w);
-    mu = fmax(mu, fabs(u));
-    mw = fmax(mw, fabs(w));
+  for (int k0 = threadIdx.x + 1; k0 <= H0; k0 += FP * NTHR) {
+    double u[FP], w[FP];
+    fold4(k0, u, w, bad);
+#pragma unroll
+    for (int t = 0; t < FP; ++t) {
+      mu = fmax(mu, fabs(u[t]));
+      mw = fmax(mw, fabs(w[t]));
+    }
   }
   __shared__ double red[2][4];
   __shared__ int badw[4];
@@ -138,11 +150,18 @@ __global__ __launch_bounds__(NTHR) void k_x_slices(int n, int hpad, const DstCol
   __syncthreads();
   const int e0 = exs[0], e1 = exs[1];
   uint2 *o0 = out + (size_t)(2 * c) * hpad, *o1 = o0 + hpad;
-  for (int k = threadIdx.x + 1; k <= hpad; k += NTHR) {
-    double u = 0.0, w = 0.0;
-    if (k <= H0) fold(k, u, w);
-    o0[k - 1] = slice_record(u, e0);
-    o1[k - 1] = slice_record(k <= H1 ? w : 0.0, e1);
+  bool unused = false;
+  for (int k0 = threadIdx.x + 1; k0 <= hpad; k0 += FP * NTHR) {
+    double u[FP], w[FP];
+    fold4(k0, u, w, unused);
+#pragma unroll
+    for (int t = 0; t < FP; ++t) {
+      const int k = k0 + t * NTHR;
+      if (k <= hpad) {
+        o0[k - 1] = slice_record(u[t], e0);
+        o1[k - 1] = slice_record(k <= H1 ? w[t] : 0.0, e1);
+      }
+    }
   }
 }
 

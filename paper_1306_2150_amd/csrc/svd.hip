@@ -51,20 +51,48 @@ __global__ __launch_bounds__(core_threads<KM>()) void k_core(int phase, Solve2D 
   const int kk = s.k;
   if (kk > KM) return;            // the launch's bucket covers every k
   const int kp = (kk + 1) & ~1;   // even number of players
-  // stage InvC (in V); element e -> (e >> 6, e & 63)
-  for (int j = threadIdx.x >> 6; j < kk; j += NW)
-    for (int i = threadIdx.x & 63; i < kk; i += 64)
-      V[j * LD + i] = plain ? (i == j ? 1.0 : 0.0) : s.InvC[i + j * KMAX];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // stage InvC (in V): every thread's loads in flight at once (indices below
+  // KM <= KMAX stay inside the buffer), masked after
+  {
+    constexpr int PV = (KM * KM + NT - 1) / NT;
+    double tv[PV];
+#pragma unroll
+    for (int u = 0; u < PV; ++u) {
+      const int e = threadIdx.x + u * NT, j = e / KM, i = e - j * KM;
+      tv[u] = s.InvC[(e < KM * KM ? i + j * KMAX : 0)];
+    }
+#pragma unroll
+    for (int u = 0; u < PV; ++u) {
+      const int e = threadIdx.x + u * NT, j = e / KM, i = e - j * KM;
+      if (e < KM * KM) V[j * LD + i] = (i < kk && j < kk) ? (plain ? (i == j ? 1.0 : 0.0) : tv[u]) : 0.0;
+    }
+  }
+  // rows c = wv + NW t of Rfin, lane j holding Rfin[c][j] (one load per lane
+  // and row, all in flight before the products; c < KM and j < 64 stay
+  // inside the KMAX x KMAX buffer)
+  constexpr int NCW = (KM + NW - 1) / NW;
+  static_assert(NW * NCW <= KMAX, "rows of Rfin inside the buffer");
+  double rrow[NCW];
+#pragma unroll
+  for (int t = 0; t < NCW; ++t) {
+    const int c = wv + NW * t;
+    rrow[t] = s.Rfin[c + lane * KMAX];
+  }
   __syncthreads();
   // K[i][c] = sum_{j >= c} InvC[i][j] * Rfin[c][j]   (Rfin upper triangular;
-  // its entries are read from global memory, the same one by a whole wave)
-  for (int c = threadIdx.x >> 6; c < kp; c += NW)
-    for (int i = threadIdx.x & 63; i < kp; i += 64) {
+  // Rfin[c][j] broadcast from lane j)
+#pragma unroll
+  for (int t = 0; t < NCW; ++t) {
+    const int c = wv + NW * t;
+    if (c >= kp) break;
+    for (int i = lane; i < kp; i += 64) {
       double v = 0.0;
       if (i < kk && c < kk)
-        for (int j = c; j < kk; ++j) v += V[j * LD + i] * s.Rfin[c + j * KMAX];
+        for (int j = c; j < kk; ++j) v += V[j * LD + i] * readlane_f64(rrow[t], j);
       K[c * LD + i] = v;
     }
+  }
   __syncthreads();
   for (int c = threadIdx.x >> 6; c < kp; c += NW)
     for (int i = threadIdx.x & 63; i < kp; i += 64) V[c * LD + i] = (i == c) ? 1.0 : 0.0;
