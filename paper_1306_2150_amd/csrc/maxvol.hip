@@ -436,9 +436,18 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
     if (t < kk) {
       v = (t == c) ? 1.0 : 0.0;
     } else {
+      // eight column loads in flight per step (columns past k: row 0 of the
+      // panel, unused), the sum in column order
       v = 0.0;
       const int rr = clamp_row(rows[t], n);
-      for (int j = 0; j < kk; ++j) v += io.Q[rr + (long)j * io.ld] * inv[j * KM + c];
+      for (int j0 = 0; j0 < kk; j0 += 8) {
+        double q[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) q[u] = io.Q[(j0 + u < kk ? rr + (long)(j0 + u) * io.ld : 0)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (j0 + u < kk) v += q[u] * inv[(j0 + u) * KM + c];
+      }
     }
     Bm[e] = v;
   }
