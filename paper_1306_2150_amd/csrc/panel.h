@@ -42,49 +42,53 @@ __device__ __forceinline__ void panel_store(const double (&y)[NS][4], T *dst,
   }
 }
 
-// Column `s` of the register panel as 4 row slots (runtime s, unrolled
-// selects instead of dynamic register indexing).
-template <int NS>
-__device__ __forceinline__ void col_get(const double (&y)[NS][4], int s, double (&x)[4]) {
+// wave_sum of N values, stage by stage, so that the N reduction chains
+// overlap (each value takes the same steps in the same order as wave_sum).
+template <int N>
+__device__ __forceinline__ void wave_sum_n(double (&v)[N]) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) x[q] = y[0][q];
+  for (int g = 0; g < N; ++g) v[g] += dpp_f64<DPP_QUAD_1032>(v[g]);
 #pragma unroll
-  for (int s2 = 1; s2 < NS; ++s2)
+  for (int g = 0; g < N; ++g) v[g] += dpp_f64<DPP_QUAD_2301>(v[g]);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) x[q] = (s2 == s) ? y[s2][q] : x[q];
-}
-template <int NS>
-__device__ __forceinline__ void col_put(double (&y)[NS][4], int s, const double (&x)[4]) {
+  for (int g = 0; g < N; ++g) v[g] += dpp_f64<DPP_ROW_SHR4>(v[g]);
 #pragma unroll
-  for (int s2 = 0; s2 < NS; ++s2)
+  for (int g = 0; g < N; ++g) v[g] += dpp_f64<DPP_ROW_SHR8>(v[g]);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) y[s2][q] = (s2 == s) ? x[q] : y[s2][q];
+  for (int g = 0; g < N; ++g) v[g] += dpp_rows_f64<DPP_ROW_BCAST15, 0xa>(v[g]);
+#pragma unroll
+  for (int g = 0; g < N; ++g) v[g] += dpp_rows_f64<DPP_ROW_BCAST31, 0xc>(v[g]);
+#pragma unroll
+  for (int g = 0; g < N; ++g) v[g] = readlane_f64(v[g], 63);
 }
 
-// Householder QR of the mp x kk panel (mp <= 256, kk <= 4 NS <= 64), LAPACK
-// convention: H_j = I - tau_j v_j v_j^T, v_j(j) = 1, beta = -sign(alpha)||x||,
-// tau = 0 when the part below the diagonal is already zero.  On return the
-// panel holds R on and above the diagonal and v_j below it; taus[j] in LDS.
-// vbuf: 2*256 doubles of LDS.
-template <int NS>
-__device__ void hh_qr_regs(double (&y)[NS][4], int mp, int kk, double *vbuf,
-                           double *taus) {
+// Columns j = 4 S .. 4 S + 3 of the Householder QR below: column j lives in
+// slot S of wave j - 4 S, so the slot index is a compile-time constant, and
+// the trailing columns are the later slots of every wave plus slot S of the
+// waves after the owner.
+template <int NS, int S>
+__device__ __forceinline__ void hh_qr_slot(double (&y)[NS][4], int mp, int kk, int jmax,
+                                           double *vbuf, double *taus) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int jmax = min(mp, kk);
-  for (int j = 0; j < jmax; ++j) {
-    const int w = j & 3, s = j >> 2;
+  // trailing slots reduced G at a time, their reduction chains overlapping
+  // (pays off once a wave holds 8 or more columns)
+  constexpr int G = NS >= 8 ? 2 : 1;
+  // kept rolled: the slots are already unrolled, and four copies of each
+  // would double the code for no measured gain
+#pragma unroll 1
+  for (int w = 0; w < 4; ++w) {
+    const int j = 4 * S + w;
+    if (j >= jmax) return;
     double *vb = vbuf + (j & 1) * PANEL_M;
     if (wave == w) {
-      double x[4];
-      col_get(y, s, x);
       double ss = 0.0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = lane + 64 * q;
-        if (i > j && i < mp) ss += x[q] * x[q];
+        if (i > j && i < mp) ss += y[S][q] * y[S][q];
       }
       ss = wave_sum(ss);
-      const double alpha = bcast_f64(x[0], j);   // j < 64: row j in slot 0
+      const double alpha = bcast_f64(y[S][0], j);   // j < 64: row j in slot 0
       double tj = 0.0, beta = alpha, scale = 0.0;
       if (ss != 0.0) {
         beta = -copysign(sqrt(alpha * alpha + ss), alpha);
@@ -97,14 +101,13 @@ __device__ void hh_qr_regs(double (&y)[NS][4], int mp, int kk, double *vbuf,
         double v = 0.0;
         if (i == j) {
           v = 1.0;
-          x[q] = beta;
+          y[S][q] = beta;
         } else if (i > j && i < mp) {
-          x[q] *= scale;
-          v = x[q];
+          y[S][q] *= scale;
+          v = y[S][q];
         }
         vb[i] = v;
       }
-      col_put(y, s, x);
       if (lane == 0) taus[j] = tj;
     }
     __syncthreads();
@@ -113,18 +116,59 @@ __device__ void hh_qr_regs(double (&y)[NS][4], int mp, int kk, double *vbuf,
 #pragma unroll
     for (int q = 0; q < 4; ++q) vv[q] = vb[lane + 64 * q];
 #pragma unroll
-    for (int s2 = 0; s2 < NS; ++s2) {
-      const int c = wave + 4 * s2;
-      if (c > j && c < kk) {
-        double d = 0.0;
+    for (int s0 = S; s0 < NS; s0 += G) {
+      // the group's first column is wave + 4 s0, its last wave + 4 (s0 + G - 1)
+      const bool any = ((s0 + G - 1 < NS ? s0 + G - 1 : NS - 1) > S || wave > w) &&
+                       wave + 4 * s0 < kk;
+      if (any) {
+        double d[G];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) d += vv[q] * y[s2][q];
-        d = wave_sum(d) * tj;
+        for (int g = 0; g < G; ++g) {
+          d[g] = 0.0;
+          if (s0 + g < NS) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) y[s2][q] -= d * vv[q];
+            for (int q = 0; q < 4; ++q) d[g] += vv[q] * y[s0 + g][q];
+          }
+        }
+        wave_sum_n(d);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const int s2 = s0 + g, c = wave + 4 * s2;
+          if (s2 < NS && (s2 > S || wave > w) && c < kk) {
+            const double f = d[g] * tj;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) y[s2][q] -= f * vv[q];
+          }
+        }
       }
     }
   }
+}
+
+template <int NS, int S>
+struct HhQrSlots {
+  static __device__ __forceinline__ void run(double (&y)[NS][4], int mp, int kk, int jmax,
+                                             double *vbuf, double *taus) {
+    if (4 * S >= jmax) return;
+    hh_qr_slot<NS, S>(y, mp, kk, jmax, vbuf, taus);
+    HhQrSlots<NS, S + 1>::run(y, mp, kk, jmax, vbuf, taus);
+  }
+};
+template <int NS>
+struct HhQrSlots<NS, NS> {
+  static __device__ __forceinline__ void run(double (&)[NS][4], int, int, int, double *,
+                                             double *) {}
+};
+
+// Householder QR of the mp x kk panel (mp <= 256, kk <= 4 NS <= 64), LAPACK
+// convention: H_j = I - tau_j v_j v_j^T, v_j(j) = 1, beta = -sign(alpha)||x||,
+// tau = 0 when the part below the diagonal is already zero.  On return the
+// panel holds R on and above the diagonal and v_j below it; taus[j] in LDS.
+// vbuf: 2*256 doubles of LDS.
+template <int NS>
+__device__ __forceinline__ void hh_qr_regs(double (&y)[NS][4], int mp, int kk, double *vbuf,
+                           double *taus) {
+  HhQrSlots<NS, 0>::run(y, mp, kk, min(mp, kk), vbuf, taus);
 }
 
 typedef double wy_d4 __attribute__((ext_vector_type(4)));
@@ -306,30 +350,28 @@ __device__ __forceinline__ double pick4(double a, double b, double c, double d, 
   return q == 0 ? a : (q == 1 ? b : (q == 2 ? c : d));
 }
 
-// Gaussian elimination with partial pivoting that only selects rows: rows are
-// never moved, chosen ones are flagged.  piv_out[j] = local row of pivot j
-// (j < min(mp, kk)).  A zero column picks the lowest unflagged row and
-// eliminates nothing.  Ties in |value| go to the lowest row.
-// lbuf: 2*256 doubles of LDS; sh_piv: int[2] of LDS.
-template <int NS>
-__device__ void gepp_select_regs(double (&y)[NS][4], int mp, int kk,
-                                 double *lbuf, int *sh_piv, int *piv_out) {
+// Columns j = 4 S .. 4 S + 3 of the pivot selection below (column j in slot
+// S of wave j - 4 S, the slot index a compile-time constant).
+template <int NS, int S>
+__device__ __forceinline__ void gepp_slot(double (&y)[NS][4], int mp, int kk, int jmax,
+                                          unsigned &used, double *lbuf, int *sh_piv,
+                                          int *piv_out) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int jmax = min(mp, kk);
-  unsigned used = 0;   // bit q: row lane + 64 q already a pivot
-  for (int j = 0; j < jmax; ++j) {
-    const int w = j & 3, s = j >> 2;
+  // kept rolled: the slots are already unrolled, and four copies of each
+  // would double the code for no measured gain
+#pragma unroll 1
+  for (int w = 0; w < 4; ++w) {
+    const int j = 4 * S + w;
+    if (j >= jmax) return;
     double *lb = lbuf + (j & 1) * PANEL_M;
     if (wave == w) {
-      double x[4];
-      col_get(y, s, x);
       double best = -1.0;
       int key = 0x7fffffff;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = lane + 64 * q;
         if (i < mp && !((used >> q) & 1u)) {
-          const double a = fabs(x[q]);
+          const double a = fabs(y[S][q]);
           if (a > best || (a == best && i < key)) {
             best = a;
             key = i;
@@ -338,14 +380,14 @@ __device__ void gepp_select_regs(double (&y)[NS][4], int mp, int kk,
       }
       wave_argmax(best, key);
       const int p = key;
-      const double pv = pick4(bcast_f64(x[0], p & 63), bcast_f64(x[1], p & 63),
-                              bcast_f64(x[2], p & 63), bcast_f64(x[3], p & 63),
+      const double pv = pick4(bcast_f64(y[S][0], p & 63), bcast_f64(y[S][1], p & 63),
+                              bcast_f64(y[S][2], p & 63), bcast_f64(y[S][3], p & 63),
                               p >> 6);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = lane + 64 * q;
         double l = 0.0;
-        if (i < mp && i != p && !((used >> q) & 1u) && pv != 0.0) l = x[q] / pv;
+        if (i < mp && i != p && !((used >> q) & 1u) && pv != 0.0) l = y[S][q] / pv;
         lb[i] = l;
       }
       if (lane == 0) sh_piv[j & 1] = p;
@@ -358,10 +400,11 @@ __device__ void gepp_select_regs(double (&y)[NS][4], int mp, int kk,
     double ll[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) ll[q] = lb[lane + 64 * q];
+    // trailing columns: the later slots, and slot S of the waves after w
 #pragma unroll
-    for (int s2 = 0; s2 < NS; ++s2) {
+    for (int s2 = S; s2 < NS; ++s2) {
       const int c = wave + 4 * s2;
-      if (c > j && c < kk) {
+      if ((s2 > S || wave > w) && c < kk) {
         // shuffle every row slot first, then choose: a select over the
         // register array itself would be turned into a scratch-memory index
         const double u = pick4(bcast_f64(y[s2][0], pl), bcast_f64(y[s2][1], pl),
@@ -371,6 +414,34 @@ __device__ void gepp_select_regs(double (&y)[NS][4], int mp, int kk,
       }
     }
   }
+}
+
+template <int NS, int S>
+struct GeppSlots {
+  static __device__ __forceinline__ void run(double (&y)[NS][4], int mp, int kk, int jmax,
+                                             unsigned &used, double *lbuf, int *sh_piv,
+                                             int *piv_out) {
+    if (4 * S >= jmax) return;
+    gepp_slot<NS, S>(y, mp, kk, jmax, used, lbuf, sh_piv, piv_out);
+    GeppSlots<NS, S + 1>::run(y, mp, kk, jmax, used, lbuf, sh_piv, piv_out);
+  }
+};
+template <int NS>
+struct GeppSlots<NS, NS> {
+  static __device__ __forceinline__ void run(double (&)[NS][4], int, int, int, unsigned &,
+                                             double *, int *, int *) {}
+};
+
+// Gaussian elimination with partial pivoting that only selects rows: rows are
+// never moved, chosen ones are flagged.  piv_out[j] = local row of pivot j
+// (j < min(mp, kk)).  A zero column picks the lowest unflagged row and
+// eliminates nothing.  Ties in |value| go to the lowest row.
+// lbuf: 2*256 doubles of LDS; sh_piv: int[2] of LDS.
+template <int NS>
+__device__ __forceinline__ void gepp_select_regs(double (&y)[NS][4], int mp, int kk,
+                                 double *lbuf, int *sh_piv, int *piv_out) {
+  unsigned used = 0;   // bit q: row lane + 64 q already a pivot
+  GeppSlots<NS, 0>::run(y, mp, kk, min(mp, kk), used, lbuf, sh_piv, piv_out);
 }
 
 }  // namespace lrp
