@@ -164,10 +164,13 @@ constexpr int DPP_ROW_SHR8 = 0x118;
 constexpr int DPP_ROW_BCAST15 = 0x142;   // lane 15 of a row -> next row
 constexpr int DPP_ROW_BCAST31 = 0x143;   // lane 31 -> rows 2 and 3
 
+// Row broadcast into the rows of ROWS; the lanes of the other rows are left
+// undefined (no zero fill), which the wave sums allow: they read only lane
+// 63, whose inputs come from written rows only.
 template <int CTRL, int ROWS>
 __device__ __forceinline__ double dpp_rows_f64(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, ROWS, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, ROWS, 0xf, false);
   return __hiloint2double(hi, lo);
 }
 
