@@ -16,13 +16,18 @@
 namespace lrp {
 namespace {
 
-// Sum over one 16-lane DPP row; every lane of the row gets the total.
-__device__ __forceinline__ double row_sum16(double v) {
-  v += dpp_f64<0x128>(v);   // row_ror:8
-  v += dpp_f64<0x124>(v);   // row_ror:4
-  v += dpp_f64<0x122>(v);   // row_ror:2
-  v += dpp_f64<0x121>(v);   // row_ror:1
-  return v;
+// Sums over each row of 16 lanes (every lane of the row gets its row's sum)
+// of N values, stage by stage so that their chains overlap.
+template <int N>
+__device__ __forceinline__ void row_sum16_n(double (&v)[N]) {
+#pragma unroll
+  for (int g = 0; g < N; ++g) v[g] += dpp_f64<0x128>(v[g]);
+#pragma unroll
+  for (int g = 0; g < N; ++g) v[g] += dpp_f64<0x124>(v[g]);
+#pragma unroll
+  for (int g = 0; g < N; ++g) v[g] += dpp_f64<0x122>(v[g]);
+#pragma unroll
+  for (int g = 0; g < N; ++g) v[g] += dpp_f64<0x121>(v[g]);
 }
 
 // phase ACT_SWEEP: K = InvC Rfin^T (the cross core); phase ACT_CORE (3D
@@ -111,29 +116,47 @@ __global__ __launch_bounds__(core_threads<KM>()) void k_core(int phase, Solve2D 
         const int pa = pr, pb = kp - 1 - pr;
         const int a = live ? ((pa == 0) ? 0 : 1 + (pa - 1 + st) % (kp - 1)) : 0;
         const int b = live ? 1 + (pb - 1 + st) % (kp - 1) : 0;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        if (live)
-          for (int i = gl; i < kp; i += 16) {
-            const double x = K[a * LD + i], y = K[b * LD + i];
-            al += x * x;
-            be += y * y;
-            ga += x * y;
+        // the pair's column entries gl, gl + 16, ... below kp (KM / 16 at
+        // most, loaded together, then masked)
+        constexpr int NI = (KM + 15) / 16;
+        double xa[NI], xb[NI];
+#pragma unroll
+        for (int u = 0; u < NI; ++u) {
+          const int i = min(gl + 16 * u, KM - 1);
+          xa[u] = K[a * LD + i];
+          xb[u] = K[b * LD + i];
+        }
+        double sums[3] = {0.0, 0.0, 0.0};   // al, be, ga
+#pragma unroll
+        for (int u = 0; u < NI; ++u)
+          if (live && gl + 16 * u < kp) {
+            sums[0] += xa[u] * xa[u];
+            sums[1] += xb[u] * xb[u];
+            sums[2] += xa[u] * xb[u];
           }
-        al = row_sum16(al);
-        be = row_sum16(be);
-        ga = row_sum16(ga);
+        row_sum16_n(sums);
+        const double al = sums[0], be = sums[1], ga = sums[2];
         if (live && al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be)) {
           const double zeta = (be - al) / (2.0 * ga);
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) /
                            (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-          for (int i = gl; i < kp; i += 16) {
-            const double x = K[a * LD + i], y = K[b * LD + i];
-            K[a * LD + i] = cs * x - sn * y;
-            K[b * LD + i] = sn * x + cs * y;
-            const double u = V[a * LD + i], w = V[b * LD + i];
-            V[a * LD + i] = cs * u - sn * w;
-            V[b * LD + i] = sn * u + cs * w;
+          double va[NI], vb[NI];
+#pragma unroll
+          for (int u = 0; u < NI; ++u) {
+            const int i = min(gl + 16 * u, KM - 1);
+            va[u] = V[a * LD + i];
+            vb[u] = V[b * LD + i];
+          }
+#pragma unroll
+          for (int u = 0; u < NI; ++u) {
+            const int i = gl + 16 * u;
+            if (i < kp) {
+              K[a * LD + i] = cs * xa[u] - sn * xb[u];
+              K[b * LD + i] = sn * xa[u] + cs * xb[u];
+              V[a * LD + i] = cs * va[u] - sn * vb[u];
+              V[b * LD + i] = sn * va[u] + cs * vb[u];
+            }
           }
           if (gl == 0) rot = 1;
         }
