@@ -234,12 +234,22 @@ __device__ void hh_apply_wy(double (&y)[NS][4], int m, int kr, int kk, const dou
     }
     if (tid < KM) stau[tid] = tv;
   }
-  wy_d4 gacc[TPW], zacc[TPW];
+  // Gram tiles: only ta <= tb (the solve below reads G above its diagonal);
+  // Z = V^T [Y; 0] tiles: all of them
+  constexpr int NTG = NT * (NT + 1) / 2, TPG = (NTG + 3) / 4;
+  int gta[TPG], gtb[TPG];
 #pragma unroll
-  for (int u = 0; u < TPW; ++u) {
-    gacc[u] = (wy_d4){0.0, 0.0, 0.0, 0.0};
-    zacc[u] = (wy_d4){0.0, 0.0, 0.0, 0.0};
+  for (int u = 0; u < TPG; ++u) {
+    int ta = 0, rem = wave + 4 * u;
+    while (ta < NT - 1 && rem >= NT - ta) rem -= NT - ta++;
+    gta[u] = ta;
+    gtb[u] = ta + rem;
   }
+  wy_d4 gacc[TPG], zacc[TPW];
+#pragma unroll
+  for (int u = 0; u < TPG; ++u) gacc[u] = (wy_d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) zacc[u] = (wy_d4){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     if (64 * q >= m) break;
@@ -248,10 +258,9 @@ __device__ void hh_apply_wy(double (&y)[NS][4], int m, int kr, int kk, const dou
     for (int u = 0; u < NS; ++u) sV[lane * LD + wave + 4 * u] = vr[u][q];
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < TPW; ++u) {
-      const int t = wave + 4 * u;
-      if (t < NTT) {
-        const int ta = t / NT, tb = t - ta * NT;
+    for (int u = 0; u < TPG; ++u) {
+      if (wave + 4 * u < NTG) {
+        const int ta = gta[u], tb = gtb[u];
         // A[i][k] = V(row 4 ks + k, col 16 ta + i): lane i + 16 k; B likewise
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks) {
@@ -259,7 +268,14 @@ __device__ void hh_apply_wy(double (&y)[NS][4], int m, int kr, int kk, const dou
           const double b = sV[(4 * ks + g) * LD + 16 * tb + li];
           gacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, gacc[u], 0, 0, 0);
         }
-        if (q == 0) {
+      }
+    }
+    if (q == 0) {
+#pragma unroll
+      for (int u = 0; u < TPW; ++u) {
+        const int t = wave + 4 * u;
+        if (t < NTT) {
+          const int ta = t / NT, tb = t - ta * NT;
 #pragma unroll
           for (int ks = 0; ks < KM / 4; ++ks) {
             const double a = sV[(4 * ks + g) * LD + 16 * ta + li];
@@ -273,16 +289,20 @@ __device__ void hh_apply_wy(double (&y)[NS][4], int m, int kr, int kk, const dou
   __syncthreads();
   // D[i][j]: lane j + 16 (i % 4), register i / 4
 #pragma unroll
+  for (int u = 0; u < TPG; ++u) {
+    if (wave + 4 * u < NTG) {
+      const int ta = gta[u], tb = gtb[u];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sV[(16 * ta + 4 * r + g) * LD + 16 * tb + li] = gacc[u][r];
+    }
+  }
+#pragma unroll
   for (int u = 0; u < TPW; ++u) {
     const int t = wave + 4 * u;
     if (t < NTT) {
       const int ta = t / NT, tb = t - ta * NT;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int e = (16 * ta + 4 * r + g) * LD + 16 * tb + li;
-        sV[e] = gacc[u][r];
-        sY[e] = zacc[u][r];
-      }
+      for (int r = 0; r < 4; ++r) sY[(16 * ta + 4 * r + g) * LD + 16 * tb + li] = zacc[u][r];
     }
   }
   __syncthreads();
