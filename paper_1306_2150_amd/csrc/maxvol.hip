@@ -191,6 +191,16 @@ __global__ __launch_bounds__(NTHR) void k_mv_inv(int which, int n, int force,
     for (int c = cl; c < kk; c += 64) io.inv[t + c * KMAX] = a[pivrow[t]][kk + c];
 }
 
+// One DPP step of a lane-wise max over 16 values (non-negative floats; lanes
+// shifted in from outside the row read 0).
+template <int CTRL>
+__device__ __forceinline__ void row_max16_f32(float (&v)[16]) {
+#pragma unroll
+  for (int e = 0; e < 16; ++e)
+    v[e] = fmaxf(v[e], __int_as_float(__builtin_amdgcn_update_dpp(
+                           0, __float_as_int(v[e]), CTRL, 0xf, 0xf, true)));
+}
+
 // ---- per block: rows of B = Q Inv, report the MV_TOP largest rows > tau.
 // The check only selects candidates: the swap loop recomputes every
 // reported row in float64 and swaps only on those values, so B is formed
@@ -265,20 +275,24 @@ __global__ __launch_bounds__(NTHR) void k_mv_check(int which, int n, Solve2D *S)
         acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kb][rb], binv[kb][cb], acc[rb][cb], 0, 0, 0);
   // largest |B| of each row: over the column blocks in the lane, then over
   // the 16 lanes (one DPP row) that hold the row's columns; lane 15 of the
-  // DPP row ends with the row's value
+  // DPP row ends with the row's value.  The maxima are taken in float (exact)
+  // and all 16 rows' steps interleaved.
+  float vm[16];
 #pragma unroll
-  for (int rb = 0; rb < 4; ++rb)
+  for (int e = 0; e < 16; ++e) {
+    float v = 0.0f;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      double v = 0.0;
+    for (int cb = 0; cb < NC; ++cb) v = fmaxf(v, fabsf(acc[e >> 2][cb][e & 3]));
+    vm[e] = v;
+  }
+  row_max16_f32<DPP_QUAD_1032>(vm);
+  row_max16_f32<DPP_QUAD_2301>(vm);
+  row_max16_f32<DPP_ROW_SHR4>(vm);
+  row_max16_f32<DPP_ROW_SHR8>(vm);
+  if (li == 15) {
 #pragma unroll
-      for (int cb = 0; cb < NC; ++cb) v = fmax(v, (double)fabsf(acc[rb][cb][r]));
-      v = fmax(v, dpp_f64<DPP_QUAD_1032>(v));
-      v = fmax(v, dpp_f64<DPP_QUAD_2301>(v));
-      v = fmax(v, dpp_f64<DPP_ROW_SHR4>(v));
-      v = fmax(v, dpp_f64<DPP_ROW_SHR8>(v));
-      if (li == 15) rowmax[64 * wave + 16 * rb + 4 * g + r] = v;
-    }
+    for (int e = 0; e < 16; ++e) rowmax[64 * wave + 16 * (e >> 2) + 4 * g + (e & 3)] = (double)vm[e];
+  }
   __syncthreads();
   const int row = blockIdx.x * NTHR + threadIdx.x;
   double mx = -1.0;
