@@ -112,15 +112,37 @@ __global__ __launch_bounds__(NTHR) void k_x_slices(int n, int hpad, const DstCol
   };
   // every entry of x is read by the fold (x[k-1] for k <= H0, x[N-k-1] for
   // 2k < N), which also finds the non-finite ones
+  // Up to NCACHE passes (hpad <= 4096, n <= 8192) the folded values stay in
+  // registers for the slicing below, so the column is read once; past that
+  // the slicing folds the column again.
+  constexpr int NCACHE = 4;
+  const int npass = (max(hpad, H0) + FP * NTHR - 1) / (FP * NTHR);
+  const bool cached = npass <= NCACHE;
+  double cu[NCACHE][FP], cw[NCACHE][FP];
   double mu = 0.0, mw = 0.0;
   bool bad = false;
-  for (int k0 = threadIdx.x + 1; k0 <= H0; k0 += FP * NTHR) {
-    double u[FP], w[FP];
-    fold4(k0, u, w, bad);
+  if (cached) {
+    // points up to hpad: past H0 the fold gives zeros (no maxima, no flags)
 #pragma unroll
-    for (int t = 0; t < FP; ++t) {
-      mu = fmax(mu, fabs(u[t]));
-      mw = fmax(mw, fabs(w[t]));
+    for (int it = 0; it < NCACHE; ++it) {
+      if (it < npass) {
+        fold4(threadIdx.x + 1 + it * FP * NTHR, cu[it], cw[it], bad);
+#pragma unroll
+        for (int t = 0; t < FP; ++t) {
+          mu = fmax(mu, fabs(cu[it][t]));
+          mw = fmax(mw, fabs(cw[it][t]));
+        }
+      }
+    }
+  } else {
+    for (int k0 = threadIdx.x + 1; k0 <= H0; k0 += FP * NTHR) {
+      double u[FP], w[FP];
+      fold4(k0, u, w, bad);
+#pragma unroll
+      for (int t = 0; t < FP; ++t) {
+        mu = fmax(mu, fabs(u[t]));
+        mw = fmax(mw, fabs(w[t]));
+      }
     }
   }
   __shared__ double red[2][4];
@@ -150,6 +172,22 @@ __global__ __launch_bounds__(NTHR) void k_x_slices(int n, int hpad, const DstCol
   __syncthreads();
   const int e0 = exs[0], e1 = exs[1];
   uint2 *o0 = out + (size_t)(2 * c) * hpad, *o1 = o0 + hpad;
+  if (cached) {
+#pragma unroll
+    for (int it = 0; it < NCACHE; ++it) {
+      if (it < npass) {
+#pragma unroll
+        for (int t = 0; t < FP; ++t) {
+          const int k = threadIdx.x + 1 + it * FP * NTHR + t * NTHR;
+          if (k <= hpad) {
+            o0[k - 1] = slice_record(cu[it][t], e0);
+            o1[k - 1] = slice_record(k <= H1 ? cw[it][t] : 0.0, e1);
+          }
+        }
+      }
+    }
+    return;
+  }
   bool unused = false;
   for (int k0 = threadIdx.x + 1; k0 <= hpad; k0 += FP * NTHR) {
     double u[FP], w[FP];
