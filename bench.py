@@ -47,11 +47,11 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "int8": 5.0e15}
 # workload and batch); otherwise the traffic is reported as null.
 TRAFFIC = {
     "k_dst_i8": {"sources": ["dst_i8.hip", "lrp_internal.h"],
-                 "sha1": "3f8c37b3cbe302876dd7003ea1140ccb77071120",
-                 "columns": 11990.857, "fetch_kib": 196753.3, "write_kib": 384224.7},
+                 "sha1": "c11ce42d2e9d40ca6b4b141f7a4d64e437dd236f",
+                 "columns": 11990.857, "fetch_kib": 196758.7, "write_kib": 384221.9},
     "k_dst_f64": {"sources": ["dst.hip", "lrp_internal.h"],
                   "sha1": "f4e3a75d3b1ec2d9cfa32b190fa2a054c2b3df4a",
-                  "columns": 41968, "fetch_kib": 675026.7, "write_kib": 1377191.6},
+                  "columns": 41968, "fetch_kib": 675162.3, "write_kib": 1371317.4},
 }
 
 
