@@ -182,9 +182,29 @@ __global__ __launch_bounds__(NTHR) void k_mv_inv(int which, int n, int force,
     for (int c = threadIdx.x; c < w2; c += NTHR) prow[c] = a[p][c] * sip;
     if (threadIdx.x < kk) f[threadIdx.x] = (threadIdx.x == p) ? 0.0 : a[threadIdx.x][j];
     __syncthreads();
-    for (int i = i0; i < kk; i += 4)
-      for (int c = cl; c < w2; c += 64)
-        a[i][c] = (i == p) ? prow[c] : a[i][c] - f[i] * prow[c];
+    {
+      // the thread's entries (rows i0 + 4 u, columns cl + 64 v) read first
+      // (indices clamped inside the arrays), then updated; each entry is
+      // read and written by its own thread only
+      constexpr int RI = KM / 4, CV = (W2 + 63) / 64;
+      double pr[CV], fv[RI], av[RI][CV];
+#pragma unroll
+      for (int v = 0; v < CV; ++v) pr[v] = prow[min(cl + 64 * v, W2 - 1)];
+#pragma unroll
+      for (int u = 0; u < RI; ++u) {
+        const int i = min(i0 + 4 * u, KM - 1);
+        fv[u] = f[i];
+#pragma unroll
+        for (int v = 0; v < CV; ++v) av[u][v] = a[i][min(cl + 64 * v, W2 - 1)];
+      }
+#pragma unroll
+      for (int u = 0; u < RI; ++u)
+#pragma unroll
+        for (int v = 0; v < CV; ++v) {
+          const int i = i0 + 4 * u, c = cl + 64 * v;
+          if (i < kk && c < w2) a[i][c] = (i == p) ? pr[v] : av[u][v] - fv[u] * pr[v];
+        }
+    }
     __syncthreads();
   }
   for (int t = i0; t < kk; t += 4)
