@@ -485,7 +485,8 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
     }
     Bm[e] = v;
   }
-  if (threadIdx.x == 0) cnt[2] = 0;
+  __shared__ int sts;
+  if (threadIdx.x == 0) cnt[2] = 0, sts = 0;
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int it = 0; it < 4 * kk; ++it) {
@@ -507,11 +508,12 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
       if (rv[w] > bv || (rv[w] == bv && rk[w] < bk)) bv = rv[w], bk = rk[w];
     if (!(bv > s.tau)) break;            // uniform: every thread sees bv
     const int gr = bk / KMAX, cs = bk - gr * KMAX;
-    int ts = 0;
-    for (int t = 0; t < nr; ++t)
-      if (rows[t] == gr) ts = t;          // rows are distinct
-    const double piv = Bm[ts * KM + cs];
+    // the winner's row position: one thread finds it (rows are distinct)
+    for (int t = threadIdx.x; t < nr; t += NTHR)
+      if (rows[t] == gr) sts = t;
     __syncthreads();
+    const int ts = sts;
+    const double piv = Bm[ts * KM + cs];
     for (int c = threadIdx.x; c < kk; c += NTHR)
       prow[c] = (Bm[ts * KM + c] - (c == cs ? 1.0 : 0.0)) / piv;
     for (int t = threadIdx.x; t < nr; t += NTHR) pcol[t] = Bm[t * KM + cs];
