@@ -409,10 +409,23 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
     for (int e = threadIdx.x; e < nv; e += NTHR) {
       const double v = cv[e];
       const int rr = crow[e];
-      int rank = 0;
-      for (int f = 0; f < nv; ++f) {
-        const double w = cv[f];
-        if (w > v || (w == v && crow[f] < rr)) ++rank;
+      // count the violators ahead of this one, eight reads in flight at once
+      int rank = 0, f0 = 0;
+      for (; f0 + 8 <= nv; f0 += 8) {
+        double w[8];
+        int r[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          w[u] = cv[f0 + u];
+          r[u] = crow[f0 + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (w[u] > v || (w[u] == v && r[u] < rr)) ++rank;
+      }
+      for (; f0 < nv; ++f0) {
+        const double w = cv[f0];
+        if (w > v || (w == v && crow[f0] < rr)) ++rank;
       }
       if (rank < MV_CAND) cr[kk + rank] = rr;
     }
