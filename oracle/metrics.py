@@ -28,14 +28,21 @@ def rel_err_factored(Ux: np.ndarray, Vx: np.ndarray, X: np.ndarray,
     return float(np.sqrt(num / den))
 
 
-def rel_err_tucker(U1, U2, U3, G, X: np.ndarray) -> float:
-    """||[[G; U1, U2, U3]] - X||_F / ||X||_F, slab by slab along mode 1."""
+def rel_err_tucker(U1, U2, U3, G, X: np.ndarray, step: int | None = None) -> float:
+    """||[[G; U1, U2, U3]] - X||_F / ||X||_F, slab by slab along mode 1.
+
+    ``step`` is the slab height (rows of mode 1 per slab); by default slabs
+    hold about 4M entries.  Pins: equals the norm of the expanded difference
+    (``poisson.tucker_full``) and an element-by-element brute-force sum at
+    small non-cubic shapes, for every slab height.
+    """
     num = 0.0
     den = 0.0
     # T[a, j, k] = sum_bc G[a,b,c] U2[j,b] U3[k,c]
     T = np.einsum("abc,jb,kc->ajk", G, U2, U3, optimize=True)
     n1 = X.shape[0]
-    step = max(1, 2 ** 22 // max(1, X.shape[1] * X.shape[2]))
+    if step is None:
+        step = max(1, 2 ** 22 // max(1, X.shape[1] * X.shape[2]))
     for i0 in range(0, n1, step):
         i1 = min(n1, i0 + step)
         blk = np.tensordot(U1[i0:i1], T, axes=(1, 0))

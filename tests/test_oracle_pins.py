@@ -215,6 +215,53 @@ def test_rel_err_small_difference_no_cancellation():
     assert abs(e - want) / want < 1e-3
 
 
+def _tucker_case(seed=21, shape=(7, 5, 6), ranks=(3, 2, 4)):
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal(ranks)
+    Us = [rng.standard_normal((shape[d], ranks[d])) for d in range(3)]
+    X = rng.standard_normal(shape)
+    return Us, G, X
+
+
+def _tucker_err_brute(Us, G, X):
+    """Element by element: sum over every (i, j, l) of the squared difference
+    between the Tucker entry (eq. "tucker") and X, over the sum of X^2."""
+    U1, U2, U3 = Us
+    num = den = 0.0
+    for i in range(X.shape[0]):
+        for j in range(X.shape[1]):
+            for l in range(X.shape[2]):
+                t = 0.0
+                for a in range(G.shape[0]):
+                    for b in range(G.shape[1]):
+                        for c in range(G.shape[2]):
+                            t += G[a, b, c] * U1[i, a] * U2[j, b] * U3[l, c]
+                num += (t - X[i, j, l]) ** 2
+                den += X[i, j, l] ** 2
+    return math.sqrt(num / den)
+
+
+@pytest.mark.parametrize("step", [None, 1, 2, 3, 6, 7, 100])
+def test_rel_err_tucker_vs_expanded_and_brute_force(step):
+    """Non-cubic shapes, every slab height (slabs of one row, slabs that do
+    not divide n1, a single slab)."""
+    Us, G, X = _tucker_case()
+    want = np.linalg.norm(poisson.tucker_full(G, *Us) - X) / np.linalg.norm(X)
+    got = metrics.rel_err_tucker(*Us, G, X, step=step)
+    assert abs(got - want) <= 1e-14 * want
+    assert abs(got - _tucker_err_brute(Us, G, X)) <= 1e-13 * want
+
+
+def test_rel_err_tucker_small_difference_and_exact():
+    Us, G, _ = _tucker_case(seed=22, shape=(9, 4, 5))
+    A = poisson.tucker_full(G, *Us)
+    assert metrics.rel_err_tucker(*Us, G, A, step=2) <= 1e-15
+    d = 1e-11 * np.random.default_rng(3).standard_normal(A.shape)
+    e = metrics.rel_err_tucker(*Us, G, A + d, step=4)
+    want = np.linalg.norm(d) / np.linalg.norm(A + d)
+    assert abs(e - want) / want < 1e-3
+
+
 # ---------------------------------------------------------------- maxvol
 def _lapack_pivot_rows(A):
     lu, piv = scipy.linalg.lu_factor(A)
@@ -437,6 +484,50 @@ def _maxvol_no_pivot_scale(A, tau=1.05):
         row[j] -= 1.0
         B -= np.outer(B[:, j], row)        # planted: drops the 1/B[i,j]
     return I, B, 0
+
+
+def _tucker_err_swapped_modes(U1, U2, U3, G, X, step=None):   # U2, U3 swapped
+    T = np.einsum("abc,jb,kc->ajk", G, U3, U2, optimize=True)
+    d = np.tensordot(U1, T, axes=(1, 0)) - X
+    return float(np.linalg.norm(d) / np.linalg.norm(X))
+
+
+def _tucker_err_skipped_slab(U1, U2, U3, G, X, step=2):       # drops the last slab
+    T = np.einsum("abc,jb,kc->ajk", G, U2, U3, optimize=True)
+    num = den = 0.0
+    starts = list(range(0, X.shape[0], step))
+    for i0 in starts[:-1]:
+        i1 = min(X.shape[0], i0 + step)
+        d = np.tensordot(U1[i0:i1], T, axes=(1, 0)) - X[i0:i1]
+        num += float(np.sum(d * d))
+        den += float(np.sum(X[i0:i1] ** 2))
+    return math.sqrt(num / den)
+
+
+def _tucker_err_not_squared(U1, U2, U3, G, X, step=2):        # sums |d|, not d^2
+    T = np.einsum("abc,jb,kc->ajk", G, U2, U3, optimize=True)
+    num = den = 0.0
+    for i0 in range(0, X.shape[0], step):
+        i1 = min(X.shape[0], i0 + step)
+        d = np.tensordot(U1[i0:i1], T, axes=(1, 0)) - X[i0:i1]
+        num += float(np.sum(np.abs(d)))
+        den += float(np.sum(X[i0:i1] ** 2))
+    return math.sqrt(num / den)
+
+
+def test_tucker_error_mutants_are_caught():
+    """Each planted mistake in the 3D error measure disagrees with the
+    expanded-difference pin (same cases as the pin test)."""
+    Us, G, X = _tucker_case(shape=(7, 5, 5), ranks=(3, 2, 2))
+    # a result close to X, so that a wrong measure shows as a large ratio
+    A = poisson.tucker_full(G, *Us)
+    Xn = A + 1e-3 * np.random.default_rng(4).standard_normal(A.shape)
+    want = np.linalg.norm(A - Xn) / np.linalg.norm(Xn)
+    assert abs(metrics.rel_err_tucker(*Us, G, Xn, step=2) - want) <= 1e-12 * want
+    for bad in (_tucker_err_swapped_modes, _tucker_err_skipped_slab,
+                _tucker_err_not_squared):
+        got = bad(*Us, G, Xn, step=2)
+        assert abs(got - want) > 0.05 * want, bad.__name__
 
 
 def test_mutants_are_caught():
