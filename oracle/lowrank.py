@@ -42,7 +42,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .poisson import dst, eigenvalues
+from .poisson import dst, eigenvalues, stokes_half_angles
 
 
 def gepp_rows(A: np.ndarray) -> np.ndarray:
@@ -117,18 +117,18 @@ def truncation_rank(s: np.ndarray, eps: float) -> int:
     return s.size
 
 
-def spread_indices(n: int, count: int, used) -> np.ndarray:
+def spread_indices(n: int, count: int, used, offset: int = 0) -> np.ndarray:
     """``count`` evenly spaced indices in [0, n) avoiding ``used``.
 
-    Candidate i is floor((2i+1) n / (2 count)); a taken candidate moves to the
-    next free index (cyclically).  Deterministic.
+    Candidate i is (floor((2i+1) n / (2 count)) + offset) mod n; a taken
+    candidate moves to the next free index (cyclically).  Deterministic.
     """
     taken = set(int(u) for u in used)
     out = []
     for i in range(count):
         if len(taken) >= n:
             break
-        j = ((2 * i + 1) * n) // (2 * count)
+        j = (((2 * i + 1) * n) // (2 * count) + offset) % n
         while j in taken:
             j = (j + 1) % n
         taken.add(j)
@@ -143,12 +143,30 @@ def _stacked_change(A, B, Ap, Bp) -> float:
     return float(np.linalg.norm(Ra @ Rb.T))
 
 
+def operator_factors(n: int, op: str = "poisson"):
+    """Per-axis factors of the 2D operator's eigenvalue at mode (i, j).
+
+    5-point Laplacian: returns (lambda, None); the eigenvalue is
+    lambda_i + lambda_j (eq. "div").  Stokes-consistent operator: returns
+    (p, q) = (2 sin^2 / h, 2 cos^2 / h) of the half angles; the eigenvalue is
+    p_i q_j + q_i p_j (``poisson.denominators2d``)."""
+    if op == "poisson":
+        return eigenvalues(n), None
+    s, c, h = stokes_half_angles(n)
+    return 2.0 * s / h, 2.0 * c / h
+
+
 def lr_solve2d(U: np.ndarray, V: np.ndarray, eps: float, kick: int = 8,
                k_max: int = 64, tau: float = 1.05, max_sweeps: int = 10,
-               min_slack: int = 4, k0_extra: int = 0):
+               min_slack: int = 4, k0_extra: int = 0, seed: int = 0,
+               op: str = "poisson"):
     """Low-rank solution of T X + X T = U V^T (returns Ux, Vx, info).
 
     See the module docstring for the steps and the reading of the paper.
+    ``op`` = "stokes" solves with the Stokes-consistent Laplacian of
+    Section 2 instead (denominators p_i q_j + q_i p_j, ``operator_factors``);
+    ``seed`` offsets the deterministic index sequences (padding of the first
+    column set, probe rows) by seed mod n.
     ``info`` has keys status ('ok' | 'rankcap' | 'noconv'), sweeps, k, rank,
     ranks (per sweep) and change (last measured change / ||X~||).
     """
@@ -159,15 +177,21 @@ def lr_solve2d(U: np.ndarray, V: np.ndarray, eps: float, kick: int = 8,
     if r == 0 or not np.any(U) or not np.any(V):
         return np.zeros((n, 0)), np.zeros((n, 0)), info
 
-    lam = eigenvalues(n)
+    lam, q = operator_factors(n, op)
+    off = int(seed % n)
     Uh = dst(U)                   # Section 4.1: transform of the factors
     Vh = dst(V)
 
+    def den(I, J):                # the operator's eigenvalue at modes (I, J)
+        if q is None:
+            return lam[I][:, None] + lam[J][None, :]
+        return lam[I][:, None] * q[J][None, :] + q[I][:, None] * lam[J][None, :]
+
     def xh_cols(J):               # eq. "div", columns J
-        return (Uh @ Vh[J].T) / (lam[:, None] + lam[J][None, :])
+        return (Uh @ Vh[J].T) / den(np.arange(n), J)
 
     def xh_rows(I):               # eq. "div", rows I
-        return (Uh[I] @ Vh.T) / (lam[I][:, None] + lam[None, :])
+        return (Uh[I] @ Vh.T) / den(I, np.arange(n))
 
     k_cap = min(n, k_max)
     k = min(n, r + kick + k0_extra, k_max)
@@ -175,7 +199,7 @@ def lr_solve2d(U: np.ndarray, V: np.ndarray, eps: float, kick: int = 8,
     J, _, _ = maxvol(Qv, tau)
     J = J[:k]
     if J.size < k:
-        J = np.concatenate([J, spread_indices(n, k - J.size, J)])
+        J = np.concatenate([J, spread_indices(n, k - J.size, J, off)])
 
     prev = None
     A = B = None
@@ -204,7 +228,7 @@ def lr_solve2d(U: np.ndarray, V: np.ndarray, eps: float, kick: int = 8,
         no_slack = (R > k - min_slack) and (k < n)
         if no_slack and k < k_cap:
             grow = min(kick, k_cap - k)
-            probe = spread_indices(n, kick, I)
+            probe = spread_indices(n, kick, I, off)
             res = xh_rows(probe) - A[probe, :] @ B.T
             score = np.max(np.abs(res), axis=0)
             score[Jn] = -1.0

@@ -68,39 +68,106 @@ def dst(X: np.ndarray, axis: int = 0) -> np.ndarray:
                          norm="ortho", axis=axis)
 
 
-def full_solve2d(F: np.ndarray, workers: int | None = None) -> np.ndarray:
-    """Full-grid 2D solve X = S[(S F S) / (lambda_i + lambda_j)]S.
+def stokes_half_angles(n: int):
+    """sin^2 and cos^2 of pi k/(2(n+1)), k = 1..n, and h.
+
+    The Stokes-consistent Laplacian of Section 2 is built from G = E - Z and
+    H = E + Z (shift difference and shift sum from the n+1 cell values to the
+    n interior vertices); A1 = G G^T = tridiag(-1, 2, -1) and A2 = H H^T =
+    tridiag(1, 2, 1) are diagonalised by the same sine transform (Section
+    4.1) with eigenvalues 4 sin^2 and 4 cos^2 of these half angles.
+    Pin: A1, A2 built from G, H and compared with eigvalsh.
+    """
+    N = n + 1
+    k = np.arange(1, n + 1, dtype=np.float64)
+    t = np.pi * k / (2.0 * N)
+    return np.sin(t) ** 2, np.cos(t) ** 2, 1.0 / N
+
+
+def denominators2d(n1: int, n2: int, op: str = "poisson") -> np.ndarray:
+    """Eigenvalue of the 2D operator at sine mode (i, j), an n1 x n2 array.
+
+    poisson: lambda_i + lambda_j (5-point, eq. "div").
+    stokes:  4 (B_x B_x^T + B_y B_y^T) with B_x = (G (x) H)/(4h),
+             B_y = (H (x) G)/(4h) (Section 2), i.e. the Kronecker form
+             A1 (x) A2 + A2 (x) A1 of Section 4.1 scaled by 1/(4 h^2):
+             (4 s_i c_j + 4 c_i s_j) / h^2 with s = sin^2, c = cos^2 of the
+             half angles.  (The scale 4 makes smooth modes see -Laplacian,
+             like the 5-point operator; Section 4.1 leaves the scale free.)
+    Pins: dense Kronecker operators built from G and H.
+    """
+    if op == "poisson":
+        return eigenvalues(n1)[:, None] + eigenvalues(n2)[None, :]
+    if op != "stokes":
+        raise ValueError(op)
+    s1, c1, h1 = stokes_half_angles(n1)
+    s2, c2, h2 = stokes_half_angles(n2)
+    if n1 != n2:
+        raise ValueError("the Stokes operator is defined on square grids")
+    return 4.0 * (s1[:, None] * c2[None, :] + c1[:, None] * s2[None, :]) / (h1 * h1)
+
+
+def denominators3d(n: int, op: str = "poisson") -> np.ndarray:
+    """Eigenvalue of the 3D operator at sine mode (i, j, l), n x n x n.
+
+    poisson: lambda_i + lambda_j + lambda_l (7-point).
+    stokes:  B_x B_x^T + B_y B_y^T + B_z B_z^T with B_x = (G (x) H (x) H)/(4h)
+             and its permutations (Section 2):
+             4 (s_i c_j c_l + c_i s_j c_l + c_i c_j s_l) / h^2.
+    Pins: dense Kronecker operators built from G and H.
+    """
+    if op == "poisson":
+        lam = eigenvalues(n)
+        return lam[:, None, None] + lam[None, :, None] + lam[None, None, :]
+    if op != "stokes":
+        raise ValueError(op)
+    s, c, h = stokes_half_angles(n)
+    S_, C_ = s[:, None, None], c[:, None, None]
+    Sj, Cj = s[None, :, None], c[None, :, None]
+    Sl, Cl = s[None, None, :], c[None, None, :]
+    return 4.0 * (S_ * Cj * Cl + C_ * Sj * Cl + C_ * Cj * Sl) / (h * h)
+
+
+def full_solve2d(F: np.ndarray, workers: int | None = None,
+                 op: str = "poisson") -> np.ndarray:
+    """Full-grid 2D solve X = S[(S F S) / D]S, D = ``denominators2d``.
 
     Section 4.1: "applying the DST, inverting the diagonal matrix, and then
     applying the DST back".  Pins: scipy.linalg.solve_sylvester, dense
-    Kronecker solve, residual, single sine mode.
+    Kronecker solve, residual, single sine mode (Stokes operator: dense
+    Kronecker solve from G and H).
     """
     F = np.asarray(F, dtype=np.float64)
     n1, n2 = F.shape
     Fh = scipy.fft.dstn(F, type=1, norm="ortho", workers=workers)
-    lam1 = eigenvalues(n1)
-    lam2 = eigenvalues(n2)
-    Fh /= (lam1[:, None] + lam2[None, :])
+    Fh /= denominators2d(n1, n2, op)
     return scipy.fft.idstn(Fh, type=1, norm="ortho", workers=workers)
 
 
 def full_solve2d_factors(U: np.ndarray, V: np.ndarray,
-                         workers: int | None = None) -> np.ndarray:
+                         workers: int | None = None, op: str = "poisson") -> np.ndarray:
     """Full-grid solve for F = U V^T (forms F, then ``full_solve2d``)."""
-    return full_solve2d(np.asarray(U) @ np.asarray(V).T, workers=workers)
+    return full_solve2d(np.asarray(U) @ np.asarray(V).T, workers=workers, op=op)
 
 
-def full_solve3d(F: np.ndarray, workers: int | None = None) -> np.ndarray:
-    """Full-grid 3D solve: S along each mode, divide by the three-term sum,
-    S back along each mode (the 3D analogue of eq. "diag").
+def full_solve3d(F: np.ndarray, workers: int | None = None,
+                 op: str = "poisson") -> np.ndarray:
+    """Full-grid 3D solve: S along each mode, divide by the operator's
+    eigenvalue (``denominators3d``; for the 7-point Laplacian the three-term
+    sum), S back along each mode (the 3D analogue of eq. "diag").
 
     Pins: dense Kronecker solve at tiny n; single sine mode.
     """
     F = np.asarray(F, dtype=np.float64)
     n1, n2, n3 = F.shape
     Fh = scipy.fft.dstn(F, type=1, norm="ortho", workers=workers)
-    l1, l2, l3 = eigenvalues(n1), eigenvalues(n2), eigenvalues(n3)
-    Fh /= (l1[:, None, None] + l2[None, :, None] + l3[None, None, :])
+    if op == "poisson":
+        l1, l2, l3 = eigenvalues(n1), eigenvalues(n2), eigenvalues(n3)
+        Fh /= (l1[:, None, None] + l2[None, :, None] + l3[None, None, :])
+    else:
+        if not n1 == n2 == n3:
+            raise ValueError("the Stokes operator is defined on cubic grids")
+        Fh /= denominators3d(n1, op)
     return scipy.fft.idstn(Fh, type=1, norm="ortho", workers=workers)
 
 
@@ -111,6 +178,7 @@ def tucker_full(G: np.ndarray, U1: np.ndarray, U2: np.ndarray,
     return np.einsum("abc,ia,jb,kc->ijk", G, U1, U2, U3, optimize=True)
 
 
-def full_solve3d_tucker(U1, U2, U3, G, workers: int | None = None):
+def full_solve3d_tucker(U1, U2, U3, G, workers: int | None = None,
+                        op: str = "poisson"):
     """Full-grid 3D solve for a Tucker RHS (forms F, then ``full_solve3d``)."""
-    return full_solve3d(tucker_full(G, U1, U2, U3), workers=workers)
+    return full_solve3d(tucker_full(G, U1, U2, U3), workers=workers, op=op)

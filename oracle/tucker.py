@@ -27,7 +27,7 @@ from __future__ import annotations
 import numpy as np
 
 from .lowrank import maxvol, spread_indices, truncation_rank
-from .poisson import dst, eigenvalues
+from .poisson import dst, eigenvalues, stokes_half_angles
 
 
 def mode_product(T: np.ndarray, M: np.ndarray, d: int) -> np.ndarray:
@@ -57,8 +57,12 @@ def _tucker_change(core, Q, core_p, Q_p) -> float:
 
 
 def lr_solve3d(U1, U2, U3, G, eps: float, kick: int = 8, k_max: int = 64,
-               tau: float = 1.05, max_sweeps: int = 10):
-    """Low-rank Tucker solution of the 7-point Dirichlet Poisson problem.
+               tau: float = 1.05, max_sweeps: int = 10, op: str = "poisson"):
+    """Low-rank Tucker solution of the 7-point Dirichlet Poisson problem
+    (``op`` = "stokes": the Stokes-consistent Laplacian of Section 2, whose
+    eigenvalue at mode (i, j, l) is 4 (s_i c_j c_l + c_i s_j c_l +
+    c_i c_j s_l) / h^2 with s, c the squared sine and cosine of the half
+    angles, ``poisson.denominators3d``).
 
     Returns (factors [V1, V2, V3], core, info).  See the module docstring.
     """
@@ -70,14 +74,21 @@ def lr_solve3d(U1, U2, U3, G, eps: float, kick: int = 8, k_max: int = 64,
         z = np.zeros((n, 0))
         return [z, z.copy(), z.copy()], np.zeros((0, 0, 0)), info
     lam = eigenvalues(n)
+    sq, cq, h = stokes_half_angles(n)
     Uh = [dst(u) for u in Us]
     eps_d = eps / np.sqrt(3.0)
 
     def entries(I1, I2, I3):
         num = np.einsum("abc,ia,jb,kc->ijk", G, Uh[0][I1], Uh[1][I2],
                         Uh[2][I3], optimize=True)
-        den = (lam[I1][:, None, None] + lam[I2][None, :, None]
-               + lam[I3][None, None, :])
+        if op == "poisson":
+            den = (lam[I1][:, None, None] + lam[I2][None, :, None]
+                   + lam[I3][None, None, :])
+        else:
+            s1, c1 = sq[I1][:, None, None], cq[I1][:, None, None]
+            s2, c2 = sq[I2][None, :, None], cq[I2][None, :, None]
+            s3, c3 = sq[I3][None, None, :], cq[I3][None, None, :]
+            den = 4.0 * (s1 * c2 * c3 + c1 * s2 * c3 + c1 * c2 * s3) / (h * h)
         return num / den
 
     idx = []

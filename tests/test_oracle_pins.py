@@ -543,3 +543,134 @@ def test_mutants_are_caught():
                                      tau=1.0001)
         caught |= (e_id > 1e-6) or (over > 1e-6)
     assert caught
+
+
+# ------------------------- Stokes-consistent Laplacian (Section 2, 4.1)
+def _gh(n):
+    """G = E - Z and H = E + Z of Section 2, (n x (n+1)): E drops the first
+    entry of a vector of n+1 cell values (moving the rest up), Z drops the
+    last.  Built entry by entry from that definition."""
+    E = np.zeros((n, n + 1))
+    Z = np.zeros((n, n + 1))
+    for i in range(n):
+        E[i, i + 1] = 1.0
+        Z[i, i] = 1.0
+    return E - Z, E + Z
+
+
+def _stokes_dense_2d(n):
+    G, H = _gh(n)
+    h = 1.0 / (n + 1)
+    Bx = np.kron(G, H) / (4 * h)
+    By = np.kron(H, G) / (4 * h)
+    return 4.0 * (Bx @ Bx.T + By @ By.T)
+
+
+def _stokes_dense_3d(n):
+    G, H = _gh(n)
+    h = 1.0 / (n + 1)
+    Bs = [np.kron(np.kron(G, H), H), np.kron(np.kron(H, G), H),
+          np.kron(np.kron(H, H), G)]
+    return sum(B @ B.T for B in Bs) / (16 * h * h)
+
+
+def check_stokes2d(solve_fn, n, seed=0):
+    rng = np.random.default_rng(seed)
+    F = rng.standard_normal((n, n))
+    x = np.linalg.solve(_stokes_dense_2d(n), F.reshape(-1)).reshape(n, n)
+    return float(np.max(np.abs(solve_fn(F) - x)) / np.max(np.abs(x)))
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 12])
+def test_stokes_half_angles_diagonalise_gg_hh(n):
+    """A1 = G G^T and A2 = H H^T (Section 4.1) have eigenvalues 4 sin^2 and
+    4 cos^2 of the half angles, on the sine modes."""
+    G, H = _gh(n)
+    s, c, _ = poisson.stokes_half_angles(n)
+    S = poisson.sine_matrix(n)
+    assert np.max(np.abs(S @ (G @ G.T) @ S - np.diag(4 * s))) < 1e-13
+    assert np.max(np.abs(S @ (H @ H.T) @ S - np.diag(4 * c))) < 1e-13
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 12])
+def test_stokes_full_solve2d_vs_dense_kron(n):
+    assert check_stokes2d(lambda F: poisson.full_solve2d(F, op="stokes"), n) < 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 6])
+def test_stokes_full_solve3d_vs_dense_kron(n):
+    rng = np.random.default_rng(n)
+    F = rng.standard_normal((n, n, n))
+    x = np.linalg.solve(_stokes_dense_3d(n), F.reshape(-1)).reshape(n, n, n)
+    X = poisson.full_solve3d(F, op="stokes")
+    assert np.max(np.abs(X - x)) < 1e-12 * np.max(np.abs(x))
+
+
+def test_stokes_smooth_modes_see_laplacian():
+    """Scale: for a smooth mode the operator's eigenvalue approaches the
+    continuous -Laplacian's pi^2 (p^2 + q^2), as the 5-point one does."""
+    n = 2047
+    D = poisson.denominators2d(n, n, "stokes")
+    assert abs(D[1, 2] / (np.pi ** 2 * (4 + 9)) - 1) < 1e-5
+    D3 = poisson.denominators3d(63, "stokes")
+    assert abs(D3[0, 1, 2] / (np.pi ** 2 * (1 + 4 + 9)) - 1) < 2e-2
+
+
+def test_stokes_lr_solve2d_vs_full():
+    U, V = inputs.workload_rhs(2, 3, n=300)
+    X = poisson.full_solve2d_factors(U, V, op="stokes")
+    for eps in (1e-6, 1e-9):
+        Ux, Vx, info = lowrank.lr_solve2d(U, V, eps, op="stokes")
+        assert info["status"] == "ok"
+        assert metrics.rel_err_factored(Ux, Vx, X) <= 10 * eps
+    # the 5-point result is a different solution
+    Ux, Vx, _ = lowrank.lr_solve2d(U, V, 1e-9)
+    assert metrics.rel_err_factored(Ux, Vx, X) > 1e-5   # O(h^2) apart
+
+
+def test_stokes_lr_solve3d_vs_full():
+    U1, U2, U3, G = inputs.rhs3d_tucker(40, (5, 5, 5), 3301)
+    X = poisson.full_solve3d_tucker(U1, U2, U3, G, op="stokes")
+    f, c, info = tucker.lr_solve3d(U1, U2, U3, G, 1e-7, op="stokes")
+    assert metrics.rel_err_tucker(f[0], f[1], f[2], c, X) <= 1e-6
+
+
+def test_seeded_sequences_lr_solve2d():
+    """Another offset of the deterministic index sequences gives another
+    approximation of the same accuracy."""
+    U, V = inputs.workload_rhs(2, 4, n=400)
+    X = poisson.full_solve2d_factors(U, V)
+    for seed in (0, 7, 10 ** 12 + 3):
+        Ux, Vx, info = lowrank.lr_solve2d(U, V, 1e-8, seed=seed)
+        assert metrics.rel_err_factored(Ux, Vx, X) <= 1e-7
+    assert list(lowrank.spread_indices(10, 3, [], 0)) == [1, 5, 8]
+    assert list(lowrank.spread_indices(10, 3, [], 4)) == [5, 9, 2]
+    assert list(lowrank.spread_indices(10, 3, [5], 4)) == [6, 9, 2]
+
+
+# planted mistakes in the Stokes denominator
+def _stokes_solve_sec42(F):            # mu_i + mu_j, mu = (4 - lambda) lambda
+    n = F.shape[0]
+    s, c, h = poisson.stokes_half_angles(n)
+    lam = 4 * s
+    mu = (4 - lam) * lam
+    D = (mu[:, None] + mu[None, :]) / (h * h)
+    Fh = poisson.dst(poisson.dst(F, 0), 1)
+    return poisson.dst(poisson.dst(Fh / D, 0), 1)
+
+
+def _stokes_solve_swapped(F):          # sin and cos exchanged in one factor
+    n = F.shape[0]
+    s, c, h = poisson.stokes_half_angles(n)
+    D = 4 * (s[:, None] * s[None, :] + c[:, None] * c[None, :]) / (h * h)
+    Fh = poisson.dst(poisson.dst(F, 0), 1)
+    return poisson.dst(poisson.dst(Fh / D, 0), 1)
+
+
+def _stokes_solve_unscaled(F):         # drops the factor 4 (the bare sum B B^T)
+    return 4.0 * poisson.full_solve2d(F, op="stokes")
+
+
+def test_stokes_mutants_are_caught():
+    for bad in (_stokes_solve_sec42, _stokes_solve_swapped, _stokes_solve_unscaled):
+        assert check_stokes2d(bad, 8) > 1e-3, bad.__name__
