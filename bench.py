@@ -83,13 +83,56 @@ def parse():
     ap.add_argument("--serve-warmup", type=int, default=50)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=6)
+    ap.add_argument("--cpu-sample", type=int, default=5)
+    ap.add_argument("--serve-check", type=int, default=1,
+                    help="served requests per (dim, n) shape checked against the oracle")
     ap.add_argument("--batch-sweep", type=str, default="",
                     help="comma-separated batch sizes: also report solves/s of both "
                          "plans at each (e.g. 1,8,32,128,256,512,1024)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="copy this many MiB once first (HBM counter calibration)")
     return ap.parse_args()
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(hostrhs, eps, runs):
+    """The oracle timed on the host cores: the float64 full-grid solve
+    (scipy.fft, threaded) and, beside it, the naive float64 low-rank solver
+    (threaded LAPACK); each the median of ``runs`` solves after one warm-up,
+    on the first ``runs`` distinct right-hand sides."""
+    import numpy as np
+    from oracle import lowrank, poisson
+    workers = min(16, os.cpu_count() or 1)
+
+    def median_time(fn):
+        fn(*hostrhs[0])
+        ts = []
+        for i in range(runs):
+            t0 = time.perf_counter()
+            fn(*hostrhs[i % len(hostrhs)])
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    t_full = median_time(lambda U, V: poisson.full_solve2d_factors(U, V, workers=workers))
+    t_lr = median_time(lambda U, V: lowrank.lr_solve2d(U, V, eps))
+    return {"value": 1.0 / t_full, "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "cpu": cpu_model(),
+            "sample": f"median of {runs} full-grid float64 DST solves at n=4096 after one "
+                      f"warm-up (scipy.fft, {workers} workers)",
+            "lowrank_oracle": {"value": 1.0 / t_lr, "unit": "solves/s",
+                               "sample": f"median of {runs} naive float64 low-rank solves "
+                                         f"(eps={eps}, numpy/LAPACK threads)"}}
 
 
 def timed_steps(ctx, problems, prec, steps, warmup):
@@ -169,40 +212,58 @@ def main():
     print("[bench] rel err per instance auto: " +
           " ".join(f"{e:.2e}" for e in errs["auto"]), file=sys.stderr, flush=True)
 
-    # roofline of the dominant kernel of the measured (AUTO) step: the int8
+    # Roofline of the dominant kernel of the measured (AUTO) step: the int8
     # slice transform (the float64 transform of the FP64 plan beside it).
-    # Algorithmic work per transformed column of length n: the folded DST is
-    # two half-size GEMMs, 2 (H0^2 + H1^2) flops with H0 = ceil(n/2), H1 =
-    # floor(n/2) (the library's flop count); the int8 slice scheme executes it
-    # as 8 v_mfma_i32_16x16x64 per 16 grid points and 16 x 16 output tile,
-    # i.e. 32 int8 ops per flop.  dense_equiv_tflops counts the unfolded
-    # 2 n^2 flops per column.
-    def kstat_roof(ks, name, peak, unit, ops_per_flop):
+    # frac is the HBM fraction: the method's minimum bytes of one launch (each
+    # column's input read once and its transform written once) over the
+    # launch's average duration, against 8 TB/s.  The dense-GEMM form does far
+    # more arithmetic than the FFT form (5 N log2(2N) flops per column), so it
+    # runs far from this bound; its matrix-core figures are kept beside it:
+    #  - folded GEMM work per column: 2 (H0^2 + H1^2) flops, H0 = ceil(n/2),
+    #    H1 = floor(n/2) (the library's count);
+    #  - the int8 scheme executes 8 v_mfma_i32_16x16x64 per 16 grid points
+    #    and 16 x 16 output tile: 32 int8 products per multiply-add, of which
+    #    21 are needed (slice levels a + b <= 5 of the six 7-bit slices of
+    #    each operand; the rest multiply zero padding).
+    def kstat_roof(ks, name, peak, unit, ops_per_flop, needed_per_flop, bytes_per_col):
         launches = max(1, ks["launches"])
         avg_ms = ks["ms"] / launches
         flops = ks["flops"] / launches
         cols = ks["columns"] / launches
-        ach = flops * ops_per_flop / (avg_ms * 1e-3) if avg_ms > 0 else 0.0
-        dense = 2.0 * n * n * cols / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
-        return {"kernel": name, "bound": "mfma", "achieved": ach / 1e12, "peak": peak / 1e12,
-                "unit": unit, "frac": ach / peak, "traffic": None,
+        sec = avg_ms * 1e-3
+        alg = cols * bytes_per_col
+        gbs = alg / sec / 1e9 if sec > 0 else 0.0
+        ach = flops * ops_per_flop / sec if sec > 0 else 0.0
+        need = flops * needed_per_flop / sec if sec > 0 else 0.0
+        fft = cols * 5.0 * (n + 1) * np.log2(2.0 * (n + 1)) / sec if sec > 0 else 0.0
+        return {"kernel": name, "bound": "hbm", "achieved": gbs, "peak": 8000.0,
+                "unit": "GB/s", "frac": gbs / 8000.0, "traffic": None,
+                "algorithmic_bytes": alg,
                 "avg_launch_ms": avg_ms, "launches": ks["launches"],
-                "columns_per_launch": cols, "dense_equiv_tflops": dense}
+                "columns_per_launch": cols,
+                "mfma_executed": {"achieved": ach / 1e12, "peak": peak / 1e12, "unit": unit,
+                                  "frac": ach / peak},
+                "mfma_needed": {"achieved": need / 1e12, "frac": need / peak},
+                "fft_form_tflops": fft / 1e12,
+                "dense_equiv_tflops": 2.0 * n * n * cols / sec / 1e12 if sec > 0 else 0.0}
     kauto = out["auto"]["ks"]
+    # minimum bytes of a column: its n float64 inputs read, n outputs written
+    colbytes = 16.0 * n
     if kauto["int8"]["launches"]:
-        roofline = kstat_roof(kauto["int8"], "k_dst_i8", PEAK["int8"], "TOP/s", 32.0)
-        # algorithmic HBM bytes of one launch: each column's two parity slice
-        # records (8 bytes per point, each padded to 32 points) and their two
-        # exponents in, its float64 transform out
+        roofline = kstat_roof(kauto["int8"], "k_dst_i8", PEAK["int8"], "TOP/s", 32.0, 21.0,
+                              colbytes)
+        # the kernel itself reads each column's two parity slice records (8
+        # bytes per point, each padded to 32 points) and exponents, written by
+        # the slicing pass, and writes the float64 transform
         hpad = -(-((n + 1) // 2) // 32) * 32
-        roofline["algorithmic_bytes"] = roofline["columns_per_launch"] * (2 * hpad * 8 + 8 + n * 8)
+        roofline["kernel_bytes"] = roofline["columns_per_launch"] * (2 * hpad * 8 + 8 + n * 8)
         roofline["traffic"] = traffic_bytes("k_dst_i8", roofline["columns_per_launch"])
     else:
-        roofline = kstat_roof(kauto["fp64"], "k_dst_f64", PEAK["fp64"], "TFLOP/s", 1.0)
+        roofline = kstat_roof(kauto["fp64"], "k_dst_f64", PEAK["fp64"], "TFLOP/s", 1.0, 1.0,
+                              colbytes)
     roofline["fp64_plan_kernel"] = kstat_roof(out["fp64"]["ks"]["fp64"], "k_dst_f64",
-                                              PEAK["fp64"], "TFLOP/s", 1.0)
+                                              PEAK["fp64"], "TFLOP/s", 1.0, 1.0, colbytes)
     f64 = roofline["fp64_plan_kernel"]
-    f64["algorithmic_bytes"] = f64["columns_per_launch"] * n * 16
     f64["traffic"] = traffic_bytes("k_dst_f64", f64["columns_per_launch"])
 
     line = {
@@ -252,34 +313,37 @@ def main():
         sv = {}
         for plan in ("auto", "fp64"):
             s = serving.run_stream(ctx, reqs, facs, prec=plan, warmup=args.serve_warmup)
-            s.pop("records")
+            recs = s.pop("records")
+            meas = recs[args.serve_warmup:]
+            counts = {}
+            for d in meas:
+                name = binding.STATUS_NAME.get(d["status"], str(d["status"]))
+                counts[name] = counts.get(name, 0) + 1
+            s["status_counts"] = counts
+            # accuracy of a sample: the first measured request of every shape
+            s["checked"] = serving.check_sample(reqs, meas, per_shape=args.serve_check,
+                                                workers=min(16, os.cpu_count() or 1))
+            del recs, meas
             sv[plan] = s
+            worst = max([c["rel_err"] / c["eps"] for c in s["checked"]] or [0.0])
             print(f"[bench] served {plan}: p50 {s['p50_ms']:.2f} ms p99 "
-                  f"{s['p99_ms']:.2f} ms {s['solves_per_s']:.1f} solves/s",
+                  f"{s['p99_ms']:.2f} ms {s['solves_per_s']:.1f} solves/s, statuses {counts}, "
+                  f"checked {len(s['checked'])} (worst err {worst:.2f} eps)",
                   file=sys.stderr, flush=True)
         line["serving"] = {"stream": "Poisson arrivals 200 req/s, 2D n in 512..8192 and "
                                      "3D n in 128..512, r 4..64, eps 1e-6/1e-8",
                            "p50_ms": sv["auto"]["p50_ms"], "p99_ms": sv["auto"]["p99_ms"],
                            "solves_per_s": sv["auto"]["solves_per_s"],
                            "by_dim": sv["auto"]["by_dim"],
+                           "status_counts": sv["auto"]["status_counts"],
+                           "checked": sv["auto"]["checked"],
                            "fp64": {k: sv["fp64"][k] for k in ("p50_ms", "p99_ms", "solves_per_s",
-                                                                "by_dim")},
+                                                                "by_dim", "status_counts",
+                                                                "checked")},
                            "requests": args.serve_requests, "warmup": args.serve_warmup}
 
     if not args.no_cpu:
-        from oracle import poisson
-        workers = min(16, os.cpu_count() or 1)
-        U, V = hostrhs[0]
-        poisson.full_solve2d_factors(U, V, workers=workers)
-        t0 = time.perf_counter()
-        for i in range(args.cpu_sample):
-            U, V = hostrhs[i % len(hostrhs)]
-            poisson.full_solve2d_factors(U, V, workers=workers)
-        dt = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": args.cpu_sample / dt, "unit": "solves/s",
-                                "cores": workers, "kind": "oracle",
-                                "sample": f"{args.cpu_sample} full-grid float64 DST solves "
-                                          f"at n=4096 (scipy.fft, {workers} workers)"}
+        line["cpu_baseline"] = cpu_baseline(hostrhs, eps, args.cpu_sample)
     print(json.dumps(line), flush=True)
     ctx.close()
 

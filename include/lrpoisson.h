@@ -56,6 +56,7 @@ extern "C" {
 #define LRP_MAX_N 32767   /* grid points per axis (sine table lives in LDS) */
 #define LRP_MAX_N3 1024   /* grid points per axis of a 3D solve            */
 #define LRP_MAX_RANK 64   /* input rank and cross-rank cap (per mode in 3D) */
+#define LRP_MAX_SWEEPS 64 /* largest accepted lrp_opts.max_sweeps           */
 
 typedef enum {
   LRP_OK = 0,
@@ -102,13 +103,45 @@ typedef enum {
   LRP_PREC_INT8 = 4
 } lrp_precision;
 
-/* Optional knobs; pass NULL for defaults.  Zero fields take defaults. */
+/* The discrete operator inverted.  Both are diagonalised by the same sine
+ * transform (Section 4.1), so only the eigenvalue that divides the
+ * transformed right-hand side differs:
+ *  LAPLACE  the 5-point (2D) / 7-point (3D) Dirichlet Laplacian
+ *           T (x) I + I (x) T (+ the third term): eigenvalue
+ *           lambda_i + lambda_j (+ lambda_l), lambda_k = 4/h^2 sin^2(pi k h/2)
+ *           (Section 4.1, eq. "diag"; eq. "div").
+ *  STOKES   the Stokes-consistent Laplacian of Section 2, the sum over axes
+ *           of B_d B_d^T with the discrete gradients B_x = (G (x) H)/(4h),
+ *           B_y = (H (x) G)/(4h) (G, H: shift difference and shift sum); its
+ *           Kronecker form A1 (x) A2 + A2 (x) A1 (Section 4.1) has, scaled
+ *           by 4 so that smooth modes see -Laplacian, the eigenvalue
+ *           4 (s_i c_j + c_i s_j) / h^2 in 2D and
+ *           4 (s_i c_j c_l + c_i s_j c_l + c_i c_j s_l) / h^2 in 3D, with
+ *           s_k = sin^2(pi k h/2), c_k = cos^2(pi k h/2).  (Section 4.2
+ *           writes the 2D denominator as a sum of one-axis terms; the
+ *           Kronecker form is not such a sum, and it is the one used.) */
+typedef enum {
+  LRP_OP_LAPLACE = 0,
+  LRP_OP_STOKES = 1
+} lrp_operator;
+
+/* Optional knobs; pass NULL for defaults.  Zero fields take defaults.
+ * LRP_EINVAL for max_sweeps > LRP_MAX_SWEEPS, a negative field, an
+ * unknown prec or op. */
 typedef struct {
   int32_t prec;         /* lrp_precision, default LRP_PREC_FP64             */
-  int32_t max_sweeps;   /* cross sweeps cap, default 10                     */
+  int32_t max_sweeps;   /* cross sweeps cap, default 10, <= LRP_MAX_SWEEPS  */
   int32_t rank_cap;     /* cross rank cap k_max, default and max 64         */
   int32_t kick;         /* cross rank growth step, default 8                */
   double maxvol_tau;    /* maxvol dominance bound, default 1.05             */
+  int32_t op;           /* lrp_operator, default LRP_OP_LAPLACE             */
+  int32_t reserved;     /* must be 0                                        */
+  uint64_t seed;        /* offset of the deterministic index sequences: the
+                           evenly spaced padding of the first column set and
+                           the probe rows of rank growth start at
+                           seed mod n.  The method draws no random numbers;
+                           different seeds give different (equally valid)
+                           pivots and the same accuracy.  Default 0.        */
 } lrp_opts;
 
 /* Per-solve report (may be NULL). */
@@ -120,6 +153,16 @@ typedef struct {
   int32_t fwd_prec;     /* lrp_precision used by the forward transform       */
   int32_t inv_prec;     /* lrp_precision used by the inverse transform       */
   double change;        /* last relative change between sweeps (-1: none)   */
+  double err_est;       /* a-posteriori relative error estimate: the
+                           truncation tail ||sigma[R:]|| / ||sigma|| plus
+                           the last change (3D: the largest over the modes
+                           plus the core truncation tails); -1 if none      */
+  float us_phase[3];    /* device time in microseconds of the call's forward
+                           transform, cross sweeps and inverse transform
+                           (HIP events on the call's stream; a batch reports
+                           the batch's phases to every problem; 0 where not
+                           measured: the serving loop)                       */
+  int32_t pad;
 } lrp_info;
 
 typedef struct lrp_ctx lrp_ctx;
@@ -248,6 +291,8 @@ typedef struct {
   double *Gx;           /* 3D output core                                    */
   int64_t ldx;
   double eps;
+  int32_t op;           /* lrp_operator                                      */
+  int32_t reserved;     /* must be 0                                         */
 } lrp_request;
 
 /* Queue a request; never blocks.  *ticket identifies it. */
@@ -264,8 +309,16 @@ lrp_status lrp_serve_step(lrp_ctx *ctx, int32_t *pending);
 
 /* Non-blocking completion check.  LRP_ENOTREADY while the request is queued
  * or running; otherwise *result holds its status, rank_out[] its ranks and
- * *info its report, and the ticket is released. */
+ * *info its report, and the ticket is released.  LRP_EINVAL for a ticket
+ * that is not known (never issued, or already released). */
 lrp_status lrp_poll(lrp_ctx *ctx, uint64_t ticket, int32_t *result,
+                    int32_t rank_out[3], lrp_info *info);
+
+/* Blocking completion: runs scheduling ticks (lrp_serve_step) until the
+ * request of ``ticket`` has finished, then reports it as lrp_poll does.
+ * Other requests advance meanwhile.  LRP_EINVAL for an unknown ticket;
+ * a device error of a tick is returned as it is. */
+lrp_status lrp_wait(lrp_ctx *ctx, uint64_t ticket, int32_t *result,
                     int32_t rank_out[3], lrp_info *info);
 
 #ifdef __cplusplus

@@ -24,37 +24,46 @@ LRP_ENOMEM = -5
 LRP_EDEVICE = -6
 LRP_EBUSY = -7
 LRP_ENOTREADY = -8
+STATUS_NAME = {0: "ok", -1: "einval", -2: "enonfinite", -3: "erankcap", -4: "enoconv",
+               -5: "enomem", -6: "edevice", -7: "ebusy", -8: "enotready"}
 
 PREC = {"fp64": 0, "auto": 1, "fp32": 2, "bf16x3": 3, "int8": 4}
 PREC_NAME = {v: k for k, v in PREC.items()}
+OP = {"laplace": 0, "stokes": 1}
 
 MAX_RANK = 64
 MAX_N = 32767
 MAX_N3 = 1024
+MAX_SWEEPS = 64
+PHASES = ("forward", "cross", "inverse")
 
 # every symbol the header declares
 EXPORTS = ["lrp_create", "lrp_destroy", "lrp_strerror", "lrpoisson_solve2d",
            "lrpoisson_solve2d_batch", "lrpoisson_solve3d", "lrp_submit",
-           "lrp_serve_step", "lrp_poll", "lrp_sine_transform",
+           "lrp_serve_step", "lrp_poll", "lrp_wait", "lrp_sine_transform",
            "lrp_set_kernel_timing", "lrp_kernel_stats"]
 
 
 class LrpOpts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("rank_cap", ctypes.c_int32), ("kick", ctypes.c_int32),
-                ("maxvol_tau", ctypes.c_double)]
+                ("maxvol_tau", ctypes.c_double), ("op", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class LrpInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("sweeps", ctypes.c_int32),
                 ("k", ctypes.c_int32), ("rank", ctypes.c_int32),
                 ("fwd_prec", ctypes.c_int32), ("inv_prec", ctypes.c_int32),
-                ("change", ctypes.c_double)]
+                ("change", ctypes.c_double), ("err_est", ctypes.c_double),
+                ("us_phase", ctypes.c_float * 3), ("pad", ctypes.c_int32)]
 
     def as_dict(self):
         return dict(status=self.status, sweeps=self.sweeps, k=self.k,
                     rank=self.rank, fwd_prec=PREC_NAME.get(self.fwd_prec),
-                    inv_prec=PREC_NAME.get(self.inv_prec), change=self.change)
+                    inv_prec=PREC_NAME.get(self.inv_prec), change=self.change,
+                    err_est=self.err_est,
+                    us_phase=dict(zip(PHASES, (float(x) for x in self.us_phase))))
 
 
 class LrpKernelStat(ctypes.Structure):
@@ -77,7 +86,8 @@ class LrpRequest(ctypes.Structure):
                 ("rmax", ctypes.c_int32 * 3), ("U", ctypes.c_void_p * 3),
                 ("G", ctypes.c_void_p), ("ld", ctypes.c_int64),
                 ("X", ctypes.c_void_p * 3), ("Gx", ctypes.c_void_p),
-                ("ldx", ctypes.c_int64), ("eps", ctypes.c_double)]
+                ("ldx", ctypes.c_int64), ("eps", ctypes.c_double),
+                ("op", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class LrpError(RuntimeError):
@@ -120,6 +130,8 @@ def load(path: str = LIB_PATH):
     lib.lrp_submit.argtypes = [P, ctypes.POINTER(LrpRequest), ctypes.POINTER(ctypes.c_uint64)]
     lib.lrp_serve_step.argtypes = [P, ctypes.POINTER(I32)]
     lib.lrp_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(I32),
+                             ctypes.POINTER(I32), ctypes.POINTER(LrpInfo)]
+    lib.lrp_wait.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(I32),
                              ctypes.POINTER(I32), ctypes.POINTER(LrpInfo)]
     for name in EXPORTS:
         f = getattr(lib, name)
@@ -174,9 +186,11 @@ def empty_colmajor(n, r, device="cuda"):
     return torch.empty((max(r, 1), n), dtype=torch.float64, device=device).T[:, :r]
 
 
-def _opts(prec="fp64", max_sweeps=0, rank_cap=0, kick=0, tau=0.0):
+def _opts(prec="fp64", max_sweeps=0, rank_cap=0, kick=0, tau=0.0, op="laplace",
+          seed=0):
     return LrpOpts(PREC[prec] if isinstance(prec, str) else int(prec),
-                   max_sweeps, rank_cap, kick, tau)
+                   max_sweeps, rank_cap, kick, tau,
+                   OP[op] if isinstance(op, str) else int(op), 0, seed)
 
 
 def _stream(stream):
@@ -360,7 +374,7 @@ class Context:
         return dict(launches=k.launches, columns=k.columns, ms=k.ms, flops=k.flops)
 
     # ---- serving
-    def submit(self, U, V, eps, prec="auto", rmax=None, out=None):
+    def submit(self, U, V, eps, prec="auto", rmax=None, out=None, op="laplace"):
         """Queue a 2D request; returns (ticket, (Ux, Vx))."""
         n, r = U.shape
         rmax = MAX_RANK if rmax is None else rmax
@@ -380,13 +394,15 @@ class Context:
         q.X[1] = _ptr(Vx)
         q.ldx = n
         q.eps = eps
+        q.op = OP[op]
         t = ctypes.c_uint64(0)
         st = self.lib.lrp_submit(self.h, ctypes.byref(q), ctypes.byref(t))
         if st != LRP_OK:
             raise LrpError(st, "lrp_submit")
         return t.value, (Ux, Vx)
 
-    def submit3d(self, U1, U2, U3, G, eps, prec="auto", rmax=None, out=None):
+    def submit3d(self, U1, U2, U3, G, eps, prec="auto", rmax=None, out=None,
+                 op="laplace"):
         """Queue a 3D request (G: Fortran-ordered flat GPU tensor, see
         ``fortran_core``); returns (ticket, (X1, X2, X3, Gbuf)).  The output
         core is Gbuf[:R0*R1*R2] in Fortran order."""
@@ -414,6 +430,7 @@ class Context:
         q.ld = lds[0] if lds else n
         q.ldx = n
         q.eps = eps
+        q.op = OP[op]
         t = ctypes.c_uint64(0)
         st = self.lib.lrp_submit(self.h, ctypes.byref(q), ctypes.byref(t))
         if st != LRP_OK:
@@ -440,11 +457,23 @@ class Context:
             raise LrpError(st, "lrp_poll")
         return res.value, list(ranks), info.as_dict()
 
+    def wait(self, ticket):
+        """Block (running scheduling ticks) until the request has finished;
+        returns (status, ranks, info)."""
+        res = ctypes.c_int32(0)
+        ranks = (ctypes.c_int32 * 3)()
+        info = LrpInfo()
+        st = self.lib.lrp_wait(self.h, ticket, ctypes.byref(res), ranks,
+                               ctypes.byref(info))
+        if st != LRP_OK:
+            raise LrpError(st, "lrp_wait")
+        return res.value, list(ranks), info.as_dict()
+
     # ---- raw call for argument-validation tests
-    def raw_solve2d(self, n, r, U, V, ld, eps, Ux, Vx, ldx, rmax, prec=0):
+    def raw_solve2d(self, n, r, U, V, ld, eps, Ux, Vx, ldx, rmax, prec=0, **kw):
         rank = ctypes.c_int32(-1)
         info = LrpInfo()
-        opts = _opts(prec)
+        opts = _opts(prec, **kw)
         return self.lib.lrpoisson_solve2d(self.h, n, r, U, V, ld, eps,
                                           ctypes.byref(opts), Ux, Vx, ldx, rmax,
                                           ctypes.byref(rank), ctypes.byref(info),

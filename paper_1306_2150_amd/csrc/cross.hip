@@ -244,13 +244,14 @@ __global__ __launch_bounds__(NTHR) void k_change_norms(Solve2D *S) {
   }
 }
 
-// count evenly spaced indices in [0, n) avoiding used[0:nu); floor((2i+1)n/(2count))
-// moved to the next free index (cyclically).  Single thread.
-__device__ void spread_indices(int n, int count, int *used, int nu, int *out) {
+// count evenly spaced indices in [0, n) avoiding used[0:nu);
+// (floor((2i+1)n/(2count)) + off) mod n moved to the next free index
+// (cyclically).  Single thread.
+__device__ void spread_indices(int n, int count, int *used, int nu, int *out, int off) {
   int have = nu;
   for (int i = 0; i < count; ++i) {
     if (have >= n) break;
-    int j = (int)(((long long)(2 * i + 1) * n) / (2LL * count));
+    int j = (int)((((long long)(2 * i + 1) * n) / (2LL * count) + off) % n);
     for (;;) {
       bool taken = false;
       for (int t = 0; t < have; ++t)
@@ -292,6 +293,9 @@ __global__ __launch_bounds__(NTHR) void k_decide(Solve2D *S) {
     else break;
   }
   if (nrm == 0.0) R = 0;
+  double tailR = 0.0;
+  for (int t = kk - 1; t >= R; --t) tailR += s.sig[t] * s.sig[t];
+  s.tail = nrm > 0.0 ? sqrt(tailR) / nrm : 0.0;
   const bool no_slack = (R > kk - s.min_slack) && (kk < min(s.n, s.m));
   int next = NEXT_CONTINUE;
   if (s.nonfinite) {
@@ -318,7 +322,7 @@ __global__ __launch_bounds__(NTHR) void k_decide(Solve2D *S) {
   s.next = next;
   if (next == NEXT_GROW) {
     for (int t = 0; t < kk; ++t) used[t] = s.I[t];
-    spread_indices(s.n, s.kick, used, kk, s.probe);
+    spread_indices(s.n, s.kick, used, kk, s.probe, s.off_r);
   }
 }
 
@@ -333,7 +337,7 @@ __global__ __launch_bounds__(NTHR) void k_growth_score(Solve2D *S) {
   constexpr int PQ = 16;
   __shared__ double uP[PQ * KMAX];
   __shared__ double aP[PQ * KMAX];
-  __shared__ double lP[PQ];
+  __shared__ double lP[PQ], lQ[PQ];
   __shared__ int jn[KMAX];
   __shared__ double rv[4];
   __shared__ int rk[4];
@@ -358,7 +362,12 @@ __global__ __launch_bounds__(NTHR) void k_growth_score(Solve2D *S) {
       aP[e] = (q < nq && c < kk) ? ta[u] : 0.0;
     }
   }
-  for (int q = threadIdx.x; q < nq; q += NTHR) lP[q] = s.lam_r[clamp_row(s.probe[q], s.n)];
+  const bool prod = s.lq_r != nullptr;
+  for (int q = threadIdx.x; q < nq; q += NTHR) {
+    const int p = clamp_row(s.probe[q], s.n);
+    lP[q] = s.lam_r[p];
+    lQ[q] = prod ? s.lq_r[p] : 1.0;
+  }
   for (int t = threadIdx.x; t < kk; t += NTHR) jn[t] = s.Jn[t];
   __syncthreads();
   const int j = blockIdx.x * NTHR + threadIdx.x;
@@ -390,11 +399,11 @@ __global__ __launch_bounds__(NTHR) void k_growth_score(Solve2D *S) {
         for (int q = 0; q < PQ; ++q) skel[q] += aP[q * KMAX + c0 + t] * bc[t];
       }
     }
-    const double lj = s.lam_c[j];
+    const double lj = s.lam_c[j], qj = prod ? s.lq_c[j] : 1.0;
     best = 0.0;
 #pragma unroll
     for (int q = 0; q < PQ; ++q)
-      if (q < nq) best = fmax(best, fabs(num[q] / (lP[q] + lj) - skel[q]));
+      if (q < nq) best = fmax(best, fabs(num[q] / den_of(prod, lP[q], lQ[q], lj, qj) - skel[q]));
     for (int t = 0; t < kk; ++t)
       if (jn[t] == j) best = -1.0;
   }
@@ -484,7 +493,7 @@ __global__ void k_init_J(Solve2D *S) {
   __shared__ int used[2 * KMAX];
   const int kin = s.k, k0 = s.k0;
   for (int t = 0; t < kin; ++t) used[t] = s.J[t];
-  if (k0 > kin) spread_indices(s.m, k0 - kin, used, kin, s.J + kin);
+  if (k0 > kin) spread_indices(s.m, k0 - kin, used, kin, s.J + kin, s.off_c);
   s.k = k0;
   s.kp = 0;
   s.sweep = 0;

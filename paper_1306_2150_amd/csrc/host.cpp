@@ -106,22 +106,29 @@ const GridTables *get_tables(lrp_ctx *ctx, int n, lrp_status *err) {
     const uint32_t lo = bf16_rne_host((float)(v - (long double)bf16_float_host(hi)));
     tbf[q] = hi | (lo << 16);
   }
-  std::vector<double> lam(n);
+  // lambda_k, then the Stokes operator's factors 2 sin^2 / h and 2 cos^2 / h
+  // of the half angle pi k/(2N) (cos^2 as sin^2 of the complementary angle)
+  std::vector<double> lam(3 * (size_t)n);
   const long double N2 = (long double)N * (long double)N;
   for (int k = 1; k <= n; ++k) {
     const long double s = sinl(pi * (long double)k / (2.0L * (long double)N));
+    const long double c = sinl(pi * (long double)(N - k) / (2.0L * (long double)N));
     lam[k - 1] = (double)(4.0L * N2 * s * s);
+    lam[n + k - 1] = (double)(2.0L * (long double)N * s * s);
+    lam[2 * n + k - 1] = (double)(2.0L * (long double)N * c * c);
   }
   GridTables g;
   g.n = n;
-  g.bytes = tab_bytes + (size_t)n * 8;
+  g.bytes = tab_bytes + (size_t)n * 24;
   void *p = nullptr;
   *err = dev_alloc(ctx, &p, g.bytes);
   if (*err != LRP_OK) return nullptr;
   g.tab = p;
   g.lam = (double *)((char *)p + tab_bytes);
+  g.sp = g.lam + n;
+  g.sq = g.lam + 2 * (size_t)n;
   if (hipMemcpy(g.tab, host.data(), tab_bytes, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(g.lam, lam.data(), (size_t)n * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(g.lam, lam.data(), (size_t)n * 24, hipMemcpyHostToDevice) != hipSuccess) {
     dev_free(ctx, p, g.bytes);
     *err = LRP_EDEVICE;
     return nullptr;
@@ -139,6 +146,8 @@ Plan make_plan(const lrp_opts *o, double eps, int n) {
   p.kick = (o && o->kick > 0) ? std::min(o->kick, 16) : 8;
   p.min_slack = std::max(1, p.kick / 2);
   p.tau = (o && o->maxvol_tau > 1.0) ? o->maxvol_tau : 1.05;
+  p.op = o ? o->op : LRP_OP_LAPLACE;
+  p.seed = o ? o->seed : 0;
   if (prec == LRP_PREC_AUTO) {
     if (dst_i8_supported(n)) {
       // exact int8 slices: about 1e-12, faster than the float64 and float32
@@ -157,6 +166,35 @@ Plan make_plan(const lrp_opts *o, double eps, int n) {
     p.fwd_prec = p.inv_prec = LRP_PREC_FP64;
   }
   return p;
+}
+
+lrp_status check_opts(const lrp_opts *o) {
+  if (!o) return LRP_OK;
+  if (o->prec < 0 || o->prec > LRP_PREC_INT8) return LRP_EINVAL;
+  if (o->max_sweeps < 0 || o->max_sweeps > LRP_MAX_SWEEPS) return LRP_EINVAL;
+  if (o->rank_cap < 0 || o->kick < 0 || o->maxvol_tau < 0.0) return LRP_EINVAL;
+  if (o->op != LRP_OP_LAPLACE && o->op != LRP_OP_STOKES) return LRP_EINVAL;
+  if (o->reserved != 0) return LRP_EINVAL;
+  return LRP_OK;
+}
+
+void phase_mark(lrp_ctx *ctx, int i, hipStream_t st) {
+  if (!ctx->phase_ev[i] && hipEventCreate(&ctx->phase_ev[i]) != hipSuccess) {
+    ctx->phase_ev[i] = nullptr;
+    return;
+  }
+  (void)hipEventRecord(ctx->phase_ev[i], st);
+}
+
+void phase_times(lrp_ctx *ctx, float us[3]) {
+  for (int i = 0; i < 3; ++i) {
+    float ms = 0.f;
+    if (ctx->phase_ev[i] && ctx->phase_ev[i + 1] &&
+        hipEventElapsedTime(&ms, ctx->phase_ev[i], ctx->phase_ev[i + 1]) == hipSuccess)
+      us[i] = 1000.f * ms;
+    else
+      us[i] = 0.f;
+  }
 }
 
 // ------------------------------------------------------------- Group2D
@@ -207,8 +245,11 @@ size_t cross_slot_bytes(int n, int m) {
   return slot_layout(n, m, make_tree(std::max(n, m), KMAX)).total;
 }
 
-Group2D::Group2D(lrp_ctx *ctx, int n, int cap, int m, const double *lam_c)
-    : ctx_(ctx), n_(n), cap_(cap), m_(m > 0 ? m : n), lam_c_(lam_c) {}
+Group2D::Group2D(lrp_ctx *ctx, int n, int cap, int m, const double *const *col)
+    : ctx_(ctx), n_(n), cap_(cap), m_(m > 0 ? m : n) {
+  if (col)
+    for (int t = 0; t < 3; ++t) col_[t] = col[t];
+}
 
 Group2D::~Group2D() {
   if (stream_) {
@@ -264,7 +305,8 @@ lrp_status Group2D::init() {
     s.ldv = m_;
     s.ldc = (long)mx;
     s.lam_r = tabs_->lam;
-    s.lam_c = lam_c_ ? lam_c_ : tabs_->lam;
+    s.lam_c = col_[0] ? col_[0] : tabs_->lam;
+    s.lq_r = s.lq_c = nullptr;
     s.Uh = (double *)(b + L.off_Uh);
     s.Vh = (double *)(b + L.off_Vh);
     double *up = (double *)(b + L.off_upan);
@@ -331,6 +373,20 @@ void Group2D::setup_slot(int i, const double *U, const double *V, long ld, int r
   s.Ux = Ux;
   s.Vx = Vx;
   s.ldx = ldx;
+  // the operator's eigenvalue tables (Solve2D: D_ij from lam and lq)
+  if (plan.op == LRP_OP_STOKES) {
+    s.lam_r = tabs_->sp;
+    s.lq_r = tabs_->sq;
+    s.lam_c = col_[0] ? col_[1] : tabs_->sp;
+    s.lq_c = col_[0] ? col_[2] : tabs_->sq;
+  } else {
+    s.lam_r = tabs_->lam;
+    s.lq_r = nullptr;
+    s.lam_c = col_[0] ? col_[0] : tabs_->lam;
+    s.lq_c = nullptr;
+  }
+  s.off_r = (int)(plan.seed % (uint64_t)n_);
+  s.off_c = (int)(plan.seed % (uint64_t)m_);
   // reset pointer roles that a previous occupant may have swapped
   double *lo = std::min(s.A, s.Ap), *hi = std::max(s.A, s.Ap);
   s.A = lo;
@@ -359,6 +415,7 @@ void Group2D::setup_slot(int i, const double *U, const double *V, long ld, int r
   s.kgrow = 0;
   s.nrm = 0.0;
   s.change = -1.0;
+  s.tail = -1.0;
   s.active = (r > 0) ? ACT_INIT : ACT_DONE;
 }
 
@@ -479,6 +536,19 @@ lrp_status Group2D::inverse(const std::vector<int> &slots, hipStream_t st) {
   return LRP_OK;
 }
 
+void fill_info2d(const Solve2D &s, const Plan &plan, lrp_info *info) {
+  info->status = s.status;
+  info->sweeps = s.sweep;
+  info->k = s.k;
+  info->rank = s.R;
+  info->fwd_prec = plan.fwd_prec;
+  info->inv_prec = plan.inv_prec;
+  info->change = s.change;
+  // truncation tail plus the last change between sweeps
+  info->err_est = (s.tail >= 0.0) ? s.tail + (s.change >= 0.0 ? s.change : 0.0) : -1.0;
+  if (s.r == 0 || s.nrm == 0.0) info->err_est = 0.0;
+}
+
 }  // namespace lrp
 
 using namespace lrp;
@@ -576,6 +646,9 @@ lrp_status lrp_sine_transform(lrp_ctx *ctx, int64_t n, int32_t ncols,
                   st) != hipSuccess)
       return LRP_EDEVICE;
   }
+  // the staging buffers belong to the context: the call returns after its
+  // work completed, so that a call on another stream may reuse them
+  if (hipStreamSynchronize(st) != hipSuccess) return LRP_EDEVICE;
   return LRP_OK;
 }
 
@@ -622,6 +695,8 @@ lrp_status lrp_destroy(lrp_ctx *ctx) {
   ctx->serve3_groups.clear();
   for (auto &kv : ctx->tables) dev_free(ctx, kv.second.tab, kv.second.bytes);
   if (ctx->serve_stream) (void)hipStreamDestroy(ctx->serve_stream);
+  for (hipEvent_t e : ctx->phase_ev)
+    if (e) (void)hipEventDestroy(e);
   delete ctx;
   return LRP_OK;
 }
@@ -640,7 +715,7 @@ lrp_status lrpoisson_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t count,
                                    void *stream) {
   if (!ctx || !probs || count < 0) return LRP_EINVAL;
   if (n < 1 || n > LRP_MAX_N) return LRP_EINVAL;
-  if (opts && (opts->prec < 0 || opts->prec > LRP_PREC_INT8)) return LRP_EINVAL;
+  if (check_opts(opts) != LRP_OK) return LRP_EINVAL;
   if (opts && opts->prec == LRP_PREC_INT8 && !dst_i8_supported((int)n)) return LRP_EINVAL;
   for (int i = 0; i < count; ++i) {
     lrp_status e = check_problem(n, probs[i]);
@@ -673,17 +748,27 @@ lrp_status lrpoisson_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t count,
   }
   lrp_status e = g.upload_all(g.cap(), st);
   if (e != LRP_OK) return e;
+  phase_mark(ctx, 0, st);
   if ((e = g.forward(all, st)) != LRP_OK) return e;
-  for (int sweep = 0; sweep <= 64; ++sweep) {
+  phase_mark(ctx, 1, st);
+  // one step for the initial column choice, then at most max_sweeps
+  // (<= LRP_MAX_SWEEPS) sweeps: the device stops every slot by then
+  for (int step = 0; step <= LRP_MAX_SWEEPS; ++step) {
     if ((e = g.step(st)) != LRP_OK) return e;
     if ((e = g.fetch(st)) != LRP_OK) return e;
     bool any = false;
     for (int i = 0; i < count; ++i) any |= g.host(i).active != ACT_DONE;
     if (!any) break;
   }
+  phase_mark(ctx, 2, st);
   std::vector<int> out;
   for (int i = 0; i < count; ++i) {
     Solve2D &s = g.host(i);
+    if (s.active != ACT_DONE) {   // cannot happen: the device caps the sweeps
+      s.status = LRP_EDEVICE;
+      s.R = 0;
+      continue;
+    }
     if (s.status == LRP_ENONFINITE || s.r == 0) {
       s.R = 0;
       continue;
@@ -695,19 +780,18 @@ lrp_status lrpoisson_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t count,
     out.push_back(i);
   }
   if ((e = g.inverse(out, st)) != LRP_OK) return e;
+  phase_mark(ctx, 3, st);
   if (hipStreamSynchronize(st) != hipSuccess) return LRP_EDEVICE;
+  float us[3];
+  phase_times(ctx, us);
   lrp_status first = LRP_OK;
   for (int i = 0; i < count; ++i) {
     const Solve2D &s = g.host(i);
     lrp_problem2d &p = probs[i];
+    std::memset(&p.info, 0, sizeof(p.info));
     p.rank_out = s.R;
-    p.info.status = s.status;
-    p.info.sweeps = s.sweep;
-    p.info.k = s.k;
-    p.info.rank = s.R;
-    p.info.fwd_prec = g.plan(i).fwd_prec;
-    p.info.inv_prec = g.plan(i).inv_prec;
-    p.info.change = s.change;
+    fill_info2d(s, g.plan(i), &p.info);
+    for (int t = 0; t < 3; ++t) p.info.us_phase[t] = us[t];
     if (first == LRP_OK && s.status != LRP_OK) first = (lrp_status)s.status;
   }
   return first;
@@ -732,7 +816,10 @@ lrp_status lrpoisson_solve2d(lrp_ctx *ctx, int64_t n, int32_t rank,
   p.ldx = ldx;
   lrp_status e = lrpoisson_solve2d_batch(ctx, n, 1, &p, opts, stream);
   *rank_out = p.rank_out;
-  if (info) *info = p.info;
+  if (info) {
+    *info = p.info;
+    if (e == LRP_EINVAL) info->status = LRP_EINVAL;
+  }
   return e;
 }
 

@@ -26,6 +26,8 @@ struct GridTables {
   int n = 0;
   void *tab = nullptr;      // [f64 quarter][f32 quarter][bf16 pair quarter]
   double *lam = nullptr;    // lambda_k, k = 1..n
+  double *sp = nullptr;     // Stokes operator factors 2 sin^2(pi k h/2)/h,
+  double *sq = nullptr;     //   2 cos^2(pi k h/2)/h, k = 1..n
   size_t bytes = 0;
 };
 
@@ -34,15 +36,18 @@ struct Plan {
   int fwd_prec, inv_prec;
   int max_sweeps, kcap, kick, min_slack;
   double tau;
+  int op;             // lrp_operator
+  uint64_t seed;      // offset of the spread index sequences
 };
 
 // A group of cross-approximation slots of one shape.  Every kernel launch
 // covers all slots; each slot's `active` flag selects which launches act on
-// it.  2D solves: n x n with lambda on both sides.  3D path: the n x n^2
-// mode unfoldings, column denominators lam_c (n^2 entries).
+// it.  2D solves: n x n with the grid's tables on both sides.  3D path: the
+// n x n^2 mode unfoldings, with column tables over the n^2 pairs
+// (col[0]: Laplace mu, col[1], col[2]: the Stokes factors).
 class Group2D {
  public:
-  Group2D(lrp_ctx *ctx, int n, int cap, int m = 0, const double *lam_c = nullptr);
+  Group2D(lrp_ctx *ctx, int n, int cap, int m = 0, const double *const *col = nullptr);
   ~Group2D();
   lrp_status init();                       // allocate
   size_t bytes() const { return bytes_; }
@@ -87,7 +92,7 @@ class Group2D {
   lrp_status dst_cols(std::vector<DstCol> &cols, int prec, hipStream_t st);
   lrp_ctx *ctx_;
   int n_, cap_, m_;
-  const double *lam_c_;
+  const double *col_[3] = {nullptr, nullptr, nullptr};
   Tree talloc_;
   size_t per_slot_ = 0, bytes_ = 0;
   char *ws_ = nullptr;
@@ -145,7 +150,7 @@ class Group3D {
   int n_, cap_;
   size_t bytes_ = 0;
   char *ws_ = nullptr;
-  double *mu_ = nullptr;
+  double *mu_ = nullptr;     // Laplace column table, then the two Stokes ones
   std::unique_ptr<Group2D> inner_;
   Solve3D *d_s_ = nullptr, *h_s_ = nullptr;
   std::vector<Plan> plans_;
@@ -201,12 +206,20 @@ struct lrp_ctx {
   };
   std::vector<PendingTime> pending_times;
   lrp_kernel_stat kstat[5] = {};
+  // phase events of the synchronous calls (forward, cross, inverse)
+  hipEvent_t phase_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::mutex mu;
 };
 
 namespace lrp {
 const GridTables *get_tables(lrp_ctx *ctx, int n, lrp_status *err);
 Plan make_plan(const lrp_opts *o, double eps, int n);
+// LRP_EINVAL for options outside their documented ranges
+lrp_status check_opts(const lrp_opts *o);
+// phase timing of a synchronous call: record event i (0..3) on st
+void phase_mark(lrp_ctx *ctx, int i, hipStream_t st);
+// after the stream completed: the three phase durations in microseconds
+void phase_times(lrp_ctx *ctx, float us[3]);
 lrp_status dev_alloc(lrp_ctx *ctx, void **p, size_t bytes);
 // launch_dst with optional event timing for the context
 hipError_t timed_dst(lrp_ctx *ctx, int prec, int n, const void *tab,
@@ -220,6 +233,8 @@ lrp_status check_problem3d(int64_t n, const int32_t rank[3], const double *const
                            double *const X[3], int64_t ldx, const double *Gx,
                            const int32_t rmax[3]);
 void fill_info3d(Group3D &g, int i, int32_t rank_out[3], lrp_info *info);
+// report of a finished 2D slot (status, sweeps, ranks, plan, estimates)
+void fill_info2d(const Solve2D &s, const Plan &plan, lrp_info *info);
 // device bytes of one slot of a cross group of shape n x m
 size_t cross_slot_bytes(int n, int m);
 // device bytes of one 3D slot of grid size n (its three mode slots included)

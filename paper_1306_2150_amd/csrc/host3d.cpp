@@ -44,16 +44,18 @@ lrp_status Group3D::init() {
   const size_t t_elems = (size_t)KMAX * KMAX * n_;
   const size_t per_slot = own_slot_bytes(n_);
   const size_t solves_b = align256(sizeof(Solve3D) * cap_);
-  bytes_ = align256(m * 8) + solves_b + per_slot * cap_;
+  // column tables over the pairs: Laplace mu, Stokes Pc and Qc
+  bytes_ = align256(3 * m * 8) + solves_b + per_slot * cap_;
   void *p = nullptr;
   if ((err = dev_alloc(ctx_, &p, bytes_)) != LRP_OK) return err;
   ws_ = (char *)p;
   mu_ = (double *)ws_;
-  d_s_ = (Solve3D *)(ws_ + align256(m * 8));
+  d_s_ = (Solve3D *)(ws_ + align256(3 * m * 8));
   char *slots = (char *)d_s_ + solves_b;
-  HIPCHK3(launch_mu(n_, tabs->lam, mu_, nullptr));
+  HIPCHK3(launch_mu(n_, tabs->lam, tabs->sp, tabs->sq, mu_, mu_ + m, mu_ + 2 * m, nullptr));
   HIPCHK3(hipDeviceSynchronize());
-  inner_.reset(new Group2D(ctx_, n_, 3 * cap_, (int)m, mu_));
+  const double *col[3] = {mu_, mu_ + m, mu_ + 2 * m};
+  inner_.reset(new Group2D(ctx_, n_, 3 * cap_, (int)m, col));
   if ((err = inner_->init()) != LRP_OK) {
     inner_.reset();
     return err;
@@ -197,16 +199,19 @@ lrp_status Group3D::finish(const std::vector<int> &slots, hipStream_t st) {
 void fill_info3d(Group3D &g, int i, int32_t rank_out[3], lrp_info *info) {
   const Solve3D &s = g.host(i);
   int sweeps = 0, k = 0, R = 0;
-  double change = -1.0;
+  double change = -1.0, est = 0.0;
   for (int d = 0; d < 3; ++d) {
     const Solve2D &m = g.modes().host(3 * i + d);
     sweeps = std::max(sweeps, m.sweep);
     k = std::max(k, m.k);
     R = std::max(R, s.R[d]);
     change = std::max(change, m.change);
+    // mode cross: its truncation tail and last change
+    est = std::max(est, std::max(m.tail, 0.0) + std::max(m.change, 0.0));
     if (rank_out) rank_out[d] = s.R[d];
   }
   if (info) {
+    std::memset(info, 0, sizeof(*info));
     info->status = s.status;
     info->sweeps = sweeps;
     info->k = k;
@@ -214,6 +219,9 @@ void fill_info3d(Group3D &g, int i, int32_t rank_out[3], lrp_info *info) {
     info->fwd_prec = g.plan(i).fwd_prec;
     info->inv_prec = g.plan(i).inv_prec;
     info->change = change;
+    // the core's HOSVD truncation at eps/sqrt(3) per mode adds at most
+    // sqrt(3 (eps/sqrt(3))^2) = eps
+    info->err_est = (s.nrm == 0.0) ? 0.0 : est + s.eps;
   }
 }
 
@@ -254,7 +262,7 @@ extern "C" lrp_status lrpoisson_solve3d(lrp_ctx *ctx, int64_t n, const int32_t r
                                         int64_t ldx, double *Gx, const int32_t rmax[3],
                                         int32_t rank_out[3], lrp_info *info, void *stream) {
   if (!ctx || !rank_out) return LRP_EINVAL;
-  if (opts && (opts->prec < 0 || opts->prec > LRP_PREC_INT8)) return LRP_EINVAL;
+  if (check_opts(opts) != LRP_OK) return LRP_EINVAL;
   if (opts && opts->prec == LRP_PREC_INT8 && !dst_i8_supported((int)n)) return LRP_EINVAL;
   const double *U[3] = {U1, U2, U3};
   double *X[3] = {U1x, U2x, U3x};
@@ -281,17 +289,24 @@ extern "C" lrp_status lrpoisson_solve3d(lrp_ctx *ctx, int64_t n, const int32_t r
   const int r[3] = {rank[0], rank[1], rank[2]};
   const int rm[3] = {rmax[0], rmax[1], rmax[2]};
   g.setup_slot(0, U, ld, r, G, eps, X, ldx, Gx, rm, plan);
+  phase_mark(ctx, 0, st);
   if ((e = g.start({0}, st)) != LRP_OK) return e;
+  phase_mark(ctx, 1, st);
+  // the mode crosses stop after at most max_sweeps (<= LRP_MAX_SWEEPS)
+  // sweeps; the core and its rounding take a few more steps
   bool done = false;
-  for (int it = 0; it <= 3 * 64 && !done; ++it) {
+  for (int it = 0; it <= LRP_MAX_SWEEPS + 8 && !done; ++it) {
     if ((e = g.step(st)) != LRP_OK) return e;
     if ((e = g.fetch(st)) != LRP_OK) return e;
     done = g.host(0).phase == P3_DONE;
   }
   if (!done) return LRP_EDEVICE;
+  phase_mark(ctx, 2, st);
   if ((e = g.finish({0}, st)) != LRP_OK) return e;
+  phase_mark(ctx, 3, st);
   if (hipStreamSynchronize(st) != hipSuccess) return LRP_EDEVICE;
   g.host(0).phase = P3_IDLE;
   fill_info3d(g, 0, rank_out, info);
+  if (info) phase_times(ctx, info->us_phase);
   return (lrp_status)g.host(0).status;
 }

@@ -40,10 +40,14 @@ struct Tree {
 // kernels and copied back to the host once per sweep.
 struct Solve2D {
   // ---- constants
-  // The matrix approximated is Xh_ij = (Uh_i . Vh_j) / (lam_r[i] + lam_c[j]),
-  // i < n, j < m.  A 2D solve has m = n and lam_c = lam_r = lambda; a mode of
-  // the 3D path has m = n^2 (pairs of the other two modes) and
-  // lam_c[j + n l] = lambda_j + lambda_l.
+  // The matrix approximated is Xh_ij = (Uh_i . Vh_j) / D_ij, i < n, j < m,
+  // with the operator's eigenvalue (see den_of)
+  //   D_ij = lam_r[i] + lam_c[j]                          (lq_r == nullptr)
+  //   D_ij = lam_r[i] * lq_c[j] + lq_r[i] * lam_c[j]      (otherwise).
+  // A 2D Laplace solve has m = n and lam_c = lam_r = lambda; the Stokes
+  // operator takes lam = 2 sin^2(pi k h/2)/h, lq = 2 cos^2(pi k h/2)/h.  A
+  // mode of the 3D path has m = n^2 (pairs of the other two modes) and
+  // column tables over the pairs (j, l), index j + n l.
   int n, m, r, kcap, kick, max_sweeps, min_slack, rmax;
   double eps, tau;
   const double *U, *V;
@@ -51,6 +55,8 @@ struct Solve2D {
   double *Ux, *Vx;
   long ldx;
   const double *lam_r, *lam_c;
+  const double *lq_r, *lq_c;
+  int off_r, off_c;         // start offsets of the spread index sequences
   // ---- workspace.  Row-side panels (n rows) have leading dimension ldu,
   // column-side panels (m rows) ldv, the shared ones (C, Hv) ldc >= both.
   long ldu, ldv, ldc;
@@ -92,6 +98,7 @@ struct Solve2D {
   int kgrow;                // columns to add on growth
   double nrm;               // ||sigma||
   double change;            // last relative change, -1 if none
+  double tail;              // ||sigma[R:]|| / ||sigma|| of the last sweep
   double chg_part[2];       // change pieces
 };
 
@@ -225,6 +232,13 @@ __device__ __forceinline__ double bcast_f64(double v, int src) {
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// The operator's eigenvalue D_ij from the row-side values (a = lam_r[i],
+// b = lq_r[i]) and the column-side values (c = lam_c[j], d = lq_c[j]);
+// `prod` selects the product form of the Stokes operator (wave-uniform).
+__device__ __forceinline__ double den_of(bool prod, double a, double b, double c, double d) {
+  return prod ? a * d + b * c : a + c;
+}
+
 // Tile order of a GEMM-like launch of R x C tiles (R row tiles, C column
 // tiles) on a 1D grid.  Workgroup L is dispatched to XCD L mod 8, and each
 // XCD has its own L2.
@@ -313,7 +327,8 @@ hipError_t launch_decide(int n, int m, Solve2D *s, int nsolves, int kmax,
 hipError_t launch_init_J(Solve2D *s, int nsolves, hipStream_t st);
 
 // ---- 3D path (tucker.hip)
-hipError_t launch_mu(int n, const double *lam, double *mu, hipStream_t st);
+hipError_t launch_mu(int n, const double *lam, const double *sp, const double *sq,
+                     double *mu, double *pc, double *qc, hipStream_t st);
 hipError_t launch_unfold_factors(Solve3D *s, int nsolves, int n, int rmax,
                                  hipStream_t st);
 hipError_t launch_core_build(Solve3D *s, int nsolves, hipStream_t st);

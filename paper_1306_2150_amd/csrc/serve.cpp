@@ -20,8 +20,9 @@
 //      slot states back to the host.
 // A slow group (a large 3D grid) therefore never holds back a fast one.
 #include <algorithm>
-#include <map>
 #include <cstring>
+#include <map>
+#include <thread>
 
 #include "host.h"
 
@@ -34,6 +35,8 @@ constexpr size_t SERVE3_SHARE = (size_t)16 << 30;   // bytes per 3D group
 
 lrp_status check_request(const lrp_request &q) {
   if (q.prec < 0 || q.prec > LRP_PREC_INT8) return LRP_EINVAL;
+  if (q.op != LRP_OP_LAPLACE && q.op != LRP_OP_STOKES) return LRP_EINVAL;
+  if (q.reserved != 0) return LRP_EINVAL;
   if (q.prec == LRP_PREC_INT8 && (q.n < 1 || q.n > LRP_MAX_N || !dst_i8_supported((int)q.n)))
     return LRP_EINVAL;
   if (q.dim == 3) {
@@ -96,6 +99,7 @@ Plan request_plan(const lrp_request &q) {
   lrp_opts o;
   std::memset(&o, 0, sizeof(o));
   o.prec = q.prec;
+  o.op = q.op;
   return make_plan(&o, q.eps, (int)q.n);
 }
 
@@ -169,13 +173,7 @@ lrp_status tick2d(lrp_ctx *ctx, Group2D *g) {
     if (s.active != ACT_DONE) continue;
     lrp_info &info = sv.result[slot];
     std::memset(&info, 0, sizeof(info));
-    info.status = s.status;
-    info.sweeps = s.sweep;
-    info.k = s.k;
-    info.rank = s.R;
-    info.fwd_prec = g->plan(slot).fwd_prec;
-    info.inv_prec = g->plan(slot).inv_prec;
-    info.change = s.change;
+    fill_info2d(s, g->plan(slot), &info);
     if (s.status == LRP_ENONFINITE || s.r == 0) {
       info.rank = 0;
     } else if (s.R > s.rmax) {
@@ -385,6 +383,21 @@ lrp_status lrp_poll(lrp_ctx *ctx, uint64_t ticket, int32_t *result,
   if (info) *info = it->second.info;
   ctx->finished.erase(it);
   return LRP_OK;
+}
+
+lrp_status lrp_wait(lrp_ctx *ctx, uint64_t ticket, int32_t *result,
+                    int32_t rank_out[3], lrp_info *info) {
+  if (!ctx) return LRP_EINVAL;
+  for (;;) {
+    const lrp_status p = lrp_poll(ctx, ticket, result, rank_out, info);
+    if (p != LRP_ENOTREADY) return p;
+    // every tick of a group waits for nothing: a group whose enqueued work
+    // has not completed is skipped, so give the device time between ticks
+    int32_t pending = 0;
+    const lrp_status e = lrp_serve_step(ctx, &pending);
+    if (e != LRP_OK) return e;
+    std::this_thread::yield();
+  }
 }
 
 }  // extern "C"

@@ -49,10 +49,12 @@ __device__ inline int ts_phase(int which) {
 // against Vh[J]) or of the cross rows Xh[I, :]^T (TS_C_TO_Q1: rows of Vh
 // against Uh[I]), evaluated straight into the register panel instead of
 // being written to and read back from memory:
-//     y(i, c) = (P_i . Qm_sel[c]) / (lp[i] + lq[sel[c]]),
-// the rank-r numerator summed in ascending order.  The selected rows of Qm
-// and their eigenvalues are staged in LDS (qs: [alpha][c], NC columns);
-// every wave reads the same P rows, which the vector cache serves.
+//     y(i, c) = (P_i . Qm_sel[c]) / D(i, sel[c]),
+// the rank-r numerator summed in ascending order, D the operator's
+// eigenvalue (den_of; it is symmetric in the two sides).  The selected rows
+// of Qm and their eigenvalue factors are staged in LDS (qs: [alpha][c], NC
+// columns; ls: [c] and [NC + c]); every wave reads the same P rows, which
+// the vector cache serves.
 template <int NS>
 __device__ __forceinline__ void cross_panel(double (&y)[NS][4], int which,
                                             const Solve2D &s, int r0, int m,
@@ -62,6 +64,8 @@ __device__ __forceinline__ void cross_panel(double (&y)[NS][4], int which,
   const double *P = cols ? s.Uh : s.Vh, *Qm = cols ? s.Vh : s.Uh;
   const long ldp = cols ? s.ldu : s.ldv, ldq = cols ? s.ldv : s.ldu;
   const double *lp = cols ? s.lam_r : s.lam_c, *lq = cols ? s.lam_c : s.lam_r;
+  const double *lp2 = cols ? s.lq_r : s.lq_c, *lq2 = cols ? s.lq_c : s.lq_r;
+  const bool prod = lp2 != nullptr;
   const int *sel = cols ? s.J : s.I;
   const int other = cols ? s.m : s.n;
   const int kk = s.k, r = s.r;
@@ -69,8 +73,10 @@ __device__ __forceinline__ void cross_panel(double (&y)[NS][4], int which,
     const int a = e / NC, c = e - a * NC;
     qs[e] = (c < kk) ? Qm[clamp_row(sel[c], other) + (long)a * ldq] : 0.0;
   }
-  for (int c = threadIdx.x; c < NC; c += NTHR)
+  for (int c = threadIdx.x; c < NC; c += NTHR) {
     ls[c] = (c < kk) ? lq[clamp_row(sel[c], other)] : 1.0;
+    ls[NC + c] = (c < kk && prod) ? lq2[clamp_row(sel[c], other)] : 1.0;
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double *Pr = P + r0 + lane;
@@ -100,10 +106,11 @@ __device__ __forceinline__ void cross_panel(double (&y)[NS][4], int which,
   for (int q = 0; q < 4; ++q) {
     const int i = lane + 64 * q;
     const double li = (i < m) ? lp[r0 + i] : 1.0;
+    const double li2 = (i < m && prod) ? lp2[r0 + i] : 1.0;
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl) {
       const int c = wave + 4 * sl;
-      y[sl][q] = (c < kk && i < m) ? y[sl][q] / (li + ls[c]) : 0.0;
+      y[sl][q] = (c < kk && i < m) ? y[sl][q] / den_of(prod, li, li2, ls[c], ls[NC + c]) : 0.0;
     }
   }
 }
@@ -116,7 +123,7 @@ __global__ __launch_bounds__(NTHR) void k_tsqr_leaf(int which, int n, Tree tr,
   __shared__ double vbuf[2 * PANEL_M];
   __shared__ double taus[KMAX];
   __shared__ double qs[CROSS ? KMAX * 4 * NS : 1];
-  __shared__ double ls[CROSS ? 4 * NS : 1];
+  __shared__ double ls[CROSS ? 8 * NS : 1];
   const int kk = s.k;
   const int b = blockIdx.x;
   const int r0 = b * PANEL_M;

@@ -34,12 +34,21 @@ __device__ __forceinline__ void other_modes(int d, int &p, int &q) {
   q = (d == 2) ? 1 : 2;
 }
 
-__global__ void k_mu(int n, const double *__restrict__ lam, double *mu) {
+// Column tables of the mode unfoldings over the pairs (j, l), index j + n l:
+// Laplace mu = lambda_j + lambda_l; Stokes (p = 2 sin^2/h, q = 2 cos^2/h of
+// the half angles) the two factors of
+// D = 4 (s_i c_j c_l + c_i s_j c_l + c_i c_j s_l) / h^2 = p_i Qc + q_i Pc,
+// Pc = h/2 (p_j q_l + q_j p_l), Qc = h/2 q_j q_l.
+__global__ void k_mu(int n, const double *__restrict__ lam, const double *__restrict__ sp,
+                     const double *__restrict__ sq, double *mu, double *pc, double *qc) {
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long m = (long)n * n;
   if (idx >= m) return;
   const int j = (int)(idx % n), l = (int)(idx / n);
+  const double hh = 0.5 / (double)(n + 1);
   mu[idx] = lam[j] + lam[l];
+  pc[idx] = hh * (sp[j] * sq[l] + sq[j] * sp[l]);
+  qc[idx] = hh * (sq[j] * sq[l]);
 }
 
 // T_d[a + r_d (b + r_p l)] = sum_c G_d[a, b, c] Uh_q[l, c]   (blockIdx.z = 3 s + d)
@@ -169,9 +178,16 @@ __global__ __launch_bounds__(NTHR) void k_core_stage(int st, Solve3D *S) {
     }
     if (st == 2) {
       const Solve2D &m0 = *s.inner[0], &m1 = *s.inner[1];
-      const double den = m0.lam_r[clamp_row(m0.I[i0], s.n)] +
-                         m1.lam_r[clamp_row(m1.I[i1], s.n)] +
-                         ia.lam_r[clamp_row(ia.I[i2], s.n)];
+      const int j0 = clamp_row(m0.I[i0], s.n), j1 = clamp_row(m1.I[i1], s.n),
+                j2 = clamp_row(ia.I[i2], s.n);
+      double den;
+      if (ia.lq_r) {   // Stokes: h/2 (p0 q1 q2 + q0 p1 q2 + q0 q1 p2)
+        const double p0 = m0.lam_r[j0], p1 = m1.lam_r[j1], p2 = ia.lam_r[j2];
+        const double q0 = m0.lq_r[j0], q1 = m1.lq_r[j1], q2 = ia.lq_r[j2];
+        den = (0.5 / (double)(s.n + 1)) * (p0 * q1 * q2 + q0 * p1 * q2 + q0 * q1 * p2);
+      } else {
+        den = m0.lam_r[j0] + m1.lam_r[j1] + ia.lam_r[j2];
+      }
       acc /= den;
     }
     g.out[o] = acc;
@@ -287,9 +303,11 @@ __global__ void k_tucker_done(Solve3D *S) {
 
 }  // namespace
 
-hipError_t launch_mu(int n, const double *lam, double *mu, hipStream_t st) {
+hipError_t launch_mu(int n, const double *lam, const double *sp, const double *sq,
+                     double *mu, double *pc, double *qc, hipStream_t st) {
   const long m = (long)n * n;
-  hipLaunchKernelGGL(k_mu, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, n, lam, mu);
+  hipLaunchKernelGGL(k_mu, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, n, lam, sp, sq,
+                     mu, pc, qc);
   return hipGetLastError();
 }
 

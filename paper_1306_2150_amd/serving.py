@@ -106,3 +106,36 @@ def run_stream(ctx: binding.Context, requests, factors, prec="auto",
 
 def default_stream(count: int, seed: int = 5000, dims=(2, 3)):
     return inputs.serving_stream(count, 200.0, seed, dims=dims)
+
+
+def check_sample(requests, records, per_shape=1, workers=None):
+    """Relative error of served results against the float64 full-grid
+    solution: the first ``per_shape`` finished requests of every (dim, n)
+    shape (in request order) whose status is LRP_OK.  Returns a list of
+    dicts (rid, dim, n, r, eps, rel_err).  Uses the CPU oracle (test and
+    measurement infrastructure), never the solver."""
+    from oracle import metrics, poisson
+    seen = {}
+    out = []
+    for d in sorted(records, key=lambda d: d["rid"]):
+        key = (d["dim"], d["n"])
+        if d["status"] != binding.LRP_OK or seen.get(key, 0) >= per_shape:
+            continue
+        seen[key] = seen.get(key, 0) + 1
+        q = requests[d["rid"]]
+        outs, R = d["outs"], d["ranks"]
+        if q.dim == 2:
+            U, V = q.rhs()
+            X = poisson.full_solve2d_factors(U, V, workers=workers)
+            e = metrics.rel_err_factored(outs[0][:, :R[0]].cpu().numpy(),
+                                         outs[1][:, :R[0]].cpu().numpy(), X)
+        else:
+            U1, U2, U3, G0 = q.rhs()
+            X = poisson.full_solve3d_tucker(U1, U2, U3, np.asarray(G0), workers=workers)
+            G = outs[3][:R[0] * R[1] * R[2]].view(R[2], R[1], R[0]).permute(2, 1, 0)
+            Us = [outs[t][:, :R[t]].cpu().numpy() for t in range(3)]
+            e = metrics.rel_err_tucker(Us[0], Us[1], Us[2], G.cpu().numpy(), X)
+        del X
+        out.append(dict(rid=int(d["rid"]), dim=q.dim, n=q.n, r=q.r, eps=q.eps,
+                        ranks=list(R), rel_err=float(e)))
+    return out

@@ -54,6 +54,9 @@ def test_null_context_rejected(lib):
     assert lib.lrp_destroy(None) == binding.LRP_EINVAL
     assert lib.lrp_serve_step(None, None) == binding.LRP_EINVAL
     assert lib.lrp_sine_transform(None, 16, 1, P(1), 16, P(1), 16, 0, None) == binding.LRP_EINVAL
+    res = ctypes.c_int32(0)
+    assert lib.lrp_wait(None, 1, ctypes.byref(res), None, None) == binding.LRP_EINVAL
+    assert lib.lrp_poll(None, 1, ctypes.byref(res), None, None) == binding.LRP_EINVAL
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -74,6 +77,9 @@ int main(void) {
   printf("%zu %zu %zu %zu\\n", offsetof(lrp_problem2d, eps),
          offsetof(lrp_problem2d, info), offsetof(lrp_request, eps),
          offsetof(lrp_request, Gx));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(lrp_opts, op), offsetof(lrp_opts, seed),
+         offsetof(lrp_info, err_est), offsetof(lrp_info, us_phase),
+         offsetof(lrp_request, op));
   return 0;
 }
 """)
@@ -86,7 +92,10 @@ int main(void) {
     want = [ctypes.sizeof(binding.LrpOpts), ctypes.sizeof(binding.LrpInfo),
             ctypes.sizeof(binding.LrpProblem2D), ctypes.sizeof(binding.LrpRequest),
             binding.LrpProblem2D.eps.offset, binding.LrpProblem2D.info.offset,
-            binding.LrpRequest.eps.offset, binding.LrpRequest.Gx.offset]
+            binding.LrpRequest.eps.offset, binding.LrpRequest.Gx.offset,
+            binding.LrpOpts.op.offset, binding.LrpOpts.seed.offset,
+            binding.LrpInfo.err_est.offset, binding.LrpInfo.us_phase.offset,
+            binding.LrpRequest.op.offset]
     assert got == want
 
 
@@ -96,9 +105,14 @@ def test_header_constants_match_binding():
     assert int(defs["LRP_MAX_N"]) == binding.MAX_N
     assert int(defs["LRP_MAX_N3"]) == binding.MAX_N3
     assert int(defs["LRP_MAX_RANK"]) == binding.MAX_RANK
+    assert int(defs["LRP_MAX_SWEEPS"]) == binding.MAX_SWEEPS
     codes = dict(re.findall(r"(LRP_E[A-Z]+|LRP_OK)\s*=\s*(-?\d+)", src))
     for name, val in codes.items():
         assert getattr(binding, name) == int(val), name
+    ops = dict(re.findall(r"LRP_OP_([A-Z]+)\s*=\s*(\d+)", src))
+    assert {k.lower(): int(v) for k, v in ops.items()} == binding.OP
+    precs = dict(re.findall(r"LRP_PREC_([A-Z0-9]+)\s*=\s*(\d+)", src))
+    assert {k.lower(): int(v) for k, v in precs.items()} == binding.PREC
 
 
 def test_solve3d_null_context_rejected(lib):

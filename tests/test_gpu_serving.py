@@ -215,3 +215,38 @@ def test_served_frees_cached_batch_groups():
         assert d <= 1e-12, d
     finally:
         c.close()
+
+
+# The served stream's largest shapes (2D n = 8192 with rank 64 at eps = 1e-8;
+# 3D n = 256 with Tucker ranks 64 and n = 512), in the AUTO plan the
+# benchmark serves, submitted together so that they share the device.
+BIG = [(2, 8192, 64, 1e-8), (3, 256, 64, 1e-6), (3, 512, 40, 1e-6), (2, 8192, 7, 1e-6),
+       (3, 256, 9, 1e-8)]
+
+
+def test_served_stream_largest_shapes():
+    from paper_1306_2150_amd import serving
+    reqs = [inputs.Request(rid=i, arrival_s=0.0, dim=d, n=n, r=r, eps=e, seed=5600 + i)
+            for i, (d, n, r, e) in enumerate(BIG)]
+    facs = serving.prepare(reqs)
+    log("serve largest shapes", len(reqs))
+    done, _ = serve_all(reqs, facs, "auto", per_tick=len(reqs))
+    for i, q in enumerate(reqs):
+        (status, ranks, info), outs = done[i]
+        log("  req", i, q.dim, q.n, q.r, q.eps, "status", status, "ranks", ranks,
+            "sweeps", info["sweeps"])
+        assert status == binding.LRP_OK, (i, status)
+        if q.dim == 2:
+            Ux, Vx = served_result(2, outs, ranks)
+            U, V = q.rhs()
+            X = poisson.full_solve2d_factors(U, V, workers=16)
+            e = metrics.rel_err_factored(host(Ux), host(Vx), X)
+        else:
+            Xs, G = served_result(3, outs, ranks)
+            U1, U2, U3, G0 = q.rhs()
+            X = poisson.full_solve3d_tucker(U1, U2, U3, np.asarray(G0), workers=16)
+            Us = [host(x) for x in Xs]
+            e = metrics.rel_err_tucker(Us[0], Us[1], Us[2], np.asarray(host(G)), X)
+            del X
+        log("    err", e)
+        assert e <= 10 * q.eps, (i, e)

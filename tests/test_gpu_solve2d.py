@@ -71,9 +71,43 @@ def test_dst_int8_columns_independent_of_batch():
     n = 3000
     rng = np.random.default_rng(5)
     X = rng.standard_normal((n, 300))
-    big = host(ctx().sine_transform(dev(X), "int8"))        # wide tiles, no K split
+    # 12 row tiles x 2 parities x 5 column tiles = 120 < 256: 32-column tiles
+    big = host(ctx().sine_transform(dev(X), "int8"))        # narrow tiles, no K split
     small = host(ctx().sine_transform(dev(X[:, 7:9]), "int8"))   # K split
     assert np.array_equal(big[:, 7:9], small)
+
+
+# (n, columns): row tiles R = ceil(ceil(n/2)/128); a launch takes the
+# 64-column tiles when R * 2 * ceil(columns/64) >= 256.
+@pytest.mark.parametrize("n,c", [
+    (4096, 1024),   # 16 * 2 * 16 = 512: 64-point stages, whole-period table
+    (4096, 460),    # 16 * 2 * 8 = 256: the smallest wide launch at this n
+    (8192, 256),    # 32 * 2 * 4 = 256
+    (8192, 1024),   # 32 * 2 * 16 = 1024
+    (12000, 300),   # 47 * 2 * 5 = 470: quarter-wave table
+    (16384, 200),   # 64 * 2 * 4 = 512: quarter table, 32-point stages
+])
+def test_dst_int8_wide_tiles_match_oracle_and_narrow(n, c):
+    """The 64-column tile kernels (the ones large batched launches run):
+    every column within 1e-11 of the oracle's DST, and bit-identical to the
+    32-column tiles of a small launch of the same columns (the exact int32
+    level sums do not depend on the tiling)."""
+    log("dst int8 wide", n, c)
+    rng = np.random.default_rng(n + c)
+    X = rng.standard_normal((n, c))
+    X[:, 1] *= 1e-200              # column scales are independent
+    X[:, 2] = 0.0
+    Y = host(ctx().sine_transform(dev(X), "int8"))
+    R = poisson.dst(X)
+    for j in range(c):
+        if j == 2:
+            assert not np.any(Y[:, j])
+            continue
+        assert rel(Y[:, j], R[:, j]) <= 1e-11, (j, rel(Y[:, j], R[:, j]))
+    # 40 columns: R * 2 * 1 < 256, narrow tiles (and a K split)
+    sub = [0, 1, 2, 3, c // 2, c - 1]
+    Ys = host(ctx().sine_transform(dev(X[:, sub]), "int8"))
+    assert np.array_equal(Ys, Y[:, sub])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
@@ -149,6 +183,24 @@ def test_solve2d_n4096_r16_eps1e8():
     U, V = inputs.workload_rhs(2, 1)
     e, info = solve_and_check(U, V, 1e-8, bar=1e-7)
     assert 15 <= info["rank"] <= 40
+
+
+@pytest.mark.parametrize("prec", ["auto", "fp64"])
+def test_solve2d_n4096_sixteen_seeds_batched(prec):
+    """The 4096-point rank-16 workload at eps = 1e-8, sixteen seeded
+    instances solved in one batched call (the launch shape the benchmark
+    times), each against its own full-grid oracle solution (bar 1e-7)."""
+    log("solve2d n4096 16 seeds", prec)
+    rhs = [inputs.workload_rhs(2, inst) for inst in range(1, 17)]
+    res = ctx().solve2d_batch([(dev(U), dev(V), 1e-8) for U, V in rhs], prec=prec)
+    worst = 0.0
+    for (U, V), (Ux, Vx, info) in zip(rhs, res):
+        assert info["status"] == binding.LRP_OK, info
+        X = poisson.full_solve2d_factors(U, V, workers=16)
+        e = metrics.rel_err_factored(host(Ux), host(Vx), X)
+        worst = max(worst, e)
+        assert e <= 1e-7, e
+    log("  worst", worst)
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 7, 20])
