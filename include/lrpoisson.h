@@ -247,6 +247,22 @@ lrp_status lrp_sine_transform(lrp_ctx *ctx, int64_t n, int32_t ncols,
                               const double *src, int64_t lds, double *dst,
                               int64_t ldd, int32_t prec, void *stream);
 
+/* The same transform as lrp_sine_transform, allocating nothing: for callers
+ * that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  No context: every
+ * device buffer it needs beyond src and dst (sine tables, column
+ * descriptors, split-K partial sums, int8 slice records) lives in one static
+ * device array of about 80 MiB that each GPU the library runs on holds
+ * until the process ends; the call uses the current device's copy.  Limits:
+ * n <= LRP_MAX_N (INT8: n up to about 18000, as lrp_sine_transform);
+ * LRP_EINVAL otherwise, and for the argument errors of lrp_sine_transform.
+ * The call returns after its work completed.  Calls on one GPU share its
+ * array and keep the last call's tables: calls that overlap on one GPU
+ * (several host threads) race.  Results equal lrp_sine_transform's. */
+lrp_status lrp_sine_transform_noalloc(int64_t n, int32_t ncols, const double *src,
+                                      int64_t lds, double *dst, int64_t ldd,
+                                      int32_t prec, void *stream);
+
 /* Kernel timing of the sine-transform launches, for measurement.  While
  * enabled, the GEMM kernel of every transform call is bracketed by two HIP
  * events recorded on the stream it runs on (the int8 slicing pass and a

@@ -41,6 +41,7 @@ PHASES = ("forward", "cross", "inverse")
 EXPORTS = ["lrp_create", "lrp_destroy", "lrp_strerror", "lrpoisson_solve2d",
            "lrpoisson_solve2d_batch", "lrpoisson_solve3d", "lrp_submit",
            "lrp_serve_step", "lrp_poll", "lrp_wait", "lrp_sine_transform",
+           "lrp_sine_transform_noalloc",
            "lrp_set_kernel_timing", "lrp_kernel_stats"]
 
 
@@ -125,6 +126,7 @@ def load(path: str = LIB_PATH):
                                       ctypes.POINTER(I32), ctypes.POINTER(I32),
                                       ctypes.POINTER(LrpInfo), P]
     lib.lrp_sine_transform.argtypes = [P, I64, I32, P, I64, P, I64, I32, P]
+    lib.lrp_sine_transform_noalloc.argtypes = [I64, I32, P, I64, P, I64, I32, P]
     lib.lrp_set_kernel_timing.argtypes = [P, I32]
     lib.lrp_kernel_stats.argtypes = [P, I32, ctypes.POINTER(LrpKernelStat), I32]
     lib.lrp_submit.argtypes = [P, ctypes.POINTER(LrpRequest), ctypes.POINTER(ctypes.c_uint64)]
@@ -357,6 +359,18 @@ class Context:
                                          _stream(stream))
         if st != LRP_OK:
             raise LrpError(st, "lrp_sine_transform")
+        return Y
+
+    def sine_transform_noalloc(self, X, prec="fp64", out=None, stream=None):
+        """S X through the entry point that allocates nothing (the output is
+        allocated here, by torch, when not given)."""
+        n, c = X.shape
+        Y = empty_colmajor(n, c, X.device) if out is None else out
+        st = self.lib.lrp_sine_transform_noalloc(n, c, _ptr(X), _ld(X), _ptr(Y),
+                                                 _ld(Y) if c else n, PREC[prec],
+                                                 _stream(stream))
+        if st != LRP_OK:
+            raise LrpError(st, "lrp_sine_transform_noalloc")
         return Y
 
     # ---- kernel timing

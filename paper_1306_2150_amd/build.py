@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblrpoisson.so")
 
 SOURCES = ["dst.hip", "dst_i8.hip", "tsqr.hip", "maxvol.hip", "svd.hip", "cross.hip", "tucker.hip",
-           "host.cpp", "host3d.cpp", "serve.cpp"]
+           "noalloc.hip", "host.cpp", "host3d.cpp", "serve.cpp"]
 
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

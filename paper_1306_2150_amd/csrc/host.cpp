@@ -79,23 +79,24 @@ static float bf16_float_host(uint32_t b) {
   return f;
 }
 
-// Quarter-wave tables of sqrt(2/N) sin(pi q/N), q = 0..floor(N/2), and the
-// eigenvalues lambda_k = 4/h^2 sin^2(pi k/(2N)), h = 1/N, N = n+1, evaluated
-// in long double and rounded once.
-const GridTables *get_tables(lrp_ctx *ctx, int n, lrp_status *err) {
-  *err = LRP_OK;
-  auto it = ctx->tables.find(n);
-  if (it != ctx->tables.end()) return &it->second;
+size_t sine_table_bytes(int n) {
+  const int Q = (n + 1) / 2 + 1;
+  const int Qp8 = (Q + 1) & ~1, Qp4 = (Q + 3) & ~3;
+  return (size_t)Qp8 * 8 + (size_t)Qp4 * 4 + (size_t)Qp4 * 4 + dst_i8_table_bytes(n);
+}
+
+// Quarter-wave tables of sqrt(2/N) sin(pi q/N), q = 0..floor(N/2), in the
+// layout launch_dst reads ([f64][f32][bf16 hi|lo][int8 records]), evaluated
+// in long double and rounded once.  out: sine_table_bytes(n) bytes.
+void build_sine_table(int n, char *out) {
   const int N = n + 1;
   const int Q = N / 2 + 1;
   const int Qp8 = (Q + 1) & ~1, Qp4 = (Q + 3) & ~3;
-  const size_t i8_bytes = dst_i8_table_bytes(n);
-  const size_t tab_bytes = (size_t)Qp8 * 8 + (size_t)Qp4 * 4 + (size_t)Qp4 * 4 + i8_bytes;
-  std::vector<char> host(tab_bytes, 0);
-  dst_i8_table(n, (unsigned char *)host.data() + (size_t)Qp8 * 8 + (size_t)Qp4 * 8);
-  double *t64 = (double *)host.data();
-  float *t32 = (float *)(host.data() + (size_t)Qp8 * 8);
-  uint32_t *tbf = (uint32_t *)(host.data() + (size_t)Qp8 * 8 + (size_t)Qp4 * 4);
+  std::memset(out, 0, sine_table_bytes(n));
+  dst_i8_table(n, (unsigned char *)out + (size_t)Qp8 * 8 + (size_t)Qp4 * 8);
+  double *t64 = (double *)out;
+  float *t32 = (float *)(out + (size_t)Qp8 * 8);
+  uint32_t *tbf = (uint32_t *)(out + (size_t)Qp8 * 8 + (size_t)Qp4 * 4);
   const long double pi = 3.14159265358979323846264338327950288L;
   const long double scale = sqrtl(2.0L / (long double)N);
   for (int q = 0; q < Q; ++q) {
@@ -106,6 +107,19 @@ const GridTables *get_tables(lrp_ctx *ctx, int n, lrp_status *err) {
     const uint32_t lo = bf16_rne_host((float)(v - (long double)bf16_float_host(hi)));
     tbf[q] = hi | (lo << 16);
   }
+}
+
+// The sine tables and the eigenvalues lambda_k = 4/h^2 sin^2(pi k/(2N)),
+// h = 1/N, N = n+1 (long double, rounded once) of grid size n.
+const GridTables *get_tables(lrp_ctx *ctx, int n, lrp_status *err) {
+  *err = LRP_OK;
+  auto it = ctx->tables.find(n);
+  if (it != ctx->tables.end()) return &it->second;
+  const int N = n + 1;
+  const size_t tab_bytes = sine_table_bytes(n);
+  std::vector<char> host(tab_bytes, 0);
+  build_sine_table(n, host.data());
+  const long double pi = 3.14159265358979323846264338327950288L;
   // lambda_k, then the Stokes operator's factors 2 sin^2 / h and 2 cos^2 / h
   // of the half angle pi k/(2N) (cos^2 as sin^2 of the complementary angle)
   std::vector<double> lam(3 * (size_t)n);

@@ -213,6 +213,10 @@ struct lrp_ctx {
 
 namespace lrp {
 const GridTables *get_tables(lrp_ctx *ctx, int n, lrp_status *err);
+// bytes and host construction of the sine tables of grid size n (the
+// layout launch_dst reads)
+size_t sine_table_bytes(int n);
+void build_sine_table(int n, char *out);
 Plan make_plan(const lrp_opts *o, double eps, int n);
 // LRP_EINVAL for options outside their documented ranges
 lrp_status check_opts(const lrp_opts *o);
