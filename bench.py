@@ -36,6 +36,10 @@ if int(os.environ.get("GPU_MAX_HW_QUEUES") or 0) < 16:
     os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "int8": 5.0e15}
+PRECS = ("fp64", "fp32", "bf16x3", "int8", "fft64")
+# arithmetic of each transform plan (everything else is float64)
+DTYPE = {"fp64": "f64", "fft64": "f64", "int8": "i8-slices+f64", "fp32": "f32+f64",
+         "bf16x3": "bf16x3+f64"}
 
 # HBM bytes moved per launch of a transform kernel in this workload, from two
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per
@@ -143,7 +147,7 @@ def timed_steps(ctx, problems, prec, steps, warmup):
     for _ in range(warmup):
         res = batch.run()
     torch.cuda.synchronize()
-    for p in ("fp64", "fp32", "bf16x3", "int8"):
+    for p in PRECS:
         ctx.kernel_stats(p, reset=True)
     ctx.set_kernel_timing(True)
     torch.cuda.synchronize()
@@ -153,7 +157,7 @@ def timed_steps(ctx, problems, prec, steps, warmup):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ctx.set_kernel_timing(False)
-    ks = {p: ctx.kernel_stats(p, reset=True) for p in ("fp64", "fp32", "bf16x3", "int8")}
+    ks = {p: ctx.kernel_stats(p, reset=True) for p in PRECS}
     return dt, res, ks
 
 
@@ -189,7 +193,7 @@ def main():
           f"after {args.warmup} warmup", file=sys.stderr, flush=True)
 
     out = {}
-    for plan in ("auto", "fp64"):
+    for plan in ("auto", "fp64", "int8"):
         dt, res, ks = timed_steps(ctx, problems, plan, args.steps, args.warmup)
         out[plan] = dict(seconds=dt, res=res, ks=ks,
                          solves_per_s=B * args.steps / dt,
@@ -200,15 +204,15 @@ def main():
     # accuracy of every distinct RHS against the float64 full-grid oracle
     from oracle import metrics, poisson
     workers = min(16, os.cpu_count() or 1)
-    errs = {"auto": [], "fp64": []}
+    errs = {"auto": [], "fp64": [], "int8": []}
     for i, (U, V) in enumerate(hostrhs):
         X = poisson.full_solve2d_factors(U, V, workers=workers)
-        for plan in ("auto", "fp64"):
+        for plan in ("auto", "fp64", "int8"):
             Ux, Vx, info = out[plan]["res"][i]
             e = metrics.rel_err_factored(Ux.cpu().numpy(), Vx.cpu().numpy(), X)
             errs[plan].append(e)
     print(f"[bench] max rel err auto {max(errs['auto']):.3e} fp64 "
-          f"{max(errs['fp64']):.3e}", file=sys.stderr, flush=True)
+          f"{max(errs['fp64']):.3e} int8 {max(errs['int8']):.3e}", file=sys.stderr, flush=True)
     print("[bench] rel err per instance auto: " +
           " ".join(f"{e:.2e}" for e in errs["auto"]), file=sys.stderr, flush=True)
 
@@ -249,7 +253,15 @@ def main():
     kauto = out["auto"]["ks"]
     # minimum bytes of a column: its n float64 inputs read, n outputs written
     colbytes = 16.0 * n
-    if kauto["int8"]["launches"]:
+    if kauto["fft64"]["launches"]:
+        # the chirp-z FFT transform: float64 vector arithmetic, two forward and
+        # two inverse 4096-point complex FFTs per column (the library's count)
+        roofline = kstat_roof(kauto["fft64"], "k_dst_fft4096", PEAK["fp64"], "TFLOP/s", 1.0,
+                              1.0, colbytes)
+        roofline["valu_fp64"] = roofline.pop("mfma_executed")
+        roofline.pop("mfma_needed")
+        roofline["traffic"] = traffic_bytes("k_dst_fft4096", roofline["columns_per_launch"])
+    elif kauto["int8"]["launches"]:
         roofline = kstat_roof(kauto["int8"], "k_dst_i8", PEAK["int8"], "TOP/s", 32.0, 21.0,
                               colbytes)
         # the kernel itself reads each column's two parity slice records (8
@@ -265,6 +277,11 @@ def main():
                                               PEAK["fp64"], "TFLOP/s", 1.0, 1.0, colbytes)
     f64 = roofline["fp64_plan_kernel"]
     f64["traffic"] = traffic_bytes("k_dst_f64", f64["columns_per_launch"])
+    if out["int8"]["ks"]["int8"]["launches"]:
+        i8 = kstat_roof(out["int8"]["ks"]["int8"], "k_dst_i8", PEAK["int8"], "TOP/s", 32.0, 21.0,
+                        colbytes)
+        i8["traffic"] = traffic_bytes("k_dst_i8", i8["columns_per_launch"])
+        roofline["int8_plan_kernel"] = i8
 
     line = {
         "metric": METRIC,
@@ -277,15 +294,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "i8-slices+f64",
+        "dtype": DTYPE.get(out["auto"]["res"][0][2]["fwd_prec"], "f64"),
         "data": "synthetic",
         "config": {"workload": "2D Poisson n=4096 r=16 eps=1e-8 Gaussian-bump RHS",
                    "n": n, "r": r, "eps": eps, "batch": B,
-                   "distinct_rhs": args.distinct, "plan": "auto"},
+                   "distinct_rhs": args.distinct, "plan": "auto",
+                   "transform": out["auto"]["res"][0][2]["fwd_prec"]},
         "fp64_path": {"value": out["fp64"]["solves_per_s"],
-                      "ms_per_step": out["fp64"]["ms_per_step"], "dtype": "f64"},
+                      "ms_per_step": out["fp64"]["ms_per_step"], "dtype": "f64",
+                      "transform": "float64 MFMA GEMM"},
+        "int8_path": {"value": out["int8"]["solves_per_s"],
+                      "ms_per_step": out["int8"]["ms_per_step"], "dtype": "i8-slices+f64",
+                      "transform": "int8 MFMA GEMM on exact 7-bit slices"},
         "accuracy": {"bar": 1e-7, "max_rel_err_auto": max(errs["auto"]),
                      "max_rel_err_fp64": max(errs["fp64"]),
+                     "max_rel_err_int8": max(errs["int8"]),
                      "checked": len(hostrhs)},
         "roofline": roofline,
     }

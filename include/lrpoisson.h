@@ -84,9 +84,15 @@ typedef enum {
  *          float64 recombination: the error-free splitting of Ozaki et al.);
  *          relative error ~1e-12 or below.  Grid sizes up to about 18000
  *          (the sine record table lives in LDS); LRP_EINVAL beyond.
- *  AUTO    per-request plan: INT8 both ways wherever it is supported (n up
- *          to about 18000; there it is faster than FP64 and FP32 and accurate
- *          to ~1e-12).  Larger grids: forward transform BF16X3 when
+ *  FFT64   not a GEMM: the transform as a chirp-z (Bluestein) convolution
+ *          of the even/odd folded halves through 4096-point float64 FFTs in
+ *          LDS, O(n log n) work and float64 accuracy (relative error ~1e-15).
+ *          Grid sizes n <= 4096; LRP_EINVAL beyond.
+ *  AUTO    per-request plan: FFT64 both ways for 2048 < n <= 4096 (the
+ *          fastest there, and float64-accurate); INT8 both ways wherever it
+ *          is supported otherwise (n up to about 18000; there it is faster
+ *          than FP64 and FP32 and accurate to ~1e-12).  Larger grids:
+ *          forward transform BF16X3 when
  *          eps >= 1e-6, FP32 when eps >= 1e-7, else FP64; inverse transform
  *          FP32 when eps >= 1e-7, else FP64.  Every floating reduced-precision
  *          transform adds a relative error near its floor (measured: FP32
@@ -100,7 +106,8 @@ typedef enum {
   LRP_PREC_AUTO = 1,
   LRP_PREC_FP32 = 2,
   LRP_PREC_BF16X3 = 3,
-  LRP_PREC_INT8 = 4
+  LRP_PREC_INT8 = 4,
+  LRP_PREC_FFT64 = 5
 } lrp_precision;
 
 /* The discrete operator inverted.  Both are diagonalised by the same sine
@@ -241,8 +248,8 @@ lrp_status lrpoisson_solve3d(lrp_ctx *ctx, int64_t n, const int32_t rank[3],
  * 1D operator; S = S^T = S^-1, so the same call transforms forward and
  * back): dst[:, c] = S src[:, c] for c < ncols.  src: n x ncols (lds >= n),
  * dst: n x ncols (ldd >= n), both float64 device memory, not overlapping.
- * ``prec`` is an lrp_precision other than AUTO.  Non-finite input is not
- * checked here. */
+ * ``prec`` is an lrp_precision other than AUTO (INT8 and FFT64 within their
+ * grid-size limits).  Non-finite input is not checked here. */
 lrp_status lrp_sine_transform(lrp_ctx *ctx, int64_t n, int32_t ncols,
                               const double *src, int64_t lds, double *dst,
                               int64_t ldd, int32_t prec, void *stream);
@@ -268,12 +275,13 @@ lrp_status lrp_sine_transform_noalloc(int64_t n, int32_t ncols, const double *sr
  * events recorded on the stream it runs on (the int8 slicing pass and a
  * split-K reduction stay outside); lrp_kernel_stats() waits for them and
  * returns, per precision (index = lrp_precision: 0 FP64, 2 FP32, 3 BF16X3,
- * 4 INT8), the number of timed GEMM dispatches (an int8 transform of more
- * columns than its work buffer holds runs several), columns, their summed
- * duration in ms and the
- * summed algorithmic work of the folded transform (two half-size GEMMs:
- * 2 (H0^2 + H1^2) flops per column, H0 = ceil(n/2), H1 = floor(n/2); the
- * dense product would be 2 n^2).  reset != 0 clears the counters after
+ * 4 INT8, 5 FFT64), the number of timed GEMM (or FFT) dispatches (an int8
+ * transform of more columns than its work buffer holds runs several),
+ * columns, their summed duration in ms and the summed algorithmic work: for
+ * the GEMMs the folded transform (two half-size GEMMs: 2 (H0^2 + H1^2) flops
+ * per column, H0 = ceil(n/2), H1 = floor(n/2); the dense product would be
+ * 2 n^2), for FFT64 two forward and two inverse 4096-point complex FFTs per
+ * column at 5 M log2 M flops each.  reset != 0 clears the counters after
  * reading.  Timing adds two event records per dispatch. */
 typedef struct {
   int64_t launches;

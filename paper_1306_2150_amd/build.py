@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblrpoisson.so")
 
-SOURCES = ["dst.hip", "dst_i8.hip", "tsqr.hip", "maxvol.hip", "svd.hip", "cross.hip", "tucker.hip",
+SOURCES = ["dst.hip", "dst_i8.hip", "dst_fft.hip", "tsqr.hip", "maxvol.hip", "svd.hip", "cross.hip", "tucker.hip",
            "noalloc.hip", "host.cpp", "host3d.cpp", "serve.cpp"]
 
 ARCH = "gfx950"

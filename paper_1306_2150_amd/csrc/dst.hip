@@ -675,6 +675,8 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
   if (prec == LRP_PREC_INT8)
     return launch_dst_i8(n, base + (size_t)Qp8 * 8 + (size_t)Qp4 * 8, (DstCol *)cols, ncols,
                          solves, partial, partial_elems, work, work_bytes, st, ev0, ev1);
+  if (prec == LRP_PREC_FFT64)
+    return launch_dst_fft(n, base + dst_fft_table_offset(n), cols, ncols, solves, st, ev0, ev1);
   const double *t64 = (const double *)base;
   const float *t32 = (const float *)(base + (size_t)Qp8 * 8);
   const uint32_t *tbf = (const uint32_t *)(base + (size_t)Qp8 * 8 + (size_t)Qp4 * 4);

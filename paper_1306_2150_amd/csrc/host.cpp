@@ -8,6 +8,10 @@
 
 namespace lrp {
 
+// AUTO takes the chirp-z FFT transform above this grid size (its 4096-point
+// FFT costs the same at any supported n; below, the int8 GEMM is cheaper)
+constexpr int FFT_AUTO_MIN_N = 2048;
+
 #define HIPCHK(x)                         \
   do {                                    \
     hipError_t e_ = (x);                  \
@@ -32,6 +36,16 @@ void dev_free(lrp_ctx *ctx, void *p, size_t bytes) {
   ctx->used -= std::min(ctx->used, bytes);
 }
 
+double transform_flops(int prec, int n) {
+  if (prec == LRP_PREC_FFT64) {
+    // two halves, each a forward and an inverse 4096-point complex FFT
+    return 2.0 * 2.0 * 5.0 * 4096.0 * 12.0;
+  }
+  // the folded transform: two half-size GEMMs of H0 = ceil(n/2), H1 = floor(n/2)
+  const double h0 = (double)((n + 1) / 2), h1 = (double)(n / 2);
+  return 2.0 * (h0 * h0 + h1 * h1);
+}
+
 hipError_t timed_dst(lrp_ctx *ctx, int prec, int n, const void *tab,
                      const DstCol *cols, int ncols, Solve2D *solves,
                      double *partial, size_t partial_elems, void *work,
@@ -46,8 +60,6 @@ hipError_t timed_dst(lrp_ctx *ctx, int prec, int n, const void *tab,
     const size_t cb = dst_i8_work_bytes(n, 1);
     per = (int)std::max<size_t>(1, std::min<size_t>((size_t)ncols, work_bytes / cb));
   }
-  // the folded transform: two half-size GEMMs of H0 = ceil(n/2), H1 = floor(n/2)
-  const double h0 = (double)((n + 1) / 2), h1 = (double)(n / 2);
   for (int c0 = 0; c0 < ncols; c0 += per) {
     const int cnt = std::min(per, ncols - c0);
     lrp_ctx::PendingTime pt;
@@ -60,7 +72,7 @@ hipError_t timed_dst(lrp_ctx *ctx, int prec, int n, const void *tab,
     if (e != hipSuccess) return e;
     pt.prec = prec;
     pt.cols = cnt;
-    pt.flops = 2.0 * (h0 * h0 + h1 * h1) * (double)cnt;
+    pt.flops = transform_flops(prec, n) * (double)cnt;
     ctx->pending_times.push_back(pt);
   }
   return hipSuccess;
@@ -82,7 +94,8 @@ static float bf16_float_host(uint32_t b) {
 size_t sine_table_bytes(int n) {
   const int Q = (n + 1) / 2 + 1;
   const int Qp8 = (Q + 1) & ~1, Qp4 = (Q + 3) & ~3;
-  return (size_t)Qp8 * 8 + (size_t)Qp4 * 4 + (size_t)Qp4 * 4 + dst_i8_table_bytes(n);
+  const size_t b = (size_t)Qp8 * 8 + (size_t)Qp4 * 4 + (size_t)Qp4 * 4 + dst_i8_table_bytes(n);
+  return dst_fft_supported(n) ? dst_fft_table_offset(n) + dst_fft_table_bytes(n) : b;
 }
 
 // Quarter-wave tables of sqrt(2/N) sin(pi q/N), q = 0..floor(N/2), in the
@@ -94,6 +107,7 @@ void build_sine_table(int n, char *out) {
   const int Qp8 = (Q + 1) & ~1, Qp4 = (Q + 3) & ~3;
   std::memset(out, 0, sine_table_bytes(n));
   dst_i8_table(n, (unsigned char *)out + (size_t)Qp8 * 8 + (size_t)Qp4 * 8);
+  if (dst_fft_supported(n)) dst_fft_table(n, (double *)(out + dst_fft_table_offset(n)));
   double *t64 = (double *)out;
   float *t32 = (float *)(out + (size_t)Qp8 * 8);
   uint32_t *tbf = (uint32_t *)(out + (size_t)Qp8 * 8 + (size_t)Qp4 * 4);
@@ -163,7 +177,10 @@ Plan make_plan(const lrp_opts *o, double eps, int n) {
   p.op = o ? o->op : LRP_OP_LAPLACE;
   p.seed = o ? o->seed : 0;
   if (prec == LRP_PREC_AUTO) {
-    if (dst_i8_supported(n)) {
+    if (dst_fft_supported(n) && n > FFT_AUTO_MIN_N) {
+      // float64 chirp-z FFT: the fewest operations and float64 accuracy
+      p.fwd_prec = p.inv_prec = LRP_PREC_FFT64;
+    } else if (dst_i8_supported(n)) {
       // exact int8 slices: about 1e-12, faster than the float64 and float32
       // transforms wherever the sine record table fits in LDS
       p.fwd_prec = p.inv_prec = LRP_PREC_INT8;
@@ -174,17 +191,30 @@ Plan make_plan(const lrp_opts *o, double eps, int n) {
       p.fwd_prec = eps >= 1e-6 ? LRP_PREC_BF16X3 : (eps >= 1e-7 ? LRP_PREC_FP32 : LRP_PREC_FP64);
       p.inv_prec = eps >= 1e-7 ? LRP_PREC_FP32 : LRP_PREC_FP64;
     }
-  } else if (prec == LRP_PREC_FP32 || prec == LRP_PREC_BF16X3 || prec == LRP_PREC_INT8) {
-    p.fwd_prec = p.inv_prec = prec;      // INT8 callers check dst_i8_supported(n)
+  } else if (prec == LRP_PREC_FP32 || prec == LRP_PREC_BF16X3 || prec == LRP_PREC_INT8 ||
+             prec == LRP_PREC_FFT64) {
+    // INT8 / FFT64 callers check dst_i8_supported(n) / dst_fft_supported(n)
+    p.fwd_prec = p.inv_prec = prec;
   } else {
     p.fwd_prec = p.inv_prec = LRP_PREC_FP64;
   }
   return p;
 }
 
+bool transform_prec_ok(int prec, int n) {
+  switch (prec) {
+    case LRP_PREC_FP64:
+    case LRP_PREC_FP32:
+    case LRP_PREC_BF16X3: return true;
+    case LRP_PREC_INT8: return dst_i8_supported(n);
+    case LRP_PREC_FFT64: return dst_fft_supported(n);
+    default: return false;
+  }
+}
+
 lrp_status check_opts(const lrp_opts *o) {
   if (!o) return LRP_OK;
-  if (o->prec < 0 || o->prec > LRP_PREC_INT8) return LRP_EINVAL;
+  if (o->prec < 0 || o->prec > LRP_PREC_FFT64) return LRP_EINVAL;
   if (o->max_sweeps < 0 || o->max_sweeps > LRP_MAX_SWEEPS) return LRP_EINVAL;
   if (o->rank_cap < 0 || o->kick < 0 || o->maxvol_tau < 0.0) return LRP_EINVAL;
   if (o->op != LRP_OP_LAPLACE && o->op != LRP_OP_STOKES) return LRP_EINVAL;
@@ -470,7 +500,7 @@ lrp_status Group2D::dst_cols(std::vector<DstCol> &cols, int prec, hipStream_t st
 }
 
 lrp_status Group2D::forward(const std::vector<int> &slots, hipStream_t st) {
-  for (int prec : {LRP_PREC_FP64, LRP_PREC_FP32, LRP_PREC_BF16X3, LRP_PREC_INT8}) {
+  for (int prec : ALL_PRECS) {
     std::vector<DstCol> cols;
     for (int i : slots) {
       const Solve2D &s = h_s_[i];
@@ -534,7 +564,7 @@ lrp_status Group2D::fetch(hipStream_t st, bool sync) {
 }
 
 lrp_status Group2D::inverse(const std::vector<int> &slots, hipStream_t st) {
-  for (int prec : {LRP_PREC_FP64, LRP_PREC_FP32, LRP_PREC_BF16X3, LRP_PREC_INT8}) {
+  for (int prec : ALL_PRECS) {
     std::vector<DstCol> cols;
     for (int i : slots) {
       const Solve2D &s = h_s_[i];
@@ -603,10 +633,7 @@ lrp_status lrp_sine_transform(lrp_ctx *ctx, int64_t n, int32_t ncols,
                               const double *src, int64_t lds, double *dst,
                               int64_t ldd, int32_t prec, void *stream) {
   if (!ctx || n < 1 || n > LRP_MAX_N || ncols < 0) return LRP_EINVAL;
-  if (prec != LRP_PREC_FP64 && prec != LRP_PREC_FP32 && prec != LRP_PREC_BF16X3 &&
-      prec != LRP_PREC_INT8)
-    return LRP_EINVAL;
-  if (prec == LRP_PREC_INT8 && !dst_i8_supported((int)n)) return LRP_EINVAL;
+  if (!transform_prec_ok(prec, (int)n)) return LRP_EINVAL;
   if (ncols == 0) return LRP_OK;
   if (!src || !dst || lds < n || ldd < n) return LRP_EINVAL;
   if (hipSetDevice(ctx->device) != hipSuccess) return LRP_EDEVICE;
@@ -675,7 +702,7 @@ lrp_status lrp_set_kernel_timing(lrp_ctx *ctx, int32_t enable) {
 
 lrp_status lrp_kernel_stats(lrp_ctx *ctx, int32_t prec, lrp_kernel_stat *out,
                             int32_t reset) {
-  if (!ctx || prec < 0 || prec > LRP_PREC_INT8 || prec == LRP_PREC_AUTO) return LRP_EINVAL;
+  if (!ctx || prec < 0 || prec > LRP_PREC_FFT64 || prec == LRP_PREC_AUTO) return LRP_EINVAL;
   std::lock_guard<std::mutex> lock(ctx->mu);
   if (hipSetDevice(ctx->device) != hipSuccess) return LRP_EDEVICE;
   for (auto &pt : ctx->pending_times) {
@@ -730,7 +757,8 @@ lrp_status lrpoisson_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t count,
   if (!ctx || !probs || count < 0) return LRP_EINVAL;
   if (n < 1 || n > LRP_MAX_N) return LRP_EINVAL;
   if (check_opts(opts) != LRP_OK) return LRP_EINVAL;
-  if (opts && opts->prec == LRP_PREC_INT8 && !dst_i8_supported((int)n)) return LRP_EINVAL;
+  if (opts && opts->prec != LRP_PREC_AUTO && !transform_prec_ok(opts->prec, (int)n))
+    return LRP_EINVAL;
   for (int i = 0; i < count; ++i) {
     lrp_status e = check_problem(n, probs[i]);
     if (e != LRP_OK) return e;

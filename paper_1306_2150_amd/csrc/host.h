@@ -205,7 +205,7 @@ struct lrp_ctx {
     double flops;
   };
   std::vector<PendingTime> pending_times;
-  lrp_kernel_stat kstat[5] = {};
+  lrp_kernel_stat kstat[LRP_PREC_FFT64 + 1] = {};
   // phase events of the synchronous calls (forward, cross, inverse)
   hipEvent_t phase_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::mutex mu;
@@ -220,6 +220,13 @@ void build_sine_table(int n, char *out);
 Plan make_plan(const lrp_opts *o, double eps, int n);
 // LRP_EINVAL for options outside their documented ranges
 lrp_status check_opts(const lrp_opts *o);
+// an explicit transform precision that grid size n supports
+bool transform_prec_ok(int prec, int n);
+// algorithmic flops of one transformed column (lrp_kernel_stat.flops)
+double transform_flops(int prec, int n);
+// every transform precision, in the order the groups launch them
+constexpr int ALL_PRECS[] = {LRP_PREC_FP64, LRP_PREC_FP32, LRP_PREC_BF16X3, LRP_PREC_INT8,
+                             LRP_PREC_FFT64};
 // phase timing of a synchronous call: record event i (0..3) on st
 void phase_mark(lrp_ctx *ctx, int i, hipStream_t st);
 // after the stream completed: the three phase durations in microseconds

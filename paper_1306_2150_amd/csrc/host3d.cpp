@@ -125,7 +125,7 @@ lrp_status Group3D::start(const std::vector<int> &slots, hipStream_t st) {
     }
   }
   // forward transforms of the three factors into the mode slots' Uh
-  for (int prec : {LRP_PREC_FP64, LRP_PREC_FP32, LRP_PREC_BF16X3, LRP_PREC_INT8}) {
+  for (int prec : ALL_PRECS) {
     std::vector<DstCol> cols;
     for (int i : slots) {
       if (plans_[i].fwd_prec != prec) continue;
@@ -176,7 +176,7 @@ lrp_status Group3D::fetch(hipStream_t st, bool sync) {
 }
 
 lrp_status Group3D::finish(const std::vector<int> &slots, hipStream_t st) {
-  for (int prec : {LRP_PREC_FP64, LRP_PREC_FP32, LRP_PREC_BF16X3, LRP_PREC_INT8}) {
+  for (int prec : ALL_PRECS) {
     std::vector<DstCol> cols;
     for (int i : slots) {
       const Solve3D &s = h_s_[i];
@@ -263,7 +263,8 @@ extern "C" lrp_status lrpoisson_solve3d(lrp_ctx *ctx, int64_t n, const int32_t r
                                         int32_t rank_out[3], lrp_info *info, void *stream) {
   if (!ctx || !rank_out) return LRP_EINVAL;
   if (check_opts(opts) != LRP_OK) return LRP_EINVAL;
-  if (opts && opts->prec == LRP_PREC_INT8 && !dst_i8_supported((int)n)) return LRP_EINVAL;
+  if (opts && opts->prec != LRP_PREC_AUTO && !transform_prec_ok(opts->prec, (int)n))
+    return LRP_EINVAL;
   const double *U[3] = {U1, U2, U3};
   double *X[3] = {U1x, U2x, U3x};
   lrp_status e = check_problem3d(n, rank, U, ld, G, eps, X, ldx, Gx, rmax);

@@ -295,6 +295,22 @@ size_t dst_i8_work_bytes(int n, int ncols);
 // columns whose slice records one work buffer holds: `want`, capped so that
 // the buffer stays within 512 MiB, but never below 1024
 int dst_i8_work_cols(int n, int want);
+// chirp-z FFT transform in float64 (dst_fft.hip): grid sizes whose folded
+// halves fit its 4096-point FFT (n <= 4096); its tables (chirp, twiddles,
+// FFT of the convolution kernel) follow the int8 records in the grid's
+// table block, 16-byte aligned (dst_fft_table_offset)
+bool dst_fft_supported(int n);
+size_t dst_fft_table_bytes(int n);
+void dst_fft_table(int n, double *out);
+hipError_t launch_dst_fft(int n, const void *tab, const DstCol *cols, int ncols,
+                          Solve2D *solves, hipStream_t st, hipEvent_t ev0 = nullptr,
+                          hipEvent_t ev1 = nullptr);
+inline size_t dst_fft_table_offset(int n) {
+  const int Q = (n + 1) / 2 + 1;
+  const int Qp8 = (Q + 1) & ~1, Qp4 = (Q + 3) & ~3;
+  const size_t o = (size_t)Qp8 * 8 + (size_t)Qp4 * 8 + dst_i8_table_bytes(n);
+  return (o + 255) & ~(size_t)255;
+}
 hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, Solve2D *solves,
                          double *partial, size_t partial_elems, void *work,
                          size_t work_bytes, hipStream_t st, hipEvent_t ev0 = nullptr,

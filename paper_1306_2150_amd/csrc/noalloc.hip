@@ -54,10 +54,7 @@ extern "C" lrp_status lrp_sine_transform_noalloc(int64_t n, int32_t ncols,
                                                  double *dst, int64_t ldd, int32_t prec,
                                                  void *stream) {
   if (n < 1 || n > LRP_MAX_N || ncols < 0) return LRP_EINVAL;
-  if (prec != LRP_PREC_FP64 && prec != LRP_PREC_FP32 && prec != LRP_PREC_BF16X3 &&
-      prec != LRP_PREC_INT8)
-    return LRP_EINVAL;
-  if (prec == LRP_PREC_INT8 && !dst_i8_supported((int)n)) return LRP_EINVAL;
+  if (!transform_prec_ok(prec, (int)n)) return LRP_EINVAL;
   if (sine_table_bytes((int)n) > NA_TAB_BYTES) return LRP_EINVAL;
   // int8: the slice records of at least one column must fit
   const size_t col_work = dst_i8_work_bytes((int)n, 1);

@@ -34,10 +34,11 @@ constexpr int SERVE_SLOTS = 32;                      // slots per 2D group
 constexpr size_t SERVE3_SHARE = (size_t)16 << 30;   // bytes per 3D group
 
 lrp_status check_request(const lrp_request &q) {
-  if (q.prec < 0 || q.prec > LRP_PREC_INT8) return LRP_EINVAL;
+  if (q.prec < 0 || q.prec > LRP_PREC_FFT64) return LRP_EINVAL;
   if (q.op != LRP_OP_LAPLACE && q.op != LRP_OP_STOKES) return LRP_EINVAL;
   if (q.reserved != 0) return LRP_EINVAL;
-  if (q.prec == LRP_PREC_INT8 && (q.n < 1 || q.n > LRP_MAX_N || !dst_i8_supported((int)q.n)))
+  if (q.prec != LRP_PREC_AUTO &&
+      (q.n < 1 || q.n > LRP_MAX_N || !transform_prec_ok(q.prec, (int)q.n)))
     return LRP_EINVAL;
   if (q.dim == 3) {
     const int32_t *rk = q.rank, *rm = q.rmax;

@@ -35,6 +35,38 @@ def test_dst_fp64_matches_oracle(n, c):
     assert rel(Y, poisson.dst(X)) <= 1e-13
 
 
+@pytest.mark.parametrize("n,c", [(1, 1), (2, 3), (3, 2), (4, 1), (63, 5), (64, 32), (65, 33),
+                                 (1000, 40), (2047, 7), (2048, 9), (2049, 300), (3001, 70),
+                                 (4095, 11), (4096, 1100)])
+def test_dst_fft64_matches_oracle(n, c):
+    """The chirp-z FFT transform (float64): every column within 1e-14 of the
+    oracle's library DST, odd and even n (with and without the middle point
+    of the fold), one- to four-point grids, the largest supported n."""
+    log("dst fft64", n, c)
+    rng = np.random.default_rng(n * 17 + c)
+    X = rng.standard_normal((n, c))
+    X[:, 0] *= 1e-250              # column scales are independent
+    Y = host(ctx().sine_transform(dev(X), "fft64"))
+    R = poisson.dst(X)
+    worst = max(rel(Y[:, j], R[:, j]) for j in range(c))
+    log("  worst column", worst)
+    assert worst <= 1e-14, worst
+
+
+def test_dst_fft64_limits_and_nonfinite():
+    log("dst fft64 limits")
+    from paper_1306_2150_amd import binding
+    with pytest.raises(binding.LrpError) as ei:
+        ctx().sine_transform(dev(np.ones((4097, 1))), "fft64")
+    assert ei.value.status == binding.LRP_EINVAL
+    # a NaN in a solve's factor is reported by the forward transform
+    U, V = inputs.workload_rhs(2, 1, n=4000)
+    U = U.copy()
+    U[3999, 2] = np.nan
+    _, _, info = ctx().solve2d(dev(U), dev(V), 1e-8, prec="fft64", check=False)
+    assert info["status_code"] == binding.LRP_ENONFINITE
+
+
 def test_dst_leading_dimension_and_involution():
     log("dst ld")
     import torch
@@ -159,7 +191,8 @@ def solve_and_check(U, V, eps, prec="fp64", bar=None, **kw):
     assert e <= bar, (e, info)
     if Vx.shape[1]:
         # orthonormal to the precision of the inverse transform
-        otol = {"fp64": 1e-10, "int8": 1e-10, "fp32": 1e-6, "bf16x3": 1e-4}[info["inv_prec"]]
+        otol = {"fp64": 1e-10, "int8": 1e-10, "fft64": 1e-10, "fp32": 1e-6,
+                "bf16x3": 1e-4}[info["inv_prec"]]
         assert np.max(np.abs(Vx.T @ Vx - np.eye(Vx.shape[1]))) < otol
     return e, info
 
@@ -324,7 +357,8 @@ def test_prepared_batch_reruns_identically():
         assert np.array_equal(Ua, host(Uc)) and np.array_equal(Va, host(Vc))
 
 
-@pytest.mark.parametrize("prec,eps,bar", [("fp32", 1e-7, 1e-6), ("auto", 1e-8, 1e-7),
+@pytest.mark.parametrize("prec,eps,bar", [("fft64", 1e-8, 1e-7), ("fft64", 1e-12, 1e-11),
+                                          ("fp32", 1e-7, 1e-6), ("auto", 1e-8, 1e-7),
                                           ("auto", 1e-7, 1e-6), ("auto", 1e-6, 1e-5),
                                           ("bf16x3", 1e-5, 1e-4), ("int8", 1e-8, 1e-7),
                                           ("int8", 1e-10, 1e-9)])
