@@ -50,6 +50,9 @@ DTYPE = {"fp64": "f64", "fft64": "f64", "int8": "i8-slices+f64", "fp32": "f32+f6
 # match) and for dispatches of the same average column count (the default
 # workload and batch); otherwise the traffic is reported as null.
 TRAFFIC = {
+    "k_dst_fft4096": {"sources": ["dst_fft.hip", "lrp_internal.h"],
+                      "sha1": "bdf0118f1a8b239db851e84fa8f6f710325f10ed",
+                      "columns": 41968, "fetch_kib": 676015.5, "write_kib": 1342977.8},
     "k_dst_i8": {"sources": ["dst_i8.hip", "lrp_internal.h"],
                  "sha1": "c11ce42d2e9d40ca6b4b141f7a4d64e437dd236f",
                  "columns": 11990.857, "fetch_kib": 196758.7, "write_kib": 384221.9},

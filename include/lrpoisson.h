@@ -142,7 +142,8 @@ typedef struct {
   int32_t kick;         /* cross rank growth step, default 8                */
   double maxvol_tau;    /* maxvol dominance bound, default 1.05             */
   int32_t op;           /* lrp_operator, default LRP_OP_LAPLACE             */
-  int32_t reserved;     /* must be 0                                        */
+  int32_t k0;           /* columns of the first cross sweep (capped at
+                           rank_cap and n), default rank + kick             */
   uint64_t seed;        /* offset of the deterministic index sequences: the
                            evenly spaced padding of the first column set and
                            the probe rows of rank growth start at

@@ -49,7 +49,7 @@ class LrpOpts(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
                 ("rank_cap", ctypes.c_int32), ("kick", ctypes.c_int32),
                 ("maxvol_tau", ctypes.c_double), ("op", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("k0", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class LrpInfo(ctypes.Structure):
@@ -189,10 +189,10 @@ def empty_colmajor(n, r, device="cuda"):
 
 
 def _opts(prec="fp64", max_sweeps=0, rank_cap=0, kick=0, tau=0.0, op="laplace",
-          seed=0):
+          seed=0, k0=0):
     return LrpOpts(PREC[prec] if isinstance(prec, str) else int(prec),
                    max_sweeps, rank_cap, kick, tau,
-                   OP[op] if isinstance(op, str) else int(op), 0, seed)
+                   OP[op] if isinstance(op, str) else int(op), k0, seed)
 
 
 def _stream(stream):

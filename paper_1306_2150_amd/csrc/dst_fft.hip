@@ -151,7 +151,6 @@ __device__ __forceinline__ void conv4096(cd (&v)[16], double2 *L, const double2 
 #pragma unroll
     for (int k2 = 0; k2 < 16; ++k2) {
       v[k2] = cmul(v[k2], cmul(b, lds_get(W1, (lo * k2) & 255)));
-      if ((k2 & 3) == 3) __builtin_amdgcn_sched_barrier(0);
     }
   }
   __syncthreads();
@@ -162,22 +161,25 @@ __device__ __forceinline__ void conv4096(cd (&v)[16], double2 *L, const double2 
   // loads of FFT_M(beta) go out first and complete under the pass
 #pragma unroll
   for (int n1 = 0; n1 < 16; ++n1) v[n1] = lds_get(L, t + FP * n1);
-  cd bv[16];
-  const int z = opaque_zero();
+  cd bv[8];
+  int z = opaque_zero();
 #pragma unroll
-  for (int k3 = 0; k3 < 16; ++k3) bv[k3] = ld2(bh + (t + 256 * k3 + z));
+  for (int k3 = 0; k3 < 8; ++k3) bv[k3] = ld2(bh + (t + 256 * k3 + z));
   dft16<false>(v);
-  // pointwise product with FFT_M(beta), then the inverse over k3
+  // pointwise product with FFT_M(beta) (in two groups of eight loads), then
+  // the inverse over k3
 #pragma unroll
-  for (int k3 = 0; k3 < 16; ++k3) v[k3] = cmul(v[k3], bv[k3]);
+  for (int k3 = 0; k3 < 8; ++k3) v[k3] = cmul(v[k3], bv[k3]);
+  z = opaque_zero();
+#pragma unroll
+  for (int k3 = 8; k3 < 16; ++k3) bv[k3 - 8] = ld2(bh + (t + 256 * k3 + z));
+#pragma unroll
+  for (int k3 = 8; k3 < 16; ++k3) v[k3] = cmul(v[k3], bv[k3 - 8]);
   dft16<true>(v);
   // inverse twiddle e^(+2 pi i n1 (k1 + 16 k2)/4096), thread (k1, k2) = (lo, hi)
 #pragma unroll
   for (int n1 = 1; n1 < 16; ++n1) {
     v[n1] = cmulc(v[n1], cmul(lds_get(W2, n1 * lo), lds_get(W1, (n1 * hi) & 255)));
-    // at most four twiddle pairs in flight: the scheduler would otherwise
-    // issue all thirty table reads at once and run out of registers
-    if ((n1 & 3) == 3) __builtin_amdgcn_sched_barrier(0);
   }
   __syncthreads();
 #pragma unroll
@@ -212,30 +214,39 @@ __global__ __launch_bounds__(FT, 2) void k_dst_fft4096(int n, const double2 *__r
   W1[t] = tab[N2 + t];
   W2[t] = tab[N2 + 256 + t];
   __syncthreads();
-  // folded inputs at k' = t + 256 j (k = k' + 1); K <= 2048, so j < 8.
-  // Each half reads its pair of source entries again (the second read hits
-  // the cache) and writes its own rows, so no half holds the other's data.
+  // folded inputs at k' = t + 256 j (k = k' + 1); K <= 2048, so j < 8: read
+  // once, both halves formed from them
+  double u[8], w[8];
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int kp = t + 256 * j, k = kp + 1;
+    double xa = 0.0, xb = 0.0;
+    if (kp < H0) {
+      xa = col.src[kp];
+      if (N - k != k) xb = col.src[N - k - 1];
+    }
+    bad |= !(isfinite(xa) && isfinite(xb));
+    u[j] = xa + xb;
+    w[j] = (kp < H1) ? xa - xb : 0.0;
+  }
+  if (bad && col.solve >= 0 && solves) solves[col.solve].nonfinite = 1;
   const double scale = sqrt(2.0 / (double)N) / (double)FM;
+  // the odd half's outputs wait in registers, so that rows 2a+1 and 2a+2 go
+  // out together (whole cache lines: stride-2 stores of each half alone
+  // would write every line twice)
+  double yo[8];
 #pragma unroll 1
   for (int half = 0; half < 2; ++half) {
-    const int K = half ? H1 : H0;
     cd v[16];
-    bool bad = false;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int kp = t + 256 * j, k = kp + 1;
-      double xa = 0.0, xb = 0.0;
-      if (kp < K) {
-        xa = col.src[kp];
-        if (N - k != k) xb = col.src[N - k - 1];
-      }
-      bad |= !(isfinite(xa) && isfinite(xb));
-      const double val = half ? xa - xb : xa + xb;
+      const int kp = t + 256 * j;
       const int ph = (kp * kp + (half ? 2 * kp : kp + 1)) % N2;
+      const double val = half ? w[j] : u[j];
       const cd e = ld2(ch + ph);
       v[j] = {val * e.x, val * e.y};
     }
-    if (bad && col.solve >= 0 && solves) solves[col.solve].nonfinite = 1;
 #pragma unroll
     for (int j = 8; j < 16; ++j) v[j] = {0.0, 0.0};
     conv4096(v, lds, W1, W2, bh);
@@ -244,8 +255,14 @@ __global__ __launch_bounds__(FT, 2) void k_dst_fft4096(int n, const double2 *__r
       const int a = t + 256 * j;
       const int ph = (a * a + 2 * a + (half ? 2 : 0)) % N2;
       const cd e = ld2(ch + ph);
-      // odd half: rows 2a + 1 (index 2a); even half: rows 2a + 2
-      if (a < K) col.dst[2 * a + half] = scale * fma(e.x, v[j].y, e.y * v[j].x);
+      const double y = scale * fma(e.x, v[j].y, e.y * v[j].x);
+      if (!half) {
+        yo[j] = y;
+      } else {
+        // rows 2a + 1 (odd half, a < H0) and 2a + 2 (even half, a < H1)
+        if (a < H0) col.dst[2 * a] = yo[j];
+        if (a < H1) col.dst[2 * a + 1] = y;
+      }
     }
     __syncthreads();   // the last exchange's reads are done before the next half writes
   }

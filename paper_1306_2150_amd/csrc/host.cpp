@@ -175,6 +175,7 @@ Plan make_plan(const lrp_opts *o, double eps, int n) {
   p.min_slack = std::max(1, p.kick / 2);
   p.tau = (o && o->maxvol_tau > 1.0) ? o->maxvol_tau : 1.05;
   p.op = o ? o->op : LRP_OP_LAPLACE;
+  p.k0 = o ? o->k0 : 0;
   p.seed = o ? o->seed : 0;
   if (prec == LRP_PREC_AUTO) {
     if (dst_fft_supported(n) && n > FFT_AUTO_MIN_N) {
@@ -218,7 +219,7 @@ lrp_status check_opts(const lrp_opts *o) {
   if (o->max_sweeps < 0 || o->max_sweeps > LRP_MAX_SWEEPS) return LRP_EINVAL;
   if (o->rank_cap < 0 || o->kick < 0 || o->maxvol_tau < 0.0) return LRP_EINVAL;
   if (o->op != LRP_OP_LAPLACE && o->op != LRP_OP_STOKES) return LRP_EINVAL;
-  if (o->reserved != 0) return LRP_EINVAL;
+  if (o->k0 < 0) return LRP_EINVAL;
   return LRP_OK;
 }
 
@@ -444,7 +445,7 @@ void Group2D::setup_slot(int i, const double *U, const double *V, long ld, int r
   s.sig = lo;
   s.sigp = hi;
   s.kcap = std::min(plan.kcap, std::min(n_, m_));
-  const int k0 = std::min(r + plan.kick, s.kcap);
+  const int k0 = std::min(plan.k0 > 0 ? plan.k0 : r + plan.kick, s.kcap);
   s.k0 = k0;
   s.k = std::min(r, k0);   // columns of the initial maxvol on Vh
   kin_[i] = s.k;

@@ -37,6 +37,7 @@ struct Plan {
   int max_sweeps, kcap, kick, min_slack;
   double tau;
   int op;             // lrp_operator
+  int k0;             // columns of the first sweep, 0: rank + kick
   uint64_t seed;      // offset of the spread index sequences
 };
 
