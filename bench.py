@@ -36,10 +36,10 @@ if int(os.environ.get("GPU_MAX_HW_QUEUES") or 0) < 16:
     os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15, "int8": 5.0e15}
-PRECS = ("fp64", "fp32", "bf16x3", "int8", "fft64")
+PRECS = ("fp64", "fp32", "bf16x3", "int8", "fft64", "bf16x6")
 # arithmetic of each transform plan (everything else is float64)
 DTYPE = {"fp64": "f64", "fft64": "f64", "int8": "i8-slices+f64", "fp32": "f32+f64",
-         "bf16x3": "bf16x3+f64"}
+         "bf16x3": "bf16x3+f64", "bf16x6": "bf16x6+f64"}
 
 # HBM bytes moved per launch of a transform kernel in this workload, from two
 # rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE, KiB per

@@ -79,6 +79,11 @@ typedef enum {
  *  BF16X3  bfloat16 MFMA on a two-piece split of both operands, three
  *          products (hi*hi + hi*lo + lo*hi), float32 accumulation inside
  *          K blocks, float64 across blocks, both ways.
+ *  BF16X6  bfloat16 MFMA on a three-piece split of both operands (each piece
+ *          the bfloat16 rounding of what the previous ones leave), the six
+ *          products of piece levels a + b <= 2, float32 accumulation inside
+ *          K blocks, float64 across blocks: float32-level accuracy (relative
+ *          error ~1e-7) on the bfloat16 matrix cores.
  *  INT8    int8 MFMA on exact 7-bit integer slices of both operands (six
  *          slices each, the products of slice levels <= 5, int32 sums,
  *          float64 recombination: the error-free splitting of Ozaki et al.);
@@ -107,7 +112,8 @@ typedef enum {
   LRP_PREC_FP32 = 2,
   LRP_PREC_BF16X3 = 3,
   LRP_PREC_INT8 = 4,
-  LRP_PREC_FFT64 = 5
+  LRP_PREC_FFT64 = 5,
+  LRP_PREC_BF16X6 = 6
 } lrp_precision;
 
 /* The discrete operator inverted.  Both are diagonalised by the same sine
@@ -276,7 +282,7 @@ lrp_status lrp_sine_transform_noalloc(int64_t n, int32_t ncols, const double *sr
  * events recorded on the stream it runs on (the int8 slicing pass and a
  * split-K reduction stay outside); lrp_kernel_stats() waits for them and
  * returns, per precision (index = lrp_precision: 0 FP64, 2 FP32, 3 BF16X3,
- * 4 INT8, 5 FFT64), the number of timed GEMM (or FFT) dispatches (an int8
+ * 4 INT8, 5 FFT64, 6 BF16X6), the number of timed GEMM (or FFT) dispatches (an int8
  * transform of more columns than its work buffer holds runs several),
  * columns, their summed duration in ms and the summed algorithmic work: for
  * the GEMMs the folded transform (two half-size GEMMs: 2 (H0^2 + H1^2) flops

@@ -27,7 +27,7 @@ LRP_ENOTREADY = -8
 STATUS_NAME = {0: "ok", -1: "einval", -2: "enonfinite", -3: "erankcap", -4: "enoconv",
                -5: "enomem", -6: "edevice", -7: "ebusy", -8: "enotready"}
 
-PREC = {"fp64": 0, "auto": 1, "fp32": 2, "bf16x3": 3, "int8": 4, "fft64": 5}
+PREC = {"fp64": 0, "auto": 1, "fp32": 2, "bf16x3": 3, "int8": 4, "fft64": 5, "bf16x6": 6}
 PREC_NAME = {v: k for k, v in PREC.items()}
 OP = {"laplace": 0, "stokes": 1}
 

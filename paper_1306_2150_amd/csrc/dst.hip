@@ -490,22 +490,29 @@ __global__ __launch_bounds__(512 / HW) void k_dst_f32(
       }
 }
 
-// ---------------------------------------------------------------- BF16x3
-// Table entries are packed (hi | lo << 16) bfloat16 splits of the sine.  64
-// rows (4 waves x 16) x TN columns per workgroup; the folded sources of the
-// next 64-deep K stage are loaded into registers while the MFMAs run on the
-// current one, then split into bfloat16 hi/lo and stashed in the other LDS
-// buffer.  A stage is one float32 run, added into the float64 chunk sum.
-__global__ __launch_bounds__(NTHR) void k_dst_bf16x3(
+// ------------------------------------------------------- BF16x3 / BF16x6
+// P = 2: table entries are packed (hi | lo << 16) bfloat16 splits of the
+// sine and both operands are split in two: three products hi*hi + hi*lo +
+// lo*hi.  P = 3: entries (hi | mid << 16, lo) and three pieces per operand,
+// each the bfloat16 rounding of what the previous ones leave: the six
+// products of piece levels a + b <= 2 (about 24 bits of each operand, the
+// dropped products below 2^-24 relative), accumulated smallest first.
+// 64 rows (4 waves x 16) x TN columns per workgroup; the folded sources of
+// the next 64-deep K stage are loaded into registers while the MFMAs run on
+// the current one, then split and stashed in the other LDS buffer.  A stage
+// is one float32 run, added into the float64 chunk sum.
+template <int P>
+__global__ __launch_bounds__(NTHR) void k_dst_bf16s(
     int n, int Q, const uint32_t *__restrict__ qtab,
     const DstCol *__restrict__ cols, int ncols, int kchunk,
     double *__restrict__ partial, Solve2D *solves) {
   constexpr int PER = KC * TN / NTHR;            // tile values per thread
   constexpr int NB = TN / 16;
+  constexpr int TW = P == 2 ? 1 : 2;             // table words per entry
   extern __shared__ __align__(16) unsigned char smem[];
   const int Qp = (Q + 3) & ~3;
   uint32_t *tab = (uint32_t *)smem;
-  uint16_t *xb0 = (uint16_t *)(tab + Qp);       // [hi|lo][TN][KC] x 2 buffers
+  uint16_t *xb0 = (uint16_t *)(tab + TW * Qp);  // [piece][TN][KC] x 2 buffers
   const int N = n + 1, twoN = 2 * N;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   FoldTile ft;
@@ -513,7 +520,7 @@ __global__ __launch_bounds__(NTHR) void k_dst_bf16x3(
   const int row0 = ft.row0, c0 = ft.c0;
   int cb, ce;
   chunk_range(ft.H0, kchunk, cb, ce);
-  for (int i = tid; i < Q; i += NTHR) tab[i] = qtab[i];
+  for (int i = tid; i < TW * Q; i += NTHR) tab[i] = qtab[i];
 
   // this thread stages point k0 + lane of columns wave + 4 t
   const double *src[PER];
@@ -540,17 +547,19 @@ __global__ __launch_bounds__(NTHR) void k_dst_bf16x3(
     for (int t = 0; t < PER; ++t) fold_load(src[t], kf, kend, n, pa[t], pb[t]);
   };
   auto stash = [&](int st) {
-    uint16_t *xh = xb0 + (st & 1) * 2 * TN * KC, *xl = xh + TN * KC;
+    uint16_t *xs = xb0 + (st & 1) * P * TN * KC;
 #pragma unroll
     for (int t = 0; t < PER; ++t) {
       bool b = false;
-      const double v = fold_combine(pa[t], pb[t], kf, n, ft.par, b);
+      double v = fold_combine(pa[t], pb[t], kf, n, ft.par, b);
       if (b) bad |= 1u << t;
-      const uint32_t h = bf16_bits_rne((float)v);
-      const uint32_t l = bf16_bits_rne((float)(v - (double)bf16_to_float(h)));
       const int c = wave + 4 * t;
-      xh[c * KC + lane] = (uint16_t)h;
-      xl[c * KC + lane] = (uint16_t)l;
+#pragma unroll
+      for (int pc = 0; pc < P; ++pc) {
+        const uint32_t h = bf16_bits_rne((float)v);
+        xs[pc * TN * KC + c * KC + lane] = (uint16_t)h;
+        v -= (double)bf16_to_float(h);
+      }
     }
   };
 
@@ -585,10 +594,10 @@ __global__ __launch_bounds__(NTHR) void k_dst_bf16x3(
         }
     }
     if (st + 1 < nst) fetch(st + 1);
-    const uint16_t *xh = xb0 + (st & 1) * 2 * TN * KC, *xl = xh + TN * KC;
+    const uint16_t *xs = xb0 + (st & 1) * P * TN * KC;
     const int kcn = min(KC, kend - k0);
     for (int kc = 0; kc < kcn; kc += 32) {
-      bf8 ah, al;
+      bf8 a[P];
       int mm = m;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
@@ -599,10 +608,15 @@ __global__ __launch_bounds__(NTHR) void k_dst_bf16x3(
           neg = true;
         }
         if (2 * q > N) q = N - q;
-        uint32_t p = tab[q];
+        uint32_t p = tab[TW * q];
         if (neg) p ^= 0x80008000u;               // negate both halves
-        ah[e] = __builtin_bit_cast(__bf16, (uint16_t)(p & 0xFFFFu));
-        al[e] = __builtin_bit_cast(__bf16, (uint16_t)(p >> 16));
+        a[0][e] = __builtin_bit_cast(__bf16, (uint16_t)(p & 0xFFFFu));
+        a[1][e] = __builtin_bit_cast(__bf16, (uint16_t)(p >> 16));
+        if constexpr (P == 3) {
+          uint32_t p2 = tab[TW * q + 1];
+          if (neg) p2 ^= 0x8000u;
+          a[2][e] = __builtin_bit_cast(__bf16, (uint16_t)(p2 & 0xFFFFu));
+        }
         mm += jm;
         if (mm >= twoN) mm -= twoN;
       }
@@ -611,11 +625,17 @@ __global__ __launch_bounds__(NTHR) void k_dst_bf16x3(
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
         const int c = b * 16 + (lane & 15);
-        const bf8 bh = *(const bf8 *)(xh + c * KC + kc + 8 * kq);
-        const bf8 bl = *(const bf8 *)(xl + c * KC + kc + 8 * kq);
-        run[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, run[b], 0, 0, 0);
-        run[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, run[b], 0, 0, 0);
-        run[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, run[b], 0, 0, 0);
+        bf8 x[P];
+#pragma unroll
+        for (int pc = 0; pc < P; ++pc) x[pc] = *(const bf8 *)(xs + pc * TN * KC + c * KC + kc + 8 * kq);
+        if constexpr (P == 3) {
+          run[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], x[0], run[b], 0, 0, 0);
+          run[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], x[1], run[b], 0, 0, 0);
+          run[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], x[2], run[b], 0, 0, 0);
+        }
+        run[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], x[0], run[b], 0, 0, 0);
+        run[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], x[1], run[b], 0, 0, 0);
+        run[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], x[0], run[b], 0, 0, 0);
       }
     }
 #pragma unroll
@@ -671,15 +691,15 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
   const int Q = quarter_len(n);
   const char *base = (const char *)tab;
   const int Qp8 = (Q + 1) & ~1, Qp4 = (Q + 3) & ~3;
-  // table layout: [f64 x Qp8][f32 x Qp4][u32 x Qp4][int8 records]
+  const TabLayout TL = tab_layout(n);
   if (prec == LRP_PREC_INT8)
-    return launch_dst_i8(n, base + (size_t)Qp8 * 8 + (size_t)Qp4 * 8, (DstCol *)cols, ncols,
-                         solves, partial, partial_elems, work, work_bytes, st, ev0, ev1);
+    return launch_dst_i8(n, base + TL.i8, (DstCol *)cols, ncols, solves, partial,
+                         partial_elems, work, work_bytes, st, ev0, ev1);
   if (prec == LRP_PREC_FFT64)
-    return launch_dst_fft(n, base + dst_fft_table_offset(n), cols, ncols, solves, st, ev0, ev1);
+    return launch_dst_fft(n, base + TL.fft, cols, ncols, solves, st, ev0, ev1);
   const double *t64 = (const double *)base;
-  const float *t32 = (const float *)(base + (size_t)Qp8 * 8);
-  const uint32_t *tbf = (const uint32_t *)(base + (size_t)Qp8 * 8 + (size_t)Qp4 * 4);
+  const float *t32 = (const float *)(base + TL.f32);
+  const uint32_t *tbf = (const uint32_t *)(base + (prec == LRP_PREC_BF16X6 ? TL.bf3 : TL.bf2));
   // folded length, and fixed K chunks of it that depend on n only (at most
   // 4, at least 256 deep, a multiple of every kernel's K stage)
   const int H0 = (n + 1) / 2;
@@ -689,7 +709,7 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
   // alone leave the 256 CUs under-filled
   const bool wide = ncols > 32;
   int tm, tn;
-  if (prec == LRP_PREC_BF16X3) {
+  if (prec == LRP_PREC_BF16X3 || prec == LRP_PREC_BF16X6) {
     tm = TM;
     tn = TN;
   } else {
@@ -730,14 +750,23 @@ hipError_t launch_dst(int prec, int n, const void *tab, const DstCol *cols,
     else
       hipLaunchKernelGGL((k_dst_f32<32, 2>), g, dim3(256), lds, st, n, Q, t32, cols, ncols,
                          kchunk, out_partial, solves);
-  } else {
+  } else if (prec == LRP_PREC_BF16X3) {
     const dim3 g(tile_grid(R, C, true), 1, split);
     lds = (size_t)Qp4 * 4 + (size_t)2 * 2 * KC * TN * 2;
-    e = hipFuncSetAttribute((const void *)k_dst_bf16x3,
+    e = hipFuncSetAttribute((const void *)k_dst_bf16s<2>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dst_bf16x3, g, block, lds, st, n, Q, tbf, cols,
+    hipLaunchKernelGGL(k_dst_bf16s<2>, g, block, lds, st, n, Q, tbf, cols,
+                       ncols, kchunk, out_partial, solves);
+  } else {
+    const dim3 g(tile_grid(R, C, true), 1, split);
+    lds = (size_t)Qp4 * 8 + (size_t)2 * 3 * KC * TN * 2;
+    e = hipFuncSetAttribute((const void *)k_dst_bf16s<3>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (ev0 && (e = hipEventRecord(ev0, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_dst_bf16s<3>, g, block, lds, st, n, Q, tbf, cols,
                        ncols, kchunk, out_partial, solves);
   }
   e = hipGetLastError();

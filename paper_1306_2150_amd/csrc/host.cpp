@@ -91,12 +91,7 @@ static float bf16_float_host(uint32_t b) {
   return f;
 }
 
-size_t sine_table_bytes(int n) {
-  const int Q = (n + 1) / 2 + 1;
-  const int Qp8 = (Q + 1) & ~1, Qp4 = (Q + 3) & ~3;
-  const size_t b = (size_t)Qp8 * 8 + (size_t)Qp4 * 4 + (size_t)Qp4 * 4 + dst_i8_table_bytes(n);
-  return dst_fft_supported(n) ? dst_fft_table_offset(n) + dst_fft_table_bytes(n) : b;
-}
+size_t sine_table_bytes(int n) { return tab_layout(n).end; }
 
 // Quarter-wave tables of sqrt(2/N) sin(pi q/N), q = 0..floor(N/2), in the
 // layout launch_dst reads ([f64][f32][bf16 hi|lo][int8 records]), evaluated
@@ -104,13 +99,14 @@ size_t sine_table_bytes(int n) {
 void build_sine_table(int n, char *out) {
   const int N = n + 1;
   const int Q = N / 2 + 1;
-  const int Qp8 = (Q + 1) & ~1, Qp4 = (Q + 3) & ~3;
-  std::memset(out, 0, sine_table_bytes(n));
-  dst_i8_table(n, (unsigned char *)out + (size_t)Qp8 * 8 + (size_t)Qp4 * 8);
-  if (dst_fft_supported(n)) dst_fft_table(n, (double *)(out + dst_fft_table_offset(n)));
+  const TabLayout L = tab_layout(n);
+  std::memset(out, 0, L.end);
+  dst_i8_table(n, (unsigned char *)out + L.i8);
+  if (dst_fft_supported(n)) dst_fft_table(n, (double *)(out + L.fft));
   double *t64 = (double *)out;
-  float *t32 = (float *)(out + (size_t)Qp8 * 8);
-  uint32_t *tbf = (uint32_t *)(out + (size_t)Qp8 * 8 + (size_t)Qp4 * 4);
+  float *t32 = (float *)(out + L.f32);
+  uint32_t *tbf = (uint32_t *)(out + L.bf2);
+  uint32_t *tb3 = (uint32_t *)(out + L.bf3);   // pairs: hi | mid << 16, lo
   const long double pi = 3.14159265358979323846264338327950288L;
   const long double scale = sqrtl(2.0L / (long double)N);
   for (int q = 0; q < Q; ++q) {
@@ -120,6 +116,13 @@ void build_sine_table(int n, char *out) {
     const uint32_t hi = bf16_rne_host((float)v);
     const uint32_t lo = bf16_rne_host((float)(v - (long double)bf16_float_host(hi)));
     tbf[q] = hi | (lo << 16);
+    // three-piece split: each piece the bfloat16 rounding of what the
+    // previous pieces leave (about 24 significant bits together)
+    const long double r1 = v - (long double)bf16_float_host(hi);
+    const uint32_t mid = bf16_rne_host((float)r1);
+    const uint32_t lo3 = bf16_rne_host((float)(r1 - (long double)bf16_float_host(mid)));
+    tb3[2 * q] = hi | (mid << 16);
+    tb3[2 * q + 1] = lo3;
   }
 }
 
@@ -193,7 +196,7 @@ Plan make_plan(const lrp_opts *o, double eps, int n) {
       p.inv_prec = eps >= 1e-7 ? LRP_PREC_FP32 : LRP_PREC_FP64;
     }
   } else if (prec == LRP_PREC_FP32 || prec == LRP_PREC_BF16X3 || prec == LRP_PREC_INT8 ||
-             prec == LRP_PREC_FFT64) {
+             prec == LRP_PREC_FFT64 || prec == LRP_PREC_BF16X6) {
     // INT8 / FFT64 callers check dst_i8_supported(n) / dst_fft_supported(n)
     p.fwd_prec = p.inv_prec = prec;
   } else {
@@ -206,7 +209,8 @@ bool transform_prec_ok(int prec, int n) {
   switch (prec) {
     case LRP_PREC_FP64:
     case LRP_PREC_FP32:
-    case LRP_PREC_BF16X3: return true;
+    case LRP_PREC_BF16X3:
+    case LRP_PREC_BF16X6: return true;
     case LRP_PREC_INT8: return dst_i8_supported(n);
     case LRP_PREC_FFT64: return dst_fft_supported(n);
     default: return false;
@@ -215,7 +219,7 @@ bool transform_prec_ok(int prec, int n) {
 
 lrp_status check_opts(const lrp_opts *o) {
   if (!o) return LRP_OK;
-  if (o->prec < 0 || o->prec > LRP_PREC_FFT64) return LRP_EINVAL;
+  if (o->prec < 0 || o->prec > LRP_PREC_BF16X6) return LRP_EINVAL;
   if (o->max_sweeps < 0 || o->max_sweeps > LRP_MAX_SWEEPS) return LRP_EINVAL;
   if (o->rank_cap < 0 || o->kick < 0 || o->maxvol_tau < 0.0) return LRP_EINVAL;
   if (o->op != LRP_OP_LAPLACE && o->op != LRP_OP_STOKES) return LRP_EINVAL;
@@ -703,7 +707,7 @@ lrp_status lrp_set_kernel_timing(lrp_ctx *ctx, int32_t enable) {
 
 lrp_status lrp_kernel_stats(lrp_ctx *ctx, int32_t prec, lrp_kernel_stat *out,
                             int32_t reset) {
-  if (!ctx || prec < 0 || prec > LRP_PREC_FFT64 || prec == LRP_PREC_AUTO) return LRP_EINVAL;
+  if (!ctx || prec < 0 || prec > LRP_PREC_BF16X6 || prec == LRP_PREC_AUTO) return LRP_EINVAL;
   std::lock_guard<std::mutex> lock(ctx->mu);
   if (hipSetDevice(ctx->device) != hipSuccess) return LRP_EDEVICE;
   for (auto &pt : ctx->pending_times) {

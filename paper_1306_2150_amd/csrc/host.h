@@ -206,7 +206,7 @@ struct lrp_ctx {
     double flops;
   };
   std::vector<PendingTime> pending_times;
-  lrp_kernel_stat kstat[LRP_PREC_FFT64 + 1] = {};
+  lrp_kernel_stat kstat[LRP_PREC_BF16X6 + 1] = {};
   // phase events of the synchronous calls (forward, cross, inverse)
   hipEvent_t phase_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::mutex mu;
@@ -227,7 +227,7 @@ bool transform_prec_ok(int prec, int n);
 double transform_flops(int prec, int n);
 // every transform precision, in the order the groups launch them
 constexpr int ALL_PRECS[] = {LRP_PREC_FP64, LRP_PREC_FP32, LRP_PREC_BF16X3, LRP_PREC_INT8,
-                             LRP_PREC_FFT64};
+                             LRP_PREC_FFT64, LRP_PREC_BF16X6};
 // phase timing of a synchronous call: record event i (0..3) on st
 void phase_mark(lrp_ctx *ctx, int i, hipStream_t st);
 // after the stream completed: the three phase durations in microseconds

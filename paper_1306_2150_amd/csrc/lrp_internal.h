@@ -305,12 +305,26 @@ void dst_fft_table(int n, double *out);
 hipError_t launch_dst_fft(int n, const void *tab, const DstCol *cols, int ncols,
                           Solve2D *solves, hipStream_t st, hipEvent_t ev0 = nullptr,
                           hipEvent_t ev1 = nullptr);
-inline size_t dst_fft_table_offset(int n) {
+// The grid's table block, per n (Q = floor(N/2) + 1 quarter-wave entries,
+// Qp8 = Q rounded up to 2, Qp4 = Q rounded up to 4):
+//   [float64 x Qp8][float32 x Qp4][bf16 hi|lo x Qp4 (uint32)]
+//   [bf16 hi|mid, lo x Qp4 (uint2)][int8 sine records][FFT tables]
+struct TabLayout {
+  size_t f32, bf2, bf3, i8, fft, end;
+};
+inline TabLayout tab_layout(int n) {
   const int Q = (n + 1) / 2 + 1;
-  const int Qp8 = (Q + 1) & ~1, Qp4 = (Q + 3) & ~3;
-  const size_t o = (size_t)Qp8 * 8 + (size_t)Qp4 * 8 + dst_i8_table_bytes(n);
-  return (o + 255) & ~(size_t)255;
+  const size_t Qp8 = (size_t)((Q + 1) & ~1), Qp4 = (size_t)((Q + 3) & ~3);
+  TabLayout L;
+  L.f32 = Qp8 * 8;
+  L.bf2 = L.f32 + Qp4 * 4;
+  L.bf3 = L.bf2 + Qp4 * 4;
+  L.i8 = L.bf3 + Qp4 * 8;
+  L.fft = (L.i8 + dst_i8_table_bytes(n) + 255) & ~(size_t)255;
+  L.end = dst_fft_supported(n) ? L.fft + dst_fft_table_bytes(n) : L.i8 + dst_i8_table_bytes(n);
+  return L;
 }
+inline size_t dst_fft_table_offset(int n) { return tab_layout(n).fft; }
 hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, Solve2D *solves,
                          double *partial, size_t partial_elems, void *work,
                          size_t work_bytes, hipStream_t st, hipEvent_t ev0 = nullptr,

@@ -34,7 +34,7 @@ constexpr int SERVE_SLOTS = 32;                      // slots per 2D group
 constexpr size_t SERVE3_SHARE = (size_t)16 << 30;   // bytes per 3D group
 
 lrp_status check_request(const lrp_request &q) {
-  if (q.prec < 0 || q.prec > LRP_PREC_FFT64) return LRP_EINVAL;
+  if (q.prec < 0 || q.prec > LRP_PREC_BF16X6) return LRP_EINVAL;
   if (q.op != LRP_OP_LAPLACE && q.op != LRP_OP_STOKES) return LRP_EINVAL;
   if (q.reserved != 0) return LRP_EINVAL;
   if (q.prec != LRP_PREC_AUTO &&

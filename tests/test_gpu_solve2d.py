@@ -142,7 +142,7 @@ def test_dst_int8_wide_tiles_match_oracle_and_narrow(n, c):
     assert np.array_equal(Ys, Y[:, sub])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
 def test_dst_columns_independent_of_batch(prec):
     """The folded transform's K chunks depend on n only: a column's result is
     the same bits whether its launch splits K over workgroups (few columns)
@@ -156,7 +156,7 @@ def test_dst_columns_independent_of_batch(prec):
     assert np.array_equal(big[:, 7:9], small)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("bf16x3", 5e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("bf16x3", 5e-5), ("bf16x6", 1e-6)])
 @pytest.mark.parametrize("n,c", [(1, 1), (2, 3), (3, 2), (64, 5), (65, 40), (1001, 33)])
 def test_dst_reduced_precision_odd_even_sizes(prec, tol, n, c):
     """Both parities of the folded transform, odd and even n (with and
@@ -169,7 +169,7 @@ def test_dst_reduced_precision_odd_even_sizes(prec, tol, n, c):
     assert e <= tol, e
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("bf16x3", 5e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-6), ("bf16x3", 5e-5), ("bf16x6", 3e-7)])
 def test_dst_reduced_precision_error_bound(prec, tol):
     log("dst", prec)
     n, c = 4096, 32
@@ -192,7 +192,7 @@ def solve_and_check(U, V, eps, prec="fp64", bar=None, **kw):
     if Vx.shape[1]:
         # orthonormal to the precision of the inverse transform
         otol = {"fp64": 1e-10, "int8": 1e-10, "fft64": 1e-10, "fp32": 1e-6,
-                "bf16x3": 1e-4}[info["inv_prec"]]
+                "bf16x6": 1e-6, "bf16x3": 1e-4}[info["inv_prec"]]
         assert np.max(np.abs(Vx.T @ Vx - np.eye(Vx.shape[1]))) < otol
     return e, info
 
@@ -358,6 +358,7 @@ def test_prepared_batch_reruns_identically():
 
 
 @pytest.mark.parametrize("prec,eps,bar", [("fft64", 1e-8, 1e-7), ("fft64", 1e-12, 1e-11),
+                                          ("bf16x6", 1e-7, 1e-6),
                                           ("fp32", 1e-7, 1e-6), ("auto", 1e-8, 1e-7),
                                           ("auto", 1e-7, 1e-6), ("auto", 1e-6, 1e-5),
                                           ("bf16x3", 1e-5, 1e-4), ("int8", 1e-8, 1e-7),
@@ -378,13 +379,12 @@ def n16384_case():
     return U, V, X
 
 
-@pytest.mark.parametrize("prec,bar", [("fp64", 1e-6), ("auto", 1e-6), ("int8", 1e-6),
-                                      ("fp32", 1e-6), ("bf16x3", 5e-5)])
-def test_precision_workload_n16384(n16384_case, prec, bar):
+@pytest.mark.parametrize("prec", ["fp64", "auto", "int8", "fp32", "bf16x6"])
+def test_precision_workload_n16384(n16384_case, prec):
     """Error of every transform precision against the float64 full solve at
-    n = 16384, r = 32, eps = 1e-7 (the acceptance bar 10 eps = 1e-6 for the
-    float64, int8 and FP32 plans; BF16x3 transforms have a relative error
-    floor near 5e-6, so their bar is that floor's order)."""
+    n = 16384, r = 32, eps = 1e-7, held to the acceptance bar 10 eps = 1e-6:
+    float64, int8 slices, FP32 and the split-BF16 plan with three pieces and
+    six products."""
     U, V, X = n16384_case
     log("precision n=16384", prec)
     Ux, Vx, info = ctx().solve2d(dev(U), dev(V), 1e-7, prec=prec)
@@ -394,7 +394,21 @@ def test_precision_workload_n16384(n16384_case, prec, bar):
     assert info["status_code"] == binding.LRP_OK
     if prec != "auto":
         assert info["fwd_prec"] == prec and info["inv_prec"] == prec, info
-    assert e <= bar, e
+    assert e <= 1e-6, e
+
+
+def test_precision_workload_n16384_bf16x3_floor(n16384_case):
+    """The two-piece split-BF16 plan (three products) cannot meet 10 eps =
+    1e-6 here: its transforms carry a relative error floor of a few 1e-6
+    that the inverse transform passes straight to the result.  Not a pass of
+    the acceptance bar: the test records the floor and checks that it stays
+    in its measured band (above the bar, below 1e-5)."""
+    U, V, X = n16384_case
+    log("precision n=16384 bf16x3 floor")
+    Ux, Vx, info = ctx().solve2d(dev(U), dev(V), 1e-7, prec="bf16x3")
+    e = metrics.rel_err_factored(host(Ux), host(Vx), X)
+    log("  bf16x3 floor err", e)
+    assert 1e-6 < e < 1e-5, e
 
 
 def test_int8_plan_limits():

@@ -13,7 +13,8 @@ from gpu_util import ctx, dev, host, log, rel
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-13, "int8": 1e-11, "fft64": 1e-14, "fp32": 1e-6, "bf16x3": 5e-5}
+TOL = {"fp64": 1e-13, "int8": 1e-11, "fft64": 1e-14, "fp32": 1e-6, "bf16x3": 5e-5,
+       "bf16x6": 1e-6}
 
 
 def check(n, c, prec, seed):
@@ -41,7 +42,8 @@ def test_noalloc_grid_sizes_and_precisions():
     for i, (n, c, prec) in enumerate([(1000, 200, "fp64"), (1, 3, "fp64"), (12000, 90, "int8"),
                                       (3001, 64, "fp32"), (3001, 5, "bf16x3"),
                                       (16384, 600, "int8"), (257, 9, "int8"),
-                                      (4096, 300, "fft64"), (2049, 3, "fft64")]):
+                                      (4096, 300, "fft64"), (2049, 3, "fft64"),
+                                      (20000, 70, "bf16x6")]):
         check(n, c, prec, 10 + i)
 
 
