@@ -54,7 +54,7 @@ extern "C" {
 #endif
 
 #define LRP_MAX_N 32767   /* grid points per axis (sine table lives in LDS) */
-#define LRP_MAX_N3 1024   /* grid points per axis of a 3D solve            */
+#define LRP_MAX_N3 32767  /* grid points per axis of a 3D solve            */
 #define LRP_MAX_RANK 64   /* input rank and cross-rank cap (per mode in 3D) */
 #define LRP_MAX_SWEEPS 64 /* largest accepted lrp_opts.max_sweeps           */
 
@@ -229,19 +229,24 @@ lrp_status lrpoisson_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t count,
                                    void *stream);
 
 /* One 3D solve in Tucker format (Section 3, eq. "tucker"; the 3D case of
- * Section 4.1): F = G x1 U1 x2 U2 x3 U3 on the 7-point Dirichlet Laplacian,
- * denominators lambda_i + lambda_j + lambda_k.  Each mode unfolding of the
- * divided spectrum (n x n^2) is approximated by the cross of the 2D solver
- * to eps/sqrt(3); the cross bases and their maxvol rows give an
- * interpolating Tucker approximation whose core is rounded by truncated
- * HOSVD at eps/sqrt(3) per mode.  U1, U2, U3: n x rank[d] (ld >= n),
- * n <= LRP_MAX_N3; G: rank[0] x rank[1] x rank[2], i1 fastest.  Outputs
- * U1x, U2x, U3x: n x rmax[d] (ldx >= n); Gx: capacity
+ * Section 4.1): F = G x1 U1 x2 U2 x3 U3 on the 7-point Dirichlet Laplacian
+ * (or the Stokes operator, lrp_opts.op), denominators
+ * lambda_i + lambda_j + lambda_k.  Tucker cross: every mode keeps a pivot
+ * set; an outer sweep approximates each mode's fiber matrix (all indices of
+ * the mode against the pairs of the other two modes' pivots, n x k_p k_q)
+ * by the cross of the 2D solver to eps/sqrt(3), which gives the mode's new
+ * basis and pivots; the outer sweeps stop once the mode ranks repeat.  The
+ * bases and pivots give an interpolating Tucker approximation whose core is
+ * rounded by truncated HOSVD at eps/sqrt(3) per mode.  U1, U2, U3:
+ * n x rank[d] (ld >= n), n <= LRP_MAX_N3; G: rank[0] x rank[1] x rank[2],
+ * i1 fastest.  Outputs U1x, U2x, U3x: n x rmax[d] (ldx >= n); Gx: capacity
  * rmax[0]*rmax[1]*rmax[2], written as rank_out[0] x rank_out[1] x
- * rank_out[2], i1 fastest.  info: sweeps and k are the largest over the
- * three mode crosses, rank the largest output rank, change the largest
- * last change.  Workspace: about 2.9 GB at n = 512 (three n x n^2 cross
- * slots), taken from the context budget. */
+ * rank_out[2], i1 fastest.  info: sweeps is the number of outer sweeps, k
+ * the largest mode rank, rank the largest output rank, change the largest
+ * last change of the mode crosses.  LRP_ENOCONV when the outer sweeps reach
+ * max_sweeps without the ranks repeating.  Workspace: about 60 MB at
+ * n = 512 (three n x 4096 cross slots and the cores), linear in n, taken
+ * from the context budget. */
 lrp_status lrpoisson_solve3d(lrp_ctx *ctx, int64_t n, const int32_t rank[3],
                              const double *U1, const double *U2,
                              const double *U3, int64_t ld, const double *G,

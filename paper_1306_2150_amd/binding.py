@@ -33,7 +33,7 @@ OP = {"laplace": 0, "stokes": 1}
 
 MAX_RANK = 64
 MAX_N = 32767
-MAX_N3 = 1024
+MAX_N3 = 32767
 MAX_SWEEPS = 64
 PHASES = ("forward", "cross", "inverse")
 

@@ -244,29 +244,6 @@ __global__ __launch_bounds__(NTHR) void k_change_norms(Solve2D *S) {
   }
 }
 
-// count evenly spaced indices in [0, n) avoiding used[0:nu);
-// (floor((2i+1)n/(2count)) + off) mod n moved to the next free index
-// (cyclically).  Single thread.
-__device__ void spread_indices(int n, int count, int *used, int nu, int *out, int off) {
-  int have = nu;
-  for (int i = 0; i < count; ++i) {
-    if (have >= n) break;
-    int j = (int)((((long long)(2 * i + 1) * n) / (2LL * count) + off) % n);
-    for (;;) {
-      bool taken = false;
-      for (int t = 0; t < have; ++t)
-        if (used[t] == j) {
-          taken = true;
-          break;
-        }
-      if (!taken) break;
-      j = (j + 1) % n;
-    }
-    used[have++] = j;
-    out[i] = j;
-  }
-}
-
 // Truncation rank, convergence and growth decision (one workgroup / solve).
 __global__ __launch_bounds__(NTHR) void k_decide(Solve2D *S) {
   Solve2D &s = S[blockIdx.x];

@@ -111,7 +111,7 @@ class Group2D {
 };
 
 // A group of 3D (Tucker) solve slots of one grid size n.  Slot i owns the
-// mode slots 3i, 3i+1, 3i+2 of an n x n^2 cross group.
+// mode slots 3i, 3i+1, 3i+2 of a cross group of n x FIB_M fiber matrices.
 class Group3D {
  public:
   Group3D(lrp_ctx *ctx, int n, int cap);
@@ -151,7 +151,6 @@ class Group3D {
   int n_, cap_;
   size_t bytes_ = 0;
   char *ws_ = nullptr;
-  double *mu_ = nullptr;     // Laplace column table, then the two Stokes ones
   std::unique_ptr<Group2D> inner_;
   Solve3D *d_s_ = nullptr, *h_s_ = nullptr;
   std::vector<Plan> plans_;

@@ -27,35 +27,30 @@ size_t Group3D::bytes() const { return bytes_ + (inner_ ? inner_->bytes() : 0); 
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-static size_t own_slot_bytes(int n) {
-  const size_t t_elems = (size_t)KMAX * KMAX * n;
-  return 3 * align256(t_elems * 8) + 2 * align256((size_t)CORE_MAX * 8);
+// half-contracted cores (r_d x r_p x k_q <= KMAX^3), the column tables of
+// the three fiber matrices, two core buffers
+static constexpr size_t T_ELEMS = (size_t)KMAX * KMAX * KMAX;
+static size_t own_slot_bytes() {
+  return 3 * align256(T_ELEMS * 8) + 6 * align256((size_t)FIB_M * 8) +
+         2 * align256((size_t)CORE_MAX * 8);
 }
 
-size_t solve3d_slot_bytes(int n) {
-  return own_slot_bytes(n) + 3 * cross_slot_bytes(n, n * n);
-}
+size_t solve3d_slot_bytes(int n) { return own_slot_bytes() + 3 * cross_slot_bytes(n, FIB_M); }
 
 lrp_status Group3D::init() {
   lrp_status err;
   const GridTables *tabs = get_tables(ctx_, n_, &err);
   if (!tabs) return err;
-  const size_t m = (size_t)n_ * n_;
-  const size_t t_elems = (size_t)KMAX * KMAX * n_;
-  const size_t per_slot = own_slot_bytes(n_);
+  const size_t per_slot = own_slot_bytes();
   const size_t solves_b = align256(sizeof(Solve3D) * cap_);
-  // column tables over the pairs: Laplace mu, Stokes Pc and Qc
-  bytes_ = align256(3 * m * 8) + solves_b + per_slot * cap_;
+  bytes_ = solves_b + per_slot * cap_;
   void *p = nullptr;
   if ((err = dev_alloc(ctx_, &p, bytes_)) != LRP_OK) return err;
   ws_ = (char *)p;
-  mu_ = (double *)ws_;
-  d_s_ = (Solve3D *)(ws_ + align256(3 * m * 8));
-  char *slots = (char *)d_s_ + solves_b;
-  HIPCHK3(launch_mu(n_, tabs->lam, tabs->sp, tabs->sq, mu_, mu_ + m, mu_ + 2 * m, nullptr));
-  HIPCHK3(hipDeviceSynchronize());
-  const double *col[3] = {mu_, mu_ + m, mu_ + 2 * m};
-  inner_.reset(new Group2D(ctx_, n_, 3 * cap_, (int)m, col));
+  d_s_ = (Solve3D *)ws_;
+  char *slots = ws_ + solves_b;
+  // mode slots: n rows, the FIB_M fiber columns (column tables per slot)
+  inner_.reset(new Group2D(ctx_, n_, 3 * cap_, FIB_M, nullptr));
   if ((err = inner_->init()) != LRP_OK) {
     inner_.reset();
     return err;
@@ -70,11 +65,17 @@ lrp_status Group3D::init() {
     char *b = slots + per_slot * i;
     s.n = n_;
     for (int d = 0; d < 3; ++d) {
-      s.T[d] = (double *)(b + d * align256(t_elems * 8));
+      s.T[d] = (double *)(b + d * align256(T_ELEMS * 8));
       s.inner[d] = inner_->dev_solves() + 3 * i + d;
     }
-    s.buf0 = (double *)(b + 3 * align256(t_elems * 8));
-    s.buf1 = (double *)(b + 3 * align256(t_elems * 8) + align256((size_t)CORE_MAX * 8));
+    char *c = b + 3 * align256(T_ELEMS * 8);
+    for (int d = 0; d < 3; ++d) {
+      s.lamc[d] = (double *)(c + (2 * d) * align256((size_t)FIB_M * 8));
+      s.lqc[d] = (double *)(c + (2 * d + 1) * align256((size_t)FIB_M * 8));
+    }
+    c += 6 * align256((size_t)FIB_M * 8);
+    s.buf0 = (double *)c;
+    s.buf1 = (double *)(c + align256((size_t)CORE_MAX * 8));
     s.phase = P3_IDLE;
   }
   HIPCHK3(hipMemcpy(d_s_, h_s_, sizeof(Solve3D) * cap_, hipMemcpyHostToDevice));
@@ -100,17 +101,27 @@ void Group3D::setup_slot(int i, const double *const U[3], long ld, const int r[3
   s.eps = eps;
   s.G = G;
   s.Gx = Gx;
-  s.phase = P3_CROSS;
+  s.phase = P3_SETUP;
+  s.outer = 0;
+  s.kick = plan.kick;
+  s.kcap = plan.kcap;
+  s.max_outer = plan.max_sweeps;
+  for (int d = 0; d < 3; ++d) s.kf[d] = 0;
   s.cross_status = LRP_OK;
   s.status = LRP_OK;
   s.out_ok = 0;
   s.nrm = 0.0;
-  // every mode cross works at eps / sqrt(3) on its n x n^2 unfolding; its
-  // numerator rank is the mode's Tucker rank
+  // every mode cross works at eps / sqrt(3) on its fiber matrix; its
+  // numerator rank is the mode's Tucker rank.  The column tables are the
+  // slot's own (filled when the fibers are built).
   const double ed = eps / std::sqrt(3.0);
-  for (int d = 0; d < 3; ++d)
+  for (int d = 0; d < 3; ++d) {
     inner_->setup_slot(3 * i + d, nullptr, nullptr, 0, r[d], ed, nullptr, nullptr, 0,
                        KMAX, plan);
+    Solve2D &m = inner_->host(3 * i + d);
+    m.lam_c = s.lamc[d];
+    m.lq_c = (plan.op == LRP_OP_STOKES) ? s.lqc[d] : nullptr;
+  }
 }
 
 lrp_status Group3D::start(const std::vector<int> &slots, hipStream_t st) {
@@ -143,7 +154,8 @@ lrp_status Group3D::start(const std::vector<int> &slots, hipStream_t st) {
   }
   int hi = 0;
   for (int i : slots) hi = std::max(hi, i + 1);
-  HIPCHK3(launch_unfold_factors(d_s_, hi, n_, rmax_in, st));
+  // the first fibers (evenly spaced pivots) and the mode crosses' start
+  HIPCHK3(launch_fiber_setup(d_s_, hi, rmax_in, st));
   return LRP_OK;
 }
 
@@ -154,10 +166,15 @@ lrp_status Group3D::step(hipStream_t st) {
   if (hi == 0) return LRP_OK;
   lrp_status e = inner_->step(st);
   if (e != LRP_OK) return e;
-  // solves whose three crosses just finished: core, its unfoldings' TSQR and
-  // Jacobi SVD, output ranks, factors and core (all gated on the device)
-  const int m = n_ * n_;
-  const int P = std::min(KMAX * KMAX, m);
+  // solves whose three crosses just finished: another outer sweep on new
+  // fibers, or the core, its unfoldings' TSQR and Jacobi SVD, output ranks,
+  // factors and core (all gated on the device)
+  int rmax_in = 1;
+  for (int i = 0; i < hi; ++i)
+    for (int d = 0; d < 3; ++d) rmax_in = std::max(rmax_in, h_s_[i].r[d]);
+  HIPCHK3(launch_fiber_outer(d_s_, hi, st));
+  HIPCHK3(launch_fiber_setup(d_s_, hi, rmax_in, st));
+  const int P = KMAX * KMAX;
   const Tree tp = make_tree(P, KMAX);
   HIPCHK3(launch_core_build(d_s_, hi, st));
   HIPCHK3(launch_core_unfold(d_s_, hi, P, st));
@@ -198,11 +215,10 @@ lrp_status Group3D::finish(const std::vector<int> &slots, hipStream_t st) {
 // Result report of a finished slot.
 void fill_info3d(Group3D &g, int i, int32_t rank_out[3], lrp_info *info) {
   const Solve3D &s = g.host(i);
-  int sweeps = 0, k = 0, R = 0;
+  int sweeps = s.outer, k = 0, R = 0;
   double change = -1.0, est = 0.0;
   for (int d = 0; d < 3; ++d) {
     const Solve2D &m = g.modes().host(3 * i + d);
-    sweeps = std::max(sweeps, m.sweep);
     k = std::max(k, m.k);
     R = std::max(R, s.R[d]);
     change = std::max(change, m.change);
@@ -293,10 +309,11 @@ extern "C" lrp_status lrpoisson_solve3d(lrp_ctx *ctx, int64_t n, const int32_t r
   phase_mark(ctx, 0, st);
   if ((e = g.start({0}, st)) != LRP_OK) return e;
   phase_mark(ctx, 1, st);
-  // the mode crosses stop after at most max_sweeps (<= LRP_MAX_SWEEPS)
-  // sweeps; the core and its rounding take a few more steps
+  // at most max_sweeps outer sweeps, each of at most max_sweeps mode-cross
+  // sweeps plus its initial step; the core and its rounding take a few more
   bool done = false;
-  for (int it = 0; it <= LRP_MAX_SWEEPS + 8 && !done; ++it) {
+  const int cap = (plan.max_sweeps + 2) * (plan.max_sweeps + 1) + 8;
+  for (int it = 0; it <= cap && !done; ++it) {
     if ((e = g.step(st)) != LRP_OK) return e;
     if ((e = g.fetch(st)) != LRP_OK) return e;
     done = g.host(0).phase == P3_DONE;

@@ -103,10 +103,12 @@ struct Solve2D {
 };
 
 // Per-solve device state of a 3D (Tucker) solve.  Mode d is approximated by
-// the cross of the mode-d unfolding of the divided spectrum, held in the
-// Solve2D slot inner[d] (n rows, n^2 columns: the pairs (j, l) of the other
-// two modes p < q, column index j + n l).
+// the cross of its fiber matrix, held in the Solve2D slot inner[d]: n rows,
+// and as columns the pairs (j, l) of the other two modes' pivot sets
+// (p < q, column index j + k_p l, k_p k_q <= FIB_M; the columns beyond are
+// zero).  Outer sweeps rebuild the fiber matrices from the latest pivots.
 constexpr int CORE_MAX = KMAX * KMAX * KMAX;   // entries of a Tucker core buffer
+constexpr int FIB_M = KMAX * KMAX;             // fiber-matrix columns of a mode slot
 struct Solve3D {
   int n;
   int r[3];                 // input Tucker ranks
@@ -115,10 +117,15 @@ struct Solve3D {
   const double *G;          // input core r0 x r1 x r2 (i0 fastest)
   double *Gx;               // output core R0 x R1 x R2
   Solve2D *inner[3];        // device addresses of the mode slots
-  double *T[3];             // r_d x r_p x n  half-contracted core per mode
+  double *T[3];             // r_d x r_p x k_q  half-contracted core per mode
+  double *lamc[3], *lqc[3]; // FIB_M column tables of each mode slot
   double *buf0, *buf1;      // CORE_MAX each, ping-pong for mode products
+  int kick, kcap, max_outer;
   // ---- control
   int phase;                // P3_*
+  int outer;                // outer sweeps finished
+  int kf[3];                // mode ranks of the last outer sweep
+  int If[3][KMAX];          // pivot sets of the last outer sweep
   int k[3];                 // cross ranks of the modes (set before the core)
   int R[3];                 // output ranks
   int cross_status;         // combined status of the three mode crosses
@@ -132,6 +139,7 @@ enum : int {
   P3_CORE = 2,    // core built, unfoldings being factored
   P3_OUT = 3,     // output factors and core being written
   P3_DONE = 4,    // finished (status, R valid)
+  P3_SETUP = 5,   // fiber matrices to (re)build, mode crosses to restart
 };
 
 // One column of a sine-transform GEMM: dst[0:n] = S * src[0:n].
@@ -269,6 +277,29 @@ inline int tile_grid(int R, int C, bool xcd) {
   return xcd ? 8 * ceil_div(R * C, 8) : R * C;
 }
 
+// count evenly spaced indices in [0, n) avoiding used[0:nu);
+// (floor((2i+1)n/(2count)) + off) mod n moved to the next free index
+// (cyclically).  Single thread.
+__device__ inline void spread_indices(int n, int count, int *used, int nu, int *out, int off) {
+  int have = nu;
+  for (int i = 0; i < count; ++i) {
+    if (have >= n) break;
+    int j = (int)((((long long)(2 * i + 1) * n) / (2LL * count) + off) % n);
+    for (;;) {
+      bool taken = false;
+      for (int t = 0; t < have; ++t)
+        if (used[t] == j) {
+          taken = true;
+          break;
+        }
+      if (!taken) break;
+      j = (j + 1) % n;
+    }
+    used[have++] = j;
+    out[i] = j;
+  }
+}
+
 // Row index from a pivot array, kept inside [0, n) so that a bookkeeping
 // error can never turn into an out-of-bounds access.
 __device__ __forceinline__ int clamp_row(int i, int n) {
@@ -357,10 +388,11 @@ hipError_t launch_decide(int n, int m, Solve2D *s, int nsolves, int kmax,
 hipError_t launch_init_J(Solve2D *s, int nsolves, hipStream_t st);
 
 // ---- 3D path (tucker.hip)
-hipError_t launch_mu(int n, const double *lam, const double *sp, const double *sq,
-                     double *mu, double *pc, double *qc, hipStream_t st);
-hipError_t launch_unfold_factors(Solve3D *s, int nsolves, int n, int rmax,
-                                 hipStream_t st);
+// After the mode crosses: the outer decision (restart on new fibers, or the
+// core), then the fiber matrices of every solve in P3_SETUP (their column
+// factors and tables, the mode slots reset to start a cross).
+hipError_t launch_fiber_outer(Solve3D *s, int nsolves, hipStream_t st);
+hipError_t launch_fiber_setup(Solve3D *s, int nsolves, int rmax, hipStream_t st);
 hipError_t launch_core_build(Solve3D *s, int nsolves, hipStream_t st);
 hipError_t launch_core_unfold(Solve3D *s, int nsolves, int P, hipStream_t st);
 hipError_t launch_tucker_out(Solve3D *s, int nsolves, int n, hipStream_t st);

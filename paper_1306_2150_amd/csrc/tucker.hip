@@ -4,16 +4,20 @@
 // eq. "tucker").
 //
 // With Uh_d = S U_d the divided spectrum is
-//     Xh(i0, i1, i2) = (G x_0 Uh_0[i0] x_1 Uh_1[i1] x_2 Uh_2[i2]) /
-//                      (lambda_i0 + lambda_i1 + lambda_i2).
-// Its mode-d unfolding (n x n^2, columns = pairs (j, l) of the other modes
-// p < q, index j + n l) is a rectangular divided spectrum of the 2D kind:
-//     Xh_(d)[i, j + n l] = (Uh_d[i] . W_d[j + n l]) / (lambda_i + mu_{j+nl}),
-//     W_d[j + n l, a] = sum_bc G_d[a, b, c] Uh_p[j, b] Uh_q[l, c],
-//     mu_{j+nl} = lambda_j + lambda_l,
-// so the cross kernels of the 2D solver approximate every unfolding to
-// eps/sqrt(3).  The column basis Q_d (n x k_d, orthonormal) and the maxvol
-// rows I_d of each mode's final sweep define the interpolating projectors
+//     Xh(i0, i1, i2) = (G x_0 Uh_0[i0] x_1 Uh_1[i1] x_2 Uh_2[i2]) / D(i0, i1, i2),
+// D the operator's eigenvalue (lambda_i0 + lambda_i1 + lambda_i2 for the
+// 7-point Laplacian).  Each mode d keeps a pivot set I_d (k_d indices).  An
+// outer sweep approximates, for every mode at once, its fiber matrix
+//     C_d[i, j + k_p l] = Xh restricted to mode d's index i and the pair
+//                         (I_p[j], I_q[l]) of the other modes p < q,
+//                       = (Uh_d[i] . W_d[j + k_p l]) / (lambda_i + mu_(j + k_p l)),
+//     W_d[j + k_p l, a] = sum_bc G_d[a, b, c] Uh_p[I_p[j], b] Uh_q[I_q[l], c],
+// an n x k_p k_q matrix of the 2D kind (rectangular, general column
+// denominators), by the cross kernels of the 2D solver to eps/sqrt(3): its
+// column basis Q_d (n x k_d) and maxvol rows give the new I_d and k_d.  The
+// outer sweeps stop at the first one (from the second on) whose mode ranks
+// k_d repeat the previous sweep's (the sweep cap ends them otherwise).  The
+// final bases and pivots define the interpolating projectors
 // P_d = Q_d (Q_d[I_d, :])^-1 E_{I_d}^T, and
 //     X~ = Xh x_0 P_0 x_1 P_1 x_2 P_2 = C x_d Q_d,
 //     C = Xh(I_0, I_1, I_2) x_0 (Q_0[I_0])^-1 x_1 (Q_1[I_1])^-1 x_2 (Q_2[I_2])^-1.
@@ -23,6 +27,8 @@
 // factor (the 2D kernels again), so the output is
 //     factors S (Q_d W_d[:, :R_d])  (orthonormal columns),
 //     core    C x_0 W_0^T x_1 W_1^T x_2 W_2^T.
+// Work and memory are linear in n: a mode slot holds n x 64 and 4096 x 64
+// panels.
 #include "lrp_internal.h"
 
 namespace lrp {
@@ -34,84 +40,180 @@ __device__ __forceinline__ void other_modes(int d, int &p, int &q) {
   q = (d == 2) ? 1 : 2;
 }
 
-// Column tables of the mode unfoldings over the pairs (j, l), index j + n l:
-// Laplace mu = lambda_j + lambda_l; Stokes (p = 2 sin^2/h, q = 2 cos^2/h of
-// the half angles) the two factors of
-// D = 4 (s_i c_j c_l + c_i s_j c_l + c_i c_j s_l) / h^2 = p_i Qc + q_i Pc,
-// Pc = h/2 (p_j q_l + q_j p_l), Qc = h/2 q_j q_l.
-__global__ void k_mu(int n, const double *__restrict__ lam, const double *__restrict__ sp,
-                     const double *__restrict__ sq, double *mu, double *pc, double *qc) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long m = (long)n * n;
-  if (idx >= m) return;
-  const int j = (int)(idx % n), l = (int)(idx / n);
-  const double hh = 0.5 / (double)(n + 1);
-  mu[idx] = lam[j] + lam[l];
-  pc[idx] = hh * (sp[j] * sq[l] + sq[j] * sp[l]);
-  qc[idx] = hh * (sq[j] * sq[l]);
+// The outer decision of every solve whose three mode crosses have finished
+// (one thread per solve): record the mode ranks and pivot sets; restart the
+// crosses on the new fibers (P3_SETUP) unless the ranks repeat the previous
+// sweep's or the sweep cap is reached, then the core (P3_CORE).  A non-finite
+// input or a zero mode (zero solution) finishes at once.
+__global__ void k_fiber_outer(Solve3D *S) {
+  Solve3D &s = S[blockIdx.x];
+  if (threadIdx.x != 0 || s.phase != P3_CROSS) return;
+  for (int d = 0; d < 3; ++d)
+    if (s.inner[d]->active != ACT_DONE) return;
+  int st = LRP_OK;
+  bool zero = false;
+  for (int d = 0; d < 3; ++d) {
+    const int sd = s.inner[d]->status;
+    if (sd == LRP_ENONFINITE) st = LRP_ENONFINITE;
+    else if (sd != LRP_OK && st == LRP_OK) st = sd;
+    zero |= (s.inner[d]->nrm == 0.0);
+  }
+  if (st == LRP_ENONFINITE || zero) {
+    s.cross_status = st;
+    s.R[0] = s.R[1] = s.R[2] = 0;
+    s.status = (st == LRP_ENONFINITE) ? st : LRP_OK;
+    s.out_ok = 1;
+    s.nrm = 0.0;
+    s.phase = P3_DONE;
+    return;
+  }
+  s.outer += 1;
+  bool same = s.outer >= 2;
+  for (int d = 0; d < 3; ++d) {
+    const Solve2D &in = *s.inner[d];
+    same &= (in.k == s.kf[d]);
+    s.kf[d] = in.k;
+    for (int t = 0; t < in.k; ++t) s.If[d][t] = clamp_row(in.I[t], s.n);
+  }
+  if (st == LRP_OK && !same && s.outer < s.max_outer) {
+    s.phase = P3_SETUP;
+    return;
+  }
+  if (st == LRP_OK && !same) st = LRP_ENOCONV;
+  s.cross_status = st;
+  for (int d = 0; d < 3; ++d) s.k[d] = s.kf[d];
+  s.phase = P3_CORE;
 }
 
-// T_d[a + r_d (b + r_p l)] = sum_c G_d[a, b, c] Uh_q[l, c]   (blockIdx.z = 3 s + d)
-__global__ __launch_bounds__(NTHR) void k_w_half(Solve3D *S) {
+// Pivot set of mode e for the fibers of the sweep: the last outer sweep's,
+// or before the first, k evenly spaced indices (k = rank + kick, capped).
+__device__ int fiber_pivots(const Solve3D &s, int e, int *out, int *scratch) {
+  if (s.outer > 0) {
+    for (int t = 0; t < s.kf[e]; ++t) out[t] = s.If[e][t];
+    return s.kf[e];
+  }
+  const int k = min(min(s.r[e] + s.kick, s.kcap), s.n);
+  spread_indices(s.n, k, scratch, 0, out, 0);
+  return k;
+}
+
+// T_d[a + r_d (b + r_p l)] = sum_c G_d[a, b, c] Uh_q[I_q[l], c] (blockIdx.z =
+// 3 s + d; first block also restarts the mode slot).
+__global__ __launch_bounds__(NTHR) void k_fiber_T(Solve3D *S) {
   Solve3D &s = S[blockIdx.z / 3];
   const int d = blockIdx.z % 3;
-  Solve2D &in = *s.inner[d];
-  if (in.active != ACT_INIT) return;
+  if (s.phase != P3_SETUP) return;
   int p, q;
   other_modes(d, p, q);
-  const int n = s.n, rd = s.r[d], rp = s.r[p], rq = s.r[q];
+  __shared__ int Iq[KMAX], scr[KMAX];
+  __shared__ int kq_s;
+  if (threadIdx.x == 0) kq_s = fiber_pivots(s, q, Iq, scr);
+  __syncthreads();
+  const int kq = kq_s;
+  const int rd = s.r[d], rp = s.r[p], rq = s.r[q];
   const long idx = (long)blockIdx.x * NTHR + threadIdx.x;
-  if (idx >= (long)rd * rp * n) return;
+  if (idx >= (long)rd * rp * kq) return;
   const int a = (int)(idx % rd);
   const int b = (int)((idx / rd) % rp);
   const int l = (int)(idx / ((long)rd * rp));
   // G index with i_d = a, i_p = b, i_q = c
-  long st[3] = {1, s.r[0], (long)s.r[0] * s.r[1]};
-  const long base = a * st[d] + b * st[p];
-  const double *uq = s.inner[q]->Uh;
-  const long ldq = s.inner[q]->ldu;
+  const long stg[3] = {1, s.r[0], (long)s.r[0] * s.r[1]};
+  const long base = a * stg[d] + b * stg[p];
+  const Solve2D &mq = *s.inner[q];
+  const double *uq = mq.Uh + Iq[l];
   double acc = 0.0;
-  for (int c = 0; c < rq; ++c) acc += s.G[base + c * st[q]] * uq[l + c * ldq];
-  if (!isfinite(acc)) in.nonfinite = 1;
+  for (int c = 0; c < rq; ++c) acc += s.G[base + c * stg[q]] * uq[(long)c * mq.ldu];
+  if (!isfinite(acc)) s.inner[d]->nonfinite = 1;
   s.T[d][idx] = acc;
 }
 
-// W_d[j + n l, a] = sum_b Uh_p[j, b] T_d[a + r_d (b + r_p l)], written to the
-// mode slot's Vh (column side).  Block: 256 values of j for one l.
-__global__ __launch_bounds__(NTHR) void k_w_full(Solve3D *S) {
+// Column side of mode d's fiber matrix: W_d rows (the slot's Vh) and the
+// column tables, zero columns beyond k_p k_q; block (x, 3 s + d) covers
+// columns [256 x, 256 x + 256).  Block 0 resets the mode slot to start a
+// cross (as a new problem: initial column choice, k0 = rank + kick).
+__global__ __launch_bounds__(NTHR) void k_fiber_cols(Solve3D *S) {
   Solve3D &s = S[blockIdx.z / 3];
   const int d = blockIdx.z % 3;
+  if (s.phase != P3_SETUP) return;
   Solve2D &in = *s.inner[d];
-  if (in.active != ACT_INIT) return;
   int p, q;
   other_modes(d, p, q);
-  const int n = s.n, rd = s.r[d], rp = s.r[p];
-  const int l = blockIdx.y;
-  __shared__ double ts[KMAX * KMAX];   // [b][a]
-  const double *T = s.T[d] + (long)rd * rp * l;
-  for (int e = threadIdx.x; e < rd * rp; e += NTHR) ts[e] = T[e];
+  __shared__ int Ip[KMAX], Iq[KMAX], scr[KMAX];
+  __shared__ int kk[2];
+  if (threadIdx.x == 0) {
+    kk[0] = fiber_pivots(s, p, Ip, scr);
+    kk[1] = fiber_pivots(s, q, Iq, scr);
+  }
   __syncthreads();
-  const int j = blockIdx.x * NTHR + threadIdx.x;
-  if (j >= n) return;
-  const double *up = s.inner[p]->Uh;
-  const long ldp = s.inner[p]->ldu;
-  double *out = in.Vh + j + (long)n * l;
-  const long ldv = in.ldv;
-  for (int a0 = 0; a0 < rd; a0 += 16) {
-    double acc[16];
+  const int kp = kk[0], kq = kk[1], m = kp * kq;
+  const int rd = s.r[d], rp = s.r[p];
+  const int col = blockIdx.x * NTHR + threadIdx.x;
+  const bool prod = in.lq_r != nullptr;
+  if (col < FIB_M) {
+    const bool live = col < m;
+    const int j = live ? col % kp : 0, l = live ? col / kp : 0;
+    const int ip = Ip[j], iq = Iq[l];
+    // eigenvalue factors of the column (the mode slot's row tables are the
+    // grid's: lambda, or the Stokes factors p = 2 sin^2/h, q = 2 cos^2/h)
+    if (!prod) {
+      s.lamc[d][col] = live ? in.lam_r[ip] + in.lam_r[iq] : 1.0;
+    } else {
+      // 4 (s_i c_j c_l + c_i s_j c_l + c_i c_j s_l)/h^2 = p_i Qc + q_i Pc,
+      // Pc = h/2 (p_j q_l + q_j p_l), Qc = h/2 q_j q_l
+      const double hh = 0.5 / (double)(s.n + 1);
+      s.lamc[d][col] = live ? hh * (in.lam_r[ip] * in.lq_r[iq] + in.lq_r[ip] * in.lam_r[iq]) : 1.0;
+      s.lqc[d][col] = live ? hh * (in.lq_r[ip] * in.lq_r[iq]) : 0.0;
+    }
+    const Solve2D &mp = *s.inner[p];
+    const double *T = s.T[d] + (long)rd * rp * l;
+    double *out = in.Vh + col;
+    for (int a0 = 0; a0 < rd; a0 += 16) {
+      double acc[16];
 #pragma unroll
-    for (int t = 0; t < 16; ++t) acc[t] = 0.0;
-    for (int b = 0; b < rp; ++b) {
-      const double u = up[j + b * ldp];
-      const double *tb = ts + b * rd + a0;
+      for (int t = 0; t < 16; ++t) acc[t] = 0.0;
+      if (live) {
+        for (int b = 0; b < rp; ++b) {
+          const double u = mp.Uh[ip + (long)b * mp.ldu];
+#pragma unroll
+          for (int t = 0; t < 16; ++t)
+            if (a0 + t < rd) acc[t] += u * T[a0 + t + (long)rd * b];
+        }
+      }
 #pragma unroll
       for (int t = 0; t < 16; ++t)
-        if (a0 + t < rd) acc[t] += u * tb[t];
+        if (a0 + t < rd) out[(long)(a0 + t) * in.ldv] = acc[t];
     }
-#pragma unroll
-    for (int t = 0; t < 16; ++t)
-      if (a0 + t < rd) out[(long)(a0 + t) * ldv] = acc[t];
   }
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  // restart the mode cross on the new fiber matrix
+  in.lam_c = s.lamc[d];
+  in.lq_c = prod ? s.lqc[d] : nullptr;
+  in.kcap = min(min(s.kcap, s.n), m);
+  const int k0 = min(s.r[d] + s.kick, in.kcap);
+  in.k0 = k0;
+  in.k = min(s.r[d], k0);
+  in.kp = 0;
+  in.R = 0;
+  in.sweep = 0;
+  in.next = NEXT_CONTINUE;
+  in.status = LRP_OK;
+  in.mv_done = 0;
+  in.mv_swaps = 0;
+  in.kgrow = 0;
+  in.nrm = 0.0;
+  in.change = -1.0;
+  in.tail = -1.0;
+  double *t;
+  if (in.Ap < in.A) t = in.A, in.A = in.Ap, in.Ap = t;
+  if (in.Bp < in.B) t = in.B, in.B = in.Bp, in.Bp = t;
+  if (in.sigp < in.sig) t = in.sig, in.sig = in.sigp, in.sigp = t;
+  in.active = (s.r[d] > 0) ? ACT_INIT : ACT_DONE;
+}
+
+// Solves whose fibers were just built start their mode crosses.
+__global__ void k_fiber_go(Solve3D *S) {
+  Solve3D &s = S[blockIdx.x];
+  if (threadIdx.x == 0 && s.phase == P3_SETUP) s.phase = P3_CROSS;
 }
 
 // ---- mode products of the core: out = in x_ax M, M(a, t) given per stage.
@@ -194,35 +296,6 @@ __global__ __launch_bounds__(NTHR) void k_core_stage(int st, Solve3D *S) {
   }
 }
 
-// The three mode crosses finished: combine their status, record the cross
-// ranks and start the core (or finish at once: a non-finite input, or a
-// zero mode, whose solution is zero).
-__global__ void k_core_begin(Solve3D *S) {
-  Solve3D &s = S[blockIdx.x];
-  if (threadIdx.x != 0 || s.phase != P3_CROSS) return;
-  for (int d = 0; d < 3; ++d)
-    if (s.inner[d]->active != ACT_DONE) return;
-  int st = LRP_OK;
-  bool zero = false;
-  for (int d = 0; d < 3; ++d) {
-    const int sd = s.inner[d]->status;
-    if (sd == LRP_ENONFINITE) st = LRP_ENONFINITE;
-    else if (sd != LRP_OK && st == LRP_OK) st = sd;
-    zero |= (s.inner[d]->nrm == 0.0);
-    s.k[d] = s.inner[d]->k;
-  }
-  s.cross_status = st;
-  if (st == LRP_ENONFINITE || zero) {
-    s.R[0] = s.R[1] = s.R[2] = 0;
-    s.status = (st == LRP_ENONFINITE) ? st : LRP_OK;
-    s.out_ok = 1;
-    s.nrm = 0.0;
-    s.phase = P3_DONE;
-    return;
-  }
-  s.phase = P3_CORE;
-}
-
 // Mode-d unfolding of the core, transposed, into the mode slot's C panel
 // (rows = pairs of the other modes, p fastest; zero rows up to P), and the
 // slot set to factor it (ACT_CORE).
@@ -303,25 +376,21 @@ __global__ void k_tucker_done(Solve3D *S) {
 
 }  // namespace
 
-hipError_t launch_mu(int n, const double *lam, const double *sp, const double *sq,
-                     double *mu, double *pc, double *qc, hipStream_t st) {
-  const long m = (long)n * n;
-  hipLaunchKernelGGL(k_mu, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, n, lam, sp, sq,
-                     mu, pc, qc);
+hipError_t launch_fiber_outer(Solve3D *s, int nsolves, hipStream_t st) {
+  hipLaunchKernelGGL(k_fiber_outer, dim3(nsolves), dim3(64), 0, st, s);
   return hipGetLastError();
 }
 
-hipError_t launch_unfold_factors(Solve3D *s, int nsolves, int n, int rmax,
-                                 hipStream_t st) {
-  const long half = (long)rmax * rmax * n;
-  hipLaunchKernelGGL(k_w_half, dim3((unsigned)((half + NTHR - 1) / NTHR), 1, 3 * nsolves),
+hipError_t launch_fiber_setup(Solve3D *s, int nsolves, int rmax, hipStream_t st) {
+  const long half = (long)rmax * rmax * KMAX;
+  hipLaunchKernelGGL(k_fiber_T, dim3((unsigned)((half + NTHR - 1) / NTHR), 1, 3 * nsolves),
                      dim3(NTHR), 0, st, s);
-  hipLaunchKernelGGL(k_w_full, dim3(ceil_div(n, NTHR), n, 3 * nsolves), dim3(NTHR), 0, st, s);
+  hipLaunchKernelGGL(k_fiber_cols, dim3(FIB_M / NTHR, 1, 3 * nsolves), dim3(NTHR), 0, st, s);
+  hipLaunchKernelGGL(k_fiber_go, dim3(nsolves), dim3(64), 0, st, s);
   return hipGetLastError();
 }
 
 hipError_t launch_core_build(Solve3D *s, int nsolves, hipStream_t st) {
-  hipLaunchKernelGGL(k_core_begin, dim3(nsolves), dim3(64), 0, st, s);
   for (int stg = 0; stg < 6; ++stg)
     hipLaunchKernelGGL(k_core_stage, dim3(CORE_MAX / NTHR / 4, nsolves), dim3(NTHR), 0, st,
                        stg, s);

@@ -152,6 +152,75 @@ def test_solve3d_rank_capacity():
     assert max(info["ranks"]) > 2
 
 
+def sine_modes(n, ps):
+    i = np.arange(1, n + 1, dtype=np.float64)
+    return np.stack([np.sin(p * np.pi * i / (n + 1)) for p in ps], axis=1)
+
+
+def tucker_diff_rel(G1, Us1, G2, Us2):
+    """||[[G1; Us1]] - [[G2; Us2]]||_F / ||[[G2; Us2]]||_F without forming
+    either tensor: QR of the stacked factors per mode, then the norm of the
+    block-diagonal core difference transformed by the R factors."""
+    shapes1, shapes2 = G1.shape, G2.shape
+    big = np.zeros(tuple(shapes1[d] + shapes2[d] for d in range(3)))
+    big[:shapes1[0], :shapes1[1], :shapes1[2]] = G1
+    big[shapes1[0]:, shapes1[1]:, shapes1[2]:] = -G2
+    ref = G2.copy()
+    for d in range(3):
+        _, R = np.linalg.qr(np.hstack([Us1[d], Us2[d]]))
+        big = np.moveaxis(np.tensordot(R, np.moveaxis(big, d, 0), axes=(1, 0)), 0, d)
+        _, R2 = np.linalg.qr(Us2[d])
+        ref = np.moveaxis(np.tensordot(R2, np.moveaxis(ref, d, 0), axes=(1, 0)), 0, d)
+    return float(np.linalg.norm(big) / np.linalg.norm(ref))
+
+
+@pytest.mark.parametrize("n,eps", [(2048, 1e-8), (6000, 1e-7)])
+def test_solve3d_large_grid_semi_analytic(n, eps):
+    """Beyond the grids a full 3D oracle solve can check: a right-hand side
+    F = sum_m s_(p_m) x s_(q_m) x w_m (sine modes in the first two modes, any
+    w_m) has the solution sum_m s_(p_m) x s_(q_m) x z_m with
+    (T + (lambda_p_m + lambda_q_m) I) z_m = w_m, a tridiagonal solve; the
+    GPU's Tucker result is compared with it in factored form."""
+    import scipy.linalg
+    log("solve3d large grid", n, eps)
+    rng = np.random.default_rng(n)
+    ps, qs = [3, 40], [7, 11]
+    U1, U2 = sine_modes(n, ps), sine_modes(n, qs)
+    x = np.arange(1, n + 1) / (n + 1)
+    W = np.stack([np.exp(-(x - 0.3) ** 2 / 0.01), np.exp(-(x - 0.7) ** 2 / 0.05) * x], 1)
+    G = np.zeros((2, 2, 2))
+    G[0, 0, 0], G[1, 1, 1] = 1.0, -0.5
+    lam = poisson.eigenvalues(n)
+    h2 = (n + 1.0) ** 2
+    Z = np.empty_like(W)
+    for m in range(2):
+        shift = lam[ps[m] - 1] + lam[qs[m] - 1]
+        ab = np.zeros((3, n))
+        ab[0, 1:] = -h2
+        ab[1, :] = 2 * h2 + shift
+        ab[2, :-1] = -h2
+        Z[:, m] = scipy.linalg.solve_banded((1, 1), ab, W[:, m])
+    Xs, Gx, info = run3d(U1, U2, W, G, eps)
+    log("  ranks", info["ranks"], "sweeps", info["sweeps"])
+    assert info["status_code"] == binding.LRP_OK
+    e = tucker_diff_rel(np.asarray(host(Gx)), [host(x) for x in Xs], G, [U1, U2, Z])
+    log("  err", e)
+    assert e <= 10 * eps, e
+
+
+def test_solve3d_workspace_linear_in_n():
+    """The 3D workspace no longer holds n x n^2 unfoldings: a 2048-point
+    solve runs inside a 2 GiB context budget."""
+    log("solve3d budget")
+    c = binding.Context(0, workspace_bytes=2 << 30)
+    try:
+        U1, U2, U3, G = inputs.rhs3d_tucker(2048, (6, 6, 6), 51)
+        Xs, Gx, info = c.solve3d(dev(U1), dev(U2), dev(U3), binding.fortran_core(G), 1e-6)
+        assert info["status_code"] == binding.LRP_OK
+    finally:
+        c.close()
+
+
 def test_solve3d_invalid_arguments():
     log("solve3d einval")
     n = binding.MAX_N3 + 1
