@@ -18,8 +18,11 @@ Contents
 ``tucker``   the 3D Tucker variant (the paper only promises it; the reading
              is stated there).
 ``metrics``  blockwise relative Frobenius error of a factored result.
+``expsum``   the exponential-sum comparator of Section 4.1 (sinc quadrature
+             of 1/x, Hadamard product with the transformed right-hand side,
+             rounding).
 
 Every function is pinned by ``tests/test_oracle_*.py`` against closed forms,
 library routines or brute force; see each function's docstring for its pin.
 """
-from . import poisson, lowrank, metrics, tucker  # noqa: F401
+from . import poisson, lowrank, metrics, tucker, expsum  # noqa: F401
