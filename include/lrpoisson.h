@@ -255,6 +255,32 @@ lrp_status lrpoisson_solve3d(lrp_ctx *ctx, int64_t n, const int32_t rank[3],
                              int64_t ldx, double *Gx, const int32_t rmax[3],
                              int32_t rank_out[3], lrp_info *info, void *stream);
 
+/* The exponential-sum comparator of Section 4.1 (timed against the cross in
+ * Section 6.1): the same 2D problems as lrpoisson_solve2d_batch, solved
+ * without the cross.  1/x is approximated on [2 lambda_1, 2 lambda_n] by the
+ * sinc (trapezoidal) rule for 1/x = int exp(t - x e^t) dt,
+ * 1/x ~ sum_k w_k exp(-p_k x), relative error <= eps (tails cut at eps/3
+ * each, the largest step h on the grid 1.5, ..., 0.05 of 300 steps whose
+ * rule meets eps at 4000 log-spaced points); the divided spectrum is then
+ * the Hadamard product of Fh = Uh Vh^T with the rank-R sum
+ * sum_k w_k exp(-p_k lambda_i) exp(-p_k lambda_j), a product of rank R*rank,
+ * and it is rounded to eps (Section 3) incrementally: columns are appended
+ * to the running factorisation up to 64 at a time and each step is rounded
+ * by QR of both factors and an SVD of the small core, dropping at most
+ * (eps/2) c/(R rank) of the core's norm for c appended columns, eps/2 at the
+ * last step.  Only the Laplace operator (lrp_opts.op = LRP_OP_LAPLACE): the
+ * Stokes eigenvalue is not a sum.  lrp_opts.prec selects the transforms;
+ * the cross's options are ignored.  LRP_EINVAL also for n < 128 and for an
+ * eps that needs more than 256 terms.  info: sweeps = rounding steps, k =
+ * the number of terms R, rank = output rank, change = -1, err_est = eps
+ * (quadrature) plus the dropped tails over the final core norm.
+ * LRP_ERANKCAP when a step had to drop more than its share to keep room for
+ * 8 new columns (the approximation is still written), or the output rank
+ * exceeds rmax. */
+lrp_status lrp_expsum_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t count,
+                                    lrp_problem2d *probs, const lrp_opts *opts,
+                                    void *stream);
+
 /* The orthonormal sine transform on its own (paper Section 4.1, eq. "diag":
  * S[j,k] = sqrt(2/(n+1)) sin(pi j k/(n+1)), the DST-I that diagonalises the
  * 1D operator; S = S^T = S^-1, so the same call transforms forward and

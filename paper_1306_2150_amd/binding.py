@@ -41,7 +41,7 @@ PHASES = ("forward", "cross", "inverse")
 EXPORTS = ["lrp_create", "lrp_destroy", "lrp_strerror", "lrpoisson_solve2d",
            "lrpoisson_solve2d_batch", "lrpoisson_solve3d", "lrp_submit",
            "lrp_serve_step", "lrp_poll", "lrp_wait", "lrp_sine_transform",
-           "lrp_sine_transform_noalloc",
+           "lrp_sine_transform_noalloc", "lrp_expsum_solve2d_batch",
            "lrp_set_kernel_timing", "lrp_kernel_stats"]
 
 
@@ -121,6 +121,8 @@ def load(path: str = LIB_PATH):
                                       ctypes.POINTER(I32), ctypes.POINTER(LrpInfo), P]
     lib.lrpoisson_solve2d_batch.argtypes = [P, I64, I32, ctypes.POINTER(LrpProblem2D),
                                             ctypes.POINTER(LrpOpts), P]
+    lib.lrp_expsum_solve2d_batch.argtypes = [P, I64, I32, ctypes.POINTER(LrpProblem2D),
+                                             ctypes.POINTER(LrpOpts), P]
     lib.lrpoisson_solve3d.argtypes = [P, I64, ctypes.POINTER(I32), P, P, P, I64, P,
                                       F64, ctypes.POINTER(LrpOpts), P, P, P, I64, P,
                                       ctypes.POINTER(I32), ctypes.POINTER(I32),
@@ -202,14 +204,18 @@ def _stream(stream):
 
 
 class Batch2D:
-    """Arguments of one lrpoisson_solve2d_batch call, kept for repeated runs:
+    """Arguments of one lrpoisson_solve2d_batch call (method "cross") or
+    lrp_expsum_solve2d_batch call (method "expsum"), kept for repeated runs:
     problems (U, V, eps) on one grid size, one (Ux, Vx) output pair of rmax
     columns per problem (the views of the last run's results stay valid until
     the next run overwrites them)."""
 
-    def __init__(self, ctx, problems, prec, rmax, kw):
+    ENTRY = {"cross": "lrpoisson_solve2d_batch", "expsum": "lrp_expsum_solve2d_batch"}
+
+    def __init__(self, ctx, problems, prec, rmax, kw, method="cross"):
         import torch
         self.ctx = ctx
+        self.entry = self.ENTRY[method]
         self.n = n = problems[0][0].shape[0] if problems else 0
         self.rmax = rmax = MAX_RANK if rmax is None else rmax
         nb = len(problems)
@@ -237,10 +243,10 @@ class Batch2D:
         nb = len(self.arr)
         if nb == 0:
             return []
-        st = self.ctx.lib.lrpoisson_solve2d_batch(self.ctx.h, self.n, nb, self.arr,
-                                                  ctypes.byref(self.opts), _stream(stream))
+        st = getattr(self.ctx.lib, self.entry)(self.ctx.h, self.n, nb, self.arr,
+                                               ctypes.byref(self.opts), _stream(stream))
         if st in (LRP_EINVAL, LRP_EDEVICE, LRP_ENOMEM):
-            raise LrpError(st, "lrpoisson_solve2d_batch")
+            raise LrpError(st, self.entry)
         if not results:
             return None
         res = []
@@ -301,11 +307,25 @@ class Context:
             return []
         return self.batch2d(problems, prec=prec, rmax=rmax, **kw).run(stream)
 
-    def batch2d(self, problems, prec="fp64", rmax=None, **kw):
+    def batch2d(self, problems, prec="fp64", rmax=None, method="cross", **kw):
         """A prepared batch: the argument array and the output factors are
         built once and reused by every ``run()`` (each run solves every
-        problem of the batch from its inputs)."""
-        return Batch2D(self, problems, prec, rmax, kw)
+        problem of the batch from its inputs).  method "expsum" runs the
+        exponential-sum comparator instead of the cross."""
+        return Batch2D(self, problems, prec, rmax, kw, method)
+
+    def expsum_solve2d_batch(self, problems, prec="fp64", stream=None, rmax=None, **kw):
+        """The exponential-sum comparator on problems (U, V, eps) of one grid
+        size: a list of (Ux, Vx, info), info["k"] = the number of terms,
+        info["sweeps"] = the rounding steps."""
+        if not problems:
+            return []
+        return self.batch2d(problems, prec=prec, rmax=rmax, method="expsum", **kw).run(stream)
+
+    def expsum_solve2d(self, U, V, eps, rmax=None, prec="fp64", stream=None, **kw):
+        """One comparator solve; returns (Ux, Vx, info)."""
+        return self.expsum_solve2d_batch([(U, V, eps)], prec=prec, stream=stream,
+                                         rmax=rmax, **kw)[0]
 
     # ---- 3D
     def solve3d(self, U1, U2, U3, G, eps, rmax=None, prec="fp64", stream=None,

@@ -19,7 +19,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblrpoisson.so")
 
 SOURCES = ["dst.hip", "dst_i8.hip", "dst_fft.hip", "tsqr.hip", "maxvol.hip", "svd.hip", "cross.hip", "tucker.hip",
-           "noalloc.hip", "host.cpp", "host3d.cpp", "serve.cpp"]
+           "noalloc.hip", "expsum.hip", "host.cpp", "host3d.cpp", "serve.cpp",
+           "host_expsum.cpp"]
 
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -737,6 +737,7 @@ lrp_status lrp_destroy(lrp_ctx *ctx) {
   if (ctx->tx_work) dev_free(ctx, ctx->tx_work, ctx->tx_work_bytes);
   ctx->batch_groups.clear();
   ctx->batch3_groups.clear();
+  ctx->expsum_groups.clear();
   ctx->serve_groups.clear();
   ctx->serve3_groups.clear();
   for (auto &kv : ctx->tables) dev_free(ctx, kv.second.tab, kv.second.bytes);

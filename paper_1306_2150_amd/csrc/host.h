@@ -157,6 +157,23 @@ class Group3D {
   std::vector<IO> io_;
 };
 
+// Slots of the exponential-sum comparator for one grid size n: the Solve2D
+// job records of both sides (a Group2D of 2 cap slots, see ExpState), the
+// device states and the quadrature nodes of every slot.
+struct ExpGroup {
+  ExpGroup(lrp_ctx *ctx, int n, int cap);
+  ~ExpGroup();
+  lrp_status init();
+  lrp_ctx *ctx;
+  int n, cap;
+  std::unique_ptr<Group2D> jobs;
+  ExpState *d_e = nullptr, *h_e = nullptr;
+  double *d_nodes = nullptr, *h_nodes = nullptr;   // per slot: sqrt(w), p
+  size_t bytes = 0;
+  // nodes of each (eps) met so far: sqrt(w_k), then p_k
+  std::map<double, std::vector<double>> node_cache;
+};
+
 }  // namespace lrp
 
 // Requests of the serving loop.
@@ -181,6 +198,7 @@ struct lrp_ctx {
   // cached groups for synchronous calls, keyed by n
   std::map<int, std::unique_ptr<lrp::Group2D>> batch_groups;
   std::map<int, std::unique_ptr<lrp::Group3D>> batch3_groups;
+  std::map<int, std::unique_ptr<lrp::ExpGroup>> expsum_groups;
   // serving
   hipStream_t serve_stream = nullptr;
   std::map<int, std::unique_ptr<lrp::Group2D>> serve_groups;

@@ -399,4 +399,48 @@ hipError_t launch_tucker_out(Solve3D *s, int nsolves, int n, hipStream_t st);
 
 Tree make_tree(int n, int kmax);
 
+// ---- exponential-sum comparator (expsum.hip, host_expsum.cpp)
+// The approach Section 4.1 sets against the cross: 1/x ~ sum_k w_k e^{-p_k x}
+// on the range of the eigenvalue sums makes the divided spectrum the
+// Hadamard product of Fh = Uh Vh^T with a rank-R matrix, i.e. the rank R r
+// product  sum_k (sqrt(w_k) e^{-p_k Lambda} Uh)(sqrt(w_k) e^{-p_k Lambda} Vh)^T,
+// rounded to eps (Section 3).  The rounding runs incrementally: each step
+// appends c of the R r columns to the current rank-K factorisation
+// Qa diag(sig) Qb^T and rounds the rank-(K + c) product by the cross's TSQR
+// (both sides) and core SVD, truncating to a share of the tolerance.
+constexpr int ES_MAX_TERMS = 256;   // exponential-sum terms
+constexpr int ES_CMIN = 8;          // columns every step can append at least
+constexpr int ES_MIN_N = 2 * KMAX;  // smallest grid (K + c <= KMAX rows fit)
+enum : int { ES_DONE = 0, ES_RUN = 1, ES_LAST = 2 };
+struct ExpState {
+  int n, r, R, tot;         // grid, input rank, terms, tot = R r columns
+  double eps;               // requested accuracy (half for the step tails)
+  const double *lam;        // lambda_k, k = 1..n
+  const double *sw, *p;     // sqrt(w_k), p_k, k < R
+  // ---- control
+  int phase;                // ES_*
+  int K;                    // rank of the current factorisation
+  int j0;                   // product columns absorbed so far
+  int steps;                // rounding steps run
+  int status;               // lrp_status
+  int capped;               // a step truncated beyond its share (rank room)
+  double drop;              // sum of the dropped tails (absolute)
+  double nrm;               // ||sig|| of the last core
+  double sig[KMAX];         // singular values of the current factorisation
+};
+// Columns the next step appends: fill the KMAX-column panel.
+__host__ __device__ inline int es_cols(int K, int j0, int tot) {
+  const int room = KMAX - K, left = tot - j0;
+  return room < left ? room : left;
+}
+// Each launcher covers `cap` solves.  jobs[i] (a side) and jobs[cap + i]
+// (b side) are the Solve2D records whose TSQR and core SVD round step i's
+// panels: Uh = the side's transformed factor, Q0 = the side's basis, Vh =
+// the panel, Q1 = the panel's orthonormal factor, A = the output staging;
+// jobs[i].Rfin points at jobs[cap + i].InvC, so that the core the b side's
+// SVD takes is R_a R_b^T.
+hipError_t launch_es_panel(ExpState *e, Solve2D *jobs, int cap, int n, hipStream_t st);
+hipError_t launch_es_trunc(ExpState *e, Solve2D *jobs, int cap, hipStream_t st);
+hipError_t launch_es_update(ExpState *e, Solve2D *jobs, int cap, int n, hipStream_t st);
+
 }  // namespace lrp

@@ -341,9 +341,11 @@ lrp_status lrp_serve_step(lrp_ctx *ctx, int32_t *pending) {
     const bool have = dim == 3 ? ctx->serve3_groups.count(n) > 0 : ctx->serve_groups.count(n) > 0;
     if (have || failed.count({dim, n})) continue;
     if (make(dim, n)) continue;
-    if (e == LRP_ENOMEM && (!ctx->batch_groups.empty() || !ctx->batch3_groups.empty())) {
+    if (e == LRP_ENOMEM && (!ctx->batch_groups.empty() || !ctx->batch3_groups.empty() ||
+                            !ctx->expsum_groups.empty())) {
       ctx->batch_groups.clear();
       ctx->batch3_groups.clear();
+      ctx->expsum_groups.clear();
       if (make(dim, n)) continue;
     }
     failed[{dim, n}] = e;

@@ -102,6 +102,26 @@ __global__ __launch_bounds__(core_threads<KM>()) void k_core(int phase, Solve2D 
   for (int c = threadIdx.x >> 6; c < kp; c += NW)
     for (int i = threadIdx.x & 63; i < kp; i += 64) V[c * LD + i] = (i == c) ? 1.0 : 0.0;
   __syncthreads();
+  // ||K||_F^2, which the rotations keep: a pair of columns whose norms are
+  // both at the rounding level of ||K||_F (geometric mean below u ||K||_F,
+  // u = 2^-52) holds no information, and rotating it only stirs rounding
+  // noise that the relative test below would chase for dozens of sweeps
+  __shared__ double fro_w[NW];
+  {
+    double v = 0.0;
+    for (int e = threadIdx.x; e < kp * KM; e += NT) {
+      const int c = e / KM, i = e - c * KM;
+      const double x = (i < kp) ? K[c * LD + i] : 0.0;
+      v += x * x;
+    }
+    v = wave_sum(v);
+    if (lane == 0) fro_w[wv] = v;
+  }
+  __syncthreads();
+  double fro2 = 0.0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) fro2 += fro_w[w];
+  const double floor2 = 0x1p-104 * fro2;   // (u ||K||_F)^2
   const int npairs = kp / 2;
   // 16 threads (one DPP row) per column pair, NT / 16 pairs in flight
   constexpr int NP = NT / 16;
@@ -136,7 +156,8 @@ __global__ __launch_bounds__(core_threads<KM>()) void k_core(int phase, Solve2D 
           }
         row_sum16_n(sums);
         const double al = sums[0], be = sums[1], ga = sums[2];
-        if (live && al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+        if (live && al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al * be) &&
+            sqrt(al * be) > floor2) {
           const double zeta = (be - al) / (2.0 * ga);
           const double t = (zeta >= 0.0 ? 1.0 : -1.0) /
                            (fabs(zeta) + sqrt(1.0 + zeta * zeta));

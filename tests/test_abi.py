@@ -57,6 +57,8 @@ def test_null_context_rejected(lib):
     res = ctypes.c_int32(0)
     assert lib.lrp_wait(None, 1, ctypes.byref(res), None, None) == binding.LRP_EINVAL
     assert lib.lrp_poll(None, 1, ctypes.byref(res), None, None) == binding.LRP_EINVAL
+    probs = (binding.LrpProblem2D * 1)()
+    assert lib.lrp_expsum_solve2d_batch(None, 1024, 1, probs, None, None) == binding.LRP_EINVAL
 
 
 def test_struct_layouts_match_header(tmp_path):
