@@ -90,6 +90,12 @@ def parse():
     ap.add_argument("--serve-warmup", type=int, default=50)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-expsum", action="store_true",
+                    help="skip the exponential-sum comparator timing")
+    ap.add_argument("--expsum-batches", type=str, default="1,256",
+                    help="batch sizes of the exponential-sum comparison")
+    ap.add_argument("--only-expsum", action="store_true",
+                    help="run only the exponential-sum comparator timing (one JSON line)")
     ap.add_argument("--cpu-sample", type=int, default=5)
     ap.add_argument("--serve-check", type=int, default=1,
                     help="served requests per (dim, n) shape checked against the oracle")
@@ -142,6 +148,53 @@ def cpu_baseline(hostrhs, eps, runs):
                                          f"(eps={eps}, numpy/LAPACK threads)"}}
 
 
+def expsum_vs_cross(ctx, workers, batches=(1, 256)):
+    """Section 6.1's comparison on its case: n = 1024, eps = 1e-7, a rank-30
+    right-hand side; the exponential-sum route (quadrature, Hadamard product
+    of rank R r, rounding) against the cross, on one problem (latency, median
+    of 5) and on a batch of 256 (throughput), both checked against the
+    float64 full-grid oracle."""
+    import numpy as np
+    import torch
+
+    from oracle import metrics, poisson
+    from paper_1306_2150_amd import binding, inputs
+    n, r, eps = 1024, 30, 1e-7
+    host = [inputs.rhs2d_bumps(n, r, 6001 + i) for i in range(8)]
+    dev = [(binding.colmajor(U), binding.colmajor(V)) for U, V in host]
+    rec = {"workload": "2D Poisson n=1024 r=30 eps=1e-7 Gaussian-bump RHS", "n": n, "r": r,
+           "eps": eps}
+    X = poisson.full_solve2d_factors(*host[0], workers=workers)
+    for nb in batches:
+        reps = 5 if nb <= 16 else 2
+        probs = [(dev[i % 8][0], dev[i % 8][1], eps) for i in range(nb)]
+        for method in ("cross", "expsum"):
+            b = ctx.batch2d(probs, prec="fp64", method=method)
+            res = b.run()
+            times = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = b.run()
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            dt = float(np.median(times))
+            info = res[0][2]
+            key = f"{method}_batch{nb}"
+            rec[key] = {"ms": dt * 1e3, "solves_per_s": nb / dt, "rank": info["rank"],
+                        "status": info["status"]}
+            if method == "expsum":
+                rec[key]["terms"] = info["k"]
+                rec[key]["steps"] = info["sweeps"]
+            if nb == 1:
+                Ux, Vx = res[0][0].cpu().numpy(), res[0][1].cpu().numpy()
+                rec[key]["rel_err"] = metrics.rel_err_factored(Ux, Vx, X)
+        rec[f"ratio_batch{nb}"] = rec[f"expsum_batch{nb}"]["ms"] / rec[f"cross_batch{nb}"]["ms"]
+        print(f"[bench] Section 6.1 case, batch {nb}: expsum {rec[f'expsum_batch{nb}']['ms']:.2f} ms, "
+              f"cross {rec[f'cross_batch{nb}']['ms']:.2f} ms", file=sys.stderr, flush=True)
+    return rec
+
+
 def timed_steps(ctx, problems, prec, steps, warmup):
     import torch
     # the argument array and output buffers are prepared once; every step
@@ -185,6 +238,12 @@ def main():
         torch.cuda.synchronize()
         del a, b
     ctx = binding.Context(0, workspace_bytes=64 << 30)
+    if args.only_expsum:
+        batches = [int(x) for x in args.expsum_batches.split(",") if x]
+        print(json.dumps({"expsum_vs_cross": expsum_vs_cross(ctx, min(16, os.cpu_count() or 1),
+                                                             batches)}), flush=True)
+        ctx.close()
+        return
     n, r, eps = 4096, 16, 1e-8
     B = args.batch
     # distinct RHS instances (seed 2000 + i), repeated to fill the batch
@@ -367,6 +426,10 @@ def main():
                                                                 "by_dim", "status_counts",
                                                                 "checked")},
                            "requests": args.serve_requests, "warmup": args.serve_warmup}
+
+    if not args.no_expsum:
+        batches = [int(x) for x in args.expsum_batches.split(",") if x]
+        line["expsum_vs_cross"] = expsum_vs_cross(ctx, min(16, os.cpu_count() or 1), batches)
 
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(hostrhs, eps, args.cpu_sample)

@@ -86,3 +86,65 @@ def test_expsum_solve2d_mutant_unweighted_is_caught(monkeypatch):
     Ux, Vx, _ = expsum.expsum_solve2d(U, V, 1e-7)
     X = poisson.full_solve2d_factors(U, V)
     assert metrics.rel_err_factored(Ux, Vx, X) > 1e-3
+
+
+def test_expsum_nodes_are_a_trapezoidal_rule_of_the_integral():
+    """The nodes discretise 1/x = int exp(t - x e^t) dt (which scipy's
+    adaptive quadrature confirms at a few x): t_k = log p_k equally spaced by
+    h, w_k = h p_k, and the tails cut where the bounds put them."""
+    from scipy import integrate
+    for x in (0.3, 7.0, 1234.5):
+        val, _ = integrate.quad(lambda t: np.exp(t - x * np.exp(t)), -60.0, 10.0, limit=400,
+                                epsabs=0.0, epsrel=1e-13)
+        assert abs(val * x - 1.0) < 1e-10
+    a, b, eps = 19.7, 8.39e6, 1e-7
+    w, p = expsum.expsum_1x(a, b, eps)
+    t = np.log(p)
+    h = np.diff(t)
+    assert np.allclose(h, h[0], rtol=1e-12, atol=0.0)
+    assert np.allclose(w, h[0] * p, rtol=1e-13, atol=0.0)
+    assert abs(t[0] - np.log(eps / (3 * b))) < 1e-12
+    assert t[-1] >= np.log(np.log(3 / eps) / a) - 1e-12
+
+
+def test_expsum_kronecker_form_entry_by_entry():
+    """sum_k w_k exp(-p_k lambda_i) exp(-p_k lambda_j) against
+    1/(lambda_i + lambda_j) on every (i, j) of a 64-point grid."""
+    n, eps = 64, 1e-9
+    lam = poisson.eigenvalues(n)
+    w, p = expsum.expsum_1x(*expsum.operator_range(n), eps)
+    E = np.exp(-np.outer(lam, p))
+    L = (E * w) @ E.T
+    exact = 1.0 / (lam[:, None] + lam[None, :])
+    assert np.max(np.abs(L / exact - 1.0)) <= eps * 1.05
+
+
+@pytest.mark.parametrize("cut", ["left", "right"])
+def test_expsum_mutant_tail_cut_early_is_caught(cut):
+    """Cutting either tail of the integral short (two nodes fewer at that
+    end) breaks the bar the rule is held to (eps, 5 % slack) somewhere in
+    the range."""
+    a, b, eps = 1.0, 1e6, 1e-8
+    w, p = expsum.expsum_1x(a, b, eps)
+    sl = slice(2, None) if cut == "left" else slice(None, -2)
+    assert dense_check(w[sl], p[sl], a, b) > 1.05 * eps
+
+
+@pytest.mark.parametrize("mutant", ["weights_both_sides", "reversed_spectrum"])
+def test_expsum_solve2d_planted_mistakes_are_caught(mutant, monkeypatch):
+    """A weight applied on both factors (w^2 instead of w), or the
+    exponentials taken of the reversed spectrum (an index mistake), must fail
+    the full-solve bar."""
+    real = expsum.expsum_1x
+    if mutant == "weights_both_sides":
+        monkeypatch.setattr(expsum, "expsum_1x",
+                            lambda a, b, eps: (real(a, b, eps)[0] ** 2, real(a, b, eps)[1]))
+    else:
+        real_eig, rng = expsum.eigenvalues, expsum.operator_range(256)
+        monkeypatch.setattr(expsum, "operator_range", lambda n: rng)
+        monkeypatch.setattr(expsum, "eigenvalues", lambda n: real_eig(n)[::-1].copy())
+    U, V = inputs.workload_rhs(2, 1, n=256)
+    Ux, Vx, _ = expsum.expsum_solve2d(U, V, 1e-7)
+    monkeypatch.undo()
+    X = poisson.full_solve2d_factors(U, V)
+    assert metrics.rel_err_factored(Ux, Vx, X) > 1e-3
