@@ -42,6 +42,7 @@ EXPORTS = ["lrp_create", "lrp_destroy", "lrp_strerror", "lrpoisson_solve2d",
            "lrpoisson_solve2d_batch", "lrpoisson_solve3d", "lrp_submit",
            "lrp_serve_step", "lrp_poll", "lrp_wait", "lrp_sine_transform",
            "lrp_sine_transform_noalloc", "lrp_expsum_solve2d_batch",
+           "lrp_kernel_qr_maxvol", "lrp_kernel_core_svd",
            "lrp_set_kernel_timing", "lrp_kernel_stats"]
 
 
@@ -123,6 +124,9 @@ def load(path: str = LIB_PATH):
                                             ctypes.POINTER(LrpOpts), P]
     lib.lrp_expsum_solve2d_batch.argtypes = [P, I64, I32, ctypes.POINTER(LrpProblem2D),
                                              ctypes.POINTER(LrpOpts), P]
+    lib.lrp_kernel_qr_maxvol.argtypes = [P, I64, I32, P, I64, F64, P, I64, P, I64,
+                                         ctypes.POINTER(I32), ctypes.POINTER(I32), P]
+    lib.lrp_kernel_core_svd.argtypes = [P, I32, P, I64, P, P, P, P]
     lib.lrpoisson_solve3d.argtypes = [P, I64, ctypes.POINTER(I32), P, P, P, I64, P,
                                       F64, ctypes.POINTER(LrpOpts), P, P, P, I64, P,
                                       ctypes.POINTER(I32), ctypes.POINTER(I32),
@@ -321,6 +325,37 @@ class Context:
         if not problems:
             return []
         return self.batch2d(problems, prec=prec, rmax=rmax, method="expsum", **kw).run(stream)
+
+    # ---- the cross's building blocks on caller data (lrpoisson_kernels.h)
+    def kernel_qr_maxvol(self, A, tau=0.0, stream=None):
+        """TSQR of A (n x k, column-major float64 on the GPU) and maxvol on
+        its Q: returns (Q, R, rows, converged)."""
+        import torch
+        n, k = A.shape
+        Q = empty_colmajor(n, k, A.device)
+        R = empty_colmajor(k, k, A.device)
+        rows = (ctypes.c_int32 * max(k, 1))()
+        conv = ctypes.c_int32(0)
+        st = self.lib.lrp_kernel_qr_maxvol(self.h, n, k, _ptr(A), _ld(A), float(tau), _ptr(Q),
+                                           n, _ptr(R), k, rows, ctypes.byref(conv),
+                                           _stream(stream))
+        if st != LRP_OK:
+            raise LrpError(st, "lrp_kernel_qr_maxvol")
+        return Q, R, [rows[i] for i in range(k)], bool(conv.value)
+
+    def kernel_core_svd(self, M, stream=None):
+        """Jacobi SVD of a k x k core (column-major float64 on the GPU):
+        returns (W, sigma, Z) with M = W diag(sigma) Z^T."""
+        import torch
+        k = M.shape[0]
+        W = empty_colmajor(k, k, M.device)
+        Z = empty_colmajor(k, k, M.device)
+        sig = torch.empty(k, dtype=torch.float64, device=M.device)
+        st = self.lib.lrp_kernel_core_svd(self.h, k, _ptr(M), _ld(M), _ptr(W), _ptr(sig),
+                                          _ptr(Z), _stream(stream))
+        if st != LRP_OK:
+            raise LrpError(st, "lrp_kernel_core_svd")
+        return W, sig, Z
 
     def expsum_solve2d(self, U, V, eps, rmax=None, prec="fp64", stream=None, **kw):
         """One comparator solve; returns (Ux, Vx, info)."""

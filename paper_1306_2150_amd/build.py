@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "liblrpoisson.so")
 
 SOURCES = ["dst.hip", "dst_i8.hip", "dst_fft.hip", "tsqr.hip", "maxvol.hip", "svd.hip", "cross.hip", "tucker.hip",
            "noalloc.hip", "expsum.hip", "host.cpp", "host3d.cpp", "serve.cpp",
-           "host_expsum.cpp"]
+           "host_expsum.cpp", "host_kernels.cpp"]
 
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

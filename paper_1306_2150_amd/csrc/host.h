@@ -199,6 +199,8 @@ struct lrp_ctx {
   std::map<int, std::unique_ptr<lrp::Group2D>> batch_groups;
   std::map<int, std::unique_ptr<lrp::Group3D>> batch3_groups;
   std::map<int, std::unique_ptr<lrp::ExpGroup>> expsum_groups;
+  // one-slot groups of the component entry points, keyed by n
+  std::map<int, std::unique_ptr<lrp::Group2D>> kernel_groups;
   // serving
   hipStream_t serve_stream = nullptr;
   std::map<int, std::unique_ptr<lrp::Group2D>> serve_groups;

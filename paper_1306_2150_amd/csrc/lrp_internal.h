@@ -374,6 +374,10 @@ hipError_t launch_tsqr(int which, int rows, const Tree &tr, Solve2D *s,
 enum : int { MV_Q0_TO_I = 0, MV_Q1_TO_JN = 1, MV_Q1_TO_J = 2 };
 hipError_t launch_maxvol(int which, int rows, const Tree &tr, Solve2D *s,
                          int nsolves, int kmax, hipStream_t st);
+// more check/swap rounds of a maxvol that launch_maxvol started (its rows
+// and inverse are current); rounds of a converged maxvol do nothing
+hipError_t launch_maxvol_rounds(int which, int rows, const Tree &tr, Solve2D *s,
+                                int nsolves, int kmax, int rounds, hipStream_t st);
 
 // kmax: the largest k of the launch's solves (selects the LDS bucket)
 hipError_t launch_core(int phase, Solve2D *s, int nsolves, int kmax, hipStream_t st);

@@ -605,7 +605,13 @@ hipError_t launch_maxvol(int which, int rows, const Tree &tr, Solve2D *s,
   else if (kmax <= 32) hipLaunchKernelGGL(k_mv_inv<32>, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
   else if (kmax <= 48) hipLaunchKernelGGL(k_mv_inv<48>, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
   else hipLaunchKernelGGL(k_mv_inv<64>, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
-  for (int round = 0; round < MV_ROUNDS; ++round) {
+  return launch_maxvol_rounds(which, rows, tr, s, nsolves, kmax, MV_ROUNDS, st);
+}
+
+hipError_t launch_maxvol_rounds(int which, int rows, const Tree &tr, Solve2D *s, int nsolves,
+                                int kmax, int rounds, hipStream_t st) {
+  const int n = rows;
+  for (int round = 0; round < rounds; ++round) {
     if (kmax <= 16) run_check<16>(which, n, tr, s, nsolves, st);
     else if (kmax <= 32) run_check<32>(which, n, tr, s, nsolves, st);
     else if (kmax <= 48) run_check<48>(which, n, tr, s, nsolves, st);

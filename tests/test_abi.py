@@ -11,13 +11,17 @@ from paper_1306_2150_amd import binding
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "lrpoisson.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(",
-                       src, flags=re.M)
+    names = []
+    for h in HEADERS:
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names += re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(",
+                            src, flags=re.M)
     return sorted(set(names))
 
 
@@ -59,6 +63,11 @@ def test_null_context_rejected(lib):
     assert lib.lrp_poll(None, 1, ctypes.byref(res), None, None) == binding.LRP_EINVAL
     probs = (binding.LrpProblem2D * 1)()
     assert lib.lrp_expsum_solve2d_batch(None, 1024, 1, probs, None, None) == binding.LRP_EINVAL
+    conv = ctypes.c_int32(0)
+    rows = (ctypes.c_int32 * 4)()
+    assert lib.lrp_kernel_qr_maxvol(None, 16, 4, P(1), 16, 0.0, P(1), 16, P(1), 4, rows,
+                                    ctypes.byref(conv), None) == binding.LRP_EINVAL
+    assert lib.lrp_kernel_core_svd(None, 4, P(1), 4, P(1), P(1), P(1), None) == binding.LRP_EINVAL
 
 
 def test_struct_layouts_match_header(tmp_path):

@@ -1,0 +1,153 @@
+"""Kernel-level parity of the cross's building blocks, through the component
+entry points of include/lrpoisson_kernels.h, against LAPACK (numpy) on host
+copies and against the maxvol exit contract:
+  - Householder TSQR (Section 3's QR of the factors): A = Q R, Q^T Q = I, R
+    upper triangular and equal to LAPACK's R up to the signs of its rows,
+    over ragged row counts, tree depths 1 to 3, ranks 1 to 64, graded and
+    rank-deficient panels;
+  - maxvol (Section 4.2): distinct rows, B = Q Q[I,:]^-1 with B[I,:] = I and
+    max|B| <= tau up to the float32 rounding of the check, and on small
+    panels a volume within the dominance bound of the brute-force maximum;
+  - the Jacobi core SVD (Section 3's SVD of the small core): singular values
+    against LAPACK, orthogonality, reconstruction, descending order, for
+    random, graded, rank-deficient and tiny cores."""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_1306_2150_amd import binding
+
+from gpu_util import ctx, dev, host, log
+
+pytestmark = pytest.mark.gpu
+
+TAU = 1.05
+F32_SLACK = 1e-5   # the check that finds violators reads a float32 copy of Q
+
+
+def panel(n, k, kind, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, k))
+    if kind == "graded":
+        A = A * np.power(10.0, -np.arange(k) / 4.0)[None, :]
+    elif kind == "deficient":
+        q = max(1, k // 2)
+        A = rng.standard_normal((n, q)) @ rng.standard_normal((q, k))
+    elif kind == "smooth":   # columns of a smooth kernel, as a cross step sees
+        x = np.arange(1, n + 1) / (n + 1)
+        c = rng.uniform(0.1, 0.9, k)
+        A = 1.0 / (1.0 + 50.0 * (x[:, None] - c[None, :]) ** 2)
+    return np.asfortranarray(A)
+
+
+def check_maxvol(Q, rows, tau):
+    n, k = Q.shape
+    assert len(set(rows)) == k and all(0 <= i < n for i in rows)
+    B = Q @ np.linalg.inv(Q[rows, :])
+    assert np.abs(B[rows, :] - np.eye(k)).max() < 1e-10
+    assert np.abs(B).max() <= tau * (1.0 + F32_SLACK) + 1e-12, np.abs(B).max()
+    return B
+
+
+@pytest.mark.parametrize("n,k,kind", [
+    (1000, 37, "random"), (256, 16, "random"), (257, 16, "random"), (5000, 64, "random"),
+    (4097, 32, "graded"), (3000, 20, "deficient"), (64, 64, "random"), (1, 1, "random"),
+    (700, 1, "random"), (2048, 48, "smooth"), (12345, 24, "random")])
+def test_tsqr_against_lapack(n, k, kind):
+    log("tsqr", n, k, kind)
+    A = panel(n, k, kind, seed=n + k)
+    Q, R, rows, conv = ctx().kernel_qr_maxvol(dev(A))
+    Q, R = host(Q), host(R)
+    nrm = np.linalg.norm(A)
+    assert np.linalg.norm(Q @ R - A) <= 1e-14 * max(nrm, 1e-300) * np.sqrt(k) * 4
+    assert np.abs(Q.T @ Q - np.eye(k)).max() < 1e-13
+    assert np.abs(np.tril(R, -1)).max() == 0.0
+    if kind in ("random", "graded"):
+        R0 = np.linalg.qr(A, mode="r")
+        # unique up to the signs of the rows for a full-rank panel
+        d = np.abs(np.diag(R0))
+        rel = np.abs(np.abs(R) - np.abs(R0)).max(axis=1) / d
+        assert rel.max() < 1e-10, rel.max()
+
+
+@pytest.mark.parametrize("n,k,kind", [
+    (1000, 37, "random"), (4096, 16, "random"), (300, 64, "random"), (2048, 32, "smooth"),
+    (777, 8, "graded"), (5000, 48, "random")])
+def test_maxvol_exit_contract(n, k, kind):
+    log("maxvol", n, k, kind)
+    A = panel(n, k, kind, seed=7 * n + k)
+    Q, R, rows, conv = ctx().kernel_qr_maxvol(dev(A), tau=TAU)
+    assert conv
+    check_maxvol(host(Q), rows, TAU)
+
+
+@pytest.mark.parametrize("n,k,seed", [(10, 2, 1), (11, 3, 2), (12, 3, 3), (9, 4, 4)])
+def test_maxvol_volume_against_brute_force(n, k, seed):
+    """A tau-dominant k x k submatrix has volume at least the maximum volume
+    over (tau sqrt(k))^k (its inverse times any other submatrix has entries
+    bounded by tau); the brute force runs over every row subset."""
+    A = panel(n, k, "random", seed)
+    Q, R, rows, conv = ctx().kernel_qr_maxvol(dev(A), tau=TAU)
+    Q = host(Q)
+    assert conv
+    check_maxvol(Q, rows, TAU)
+    vmax = max(abs(np.linalg.det(Q[list(s), :])) for s in itertools.combinations(range(n), k))
+    v = abs(np.linalg.det(Q[rows, :]))
+    assert v >= vmax / (TAU * np.sqrt(k)) ** k * (1 - 1e-12)
+
+
+def test_maxvol_custom_tau_and_deficient_panel():
+    A = panel(2000, 30, "deficient", 11)
+    Q, R, rows, conv = ctx().kernel_qr_maxvol(dev(A), tau=1.5)
+    assert conv
+    check_maxvol(host(Q), rows, 1.5)
+
+
+def test_component_argument_errors():
+    c = ctx()
+    A = dev(panel(100, 4, "random", 1))
+    with pytest.raises(binding.LrpError):
+        c.kernel_qr_maxvol(A, tau=0.5)
+    with pytest.raises(binding.LrpError):
+        c.kernel_qr_maxvol(dev(panel(3, 4, "random", 1)))   # n < k
+
+
+def core(k, kind, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "random":
+        return rng.standard_normal((k, k))
+    Ua, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    Va, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    if kind == "graded":
+        s = np.power(10.0, -np.arange(k) * 12.0 / max(k - 1, 1))
+    elif kind == "deficient":
+        s = np.concatenate([np.linspace(1.0, 0.1, k // 3 + 1), np.zeros(k - k // 3 - 1)])
+    else:   # clustered
+        s = np.ones(k) + 1e-9 * np.arange(k)
+    return (Ua * s) @ Va.T
+
+
+@pytest.mark.parametrize("k,kind", [
+    (37, "random"), (64, "random"), (1, "random"), (2, "random"), (16, "graded"),
+    (48, "graded"), (30, "deficient"), (64, "deficient"), (20, "clustered")])
+def test_core_svd_against_lapack(k, kind):
+    log("core svd", k, kind)
+    M = np.asfortranarray(core(k, kind, seed=k))
+    W, sig, Z = ctx().kernel_core_svd(dev(M))
+    W, sig, Z = host(W), host(sig).ravel(), host(Z)
+    s0 = np.linalg.svd(M, compute_uv=False)
+    smax = s0[0]
+    assert np.all(np.diff(sig) <= 0.0)
+    assert np.abs(sig - s0).max() <= 1e-13 * smax
+    # relative accuracy where the input fixes the singular values to it
+    # (forming M perturbs every value by about u ||M||)
+    big = s0 >= 1e-5 * smax
+    assert np.all(np.abs(sig[big] - s0[big]) <= 1e-10 * s0[big])
+    assert np.abs(Z.T @ Z - np.eye(k)).max() < 1e-12
+    # left vectors: W = M Z / sigma, accurate to about u sigma_max / sigma
+    keep = sig >= 1e-6 * smax
+    Wk = W[:, keep]
+    assert np.abs(Wk.T @ Wk - np.eye(keep.sum())).max() < 1e-9
+    assert np.all(W[:, sig == 0.0] == 0.0)
+    assert np.linalg.norm((W * sig) @ Z.T - M) <= 1e-13 * np.linalg.norm(M) * k
