@@ -21,8 +21,11 @@ Contents
 ``expsum``   the exponential-sum comparator of Section 4.1 (sinc quadrature
              of 1/x, Hadamard product with the transformed right-hand side,
              rounding).
+``stokes``   the discrete 2D Stokes problem of Section 2 (gradients from the
+             shift matrices, the consistent Laplacian, the Schur complement)
+             and its full-format Uzawa solve; the test problem of Section 6.
 
 Every function is pinned by ``tests/test_oracle_*.py`` against closed forms,
 library routines or brute force; see each function's docstring for its pin.
 """
-from . import poisson, lowrank, metrics, tucker, expsum  # noqa: F401
+from . import poisson, lowrank, metrics, tucker, expsum, stokes  # noqa: F401
