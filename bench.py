@@ -94,6 +94,8 @@ def parse():
                     help="skip the exponential-sum comparator timing")
     ap.add_argument("--expsum-batches", type=str, default="1,256",
                     help="batch sizes of the exponential-sum comparison")
+    ap.add_argument("--only-stokes", action="store_true",
+                    help="run only the Stokes driver on Section 6's test problem (one JSON line)")
     ap.add_argument("--only-expsum", action="store_true",
                     help="run only the exponential-sum comparator timing (one JSON line)")
     ap.add_argument("--cpu-sample", type=int, default=5)
@@ -195,6 +197,49 @@ def expsum_vs_cross(ctx, workers, batches=(1, 256)):
     return rec
 
 
+# Section 6's test problem on the grids of Table 1, with the thresholds the
+# 64-column rounding panels allow (the paper: 5e-9 at every n)
+STOKES_CASES = [(64, 5e-9), (128, 5e-9), (256, 1e-7), (512, 2e-7), (1024, 5e-7)]
+
+
+def stokes_table(ctx, workers):
+    """Table 1's columns for the low-rank Uzawa-GMRES driver on the GPU and
+    the full-format Uzawa (CG) of the CPU oracle: time and relative error of
+    p against the prescribed solution (eq. "ansin2d")."""
+    import numpy as np
+    import torch
+
+    from oracle import stokes
+    from paper_1306_2150_amd import binding
+    rows = []
+    for n, eps in STOKES_CASES:
+        fu, fv, g = stokes.ansin2d_factors(n)
+        d = lambda pr: (binding.colmajor(pr[0]), binding.colmajor(pr[1]))
+        args = (d(fu), d(fv), d(g))
+        ctx.stokes2d(*args, eps)          # warm-up (tables, groups)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        (pU, pV), _, _, info = ctx.stokes2d(*args, eps)
+        torch.cuda.synchronize()
+        t_lr = time.perf_counter() - t0
+        P = pU.cpu().numpy() @ pV.cpu().numpy().T
+        Fu, Fv, Gd, _, _, p_ex = stokes.ansin2d(n)
+        t0 = time.perf_counter()
+        pf, _, _, its = stokes.uzawa_cg(Fu, Fv, Gd, tol=1e-12)
+        t_full = time.perf_counter() - t0
+        pe = stokes.project(p_ex)
+        rec = {"n": n, "eps": eps, "lr_s": t_lr, "full_cpu_s": t_full,
+               "err_p_lr": float(np.linalg.norm(P - pe) / np.linalg.norm(pe)),
+               "err_p_full": float(np.linalg.norm(stokes.project(pf) - pe) / np.linalg.norm(pe)),
+               "gmres_iterations": info["iterations"], "restarts": info["restarts"],
+               "rank_p": info["ranks"][0], "max_krylov_rank": info["max_krylov_rank"],
+               "true_residual": info["true_residual"], "full_cg_iterations": its}
+        print(f"[bench] Stokes n={n} eps={eps}: LR {t_lr:.3f} s (GPU), full {t_full:.3f} s (CPU), "
+              f"err p {rec['err_p_lr']:.2e}/{rec['err_p_full']:.2e}", file=sys.stderr, flush=True)
+        rows.append(rec)
+    return {"problem": "Section 6 eq. ansin2d on n x n pressure cells", "rows": rows}
+
+
 def timed_steps(ctx, problems, prec, steps, warmup):
     import torch
     # the argument array and output buffers are prepared once; every step
@@ -238,6 +283,11 @@ def main():
         torch.cuda.synchronize()
         del a, b
     ctx = binding.Context(0, workspace_bytes=64 << 30)
+    if args.only_stokes:
+        print(json.dumps({"stokes_table1": stokes_table(ctx, min(16, os.cpu_count() or 1))}),
+              flush=True)
+        ctx.close()
+        return
     if args.only_expsum:
         batches = [int(x) for x in args.expsum_batches.split(",") if x]
         print(json.dumps({"expsum_vs_cross": expsum_vs_cross(ctx, min(16, os.cpu_count() or 1),

@@ -281,6 +281,55 @@ lrp_status lrp_expsum_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t count,
                                     lrp_problem2d *probs, const lrp_opts *opts,
                                     void *stream);
 
+/* The low-rank Uzawa solve of the 2D Stokes problem (Section 2, eq.
+ * "stprob"; Section 5), the application the Poisson solver serves.
+ * Pressure at the n x n cell centres of [0,1]^2 (h = 1/n), velocity at the
+ * (n-1) x (n-1) interior vertices (zero on the boundary); with the shift
+ * matrices G = E - Z and H = E + Z ((n-1) x n), and matrices whose first
+ * index runs along x, the discrete gradients are B_x p = G p H^T/(4h),
+ * B_y p = H p G^T/(4h), and the Laplacian is Delta = B_x B_x^T +
+ * B_y B_y^T (the Stokes-consistent operator of LRP_OP_STOKES, which is
+ * 4 Delta).  The system  Delta u + B_x p = f_u,  Delta v + B_y p = f_v,
+ * B_x^T u + B_y^T v = g  is reduced to the Schur system (eq. "schur")
+ * S p = B_x^T Delta^-1 f_u + B_y^T Delta^-1 f_v - g,
+ * S = B_x^T Delta^-1 B_x + B_y^T Delta^-1 B_y, solved by restarted GMRES
+ * whose vectors are low-rank matrices: every sum is rounded, each
+ * application of S runs two low-rank Poisson solves, and the accuracy of
+ * the products is relaxed as the residual falls (inexact GMRES, Section 5).
+ * Then u = Delta^-1 (f_u - B_x p), v likewise.  S has a two-dimensional
+ * kernel (the constant and the checkerboard pressure): g's components
+ * along it are removed first, and p is returned without them.
+ * All factors: device float64, column-major, leading dimension ld (inputs)
+ * and ldx (outputs), >= n.  n >= 32; ranks <= LRP_MAX_RANK.  The call
+ * returns after its work completed; status as the 2D solve (LRP_ENOCONV
+ * when max_iter iterations do not reach eps, the last iterate written). */
+typedef struct {
+  int64_t n;
+  int32_t rank_fu, rank_fv, rank_g;
+  int32_t prec;               /* lrp_precision of the Poisson solves        */
+  const double *fu_U, *fu_V;  /* f_u = fu_U fu_V^T, (n-1) x rank_fu each    */
+  const double *fv_U, *fv_V;  /* f_v, (n-1) x rank_fv                       */
+  const double *g_U, *g_V;    /* g, n x rank_g                              */
+  int64_t ld;
+  double eps;                 /* relative accuracy of the Schur residual    */
+  int32_t max_iter;           /* GMRES iterations cap, default 200          */
+  int32_t restart;            /* GMRES restart length, default 30, <= 60    */
+  double *p_U, *p_V;          /* out: p = p_U p_V^T, n x rmax each          */
+  double *u_U, *u_V;          /* out: u, (n-1) x rmax each                  */
+  double *v_U, *v_V;          /* out: v, (n-1) x rmax each                  */
+  int64_t ldx;
+  int32_t rmax;
+  int32_t rank_out[3];        /* out: ranks of p, u, v                      */
+  int32_t iterations;         /* out: GMRES iterations (all restarts)       */
+  int32_t restarts;           /* out                                        */
+  int32_t max_krylov_rank;    /* out: the largest rank of a Krylov vector   */
+  int32_t status;             /* out                                        */
+  double residual;            /* out: GMRES's residual estimate / ||b||     */
+  double true_residual;       /* out: ||b - S p|| / ||b||, recomputed       */
+} lrp_stokes2d_problem;
+
+lrp_status lrp_stokes2d(lrp_ctx *ctx, lrp_stokes2d_problem *prob, void *stream);
+
 /* The orthonormal sine transform on its own (paper Section 4.1, eq. "diag":
  * S[j,k] = sqrt(2/(n+1)) sin(pi j k/(n+1)), the DST-I that diagonalises the
  * 1D operator; S = S^T = S^-1, so the same call transforms forward and

@@ -50,6 +50,19 @@ lrp_status lrp_kernel_qr_maxvol(lrp_ctx *ctx, int64_t n, int32_t k, const double
 lrp_status lrp_kernel_core_svd(lrp_ctx *ctx, int32_t k, const double *M, int64_t ldm,
                                double *W, double *sigma, double *Z, void *stream);
 
+/* Rounding of a low-rank product (Section 3's rounding, for the sums of
+ * low-rank matrices that the Stokes driver forms; Section 5): X = U V^T with
+ * U, V: n x K (ld >= n, read only), 16 <= n <= LRP_MAX_N, K >= 0 (any
+ * number of columns), to the relative Frobenius accuracy eps in (0, 1):
+ * Ux (n x rmax, ldx >= n, written: carries the scale) and Vx (orthonormal
+ * columns) of rank *rank_out.  Randomized range finder: a Gaussian sketch of
+ * min(64, n) columns, one power step, TSQR twice and the Jacobi core SVD;
+ * LRP_ERANKCAP when the rank exceeds rmax or comes within 8 of the sketch
+ * width (*rank_out then holds the rank found; outputs unwritten). */
+lrp_status lrp_lowrank_round(lrp_ctx *ctx, int64_t n, int32_t K, const double *U,
+                             const double *V, int64_t ld, double eps, double *Ux, double *Vx,
+                             int64_t ldx, int32_t rmax, int32_t *rank_out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -42,7 +42,8 @@ EXPORTS = ["lrp_create", "lrp_destroy", "lrp_strerror", "lrpoisson_solve2d",
            "lrpoisson_solve2d_batch", "lrpoisson_solve3d", "lrp_submit",
            "lrp_serve_step", "lrp_poll", "lrp_wait", "lrp_sine_transform",
            "lrp_sine_transform_noalloc", "lrp_expsum_solve2d_batch",
-           "lrp_kernel_qr_maxvol", "lrp_kernel_core_svd",
+           "lrp_kernel_qr_maxvol", "lrp_kernel_core_svd", "lrp_stokes2d",
+           "lrp_lowrank_round",
            "lrp_set_kernel_timing", "lrp_kernel_stats"]
 
 
@@ -80,6 +81,25 @@ class LrpProblem2D(ctypes.Structure):
                 ("Ux", ctypes.c_void_p), ("Vx", ctypes.c_void_p),
                 ("ldx", ctypes.c_int64), ("rank_out", ctypes.c_int32),
                 ("info", LrpInfo)]
+
+
+class LrpStokes2DProblem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("rank_fu", ctypes.c_int32),
+                ("rank_fv", ctypes.c_int32), ("rank_g", ctypes.c_int32),
+                ("prec", ctypes.c_int32),
+                ("fu_U", ctypes.c_void_p), ("fu_V", ctypes.c_void_p),
+                ("fv_U", ctypes.c_void_p), ("fv_V", ctypes.c_void_p),
+                ("g_U", ctypes.c_void_p), ("g_V", ctypes.c_void_p),
+                ("ld", ctypes.c_int64), ("eps", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("p_U", ctypes.c_void_p), ("p_V", ctypes.c_void_p),
+                ("u_U", ctypes.c_void_p), ("u_V", ctypes.c_void_p),
+                ("v_U", ctypes.c_void_p), ("v_V", ctypes.c_void_p),
+                ("ldx", ctypes.c_int64), ("rmax", ctypes.c_int32),
+                ("rank_out", ctypes.c_int32 * 3), ("iterations", ctypes.c_int32),
+                ("restarts", ctypes.c_int32), ("max_krylov_rank", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("residual", ctypes.c_double),
+                ("true_residual", ctypes.c_double)]
 
 
 class LrpRequest(ctypes.Structure):
@@ -127,6 +147,9 @@ def load(path: str = LIB_PATH):
     lib.lrp_kernel_qr_maxvol.argtypes = [P, I64, I32, P, I64, F64, P, I64, P, I64,
                                          ctypes.POINTER(I32), ctypes.POINTER(I32), P]
     lib.lrp_kernel_core_svd.argtypes = [P, I32, P, I64, P, P, P, P]
+    lib.lrp_stokes2d.argtypes = [P, ctypes.POINTER(LrpStokes2DProblem), P]
+    lib.lrp_lowrank_round.argtypes = [P, I64, I32, P, P, I64, F64, P, P, I64, I32,
+                                      ctypes.POINTER(I32), P]
     lib.lrpoisson_solve3d.argtypes = [P, I64, ctypes.POINTER(I32), P, P, P, I64, P,
                                       F64, ctypes.POINTER(LrpOpts), P, P, P, I64, P,
                                       ctypes.POINTER(I32), ctypes.POINTER(I32),
@@ -326,6 +349,50 @@ class Context:
             return []
         return self.batch2d(problems, prec=prec, rmax=rmax, method="expsum", **kw).run(stream)
 
+    # ---- the low-rank Uzawa-GMRES Stokes driver
+    def stokes2d(self, fu, fv, g, eps, rmax=None, prec="fp64", max_iter=0, restart=0,
+                 stream=None, check=True):
+        """The 2D Stokes problem on n x n pressure cells: fu, fv = (U, V)
+        factor pairs of the velocity right-hand sides ((n-1) rows), g = (U, V)
+        of the pressure one (n rows), column-major float64 GPU tensors.
+        Returns ((pU, pV), (uU, uV), (vU, vV), info)."""
+        import torch
+        n = g[0].shape[0]
+        rmax = MAX_RANK if rmax is None else rmax
+        dev = g[0].device
+        # inputs share one leading dimension: copy them into n-row blocks
+        ld = n
+
+        def pad(t, rows):
+            out = torch.zeros((max(t.shape[1], 1), ld), dtype=torch.float64, device=dev).T
+            out[:rows, :t.shape[1]] = t
+            return out[:, :t.shape[1]]
+        ins = [pad(fu[0], n - 1), pad(fu[1], n - 1), pad(fv[0], n - 1), pad(fv[1], n - 1),
+               pad(g[0], n), pad(g[1], n)]
+        outs = [empty_colmajor(n, rmax, dev) for _ in range(6)]
+        pr = LrpStokes2DProblem()
+        pr.n = n
+        pr.rank_fu, pr.rank_fv, pr.rank_g = fu[0].shape[1], fv[0].shape[1], g[0].shape[1]
+        pr.prec = PREC[prec] if isinstance(prec, str) else int(prec)
+        pr.fu_U, pr.fu_V, pr.fv_U, pr.fv_V, pr.g_U, pr.g_V = [_ptr(t) for t in ins]
+        pr.ld = ld
+        pr.eps = eps
+        pr.max_iter = max_iter
+        pr.restart = restart
+        pr.p_U, pr.p_V, pr.u_U, pr.u_V, pr.v_U, pr.v_V = [_ptr(t) for t in outs]
+        pr.ldx = n
+        pr.rmax = rmax
+        st = self.lib.lrp_stokes2d(self.h, ctypes.byref(pr), _stream(stream))
+        if check and st != LRP_OK:
+            raise LrpError(st, "lrp_stokes2d")
+        rp, ru, rv = pr.rank_out[0], pr.rank_out[1], pr.rank_out[2]
+        info = dict(status=st, iterations=pr.iterations, restarts=pr.restarts,
+                    max_krylov_rank=pr.max_krylov_rank, residual=pr.residual,
+                    true_residual=pr.true_residual, ranks=(rp, ru, rv))
+        return ((outs[0][:, :rp], outs[1][:, :rp]),
+                (outs[2][:n - 1, :ru], outs[3][:n - 1, :ru]),
+                (outs[4][:n - 1, :rv], outs[5][:n - 1, :rv]), info)
+
     # ---- the cross's building blocks on caller data (lrpoisson_kernels.h)
     def kernel_qr_maxvol(self, A, tau=0.0, stream=None):
         """TSQR of A (n x k, column-major float64 on the GPU) and maxvol on
@@ -342,6 +409,19 @@ class Context:
         if st != LRP_OK:
             raise LrpError(st, "lrp_kernel_qr_maxvol")
         return Q, R, [rows[i] for i in range(k)], bool(conv.value)
+
+    def lowrank_round(self, U, V, eps, rmax=MAX_RANK, stream=None):
+        """Round U V^T (n x K factors on the GPU) to eps: returns (Ux, Vx)."""
+        n, K = U.shape
+        Ux = empty_colmajor(n, rmax, U.device)
+        Vx = empty_colmajor(n, rmax, U.device)
+        rank = ctypes.c_int32(0)
+        st = self.lib.lrp_lowrank_round(self.h, n, K, _ptr(U), _ptr(V), _ld(U) if K else n,
+                                        eps, _ptr(Ux), _ptr(Vx), n, rmax, ctypes.byref(rank),
+                                        _stream(stream))
+        if st != LRP_OK:
+            raise LrpError(st, f"lrp_lowrank_round (rank {rank.value})")
+        return Ux[:, :rank.value], Vx[:, :rank.value]
 
     def kernel_core_svd(self, M, stream=None):
         """Jacobi SVD of a k x k core (column-major float64 on the GPU):

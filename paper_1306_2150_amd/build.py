@@ -19,8 +19,9 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblrpoisson.so")
 
 SOURCES = ["dst.hip", "dst_i8.hip", "dst_fft.hip", "tsqr.hip", "maxvol.hip", "svd.hip", "cross.hip", "tucker.hip",
-           "noalloc.hip", "expsum.hip", "host.cpp", "host3d.cpp", "serve.cpp",
-           "host_expsum.cpp", "host_kernels.cpp"]
+           "noalloc.hip", "expsum.hip", "lowrank.hip", "host.cpp", "host3d.cpp", "serve.cpp",
+           "host_expsum.cpp", "host_kernels.cpp", "host_stokes.cpp",
+           "host_round.cpp"]
 
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -12,12 +12,14 @@
 // in c at a time: the rank-K factorisation Qa diag(sig) Qb^T so far and the
 // next c columns form the panels
 //     Pa = [Qa diag(sig), new a columns],  Pb = [Qb, new b columns],
-// n x (K + c) with K + c <= KMAX; Pa = Qa~ Ra, Pb = Qb~ Rb (TSQR), Ra Rb^T
+// n x (K + c) with K + c <= kw = min(KMAX, n); Pa = Qa~ Ra, Pb = Qb~ Rb (TSQR), Ra Rb^T
 // = W S Z^T (Jacobi SVD), and the step keeps the leading K' columns of
 // Qa~ W and Qb~ Z, K' the smallest rank whose dropped tail is within the
 // step's share of the tolerance: (eps/2) c / (R r) of ||S|| per step, eps/2
 // at the last step, so that the dropped tails add up to at most eps times
-// the largest core norm.
+// the largest core norm.  In plain mode the same steps round a given
+// product U V^T of many columns (the sums of low-rank matrices that the
+// Stokes driver forms).
 #include "lrp_internal.h"
 
 namespace lrp {
@@ -33,7 +35,7 @@ __global__ __launch_bounds__(ES_T) void k_es_panel(ExpState *E, Solve2D *jobs, i
   const int side = blockIdx.y;
   Solve2D &j = jobs[side * cap + blockIdx.z];
   const bool run = e.phase == ES_RUN;
-  const int K = e.K, c = es_cols(e.K, e.j0, e.tot);
+  const int K = e.K, c = es_cols(e.K, e.j0, e.tot, e.kw);
   // the TSQR and the core act on the job records of running solves only
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     j.active = run ? ACT_INIT : ACT_DONE;
@@ -46,6 +48,11 @@ __global__ __launch_bounds__(ES_T) void k_es_panel(ExpState *E, Solve2D *jobs, i
   double *P = j.Vh;
   const double *Q = j.Q0;
   for (int t = 0; t < K; ++t) P[i + t * ldp] = Q[i + t * ldq] * (side == 0 ? e.sig[t] : 1.0);
+  if (e.pu) {   // plain rounding: the product's own columns
+    const double *F = side == 0 ? e.pu : e.pv;
+    for (int t = 0; t < c; ++t) P[i + (K + t) * ldp] = F[i + (long)(e.j0 + t) * e.ldp];
+    return;
+  }
   const double li = e.lam[i];
   const double *F = j.Uh;
   int k = e.j0 / e.r, a = e.j0 - k * e.r;
@@ -91,8 +98,8 @@ __global__ __launch_bounds__(64) void k_es_trunc(ExpState *E, const Solve2D *job
       }
       if (nrm == 0.0) R = 0;
       // room for the next step's columns
-      if (!last && R > KMAX - ES_CMIN) {
-        R = KMAX - ES_CMIN;
+      if (!last && R > e.kw - ES_CMIN) {
+        R = e.kw - ES_CMIN;
         e.capped = 1;
       }
       double drop2 = 0.0;

@@ -739,6 +739,7 @@ lrp_status lrp_destroy(lrp_ctx *ctx) {
   ctx->batch3_groups.clear();
   ctx->expsum_groups.clear();
   ctx->kernel_groups.clear();
+  ctx->round_groups.clear();
   ctx->serve_groups.clear();
   ctx->serve3_groups.clear();
   for (auto &kv : ctx->tables) dev_free(ctx, kv.second.tab, kv.second.bytes);

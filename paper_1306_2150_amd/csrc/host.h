@@ -173,6 +173,48 @@ struct ExpGroup {
   // nodes of each (eps) met so far: sqrt(w_k), then p_k
   std::map<double, std::vector<double>> node_cache;
 };
+ExpGroup *expsum_group(lrp_ctx *ctx, int n, int count, lrp_status *err);
+// the incremental rounding steps of slots [0, count) (states uploaded)
+lrp_status run_steps(ExpGroup &g, int count, hipStream_t st);
+
+// One product U V^T (n x K factors, device, leading dimension ld) to round
+// to eps (relative Frobenius): Ux (the scale) and Vx (orthonormal columns)
+// receive `rank` <= rmax columns; status LRP_ERANKCAP when the rank exceeds
+// rmax (outputs unwritten) or a step lacked room.
+struct RoundJob {
+  const double *U, *V;
+  long ld;
+  int K;
+  double eps;
+  double *Ux, *Vx;
+  long ldx;
+  int rmax;
+  int rank;       // out
+  int status;     // out
+  double err;     // out: the dropped tails over the final core norm
+};
+// Rounds `count` products of grid size n >= ES_MIN_N_PLAIN together; the
+// outputs are enqueued on st (the call waits only for the rank read-backs).
+lrp_status round_products(lrp_ctx *ctx, int n, int count, RoundJob *jobs, hipStream_t st);
+
+// The randomized rounding of one product U V^T (n x K, host_round.cpp): a
+// one-slot group for its TSQR and core, the Gaussian sketch and buffers.
+struct RoundGroup {
+  ~RoundGroup();
+  lrp_ctx *ctx = nullptr;
+  int n = 0, L = 0, kcap = 0;
+  std::unique_ptr<Group2D> g;
+  double *buf = nullptr, *omega = nullptr, *Z = nullptr, *Qk = nullptr;
+  size_t bytes = 0;
+};
+// Ux (scale) and Vx (orthonormal) of rank <= rmax with relative error
+// <= eps (*err: the dropped tail over the result's norm); LRP_ERANKCAP when
+// the rank exceeds rmax or comes within 8 of the sketch width min(64, n).
+// Enqueued on st; waits for the singular values only.
+// A tail up to abs_tol (absolute Frobenius) may also be dropped.
+lrp_status round_random(lrp_ctx *ctx, int n, int K, const double *U, const double *V, long ld,
+                        double eps, double *Ux, double *Vx, long ldx, int rmax, int *rank,
+                        double *err, hipStream_t st, double abs_tol = 0.0);
 
 }  // namespace lrp
 
@@ -201,6 +243,8 @@ struct lrp_ctx {
   std::map<int, std::unique_ptr<lrp::ExpGroup>> expsum_groups;
   // one-slot groups of the component entry points, keyed by n
   std::map<int, std::unique_ptr<lrp::Group2D>> kernel_groups;
+  // randomized rounding of the Stokes driver's sums, keyed by n
+  std::map<int, std::unique_ptr<lrp::RoundGroup>> round_groups;
   // serving
   hipStream_t serve_stream = nullptr;
   std::map<int, std::unique_ptr<lrp::Group2D>> serve_groups;

@@ -77,6 +77,103 @@ size_t states_bytes(int cap) { return ((size_t)cap * sizeof(ExpState) + 255) & ~
 
 }  // namespace
 
+// The rounding steps of slots [0, count) of g (their states uploaded): until
+// every slot has left ES_RUN, ES_STEPS_PER_FETCH steps between read-backs
+// of the states (a finished slot's launches exit at once).
+lrp_status run_steps(ExpGroup &g, int count, hipStream_t st) {
+  const int cap = g.cap, n = g.n;
+  // every step appends at least min(ES_CMIN, what is left) columns
+  int max_steps = 0;
+  for (int i = 0; i < count; ++i)
+    max_steps = std::max(max_steps, 1 + ceil_div(g.h_e[i].tot, ES_CMIN));
+  const Tree tree = make_tree(n, KMAX);
+  Solve2D *d_jobs = g.jobs->dev_solves();
+  bool running = true;
+  for (int done = 0; running && done <= max_steps; done += ES_STEPS_PER_FETCH) {
+    for (int s = 0; s < ES_STEPS_PER_FETCH; ++s) {
+      HIPCHK(launch_es_panel(g.d_e, d_jobs, cap, n, st));
+      HIPCHK(launch_tsqr(TS_VH_TO_Q1, n, tree, d_jobs, 2 * cap, KMAX, st));
+      HIPCHK(launch_core(ACT_INIT, d_jobs + cap, cap, KMAX, st));
+      HIPCHK(launch_es_trunc(g.d_e, d_jobs, cap, st));
+      HIPCHK(launch_es_update(g.d_e, d_jobs, cap, n, st));
+    }
+    HIPCHK(hipMemcpyAsync(g.h_e, g.d_e, sizeof(ExpState) * cap, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    running = false;
+    for (int i = 0; i < count; ++i) running |= g.h_e[i].phase == ES_RUN;
+  }
+  return LRP_OK;
+}
+
+ExpGroup *expsum_group(lrp_ctx *ctx, int n, int count, lrp_status *err) {
+  auto &slot = ctx->expsum_groups[n];
+  if (!slot || slot->cap < count) {
+    slot.reset();
+    std::unique_ptr<ExpGroup> g(new ExpGroup(ctx, n, count));
+    if ((*err = g->init()) != LRP_OK) return nullptr;
+    slot = std::move(g);
+  }
+  *err = LRP_OK;
+  return slot.get();
+}
+
+// Reset slot i's state and both job records for a new problem (host mirror).
+static void reset_state(ExpGroup &g, int i) {
+  ExpState &e = g.h_e[i];
+  std::memset(&e, 0, sizeof(e));
+  e.phase = ES_DONE;
+  e.n = g.n;
+  e.kw = std::min(KMAX, g.n);
+  e.status = LRP_OK;
+  Solve2D &a = g.jobs->host(i), &b = g.jobs->host(g.cap + i);
+  a.active = b.active = ACT_DONE;
+  a.k = b.k = 0;
+  a.nonfinite = b.nonfinite = 0;
+}
+
+lrp_status round_products(lrp_ctx *ctx, int n, int count, RoundJob *jobs, hipStream_t st) {
+  if (count == 0) return LRP_OK;
+  if (n < ES_MIN_N_PLAIN) return LRP_EINVAL;
+  lrp_status err;
+  ExpGroup *gp = expsum_group(ctx, n, count, &err);
+  if (!gp) return err;
+  ExpGroup &g = *gp;
+  for (int i = 0; i < g.cap; ++i) {
+    reset_state(g, i);
+    if (i >= count) continue;
+    ExpState &e = g.h_e[i];
+    const RoundJob &J = jobs[i];
+    e.tot = J.K;
+    e.eps = J.eps;
+    e.pu = J.U;
+    e.pv = J.V;
+    e.ldp = J.ld;
+    e.phase = J.K > 0 ? ES_RUN : ES_DONE;
+  }
+  HIPCHK(hipMemcpyAsync(g.d_e, g.h_e, sizeof(ExpState) * g.cap, hipMemcpyHostToDevice, st));
+  if ((err = g.jobs->upload_all(2 * g.cap, st)) != LRP_OK) return err;
+  if ((err = run_steps(g, count, st)) != LRP_OK) return err;
+  for (int i = 0; i < count; ++i) {
+    const ExpState &e = g.h_e[i];
+    RoundJob &J = jobs[i];
+    J.status = e.phase == ES_RUN ? LRP_EDEVICE : e.status;
+    J.rank = (e.phase == ES_LAST && e.status == LRP_OK) ? e.K : 0;
+    if (J.status == LRP_OK && e.capped) J.status = LRP_ERANKCAP;
+    J.err = e.nrm > 0.0 ? e.drop / e.nrm : 0.0;
+    if (J.rank > J.rmax) {
+      J.status = LRP_ERANKCAP;
+      continue;
+    }
+    if (J.rank == 0) continue;
+    const Solve2D &a = g.jobs->host(i), &b = g.jobs->host(g.cap + i);
+    HIPCHK(hipMemcpy2DAsync(J.Ux, (size_t)J.ldx * 8, a.A, (size_t)a.ldu * 8, (size_t)n * 8,
+                            J.rank, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpy2DAsync(J.Vx, (size_t)J.ldx * 8, b.A, (size_t)b.ldu * 8, (size_t)n * 8,
+                            J.rank, hipMemcpyDeviceToDevice, st));
+  }
+  return LRP_OK;
+}
+
 ExpGroup::ExpGroup(lrp_ctx *c, int n_, int cap_) : ctx(c), n(n_), cap(cap_) {}
 
 ExpGroup::~ExpGroup() {
@@ -133,15 +230,10 @@ extern "C" lrp_status lrp_expsum_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t 
   if (hipSetDevice(ctx->device) != hipSuccess) return LRP_EDEVICE;
   hipStream_t st = (hipStream_t)stream;
   std::lock_guard<std::mutex> lock(ctx->mu);
-  auto &slot = ctx->expsum_groups[(int)n];
-  if (!slot || slot->cap < count) {
-    slot.reset();
-    std::unique_ptr<ExpGroup> g(new ExpGroup(ctx, (int)n, count));
-    lrp_status e = g->init();
-    if (e != LRP_OK) return e;
-    slot = std::move(g);
-  }
-  ExpGroup &g = *slot;
+  lrp_status err;
+  ExpGroup *gp = expsum_group(ctx, (int)n, count, &err);
+  if (!gp) return err;
+  ExpGroup &g = *gp;
   Group2D &J = *g.jobs;
   const int cap = g.cap;
   // the nodes of every problem, before any device work
@@ -160,13 +252,8 @@ extern "C" lrp_status lrp_expsum_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t 
   }
   std::vector<Plan> plans(count);
   for (int i = 0; i < cap; ++i) {
+    reset_state(g, i);
     ExpState &e = g.h_e[i];
-    std::memset(&e, 0, sizeof(e));
-    e.phase = ES_DONE;
-    Solve2D &a = J.host(i), &b = J.host(cap + i);
-    a.active = b.active = ACT_DONE;
-    a.k = b.k = 0;
-    a.nonfinite = b.nonfinite = 0;
     if (i >= count) continue;
     const lrp_problem2d &p = probs[i];
     plans[i] = make_plan(opts, p.eps, (int)n);
@@ -174,7 +261,6 @@ extern "C" lrp_status lrp_expsum_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t 
     double *hn = g.h_nodes + (size_t)i * 2 * ES_MAX_TERMS;
     std::memcpy(hn, nodes[i]->data(), sizeof(double) * R);
     std::memcpy(hn + ES_MAX_TERMS, nodes[i]->data() + R, sizeof(double) * R);
-    e.n = (int)n;
     e.r = p.rank;
     e.R = R;
     e.tot = R * p.rank;
@@ -188,8 +274,7 @@ extern "C" lrp_status lrp_expsum_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t 
   HIPCHK(hipMemcpyAsync(g.d_e, g.h_e, sizeof(ExpState) * cap, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(g.d_nodes, g.h_nodes, (size_t)cap * 2 * ES_MAX_TERMS * 8,
                         hipMemcpyHostToDevice, st));
-  lrp_status err = J.upload_all(2 * cap, st);
-  if (err != LRP_OK) return err;
+  if ((err = J.upload_all(2 * cap, st)) != LRP_OK) return err;
   J.begin_batch();
   phase_mark(ctx, 0, st);
   for (int prec : ALL_PRECS) {
@@ -206,26 +291,7 @@ extern "C" lrp_status lrp_expsum_solve2d_batch(lrp_ctx *ctx, int64_t n, int32_t 
     if (!cols.empty() && (err = J.transform(cols, prec, st)) != LRP_OK) return err;
   }
   phase_mark(ctx, 1, st);
-  // every step appends at least min(ES_CMIN, what is left) columns
-  int max_steps = 0;
-  for (int i = 0; i < count; ++i)
-    max_steps = std::max(max_steps, 1 + ceil_div(g.h_e[i].tot, ES_CMIN));
-  const Tree tree = make_tree((int)n, KMAX);
-  Solve2D *d_jobs = J.dev_solves();
-  bool running = true;
-  for (int done = 0; running && done <= max_steps; done += ES_STEPS_PER_FETCH) {
-    for (int s = 0; s < ES_STEPS_PER_FETCH; ++s) {
-      HIPCHK(launch_es_panel(g.d_e, d_jobs, cap, (int)n, st));
-      HIPCHK(launch_tsqr(TS_VH_TO_Q1, (int)n, tree, d_jobs, 2 * cap, KMAX, st));
-      HIPCHK(launch_core(ACT_INIT, d_jobs + cap, cap, KMAX, st));
-      HIPCHK(launch_es_trunc(g.d_e, d_jobs, cap, st));
-      HIPCHK(launch_es_update(g.d_e, d_jobs, cap, (int)n, st));
-    }
-    HIPCHK(hipMemcpyAsync(g.h_e, g.d_e, sizeof(ExpState) * cap, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    running = false;
-    for (int i = 0; i < count; ++i) running |= g.h_e[i].phase == ES_RUN;
-  }
+  if ((err = run_steps(g, count, st)) != LRP_OK) return err;
   phase_mark(ctx, 2, st);
   std::vector<int> status(count, LRP_OK), rank(count, 0);
   for (int i = 0; i < count; ++i) {

@@ -414,13 +414,20 @@ Tree make_tree(int n, int kmax);
 // (both sides) and core SVD, truncating to a share of the tolerance.
 constexpr int ES_MAX_TERMS = 256;   // exponential-sum terms
 constexpr int ES_CMIN = 8;          // columns every step can append at least
-constexpr int ES_MIN_N = 2 * KMAX;  // smallest grid (K + c <= KMAX rows fit)
+constexpr int ES_MIN_N = 2 * KMAX;  // smallest grid of the exponential sum
+constexpr int ES_MIN_N_PLAIN = 2 * ES_CMIN;   // smallest grid of a plain rounding
 enum : int { ES_DONE = 0, ES_RUN = 1, ES_LAST = 2 };
+// The same steps round any product U V^T of many columns ("plain" mode,
+// pu != nullptr: column j of the product is pu[:, j] pv[:, j]^T), as the
+// sums of low-rank matrices of the Stokes driver need.
 struct ExpState {
   int n, r, R, tot;         // grid, input rank, terms, tot = R r columns
+  int kw;                   // panel width cap min(KMAX, n)
   double eps;               // requested accuracy (half for the step tails)
   const double *lam;        // lambda_k, k = 1..n
   const double *sw, *p;     // sqrt(w_k), p_k, k < R
+  const double *pu, *pv;    // plain mode: the product's factors (n x tot)
+  long ldp;
   // ---- control
   int phase;                // ES_*
   int K;                    // rank of the current factorisation
@@ -432,9 +439,9 @@ struct ExpState {
   double nrm;               // ||sig|| of the last core
   double sig[KMAX];         // singular values of the current factorisation
 };
-// Columns the next step appends: fill the KMAX-column panel.
-__host__ __device__ inline int es_cols(int K, int j0, int tot) {
-  const int room = KMAX - K, left = tot - j0;
+// Columns the next step appends: fill the panel (kw columns).
+__host__ __device__ inline int es_cols(int K, int j0, int tot, int kw) {
+  const int room = kw - K, left = tot - j0;
   return room < left ? room : left;
 }
 // Each launcher covers `cap` solves.  jobs[i] (a side) and jobs[cap + i]
@@ -446,5 +453,29 @@ __host__ __device__ inline int es_cols(int K, int j0, int tot) {
 hipError_t launch_es_panel(ExpState *e, Solve2D *jobs, int cap, int n, hipStream_t st);
 hipError_t launch_es_trunc(ExpState *e, Solve2D *jobs, int cap, hipStream_t st);
 hipError_t launch_es_update(ExpState *e, Solve2D *jobs, int cap, int n, hipStream_t st);
+
+// ---- low-rank Stokes driver (lowrank.hip, host_stokes.cpp)
+// The shift matrices of the discrete gradients (Section 2), applied to the
+// columns of a factor: out[:, c] = alpha Op in[:, c].
+enum : int { SHIFT_G = 0, SHIFT_H = 1, SHIFT_GT = 2, SHIFT_HT = 3 };
+hipError_t launch_shift(int op, int m_out, int cols, const double *in, long ldi, double *out,
+                        long ldo, double alpha, hipStream_t st);
+// dst[:, c] = alpha src[:, c], c < cols
+hipError_t launch_copy_scaled(int rows, int cols, const double *src, long lds, double *dst,
+                              long ldd, double alpha, hipStream_t st);
+// One Frobenius inner product <Xu Xv^T, Yu Yv^T> (rows x rx, rows x ry
+// factors, rx, ry <= KMAX).
+struct LrDot {
+  const double *xu, *xv, *yu, *yv;
+  long ldx, ldy;
+  int rows, rx, ry;
+};
+hipError_t launch_lr_dots(const LrDot *pairs, int npairs, double *out, hipStream_t st);
+// C (K x L) = A^T B (A: rows x K, B: rows x L)
+hipError_t launch_gemm_tn(int rows, int K, int L, const double *A, long lda, const double *B,
+                          long ldb, double *C, long ldc, hipStream_t st);
+// C (rows x L) = A B diag(scale) (A: rows x K, B: K x L; scale null: ones)
+hipError_t launch_gemm_nn(int rows, int K, int L, const double *A, long lda, const double *B,
+                          long ldb, double *C, long ldc, const double *scale, hipStream_t st);
 
 }  // namespace lrp

@@ -68,6 +68,8 @@ def test_null_context_rejected(lib):
     assert lib.lrp_kernel_qr_maxvol(None, 16, 4, P(1), 16, 0.0, P(1), 16, P(1), 4, rows,
                                     ctypes.byref(conv), None) == binding.LRP_EINVAL
     assert lib.lrp_kernel_core_svd(None, 4, P(1), 4, P(1), P(1), P(1), None) == binding.LRP_EINVAL
+    sp = binding.LrpStokes2DProblem()
+    assert lib.lrp_stokes2d(None, ctypes.byref(sp), None) == binding.LRP_EINVAL
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -91,6 +93,9 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", offsetof(lrp_opts, op), offsetof(lrp_opts, seed),
          offsetof(lrp_info, err_est), offsetof(lrp_info, us_phase),
          offsetof(lrp_request, op));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(lrp_stokes2d_problem),
+         offsetof(lrp_stokes2d_problem, eps), offsetof(lrp_stokes2d_problem, p_U),
+         offsetof(lrp_stokes2d_problem, rank_out), offsetof(lrp_stokes2d_problem, true_residual));
   return 0;
 }
 """)
@@ -106,7 +111,10 @@ int main(void) {
             binding.LrpRequest.eps.offset, binding.LrpRequest.Gx.offset,
             binding.LrpOpts.op.offset, binding.LrpOpts.seed.offset,
             binding.LrpInfo.err_est.offset, binding.LrpInfo.us_phase.offset,
-            binding.LrpRequest.op.offset]
+            binding.LrpRequest.op.offset,
+            ctypes.sizeof(binding.LrpStokes2DProblem), binding.LrpStokes2DProblem.eps.offset,
+            binding.LrpStokes2DProblem.p_U.offset, binding.LrpStokes2DProblem.rank_out.offset,
+            binding.LrpStokes2DProblem.true_residual.offset]
     assert got == want
 
 

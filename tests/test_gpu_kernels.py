@@ -151,3 +151,54 @@ def test_core_svd_against_lapack(k, kind):
     assert np.abs(Wk.T @ Wk - np.eye(keep.sum())).max() < 1e-9
     assert np.all(W[:, sig == 0.0] == 0.0)
     assert np.linalg.norm((W * sig) @ Z.T - M) <= 1e-13 * np.linalg.norm(M) * k
+
+
+def optimal_rank(X, eps):
+    s = np.linalg.svd(X, compute_uv=False)
+    tail = np.sqrt(np.cumsum((s * s)[::-1]))[::-1]
+    return int(np.sum(tail > eps * np.linalg.norm(s)))
+
+
+def smooth_terms(n, terms, r, seed):
+    """Sums of separable smooth functions on the grid (decaying spectra)."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(1, n + 1) / (n + 1)
+    Us, Vs = [], []
+    for _ in range(terms):
+        a, b = rng.uniform(0.1, 0.9, (2, r))
+        w = rng.uniform(0.05, 0.3, r)
+        Us.append(np.exp(-((x[:, None] - a[None, :]) / w) ** 2) * rng.standard_normal(r))
+        Vs.append(np.exp(-((x[:, None] - b[None, :]) / w) ** 2))
+    return np.hstack(Us), np.hstack(Vs)
+
+
+@pytest.mark.parametrize("case", ["exact30", "cancel", "many", "small", "zero"])
+def test_lowrank_round_against_svd(case):
+    n = 300
+    rng = np.random.default_rng(7)
+    if case == "exact30":
+        U, V, eps = rng.standard_normal((n, 30)), rng.standard_normal((n, 30)), 1e-12
+    elif case == "cancel":
+        # X = W + E - E: the big rank-40 parts cancel, rank 10 remains
+        W1, W2 = rng.standard_normal((2, n, 10))
+        E1, E2 = rng.standard_normal((2, n, 40)) * 1e3
+        U, V, eps = np.hstack([W1, E1, -E1]), np.hstack([W2, E2, E2]), 1e-8
+    elif case == "many":
+        U, V = smooth_terms(n, 15, 40, 3)
+        eps = 1e-9
+    elif case == "small":
+        U, V, eps = rng.standard_normal((n, 3)), rng.standard_normal((n, 3)), 1e-10
+    else:
+        U, V, eps = np.zeros((n, 5)), np.zeros((n, 5)), 1e-8
+    X = U @ V.T
+    log("round", case, U.shape[1], "optimal rank", optimal_rank(X, eps) if case != "zero" else 0)
+    Ux, Vx = ctx().lowrank_round(dev(U), dev(V), eps)
+    Ux, Vx = host(Ux), host(Vx)
+    if case == "zero":
+        assert Ux.shape[1] == 0
+        return
+    err = np.linalg.norm(Ux @ Vx.T - X) / np.linalg.norm(X)
+    log("  rank", Ux.shape[1], "err", err)
+    assert err <= 2 * eps
+    assert Ux.shape[1] <= optimal_rank(X, eps) + 3
+    assert np.abs(Vx.T @ Vx - np.eye(Vx.shape[1])).max() < 1e-12
