@@ -240,6 +240,28 @@ def stokes_table(ctx, workers):
     return {"problem": "Section 6 eq. ansin2d on n x n pressure cells", "rows": rows}
 
 
+# HBM bytes the cross phase (a3-a6: entries, TSQR, maxvol, core, factors,
+# change) moves per 1024-solve call of the default workload, summed over its
+# kernels from the FETCH_SIZE / WRITE_SIZE counters of
+# profiles/kernel_traffic_n4096_b1024.md (2 x FETCH + WRITE, calibrated by a
+# device copy)
+CROSS_BYTES_PER_CALL = 120242.0 * 2 ** 20
+
+
+def cross_phase(res, batch):
+    """Device time of the cross sweeps of one call (HIP events around the
+    phase), per sweep of its longest solve, and the bandwidth it implies."""
+    sweeps = [r[2]["sweeps"] for r in res]
+    us = res[0][2]["us_phase"]["cross"]
+    rec = {"us_per_call": us, "sweeps_mean": sum(sweeps) / len(sweeps),
+           "sweeps_max": max(sweeps), "us_per_sweep": us / max(1, max(sweeps)),
+           "solves": batch}
+    if batch == 1024:
+        rec["bytes_per_call_counters"] = CROSS_BYTES_PER_CALL
+        rec["GB_per_s"] = CROSS_BYTES_PER_CALL / (us * 1e-6) / 1e9 if us > 0 else None
+    return rec
+
+
 def timed_steps(ctx, problems, prec, steps, warmup):
     import torch
     # the argument array and output buffers are prepared once; every step
@@ -434,6 +456,7 @@ def main():
                      "max_rel_err_int8": max(errs["int8"]),
                      "checked": len(hostrhs)},
         "roofline": roofline,
+        "cross_phase": cross_phase(out["auto"]["res"], B),
     }
 
     if args.batch_sweep:

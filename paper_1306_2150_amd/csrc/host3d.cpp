@@ -116,8 +116,13 @@ void Group3D::setup_slot(int i, const double *const U[3], long ld, const int r[3
   // slot's own (filled when the fibers are built).
   const double ed = eps / std::sqrt(3.0);
   for (int d = 0; d < 3; ++d) {
+    // the first width the device gives a mode cross when it (re)starts it on
+    // new fibers (rank + kick, k_fiber_cols): the host mirror must agree, as
+    // the launches take their rank bucket from it
+    Plan pm = plan;
+    pm.k0 = r[d] + plan.kick;
     inner_->setup_slot(3 * i + d, nullptr, nullptr, 0, r[d], ed, nullptr, nullptr, 0,
-                       KMAX, plan);
+                       KMAX, pm);
     Solve2D &m = inner_->host(3 * i + d);
     m.lam_c = s.lamc[d];
     m.lq_c = (plan.op == LRP_OP_STOKES) ? s.lqc[d] : nullptr;
