@@ -30,7 +30,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 template <int KM>
 __global__ __launch_bounds__(NTHR) void k_factors(Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
-  if (s.active != ACT_SWEEP) return;
+  if (s.active != ACT_SWEEP || rank_bucket(s.k) != KM) return;
   __shared__ double M[KMAX * KMAX];   // [j][c]
   const int kk = s.k, z = blockIdx.z;
   const double *Qz = z ? s.Q1 : s.Q0;
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(NTHR) void k_factors(Solve2D *S) {
 template <int KM>
 __global__ __launch_bounds__(NTHR) void k_change_M(int nbm, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
-  if (s.active != ACT_SWEEP || s.kp == 0) return;
+  if (s.active != ACT_SWEEP || s.kp == 0 || rank_bucket(s.k) != KM) return;
   constexpr int NB = KM / 16;
   __shared__ double red[KMAX * KMAX];
   const int kk = s.k, kq = s.kp, m = s.m;
@@ -154,9 +154,9 @@ __global__ __launch_bounds__(NTHR) void k_change_M(int nbm, Solve2D *S) {
 // Mc = the sum of the nbm block partials, in block order; one thread per
 // entry (grid x covers the kp x k entries, 64 per workgroup), its loads
 // independent so that many are in flight.
-__global__ __launch_bounds__(64) void k_change_reduce(int nbm, Solve2D *S) {
+__global__ __launch_bounds__(64) void k_change_reduce(int nbm, int km, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
-  if (s.active != ACT_SWEEP || s.kp == 0) return;
+  if (s.active != ACT_SWEEP || s.kp == 0 || rank_bucket(s.k) != km) return;
   const int kk = s.k, kq = s.kp;
   const int o = blockIdx.x * 64 + threadIdx.x;
   if (o >= kq * kk) return;
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(64) void k_change_reduce(int nbm, Solve2D *S) {
 template <int KM>
 __global__ __launch_bounds__(NTHR) void k_change_norms(Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
-  if (s.active != ACT_SWEEP || s.kp == 0) return;
+  if (s.active != ACT_SWEEP || s.kp == 0 || rank_bucket(s.k) != KM) return;
   __shared__ double M[KMAX * KMAX];
   __shared__ double sp2[KMAX];
   __shared__ double red[2][4];
@@ -520,7 +520,8 @@ hipError_t launch_change(int n, int m, Solve2D *s, int nsolves, int kmax,
                          hipStream_t st) {
   const int nbm = change_blocks(m);
   LRP_BUCKET(k_change_M, dim3(nbm, nsolves), nbm, s);
-  hipLaunchKernelGGL(k_change_reduce, dim3(KMAX * KMAX / 64, nsolves), dim3(64), 0, st, nbm, s);
+  hipLaunchKernelGGL(k_change_reduce, dim3(KMAX * KMAX / 64, nsolves), dim3(64), 0, st, nbm,
+                     rank_bucket(kmax), s);
   dim3 g(ceil_div(max(n, m), NTHR), nsolves);
   LRP_BUCKET(k_change_norms, g, s);
   return hipGetLastError();

@@ -240,6 +240,15 @@ __device__ __forceinline__ double bcast_f64(double v, int src) {
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// Rank bucket of a cross of k columns: the sweep kernels are instantiated for
+// k <= 16, 32, 48 and 64.  A sweep launches every bucket its slots occupy,
+// and a sweep-phase kernel of bucket KM takes only the slots of that bucket,
+// so a slot of 32 columns does not run at the register size and occupancy of
+// a neighbour that grew to 40.
+__host__ __device__ inline int rank_bucket(int k) {
+  return k <= 16 ? 16 : (k <= 32 ? 32 : (k <= 48 ? 48 : 64));
+}
+
 // The operator's eigenvalue D_ij from the row-side values (a = lam_r[i],
 // b = lq_r[i]) and the column-side values (c = lam_c[j], d = lq_c[j]);
 // `prod` selects the product form of the Stokes operator (wave-uniform).
@@ -363,6 +372,11 @@ hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, Solve2
 
 // Row counts: calls on the column side (Xh[:, J], Q0, A) cover the n rows,
 // calls on the row side (Xh[I, :]^T, Q1, B, Vh) the m columns.
+// kmax selects the kernels' rank bucket (rank_bucket(kmax)).  In the other
+// phases a launch covers every slot with k <= its bucket; in the sweep phase
+// (TS_C_TO_Q0 / TS_C_TO_Q1, MV_Q0_TO_I / MV_Q1_TO_JN, launch_core with
+// ACT_SWEEP, launch_factors, launch_change) only the slots whose own bucket
+// it is, so a sweep launches each bucket its slots occupy.
 // TSQR inputs/outputs.  TS_C_TO_Q0 / TS_C_TO_Q1 evaluate the cross columns
 // Xh[:, J] / rows Xh[I, :]^T in the leaf kernel itself and orthonormalise
 // them.  TS_CORE factors the panel in C with `rows` rows and keeps only R
@@ -379,7 +393,6 @@ hipError_t launch_maxvol(int which, int rows, const Tree &tr, Solve2D *s,
 hipError_t launch_maxvol_rounds(int which, int rows, const Tree &tr, Solve2D *s,
                                 int nsolves, int kmax, int rounds, hipStream_t st);
 
-// kmax: the largest k of the launch's solves (selects the LDS bucket)
 hipError_t launch_core(int phase, Solve2D *s, int nsolves, int kmax, hipStream_t st);
 hipError_t launch_factors(int n, int m, Solve2D *s, int nsolves, int kmax,
                           hipStream_t st);

@@ -41,6 +41,12 @@ __device__ inline int mv_phase(int which) {
   return which == MV_Q1_TO_J ? ACT_INIT : ACT_SWEEP;
 }
 
+// A sweep-phase launch of rank bucket KM takes only the slots of that bucket.
+__device__ inline bool mv_skip(const Solve2D &s, int which, int km) {
+  return s.active != mv_phase(which) ||
+         (mv_phase(which) == ACT_SWEEP && rank_bucket(s.k) != km);
+}
+
 // A sweep that kept the cross rank starts its maxvol from the rows the same
 // maxvol chose in the previous sweep (the bases move little between sweeps,
 // so those rows are nearly maximal-volume already); the tournament only
@@ -60,7 +66,7 @@ template <int NS>
 __global__ __launch_bounds__(NTHR) void k_mv_leaf(int which, int n, Tree tr,
                                                  Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
-  if (s.active != mv_phase(which)) return;
+  if (mv_skip(s, which, 4 * NS)) return;
   __shared__ double lbuf[2 * PANEL_M];
   __shared__ int shp[2];
   __shared__ int piv[KMAX];
@@ -83,7 +89,7 @@ template <int NS>
 __global__ __launch_bounds__(NTHR) void k_mv_node(int which, int n, int lev,
                                                  Tree tr, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
-  if (s.active != mv_phase(which) || mv_warm(s, which)) return;
+  if (mv_skip(s, which, 4 * NS) || mv_warm(s, which)) return;
   __shared__ double lbuf[2 * PANEL_M];
   __shared__ int shp[2];
   __shared__ int piv[KMAX];
@@ -139,7 +145,7 @@ template <int KM>
 __global__ __launch_bounds__(NTHR) void k_mv_inv(int which, int n, int force,
                                                 Solve2D *S) {
   Solve2D &s = S[blockIdx.x];
-  if (s.active != mv_phase(which)) return;
+  if (mv_skip(s, which, KM)) return;
   if (!force && s.mv_done) return;
   constexpr int W2 = 2 * KM;                   // augmented row length
   __shared__ double a[KM][W2 + 1];
@@ -235,7 +241,7 @@ __device__ __forceinline__ void row_max16_f32(float (&v)[16]) {
 template <int KM>
 __global__ __launch_bounds__(NTHR) void k_mv_check(int which, int n, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
-  if (s.active != mv_phase(which) || s.mv_done) return;
+  if (mv_skip(s, which, KM) || s.mv_done) return;
   constexpr int NC = KM / 16;                   // 16-column blocks of B
   constexpr int NK = KM / 4;                    // K steps
   __shared__ double rowmax[NTHR];
@@ -364,7 +370,7 @@ template <int KM>
 __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
                                                  Solve2D *S) {
   Solve2D &s = S[blockIdx.x];
-  if (s.active != mv_phase(which) || s.mv_done) return;
+  if (mv_skip(s, which, KM) || s.mv_done) return;
   extern __shared__ __align__(16) unsigned char smem[];
   const int kk = s.k;
   if (kk > KM) return;                              // the bucket covers every k

@@ -120,6 +120,7 @@ __global__ __launch_bounds__(NTHR) void k_tsqr_leaf(int which, int n, Tree tr,
                                                    Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (s.active != ts_phase(which)) return;
+  if (ts_phase(which) == ACT_SWEEP && rank_bucket(s.k) != 4 * NS) return;
   __shared__ double vbuf[2 * PANEL_M];
   __shared__ double taus[KMAX];
   __shared__ double qs[CROSS ? KMAX * 4 * NS : 1];
@@ -163,6 +164,7 @@ __global__ __launch_bounds__(NTHR) void k_tsqr_node(int which, int lev, Tree tr,
                                                    Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (s.active != ts_phase(which)) return;
+  if (ts_phase(which) == ACT_SWEEP && rank_bucket(s.k) != 4 * NS) return;
   __shared__ double vbuf[2 * PANEL_M];
   __shared__ double taus[KMAX];
   const int kk = s.k;
@@ -215,6 +217,7 @@ __global__ __launch_bounds__(NTHR) void k_tsqr_node_apply(int which, int lev,
                                                          Tree tr, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (s.active != ts_phase(which)) return;
+  if (ts_phase(which) == ACT_SWEEP && rank_bucket(s.k) != 4 * NS) return;
   const int kk = s.k;
   const int t = blockIdx.x;
   const int c0 = t * tr.fan;
@@ -259,6 +262,7 @@ __global__ __launch_bounds__(NTHR) void k_tsqr_leaf_apply(int which, int n,
                                                          Tree tr, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (s.active != ts_phase(which)) return;
+  if (ts_phase(which) == ACT_SWEEP && rank_bucket(s.k) != 4 * NS) return;
   const int kk = s.k;
   const int b = blockIdx.x;
   const int r0 = b * PANEL_M;
