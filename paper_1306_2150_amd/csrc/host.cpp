@@ -524,7 +524,7 @@ lrp_status Group2D::forward(const std::vector<int> &slots, hipStream_t st) {
 lrp_status Group2D::step(hipStream_t st) {
   int kin = 0, kmax = 0, rmax = 0;
   bool any_init = false, any_sweep = false;
-  bool buckets[4] = {false, false, false, false};   // rank buckets 16, 32, 48, 64
+  unsigned bmask = 0;   // rank buckets the sweep's slots occupy
   int hi = 0;   // launches cover slots [0, hi): the live ones
   for (int i = 0; i < cap_; ++i) {
     const Solve2D &s = h_s_[i];
@@ -534,12 +534,12 @@ lrp_status Group2D::step(hipStream_t st) {
       kin = std::max(kin, s.k);
       kmax = std::max(kmax, s.k0);
       rmax = std::max(rmax, s.r);
-      buckets[rank_bucket(s.k0) / 16 - 1] = true;   // k_init_J sets k = k0
+      bmask |= bucket_bit(s.k0);   // k_init_J sets k = k0
     } else if (s.active == ACT_SWEEP) {
       any_sweep = true;
       kmax = std::max(kmax, s.k);
       rmax = std::max(rmax, s.r);
-      buckets[rank_bucket(s.k) / 16 - 1] = true;
+      bmask |= bucket_bit(s.k);
     }
   }
   // trees depend on the shape only, so a slot's arithmetic does not depend
@@ -551,20 +551,21 @@ lrp_status Group2D::step(hipStream_t st) {
     HIPCHK(launch_init_J(d_s_, hi, st));
   }
   if (!any_init && !any_sweep) return LRP_OK;
-  // k of a slot only grows at the end of a sweep, so the buckets hold for
-  // this sweep; every step runs once per occupied bucket, on its slots
+  // k of a slot only grows at the end of a sweep, so kmax and the buckets
+  // hold for this sweep: the kernels with many workgroups per slot run once
+  // per occupied bucket, on its slots, the rest once at the largest
   const int km = std::max(kmax, 1);
   const int kev = std::max(km, rmax);
-  int kbs[4], nkb = 0;
-  for (int b = 0; b < 4; ++b)
-    if (buckets[b]) kbs[nkb++] = 16 * (b + 1);
-  for (int b = 0; b < nkb; ++b) HIPCHK(launch_tsqr(TS_C_TO_Q0, n_, tn, d_s_, hi, kbs[b], st));
-  for (int b = 0; b < nkb; ++b) HIPCHK(launch_maxvol(MV_Q0_TO_I, n_, tn, d_s_, hi, kbs[b], st));
-  for (int b = 0; b < nkb; ++b) HIPCHK(launch_tsqr(TS_C_TO_Q1, m_, tm, d_s_, hi, kbs[b], st));
-  for (int b = 0; b < nkb; ++b) HIPCHK(launch_maxvol(MV_Q1_TO_JN, m_, tm, d_s_, hi, kbs[b], st));
-  for (int b = 0; b < nkb; ++b) HIPCHK(launch_core(ACT_SWEEP, d_s_, hi, kbs[b], st));
-  for (int b = 0; b < nkb; ++b) HIPCHK(launch_factors(n_, m_, d_s_, hi, kbs[b], st));
-  for (int b = 0; b < nkb; ++b) HIPCHK(launch_change(n_, m_, d_s_, hi, kbs[b], st));
+  HIPCHK(launch_tsqr(TS_C_TO_Q0, n_, tn, d_s_, hi, km, st, bmask));
+  HIPCHK(launch_maxvol(MV_Q0_TO_I, n_, tn, d_s_, hi, km, st, bmask));
+  HIPCHK(launch_tsqr(TS_C_TO_Q1, m_, tm, d_s_, hi, km, st, bmask));
+  HIPCHK(launch_maxvol(MV_Q1_TO_JN, m_, tm, d_s_, hi, km, st, bmask));
+  HIPCHK(launch_core(ACT_SWEEP, d_s_, hi, km, st));
+  for (int kb = 16; kb <= 64; kb += 16) {
+    if (!(bmask & bucket_bit(kb))) continue;
+    HIPCHK(launch_factors(n_, m_, d_s_, hi, kb, st));
+    HIPCHK(launch_change(n_, m_, d_s_, hi, kb, st));
+  }
   HIPCHK(launch_decide(n_, m_, d_s_, hi, kev, st));
   return LRP_OK;
 }

@@ -248,6 +248,12 @@ __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; 
 __host__ __device__ inline int rank_bucket(int k) {
   return k <= 16 ? 16 : (k <= 32 ? 32 : (k <= 48 ? 48 : 64));
 }
+// Bit of the bucket of k in a mask of occupied buckets, and the largest
+// bucket of a mask.
+__host__ __device__ inline unsigned bucket_bit(int k) { return 1u << (rank_bucket(k) / 16 - 1); }
+__host__ __device__ inline int top_bucket(unsigned mask) {
+  return (mask & 8u) ? 64 : (mask & 4u) ? 48 : (mask & 2u) ? 32 : 16;
+}
 
 // The operator's eigenvalue D_ij from the row-side values (a = lam_r[i],
 // b = lq_r[i]) and the column-side values (c = lam_c[j], d = lq_c[j]);
@@ -372,26 +378,30 @@ hipError_t launch_dst_i8(int n, const void *rec, DstCol *cols, int ncols, Solve2
 
 // Row counts: calls on the column side (Xh[:, J], Q0, A) cover the n rows,
 // calls on the row side (Xh[I, :]^T, Q1, B, Vh) the m columns.
-// kmax selects the kernels' rank bucket (rank_bucket(kmax)).  In the other
-// phases a launch covers every slot with k <= its bucket; in the sweep phase
-// (TS_C_TO_Q0 / TS_C_TO_Q1, MV_Q0_TO_I / MV_Q1_TO_JN, launch_core with
-// ACT_SWEEP, launch_factors, launch_change) only the slots whose own bucket
-// it is, so a sweep launches each bucket its slots occupy.
+// kmax selects the kernels' rank bucket (rank_bucket(kmax)), and a launch
+// covers every slot with k <= its bucket -- except, in the sweep phase, the
+// kernels with many workgroups per slot (the TSQR and maxvol leaves, the
+// maxvol check, the factors, the change): those take only the slots of their
+// own bucket.  Sweep launches therefore pass the mask of occupied buckets
+// (bmask, bucket_bit): the leaf-level kernels run once per bucket in it, the
+// few-workgroup ones (tree nodes, maxvol inverse and swaps, core) once at
+// its largest bucket.  bmask 0: the bucket of kmax alone.
 // TSQR inputs/outputs.  TS_C_TO_Q0 / TS_C_TO_Q1 evaluate the cross columns
 // Xh[:, J] / rows Xh[I, :]^T in the leaf kernel itself and orthonormalise
 // them.  TS_CORE factors the panel in C with `rows` rows and keeps only R
 // (in Rfin); it acts on slots in the ACT_CORE phase.
 enum : int { TS_C_TO_Q0 = 0, TS_C_TO_Q1 = 1, TS_VH_TO_Q1 = 2, TS_CORE = 3 };
 hipError_t launch_tsqr(int which, int rows, const Tree &tr, Solve2D *s,
-                       int nsolves, int kmax, hipStream_t st);
+                       int nsolves, int kmax, hipStream_t st, unsigned bmask = 0);
 
 enum : int { MV_Q0_TO_I = 0, MV_Q1_TO_JN = 1, MV_Q1_TO_J = 2 };
 hipError_t launch_maxvol(int which, int rows, const Tree &tr, Solve2D *s,
-                         int nsolves, int kmax, hipStream_t st);
+                         int nsolves, int kmax, hipStream_t st, unsigned bmask = 0);
 // more check/swap rounds of a maxvol that launch_maxvol started (its rows
 // and inverse are current); rounds of a converged maxvol do nothing
 hipError_t launch_maxvol_rounds(int which, int rows, const Tree &tr, Solve2D *s,
-                                int nsolves, int kmax, int rounds, hipStream_t st);
+                                int nsolves, int kmax, int rounds, hipStream_t st,
+                                unsigned bmask = 0);
 
 hipError_t launch_core(int phase, Solve2D *s, int nsolves, int kmax, hipStream_t st);
 hipError_t launch_factors(int n, int m, Solve2D *s, int nsolves, int kmax,

@@ -41,7 +41,8 @@ __device__ inline int mv_phase(int which) {
   return which == MV_Q1_TO_J ? ACT_INIT : ACT_SWEEP;
 }
 
-// A sweep-phase launch of rank bucket KM takes only the slots of that bucket.
+// A sweep-phase launch of the tournament leaves or the check (many
+// workgroups per slot) of rank bucket km takes only the slots of that bucket.
 __device__ inline bool mv_skip(const Solve2D &s, int which, int km) {
   return s.active != mv_phase(which) ||
          (mv_phase(which) == ACT_SWEEP && rank_bucket(s.k) != km);
@@ -89,7 +90,7 @@ template <int NS>
 __global__ __launch_bounds__(NTHR) void k_mv_node(int which, int n, int lev,
                                                  Tree tr, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
-  if (mv_skip(s, which, 4 * NS) || mv_warm(s, which)) return;
+  if (s.active != mv_phase(which) || mv_warm(s, which)) return;
   __shared__ double lbuf[2 * PANEL_M];
   __shared__ int shp[2];
   __shared__ int piv[KMAX];
@@ -145,7 +146,7 @@ template <int KM>
 __global__ __launch_bounds__(NTHR) void k_mv_inv(int which, int n, int force,
                                                 Solve2D *S) {
   Solve2D &s = S[blockIdx.x];
-  if (mv_skip(s, which, KM)) return;
+  if (s.active != mv_phase(which)) return;
   if (!force && s.mv_done) return;
   constexpr int W2 = 2 * KM;                   // augmented row length
   __shared__ double a[KM][W2 + 1];
@@ -370,7 +371,7 @@ template <int KM>
 __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
                                                  Solve2D *S) {
   Solve2D &s = S[blockIdx.x];
-  if (mv_skip(s, which, KM) || s.mv_done) return;
+  if (s.active != mv_phase(which) || s.mv_done) return;
   extern __shared__ __align__(16) unsigned char smem[];
   const int kk = s.k;
   if (kk > KM) return;                              // the bucket covers every k
@@ -565,14 +566,15 @@ __global__ __launch_bounds__(NTHR) void k_mv_swap(int which, int n, int nb0,
 }
 
 template <int NS>
-hipError_t run_tournament(int which, int n, const Tree &tr, Solve2D *s, int ns,
-                          hipStream_t st) {
-  hipLaunchKernelGGL((k_mv_leaf<NS>), dim3(tr.nb[0], ns), dim3(NTHR), 0, st,
-                     which, n, tr, s);
+void run_mv_leaf(int which, int n, const Tree &tr, Solve2D *s, int ns, hipStream_t st) {
+  hipLaunchKernelGGL((k_mv_leaf<NS>), dim3(tr.nb[0], ns), dim3(NTHR), 0, st, which, n, tr, s);
+}
+
+template <int NS>
+void run_mv_nodes(int which, int n, const Tree &tr, Solve2D *s, int ns, hipStream_t st) {
   for (int l = 1; l < tr.nlev; ++l)
     hipLaunchKernelGGL((k_mv_node<NS>), dim3(tr.nb[l], ns), dim3(NTHR), 0, st,
                        which, n, l, tr, s);
-  return hipGetLastError();
 }
 
 template <int KM>
@@ -584,14 +586,26 @@ void run_check(int which, int n, const Tree &tr, Solve2D *s, int ns,
 
 }  // namespace
 
+// The tournament leaves and the checks run once per bucket of the mask, on
+// its slots; the tournament nodes, the inverse and the swap loops (a few
+// workgroups or one per slot) once at the largest bucket, on every slot.
 hipError_t launch_maxvol(int which, int rows, const Tree &tr, Solve2D *s,
-                         int nsolves, int kmax, hipStream_t st) {
+                         int nsolves, int kmax, hipStream_t st, unsigned bmask) {
   const int n = rows;
-  hipError_t e;
-  if (kmax <= 16) e = run_tournament<4>(which, n, tr, s, nsolves, st);
-  else if (kmax <= 32) e = run_tournament<8>(which, n, tr, s, nsolves, st);
-  else if (kmax <= 48) e = run_tournament<12>(which, n, tr, s, nsolves, st);
-  else e = run_tournament<16>(which, n, tr, s, nsolves, st);
+  if (!bmask) bmask = bucket_bit(kmax);
+  const int ktop = top_bucket(bmask);
+  for (int kb = 16; kb <= 64; kb += 16) {
+    if (!(bmask & bucket_bit(kb))) continue;
+    if (kb == 16) run_mv_leaf<4>(which, n, tr, s, nsolves, st);
+    else if (kb == 32) run_mv_leaf<8>(which, n, tr, s, nsolves, st);
+    else if (kb == 48) run_mv_leaf<12>(which, n, tr, s, nsolves, st);
+    else run_mv_leaf<16>(which, n, tr, s, nsolves, st);
+  }
+  if (ktop == 16) run_mv_nodes<4>(which, n, tr, s, nsolves, st);
+  else if (ktop == 32) run_mv_nodes<8>(which, n, tr, s, nsolves, st);
+  else if (ktop == 48) run_mv_nodes<12>(which, n, tr, s, nsolves, st);
+  else run_mv_nodes<16>(which, n, tr, s, nsolves, st);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   static bool attr = false;
   if (!attr) {
@@ -607,28 +621,33 @@ hipError_t launch_maxvol(int which, int rows, const Tree &tr, Solve2D *s,
   }
   // one explicit inverse of the tournament's rows; the swap rounds keep it
   // current with the rank-1 updates of their swaps
-  if (kmax <= 16) hipLaunchKernelGGL(k_mv_inv<16>, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
-  else if (kmax <= 32) hipLaunchKernelGGL(k_mv_inv<32>, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
-  else if (kmax <= 48) hipLaunchKernelGGL(k_mv_inv<48>, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
+  if (ktop == 16) hipLaunchKernelGGL(k_mv_inv<16>, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
+  else if (ktop == 32) hipLaunchKernelGGL(k_mv_inv<32>, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
+  else if (ktop == 48) hipLaunchKernelGGL(k_mv_inv<48>, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
   else hipLaunchKernelGGL(k_mv_inv<64>, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);
-  return launch_maxvol_rounds(which, rows, tr, s, nsolves, kmax, MV_ROUNDS, st);
+  return launch_maxvol_rounds(which, rows, tr, s, nsolves, kmax, MV_ROUNDS, st, bmask);
 }
 
 hipError_t launch_maxvol_rounds(int which, int rows, const Tree &tr, Solve2D *s, int nsolves,
-                                int kmax, int rounds, hipStream_t st) {
+                                int kmax, int rounds, hipStream_t st, unsigned bmask) {
   const int n = rows;
+  if (!bmask) bmask = bucket_bit(kmax);
+  const int ktop = top_bucket(bmask);
   for (int round = 0; round < rounds; ++round) {
-    if (kmax <= 16) run_check<16>(which, n, tr, s, nsolves, st);
-    else if (kmax <= 32) run_check<32>(which, n, tr, s, nsolves, st);
-    else if (kmax <= 48) run_check<48>(which, n, tr, s, nsolves, st);
-    else run_check<64>(which, n, tr, s, nsolves, st);
-    if (kmax <= 16)
+    for (int kb = 16; kb <= 64; kb += 16) {
+      if (!(bmask & bucket_bit(kb))) continue;
+      if (kb == 16) run_check<16>(which, n, tr, s, nsolves, st);
+      else if (kb == 32) run_check<32>(which, n, tr, s, nsolves, st);
+      else if (kb == 48) run_check<48>(which, n, tr, s, nsolves, st);
+      else run_check<64>(which, n, tr, s, nsolves, st);
+    }
+    if (ktop == 16)
       hipLaunchKernelGGL(k_mv_swap<16>, dim3(nsolves), dim3(NTHR), mv_swap_lds(16), st, which,
                          n, tr.nb[0], s);
-    else if (kmax <= 32)
+    else if (ktop == 32)
       hipLaunchKernelGGL(k_mv_swap<32>, dim3(nsolves), dim3(NTHR), mv_swap_lds(32), st, which,
                          n, tr.nb[0], s);
-    else if (kmax <= 48)
+    else if (ktop == 48)
       hipLaunchKernelGGL(k_mv_swap<48>, dim3(nsolves), dim3(NTHR), mv_swap_lds(48), st, which,
                          n, tr.nb[0], s);
     else

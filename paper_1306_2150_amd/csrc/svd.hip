@@ -47,7 +47,6 @@ __global__ __launch_bounds__(core_threads<KM>()) void k_core(int phase, Solve2D 
   constexpr int NW = NT / 64;     // waves
   Solve2D &s = S[blockIdx.x];
   if (s.active != phase) return;
-  if (phase == ACT_SWEEP && rank_bucket(s.k) != KM) return;   // launched per bucket
   const bool plain = phase == ACT_CORE;
   __shared__ double K[KM * LD];   // column c at K[c*LD + i]
   __shared__ double V[KM * LD];

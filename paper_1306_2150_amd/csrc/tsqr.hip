@@ -164,7 +164,6 @@ __global__ __launch_bounds__(NTHR) void k_tsqr_node(int which, int lev, Tree tr,
                                                    Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (s.active != ts_phase(which)) return;
-  if (ts_phase(which) == ACT_SWEEP && rank_bucket(s.k) != 4 * NS) return;
   __shared__ double vbuf[2 * PANEL_M];
   __shared__ double taus[KMAX];
   const int kk = s.k;
@@ -217,7 +216,6 @@ __global__ __launch_bounds__(NTHR) void k_tsqr_node_apply(int which, int lev,
                                                          Tree tr, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (s.active != ts_phase(which)) return;
-  if (ts_phase(which) == ACT_SWEEP && rank_bucket(s.k) != 4 * NS) return;
   const int kk = s.k;
   const int t = blockIdx.x;
   const int c0 = t * tr.fan;
@@ -292,25 +290,30 @@ __global__ __launch_bounds__(NTHR) void k_tsqr_leaf_apply(int which, int n,
 }
 
 template <int NS>
-hipError_t run_tsqr(int which, int n, const Tree &tr, Solve2D *s, int ns,
-                    hipStream_t st) {
-  dim3 blk(NTHR);
+void run_leaf(int which, int n, const Tree &tr, Solve2D *s, int ns, hipStream_t st) {
   if (which == TS_C_TO_Q0 || which == TS_C_TO_Q1)
-    hipLaunchKernelGGL((k_tsqr_leaf<NS, true>), dim3(tr.nb[0], ns), blk, 0, st,
+    hipLaunchKernelGGL((k_tsqr_leaf<NS, true>), dim3(tr.nb[0], ns), dim3(NTHR), 0, st,
                        which, n, tr, s);
   else
-    hipLaunchKernelGGL((k_tsqr_leaf<NS, false>), dim3(tr.nb[0], ns), blk, 0, st,
+    hipLaunchKernelGGL((k_tsqr_leaf<NS, false>), dim3(tr.nb[0], ns), dim3(NTHR), 0, st,
                        which, n, tr, s);
+}
+
+template <int NS>
+void run_nodes(int which, const Tree &tr, Solve2D *s, int ns, hipStream_t st) {
   for (int l = 1; l < tr.nlev; ++l)
-    hipLaunchKernelGGL((k_tsqr_node<NS>), dim3(tr.nb[l], ns), blk, 0, st, which, l,
+    hipLaunchKernelGGL((k_tsqr_node<NS>), dim3(tr.nb[l], ns), dim3(NTHR), 0, st, which, l,
                        tr, s);
-  if (which == TS_CORE) return hipGetLastError();   // R only
+  if (which == TS_CORE) return;   // R only
   for (int l = tr.nlev - 1; l >= 1; --l)
-    hipLaunchKernelGGL((k_tsqr_node_apply<NS>), dim3(tr.nb[l], ns), blk, 0, st,
+    hipLaunchKernelGGL((k_tsqr_node_apply<NS>), dim3(tr.nb[l], ns), dim3(NTHR), 0, st,
                        which, l, tr, s);
-  hipLaunchKernelGGL((k_tsqr_leaf_apply<NS>), dim3(tr.nb[0], ns), blk, 0, st,
+}
+
+template <int NS>
+void run_leaf_apply(int which, int n, const Tree &tr, Solve2D *s, int ns, hipStream_t st) {
+  hipLaunchKernelGGL((k_tsqr_leaf_apply<NS>), dim3(tr.nb[0], ns), dim3(NTHR), 0, st,
                      which, n, tr, s);
-  return hipGetLastError();
 }
 
 }  // namespace
@@ -330,13 +333,34 @@ Tree make_tree(int n, int kmax) {
   return t;
 }
 
+// The leaf kernels (16 workgroups per slot at n = 4096) run once per bucket
+// of the mask, each on its own slots; the tree nodes (a few workgroups per
+// slot, latency-bound) once at the largest bucket, on every slot.
 hipError_t launch_tsqr(int which, int rows, const Tree &tr, Solve2D *s,
-                       int nsolves, int kmax, hipStream_t st) {
+                       int nsolves, int kmax, hipStream_t st, unsigned bmask) {
   const int n = rows;
-  if (kmax <= 16) return run_tsqr<4>(which, n, tr, s, nsolves, st);
-  if (kmax <= 32) return run_tsqr<8>(which, n, tr, s, nsolves, st);
-  if (kmax <= 48) return run_tsqr<12>(which, n, tr, s, nsolves, st);
-  return run_tsqr<16>(which, n, tr, s, nsolves, st);
+  if (!bmask) bmask = bucket_bit(kmax);
+  const int ktop = top_bucket(bmask);
+  for (int kb = 16; kb <= 64; kb += 16) {
+    if (!(bmask & bucket_bit(kb))) continue;
+    if (kb == 16) run_leaf<4>(which, n, tr, s, nsolves, st);
+    else if (kb == 32) run_leaf<8>(which, n, tr, s, nsolves, st);
+    else if (kb == 48) run_leaf<12>(which, n, tr, s, nsolves, st);
+    else run_leaf<16>(which, n, tr, s, nsolves, st);
+  }
+  if (ktop == 16) run_nodes<4>(which, tr, s, nsolves, st);
+  else if (ktop == 32) run_nodes<8>(which, tr, s, nsolves, st);
+  else if (ktop == 48) run_nodes<12>(which, tr, s, nsolves, st);
+  else run_nodes<16>(which, tr, s, nsolves, st);
+  if (which == TS_CORE) return hipGetLastError();   // R only
+  for (int kb = 16; kb <= 64; kb += 16) {
+    if (!(bmask & bucket_bit(kb))) continue;
+    if (kb == 16) run_leaf_apply<4>(which, n, tr, s, nsolves, st);
+    else if (kb == 32) run_leaf_apply<8>(which, n, tr, s, nsolves, st);
+    else if (kb == 48) run_leaf_apply<12>(which, n, tr, s, nsolves, st);
+    else run_leaf_apply<16>(which, n, tr, s, nsolves, st);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace lrp
