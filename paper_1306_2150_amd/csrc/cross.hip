@@ -197,39 +197,49 @@ __global__ __launch_bounds__(NTHR) void k_change_norms(Solve2D *S) {
   __syncthreads();
   const int i = blockIdx.x * NTHR + threadIdx.x;
   double n1 = 0.0, n2 = 0.0;
+  // one side's row in registers, the other side's entries streamed in
+  // groups of eight (half the registers of holding both rows)
   if (i < s.n) {
     const long ld = s.ldu;
-    double v[KM], w[KM];
+    double v[KM];
 #pragma unroll
-    for (int a = 0; a < KM; ++a) {
-      v[a] = (a < kq) ? s.Ap[i + (long)a * ld] : 0.0;
-      w[a] = (a < kk) ? s.A[i + (long)a * ld] : 0.0;
-    }
+    for (int a = 0; a < KM; ++a) v[a] = (a < kq) ? s.Ap[i + (long)a * ld] : 0.0;
+#pragma unroll 1
+    for (int c0 = 0; c0 < kk; c0 += 8) {
+      double w[8];
 #pragma unroll
-    for (int c = 0; c < KM; ++c) {
-      if (c < kk) {
-        double x = w[c];
+      for (int t = 0; t < 8; ++t) w[t] = (c0 + t < kk) ? s.A[i + (long)(c0 + t) * ld] : 0.0;
 #pragma unroll
-        for (int a = 0; a < KM; ++a) x -= v[a] * M[a * KMAX + c];
-        n1 += x * x;
+      for (int t = 0; t < 8; ++t) {
+        const int c = c0 + t;
+        if (c < kk) {
+          double x = w[t];
+#pragma unroll
+          for (int a = 0; a < KM; ++a) x -= v[a] * M[a * KMAX + c];
+          n1 += x * x;
+        }
       }
     }
   }
   if (i < s.m) {
     const long ld = s.ldv;
-    double v[KM], w[KM];
+    double v[KM];
 #pragma unroll
-    for (int c = 0; c < KM; ++c) {
-      v[c] = (c < kk) ? s.B[i + (long)c * ld] : 0.0;
-      w[c] = (c < kq) ? s.Bp[i + (long)c * ld] : 0.0;
-    }
+    for (int c = 0; c < KM; ++c) v[c] = (c < kk) ? s.B[i + (long)c * ld] : 0.0;
+#pragma unroll 1
+    for (int a0 = 0; a0 < kq; a0 += 8) {
+      double w[8];
 #pragma unroll
-    for (int a = 0; a < KM; ++a) {
-      if (a < kq) {
-        double x = w[a];
+      for (int t = 0; t < 8; ++t) w[t] = (a0 + t < kq) ? s.Bp[i + (long)(a0 + t) * ld] : 0.0;
 #pragma unroll
-        for (int c = 0; c < KM; ++c) x -= v[c] * M[a * KMAX + c];
-        n2 += sp2[a] * x * x;
+      for (int t = 0; t < 8; ++t) {
+        const int a = a0 + t;
+        if (a < kq) {
+          double x = w[t];
+#pragma unroll
+          for (int c = 0; c < KM; ++c) x -= v[c] * M[a * KMAX + c];
+          n2 += sp2[a] * x * x;
+        }
       }
     }
   }

@@ -63,9 +63,10 @@ __device__ inline size_t piv_off(const Tree &t, int l) {
 }
 
 // ---- tournament elimination
+// At NS <= 8 six waves per SIMD fit without spilling.
 template <int NS>
-__global__ __launch_bounds__(NTHR) void k_mv_leaf(int which, int n, Tree tr,
-                                                 Solve2D *S) {
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(NS <= 8 ? 6 : 1)))
+void k_mv_leaf(int which, int n, Tree tr, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (mv_skip(s, which, 4 * NS)) return;
   __shared__ double lbuf[2 * PANEL_M];
@@ -239,8 +240,11 @@ __device__ __forceinline__ void row_max16_f32(float (&v)[16]) {
 // zero past k) stays in registers for the whole K loop.  Operand layouts:
 // A[i][kq] in lane i + 16 kq, B[kq][j] in lane j + 16 kq, D[i][j] in lane
 // j + 16 (i / 4), register i % 4.
+// At KM <= 32 the register budget of five waves per SIMD fits without
+// spilling (the check is latency-bound: more waves in flight, more overlap).
 template <int KM>
-__global__ __launch_bounds__(NTHR) void k_mv_check(int which, int n, Solve2D *S) {
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(KM <= 32 ? 5 : 1)))
+void k_mv_check(int which, int n, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (mv_skip(s, which, KM) || s.mv_done) return;
   constexpr int NC = KM / 16;                   // 16-column blocks of B

@@ -255,9 +255,10 @@ __global__ __launch_bounds__(NTHR) void k_tsqr_node_apply(int which, int lev,
   }
 }
 
+// At NS <= 8 a budget of four waves per SIMD fits without spilling.
 template <int NS>
-__global__ __launch_bounds__(NTHR) void k_tsqr_leaf_apply(int which, int n,
-                                                         Tree tr, Solve2D *S) {
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(NS <= 8 ? 4 : 1)))
+void k_tsqr_leaf_apply(int which, int n, Tree tr, Solve2D *S) {
   Solve2D &s = S[blockIdx.y];
   if (s.active != ts_phase(which)) return;
   if (ts_phase(which) == ACT_SWEEP && rank_bucket(s.k) != 4 * NS) return;
