@@ -254,26 +254,6 @@ __global__ __launch_bounds__(NTHR) void k_change_norms(Solve2D *S) {
   }
 }
 
-// Columns a growth step adds: kick, or -- while no singular value is under
-// the tolerance yet, so the rank it needs is unknown -- the distance to the
-// rank at which a geometric decay fitted to the last singular values meets
-// it (the tail of sigma_t rho^j summed in squares is sigma_t / sqrt(1 -
-// rho^2)), plus the slack, at most GROW_TOP.
-__device__ int growth_step(const Solve2D &s, int kk, int R, double nrm) {
-  int g = s.kick;
-  if (R == kk && kk >= 4) {
-    const int d = min(8, kk / 2);
-    const double a = s.sig[kk - 1], b = s.sig[kk - 1 - d];
-    if (a > 0.0 && b > a) {
-      const double lr = log(a / b) / d;   // log of the decay per index, < 0
-      const double need = log(s.eps * nrm * sqrt(1.0 - exp(2.0 * lr)) / a) / lr;
-      if (need > 0.0 && need < (double)GROW_TOP) g = max(g, (int)ceil(need) + s.min_slack);
-      else if (need >= (double)GROW_TOP) g = GROW_TOP;
-    }
-  }
-  return min(g, GROW_TOP);
-}
-
 // Truncation rank, convergence and growth decision (one workgroup / solve).
 __global__ __launch_bounds__(NTHR) void k_decide(Solve2D *S) {
   Solve2D &s = S[blockIdx.x];
@@ -313,7 +293,7 @@ __global__ __launch_bounds__(NTHR) void k_decide(Solve2D *S) {
     s.status = LRP_OK;
   } else if (no_slack && kk < s.kcap) {
     next = NEXT_GROW;
-    s.kgrow = min(growth_step(s, kk, R, nrm), s.kcap - kk);
+    s.kgrow = min(s.kick, s.kcap - kk);
   } else if (change >= 0.0 && change <= s.eps * nrm) {
     next = NEXT_STOP;
     s.status = no_slack ? LRP_ERANKCAP : LRP_OK;

@@ -333,6 +333,31 @@ def test_solve2d_batch_same_as_alone():
         assert metrics.rel_err_factored(host(Uxb), host(Vxb), X) <= 10 * eps
 
 
+def test_solve2d_batch_mixed_rank_buckets():
+    """A batch whose slots sit in three rank buckets (the leaf-level sweep
+    kernels run once per bucket, each on its own slots; the tree nodes,
+    maxvol inverse and swaps and the core once at the largest): every
+    problem gives the rank and, to 1e-12, the result it gives alone, and is
+    within 10 eps of the float64 full solve."""
+    n = 1024
+    probs = [(*inputs.rhs2d_single_bumps(n, 1, 77), 1e-4),     # k <= 16
+             (*inputs.workload_rhs(2, 5, n=n), 1e-8),            # k about 32
+             (*inputs.workload_rhs(2, 6, n=n), 1e-12),           # k above 32
+             (*inputs.rhs2d_single_bumps(n, 1, 79), 1e-5)]
+    log("solve2d batch buckets", [(U.shape[1], eps) for U, V, eps in probs])
+    res_b = ctx().solve2d_batch([(dev(U), dev(V), eps) for U, V, eps in probs])
+    ks = []
+    for (U, V, eps), (Uxb, Vxb, ib) in zip(probs, res_b):
+        Uxa, Vxa, ia = ctx().solve2d(dev(U), dev(V), eps)
+        ks.append(ib["k"])
+        assert ia["rank"] == ib["rank"] and ia["k"] == ib["k"]
+        assert rel(host(Uxb) @ host(Vxb).T, host(Uxa) @ host(Vxa).T) <= 1e-12
+        X = poisson.full_solve2d_factors(U, V)
+        assert metrics.rel_err_factored(host(Uxb), host(Vxb), X) <= 10 * eps
+    log("  k", ks)
+    assert min(ks) <= 16 and max(ks) > 32, ks
+
+
 def test_prepared_batch_reruns_identically():
     """A prepared batch (argument array and outputs built once) solves every
     problem again on each run: equal bits on a second run, and equal to a
