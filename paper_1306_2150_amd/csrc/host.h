@@ -204,7 +204,8 @@ struct RoundGroup {
   lrp_ctx *ctx = nullptr;
   int n = 0, L = 0, kcap = 0;
   std::unique_ptr<Group2D> g;
-  double *buf = nullptr, *omega = nullptr, *Z = nullptr, *Qk = nullptr;
+  // zpart: the row layers' partial products of the A^T B steps
+  double *buf = nullptr, *omega = nullptr, *Z = nullptr, *Qk = nullptr, *zpart = nullptr;
   size_t bytes = 0;
 };
 // Ux (scale) and Vx (orthonormal) of rank <= rmax with relative error

@@ -76,13 +76,15 @@ static lrp_status round_group(lrp_ctx *ctx, int n, int K, RoundGroup **out) {
     lrp_status e = r->g->init();
     if (e != LRP_OK) return e;
     const size_t om = (size_t)n * L, z = (size_t)r->kcap * L, qk = (size_t)n * L;
-    r->bytes = (om + z + qk) * 8 + 3 * 256;
+    const size_t zp = gemm_tn_work(n, r->kcap, L);
+    r->bytes = (om + z + qk + zp) * 8 + 4 * 256;
     void *p = nullptr;
     if ((e = dev_alloc(ctx, &p, r->bytes)) != LRP_OK) return e;
     r->buf = (double *)p;
     r->omega = r->buf;
     r->Z = r->omega + ((om + 31) & ~(size_t)31);
     r->Qk = r->Z + ((z + 31) & ~(size_t)31);
+    r->zpart = zp ? r->Qk + ((qk + 31) & ~(size_t)31) : nullptr;
     std::vector<double> h(om);
     gaussian(h, 0x5EEDULL * 1000003ULL + (uint64_t)n);
     Solve2D &s = r->g->host(0);
@@ -125,20 +127,20 @@ lrp_status round_random(lrp_ctx *ctx, int n, int K, const double *U, const doubl
     return launch_tsqr(TS_VH_TO_Q1, n, tr, d, 1, L, st);
   };
   // Y = X Omega = U (V^T Omega), Q = orth(Y)
-  HIPCHK(launch_gemm_tn(n, K, L, V, ld, r.omega, n, r.Z, K, st));
+  HIPCHK(launch_gemm_tn(n, K, L, V, ld, r.omega, n, r.Z, K, st, r.zpart));
   HIPCHK(launch_gemm_nn(n, K, L, U, ld, r.Z, K, s.Vh, s.ldv, nullptr, st));
   HIPCHK(orth());
   // one power step: Q' = orth(X^T Q), Q = orth(X Q')
-  HIPCHK(launch_gemm_tn(n, K, L, U, ld, s.Q1, s.ldv, r.Z, K, st));
+  HIPCHK(launch_gemm_tn(n, K, L, U, ld, s.Q1, s.ldv, r.Z, K, st, r.zpart));
   HIPCHK(launch_gemm_nn(n, K, L, V, ld, r.Z, K, s.Vh, s.ldv, nullptr, st));
   HIPCHK(orth());
-  HIPCHK(launch_gemm_tn(n, K, L, V, ld, s.Q1, s.ldv, r.Z, K, st));
+  HIPCHK(launch_gemm_tn(n, K, L, V, ld, s.Q1, s.ldv, r.Z, K, st, r.zpart));
   HIPCHK(launch_gemm_nn(n, K, L, U, ld, r.Z, K, s.Vh, s.ldv, nullptr, st));
   HIPCHK(orth());
   HIPCHK(hipMemcpy2DAsync(r.Qk, (size_t)n * 8, s.Q1, (size_t)s.ldv * 8, (size_t)n * 8, L,
                           hipMemcpyDeviceToDevice, st));
   // X^T Q = V (U^T Q) = Q2 R2
-  HIPCHK(launch_gemm_tn(n, K, L, U, ld, r.Qk, n, r.Z, K, st));
+  HIPCHK(launch_gemm_tn(n, K, L, U, ld, r.Qk, n, r.Z, K, st, r.zpart));
   HIPCHK(launch_gemm_nn(n, K, L, V, ld, r.Z, K, s.Vh, s.ldv, nullptr, st));
   HIPCHK(orth());
   // R2^T = W S Z^T

@@ -5,6 +5,8 @@
 // Frobenius inner products of low-rank matrices.
 #include "lrp_internal.h"
 
+#include <algorithm>
+
 namespace lrp {
 namespace {
 
@@ -102,18 +104,22 @@ __global__ __launch_bounds__(LR_T) void k_lr_dot(const LrDot *pairs, double *out
 // chunks of 16 along the summed index.
 constexpr int GT = 64, GK = 16;
 
-// C (K x L) = A^T B, A: rows x K, B: rows x L (sum over the rows).
-__global__ __launch_bounds__(LR_T) void k_gemm_tn(int rows, int K, int L, const double *A,
-                                                 long lda, const double *B, long ldb,
-                                                 double *C, long ldc) {
+// C (K x L) = A^T B, A: rows x K, B: rows x L (sum over the rows).  Layer
+// z = blockIdx.z sums the rows [z chunk, (z + 1) chunk) into C + z * ldc * L
+// (its own K x L partial; one layer: C itself).
+__global__ __launch_bounds__(LR_T) void k_gemm_tn(int rows, int chunk, int K, int L,
+                                                 const double *A, long lda, const double *B,
+                                                 long ldb, double *C, long ldc) {
   __shared__ double as[GK][GT + 1], bs[GK][GT + 1];
   const int k0 = blockIdx.x * GT, l0 = blockIdx.y * GT;
   const int tk = (threadIdx.x & 15) * 4, tl = (threadIdx.x >> 4) * 4;
+  const int r0 = blockIdx.z * chunk, r1 = min(rows, r0 + chunk);
+  C += (long)blockIdx.z * ldc * L;
   double acc[4][4] = {};
-  for (int i0 = 0; i0 < rows; i0 += GK) {
+  for (int i0 = r0; i0 < r1; i0 += GK) {
     for (int e = threadIdx.x; e < GK * GT; e += LR_T) {
       const int i = e % GK, c = e / GK;
-      const bool in = i0 + i < rows;
+      const bool in = i0 + i < r1;
       as[i][c] = (in && k0 + c < K) ? A[i0 + i + (long)(k0 + c) * lda] : 0.0;
       bs[i][c] = (in && l0 + c < L) ? B[i0 + i + (long)(l0 + c) * ldb] : 0.0;
     }
@@ -135,6 +141,19 @@ __global__ __launch_bounds__(LR_T) void k_gemm_tn(int rows, int K, int L, const 
 #pragma unroll
     for (int v = 0; v < 4; ++v)
       if (k0 + tk + u < K && l0 + tl + v < L) C[k0 + tk + u + (long)(l0 + tl + v) * ldc] = acc[u][v];
+}
+
+// C[e] = sum over the layers z < nz of P[z * per + e], in layer order, for
+// the K x L entries e of a partial (leading dimension K), into C (ldc).
+__global__ __launch_bounds__(LR_T) void k_sum_layers(int nz, int K, int L, const double *P,
+                                                    double *C, long ldc) {
+  const long per = (long)K * L;
+  const long e = (long)blockIdx.x * LR_T + threadIdx.x;
+  if (e >= per) return;
+  double v = 0.0;
+  for (int z = 0; z < nz; ++z) v += P[z * per + e];
+  const int k = (int)(e % K), l = (int)(e / K);
+  C[k + (long)l * ldc] = v;
 }
 
 // C (rows x L) = A B diag(scale), A: rows x K, B: K x L (sum over K);
@@ -195,11 +214,37 @@ hipError_t launch_copy_scaled(int rows, int cols, const double *src, long lds, d
   return hipGetLastError();
 }
 
+// Layers of the split sum over the rows: chunks of at least 128 rows (a
+// multiple of GK), at most GEMM_SPLIT of them.
+static int gemm_tn_layers(int rows, int *chunk) {
+  int nz = std::min(GEMM_SPLIT, std::max(1, ceil_div(rows, 128)));
+  int c = ceil_div(ceil_div(rows, nz), GK) * GK;
+  nz = ceil_div(rows, c);
+  *chunk = c;
+  return nz;
+}
+
+size_t gemm_tn_work(int rows, int K, int L) {
+  int chunk;
+  const int nz = gemm_tn_layers(rows, &chunk);
+  return nz > 1 ? (size_t)nz * K * L : 0;
+}
+
 hipError_t launch_gemm_tn(int rows, int K, int L, const double *A, long lda, const double *B,
-                          long ldb, double *C, long ldc, hipStream_t st) {
+                          long ldb, double *C, long ldc, hipStream_t st, double *work) {
   if (K <= 0 || L <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gemm_tn, dim3(ceil_div(K, GT), ceil_div(L, GT)), dim3(LR_T), 0, st, rows,
-                     K, L, A, lda, B, ldb, C, ldc);
+  int chunk;
+  const int nz = work ? gemm_tn_layers(rows, &chunk) : 1;
+  if (nz <= 1) {
+    hipLaunchKernelGGL(k_gemm_tn, dim3(ceil_div(K, GT), ceil_div(L, GT), 1), dim3(LR_T), 0, st,
+                       rows, std::max(rows, 1), K, L, A, lda, B, ldb, C, ldc);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_gemm_tn, dim3(ceil_div(K, GT), ceil_div(L, GT), nz), dim3(LR_T), 0, st,
+                     rows, chunk, K, L, A, lda, B, ldb, work, (long)K);
+  const long per = (long)K * L;
+  hipLaunchKernelGGL(k_sum_layers, dim3((unsigned)ceil_div((int)per, LR_T)), dim3(LR_T), 0, st,
+                     nz, K, L, (const double *)work, C, ldc);
   return hipGetLastError();
 }
 

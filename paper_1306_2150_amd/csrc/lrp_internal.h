@@ -494,9 +494,16 @@ struct LrDot {
   int rows, rx, ry;
 };
 hipError_t launch_lr_dots(const LrDot *pairs, int npairs, double *out, hipStream_t st);
-// C (K x L) = A^T B (A: rows x K, B: rows x L)
+// C (K x L) = A^T B (A: rows x K, B: rows x L).  With a workspace of
+// gemm_tn_work(rows, K, L) doubles the rows are split over up to
+// GEMM_SPLIT workgroup layers whose partial products are then summed in
+// layer order (the same sum for every launch shape); without one, each
+// output tile sums all rows itself.
+constexpr int GEMM_SPLIT = 64;
+size_t gemm_tn_work(int rows, int K, int L);
 hipError_t launch_gemm_tn(int rows, int K, int L, const double *A, long lda, const double *B,
-                          long ldb, double *C, long ldc, hipStream_t st);
+                          long ldb, double *C, long ldc, hipStream_t st,
+                          double *work = nullptr);
 // C (rows x L) = A B diag(scale) (A: rows x K, B: K x L; scale null: ones)
 hipError_t launch_gemm_nn(int rows, int K, int L, const double *A, long lda, const double *B,
                           long ldb, double *C, long ldc, const double *scale, hipStream_t st);
