@@ -172,9 +172,11 @@ def smooth_terms(n, terms, r, seed):
     return np.hstack(Us), np.hstack(Vs)
 
 
-@pytest.mark.parametrize("case", ["exact30", "cancel", "many", "small", "zero"])
+@pytest.mark.parametrize("case", ["exact30", "cancel", "many", "small", "zero", "many_tall"])
 def test_lowrank_round_against_svd(case):
-    n = 300
+    # n = 300: the A^T B products sum three row layers (112, 112, 76 rows);
+    # n = 2100: seventeen layers of 128 rows, the last one of 52
+    n = 2100 if case == "many_tall" else 300
     rng = np.random.default_rng(7)
     if case == "exact30":
         U, V, eps = rng.standard_normal((n, 30)), rng.standard_normal((n, 30)), 1e-12
@@ -183,7 +185,7 @@ def test_lowrank_round_against_svd(case):
         W1, W2 = rng.standard_normal((2, n, 10))
         E1, E2 = rng.standard_normal((2, n, 40)) * 1e3
         U, V, eps = np.hstack([W1, E1, -E1]), np.hstack([W2, E2, E2]), 1e-8
-    elif case == "many":
+    elif case in ("many", "many_tall"):
         U, V = smooth_terms(n, 15, 40, 3)
         eps = 1e-9
     elif case == "small":
