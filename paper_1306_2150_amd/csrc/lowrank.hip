@@ -214,8 +214,9 @@ hipError_t launch_copy_scaled(int rows, int cols, const double *src, long lds, d
   return hipGetLastError();
 }
 
-// Layers of the split sum over the rows: chunks of at least 128 rows (a
-// multiple of GK), at most GEMM_SPLIT of them.
+// Layers of the split sum over the rows: ceil(rows / 128) of them, at most
+// GEMM_SPLIT, each a chunk of equal length rounded up to a multiple of GK
+// (the last one takes the rest).
 static int gemm_tn_layers(int rows, int *chunk) {
   int nz = std::min(GEMM_SPLIT, std::max(1, ceil_div(rows, 128)));
   int c = ceil_div(ceil_div(rows, nz), GK) * GK;
