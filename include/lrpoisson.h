@@ -381,6 +381,17 @@ lrp_status lrp_set_kernel_timing(lrp_ctx *ctx, int32_t enable);
 lrp_status lrp_kernel_stats(lrp_ctx *ctx, int32_t prec, lrp_kernel_stat *out,
                             int32_t reset);
 
+/* Graph replay of the cross sweeps (the batched and served execution around
+ * the cross of Section 4.2; on by default).  With it on, each sweep step of a
+ * slot group (its tree QRs, maxvol, core, factors, change and decision
+ * launches) is captured once per launch plan -- the live slots rounded up to
+ * a power of two, the rank buckets the slots occupy -- into a HIP graph
+ * (at most 64 per group; further plans run as plain launches) and replayed
+ * on the caller's stream.  The graphs hold no memory set or copy nodes.  Results are the same with it off (plain launches on the
+ * caller's stream covering exactly the live slots).  LRP_EINVAL for a null
+ * ctx. */
+lrp_status lrp_set_graph_replay(lrp_ctx *ctx, int32_t enable);
+
 /* ---- Continuous-batching serving (same solver, asynchronous) ----------
  * A request is admitted when the context's device-memory budget has room
  * for its workspace; its factors stay resident on the device.  Each call of

@@ -44,7 +44,7 @@ EXPORTS = ["lrp_create", "lrp_destroy", "lrp_strerror", "lrpoisson_solve2d",
            "lrp_sine_transform_noalloc", "lrp_expsum_solve2d_batch",
            "lrp_kernel_qr_maxvol", "lrp_kernel_core_svd", "lrp_stokes2d",
            "lrp_lowrank_round",
-           "lrp_set_kernel_timing", "lrp_kernel_stats"]
+           "lrp_set_kernel_timing", "lrp_kernel_stats", "lrp_set_graph_replay"]
 
 
 class LrpOpts(ctypes.Structure):
@@ -157,6 +157,7 @@ def load(path: str = LIB_PATH):
     lib.lrp_sine_transform.argtypes = [P, I64, I32, P, I64, P, I64, I32, P]
     lib.lrp_sine_transform_noalloc.argtypes = [I64, I32, P, I64, P, I64, I32, P]
     lib.lrp_set_kernel_timing.argtypes = [P, I32]
+    lib.lrp_set_graph_replay.argtypes = [P, I32]
     lib.lrp_kernel_stats.argtypes = [P, I32, ctypes.POINTER(LrpKernelStat), I32]
     lib.lrp_submit.argtypes = [P, ctypes.POINTER(LrpRequest), ctypes.POINTER(ctypes.c_uint64)]
     lib.lrp_serve_step.argtypes = [P, ctypes.POINTER(I32)]
@@ -516,6 +517,12 @@ class Context:
         st = self.lib.lrp_set_kernel_timing(self.h, 1 if on else 0)
         if st != LRP_OK:
             raise LrpError(st, "lrp_set_kernel_timing")
+
+    def set_graph_replay(self, on: bool):
+        """Replay the cross sweep steps as captured HIP graphs (default on)."""
+        st = self.lib.lrp_set_graph_replay(self.h, 1 if on else 0)
+        if st != LRP_OK:
+            raise LrpError(st, "lrp_set_graph_replay")
 
     def kernel_stats(self, prec="fp64", reset=False):
         k = LrpKernelStat()

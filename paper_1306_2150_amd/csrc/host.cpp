@@ -305,6 +305,7 @@ Group2D::~Group2D() {
     (void)hipStreamSynchronize(stream_);
     (void)hipStreamDestroy(stream_);
   }
+  for (auto &kv : graphs_) (void)hipGraphExecDestroy(kv.second);
   dev_free(ctx_, ws_, bytes_);
   dev_free(ctx_, d_work_, work_bytes_);
   if (h_s_) (void)hipHostFree(h_s_);
@@ -521,52 +522,100 @@ lrp_status Group2D::forward(const std::vector<int> &slots, hipStream_t st) {
   return LRP_OK;
 }
 
-lrp_status Group2D::step(hipStream_t st) {
-  int kin = 0, kmax = 0, rmax = 0;
-  bool any_init = false, any_sweep = false;
-  unsigned bmask = 0;   // rank buckets the sweep's slots occupy
-  int hi = 0;   // launches cover slots [0, hi): the live ones
-  for (int i = 0; i < cap_; ++i) {
-    const Solve2D &s = h_s_[i];
-    if (s.active != ACT_DONE) hi = i + 1;
-    if (s.active == ACT_INIT) {
-      any_init = true;
-      kin = std::max(kin, s.k);
-      kmax = std::max(kmax, s.k0);
-      rmax = std::max(rmax, s.r);
-      bmask |= bucket_bit(s.k0);   // k_init_J sets k = k0
-    } else if (s.active == ACT_SWEEP) {
-      any_sweep = true;
-      kmax = std::max(kmax, s.k);
-      rmax = std::max(rmax, s.r);
-      bmask |= bucket_bit(s.k);
-    }
-  }
+uint64_t Group2D::StepPlan::key() const {
+  // hi < 2^24; the three rank buckets in 2 bits each, the mask in 4
+  const auto b2 = [](int k) { return (uint64_t)(rank_bucket(std::max(k, 1)) / 16 - 1); };
+  return (uint64_t)hi | (b2(kin) << 24) | (b2(km) << 26) | (b2(kev) << 28) |
+         ((uint64_t)bmask << 30) | ((uint64_t)init << 34) | ((uint64_t)sweep << 35);
+}
+
+lrp_status Group2D::launch_step(const StepPlan &p, hipStream_t st) {
   // trees depend on the shape only, so a slot's arithmetic does not depend
   // on which other slots share the launch
   const Tree tn = make_tree(n_, KMAX), tm = make_tree(m_, KMAX);
-  if (any_init) {
-    HIPCHK(launch_tsqr(TS_VH_TO_Q1, m_, tm, d_s_, hi, kin, st));
-    HIPCHK(launch_maxvol(MV_Q1_TO_J, m_, tm, d_s_, hi, kin, st));
+  const int hi = p.hi;
+  if (p.init) {
+    HIPCHK(launch_tsqr(TS_VH_TO_Q1, m_, tm, d_s_, hi, p.kin, st));
+    HIPCHK(launch_maxvol(MV_Q1_TO_J, m_, tm, d_s_, hi, p.kin, st));
     HIPCHK(launch_init_J(d_s_, hi, st));
   }
-  if (!any_init && !any_sweep) return LRP_OK;
   // k of a slot only grows at the end of a sweep, so kmax and the buckets
   // hold for this sweep: the kernels with many workgroups per slot run once
   // per occupied bucket, on its slots, the rest once at the largest
-  const int km = std::max(kmax, 1);
-  const int kev = std::max(km, rmax);
-  HIPCHK(launch_tsqr(TS_C_TO_Q0, n_, tn, d_s_, hi, km, st, bmask));
-  HIPCHK(launch_maxvol(MV_Q0_TO_I, n_, tn, d_s_, hi, km, st, bmask));
-  HIPCHK(launch_tsqr(TS_C_TO_Q1, m_, tm, d_s_, hi, km, st, bmask));
-  HIPCHK(launch_maxvol(MV_Q1_TO_JN, m_, tm, d_s_, hi, km, st, bmask));
-  HIPCHK(launch_core(ACT_SWEEP, d_s_, hi, km, st));
+  HIPCHK(launch_tsqr(TS_C_TO_Q0, n_, tn, d_s_, hi, p.km, st, p.bmask));
+  HIPCHK(launch_maxvol(MV_Q0_TO_I, n_, tn, d_s_, hi, p.km, st, p.bmask));
+  HIPCHK(launch_tsqr(TS_C_TO_Q1, m_, tm, d_s_, hi, p.km, st, p.bmask));
+  HIPCHK(launch_maxvol(MV_Q1_TO_JN, m_, tm, d_s_, hi, p.km, st, p.bmask));
+  HIPCHK(launch_core(ACT_SWEEP, d_s_, hi, p.km, st));
   for (int kb = 16; kb <= 64; kb += 16) {
-    if (!(bmask & bucket_bit(kb))) continue;
+    if (!(p.bmask & bucket_bit(kb))) continue;
     HIPCHK(launch_factors(n_, m_, d_s_, hi, kb, st));
     HIPCHK(launch_change(n_, m_, d_s_, hi, kb, st));
   }
-  HIPCHK(launch_decide(n_, m_, d_s_, hi, kev, st));
+  HIPCHK(launch_decide(n_, m_, d_s_, hi, p.kev, st));
+  return LRP_OK;
+}
+
+// Graphs kept per group; a plan beyond them runs as plain launches.
+constexpr size_t GRAPH_CACHE = 64;
+
+lrp_status Group2D::step(hipStream_t st) {
+  StepPlan p{0, 0, 0, 0, 0u, false, false};
+  int kmax = 0, rmax = 0;
+  int live = 0;   // launches cover slots [0, hi): the live ones
+  for (int i = 0; i < cap_; ++i) {
+    const Solve2D &s = h_s_[i];
+    if (s.active != ACT_DONE) live = i + 1;
+    if (s.active == ACT_INIT) {
+      p.init = true;
+      p.kin = std::max(p.kin, s.k);
+      kmax = std::max(kmax, s.k0);
+      rmax = std::max(rmax, s.r);
+      p.bmask |= bucket_bit(s.k0);   // k_init_J sets k = k0
+    } else if (s.active == ACT_SWEEP) {
+      p.sweep = true;
+      kmax = std::max(kmax, s.k);
+      rmax = std::max(rmax, s.r);
+      p.bmask |= bucket_bit(s.k);
+    }
+  }
+  if (!p.init && !p.sweep) return LRP_OK;
+  p.km = std::max(kmax, 1);
+  p.kev = std::max(p.km, rmax);
+  if (!ctx_->graphs) {
+    p.hi = live;
+    return launch_step(p, st);
+  }
+  // Replayed: the launches cover the live slots rounded up to a power of
+  // two (finished and unused slots return at once), so that a few graphs
+  // serve every step of a batch.  Every slot of [0, cap) holds a valid
+  // state (init uploads them all as finished).
+  int hi = 1;
+  while (hi < live) hi *= 2;
+  p.hi = std::min(hi, cap_);
+  auto it = graphs_.find(p.key());
+  if (it == graphs_.end()) {
+    if (graphs_.size() >= GRAPH_CACHE) return launch_step(p, st);
+    hipStream_t gs = stream();
+    if (!gs) return LRP_EDEVICE;
+    HIPCHK(maxvol_prepare());   // no host-side attribute calls inside a capture
+    hipGraph_t gr = nullptr;
+    HIPCHK(hipStreamBeginCapture(gs, hipStreamCaptureModeThreadLocal));
+    const lrp_status e = launch_step(p, gs);
+    const hipError_t ce = hipStreamEndCapture(gs, &gr);
+    if (e != LRP_OK || ce != hipSuccess) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return e != LRP_OK ? e : LRP_EDEVICE;
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (ie != hipSuccess) return LRP_EDEVICE;
+    it = graphs_.emplace(p.key(), ex).first;
+  }
+  // captured on the group's own stream (capture needs one that is not the
+  // legacy default stream), replayed on the caller's
+  HIPCHK(hipGraphLaunch(it->second, st));
   return LRP_OK;
 }
 
@@ -710,6 +759,13 @@ lrp_status lrp_set_kernel_timing(lrp_ctx *ctx, int32_t enable) {
   if (!ctx) return LRP_EINVAL;
   std::lock_guard<std::mutex> lock(ctx->mu);
   ctx->timing = enable != 0;
+  return LRP_OK;
+}
+
+lrp_status lrp_set_graph_replay(lrp_ctx *ctx, int32_t enable) {
+  if (!ctx) return LRP_EINVAL;
+  std::lock_guard<std::mutex> lock(ctx->mu);
+  ctx->graphs = enable != 0;
   return LRP_OK;
 }
 

@@ -108,6 +108,16 @@ class Group2D {
   std::vector<int> kin_;
   const GridTables *tabs_ = nullptr;
   hipStream_t stream_ = nullptr;
+  // sweep steps captured as graphs (on stream_), keyed by their launch plan,
+  // replayed on the caller's stream
+  struct StepPlan {
+    int hi, kin, km, kev;
+    unsigned bmask;
+    bool init, sweep;
+    uint64_t key() const;
+  };
+  lrp_status launch_step(const StepPlan &p, hipStream_t st);
+  std::map<uint64_t, hipGraphExec_t> graphs_;
 };
 
 // A group of 3D (Tucker) solve slots of one grid size n.  Slot i owns the
@@ -273,6 +283,8 @@ struct lrp_ctx {
   lrp_kernel_stat kstat[LRP_PREC_BF16X6 + 1] = {};
   // phase events of the synchronous calls (forward, cross, inverse)
   hipEvent_t phase_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // replay the cross sweep steps as captured HIP graphs (lrp_set_graph_replay)
+  bool graphs = true;
   std::mutex mu;
 };
 

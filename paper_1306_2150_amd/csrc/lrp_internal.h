@@ -397,6 +397,9 @@ hipError_t launch_tsqr(int which, int rows, const Tree &tr, Solve2D *s,
 enum : int { MV_Q0_TO_I = 0, MV_Q1_TO_JN = 1, MV_Q1_TO_J = 2 };
 hipError_t launch_maxvol(int which, int rows, const Tree &tr, Solve2D *s,
                          int nsolves, int kmax, hipStream_t st, unsigned bmask = 0);
+// host-side kernel attributes of launch_maxvol, set once (launch_maxvol
+// calls it; call it before capturing launches into a graph)
+hipError_t maxvol_prepare();
 // more check/swap rounds of a maxvol that launch_maxvol started (its rows
 // and inverse are current); rounds of a converged maxvol do nothing
 hipError_t launch_maxvol_rounds(int which, int rows, const Tree &tr, Solve2D *s,

@@ -590,6 +590,23 @@ void run_check(int which, int n, const Tree &tr, Solve2D *s, int ns,
 
 }  // namespace
 
+// The swap kernels' dynamic LDS limits, set once per process (before any
+// launch is captured into a graph).
+hipError_t maxvol_prepare() {
+  static bool attr = false;
+  if (attr) return hipSuccess;
+  const void *fns[4] = {(const void *)k_mv_swap<16>, (const void *)k_mv_swap<32>,
+                        (const void *)k_mv_swap<48>, (const void *)k_mv_swap<64>};
+  const int kms[4] = {16, 32, 48, 64};
+  for (int t = 0; t < 4; ++t) {
+    const hipError_t e = hipFuncSetAttribute(fns[t], hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)mv_swap_lds(kms[t]));
+    if (e != hipSuccess) return e;
+  }
+  attr = true;
+  return hipSuccess;
+}
+
 // The tournament leaves and the checks run once per bucket of the mask, on
 // its slots; the tournament nodes, the inverse and the swap loops (a few
 // workgroups or one per slot) once at the largest bucket, on every slot.
@@ -611,18 +628,7 @@ hipError_t launch_maxvol(int which, int rows, const Tree &tr, Solve2D *s,
   else run_mv_nodes<16>(which, n, tr, s, nsolves, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  static bool attr = false;
-  if (!attr) {
-    const void *fns[4] = {(const void *)k_mv_swap<16>, (const void *)k_mv_swap<32>,
-                          (const void *)k_mv_swap<48>, (const void *)k_mv_swap<64>};
-    const int kms[4] = {16, 32, 48, 64};
-    for (int t = 0; t < 4; ++t) {
-      e = hipFuncSetAttribute(fns[t], hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)mv_swap_lds(kms[t]));
-      if (e != hipSuccess) return e;
-    }
-    attr = true;
-  }
+  if ((e = maxvol_prepare()) != hipSuccess) return e;
   // one explicit inverse of the tournament's rows; the swap rounds keep it
   // current with the rank-1 updates of their swaps
   if (ktop == 16) hipLaunchKernelGGL(k_mv_inv<16>, dim3(nsolves), dim3(NTHR), 0, st, which, n, 0, s);

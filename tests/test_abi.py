@@ -70,6 +70,7 @@ def test_null_context_rejected(lib):
     assert lib.lrp_kernel_core_svd(None, 4, P(1), 4, P(1), P(1), P(1), None) == binding.LRP_EINVAL
     sp = binding.LrpStokes2DProblem()
     assert lib.lrp_stokes2d(None, ctypes.byref(sp), None) == binding.LRP_EINVAL
+    assert lib.lrp_set_graph_replay(None, 1) == binding.LRP_EINVAL
 
 
 def test_struct_layouts_match_header(tmp_path):
