@@ -53,14 +53,14 @@ DTYPE = {"fp64": "f64", "fft64": "f64", "int8": "i8-slices+f64", "fp32": "f32+f6
 # the narrow tail launch), as the timed launch average does.
 TRAFFIC = {
     "k_dst_fft4096": {"sources": ["dst_fft.hip", "lrp_internal.h"],
-                      "sha1": "3657c748d2a170b75923d4a4a6abdc3221af537b",
-                      "columns": 83936, "fetch_kib": 1350950.6, "write_kib": 2685955.4},
+                      "sha1": "b7409872572ad5116ca93bc8a2598df84db30252",
+                      "columns": 83968, "fetch_kib": 1351473.0, "write_kib": 2686983.9},
     "k_dst_i8": {"sources": ["dst_i8.hip", "lrp_internal.h"],
-                 "sha1": "299f9d7546a202b159d0c21511dff647a6444096",
-                 "columns": 13989.333, "fetch_kib": 229240.1, "write_kib": 448128.0},
+                 "sha1": "5fd4f8c754166ab32eeabd320b2ba49e58c03a73",
+                 "columns": 13989.333, "fetch_kib": 229131.2, "write_kib": 448128.0},
     "k_dst_f64": {"sources": ["dst.hip", "lrp_internal.h"],
-                  "sha1": "3d24c1781c2354b3176995c45766d59672ccc06e",
-                  "columns": 83936, "fetch_kib": 1998926.8, "write_kib": 3746467.0},
+                  "sha1": "89e1060fe35e75a54761a80325908be97c1b3497",
+                  "columns": 83968, "fetch_kib": 1350067.9, "write_kib": 2818574.6},
 }
 
 
@@ -249,7 +249,7 @@ def stokes_table(ctx, workers):
 # profiles/kernel_traffic_n4096_b2048.md (2 x FETCH + WRITE, calibrated by a
 # device copy)
 CROSS_BATCH = 2048
-CROSS_BYTES_PER_CALL = 241350.7 * 2 ** 20
+CROSS_BYTES_PER_CALL = 235460.5 * 2 ** 20
 
 
 def cross_phase(res, batch):

@@ -132,8 +132,8 @@ def full_solve2d(F: np.ndarray, workers: int | None = None,
                  op: str = "poisson") -> np.ndarray:
     """Full-grid 2D solve X = S[(S F S) / D]S, D = ``denominators2d``.
 
-    Section 4.1: "applying the DST, inverting the diagonal matrix, and then
-    applying the DST back".  Pins: scipy.linalg.solve_sylvester, dense
+    Section 4.1's direct method: the sine transform on both sides, a
+    division by the operator's eigenvalues, the sine transform back.  Pins: scipy.linalg.solve_sylvester, dense
     Kronecker solve, residual, single sine mode (Stokes operator: dense
     Kronecker solve from G and H).
     """

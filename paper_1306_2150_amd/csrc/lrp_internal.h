@@ -15,7 +15,7 @@ constexpr int PANEL_M = 256;         // rows of one LDS-resident QR/LU panel
 constexpr int NTHR = 256;            // threads of every panel kernel
 constexpr int MV_TOP = 8;            // violator rows kept per block in maxvol
 constexpr int MV_CAND = 128;         // candidate rows of the maxvol swap kernel
-constexpr int MV_ROUNDS = 3;         // check/swap rounds launched per maxvol
+constexpr int MV_ROUNDS = 2;         // check/swap rounds launched per maxvol
 constexpr int GROW_TOP = 16;         // growth candidates kept per block (>= kick)
 constexpr int BLOCK_TOP = (MV_TOP > GROW_TOP) ? MV_TOP : GROW_TOP;
 

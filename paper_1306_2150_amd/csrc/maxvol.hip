@@ -1,8 +1,8 @@
 // maxvol: k rows I of an n x k orthonormal basis Q whose k x k submatrix has
 // (locally) maximal volume -- the pivot choice of the cross approximation
-// (paper Section 4.2, "maximal-volume submatrix ... maxvol-algorithm",
-// refs. gt-maxvol-2001, gostz-maxvol-2010).  The exit contract is the one of
-// the algorithm: B = Q Q[I,:]^-1 has B[I,:] = identity and max|B| <= tau.
+// (paper Section 4.2, refs. gt-maxvol-2001, gostz-maxvol-2010).  The exit
+// contract is the one of the algorithm: B = Q Q[I,:]^-1 has B[I,:] =
+// identity and max|B| <= tau.
 //
 // GPU formulation (same contract, parallel steps):
 //  1. starting rows: Gaussian elimination with partial pivoting run as a
@@ -16,7 +16,10 @@
 //     argmax row in, rank-1 update of B) on I plus the reported rows and
 //     applies the same rank-1 updates to Inv.  A round that finds no entry
 //     above tau ends the iteration.  Each swap multiplies |det Q[I,:]| by
-//     more than tau, so the rounds terminate.
+//     more than tau, so the rounds terminate.  Inside a cross sweep at most
+//     MV_ROUNDS rounds run (the next sweep starts from the rows reached, so
+//     the iteration goes on across sweeps); launch_maxvol_rounds continues
+//     one to the contract.
 #include "panel.h"
 
 namespace lrp {
